@@ -1,0 +1,191 @@
+"""Plain FP64 CPU reference of the pressure-projection solve (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the bench's
+CPU-baseline leg are the only callers.  The product library never imports
+this package and this package never imports the product library.
+
+All arrays are NumPy, C-ordered ``[nz, ny, nx]`` (x fastest).  Sign convention
+follows Eq. (pois): ``apply`` returns ``L p = div((1/rho) grad p)`` and
+``pcg`` solves ``L p = rhs``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, MAXIT = 0, 1
+EINVAL, EDOMAIN, ESINGULAR, EBREAKDOWN, ENOMEM, EUNSUPPORTED = -1, -2, -3, -4, -5, -8
+
+_lib = None
+
+
+def build(src: str = _SRC, out: str = _LIB) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+           "-Wall", "-Wno-unknown-pragmas", "-o", out, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def load(path: Optional[str] = None):
+    """Load the built oracle, building it first if nothing is built."""
+    global _lib
+    if path is None and _lib is not None:
+        return _lib
+    p = path or _LIB
+    if not os.path.exists(p):
+        build(out=p)
+    lib = ctypes.CDLL(p)
+    dp = ctypes.POINTER(ctypes.c_double)
+    up = ctypes.POINTER(ctypes.c_uint8)
+    ip = ctypes.POINTER(ctypes.c_int)
+    i, d = ctypes.c_int, ctypes.c_double
+    lib.oracle_apply.argtypes = [i, i, i, d, dp, up, ip, dp, dp]
+    lib.oracle_apply.restype = i
+    lib.oracle_relres.argtypes = [i, i, i, d, dp, up, ip, dp, dp]
+    lib.oracle_relres.restype = d
+    lib.oracle_pcg.argtypes = [i, i, i, d, dp, up, ip, dp, d, i, dp, ip, dp, dp]
+    lib.oracle_pcg.restype = i
+    lib.oracle_project.argtypes = [i, i, i, d, dp, up, ip, d, dp, dp, dp, dp]
+    lib.oracle_project.restype = i
+    lib.oracle_divergence.argtypes = [i, i, i, d, dp, dp, dp, dp]
+    lib.oracle_divergence.restype = None
+    lib.oracle_connected.argtypes = [i, i, i, up, ip]
+    lib.oracle_connected.restype = i
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = i
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _f64(a):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _u8(a):
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _bc(bc):
+    arr = (ctypes.c_int * 6)(*[int(b) for b in bc])
+    return arr
+
+
+def _dims(rho):
+    nz, ny, nx = rho.shape
+    return nx, ny, nz
+
+
+def apply(rho, mask, bc, h, p, lib=None):
+    """L p per Eq. (pois) with the face rules of the module docstring."""
+    lib = lib or load()
+    rho, rp = _f64(rho)
+    mask, mp = _u8(mask)
+    p, pp = _f64(p)
+    out = np.empty_like(rho)
+    nx, ny, nz = _dims(rho)
+    st = lib.oracle_apply(nx, ny, nz, float(h), rp, mp, _bc(bc), pp,
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if st != OK:
+        raise ValueError(f"oracle_apply status {st}")
+    return out
+
+
+def relres(rho, mask, bc, h, rhs, p, lib=None) -> float:
+    """||rhs - L p||_2 / ||rhs||_2 over fluid cells."""
+    lib = lib or load()
+    rho, rp = _f64(rho)
+    mask, mp = _u8(mask)
+    rhs, bp = _f64(rhs)
+    p, pp = _f64(p)
+    nx, ny, nz = _dims(rho)
+    return float(lib.oracle_relres(nx, ny, nz, float(h), rp, mp, _bc(bc), bp, pp))
+
+
+class PCGResult:
+    def __init__(self, p, status, iters, relres, hist):
+        self.p, self.status, self.iters, self.relres, self.hist = \
+            p, status, iters, relres, hist
+
+    def __repr__(self):
+        return (f"PCGResult(status={self.status}, iters={self.iters}, "
+                f"relres={self.relres:.3e})")
+
+
+def pcg(rho, mask, bc, h, rhs, tol=1e-8, maxit=100000, history=False,
+        lib=None) -> PCGResult:
+    """Jacobi-PCG solve of L p = rhs (cold start); see oracle.c."""
+    lib = lib or load()
+    rho, rp = _f64(rho)
+    mask, mp = _u8(mask)
+    rhs, bp = _f64(rhs)
+    nx, ny, nz = _dims(rho)
+    p = np.zeros_like(rho)
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    hist = np.zeros(maxit + 1) if history else None
+    hp = (hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+          if history else None)
+    st = lib.oracle_pcg(nx, ny, nz, float(h), rp, mp, _bc(bc), bp, float(tol),
+                        int(maxit),
+                        p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                        ctypes.byref(it), ctypes.byref(rr), hp)
+    if history:
+        hist = hist[: it.value + 1]
+    return PCGResult(p, st, it.value, rr.value, hist)
+
+
+def project(rho, mask, bc, h, dt, p, u, v, w, lib=None):
+    """Return projected copies of the face velocities (Section 2.1)."""
+    lib = lib or load()
+    rho, rp = _f64(rho)
+    mask, mp = _u8(mask)
+    p, pp = _f64(p)
+    u = np.array(u, dtype=np.float64, copy=True, order="C")
+    v = np.array(v, dtype=np.float64, copy=True, order="C")
+    w = np.array(w, dtype=np.float64, copy=True, order="C")
+    nx, ny, nz = _dims(rho)
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = lib.oracle_project(nx, ny, nz, float(h), rp, mp, _bc(bc), float(dt), pp,
+                            u.ctypes.data_as(dp), v.ctypes.data_as(dp),
+                            w.ctypes.data_as(dp))
+    if st != OK:
+        raise ValueError(f"oracle_project status {st}")
+    return u, v, w
+
+
+def divergence(u, v, w, h, lib=None):
+    """Face-difference divergence of MAC velocities."""
+    lib = lib or load()
+    nz, ny, nx1 = u.shape
+    nx = nx1 - 1
+    u, up_ = _f64(u)
+    v, vp = _f64(v)
+    w, wp = _f64(w)
+    out = np.empty((nz, ny, nx))
+    lib.oracle_divergence(nx, ny, nz, float(h), up_, vp, wp,
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return out
+
+
+def connected(mask, bc, lib=None) -> bool:
+    lib = lib or load()
+    mask, mp = _u8(mask)
+    nz, ny, nx = mask.shape
+    return bool(lib.oracle_connected(nx, ny, nz, mp, _bc(bc)))
+
+
+def threads(lib=None) -> int:
+    lib = lib or load()
+    return int(lib.oracle_threads())

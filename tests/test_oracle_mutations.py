@@ -1,0 +1,119 @@
+"""The pins catch plausible mistakes in the reference.
+
+Each case copies the reference source, plants one mistake by text
+replacement, builds the copy with gcc into a temporary directory and runs the
+pins that should catch it.  The real reference source is never modified.
+"""
+import functools
+import json
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+
+class Bound:
+    """The oracle module's API bound to another build of the library."""
+
+    def __init__(self, lib):
+        for name in ("apply", "pcg", "relres", "project", "divergence",
+                     "connected"):
+            setattr(self, name, functools.partial(getattr(oracle, name), lib=lib))
+        for name in ("OK", "MAXIT", "EINVAL", "EDOMAIN", "ESINGULAR",
+                     "EBREAKDOWN", "EUNSUPPORTED"):
+            setattr(self, name, getattr(oracle, name))
+
+
+def _gold(name):
+    return [c for c in pins._gold_cases() if c["name"] == name][0]
+
+
+def _F():
+    from paper_1410_1942_amd import fields
+    return fields
+
+
+PIN_RUNS = {
+    "hand_column": lambda o: pins.test_hand_solved(o, _gold("water_air_column")),
+    "hand_hull": lambda o: pins.test_hand_solved(o, _gold("water_cell_beside_hull")),
+    "hand_row": lambda o: pins.test_hand_solved(o, _gold("three_cell_row_open_ends")),
+    "eig_dirichlet": lambda o: pins.test_eigvec_all_dirichlet(o, (12, 10, 8), 2.5, (1, 2, 3)),
+    "eig_tank": lambda o: pins.test_eigvec_tank(o, (10, 6, 12)),
+    "manufactured": lambda o: pins.test_manufactured_second_order(o),
+    "dense": lambda o: pins.test_dense_cholesky(o, _F(), (8, 8, 8), (1, 0, 0, 1, 0, 1), True),
+    "banded": lambda o: pins.test_column_reduction_banded(o),
+    "divergence": lambda o: pins.test_projection_divergence(o, _F(), 1e-6),
+    "termination": lambda o: pins.test_finite_termination(o, 8),
+}
+
+MUTANTS = [
+    # average 1/rho instead of rho on a face
+    ("harmonic_face", "return 1.0 / ((P->rho[a] + P->rho[b]) / 2.0);",
+     "return (1.0 / P->rho[a] + 1.0 / P->rho[b]) / 2.0;"),
+    # Dirichlet ghost mirrored with the wrong sign (acts as Neumann)
+    ("ghost_sign", "double pn = nb[f] >= 0 ? p[nb[f]] : -p[c]; /* ghost */",
+     "double pn = nb[f] >= 0 ? p[nb[f]] : p[c]; /* ghost */"),
+    # hull faces left open
+    ("hull_open", "if (P->solid[a] || P->solid[b]) return 0.0;",
+     "if (P->solid[a] && P->solid[b]) return 0.0;"),
+    # y- and y+ walls exchanged
+    ("y_walls_swapped", "int jj[6] = { j, j, j - 1, j + 1, j, j };\n    int kk[6] = { k, k, k, k, k - 1, k + 1 };\n    for (int f = 0; f < 6; ++f) {\n        int inside",
+     "int jj[6] = { j, j, j + 1, j - 1, j, j };\n    int kk[6] = { k, k, k, k, k - 1, k + 1 };\n    for (int f = 0; f < 6; ++f) {\n        int inside"),
+    # conjugate direction dropped: steepest descent
+    ("no_conjugation", "pp[c] = z[c] + beta * pp[c];", "pp[c] = z[c];"),
+    # grid spacing not squared in the scaled right-hand side
+    ("h_not_squared", "double h2 = h * h;", "double h2 = h;"),
+    # projection moves velocity up the pressure gradient
+    ("projection_sign", "*uf -= s * face_beta(&P, a, b) * (p[b] - p[a]);",
+     "*uf += s * face_beta(&P, a, b) * (p[b] - p[a]);"),
+    # z face coefficient taken from the wrong neighbour
+    ("z_index", "int kk[6] = { k, k, k, k, k - 1, k + 1 };\n    for (int f = 0; f < 6; ++f) {\n        int inside",
+     "int kk[6] = { k, k, k, k, k + 1, k + 1 };\n    for (int f = 0; f < 6; ++f) {\n        int inside"),
+]
+
+
+@pytest.fixture(scope="module")
+def tmpdir_mut():
+    d = tempfile.mkdtemp(prefix="oracle_mut_")
+    yield d
+    shutil.rmtree(d, ignore_errors=True)
+
+
+def _caught(o, name):
+    try:
+        PIN_RUNS[name](o)
+    except (AssertionError, ValueError):
+        return True
+    return False
+
+
+def test_unmutated_passes_all(tmpdir_mut):
+    out = os.path.join(tmpdir_mut, "lib_ref.so")
+    oracle.build(SRC, out)
+    o = Bound(oracle.load(out))
+    for name in PIN_RUNS:
+        assert not _caught(o, name), name
+
+
+@pytest.mark.parametrize("mutant", MUTANTS, ids=lambda m: m[0])
+def test_mutant_is_caught(tmpdir_mut, mutant):
+    name, old, new = mutant
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation anchor not found: {name}"
+    src = src.replace(old, new)
+    cpath = os.path.join(tmpdir_mut, f"{name}.c")
+    with open(cpath, "w") as f:
+        f.write(src)
+    out = os.path.join(tmpdir_mut, f"lib_{name}.so")
+    oracle.build(cpath, out)
+    o = Bound(oracle.load(out))
+    caught = next((p for p in PIN_RUNS if _caught(o, p)), None)
+    assert caught is not None, f"mutant {name} passed every pin"

@@ -1,0 +1,333 @@
+"""Pins of the CPU reference against facts that do not come from it.
+
+Each test checks the reference against something fixed by the paper's
+equations and by mathematics: hand-solved tiny problems, exact discrete
+eigenvectors, second-order convergence to a manufactured continuous solution,
+symmetry and definiteness, a dense direct solve assembled independently, a
+1-D reduction solved by a banded routine, the divergence of the projected
+velocity, invariances, and the finite termination of conjugate gradients.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+D, N = 1, 0
+ALL_D = (D, D, D, D, D, D)
+TANK = (N, N, N, N, N, D)
+
+
+def _grid(nx, ny, nz):
+    h = 1.0 / nz
+    x = (np.arange(nx) + 0.5) * h
+    y = (np.arange(ny) + 0.5) * h
+    z = (np.arange(nz) + 0.5) * h
+    return h, x[None, None, :], y[None, :, None], z[:, None, None]
+
+
+# --------------------------------------------------------------------------
+# hand-solved problems (tests/golden/hand_solved.json)
+# --------------------------------------------------------------------------
+
+def _gold_cases():
+    with open(os.path.join(GOLD, "hand_solved.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _gold_cases(), ids=lambda c: c["name"])
+def test_hand_solved(orc, case):
+    shp = (case["nz"], case["ny"], case["nx"])
+    rho = np.array(case["rho"], float).reshape(shp)
+    mask = np.array(case["mask"], np.uint8).reshape(shp)
+    rhs = np.array(case["rhs"], float).reshape(shp)
+    want = np.array(case["p"], float).reshape(shp)
+    # operator: L applied to the hand solution gives the source on fluid cells
+    Lp = orc.apply(rho, mask, case["bc"], case["h"], want)
+    fluid = mask == 0
+    np.testing.assert_allclose(Lp[fluid], rhs[fluid], rtol=1e-12, atol=1e-12)
+    # solver
+    r = orc.pcg(rho, mask, case["bc"], case["h"], rhs, tol=1e-14, maxit=50)
+    assert r.status == orc.OK
+    np.testing.assert_allclose(r.p, want, rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# exact discrete eigenvectors
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,c,modes", [
+    ((8, 8, 8), 1.0, (1, 1, 1)),
+    ((12, 10, 8), 2.5, (1, 2, 3)),
+    ((5, 9, 7), 1000.0, (2, 1, 1)),
+])
+def test_eigvec_all_dirichlet(orc, shape, c, modes):
+    """prod_d sin(m_d pi x_d / L_d) at cell centres is an exact eigenvector
+    of the face-Dirichlet operator with eigenvalue
+    -(1/c) sum_d 2(1 - cos(m_d pi h / L_d)) / h^2."""
+    nx, ny, nz = shape
+    h, x, y, z = _grid(nx, ny, nz)
+    L = (nx * h, ny * h, nz * h)
+    m = modes
+    v = (np.sin(m[0] * math.pi * x / L[0]) * np.sin(m[1] * math.pi * y / L[1])
+         * np.sin(m[2] * math.pi * z / L[2]))
+    lam = sum(2.0 * (1.0 - math.cos(m[d] * math.pi * h / L[d])) for d in range(3))
+    rho = np.full((nz, ny, nx), c)
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    Lv = orc.apply(rho, mask, ALL_D, h, v)
+    np.testing.assert_allclose(Lv, -(lam / c) / h**2 * v, rtol=0,
+                               atol=1e-11 * np.abs(lam / c / h**2))
+    # the solver returns the eigenvector for the matching source
+    r = orc.pcg(rho, mask, ALL_D, h, -(lam / c) / h**2 * v, tol=1e-13)
+    assert r.status == orc.OK
+    np.testing.assert_allclose(r.p, v, rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (10, 6, 12)])
+def test_eigvec_tank(orc, shape):
+    """Neumann on x, y and the bottom, p = 0 on top:
+    cos(pi x/Lx) cos(pi y/Ly) cos(pi z/(2 Lz)) is exact with eigenvalue
+    -[2(1-cos(pi h/Lx)) + 2(1-cos(pi h/Ly)) + 2(1-cos(pi h/(2Lz)))]/h^2."""
+    nx, ny, nz = shape
+    h, x, y, z = _grid(nx, ny, nz)
+    Lx, Ly, Lz = nx * h, ny * h, nz * h
+    v = (np.cos(math.pi * x / Lx) * np.cos(math.pi * y / Ly)
+         * np.cos(math.pi * z / (2 * Lz)))
+    lam = (2 * (1 - math.cos(math.pi * h / Lx)) + 2 * (1 - math.cos(math.pi * h / Ly))
+           + 2 * (1 - math.cos(math.pi * h / (2 * Lz))))
+    rho = np.ones((nz, ny, nx))
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    Lv = orc.apply(rho, mask, TANK, h, v)
+    np.testing.assert_allclose(Lv, -lam / h**2 * v, rtol=0,
+                               atol=1e-11 * lam / h**2)
+
+
+# --------------------------------------------------------------------------
+# manufactured continuous solution: second order
+# --------------------------------------------------------------------------
+
+def test_manufactured_second_order(orc):
+    """Sigma = -3 pi^2 sin(pi x) sin(pi y) sin(pi z) with p = 0 on all walls
+    of the unit cube has the continuous solution sin sin sin; the discrete
+    error must fall by about 4 per halving of h."""
+    errs = []
+    for n in (8, 16, 32):
+        h, x, y, z = _grid(n, n, n)
+        exact = np.sin(math.pi * x) * np.sin(math.pi * y) * np.sin(math.pi * z)
+        rhs = -3 * math.pi**2 * exact
+        rho = np.ones((n, n, n))
+        r = orc.pcg(rho, np.zeros((n, n, n), np.uint8), ALL_D, h, rhs, tol=1e-12)
+        assert r.status == orc.OK
+        errs.append(np.abs(r.p - exact).max())
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    for q in ratios:
+        assert 3.5 < q < 4.5, (errs, ratios)
+
+
+# --------------------------------------------------------------------------
+# symmetry and definiteness
+# --------------------------------------------------------------------------
+
+def _two_phase_wedge(F, nx, ny, nz, bc=(D, N, N, D, N, D)):
+    c = F.make_two_phase(nx, ny, nz, surface_seed=5, velocity_seed=6,
+                         wedge=F.Wedge(), bc=bc)
+    return c
+
+
+def test_symmetric_positive_definite(orc, F):
+    c = _two_phase_wedge(F, 14, 12, 10)
+    assert c.mask.any() and (c.rho == F.RHO_AIR).any() and (c.rho == F.RHO_WATER).any()
+    fluid = c.mask == 0
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        x = rng.standard_normal(c.shape) * fluid
+        y = rng.standard_normal(c.shape) * fluid
+        Lx = orc.apply(c.rho, c.mask, c.bc, c.h, x)
+        Ly = orc.apply(c.rho, c.mask, c.bc, c.h, y)
+        a, b = np.vdot(x, Ly), np.vdot(y, Lx)
+        scale = np.linalg.norm(x) * np.linalg.norm(Ly)
+        assert abs(a - b) <= 1e-13 * scale
+        assert np.vdot(x, Lx) < 0.0          # -L is positive definite
+
+
+# --------------------------------------------------------------------------
+# dense direct solve, assembled here from the definition
+# --------------------------------------------------------------------------
+
+def _dense_minus_h2L(rho, mask, bc):
+    nz, ny, nx = rho.shape
+    n = rho.size
+    A = np.zeros((n, n))
+    idx = lambda i, j, k: (k * ny + j) * nx + i
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                c = idx(i, j, k)
+                if mask[k, j, i]:
+                    A[c, c] = 1.0
+                    continue
+                for f, (di, dj, dk) in enumerate([(-1, 0, 0), (1, 0, 0), (0, -1, 0),
+                                                  (0, 1, 0), (0, 0, -1), (0, 0, 1)]):
+                    ii, jj, kk = i + di, j + dj, k + dk
+                    if 0 <= ii < nx and 0 <= jj < ny and 0 <= kk < nz:
+                        if mask[kk, jj, ii]:
+                            continue
+                        b = 2.0 / (rho[k, j, i] + rho[kk, jj, ii])
+                        m = idx(ii, jj, kk)
+                        A[c, c] += b
+                        A[c, m] -= b
+                    elif bc[f] == D:
+                        A[c, c] += 2.0 / rho[k, j, i]
+    return A
+
+
+@pytest.mark.parametrize("shape,bc,wedge", [
+    ((6, 5, 8), TANK, True),
+    ((8, 8, 8), (D, N, N, D, N, D), True),
+    ((7, 4, 6), ALL_D, False),
+])
+def test_dense_cholesky(orc, F, shape, bc, wedge):
+    nx, ny, nz = shape
+    c = F.make_two_phase(nx, ny, nz, surface_seed=11, velocity_seed=12,
+                         wedge=F.Wedge() if wedge else None, bc=bc)
+    A = _dense_minus_h2L(c.rho, c.mask, c.bc)
+    b = (-c.h**2 * c.rhs * (c.mask == 0)).ravel()
+    Lc = np.linalg.cholesky(A)
+    p = scipy.linalg.solve_triangular(Lc.T, scipy.linalg.solve_triangular(Lc, b, lower=True))
+    r = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-14, maxit=5000)
+    assert r.status in (orc.OK, orc.MAXIT)
+    scale = np.abs(p).max()
+    assert np.abs(r.p.ravel() - p).max() <= 1e-10 * scale
+
+
+# --------------------------------------------------------------------------
+# 1-D reduction: flat interface, Neumann sides, source depending on z only
+# --------------------------------------------------------------------------
+
+def test_column_reduction_banded(orc):
+    nx, ny, nz = 3, 4, 16
+    h = 1.0 / nz
+    zc = (np.arange(nz) + 0.5) * h
+    rho1 = np.where(zc < 0.5, 1000.0, 1.2)
+    sig1 = np.cos(3 * zc) + 0.3
+    rho = np.broadcast_to(rho1[:, None, None], (nz, ny, nx)).copy()
+    rhs = np.broadcast_to(sig1[:, None, None], (nz, ny, nx)).copy()
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    r = orc.pcg(rho, mask, TANK, h, rhs, tol=1e-12)
+    assert r.status == orc.OK
+    # tridiagonal -h^2 L restricted to the column
+    bf = 2.0 / (rho1[:-1] + rho1[1:])          # faces k+1/2
+    diag = np.zeros(nz)
+    diag[:-1] += bf
+    diag[1:] += bf
+    diag[-1] += 2.0 / rho1[-1]                 # p = 0 on the top face
+    ab = np.zeros((3, nz))
+    ab[0, 1:] = -bf
+    ab[1] = diag
+    ab[2, :-1] = -bf
+    p1 = scipy.linalg.solve_banded((1, 1), ab, -h**2 * sig1)
+    for j in range(ny):
+        for i in range(nx):
+            np.testing.assert_allclose(r.p[:, j, i], p1, rtol=1e-8,
+                                       atol=1e-12 * np.abs(p1).max())
+
+
+# --------------------------------------------------------------------------
+# divergence of the projected velocity
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+def test_projection_divergence(orc, F, tol):
+    """With Sigma = D u / dt, u - dt (1/rho) grad p has divergence
+    dt (Sigma - L p): its norm relative to ||D u|| is the relative residual."""
+    c = _two_phase_wedge(F, 20, 16, 18, bc=TANK)
+    r = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=tol)
+    assert r.status == orc.OK
+    div0 = orc.divergence(c.u, c.v, c.w, c.h)
+    u, v, w = orc.project(c.rho, c.mask, c.bc, c.h, c.dt, r.p, c.u, c.v, c.w)
+    div1 = orc.divergence(u, v, w, c.h)
+    ratio = np.linalg.norm(div1) / np.linalg.norm(div0)
+    assert ratio <= tol
+    assert abs(ratio - r.relres) <= 1e-6 * r.relres + 1e-15
+    # hull and Neumann faces keep zero normal velocity
+    assert np.all(u[:, :, 0] == 0) and np.all(w[0] == 0)
+
+
+# --------------------------------------------------------------------------
+# invariances
+# --------------------------------------------------------------------------
+
+def test_density_scaling(orc, F):
+    c = _two_phase_wedge(F, 12, 10, 12, bc=TANK)
+    r1 = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-12)
+    r3 = orc.pcg(3.0 * c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-12)
+    np.testing.assert_allclose(r3.p, 3.0 * r1.p, rtol=0,
+                               atol=1e-8 * np.abs(r1.p).max())
+
+
+def test_axis_swap_and_mirror(orc, F):
+    c = _two_phase_wedge(F, 12, 10, 8, bc=(D, N, N, N, N, D))
+    base = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-12).p
+    s = np.abs(base).max()
+    # swap x and y (and their boundary kinds)
+    bc_t = (c.bc[2], c.bc[3], c.bc[0], c.bc[1], c.bc[4], c.bc[5])
+    t = lambda a: np.ascontiguousarray(np.swapaxes(a, 1, 2))
+    pt = orc.pcg(t(c.rho), t(c.mask), bc_t, c.h, t(c.rhs), tol=1e-12).p
+    np.testing.assert_allclose(pt, t(base), rtol=0, atol=1e-8 * s)
+    # mirror in x (swap x- and x+)
+    bc_m = (c.bc[1], c.bc[0]) + tuple(c.bc[2:])
+    m = lambda a: np.ascontiguousarray(a[:, :, ::-1])
+    pm = orc.pcg(m(c.rho), m(c.mask), bc_m, c.h, m(c.rhs), tol=1e-12).p
+    np.testing.assert_allclose(pm, m(base), rtol=0, atol=1e-8 * s)
+
+
+# --------------------------------------------------------------------------
+# conjugate gradients terminate in at most n steps (up to rounding)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nz", [2, 5, 8])
+def test_finite_termination(orc, nz):
+    """On an n-unknown SPD system CG terminates in at most n steps in exact
+    arithmetic; a steepest-descent or mis-scaled update does not."""
+    h = 1.0 / nz
+    rho = np.where((np.arange(nz) + 0.5) * h < 0.5, 1000.0, 1.2)[:, None, None].copy()
+    rhs = np.linspace(1.0, 2.0, nz)[:, None, None].copy()
+    r = orc.pcg(rho, np.zeros_like(rho, np.uint8), TANK, h, rhs, tol=1e-12, maxit=200)
+    assert r.status == orc.OK
+    assert r.iters <= nz + 1
+
+
+# --------------------------------------------------------------------------
+# failure reporting
+# --------------------------------------------------------------------------
+
+def test_failures(orc):
+    n = 4
+    rho = np.ones((n, n, n))
+    mask = np.zeros((n, n, n), np.uint8)
+    rhs = np.ones((n, n, n))
+    h = 1.0 / n
+    assert orc.pcg(rho, mask, (N,) * 6, h, rhs).status == orc.ESINGULAR
+    assert orc.pcg(rho, mask, (2, 2, N, N, N, D), h, rhs).status == orc.EUNSUPPORTED
+    bad = rho.copy(); bad[1, 1, 1] = -1.0
+    assert orc.pcg(bad, mask, TANK, h, rhs).status == orc.EDOMAIN
+    bad[1, 1, 1] = np.nan
+    assert orc.pcg(bad, mask, TANK, h, rhs).status == orc.EDOMAIN
+    # a negative density inside the hull is ignored
+    m2 = mask.copy(); m2[1, 1, 1] = 1; bad[1, 1, 1] = -1.0
+    assert orc.pcg(bad, m2, TANK, h, rhs).status == orc.OK
+    # sealed fluid pocket: one fluid cell at the bottom centre walled by hull
+    m3 = np.zeros((n, n, n), np.uint8)
+    m3[0:2, 0:3, 0:3] = 1
+    m3[0, 1, 1] = 0
+    assert not orc.connected(m3, TANK)
+    assert orc.pcg(rho, m3, TANK, h, rhs).status == orc.ESINGULAR
+    # zero source: p = 0 with no iteration
+    r = orc.pcg(rho, mask, TANK, h, np.zeros_like(rhs))
+    assert r.status == orc.OK and r.iters == 0 and not r.p.any()
+    # iteration cap
+    r = orc.pcg(rho, mask, TANK, h, rhs, tol=1e-14, maxit=1)
+    assert r.status == orc.MAXIT and r.iters == 1
