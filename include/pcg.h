@@ -1,0 +1,257 @@
+/*
+ * pcg.h -- C ABI of the MI355X pressure-projection solver.
+ *
+ * The library solves the variable-coefficient pressure equation of the
+ * cartesian-grid ship-wave method (Section 2, Eq. pois):
+ *
+ *     d/dx_i ( (1/rho) dP/dx_i ) = Sigma
+ *
+ * on a uniform grid of nx*ny*nz cubic cells of edge h, by Jacobi-
+ * preconditioned conjugate gradients (the Introduction names a
+ * preconditioned conjugate-gradient solver for this equation).  The solution
+ * is the pressure used to project the velocity onto a solenoidal field
+ * (Section 2.1, first and second Runge-Kutta stages).
+ *
+ * Discretisation (cell-centred pressure and density):
+ *   - face coefficient between fluid cells c, n: beta = 1/((rho_c+rho_n)/2);
+ *   - a face touching a hull ("solid") cell carries beta = 0: the binary
+ *     form of the finite-volume free-slip hull (Section 2.2.1); solid cells
+ *     get p = 0 and their rhs is ignored;
+ *   - a Neumann wall carries beta = 0; a Dirichlet wall imposes p = 0 on the
+ *     face (the zero reduced pressure at the walls, Section 2.4.2) with
+ *     beta = 1/rho_c and the mirrored ghost value -p_c;
+ *   - (L p)_c = h^-2 [ sum_n beta_cn (p_n - p_c) - 2 sum_D beta_c p_c ].
+ * A solve succeeds when ||Sigma - L p||_2 <= tol * ||Sigma||_2 over fluid
+ * cells.  The solution is unique iff every connected fluid region touches a
+ * Dirichlet wall.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller,
+ * C-ordered [nz][ny][nx] (x fastest; cell (i,j,k) at (k*ny + j)*nx + i),
+ * unless marked "host".  The library never allocates device memory: it
+ * carves what it needs out of a caller-provided workspace or arena.  It does
+ * allocate small pinned host buffers (status mirrors) and hipGraph objects.
+ *
+ * Streams: all device work of a context or batch is ordered on the HIP
+ * stream passed at creation (NULL = the legacy default stream).  Calls on
+ * one context or batch must not overlap in time (not thread-safe).
+ *
+ * Errors: every function returns an int status; no exception crosses the
+ * ABI.  0 is success, positive values are non-fatal conditions, negative
+ * values are errors.  pcg_strerror() gives a static description;
+ * pcg_last_hip_error() gives the text of the last HIP runtime failure.
+ */
+#ifndef PCG_MI355X_H
+#define PCG_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+enum {
+    PCG_OK = 0,
+    PCG_MAXIT = 1,        /* iteration cap reached; p holds the last iterate */
+    PCG_PENDING = 2,      /* batched solve still running                     */
+    PCG_EINVAL = -1,      /* null pointer, n < 1, h <= 0, tol <= 0, ...      */
+    PCG_EDOMAIN = -2,     /* rho <= 0 or non-finite in a fluid cell, or a
+                             non-finite rhs                                  */
+    PCG_ESINGULAR = -3,   /* a fluid region touches no Dirichlet wall        */
+    PCG_EBREAKDOWN = -4,  /* p.Ap <= 0 or non-finite during the iteration    */
+    PCG_ENOMEM = -5,      /* workspace / arena too small                     */
+    PCG_EBUSY = -6,       /* admission refused: over the memory budget or no
+                             free slot; retry after a release                */
+    PCG_EHIP = -7,        /* HIP runtime failure (see pcg_last_hip_error)     */
+    PCG_EUNSUPPORTED = -8 /* periodic walls, or a grid above the size limit  */
+};
+
+/* ---- problem description --------------------------------------------- */
+typedef struct {
+    int32_t nx, ny, nz; /* cells along x, y, z (each >= 1)                   */
+    double h;           /* cell edge (> 0)                                   */
+} pcg_grid_t;
+
+enum { PCG_BC_NEUMANN = 0, PCG_BC_DIRICHLET = 1, PCG_BC_PERIODIC = 2 };
+
+typedef struct {
+    int32_t kind[6];    /* walls in the order x-, x+, y-, y+, z-, z+         */
+} pcg_bc_t;
+
+enum { PCG_PREC_FP64 = 0, PCG_PREC_FP32_IR = 1 };
+
+enum {
+    PCG_WARM_START = 1,              /* p holds an initial guess on entry    */
+    PCG_SKIP_CONNECTIVITY_CHECK = 2  /* trust that every fluid region touches
+                                        a Dirichlet wall (skips a host flood
+                                        fill of the mask)                    */
+};
+
+/*
+ * Options.  Zero-initialised fields take the defaults in brackets.
+ *   precision   PCG_PREC_FP64 [default] or PCG_PREC_FP32_IR: FP32 stencil
+ *               and vectors inside, FP64 residual, dot products, alpha/beta
+ *               and solution update (iterative refinement).
+ *   check_every iterations per captured graph replay between host polls [32]
+ *   flags       PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK
+ *   inner_maxit FP32_IR: cap on inner iterations per refinement trip [none]
+ *   inner_tol   FP32_IR: relative reduction of each inner solve [1e-5]
+ *   tz          cells per tile along z; 0 = chosen by the autotuner table
+ *   grid_blocks workgroups per launch; 0 = chosen by the autotuner table
+ */
+typedef struct {
+    int32_t precision;
+    int32_t check_every;
+    int32_t flags;
+    int32_t inner_maxit;
+    double inner_tol;
+    int32_t tz;
+    int32_t grid_blocks;
+} pcg_opts_t;
+
+/* Per-solve statistics (host structure). */
+typedef struct {
+    int32_t status;           /* PCG_* code of the solve                     */
+    int32_t iters;            /* CG iterations (inner iterations for IR)     */
+    int32_t outer_iters;      /* refinement trips (IR), 0 for FP64           */
+    double rel_res_true;      /* ||b - A p|| / ||b|| recomputed in FP64      */
+    double rel_res_recursive; /* last recursive residual of the iteration    */
+    double ms;                /* wall time of the call (pcg_solve), or from
+                                 admission to completion (batched)           */
+} pcg_stats_t;
+
+typedef struct pcg_ctx pcg_ctx_t;     /* opaque, owned by the library */
+typedef struct pcg_batch pcg_batch_t; /* opaque, owned by the library */
+
+/* ---- single solve ----------------------------------------------------- */
+
+/*
+ * Bytes of device workspace pcg_setup needs for this grid and options.
+ * Returns PCG_EINVAL on bad arguments, PCG_EUNSUPPORTED when
+ * nx*ny*nz >= 2^31.
+ */
+int pcg_workspace_bytes(const pcg_grid_t *grid, const pcg_opts_t *opts,
+                        size_t *out_bytes);
+
+/*
+ * Prepare a solver for one density field (Eq. density gives rho from the
+ * volume fraction; here rho is given directly).
+ *   rho        device f64[n]: density per cell (> 0 and finite in fluid cells)
+ *   solid_mask device u8[n]: 1 = hull cell, 0 = fluid; NULL = no hull
+ *   bc         host: the six wall kinds
+ *   opts       host, may be NULL (defaults)
+ *   workspace  device buffer of at least pcg_workspace_bytes(), 256-byte
+ *              aligned, owned by the caller and kept alive until pcg_destroy
+ *   hip_stream hipStream_t the context works on (NULL = default stream)
+ * rho and solid_mask are read during the call and not retained.  Errors:
+ * EINVAL, EDOMAIN (checked on the device), ESINGULAR (host flood fill of the
+ * mask unless PCG_SKIP_CONNECTIVITY_CHECK), ENOMEM, EUNSUPPORTED, EHIP.
+ */
+int pcg_setup(pcg_ctx_t **out, const pcg_grid_t *grid, const double *rho,
+              const uint8_t *solid_mask, const pcg_bc_t *bc,
+              const pcg_opts_t *opts, void *workspace, size_t ws_bytes,
+              void *hip_stream);
+
+/*
+ * Solve L p = rhs to relative residual tol with at most maxit iterations.
+ *   rhs   device f64[n]: the source Sigma (values in solid cells ignored);
+ *         must stay unchanged during the call
+ *   p     device f64[n]: output pressure (0 in solid cells); input guess
+ *         when the context was set up with PCG_WARM_START
+ *   stats host, may be NULL
+ * Blocks until the solve is complete.  Returns PCG_OK, PCG_MAXIT (p holds
+ * the last iterate, usable as a warm start), or an error (EINVAL, EDOMAIN
+ * for a non-finite rhs, EBREAKDOWN, EHIP).  A zero rhs gives p = 0 after
+ * zero iterations.
+ */
+int pcg_solve(pcg_ctx_t *ctx, const double *rhs, double *p, double tol,
+              int32_t maxit, pcg_stats_t *stats);
+
+/* Release the context (not the workspace).  NULL is accepted. */
+int pcg_destroy(pcg_ctx_t *ctx);
+
+/* Static text for a status code. */
+const char *pcg_strerror(int code);
+
+/* Text of the last HIP runtime error seen by the library on this thread. */
+const char *pcg_last_hip_error(void);
+
+/* ---- batched and served solves ---------------------------------------- */
+
+/*
+ * A batch keeps several independent solves resident on the device and
+ * advances all of them together: every launch covers the tiles of every
+ * active solve, and each solve's iterations are captured once in a hipGraph
+ * and replayed.  Solves may be admitted and released between steps
+ * (continuous batching).  A solve's arithmetic depends only on its own
+ * grid, tile shape and data, so its result is bitwise the same alone or in
+ * any mix.
+ *
+ *   arena       device buffer owned by the caller; admission succeeds only
+ *               while the sum of the resident solves' footprints fits in it
+ *   arena_bytes its size
+ *   max_slots   most solves resident at once (>= 1)
+ *   opts        precision and tiling for every solve of the batch
+ */
+int pcg_batch_create(pcg_batch_t **out, void *arena, size_t arena_bytes,
+                     int32_t max_slots, const pcg_opts_t *opts,
+                     void *hip_stream);
+
+/* Device bytes one solve of this grid occupies in a batch's arena. */
+int pcg_batch_footprint(const pcg_batch_t *b, const pcg_grid_t *grid,
+                        size_t *out_bytes);
+
+/*
+ * Admit one solve.  rho, mask (NULL = none) are read during the call;
+ * rhs and p must stay valid until the solve is released.  Returns PCG_EBUSY
+ * when the footprint does not fit in the free arena space or no slot is
+ * free, and validation errors as pcg_setup.  On success *slot names it.
+ */
+int pcg_batch_admit(pcg_batch_t *b, const pcg_grid_t *grid, const double *rho,
+                    const uint8_t *mask, const pcg_bc_t *bc, const double *rhs,
+                    double *p, double tol, int32_t maxit, int32_t flags,
+                    int32_t *slot);
+
+/*
+ * Run `replays` captured graphs of check_every iterations each over every
+ * active solve, then refresh the host mirror of every solve's status.
+ * Blocks until the work is done.  *active_out (may be NULL) receives the
+ * number of solves still running.
+ */
+int pcg_batch_step(pcg_batch_t *b, int32_t replays, int32_t *active_out);
+
+/* Status of one solve: PCG_PENDING while running, else its final code. */
+int pcg_batch_poll(pcg_batch_t *b, int32_t slot, pcg_stats_t *stats);
+
+/* Free a slot and its arena space (finished or not). */
+int pcg_batch_release(pcg_batch_t *b, int32_t slot);
+
+int pcg_batch_destroy(pcg_batch_t *b);
+
+/* ---- measurement helpers ---------------------------------------------- */
+
+/*
+ * Kernel timing of pcg_solve.  After pcg_set_timing(ctx, 1) the solve
+ * launches its two iteration kernels directly (not through the captured
+ * graph) with a hipEvent recorded on the context's stream around each
+ * launch; pcg_last_timing then gives the average duration (ms) of the first
+ * (direction update + p.Ap) and second (operator apply + vector update +
+ * dots) kernel over the launches that did work, and how many first-kernel
+ * launches were averaged.  PCG_EINVAL when no timed solve has run.
+ */
+int pcg_set_timing(pcg_ctx_t *ctx, int32_t on);
+int pcg_last_timing(pcg_ctx_t *ctx, double *ms_k1, double *ms_k2,
+                    int32_t *launches);
+
+/*
+ * Copy-kernel bandwidth probe: copies n doubles src -> dst `reps` times on
+ * the given stream and returns the average ms per copy.
+ */
+int pcg_copy_probe(const double *src, double *dst, size_t n, int32_t reps,
+                   void *hip_stream, double *ms_per_copy);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCG_MI355X_H */

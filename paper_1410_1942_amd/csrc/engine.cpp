@@ -1,0 +1,898 @@
+// Host runtime of the MI355X pressure solver: arena allocator, slot table,
+// hipGraph capture of the iteration, polling, and the C ABI of pcg.h.
+//
+// One Engine drives any number of resident solves ("slots").  Device memory
+// comes from a caller-owned arena: a fixed head (batch header, slot table,
+// slot states, error flag) followed by one block per slot carved by a
+// first-fit allocator.  The iteration is captured once as a hipGraph of
+// check_every x [K1, K2] launches that read the slot table from device
+// memory, so slots can join and leave between replays without re-capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pcg.h"
+#include "pcg_types.h"
+
+namespace pcgmi {
+hipError_t launch_iter(int family, int which, int grid, const BatchHeader *hdr,
+                       const Slot *slots, hipStream_t s);
+hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
+                         float *r32, int64_t n, int *bad, hipStream_t s);
+hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
+}  // namespace pcgmi
+
+using namespace pcgmi;
+
+namespace {
+
+thread_local std::string g_hip_err;
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_hip_err = std::string(what) + ": " + hipGetErrorString(e);
+    return PCG_EHIP;
+}
+
+#define HIP_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t _e = (expr);                            \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);  \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kDefaultCheckEvery = 32;
+constexpr int kDefaultGridMax = 2048;
+constexpr double kDefaultInnerTol = 1e-5;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point t0)
+{
+    return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+// ---- tile shape table (autotuned values can be installed at run time) ----
+
+struct TileRule {
+    int64_t max_cells;  // rule applies to grids with at most this many cells
+    int tz;
+};
+
+std::vector<TileRule> g_rules_fp64 = { { 1 << 16, 8 }, { 1 << 22, 16 }, { INT64_MAX, 32 } };
+std::vector<TileRule> g_rules_ir = { { 1 << 16, 8 }, { 1 << 22, 16 }, { INT64_MAX, 32 } };
+
+int choose_tz(int64_t n, int prec)
+{
+    const auto &rules = prec == PCG_PREC_FP32_IR ? g_rules_ir : g_rules_fp64;
+    for (const auto &r : rules)
+        if (n <= r.max_cells) return r.tz;
+    return 16;
+}
+
+// ---- first-fit allocator over [0, size) ----
+
+class Arena {
+public:
+    void reset(size_t base, size_t size)
+    {
+        free_.clear();
+        if (size > base) free_[base] = size - base;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = align_up(bytes, kAlign);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes;
+                const size_t start = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[start] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = align_up(bytes, kAlign);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t largest() const
+    {
+        size_t m = 0;
+        for (auto &kv : free_) m = std::max(m, kv.second);
+        return m;
+    }
+
+private:
+    std::map<size_t, size_t> free_;
+};
+
+struct Geometry {
+    int nx, ny, nz, tz, plane_tiles, ztiles;
+    int64_t n, ntiles;
+};
+
+Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt)
+{
+    Geometry G;
+    G.nx = g.nx; G.ny = g.ny; G.nz = g.nz;
+    G.n = (int64_t)g.nx * g.ny * g.nz;
+    G.tz = tz_opt > 0 ? tz_opt : choose_tz(G.n, prec);
+    if (G.tz > g.nz) G.tz = g.nz;
+    const int64_t plane = (int64_t)g.nx * g.ny;
+    G.plane_tiles = (int)((plane + kBlock - 1) / kBlock);
+    G.ztiles = (g.nz + G.tz - 1) / G.tz;
+    G.ntiles = (int64_t)G.plane_tiles * G.ztiles;
+    return G;
+}
+
+size_t slot_bytes(const Geometry &G, int prec)
+{
+    const size_t n = (size_t)G.n;
+    const size_t es = prec == PCG_PREC_FP32_IR ? 4 : 8;
+    size_t b = 0;
+    b += align_up(8 * n, kAlign);                    // rho64
+    if (prec == PCG_PREC_FP32_IR) b += align_up(4 * n, kAlign);  // rho32
+    b += 3 * align_up(es * n, kAlign);               // z, pa, pb
+    if (prec == PCG_PREC_FP32_IR) b += align_up(4 * n, kAlign);  // d32
+    b += align_up(kMaxPartials * 8 * (size_t)G.ntiles, kAlign);  // partials
+    return b;
+}
+
+size_t head_bytes(int max_slots)
+{
+    return align_up(sizeof(BatchHeader), kAlign) +
+           align_up(sizeof(Slot) * max_slots, kAlign) +
+           align_up(sizeof(SlotState) * max_slots, kAlign) + kAlign;  // + error flag
+}
+
+int check_grid(const pcg_grid_t *g)
+{
+    if (!g) return PCG_EINVAL;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return PCG_EINVAL;
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) return PCG_EINVAL;
+    const int64_t n = (int64_t)g->nx * g->ny * g->nz;
+    if (n >= ((int64_t)1 << 31)) return PCG_EUNSUPPORTED;
+    return PCG_OK;
+}
+
+int check_bc(const pcg_bc_t *bc, int *mask_out)
+{
+    if (!bc) return PCG_EINVAL;
+    int m = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int k = bc->kind[f];
+        if (k == PCG_BC_PERIODIC) return PCG_EUNSUPPORTED;
+        if (k != PCG_BC_NEUMANN && k != PCG_BC_DIRICHLET) return PCG_EINVAL;
+        if (k == PCG_BC_DIRICHLET) m |= 1 << f;
+    }
+    *mask_out = m;
+    return PCG_OK;
+}
+
+int check_opts(const pcg_opts_t *o)
+{
+    if (!o) return PCG_OK;
+    if (o->precision != PCG_PREC_FP64 && o->precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
+    if (o->check_every < 0 || o->inner_maxit < 0 || o->tz < 0 || o->grid_blocks < 0) return PCG_EINVAL;
+    if (o->inner_tol < 0.0 || o->inner_tol >= 1.0 || std::isnan(o->inner_tol)) return PCG_EINVAL;
+    if (o->flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK)) return PCG_EINVAL;
+    return PCG_OK;
+}
+
+// Every fluid region must reach a Dirichlet wall (flood fill on the host).
+bool fluid_reaches_dirichlet(const std::vector<uint8_t> &solid, int nx, int ny,
+                             int nz, int bcmask)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    std::vector<uint8_t> seen(n, 0);
+    std::vector<int32_t> stack;
+    stack.reserve(1 << 16);
+    auto seed = [&](int64_t c) {
+        if (!solid[c] && !seen[c]) { seen[c] = 1; stack.push_back((int32_t)c); }
+    };
+    const int64_t plane = (int64_t)nx * ny;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            const int64_t row = k * plane + (int64_t)j * nx;
+            if (bcmask & 1) seed(row);
+            if (bcmask & 2) seed(row + nx - 1);
+            if ((bcmask & 4) && j == 0)
+                for (int i = 0; i < nx; ++i) seed(row + i);
+            if ((bcmask & 8) && j == ny - 1)
+                for (int i = 0; i < nx; ++i) seed(row + i);
+            if ((bcmask & 16) && k == 0)
+                for (int i = 0; i < nx; ++i) seed(row + i);
+            if ((bcmask & 32) && k == nz - 1)
+                for (int i = 0; i < nx; ++i) seed(row + i);
+        }
+    while (!stack.empty()) {
+        const int64_t c = stack.back();
+        stack.pop_back();
+        const int i = (int)(c % nx);
+        const int j = (int)((c / nx) % ny);
+        const int k = (int)(c / plane);
+        if (i > 0) seed(c - 1);
+        if (i < nx - 1) seed(c + 1);
+        if (j > 0) seed(c - nx);
+        if (j < ny - 1) seed(c + nx);
+        if (k > 0) seed(c - plane);
+        if (k < nz - 1) seed(c + plane);
+    }
+    for (int64_t c = 0; c < n; ++c)
+        if (!solid[c] && !seen[c]) return false;
+    return true;
+}
+
+struct SlotHost {
+    bool used = false;      // holds a prepared density field
+    bool running = false;   // in the slot table
+    bool finished = false;  // completion observed on the host
+    Geometry geo{};
+    int bcmask = 0;
+    double h2 = 0.0;
+    size_t off = 0, bytes = 0;
+    double *rho64 = nullptr;
+    float *rho32 = nullptr;
+    void *z = nullptr, *pa = nullptr, *pb = nullptr;
+    float *d32 = nullptr;
+    double *partials = nullptr;
+    const double *rhs = nullptr;
+    double *x = nullptr;
+    Clock::time_point t0;
+    double ms = 0.0;
+};
+
+}  // namespace
+
+struct Engine {
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    int prec = PCG_PREC_FP64;
+    int check_every = kDefaultCheckEvery;
+    int grid = 0;
+    int grid_opt = 0;
+    int tz_opt = 0;
+    int inner_maxit = 0;
+    double inner_tol = kDefaultInnerTol;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    int max_slots = 0;
+    BatchHeader *d_hdr = nullptr;
+    Slot *d_slots = nullptr;
+    SlotState *d_states = nullptr;
+    int *d_bad = nullptr;
+    BatchHeader *h_hdr = nullptr;
+    Slot *h_slots = nullptr;
+    SlotState *h_states = nullptr;
+    int *h_bad = nullptr;
+    Arena alloc;
+    std::vector<SlotHost> slots;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool table_dirty = true;
+    int64_t total_tiles = 0;
+    int nrunning = 0;
+    // timing mode
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<float> t_k1, t_k2;
+
+    ~Engine() { teardown(); }
+
+    void teardown()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        for (auto e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        if (cap) (void)hipStreamDestroy(cap);
+        cap = nullptr;
+        if (h_hdr) (void)hipHostFree(h_hdr);
+        if (h_slots) (void)hipHostFree(h_slots);
+        if (h_states) (void)hipHostFree(h_states);
+        if (h_bad) (void)hipHostFree(h_bad);
+        h_hdr = nullptr; h_slots = nullptr; h_states = nullptr; h_bad = nullptr;
+    }
+
+    int init(void *arena_ptr, size_t bytes, int nslots, const pcg_opts_t *o,
+             void *hip_stream)
+    {
+        if (!arena_ptr || nslots < 1) return PCG_EINVAL;
+        if (((uintptr_t)arena_ptr) % kAlign) return PCG_EINVAL;
+        int st = check_opts(o);
+        if (st) return st;
+        if (o) {
+            prec = o->precision;
+            if (o->check_every > 0) check_every = o->check_every;
+            inner_maxit = o->inner_maxit;
+            if (o->inner_tol > 0.0) inner_tol = o->inner_tol;
+            tz_opt = o->tz;
+            grid_opt = o->grid_blocks;
+        }
+        arena = (char *)arena_ptr;
+        arena_bytes = bytes;
+        max_slots = nslots;
+        const size_t hb = head_bytes(nslots);
+        if (bytes < hb) return PCG_ENOMEM;
+        size_t off = 0;
+        d_hdr = (BatchHeader *)(arena + off);
+        off += align_up(sizeof(BatchHeader), kAlign);
+        d_slots = (Slot *)(arena + off);
+        off += align_up(sizeof(Slot) * nslots, kAlign);
+        d_states = (SlotState *)(arena + off);
+        off += align_up(sizeof(SlotState) * nslots, kAlign);
+        d_bad = (int *)(arena + off);
+        alloc.reset(hb, bytes);
+        slots.assign(nslots, SlotHost{});
+        stream = (hipStream_t)hip_stream;
+        HIP_TRY(hipHostMalloc((void **)&h_hdr, sizeof(BatchHeader), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void **)&h_slots, sizeof(Slot) * nslots, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void **)&h_states, sizeof(SlotState) * nslots, hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void **)&h_bad, sizeof(int), hipHostMallocDefault));
+        std::memset(h_states, 0, sizeof(SlotState) * nslots);
+        for (int i = 0; i < nslots; ++i) h_states[i].phase = PH_IDLE;
+        HIP_TRY(hipMemcpyAsync(d_states, h_states, sizeof(SlotState) * nslots,
+                               hipMemcpyHostToDevice, stream));
+        h_hdr->total_tiles = 0;
+        h_hdr->nslots = 0;
+        HIP_TRY(hipMemcpyAsync(d_hdr, h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        return PCG_OK;
+    }
+
+    size_t footprint(const pcg_grid_t &g) const
+    {
+        return slot_bytes(make_geometry(g, prec, tz_opt), prec);
+    }
+
+    // Reserve a slot and its memory, encode the density.  Does not start a solve.
+    int prepare(const pcg_grid_t *grid_, const double *rho, const uint8_t *mask,
+                const pcg_bc_t *bc, int flags, int *slot_out)
+    {
+        int st = check_grid(grid_);
+        if (st) return st;
+        int bm = 0;
+        st = check_bc(bc, &bm);
+        if (st) return st;
+        if (!rho) return PCG_EINVAL;
+        int id = -1;
+        for (int i = 0; i < max_slots; ++i)
+            if (!slots[i].used) { id = i; break; }
+        if (id < 0) return PCG_EBUSY;
+        const Geometry geo = make_geometry(*grid_, prec, tz_opt);
+        const size_t need = slot_bytes(geo, prec);
+        size_t off = 0;
+        if (!alloc.alloc(need, &off)) return max_slots == 1 ? PCG_ENOMEM : PCG_EBUSY;
+
+        // connectivity: every fluid region must touch a Dirichlet wall
+        if (!(flags & PCG_SKIP_CONNECTIVITY_CHECK)) {
+            bool ok;
+            if (mask) {
+                std::vector<uint8_t> h((size_t)geo.n);
+                hipError_t e = hipMemcpy(h.data(), mask, (size_t)geo.n, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) { alloc.release(off, need); return hip_fail(e, "mask copy"); }
+                ok = fluid_reaches_dirichlet(h, geo.nx, geo.ny, geo.nz, bm);
+            } else {
+                ok = bm != 0;
+            }
+            if (!ok) { alloc.release(off, need); return PCG_ESINGULAR; }
+        }
+
+        SlotHost &S = slots[id];
+        S = SlotHost{};
+        S.geo = geo;
+        S.bcmask = bm;
+        S.h2 = grid_->h * grid_->h;
+        S.off = off;
+        S.bytes = need;
+        const size_t n = (size_t)geo.n;
+        const size_t es = prec == PCG_PREC_FP32_IR ? 4 : 8;
+        char *p = arena + off;
+        S.rho64 = (double *)p; p += align_up(8 * n, kAlign);
+        if (prec == PCG_PREC_FP32_IR) { S.rho32 = (float *)p; p += align_up(4 * n, kAlign); }
+        S.z = p; p += align_up(es * n, kAlign);
+        S.pa = p; p += align_up(es * n, kAlign);
+        S.pb = p; p += align_up(es * n, kAlign);
+        if (prec == PCG_PREC_FP32_IR) { S.d32 = (float *)p; p += align_up(4 * n, kAlign); }
+        S.partials = (double *)p;
+
+        *h_bad = 0;
+        hipError_t e = hipMemcpyAsync(d_bad, h_bad, sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = launch_encode(rho, mask, S.rho64, S.rho32, geo.n, d_bad, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) { alloc.release(off, need); return hip_fail(e, "encode"); }
+        if (*h_bad) { alloc.release(off, need); return PCG_EDOMAIN; }
+        S.used = true;
+        *slot_out = id;
+        return PCG_OK;
+    }
+
+    // Start a solve on a prepared slot.
+    int start(int id, const double *rhs, double *x, double tol, int maxit, int flags)
+    {
+        if (id < 0 || id >= max_slots || !slots[id].used) return PCG_EINVAL;
+        if (!rhs || !x) return PCG_EINVAL;
+        if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0) return PCG_EINVAL;
+        SlotHost &S = slots[id];
+        if (S.running) return PCG_EBUSY;
+        S.rhs = rhs;
+        S.x = x;
+        S.finished = false;
+        S.ms = 0.0;
+        SlotState &h = h_states[id];
+        std::memset(&h, 0, sizeof(SlotState));
+        h.phase = prec == PCG_PREC_FP64 ? K1_INIT64 : K1_IR_INIT;
+        h.status = PCG_PENDING;
+        h.tol = tol;
+        h.maxit = maxit;
+        h.inner_maxit = inner_maxit > 0 ? inner_maxit : INT32_MAX;
+        h.inner_tol2 = inner_tol * inner_tol;
+        h.warm = (flags & PCG_WARM_START) ? 1 : 0;
+        h.scale = 1.0;
+        HIP_TRY(hipMemcpyAsync(d_states + id, &h, sizeof(SlotState), hipMemcpyHostToDevice, stream));
+        S.running = true;
+        S.t0 = Clock::now();
+        table_dirty = true;
+        return PCG_OK;
+    }
+
+    void release(int id)
+    {
+        SlotHost &S = slots[id];
+        if (!S.used) return;
+        alloc.release(S.off, S.bytes);
+        if (S.running) table_dirty = true;
+        S = SlotHost{};
+        h_states[id].phase = PH_IDLE;
+    }
+
+    int upload_table()
+    {
+        if (!table_dirty) return PCG_OK;
+        int64_t tb = 0;
+        int ns = 0;
+        for (int id = 0; id < max_slots; ++id) {
+            SlotHost &S = slots[id];
+            if (!S.used || !S.running) continue;
+            Slot &d = h_slots[ns++];
+            std::memset(&d, 0, sizeof(Slot));
+            d.nx = S.geo.nx; d.ny = S.geo.ny; d.nz = S.geo.nz;
+            d.bcmask = S.bcmask;
+            d.plane_tiles = S.geo.plane_tiles;
+            d.ztiles = S.geo.ztiles;
+            d.tz = S.geo.tz;
+            d.tile_begin = tb;
+            d.ntiles = S.geo.ntiles;
+            d.h2 = S.h2;
+            d.rhs = S.rhs;
+            d.x = S.x;
+            d.rho64 = S.rho64;
+            d.rho32 = S.rho32;
+            d.z = S.z;
+            d.pa = S.pa;
+            d.pb = S.pb;
+            d.d32 = S.d32;
+            d.partials = S.partials;
+            d.st = d_states + id;
+            tb += S.geo.ntiles;
+        }
+        h_hdr->total_tiles = tb;
+        h_hdr->nslots = ns;
+        total_tiles = tb;
+        nrunning = ns;
+        if (ns) HIP_TRY(hipMemcpyAsync(d_slots, h_slots, sizeof(Slot) * ns, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(d_hdr, h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, stream));
+        table_dirty = false;
+        return PCG_OK;
+    }
+
+    int choose_grid() const
+    {
+        const int gmax = grid_opt > 0 ? grid_opt : kDefaultGridMax;
+        int g = gmax;
+        if (max_slots == 1) {
+            int64_t t = 0;
+            for (auto &S : slots) if (S.used) t = std::max<int64_t>(t, S.geo.ntiles);
+            if (t > 0 && t < g) g = (int)t;
+        }
+        g = std::max(8, (g + 7) / 8 * 8);
+        return g;
+    }
+
+    int capture()
+    {
+        const int g = choose_grid();
+        if (exec && g == grid) return PCG_OK;
+        if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
+        if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+        grid = g;
+        HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        for (int i = 0; i < check_every && err == hipSuccess; ++i) {
+            err = launch_iter(prec, 1, grid, d_hdr, d_slots, cap);
+            if (err == hipSuccess) err = launch_iter(prec, 2, grid, d_hdr, d_slots, cap);
+        }
+        hipGraph_t gph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap, &gph);
+        if (err != hipSuccess) { if (gph) (void)hipGraphDestroy(gph); return hip_fail(err, "capture launch"); }
+        if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+        graph = gph;
+        HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        return PCG_OK;
+    }
+
+    // Direct launches with an event around each kernel (timing mode).
+    int timed_chunk()
+    {
+        const int ne = 2 * check_every + 1;
+        while ((int)ev.size() < ne) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        HIP_TRY(hipEventRecord(ev[0], stream));
+        for (int i = 0; i < check_every; ++i) {
+            HIP_TRY(launch_iter(prec, 1, grid, d_hdr, d_slots, stream));
+            HIP_TRY(hipEventRecord(ev[2 * i + 1], stream));
+            HIP_TRY(launch_iter(prec, 2, grid, d_hdr, d_slots, stream));
+            HIP_TRY(hipEventRecord(ev[2 * i + 2], stream));
+        }
+        HIP_TRY(hipEventSynchronize(ev[ne - 1]));
+        for (int i = 0; i < check_every; ++i) {
+            float a = 0.f, b = 0.f;
+            HIP_TRY(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]));
+            HIP_TRY(hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]));
+            t_k1.push_back(a);
+            t_k2.push_back(b);
+        }
+        return PCG_OK;
+    }
+
+    // Run `replays` graphs (or timed chunks), then refresh the status mirror.
+    int step(int replays)
+    {
+        int st = upload_table();
+        if (st) return st;
+        if (nrunning == 0) return PCG_OK;
+        st = capture();
+        if (st) return st;
+        for (int r = 0; r < replays; ++r) {
+            if (timing) {
+                st = timed_chunk();
+                if (st) return st;
+            } else {
+                HIP_TRY(hipGraphLaunch(exec, stream));
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(h_states, d_states, sizeof(SlotState) * max_slots,
+                               hipMemcpyDeviceToHost, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        for (int id = 0; id < max_slots; ++id) {
+            SlotHost &S = slots[id];
+            if (!S.used || !S.running) continue;
+            if (h_states[id].phase == PH_DONE) {
+                S.running = false;
+                S.finished = true;
+                S.ms = ms_since(S.t0);
+                table_dirty = true;
+            }
+        }
+        return PCG_OK;
+    }
+
+    int running_count() const
+    {
+        int n = 0;
+        for (auto &S : slots) n += S.running ? 1 : 0;
+        return n;
+    }
+
+    void fill_stats(int id, pcg_stats_t *out) const
+    {
+        const SlotState &h = h_states[id];
+        out->status = h.status;
+        out->iters = h.iter;
+        out->outer_iters = h.outer;
+        const double bb = h.bb;
+        out->rel_res_true = bb > 0 ? std::sqrt(h.rr_true / bb) : 0.0;
+        out->rel_res_recursive = bb > 0 ? std::sqrt(h.rr / bb) : 0.0;
+        if (prec == PCG_PREC_FP32_IR) out->rel_res_recursive = out->rel_res_true;
+        out->ms = slots[id].ms;
+    }
+};
+
+struct pcg_ctx {
+    Engine eng;
+    int slot = -1;
+    int flags = 0;
+    double last_k1 = 0.0, last_k2 = 0.0;
+    int last_n = 0;
+    bool have_timing = false;
+};
+
+struct pcg_batch {
+    Engine eng;
+};
+
+namespace {
+
+void average_nonempty(const std::vector<float> &t, double *avg, int *n)
+{
+    // launches that did work dominate; an early-exit launch (solve already
+    // finished) is far shorter than the median working launch
+    if (t.empty()) { *avg = 0.0; *n = 0; return; }
+    std::vector<float> s(t);
+    std::sort(s.begin(), s.end());
+    const float med = s[s.size() / 2];
+    double sum = 0.0;
+    int c = 0;
+    for (float v : t)
+        if (v >= 0.25f * med) { sum += v; ++c; }
+    *avg = c ? sum / c : 0.0;
+    *n = c;
+}
+
+}  // namespace
+
+// ======================================================================
+// C ABI
+// ======================================================================
+
+extern "C" {
+
+int pcg_workspace_bytes(const pcg_grid_t *grid, const pcg_opts_t *opts,
+                        size_t *out_bytes)
+{
+    if (!out_bytes) return PCG_EINVAL;
+    int st = check_grid(grid);
+    if (st) return st;
+    st = check_opts(opts);
+    if (st) return st;
+    const int prec = opts ? opts->precision : PCG_PREC_FP64;
+    const Geometry G = make_geometry(*grid, prec, opts ? opts->tz : 0);
+    *out_bytes = head_bytes(1) + slot_bytes(G, prec);
+    return PCG_OK;
+}
+
+int pcg_setup(pcg_ctx_t **out, const pcg_grid_t *grid, const double *rho,
+              const uint8_t *solid_mask, const pcg_bc_t *bc,
+              const pcg_opts_t *opts, void *workspace, size_t ws_bytes,
+              void *hip_stream)
+{
+    if (!out) return PCG_EINVAL;
+    *out = nullptr;
+    int st = check_grid(grid);
+    if (st) return st;
+    int bm = 0;
+    st = check_bc(bc, &bm);
+    if (st) return st;
+    st = check_opts(opts);
+    if (st) return st;
+    if (!rho || !workspace) return PCG_EINVAL;
+    size_t need = 0;
+    pcg_workspace_bytes(grid, opts, &need);
+    if (ws_bytes < need) return PCG_ENOMEM;
+    pcg_ctx *c = new (std::nothrow) pcg_ctx();
+    if (!c) return PCG_ENOMEM;
+    st = c->eng.init(workspace, ws_bytes, 1, opts, hip_stream);
+    if (st) { delete c; return st; }
+    c->flags = opts ? opts->flags : 0;
+    st = c->eng.prepare(grid, rho, solid_mask, bc, c->flags, &c->slot);
+    if (st) { delete c; return st; }
+    *out = c;
+    return PCG_OK;
+}
+
+int pcg_solve(pcg_ctx_t *c, const double *rhs, double *p, double tol,
+              int32_t maxit, pcg_stats_t *stats)
+{
+    if (!c) return PCG_EINVAL;
+    const auto t0 = Clock::now();
+    int st = c->eng.start(c->slot, rhs, p, tol, maxit, c->flags);
+    if (st) return st;
+    c->eng.t_k1.clear();
+    c->eng.t_k2.clear();
+    // every replay advances a running solve (its iteration count or its
+    // phase); a solve that stops moving is reported instead of polled forever
+    int last_iter = -1, last_phase = -1, still = 0;
+    while (c->eng.slots[c->slot].running) {
+        st = c->eng.step(1);
+        if (st) return st;
+        const SlotState &h = c->eng.h_states[c->slot];
+        if (h.iter == last_iter && h.phase == last_phase) {
+            if (++still >= 4) {
+                g_hip_err = "solve made no progress";
+                return PCG_EHIP;
+            }
+        } else {
+            still = 0;
+        }
+        last_iter = h.iter;
+        last_phase = h.phase;
+    }
+    if (c->eng.timing) {
+        average_nonempty(c->eng.t_k1, &c->last_k1, &c->last_n);
+        int n2 = 0;
+        average_nonempty(c->eng.t_k2, &c->last_k2, &n2);
+        c->have_timing = true;
+    }
+    pcg_stats_t s;
+    c->eng.fill_stats(c->slot, &s);
+    s.ms = ms_since(t0);
+    if (stats) *stats = s;
+    return s.status;
+}
+
+int pcg_destroy(pcg_ctx_t *c)
+{
+    delete c;
+    return PCG_OK;
+}
+
+const char *pcg_strerror(int code)
+{
+    switch (code) {
+    case PCG_OK: return "ok";
+    case PCG_MAXIT: return "iteration limit reached";
+    case PCG_PENDING: return "solve still running";
+    case PCG_EINVAL: return "invalid argument";
+    case PCG_EDOMAIN: return "density not positive and finite in a fluid cell, or non-finite source";
+    case PCG_ESINGULAR: return "a fluid region touches no Dirichlet wall";
+    case PCG_EBREAKDOWN: return "conjugate-gradient breakdown (p.Ap <= 0 or not finite)";
+    case PCG_ENOMEM: return "workspace or arena too small";
+    case PCG_EBUSY: return "admission refused: no free slot or not enough arena memory";
+    case PCG_EHIP: return "HIP runtime error";
+    case PCG_EUNSUPPORTED: return "unsupported: periodic walls or grid too large";
+    default: return "unknown status";
+    }
+}
+
+const char *pcg_last_hip_error(void) { return g_hip_err.c_str(); }
+
+int pcg_set_timing(pcg_ctx_t *c, int32_t on)
+{
+    if (!c) return PCG_EINVAL;
+    c->eng.timing = on != 0;
+    return PCG_OK;
+}
+
+int pcg_last_timing(pcg_ctx_t *c, double *ms_k1, double *ms_k2, int32_t *n)
+{
+    if (!c || !c->have_timing) return PCG_EINVAL;
+    if (ms_k1) *ms_k1 = c->last_k1;
+    if (ms_k2) *ms_k2 = c->last_k2;
+    if (n) *n = c->last_n;
+    return PCG_OK;
+}
+
+int pcg_batch_create(pcg_batch_t **out, void *arena, size_t arena_bytes,
+                     int32_t max_slots, const pcg_opts_t *opts, void *hip_stream)
+{
+    if (!out) return PCG_EINVAL;
+    *out = nullptr;
+    if (max_slots < 1) return PCG_EINVAL;
+    pcg_batch *b = new (std::nothrow) pcg_batch();
+    if (!b) return PCG_ENOMEM;
+    int st = b->eng.init(arena, arena_bytes, max_slots, opts, hip_stream);
+    if (st) { delete b; return st; }
+    *out = b;
+    return PCG_OK;
+}
+
+int pcg_batch_footprint(const pcg_batch_t *b, const pcg_grid_t *grid,
+                        size_t *out_bytes)
+{
+    if (!b || !out_bytes) return PCG_EINVAL;
+    int st = check_grid(grid);
+    if (st) return st;
+    *out_bytes = align_up(b->eng.footprint(*grid), kAlign);
+    return PCG_OK;
+}
+
+int pcg_batch_admit(pcg_batch_t *b, const pcg_grid_t *grid, const double *rho,
+                    const uint8_t *mask, const pcg_bc_t *bc, const double *rhs,
+                    double *p, double tol, int32_t maxit, int32_t flags,
+                    int32_t *slot)
+{
+    if (!b || !slot || !rhs || !p) return PCG_EINVAL;
+    if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0) return PCG_EINVAL;
+    if (flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK)) return PCG_EINVAL;
+    int id = -1;
+    int st = b->eng.prepare(grid, rho, mask, bc, flags, &id);
+    if (st) return st;
+    st = b->eng.start(id, rhs, p, tol, maxit, flags);
+    if (st) { b->eng.release(id); return st; }
+    *slot = id;
+    return PCG_OK;
+}
+
+int pcg_batch_step(pcg_batch_t *b, int32_t replays, int32_t *active_out)
+{
+    if (!b || replays < 1) return PCG_EINVAL;
+    int st = b->eng.step(replays);
+    if (st) return st;
+    if (active_out) *active_out = b->eng.running_count();
+    return PCG_OK;
+}
+
+int pcg_batch_poll(pcg_batch_t *b, int32_t slot, pcg_stats_t *stats)
+{
+    if (!b || slot < 0 || slot >= b->eng.max_slots || !b->eng.slots[slot].used)
+        return PCG_EINVAL;
+    const SlotHost &S = b->eng.slots[slot];
+    if (S.running) {
+        if (stats) { std::memset(stats, 0, sizeof(*stats)); stats->status = PCG_PENDING; }
+        return PCG_PENDING;
+    }
+    pcg_stats_t s;
+    b->eng.fill_stats(slot, &s);
+    if (stats) *stats = s;
+    return s.status;
+}
+
+int pcg_batch_release(pcg_batch_t *b, int32_t slot)
+{
+    if (!b || slot < 0 || slot >= b->eng.max_slots || !b->eng.slots[slot].used)
+        return PCG_EINVAL;
+    b->eng.release(slot);
+    return PCG_OK;
+}
+
+int pcg_batch_destroy(pcg_batch_t *b)
+{
+    if (b) (void)hipStreamSynchronize(b->eng.stream);
+    delete b;
+    return PCG_OK;
+}
+
+int pcg_copy_probe(const double *src, double *dst, size_t n, int32_t reps,
+                   void *hip_stream, double *ms_per_copy)
+{
+    if (!src || !dst || n < 2 || reps < 1 || !ms_per_copy) return PCG_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(launch_copy(src, dst, n, s));
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) HIP_TRY(launch_copy(src, dst, n, s));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms_per_copy = ms / reps;
+    return PCG_OK;
+}
+
+}  // extern "C"

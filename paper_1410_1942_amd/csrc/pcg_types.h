@@ -1,0 +1,92 @@
+// Internal layout shared by the host engine and the device kernels.
+//
+// A "slot" is one resident solve.  Every launch covers all tiles of all
+// active slots; each slot carries its own scalars and a small state machine
+// that the last-arriving workgroup of a launch advances.  A single solve is
+// a batch of one slot.
+#pragma once
+#include <stdint.h>
+
+namespace pcgmi {
+
+constexpr int kBlock = 256;       // threads per workgroup = cells per plane tile
+constexpr int kMaxPartials = 3;   // reduction values per tile
+
+// Next action of a slot.  Launches alternate K1, K2, K1, K2, ...; a K1
+// action is always followed by a K2 action and vice versa.
+enum Phase : int32_t {
+    PH_IDLE = 0,       // empty slot or finished solve: no work, no state change
+    // K1 actions (first launch of an iteration)
+    K1_INIT64 = 1,     // b = -h^2 Sigma, x = 0 (or r = b - A x0), z = D^-1 r
+    K1_CG_A = 2,       // p = z + beta p ; p.Ap
+    K1_CHECK64 = 3,    // true residual ||b - A x||
+    K1_IR_INIT = 4,    // ||b||, x = 0 (or solids zeroed), d = 0
+    K1_IR_RESID = 5,   // r = b - A (x + s d) in FP64, z32 = D32^-1 (scale r)
+    K1_IR_A = 6,       // FP32 p = z + beta p ; p.Ap (FP64 sum)
+    // K2 actions (second launch of an iteration)
+    K2_NONE = 11,      // nothing; then the K1 action in `after`
+    K2_CG_B = 12,      // q = A p, x += alpha p, z -= alpha D^-1 q ; r.z, r.r
+    K2_IR_B = 13,      // FP32 d += alpha p, z -= alpha D^-1 q ; r.z, r.r (FP64)
+    K2_IR_UPDATE = 14, // x += s d, d = 0
+    K2_ZERO_X = 15,    // x = 0 (zero source with a warm start)
+    PH_DONE = 20
+};
+
+// Device-resident, mutated only by the last workgroup of each launch.
+struct alignas(128) SlotState {
+    double rz;        // r.z of the current iterate (preconditioned)
+    double pap;       // p.A p
+    double alpha, beta;
+    double bb;        // ||b||^2
+    double tol2;      // tol^2 * ||b||^2
+    double rr;        // recursive ||r||^2 (FP64) or inner ||r||^2 (IR)
+    double rr_true;   // last FP64 recomputed ||b - A x||^2
+    double rr0_inner; // IR: ||r||^2 at the start of the inner solve
+    double inner_tol2;// IR: (inner reduction)^2
+    double scale;     // IR: power-of-two scale of the current inner system
+    double upd_s;     // IR: multiplier of the pending update x += upd_s * d
+    double tol;
+    int32_t phase;
+    int32_t after;    // K1 action after a K2_NONE
+    int32_t status;   // PCG_PENDING while running, else the final code
+    int32_t iter;     // CG iterations (inner iterations for IR)
+    int32_t outer;    // IR refinement trips
+    int32_t inner_iter;
+    int32_t maxit, inner_maxit;
+    int32_t first;    // next pass A uses beta = 0
+    int32_t pbuf;     // which p buffer holds the current direction
+    int32_t final_upd;// IR: the pending update is the last one
+    uint32_t ticket;  // arrivals of the current launch
+    int32_t warm;     // warm start requested
+    int32_t pad_[3];
+};
+
+// Read-only description of a slot (rewritten by the host between replays).
+struct Slot {
+    int32_t nx, ny, nz;
+    int32_t bcmask;        // bit f set: wall f is Dirichlet (x-,x+,y-,y+,z-,z+)
+    int32_t plane_tiles;   // ceil(nx*ny / kBlock)
+    int32_t ztiles;        // ceil(nz / tz)
+    int32_t tz;            // planes per tile
+    int32_t pad0;
+    int64_t tile_begin;    // first global tile of this slot
+    int64_t ntiles;        // plane_tiles * ztiles
+    double h2;             // h*h
+    const double *rhs;     // caller's Sigma
+    double *x;             // caller's p (the CG iterate)
+    const double *rho64;   // density, +inf in solid cells
+    const float *rho32;    // IR only
+    void *z;               // D^-1 r   (double, or float for IR)
+    void *pa, *pb;         // search direction, ping-pong
+    float *d32;            // IR inner correction
+    double *partials;      // kMaxPartials * ntiles
+    SlotState *st;
+};
+
+struct BatchHeader {
+    int64_t total_tiles;
+    int32_t nslots;
+    int32_t pad;
+};
+
+}  // namespace pcgmi

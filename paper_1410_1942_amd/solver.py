@@ -1,0 +1,206 @@
+"""Python front end of the HIP pressure solver.
+
+PyTorch supplies device memory and the HIP stream; every step of the solve
+runs in the library behind include/pcg.h (see _lib).  There is no CPU path:
+constructing a Solver or Batch without the built library or without a GPU
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+
+def _grid(shape_zyx, h) -> L.Grid:
+    nz, ny, nx = shape_zyx
+    return L.Grid(int(nx), int(ny), int(nz), float(h))
+
+
+def _bc(bc: Sequence[int]) -> L.BC:
+    b = L.BC()
+    for f in range(6):
+        b.kind[f] = int(bc[f])
+    return b
+
+
+def make_opts(precision: int = L.PREC_FP64, check_every: int = 0,
+              flags: int = 0, inner_maxit: int = 0, inner_tol: float = 0.0,
+              tz: int = 0, grid_blocks: int = 0) -> L.Opts:
+    return L.Opts(int(precision), int(check_every), int(flags),
+                  int(inner_maxit), float(inner_tol), int(tz), int(grid_blocks))
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require_device(*ts):
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("arrays must be contiguous device tensors")
+
+
+class Solver:
+    """One density field, any number of solves (pcg_setup / pcg_solve).
+
+    rho: float64 [nz, ny, nx] device tensor; mask: uint8 (1 = hull) or None;
+    bc: six wall kinds (x-, x+, y-, y+, z-, z+), 0 Neumann / 1 Dirichlet.
+    """
+
+    def __init__(self, rho: torch.Tensor, mask: Optional[torch.Tensor], bc,
+                 h: float, precision: int = L.PREC_FP64, flags: int = 0,
+                 stream: Optional[torch.cuda.Stream] = None, **opt_kw):
+        lib = L.load()
+        _require_device(rho, mask)
+        if rho.dtype != torch.float64:
+            raise ValueError("rho must be float64")
+        if mask is not None and mask.dtype != torch.uint8:
+            raise ValueError("mask must be uint8")
+        self.shape = tuple(rho.shape)
+        self.grid = _grid(self.shape, h)
+        self.opts = make_opts(precision=precision, flags=flags, **opt_kw)
+        nbytes = ctypes.c_size_t(0)
+        L.check(lib.pcg_workspace_bytes(ctypes.byref(self.grid),
+                                        ctypes.byref(self.opts),
+                                        ctypes.byref(nbytes)), "workspace")
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8,
+                                     device=rho.device)
+        self._stream = _stream_handle(stream)
+        self._ctx = ctypes.c_void_p()
+        L.check(lib.pcg_setup(ctypes.byref(self._ctx), ctypes.byref(self.grid),
+                              _ptr(rho), _ptr(mask), ctypes.byref(_bc(bc)),
+                              ctypes.byref(self.opts), _ptr(self.workspace),
+                              nbytes.value, self._stream), "pcg_setup")
+        self.lib = lib
+
+    def solve(self, rhs: torch.Tensor, p: Optional[torch.Tensor] = None,
+              tol: float = 1e-8, maxit: int = 1000000, raise_on_error=True):
+        """Solve L p = rhs.  Returns (p, stats dict)."""
+        _require_device(rhs)
+        if rhs.dtype != torch.float64 or tuple(rhs.shape) != self.shape:
+            raise ValueError("rhs must be float64 with the grid's shape")
+        if p is None:
+            p = torch.empty_like(rhs)
+        _require_device(p)
+        st = L.Stats()
+        code = self.lib.pcg_solve(self._ctx, _ptr(rhs), _ptr(p), float(tol),
+                                  int(maxit), ctypes.byref(st))
+        if raise_on_error:
+            L.check(code, "pcg_solve")
+        return p, st.as_dict()
+
+    def set_timing(self, on: bool = True):
+        L.check(self.lib.pcg_set_timing(self._ctx, int(on)), "pcg_set_timing")
+
+    def last_timing(self):
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        L.check(self.lib.pcg_last_timing(self._ctx, ctypes.byref(a),
+                                         ctypes.byref(b), ctypes.byref(n)),
+                "pcg_last_timing")
+        return a.value, b.value, n.value
+
+    def close(self):
+        if self._ctx:
+            self.lib.pcg_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Resident solves advanced together (pcg_batch_*).
+
+    The arena is one device tensor of ``arena_bytes``; admission fails with
+    PCG_EBUSY (returned, not raised) when a solve does not fit.
+    """
+
+    def __init__(self, arena_bytes: int, max_slots: int,
+                 precision: int = L.PREC_FP32_IR, device="cuda",
+                 stream: Optional[torch.cuda.Stream] = None, **opt_kw):
+        lib = L.load()
+        self.lib = lib
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8,
+                                 device=device)
+        self.opts = make_opts(precision=precision, **opt_kw)
+        self._b = ctypes.c_void_p()
+        L.check(lib.pcg_batch_create(ctypes.byref(self._b), _ptr(self.arena),
+                                     int(arena_bytes), int(max_slots),
+                                     ctypes.byref(self.opts),
+                                     _stream_handle(stream)), "pcg_batch_create")
+        self._keep = {}
+
+    def footprint(self, shape_zyx, h=1.0) -> int:
+        out = ctypes.c_size_t()
+        g = _grid(shape_zyx, h)
+        L.check(self.lib.pcg_batch_footprint(self._b, ctypes.byref(g),
+                                             ctypes.byref(out)), "footprint")
+        return int(out.value)
+
+    def admit(self, rho, mask, bc, h, rhs, p, tol=1e-8, maxit=1000000,
+              flags=0):
+        """Returns (status, slot).  status PCG_EBUSY means "try later"."""
+        _require_device(rho, mask, rhs, p)
+        g = _grid(tuple(rho.shape), h)
+        slot = ctypes.c_int32(-1)
+        code = self.lib.pcg_batch_admit(self._b, ctypes.byref(g), _ptr(rho),
+                                        _ptr(mask), ctypes.byref(_bc(bc)),
+                                        _ptr(rhs), _ptr(p), float(tol),
+                                        int(maxit), int(flags),
+                                        ctypes.byref(slot))
+        if code == L.EBUSY:
+            return code, -1
+        L.check(code, "pcg_batch_admit")
+        self._keep[slot.value] = (rhs, p)
+        return code, slot.value
+
+    def step(self, replays: int = 1) -> int:
+        active = ctypes.c_int32()
+        L.check(self.lib.pcg_batch_step(self._b, int(replays),
+                                        ctypes.byref(active)), "pcg_batch_step")
+        return active.value
+
+    def poll(self, slot: int):
+        st = L.Stats()
+        code = self.lib.pcg_batch_poll(self._b, int(slot), ctypes.byref(st))
+        return code, st.as_dict()
+
+    def release(self, slot: int):
+        L.check(self.lib.pcg_batch_release(self._b, int(slot)), "release")
+        self._keep.pop(slot, None)
+
+    def close(self):
+        if self._b:
+            self.lib.pcg_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def copy_probe(n_doubles: int, reps: int = 20, device="cuda") -> float:
+    """Achieved copy bandwidth (GB/s, read + write) of a plain copy kernel."""
+    lib = L.load()
+    src = torch.ones(n_doubles, dtype=torch.float64, device=device)
+    dst = torch.empty_like(src)
+    ms = ctypes.c_double()
+    L.check(lib.pcg_copy_probe(_ptr(src), _ptr(dst), n_doubles, int(reps),
+                               _stream_handle(None), ctypes.byref(ms)), "probe")
+    return 2 * 8 * n_doubles / (ms.value * 1e-3) / 1e9

@@ -1,0 +1,115 @@
+"""The C ABI library loads and exports what include/pcg.h declares; host-side
+argument validation answers without touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1410_1942_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pcg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcg_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return L.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_strerror(lib):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7, -8):
+        assert lib.pcg_strerror(code)
+    assert b"unknown" in lib.pcg_strerror(99)
+
+
+def _g(nx, ny, nz, h=0.1):
+    return L.Grid(nx, ny, nz, h)
+
+
+def test_workspace_bytes_validation(lib):
+    out = ctypes.c_size_t()
+    o = L.Opts()
+    assert lib.pcg_workspace_bytes(ctypes.byref(_g(32, 32, 32)), ctypes.byref(o),
+                                   ctypes.byref(out)) == L.OK
+    n = 32 ** 3
+    assert out.value >= 32 * n                 # rho, z, p, p' in FP64
+    assert out.value < 40 * n
+    o.precision = L.PREC_FP32_IR
+    out_ir = ctypes.c_size_t()
+    assert lib.pcg_workspace_bytes(ctypes.byref(_g(32, 32, 32)), ctypes.byref(o),
+                                   ctypes.byref(out_ir)) == L.OK
+    assert 28 * n <= out_ir.value < 36 * n
+    for bad in (_g(0, 4, 4), _g(4, -1, 4), _g(4, 4, 4, 0.0), _g(4, 4, 4, float("nan"))):
+        assert lib.pcg_workspace_bytes(ctypes.byref(bad), None, ctypes.byref(out)) == L.EINVAL
+    big = _g(2048, 1024, 1024)
+    assert lib.pcg_workspace_bytes(ctypes.byref(big), None, ctypes.byref(out)) == L.EUNSUPPORTED
+    o2 = L.Opts()
+    o2.precision = 7
+    assert lib.pcg_workspace_bytes(ctypes.byref(_g(4, 4, 4)), ctypes.byref(o2),
+                                   ctypes.byref(out)) == L.EINVAL
+    o2 = L.Opts()
+    o2.inner_tol = 1.5
+    assert lib.pcg_workspace_bytes(ctypes.byref(_g(4, 4, 4)), ctypes.byref(o2),
+                                   ctypes.byref(out)) == L.EINVAL
+
+
+def test_setup_validation_without_device_work(lib):
+    ctx = ctypes.c_void_p()
+    g = _g(8, 8, 8)
+    bc = L.BC()
+    bc.kind[5] = L.BC_DIRICHLET
+    fake = ctypes.c_void_p(0x1000)
+    # null output, null rho, null workspace
+    assert lib.pcg_setup(None, ctypes.byref(g), fake, None, ctypes.byref(bc), None,
+                         fake, 1 << 20, None) == L.EINVAL
+    assert lib.pcg_setup(ctypes.byref(ctx), ctypes.byref(g), None, None,
+                         ctypes.byref(bc), None, fake, 1 << 20, None) == L.EINVAL
+    assert lib.pcg_setup(ctypes.byref(ctx), ctypes.byref(g), fake, None,
+                         ctypes.byref(bc), None, None, 1 << 20, None) == L.EINVAL
+    # periodic walls are not supported; unknown kinds are invalid
+    bp = L.BC()
+    bp.kind[0] = bp.kind[1] = L.BC_PERIODIC
+    bp.kind[5] = L.BC_DIRICHLET
+    assert lib.pcg_setup(ctypes.byref(ctx), ctypes.byref(g), fake, None,
+                         ctypes.byref(bp), None, fake, 1 << 20, None) == L.EUNSUPPORTED
+    bx = L.BC()
+    bx.kind[2] = 9
+    assert lib.pcg_setup(ctypes.byref(ctx), ctypes.byref(g), fake, None,
+                         ctypes.byref(bx), None, fake, 1 << 20, None) == L.EINVAL
+    # workspace too small
+    assert lib.pcg_setup(ctypes.byref(ctx), ctypes.byref(g), fake, None,
+                         ctypes.byref(bc), None, fake, 1024, None) == L.ENOMEM
+    assert not ctx.value
+
+
+def test_null_handles(lib):
+    st = L.Stats()
+    assert lib.pcg_solve(None, None, None, 1e-8, 10, ctypes.byref(st)) == L.EINVAL
+    assert lib.pcg_destroy(None) == L.OK
+    assert lib.pcg_batch_step(None, 1, None) == L.EINVAL
+    assert lib.pcg_batch_poll(None, 0, None) == L.EINVAL
+    assert lib.pcg_batch_release(None, 0) == L.EINVAL
+    assert lib.pcg_batch_destroy(None) == L.OK
+    b = ctypes.c_void_p()
+    assert lib.pcg_batch_create(ctypes.byref(b), ctypes.c_void_p(0x1000), 1 << 20, 0,
+                                None, None) == L.EINVAL
+    assert lib.pcg_last_timing(None, None, None, None) == L.EINVAL
+    ms = ctypes.c_double()
+    assert lib.pcg_copy_probe(None, None, 0, 1, None, ctypes.byref(ms)) == L.EINVAL

@@ -1,0 +1,281 @@
+"""HIP path vs the CPU reference, element by element, through the C ABI.
+
+Bar: the GPU solution's relative residual, recomputed by the reference in
+FP64, is <= tol; max|p - p_ref| / max|p_ref| <= 1e-6 against the reference
+solved to 1e-12; iteration counts of the FP64 solver within 2% of the
+reference's (same start, preconditioner and stop rule).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TANK = (0, 0, 0, 0, 0, 1)
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+def _to(torch, dev, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def gpu_solve(torch_dev, case, tol=1e-8, precision=0, maxit=1000000,
+              flags=0, p0=None, **kw):
+    torch, dev = torch_dev
+    from paper_1410_1942_amd.solver import Solver
+    rho = _to(torch, dev, case.rho)
+    mask = _to(torch, dev, case.mask)
+    rhs = _to(torch, dev, case.rhs)
+    s = Solver(rho, mask, case.bc, case.h, precision=precision, flags=flags, **kw)
+    p = _to(torch, dev, p0) if p0 is not None else torch.empty_like(rhs)
+    p, st = s.solve(rhs, p=p, tol=tol, maxit=maxit, raise_on_error=False)
+    torch.cuda.synchronize()
+    s.close()
+    return p.cpu().numpy(), st
+
+
+def _two_phase(F, nx, ny, nz, wedge=True, bc=TANK, s1=1, s2=2):
+    return F.make_two_phase(nx, ny, nz, surface_seed=s1, velocity_seed=s2,
+                            wedge=F.Wedge() if wedge else None, bc=bc)
+
+
+def _check_against_oracle(orc, case, p, st, tol, ref=None, iters_ref=None):
+    rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p)
+    assert st["status"] == 0, st
+    assert rr <= tol, (rr, st)
+    assert abs(st["rel_res_true"] - rr) <= 1e-3 * rr + 1e-15
+    if ref is None:
+        ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-12).p
+    scale = np.abs(ref).max()
+    err = np.abs(p - ref).max() / scale
+    assert err <= 1e-6, err
+    assert np.all(p[case.mask.astype(bool)] == 0.0)
+    return rr, err
+
+
+# ---------------------------------------------------------------------------
+# FP64 solver
+# ---------------------------------------------------------------------------
+
+def test_flat_tank_32(orc, F, torch_dev):
+    """32^3 flat interface, Neumann walls and p = 0 on top, seed 0."""
+    case = F.config1(32)
+    _say("case flat32 fp64")
+    p, st = gpu_solve(torch_dev, case, tol=1e-8)
+    o8 = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-8)
+    _check_against_oracle(orc, case, p, st, 1e-8)
+    assert abs(st["iters"] - o8.iters) <= max(1, 0.02 * o8.iters), (st, o8)
+
+
+SHAPES = [
+    ((37, 29, 23), TANK, True),        # ragged plane tiles, wedge
+    ((64, 48, 40), (1, 0, 0, 1, 0, 1), True),
+    ((300, 7, 5), TANK, False),        # plane of 2100 cells: 9 tiles, tail
+    ((5, 6, 70), (1, 1, 1, 1, 1, 1), True),
+    ((1, 1, 9), TANK, False),          # a single column
+    ((17, 1, 1), (1, 0, 0, 0, 0, 0), False),
+    ((256, 3, 4), TANK, False),        # plane exactly 3 tiles
+]
+
+
+@pytest.mark.parametrize("shape,bc,wedge", SHAPES, ids=lambda v: str(v))
+def test_fp64_shapes(orc, F, torch_dev, shape, bc, wedge):
+    nx, ny, nz = shape
+    case = _two_phase(F, nx, ny, nz, wedge=wedge, bc=bc)
+    _say(f"case fp64 {shape} bc={bc} wedge={wedge}")
+    p, st = gpu_solve(torch_dev, case, tol=1e-8)
+    o8 = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-8)
+    _check_against_oracle(orc, case, p, st, 1e-8)
+    assert abs(st["iters"] - o8.iters) <= max(2, 0.02 * o8.iters), (st, o8)
+
+
+@pytest.mark.parametrize("tz", [1, 3, 8, 64])
+def test_tile_heights(orc, F, torch_dev, tz):
+    """Results hold for any tile height, including ones that leave a tail."""
+    case = _two_phase(F, 40, 33, 27)
+    _say(f"case tz={tz}")
+    p, st = gpu_solve(torch_dev, case, tol=1e-8, tz=tz)
+    _check_against_oracle(orc, case, p, st, 1e-8)
+
+
+def test_hand_solved_on_gpu(torch_dev):
+    """The hand-solved problems of the golden file, through the HIP path."""
+    import json
+    import os
+    from paper_1410_1942_amd.fields import Case
+    cases = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                        "hand_solved.json")))["cases"]
+    for c in cases:
+        shp = (c["nz"], c["ny"], c["nx"])
+        case = Case(c["nx"], c["ny"], c["nz"], c["h"],
+                    np.array(c["rho"], float).reshape(shp),
+                    np.array(c["mask"], np.uint8).reshape(shp), tuple(c["bc"]),
+                    1.0, None, None, None, np.array(c["rhs"], float).reshape(shp))
+        _say(f"case golden {c['name']}")
+        p, st = gpu_solve(torch_dev, case, tol=1e-13, maxit=100)
+        assert st["status"] == 0, (c["name"], st)
+        np.testing.assert_allclose(p.ravel(), c["p"], rtol=1e-11, atol=1e-11)
+
+
+def test_projection_divergence_gpu(orc, F, torch_dev):
+    """The GPU pressure makes the projected velocity divergence-free to tol."""
+    case = _two_phase(F, 48, 40, 36)
+    _say("case projection")
+    p, st = gpu_solve(torch_dev, case, tol=1e-8)
+    u, v, w = orc.project(case.rho, case.mask, case.bc, case.h, case.dt, p,
+                          case.u, case.v, case.w)
+    d0 = orc.divergence(case.u, case.v, case.w, case.h)
+    d1 = orc.divergence(u, v, w, case.h)
+    assert np.linalg.norm(d1) <= 1e-8 * np.linalg.norm(d0)
+
+
+def test_deterministic(F, torch_dev):
+    case = _two_phase(F, 70, 50, 30)
+    _say("case determinism")
+    p1, s1 = gpu_solve(torch_dev, case)
+    p2, s2 = gpu_solve(torch_dev, case)
+    assert s1["iters"] == s2["iters"]
+    assert np.array_equal(p1, p2)
+
+
+def test_grid_size_does_not_change_result(F, torch_dev):
+    """Per-tile partial sums make the result independent of the launch grid."""
+    case = _two_phase(F, 70, 50, 30)
+    _say("case grid blocks")
+    p1, _ = gpu_solve(torch_dev, case, grid_blocks=8)
+    p2, _ = gpu_solve(torch_dev, case, grid_blocks=1024)
+    assert np.array_equal(p1, p2)
+
+
+# ---------------------------------------------------------------------------
+# edge cases and failures
+# ---------------------------------------------------------------------------
+
+def test_zero_source(F, torch_dev):
+    case = _two_phase(F, 20, 16, 12)
+    case.rhs[:] = 0.0
+    p, st = gpu_solve(torch_dev, case, p0=np.full(case.shape, 7.0),
+                      flags=1)   # warm start with garbage: still p = 0
+    assert st["status"] == 0 and st["iters"] == 0
+    assert not p.any()
+    p, st = gpu_solve(torch_dev, case)
+    assert st["status"] == 0 and st["iters"] == 0 and not p.any()
+
+
+def test_maxit_and_warm_resume(orc, F, torch_dev):
+    case = _two_phase(F, 32, 24, 20)
+    _say("case maxit")
+    p, st = gpu_solve(torch_dev, case, maxit=0)
+    assert st["status"] == 1 and st["iters"] == 0
+    assert abs(st["rel_res_true"] - 1.0) < 1e-12
+    p, st = gpu_solve(torch_dev, case, maxit=15)
+    assert st["status"] == 1 and st["iters"] == 15
+    rr15 = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p)
+    assert abs(rr15 - st["rel_res_true"]) <= 1e-6 * rr15
+    # resume from the capped iterate
+    p2, st2 = gpu_solve(torch_dev, case, p0=p, flags=1)
+    assert st2["status"] == 0
+    rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p2)
+    assert rr <= 1e-8
+
+
+def test_warm_start_with_solution(orc, F, torch_dev):
+    case = _two_phase(F, 24, 20, 16)
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-12).p
+    p, st = gpu_solve(torch_dev, case, p0=ref, flags=1)
+    assert st["status"] == 0 and st["iters"] == 0
+
+
+def test_errors(F, torch_dev):
+    from paper_1410_1942_amd import _lib as L
+    case = _two_phase(F, 12, 10, 8, wedge=False)
+    bad = case.rhs.copy()
+    bad[3, 3, 3] = np.nan
+    c2 = _two_phase(F, 12, 10, 8, wedge=False)
+    c2.rhs = bad
+    _, st = gpu_solve(torch_dev, c2)
+    assert st["status"] == L.EDOMAIN
+    c3 = _two_phase(F, 12, 10, 8, wedge=False)
+    c3.rho[2, 2, 2] = -1.0
+    with pytest.raises(L.PCGError) as e:
+        gpu_solve(torch_dev, c3)
+    assert e.value.code == L.EDOMAIN
+    c3.mask[2, 2, 2] = 1            # negative density inside the hull is ignored
+    _, st = gpu_solve(torch_dev, c3)
+    assert st["status"] == 0
+    c4 = _two_phase(F, 12, 10, 8, wedge=False, bc=(0,) * 6)
+    with pytest.raises(L.PCGError) as e:
+        gpu_solve(torch_dev, c4)
+    assert e.value.code == L.ESINGULAR
+    c5 = _two_phase(F, 8, 8, 8, wedge=False)
+    c5.mask[0:2, 0:3, 0:3] = 1
+    c5.mask[0, 1, 1] = 0            # sealed pocket
+    with pytest.raises(L.PCGError) as e:
+        gpu_solve(torch_dev, c5)
+    assert e.value.code == L.ESINGULAR
+
+
+# ---------------------------------------------------------------------------
+# FP32 stencil with FP64 iterative refinement
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape,wedge", [((32, 32, 32), False), ((45, 38, 33), True),
+                                         ((96, 64, 80), True)])
+def test_ir_parity(orc, F, torch_dev, shape, wedge):
+    nx, ny, nz = shape
+    case = _two_phase(F, nx, ny, nz, wedge=wedge)
+    _say(f"case ir {shape}")
+    p, st = gpu_solve(torch_dev, case, tol=1e-8, precision=1)
+    assert st["outer_iters"] >= 2
+    _check_against_oracle(orc, case, p, st, 1e-8)
+
+
+def test_ir_tolerances(orc, F, torch_dev):
+    case = _two_phase(F, 40, 30, 36)
+    for tol in (1e-6, 1e-10):
+        _say(f"case ir tol {tol}")
+        p, st = gpu_solve(torch_dev, case, tol=tol, precision=1)
+        assert st["status"] == 0, st
+        rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p)
+        assert rr <= tol
+
+
+def test_ir_deterministic(F, torch_dev):
+    case = _two_phase(F, 50, 40, 30)
+    p1, s1 = gpu_solve(torch_dev, case, precision=1)
+    p2, s2 = gpu_solve(torch_dev, case, precision=1)
+    assert np.array_equal(p1, p2) and s1["iters"] == s2["iters"]
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads, launch configuration of the bench
+# ---------------------------------------------------------------------------
+
+def test_wedge_256_fp64_and_ir(orc, F, torch_dev):
+    """256^3 two-phase + wedge: both forms reach 1e-8 by the reference's
+    residual, and agree with each other to 1e-6."""
+    case = F.config_wedge(256)
+    _say("case wedge256 fp64")
+    p64, st64 = gpu_solve(torch_dev, case, tol=1e-8)
+    rr64 = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p64)
+    _say(f"  fp64 iters={st64['iters']} rr={rr64:.3e}")
+    assert st64["status"] == 0 and rr64 <= 1e-8
+    _say("case wedge256 ir")
+    p32, st32 = gpu_solve(torch_dev, case, tol=1e-8, precision=1)
+    rr32 = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p32)
+    _say(f"  ir iters={st32['iters']} outer={st32['outer_iters']} rr={rr32:.3e}")
+    assert st32["status"] == 0 and rr32 <= 1e-8
+    err = np.abs(p32 - p64).max() / np.abs(p64).max()
+    assert err <= 1e-6, err
