@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X pressure solve (one JSON line on stdout).
+
+Workload: 512^3 two-phase tank (water 1000 below an eight-mode free surface,
+air 1.2 above), vertical wedge hull (half-angle 15 deg, draft 0.2), Neumann
+on five walls and p = 0 on top, source = div(u)/dt of seeded face
+velocities, tolerance 1e-8 on the relative residual.
+
+A step is the whole hot path on that input: density encoding and validation
+(setup) plus the FP64 Jacobi-PCG solve to 1e-8, inputs resident in HBM.
+The metric is cell-iterations per second, nx*ny*nz*iterations / step time.
+Beside it: the FP32-stencil form with FP64 iterative refinement on the same
+input, the roofline of the dominant kernel (hipEvent-timed on the solver's
+stream), the copy bandwidth achieved on this device, and the CPU reference
+timed on the host cores for a bounded number of iterations.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell of the two iteration kernels (FP64 / FP32 inner)
+BYTES_K1 = {"fp64": 32, "fp32": 16}   # read p_old, z, rho; write p
+BYTES_K2 = {"fp64": 48, "fp32": 24}   # read x, p, z, rho; write x, z
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512, help="grid edge")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-ir", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
+                                                      "traffic_wedge512.txt"))
+    return ap.parse_args()
+
+
+def read_traffic(path):
+    """key = value lines of a committed counter summary (or None)."""
+    if not os.path.exists(path):
+        return None
+    out = {}
+    for line in open(path):
+        line = line.strip()
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the solve is not sharded "
+              "across GPUs in this build (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1410_1942_amd import _lib as L
+    from paper_1410_1942_amd import fields as F
+    from paper_1410_1942_amd.solver import Solver, copy_probe
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    n = args.n
+    log(f"generating wedge{n} input")
+    t = time.time()
+    case = F.config_wedge(n, keep_velocity=False)
+    log(f"  {time.time() - t:.1f} s")
+    rho = torch.from_numpy(case.rho).to(dev)
+    mask = torch.from_numpy(case.mask).to(dev)
+    rhs = torch.from_numpy(case.rhs).to(dev)
+    cells = case.ncells
+    torch.cuda.synchronize()
+
+    # achievable bandwidth: plain copy of 4 GiB
+    log("copy probe")
+    copy_gbs = copy_probe(1 << 29, reps=10)
+    log(f"  copy {copy_gbs:.0f} GB/s")
+
+    def step(precision=L.PREC_FP64, p=None, timing=False):
+        s = Solver(rho, mask, case.bc, case.h, precision=precision)
+        if timing:
+            s.set_timing(True)
+        p, st = s.solve(rhs, p=p, tol=args.tol)
+        tm = s.last_timing() if timing else None
+        s.close()
+        return p, st, tm
+
+    # setup alone (density encoding + host connectivity check)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s0 = Solver(rho, mask, case.bc, case.h)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t) * 1e3
+    s0.close()
+    del s0
+
+    p64 = torch.empty_like(rhs)
+    for w in range(args.warmup):
+        log(f"warmup {w}")
+        _, st, _ = step(p=p64)
+        log(f"  iters {st['iters']} relres {st['rel_res_true']:.3e}")
+    torch.cuda.synchronize()
+    log(f"timed {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, st64, _ = step(p=p64)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    iters = st64["iters"]
+    value = cells * iters / (ms_step * 1e-3) / 1e9
+    log(f"  {ms_step:.1f} ms/step, {iters} iters, {value:.2f} Gcell-iter/s")
+
+    out = {
+        "metric": "PCG Gcell-iter/s & %HBM roofline at 1e-8 rel-res",
+        "value": round(value, 3),
+        "unit": "Gcell-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"wedge{n}_fp64: {n}^3 two-phase tank + wedge hull, "
+                        f"FP64 Jacobi-PCG to rel-res {args.tol:g}",
+            "grid": [n, n, n], "cells": cells, "tol": args.tol,
+            "rho_water": F.RHO_WATER, "rho_air": F.RHO_AIR,
+            "surface": "8 modes, amp 0.01, k 2-16, seed 1", "velocity_seed": 2,
+            "hull": "wedge half-angle 15 deg, draft 0.2",
+            "bc": "Neumann x,y,z-; Dirichlet z+",
+        },
+        "iters": iters,
+        "rel_res_true": st64["rel_res_true"],
+        "setup_ms": round(setup_ms, 2),
+        "copy_GBps": round(copy_gbs, 1),
+    }
+
+    # roofline of the dominant kernel, hipEvent-timed on the solver's stream
+    if not args.no_roofline:
+        log("event-timed solve")
+        _, stt, (k1_ms, k2_ms, nlaunch) = step(p=p64, timing=True)
+        a2 = BYTES_K2["fp64"] * cells / (k2_ms * 1e-3) / 1e9
+        a1 = BYTES_K1["fp64"] * cells / (k1_ms * 1e-3) / 1e9
+        traffic = None
+        tr = read_traffic(args.traffic)
+        if tr and tr.get("kernel_source_sha") == kernel_sha():
+            try:
+                traffic = float(tr["k2_hbm_bytes_per_launch"])
+            except (KeyError, ValueError):
+                traffic = None
+        out["roofline"] = {
+            "bound": "hbm", "achieved": round(a2, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(a2 / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_iter<FP64,2>: operator apply + x/z update + r.z, r.r "
+                      f"({BYTES_K2['fp64']} B/cell)",
+            "avg_ms": round(k2_ms, 4), "launches": nlaunch,
+            "frac_of_copy": round(a2 / copy_gbs, 4),
+        }
+        out["kernel_k1"] = {
+            "kernel": "k_iter<FP64,1>: p update + p.Ap "
+                      f"({BYTES_K1['fp64']} B/cell)",
+            "avg_ms": round(k1_ms, 4), "achieved_GBps": round(a1, 1),
+            "frac": round(a1 / HBM_PEAK_GBS, 4),
+        }
+        per_iter_ms = k1_ms + k2_ms
+        out["iteration_GBps"] = round(
+            (BYTES_K1["fp64"] + BYTES_K2["fp64"]) * cells / (per_iter_ms * 1e-3) / 1e9, 1)
+        log(f"  K1 {k1_ms:.3f} ms ({a1:.0f} GB/s)  K2 {k2_ms:.3f} ms ({a2:.0f} GB/s)")
+
+    # mixed precision: FP32 stencil, FP64 refinement, same input and tolerance
+    if not args.no_ir:
+        log("FP32+IR solve")
+        pir = torch.empty_like(rhs)
+        step(precision=L.PREC_FP32_IR, p=pir)   # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, stir, _ = step(precision=L.PREC_FP32_IR, p=pir)
+        torch.cuda.synchronize()
+        ir_ms = (time.perf_counter() - t) * 1e3
+        err = (pir - p64).abs().max().item() / p64.abs().max().item()
+        out["ir"] = {
+            "ms_per_step": round(ir_ms, 2),
+            "inner_iters": stir["iters"], "outer_iters": stir["outer_iters"],
+            "rel_res_true": stir["rel_res_true"],
+            "Gcell_iter_per_s": round(cells * stir["iters"] / (ir_ms * 1e-3) / 1e9, 3),
+            "speedup_vs_fp64": round(ms_step / ir_ms, 3),
+            "max_err_vs_fp64": err,
+        }
+        log(f"  {ir_ms:.1f} ms, {stir['iters']} inner / {stir['outer_iters']} outer, "
+            f"err vs fp64 {err:.2e}")
+
+    # CPU reference on the host cores: a bounded number of iterations
+    if not args.no_cpu:
+        import oracle
+        log("cpu baseline")
+        k = args.cpu_iters
+        t = time.perf_counter()
+        oracle.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=1)
+        ta = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=1 + k)
+        tb = time.perf_counter() - t
+        cpu_val = cells * k / max(tb - ta, 1e-9) / 1e9
+        out["cpu_baseline"] = {
+            "value": round(cpu_val, 5), "unit": "Gcell-iter/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"wedge{n} input, {k} PCG iterations timed as the "
+                      f"difference of a {1 + k}- and a 1-iteration run "
+                      f"(setup {ta:.1f} s excluded)",
+        }
+        # relative residual of the GPU solutions recomputed by the reference
+        out["rel_res_oracle"] = oracle.relres(case.rho, case.mask, case.bc, case.h,
+                                              case.rhs, p64.cpu().numpy())
+        if not args.no_ir:
+            out["ir"]["rel_res_oracle"] = oracle.relres(
+                case.rho, case.mask, case.bc, case.h, case.rhs, pir.cpu().numpy())
+        log(f"  {cpu_val:.4f} Gcell-iter/s on {oracle.threads()} threads")
+
+    print(json.dumps(out), flush=True)
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "pcg_types.h"):
+        h.update(open(os.path.join(ROOT, "paper_1410_1942_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -168,6 +168,17 @@ int pcg_setup(pcg_ctx_t **out, const pcg_grid_t *grid, const double *rho,
 int pcg_solve(pcg_ctx_t *ctx, const double *rhs, double *p, double tol,
               int32_t maxit, pcg_stats_t *stats);
 
+/*
+ * Host-side check that every connected region of fluid cells (face
+ * adjacency, mask == 0) touches a Dirichlet wall, which is when the
+ * discrete problem has a unique solution.  host_mask is a HOST u8[n] array
+ * (1 = hull; NULL = no hull).  Returns PCG_OK, PCG_ESINGULAR, or PCG_EINVAL
+ * / PCG_EUNSUPPORTED for a bad grid or wall kinds.  pcg_setup and
+ * pcg_batch_admit run the same check unless PCG_SKIP_CONNECTIVITY_CHECK.
+ */
+int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
+                           const pcg_bc_t *bc);
+
 /* Release the context (not the workspace).  NULL is accepted. */
 int pcg_destroy(pcg_ctx_t *ctx);
 

@@ -9,7 +9,8 @@ import ctypes
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libpcgmi.so")
+# PCGMI_LIB selects another build of the same library (e.g. an install path)
+LIB_PATH = os.environ.get("PCGMI_LIB", os.path.join(PKG, "libpcgmi.so"))
 
 OK, MAXIT, PENDING = 0, 1, 2
 EINVAL, EDOMAIN, ESINGULAR, EBREAKDOWN, ENOMEM, EBUSY, EHIP, EUNSUPPORTED = \
@@ -24,6 +25,7 @@ EXPORTED = [
     "pcg_batch_footprint", "pcg_batch_admit", "pcg_batch_step",
     "pcg_batch_poll", "pcg_batch_release", "pcg_batch_destroy",
     "pcg_set_timing", "pcg_last_timing", "pcg_copy_probe",
+    "pcg_check_connectivity",
 ]
 
 
@@ -96,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.pcg_set_timing.argtypes = [vp, i32]
     lib.pcg_last_timing.argtypes = [vp, P(dbl), P(dbl), P(i32)]
     lib.pcg_copy_probe.argtypes = [vp, vp, sz, i32, vp, P(dbl)]
+    lib.pcg_check_connectivity.argtypes = [vp, P(Grid), P(BC)]
     for name in EXPORTED:
         if name not in ("pcg_strerror", "pcg_last_hip_error"):
             getattr(lib, name).restype = ctypes.c_int

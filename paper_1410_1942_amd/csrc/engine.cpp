@@ -49,7 +49,7 @@ int hip_fail(hipError_t e, const char *what)
 
 constexpr size_t kAlign = 256;
 constexpr int kDefaultCheckEvery = 32;
-constexpr int kDefaultGridMax = 2048;
+constexpr int kDefaultGridMax = 1024;
 constexpr double kDefaultInnerTol = 1e-5;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -204,48 +204,69 @@ int check_opts(const pcg_opts_t *o)
     return PCG_OK;
 }
 
-// Every fluid region must reach a Dirichlet wall (flood fill on the host).
+// Every fluid region must reach a Dirichlet wall.  Flood fill over x-runs
+// of fluid cells: one scan of the mask splits every row into maximal runs,
+// then a breadth-first search moves between runs of neighbouring rows (y and
+// z) that overlap in x.  Work is linear in the cells for the scan and in
+// the runs for the search.
 bool fluid_reaches_dirichlet(const std::vector<uint8_t> &solid, int nx, int ny,
                              int nz, int bcmask)
 {
-    const int64_t n = (int64_t)nx * ny * nz;
-    std::vector<uint8_t> seen(n, 0);
-    std::vector<int32_t> stack;
-    stack.reserve(1 << 16);
-    auto seed = [&](int64_t c) {
-        if (!solid[c] && !seen[c]) { seen[c] = 1; stack.push_back((int32_t)c); }
+    const int64_t nrows = (int64_t)ny * nz;
+    std::vector<int64_t> row_start(nrows + 1, 0);
+    std::vector<int32_t> ra, rb;  // run [ra, rb) in x
+    ra.reserve(nrows * 2);
+    rb.reserve(nrows * 2);
+    for (int64_t r = 0; r < nrows; ++r) {
+        row_start[r] = (int64_t)ra.size();
+        const uint8_t *m = solid.data() + r * nx;
+        int i = 0;
+        while (i < nx) {
+            while (i < nx && m[i]) ++i;
+            if (i >= nx) break;
+            const int a = i;
+            while (i < nx && !m[i]) ++i;
+            ra.push_back(a);
+            rb.push_back(i);
+        }
+    }
+    row_start[nrows] = (int64_t)ra.size();
+    const int64_t nruns = (int64_t)ra.size();
+    if (nruns == 0) return true;
+    std::vector<uint8_t> seen(nruns, 0);
+    std::vector<int64_t> queue;
+    queue.reserve(1024);
+    auto push = [&](int64_t u) {
+        if (!seen[u]) { seen[u] = 1; queue.push_back(u); }
     };
-    const int64_t plane = (int64_t)nx * ny;
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j) {
-            const int64_t row = k * plane + (int64_t)j * nx;
-            if (bcmask & 1) seed(row);
-            if (bcmask & 2) seed(row + nx - 1);
-            if ((bcmask & 4) && j == 0)
-                for (int i = 0; i < nx; ++i) seed(row + i);
-            if ((bcmask & 8) && j == ny - 1)
-                for (int i = 0; i < nx; ++i) seed(row + i);
-            if ((bcmask & 16) && k == 0)
-                for (int i = 0; i < nx; ++i) seed(row + i);
-            if ((bcmask & 32) && k == nz - 1)
-                for (int i = 0; i < nx; ++i) seed(row + i);
+            const int64_t r = (int64_t)k * ny + j;
+            const bool whole = ((bcmask & 4) && j == 0) || ((bcmask & 8) && j == ny - 1) ||
+                               ((bcmask & 16) && k == 0) || ((bcmask & 32) && k == nz - 1);
+            for (int64_t u = row_start[r]; u < row_start[r + 1]; ++u)
+                if (whole || ((bcmask & 1) && ra[u] == 0) || ((bcmask & 2) && rb[u] == nx))
+                    push(u);
         }
-    while (!stack.empty()) {
-        const int64_t c = stack.back();
-        stack.pop_back();
-        const int i = (int)(c % nx);
-        const int j = (int)((c / nx) % ny);
-        const int k = (int)(c / plane);
-        if (i > 0) seed(c - 1);
-        if (i < nx - 1) seed(c + 1);
-        if (j > 0) seed(c - nx);
-        if (j < ny - 1) seed(c + nx);
-        if (k > 0) seed(c - plane);
-        if (k < nz - 1) seed(c + plane);
+    auto row_of = [&](int64_t u) {
+        return (int64_t)(std::upper_bound(row_start.begin(), row_start.end(), u) -
+                         row_start.begin()) - 1;
+    };
+    for (size_t h = 0; h < queue.size(); ++h) {
+        const int64_t u = queue[h];
+        const int64_t r = row_of(u);
+        const int j = (int)(r % ny), k = (int)(r / ny);
+        const int64_t nb[4] = { j > 0 ? r - 1 : -1, j < ny - 1 ? r + 1 : -1,
+                                k > 0 ? r - ny : -1, k < nz - 1 ? r + ny : -1 };
+        for (int e = 0; e < 4; ++e) {
+            if (nb[e] < 0) continue;
+            const int64_t b0 = row_start[nb[e]], b1 = row_start[nb[e] + 1];
+            // first run of the neighbouring row ending after ra[u]
+            int64_t v = std::upper_bound(rb.begin() + b0, rb.begin() + b1, ra[u]) - rb.begin();
+            for (; v < b1 && ra[v] < rb[u]; ++v) push(v);
+        }
     }
-    for (int64_t c = 0; c < n; ++c)
-        if (!solid[c] && !seen[c]) return false;
-    return true;
+    return (int64_t)queue.size() == nruns;
 }
 
 struct SlotHost {
@@ -537,10 +558,9 @@ struct Engine {
         grid = g;
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
-        for (int i = 0; i < check_every && err == hipSuccess; ++i) {
-            err = launch_iter(prec, 1, grid, d_hdr, d_slots, cap);
-            if (err == hipSuccess) err = launch_iter(prec, 2, grid, d_hdr, d_slots, cap);
-        }
+        for (int i = 0; i < check_every && err == hipSuccess; ++i)
+            for (int w = 0; w < 3 && err == hipSuccess; ++w)
+                err = launch_iter(prec, w, grid, d_hdr, d_slots, cap);
         hipGraph_t gph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &gph);
         if (err != hipSuccess) { if (gph) (void)hipGraphDestroy(gph); return hip_fail(err, "capture launch"); }
@@ -553,24 +573,23 @@ struct Engine {
     // Direct launches with an event around each kernel (timing mode).
     int timed_chunk()
     {
-        const int ne = 2 * check_every + 1;
+        const int ne = 3 * check_every + 1;
         while ((int)ev.size() < ne) {
             hipEvent_t e;
             HIP_TRY(hipEventCreate(&e));
             ev.push_back(e);
         }
         HIP_TRY(hipEventRecord(ev[0], stream));
-        for (int i = 0; i < check_every; ++i) {
-            HIP_TRY(launch_iter(prec, 1, grid, d_hdr, d_slots, stream));
-            HIP_TRY(hipEventRecord(ev[2 * i + 1], stream));
-            HIP_TRY(launch_iter(prec, 2, grid, d_hdr, d_slots, stream));
-            HIP_TRY(hipEventRecord(ev[2 * i + 2], stream));
-        }
+        for (int i = 0; i < check_every; ++i)
+            for (int w = 0; w < 3; ++w) {
+                HIP_TRY(launch_iter(prec, w, grid, d_hdr, d_slots, stream));
+                HIP_TRY(hipEventRecord(ev[3 * i + w + 1], stream));
+            }
         HIP_TRY(hipEventSynchronize(ev[ne - 1]));
         for (int i = 0; i < check_every; ++i) {
             float a = 0.f, b = 0.f;
-            HIP_TRY(hipEventElapsedTime(&a, ev[2 * i], ev[2 * i + 1]));
-            HIP_TRY(hipEventElapsedTime(&b, ev[2 * i + 1], ev[2 * i + 2]));
+            HIP_TRY(hipEventElapsedTime(&a, ev[3 * i + 1], ev[3 * i + 2]));
+            HIP_TRY(hipEventElapsedTime(&b, ev[3 * i + 2], ev[3 * i + 3]));
             t_k1.push_back(a);
             t_k2.push_back(b);
         }
@@ -750,6 +769,21 @@ int pcg_solve(pcg_ctx_t *c, const double *rhs, double *p, double tol,
     s.ms = ms_since(t0);
     if (stats) *stats = s;
     return s.status;
+}
+
+int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
+                           const pcg_bc_t *bc)
+{
+    int st = check_grid(grid);
+    if (st) return st;
+    int bm = 0;
+    st = check_bc(bc, &bm);
+    if (st) return st;
+    if (!host_mask) return bm ? PCG_OK : PCG_ESINGULAR;
+    const size_t n = (size_t)grid->nx * grid->ny * grid->nz;
+    std::vector<uint8_t> m(host_mask, host_mask + n);
+    return fluid_reaches_dirichlet(m, grid->nx, grid->ny, grid->nz, bm) ? PCG_OK
+                                                                        : PCG_ESINGULAR;
 }
 
 int pcg_destroy(pcg_ctx_t *c)

@@ -89,17 +89,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
     __syncthreads();
 }
 
-__device__ __forceinline__ void store_agent(double *p, double v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double load_agent(const double *p)
-{
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-}
-
 struct TileCtx {
     int q;       // index of this thread's column in the x-y plane
     int i, j;
@@ -123,74 +112,106 @@ __device__ __forceinline__ TileCtx tile_ctx(const Slot &S, int64_t lt)
     return t;
 }
 
-// One interior face: beta = 2/(rho_c + rho_n).
+// Global-address-space views: pointers read from the slot table are
+// generic; casting them lets the compiler emit global (not flat) accesses.
+#define GLB __attribute__((address_space(1)))
 template <typename T>
-__device__ __forceinline__ void face(T vc, T rc, T vn, T rn, T &q, T &dg)
+__device__ __forceinline__ GLB T *gp(T *p) { return (GLB T *)p; }
+template <typename T>
+__device__ __forceinline__ const GLB T *gp(const T *p) { return (const GLB T *)p; }
+
+// Reciprocal of a positive finite value: hardware estimate refined by two
+// Newton-Raphson steps (quadratic convergence from the ~2^-23 estimate).
+__device__ __forceinline__ double recip(double d)
 {
-    const T b = T(2) / (rc + rn);
-    q += b * (vc - vn);
-    dg += b;
+    double y = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-d, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ float recip(float d) { return __builtin_amdgcn_rcpf(d); }
+
+// Face coefficient from the sum of the two densities on either side:
+// beta = 1/((rho_c + rho_n)/2) = 2/(rho_c + rho_n).  A hull cell holds +inf,
+// so the sum is +inf and beta = 0.  Walls use rho_n = 0 for Dirichlet
+// (beta = 2/rho_c: the mirrored ghost -p_c) and +inf for Neumann (beta = 0).
+template <typename T>
+__device__ __forceinline__ T fb(T den)
+{
+    const T inf = (T)INFINITY;
+    return den < inf ? T(2) * recip(den) : T(0);
 }
 
-// One wall face: Dirichlet contributes (2/rho_c) to the diagonal.
+// Per-thread neighbour description for the x/y faces of a column: offset to
+// the neighbour (0 at a wall, so the load stays in bounds) and the density
+// standing in for a missing neighbour.
 template <typename T>
-__device__ __forceinline__ void wall(T vc, T rc, bool dirichlet, T &q, T &dg)
-{
-    if (dirichlet) {
-        const T b = T(2) / rc;
-        q += b * vc;
-        dg += b;
-    }
-}
+struct Nbr {
+    int oxm, oxp, oym, oyp;
+    bool hxm, hxp, hym, hyp;
+    T wxm, wxp, wym, wyp, wzm, wzp;
+};
 
-// q = (A v)_c and dg = A_cc for cell c.  x and y neighbours are loaded; the
-// z neighbours are passed in by the z march.  MASK: read v as 0 in hull
-// cells (for vectors whose hull entries are not yet cleared).
-template <typename T, bool MASK = false>
-__device__ __forceinline__ void stencil(const T *__restrict__ v,
-                                        const T *__restrict__ rho, int64_t c,
-                                        const TileCtx &t, int k, const Slot &S,
-                                        T vc, T rc, T vzm, T rzm, T vzp, T rzp,
-                                        T &q, T &dg)
+template <typename T>
+__device__ __forceinline__ Nbr<T> make_nbr(const TileCtx &t, const Slot &S)
 {
-    q = T(0);
-    dg = T(0);
+    Nbr<T> n;
+    const T inf = (T)INFINITY;
     const int bm = S.bcmask;
-    auto val = [&](int64_t n, T rn) -> T {
-        T vn = v[n];
-        if (MASK) vn = isinf(rn) ? T(0) : vn;
-        return vn;
-    };
-    if (t.i > 0) { T rn = rho[c - 1]; face(vc, rc, val(c - 1, rn), rn, q, dg); }
-    else wall(vc, rc, bm & 1, q, dg);
-    if (t.i < S.nx - 1) { T rn = rho[c + 1]; face(vc, rc, val(c + 1, rn), rn, q, dg); }
-    else wall(vc, rc, bm & 2, q, dg);
-    if (t.j > 0) { T rn = rho[c - S.nx]; face(vc, rc, val(c - S.nx, rn), rn, q, dg); }
-    else wall(vc, rc, bm & 4, q, dg);
-    if (t.j < S.ny - 1) { T rn = rho[c + S.nx]; face(vc, rc, val(c + S.nx, rn), rn, q, dg); }
-    else wall(vc, rc, bm & 8, q, dg);
-    if (k > 0) face(vc, rc, vzm, rzm, q, dg);
-    else wall(vc, rc, bm & 16, q, dg);
-    if (k < S.nz - 1) face(vc, rc, vzp, rzp, q, dg);
-    else wall(vc, rc, bm & 32, q, dg);
+    n.hxm = t.i > 0;
+    n.hxp = t.i < S.nx - 1;
+    n.hym = t.j > 0;
+    n.hyp = t.j < S.ny - 1;
+    n.oxm = n.hxm ? -1 : 0;
+    n.oxp = n.hxp ? 1 : 0;
+    n.oym = n.hym ? -S.nx : 0;
+    n.oyp = n.hyp ? S.nx : 0;
+    n.wxm = (bm & 1) ? T(0) : inf;
+    n.wxp = (bm & 2) ? T(0) : inf;
+    n.wym = (bm & 4) ? T(0) : inf;
+    n.wyp = (bm & 8) ? T(0) : inf;
+    n.wzm = (bm & 16) ? T(0) : inf;
+    n.wzp = (bm & 32) ? T(0) : inf;
+    return n;
 }
 
-// Diagonal only (no vector).
-template <typename T>
-__device__ __forceinline__ T diag_at(const T *__restrict__ rho, int64_t c,
-                                     const TileCtx &t, int k, const Slot &S,
-                                     T rc, T rzm, T rzp)
+// Full operator at one cell: q = (A v)_c, dg = A_cc, given the cell's value
+// and density, the z neighbours (already substituted at walls: value 0 and
+// wall density) and a fetch of v for the x/y neighbours.
+template <typename T, class Fetch>
+__device__ __forceinline__ void apply_cell(Fetch v, const GLB T *__restrict__ rho,
+                                           int64_t c, const Nbr<T> &n, T vc, T rc,
+                                           T vzm, T rzm, T vzp, T rzp, T &q, T &dg)
 {
-    T q = T(0), dg = T(0);
-    const int bm = S.bcmask;
-    const T z0 = T(0);
-    if (t.i > 0) face(z0, rc, z0, rho[c - 1], q, dg); else wall(z0, rc, bm & 1, q, dg);
-    if (t.i < S.nx - 1) face(z0, rc, z0, rho[c + 1], q, dg); else wall(z0, rc, bm & 2, q, dg);
-    if (t.j > 0) face(z0, rc, z0, rho[c - S.nx], q, dg); else wall(z0, rc, bm & 4, q, dg);
-    if (t.j < S.ny - 1) face(z0, rc, z0, rho[c + S.nx], q, dg); else wall(z0, rc, bm & 8, q, dg);
-    if (k > 0) face(z0, rc, z0, rzm, q, dg); else wall(z0, rc, bm & 16, q, dg);
-    if (k < S.nz - 1) face(z0, rc, z0, rzp, q, dg); else wall(z0, rc, bm & 32, q, dg);
-    return dg;
+    // loads are unconditional (wall offsets are 0); walls substituted after
+    const T lrxm = rho[c + n.oxm], lrxp = rho[c + n.oxp];
+    const T lrym = rho[c + n.oym], lryp = rho[c + n.oyp];
+    const T lvxm = v(c + n.oxm), lvxp = v(c + n.oxp);
+    const T lvym = v(c + n.oym), lvyp = v(c + n.oyp);
+    const T rxm = n.hxm ? lrxm : n.wxm, rxp = n.hxp ? lrxp : n.wxp;
+    const T rym = n.hym ? lrym : n.wym, ryp = n.hyp ? lryp : n.wyp;
+    const T vxm = n.hxm ? lvxm : T(0), vxp = n.hxp ? lvxp : T(0);
+    const T vym = n.hym ? lvym : T(0), vyp = n.hyp ? lvyp : T(0);
+    const T bxm = fb(rc + rxm), bxp = fb(rc + rxp);
+    const T bym = fb(rc + rym), byp = fb(rc + ryp);
+    const T bzm = fb(rc + rzm), bzp = fb(rc + rzp);
+    dg = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
+    q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) + (bym * (vc - vym) + byp * (vc - vyp))) +
+        (bzm * (vc - vzm) + bzp * (vc - vzp));
+}
+
+// Diagonal only.
+template <typename T>
+__device__ __forceinline__ T diag_cell(const GLB T *__restrict__ rho, int64_t c,
+                                       const Nbr<T> &n, T rc, T rzm, T rzp)
+{
+    const T lrxm = rho[c + n.oxm], lrxp = rho[c + n.oxp];
+    const T lrym = rho[c + n.oym], lryp = rho[c + n.oyp];
+    const T rxm = n.hxm ? lrxm : n.wxm, rxp = n.hxp ? lrxp : n.wxp;
+    const T rym = n.hym ? lrym : n.wym, ryp = n.hyp ? lryp : n.wyp;
+    return ((fb(rc + rxm) + fb(rc + rxp)) + (fb(rc + rym) + fb(rc + ryp))) +
+           (fb(rc + rzm) + fb(rc + rzp));
 }
 
 // x + s d, evaluated identically wherever the refined iterate is needed.
@@ -200,7 +221,10 @@ __device__ __forceinline__ double refined(double x, double s, float d)
 }
 
 // ------------------------------------------------------------------------
-// phase bodies (one tile each); acc[] receives this thread's partial sums
+// phase bodies (one tile each); acc[] receives this thread's partial sums.
+// Every body marches its column up through planes k0..k1-1 carrying the
+// k-1 and k values; z neighbours beyond the domain are replaced by the wall
+// (value 0, density 0 for Dirichlet / +inf for Neumann).
 // ------------------------------------------------------------------------
 
 // K1_INIT64: b = -h^2 Sigma (0 on hull), r = b (cold) or b - A x0 (warm),
@@ -210,98 +234,96 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const double *rho = S.rho64;
-    double *x = S.x;
-    double *z = (double *)S.z;
+    const GLB double *__restrict__ rho = gp(S.rho64);
+    GLB double *__restrict__ x = gp(S.x);
+    GLB double *__restrict__ z = gp((double *)S.z);
+    const GLB double *__restrict__ rhs = gp(S.rhs);
+    const Nbr<double> n = make_nbr<double>(t, S);
     const bool warm = st.warm != 0;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    double rzm = 1.0, xzm = 0.0;
+    const int64_t P = t.P;
+    // warm start: hull entries of x0 are read as 0 (they are cleared here)
+    auto xv = [&](int64_t m) -> double {
+        const double r = rho[m], v = x[m];
+        return isinf(r) ? 0.0 : v;
+    };
+    int64_t c = (int64_t)t.k0 * P + t.q;
     double rc = rho[c];
-    double xc = 0.0;
-    if (warm) {
-        xc = isinf(rc) ? 0.0 : x[c];
-        if (t.k0 > 0) {
-            rzm = rho[c - t.P];
-            xzm = isinf(rzm) ? 0.0 : x[c - t.P];
-        }
-    } else if (t.k0 > 0) {
-        rzm = rho[c - t.P];
-    }
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) {
-        double rzp = 1.0, xzp = 0.0;
-        if (k + 1 < S.nz) {
-            rzp = rho[c + t.P];
-            if (warm) xzp = isinf(rzp) ? 0.0 : x[c + t.P];
-        }
+    double xc = warm ? xv(c) : 0.0;
+    double rzm = n.wzm, xzm = 0.0;
+    if (t.k0 > 0) { rzm = rho[c - P]; if (warm) xzm = xv(c - P); }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int k = t.k0; k < t.k1; ++k, c += P) {
+        const bool top = k == S.nz - 1;
+        double rzp = n.wzp, xzp = 0.0;
+        if (!top) { rzp = rho[c + P]; if (warm) xzp = xv(c + P); }
         const bool solid = isinf(rc);
-        const double b = solid ? 0.0 : -S.h2 * S.rhs[c];
+        const double b = solid ? 0.0 : -S.h2 * rhs[c];
         double r, dg;
         if (warm) {
             double q;
-            stencil<double, true>(x, rho, c, t, k, S, xc, rc, xzm, rzm, xzp, rzp, q, dg);
+            apply_cell<double>(xv, rho, c, n, xc, rc, xzm, rzm, xzp, rzp, q, dg);
             r = solid ? 0.0 : b - q;
             if (solid) x[c] = 0.0;
         } else {
-            dg = diag_at(rho, c, t, k, S, rc, rzm, rzp);
+            dg = diag_cell<double>(rho, c, n, rc, rzm, rzp);
             r = b;
             x[c] = 0.0;
         }
         const double zc = dg > 0.0 ? r / dg : 0.0;
         z[c] = zc;
-        acc[0] += b * b;
-        acc[1] += r * zc;
-        acc[2] += r * r;
+        a0 += b * b;
+        a1 += r * zc;
+        a2 += r * r;
         rzm = rc; xzm = xc;
         rc = rzp; xc = xzp;
     }
+    acc[0] += a0;
+    acc[1] += a1;
+    acc[2] += a2;
 }
 
 // K1_CG_A / K1_IR_A: p_new = z + beta p_old (z when first), stored; the
-// quadratic form p.Ap summed over the low faces of each cell.
+// quadratic form p.Ap = sum over faces of beta_f (p_c - p_n)^2, each face
+// counted once from the cell above it (x, y, z low faces), plus the wall
+// terms (2/rho_c) p_c^2 of the Dirichlet walls.
 template <typename T>
 __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
                            double (&acc)[3])
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const T *ps = (const T *)(st.pbuf ? S.pb : S.pa);
-    T *pd = (T *)(st.pbuf ? S.pa : S.pb);
-    const T *z = (const T *)S.z;
-    const T *rho = std::is_same<T, double>::value ? (const T *)S.rho64
-                                                   : (const T *)S.rho32;
+    const GLB T *__restrict__ ps = gp((const T *)(st.pbuf ? S.pb : S.pa));
+    GLB T *__restrict__ pd = gp((T *)(st.pbuf ? S.pa : S.pb));
+    const GLB T *__restrict__ z = gp((const T *)S.z);
+    const GLB T *__restrict__ rho =
+        gp(std::is_same<T, double>::value ? (const T *)S.rho64 : (const T *)S.rho32);
     const bool first = st.first != 0;
     const T beta = (T)st.beta;
-    auto pnew = [&](int64_t n) -> T {
-        const T zz = z[n];
-        return first ? zz : zz + beta * ps[n];
+    auto pnew = [&](int64_t m) -> T {
+        const T zz = z[m];
+        return first ? zz : zz + beta * ps[m];
     };
+    const Nbr<T> n = make_nbr<T>(t, S);
     const int bm = S.bcmask;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    T pzm = T(0), rzm = T(1);
-    if (t.k0 > 0) { pzm = pnew(c - t.P); rzm = rho[c - t.P]; }
+    // Dirichlet high walls of this column (x+, y+); z+ is added on the top plane
+    const int hw = ((!n.hxp && (bm & 2)) ? 1 : 0) + ((!n.hyp && (bm & 8)) ? 1 : 0);
+    const int64_t P = t.P;
+    int64_t c = (int64_t)t.k0 * P + t.q;
+    T pzm = T(0), rzm = n.wzm;
+    if (t.k0 > 0) { pzm = pnew(c - P); rzm = rho[c - P]; }
     double a = 0.0;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) {
+    for (int k = t.k0; k < t.k1; ++k, c += P) {
         const T pc = pnew(c);
         const T rc = rho[c];
         pd[c] = pc;
-        T s = T(0);
-        const T bd = T(2) / rc;          // Dirichlet wall weight (0 on hull)
-        const T pc2 = pc * pc;
-        if (t.i > 0) {
-            const T d = pc - pnew(c - 1);
-            s += (T(2) / (rc + rho[c - 1])) * d * d;
-        } else if (bm & 1) s += bd * pc2;
-        if (t.i == S.nx - 1 && (bm & 2)) s += bd * pc2;
-        if (t.j > 0) {
-            const T d = pc - pnew(c - S.nx);
-            s += (T(2) / (rc + rho[c - S.nx])) * d * d;
-        } else if (bm & 4) s += bd * pc2;
-        if (t.j == S.ny - 1 && (bm & 8)) s += bd * pc2;
-        if (k > 0) {
-            const T d = pc - pzm;
-            s += (T(2) / (rc + rzm)) * d * d;
-        } else if (bm & 16) s += bd * pc2;
-        if (k == S.nz - 1 && (bm & 32)) s += bd * pc2;
+        const T lrxm = rho[c + n.oxm], lrym = rho[c + n.oym];
+        const T lpxm = pnew(c + n.oxm), lpym = pnew(c + n.oym);
+        const T rxm = n.hxm ? lrxm : n.wxm, rym = n.hym ? lrym : n.wym;
+        const T pxm = n.hxm ? lpxm : T(0), pym = n.hym ? lpym : T(0);
+        const T dx = pc - pxm, dy = pc - pym, dz = pc - pzm;
+        T s = (fb(rc + rxm) * dx * dx + fb(rc + rym) * dy * dy) + fb(rc + rzm) * dz * dz;
+        const int w = hw + ((k == S.nz - 1 && (bm & 32)) ? 1 : 0);
+        if (w) s += (T)w * fb(rc) * (pc * pc);
         a += (double)s;
         pzm = pc;
         rzm = rc;
@@ -310,39 +332,63 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
 }
 
 // K2_CG_B (T = double, X = double: x) / K2_IR_B (T = float, X = float: d):
-// q = A p, x += alpha p, z -= alpha q / diag; acc = [r.z, r.r].
+// q = A p, x += alpha p, z -= alpha q / diag; acc = [r.z, r.r] with
+// r = diag z.  The low z face coefficient is carried from the plane below.
 template <typename T, typename X>
 __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
                            double (&acc)[3])
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const T *p = (const T *)(st.pbuf ? S.pb : S.pa);
-    const T *rho = std::is_same<T, double>::value ? (const T *)S.rho64
-                                                   : (const T *)S.rho32;
-    T *z = (T *)S.z;
-    X *x = std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32;
+    const GLB T *__restrict__ p = gp((const T *)(st.pbuf ? S.pb : S.pa));
+    const GLB T *__restrict__ rho =
+        gp(std::is_same<T, double>::value ? (const T *)S.rho64 : (const T *)S.rho32);
+    GLB T *__restrict__ z = gp((T *)S.z);
+    GLB X *__restrict__ x = gp(std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32);
     const T alpha = (T)st.alpha;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    T vzm = T(0), rzm = T(1);
+    const Nbr<T> n = make_nbr<T>(t, S);
+    const int64_t P = t.P;
+    int64_t c = (int64_t)t.k0 * P + t.q;
     T vc = p[c], rc = rho[c];
-    if (t.k0 > 0) { vzm = p[c - t.P]; rzm = rho[c - t.P]; }
+    T vzm = T(0), rzm = n.wzm;
+    if (t.k0 > 0) { vzm = p[c - P]; rzm = rho[c - P]; }
+    T bzm = fb(rc + rzm);
     double a0 = 0.0, a1 = 0.0;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) {
-        T vzp = T(0), rzp = T(1);
-        if (k + 1 < S.nz) { vzp = p[c + t.P]; rzp = rho[c + t.P]; }
-        T q, dg;
-        stencil<T>(p, rho, c, t, k, S, vc, rc, vzm, rzm, vzp, rzp, q, dg);
-        x[c] += (X)(alpha * vc);
+    for (int k = t.k0; k < t.k1; ++k, c += P) {
+        const bool top = k == S.nz - 1;
+        const int64_t cz = top ? c : c + P;
+        const T vzp_l = p[cz], rzp_l = rho[cz];
+        const T vzp = top ? T(0) : vzp_l;
+        const T rzp = top ? n.wzp : rzp_l;
+        const T lrxm = rho[c + n.oxm], lrxp = rho[c + n.oxp];
+        const T lrym = rho[c + n.oym], lryp = rho[c + n.oyp];
+        const T lvxm = p[c + n.oxm], lvxp = p[c + n.oxp];
+        const T lvym = p[c + n.oym], lvyp = p[c + n.oyp];
+        const T rxm = n.hxm ? lrxm : n.wxm, rxp = n.hxp ? lrxp : n.wxp;
+        const T rym = n.hym ? lrym : n.wym, ryp = n.hyp ? lryp : n.wyp;
+        const T vxm = n.hxm ? lvxm : T(0), vxp = n.hxp ? lvxp : T(0);
+        const T vym = n.hym ? lvym : T(0), vyp = n.hyp ? lvyp : T(0);
+        const X xc = x[c];
         T zc = z[c];
-        if (dg > T(0)) zc -= alpha * q / dg;
+        const T bxm = fb(rc + rxm), bxp = fb(rc + rxp);
+        const T bym = fb(rc + rym), byp = fb(rc + ryp);
+        const T bzp = fb(rc + rzp);
+        const T dg = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
+        const T q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) +
+                     (bym * (vc - vym) + byp * (vc - vyp))) +
+                    (bzm * (vc - vzm) + bzp * (vc - vzp));
+        x[c] = xc + (X)(alpha * vc);
+        const T inv = dg > T(0) ? recip(dg) : T(0);   // hull rows keep z = 0
+        zc -= alpha * q * inv;
         z[c] = zc;
         const double dd = (double)dg, dz = (double)zc;
         const double r = dd * dz;
         a0 += r * dz;
         a1 += r * r;
-        vzm = vc; rzm = rc;
-        vc = vzp; rc = rzp;
+        vzm = vc;
+        bzm = bzp;
+        vc = vzp;
+        rc = rzp;
     }
     acc[0] += a0;
     acc[1] += a1;
@@ -354,19 +400,25 @@ __device__ void body_check64(const Slot &S, const SlotState &st, int64_t lt,
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const double *rho = S.rho64;
-    const double *x = S.x;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    double vzm = 0.0, rzm = 1.0, vc = x[c], rc = rho[c];
-    if (t.k0 > 0) { vzm = x[c - t.P]; rzm = rho[c - t.P]; }
+    const GLB double *__restrict__ rho = gp(S.rho64);
+    const GLB double *__restrict__ x = gp((const double *)S.x);
+    const GLB double *__restrict__ rhs = gp(S.rhs);
+    const Nbr<double> n = make_nbr<double>(t, S);
+    auto xv = [&](int64_t m) -> double { return x[m]; };
+    const int64_t P = t.P;
+    int64_t c = (int64_t)t.k0 * P + t.q;
+    double vc = x[c], rc = rho[c];
+    double vzm = 0.0, rzm = n.wzm;
+    if (t.k0 > 0) { vzm = x[c - P]; rzm = rho[c - P]; }
     double a = 0.0;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) {
-        double vzp = 0.0, rzp = 1.0;
-        if (k + 1 < S.nz) { vzp = x[c + t.P]; rzp = rho[c + t.P]; }
+    for (int k = t.k0; k < t.k1; ++k, c += P) {
+        const bool top = k == S.nz - 1;
+        double vzp = 0.0, rzp = n.wzp;
+        if (!top) { vzp = x[c + P]; rzp = rho[c + P]; }
         double q, dg;
-        stencil<double>(x, rho, c, t, k, S, vc, rc, vzm, rzm, vzp, rzp, q, dg);
+        apply_cell<double>(xv, rho, c, n, vc, rc, vzm, rzm, vzp, rzp, q, dg);
         if (!isinf(rc)) {
-            const double r = -S.h2 * S.rhs[c] - q;
+            const double r = -S.h2 * rhs[c] - q;
             a += r * r;
         }
         vzm = vc; rzm = rc;
@@ -381,14 +433,18 @@ __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
+    const GLB double *__restrict__ rho = gp(S.rho64);
+    GLB double *__restrict__ x = gp(S.x);
+    GLB float *__restrict__ d = gp(S.d32);
+    const GLB double *__restrict__ rhs = gp(S.rhs);
     int64_t c = (int64_t)t.k0 * t.P + t.q;
     const bool warm = st.warm != 0;
     double a = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += t.P) {
-        const bool solid = isinf(S.rho64[c]);
-        if (!warm || solid) S.x[c] = 0.0;
-        S.d32[c] = 0.0f;
-        const double b = solid ? 0.0 : -S.h2 * S.rhs[c];
+        const bool solid = isinf(rho[c]);
+        if (!warm || solid) x[c] = 0.0;
+        d[c] = 0.0f;
+        const double b = solid ? 0.0 : -S.h2 * rhs[c];
         a += b * b;
     }
     acc[0] += a;
@@ -401,39 +457,36 @@ __device__ void body_ir_resid(const Slot &S, const SlotState &st, int64_t lt,
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const double *rho = S.rho64;
-    const float *rho32 = S.rho32;
-    const double *x = S.x;
-    const float *d = S.d32;
-    float *z = (float *)S.z;
+    const GLB double *__restrict__ rho = gp(S.rho64);
+    const GLB float *__restrict__ rho32 = gp((const float *)S.rho32);
+    const GLB double *__restrict__ x = gp((const double *)S.x);
+    const GLB float *__restrict__ d = gp((const float *)S.d32);
+    GLB float *__restrict__ z = gp((float *)S.z);
+    const GLB double *__restrict__ rhs = gp(S.rhs);
     const double s = st.upd_s;
     const double scale = st.scale;
+    const Nbr<double> n = make_nbr<double>(t, S);
+    const Nbr<float> nf = make_nbr<float>(t, S);
+    auto xe = [&](int64_t m) -> double { return refined(x[m], s, d[m]); };
     const int64_t P = t.P;
     int64_t c = (int64_t)t.k0 * P + t.q;
-    auto xe = [&](int64_t n) { return refined(x[n], s, d[n]); };
-    double vzm = 0.0, rzm = 1.0;
-    float fzm = 1.0f;
     double vc = xe(c), rc = rho[c];
     float fc = rho32[c];
+    double vzm = 0.0, rzm = n.wzm;
+    float fzm = nf.wzm;
     if (t.k0 > 0) { vzm = xe(c - P); rzm = rho[c - P]; fzm = rho32[c - P]; }
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    const int bm = S.bcmask;
     for (int k = t.k0; k < t.k1; ++k, c += P) {
-        double vzp = 0.0, rzp = 1.0;
-        float fzp = 1.0f;
-        if (k + 1 < S.nz) { vzp = xe(c + P); rzp = rho[c + P]; fzp = rho32[c + P]; }
-        // FP64 residual of the refined iterate
-        double q = 0.0, dg = 0.0;
-        if (t.i > 0) face(vc, rc, xe(c - 1), rho[c - 1], q, dg); else wall(vc, rc, bm & 1, q, dg);
-        if (t.i < S.nx - 1) face(vc, rc, xe(c + 1), rho[c + 1], q, dg); else wall(vc, rc, bm & 2, q, dg);
-        if (t.j > 0) face(vc, rc, xe(c - S.nx), rho[c - S.nx], q, dg); else wall(vc, rc, bm & 4, q, dg);
-        if (t.j < S.ny - 1) face(vc, rc, xe(c + S.nx), rho[c + S.nx], q, dg); else wall(vc, rc, bm & 8, q, dg);
-        if (k > 0) face(vc, rc, vzm, rzm, q, dg); else wall(vc, rc, bm & 16, q, dg);
-        if (k < S.nz - 1) face(vc, rc, vzp, rzp, q, dg); else wall(vc, rc, bm & 32, q, dg);
+        const bool top = k == S.nz - 1;
+        double vzp = 0.0, rzp = n.wzp;
+        float fzp = nf.wzp;
+        if (!top) { vzp = xe(c + P); rzp = rho[c + P]; fzp = rho32[c + P]; }
+        double q, dg;
+        apply_cell<double>(xe, rho, c, n, vc, rc, vzm, rzm, vzp, rzp, q, dg);
         const bool solid = isinf(rc);
-        const double r = solid ? 0.0 : (-S.h2 * S.rhs[c] - q);
+        const double r = solid ? 0.0 : (-S.h2 * rhs[c] - q);
         // inner diagonal from the FP32 densities, as the inner passes see it
-        const float dg32 = diag_at<float>(rho32, c, t, k, S, fc, fzm, fzp);
+        const float dg32 = diag_cell<float>(rho32, c, nf, fc, fzm, fzp);
         const float z32 = dg32 > 0.0f ? (float)((scale * r) / (double)dg32) : 0.0f;
         z[c] = z32;
         const double rz = (double)dg32 * (double)z32;
@@ -454,11 +507,13 @@ __device__ void body_ir_update(const Slot &S, const SlotState &st, int64_t lt,
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
+    GLB double *__restrict__ x = gp(S.x);
+    GLB float *__restrict__ d = gp(S.d32);
     const double s = st.upd_s;
     int64_t c = (int64_t)t.k0 * t.P + t.q;
     for (int k = t.k0; k < t.k1; ++k, c += t.P) {
-        S.x[c] = refined(S.x[c], s, S.d32[c]);
-        S.d32[c] = 0.0f;
+        x[c] = refined(x[c], s, d[c]);
+        d[c] = 0.0f;
     }
 }
 
@@ -468,8 +523,9 @@ __device__ void body_zero_x(const Slot &S, const SlotState &st, int64_t lt,
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
+    GLB double *__restrict__ x = gp(S.x);
     int64_t c = (int64_t)t.k0 * t.P + t.q;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) S.x[c] = 0.0;
+    for (int k = t.k0; k < t.k1; ++k, c += t.P) x[c] = 0.0;
 }
 
 // ------------------------------------------------------------------------
@@ -628,35 +684,48 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
 // launch skeleton
 // ------------------------------------------------------------------------
 
-template <int FAMILY>
+// Launch positions of an iteration: K0 (rare first-half actions: set-up and
+// FP64 residuals), K1 (direction update), K2 (operator apply and vector
+// update).  K0 and K1 serve disjoint sets of first-half actions, so a slot
+// is worked on by exactly one of them; keeping the rare actions out of K1
+// keeps its register footprint (and so its occupancy) that of pass A alone.
+template <int FAMILY, int WHICH>
 __device__ __forceinline__ void run_body(int ph, const Slot &S,
                                          const SlotState &st, int64_t lt,
                                          double (&acc)[3])
 {
     if (FAMILY == PCG_PREC_FP64) {
-        switch (ph) {
-        case K1_INIT64: body_init64(S, st, lt, acc); break;
-        case K1_CG_A: body_passA<double>(S, st, lt, acc); break;
-        case K1_CHECK64: body_check64(S, st, lt, acc); break;
-        case K2_CG_B: body_passB<double, double>(S, st, lt, acc); break;
-        case K2_ZERO_X: body_zero_x(S, st, lt, acc); break;
-        default: break;
+        if (WHICH == 0) {
+            if (ph == K1_INIT64) body_init64(S, st, lt, acc);
+            else if (ph == K1_CHECK64) body_check64(S, st, lt, acc);
+        } else if (WHICH == 1) {
+            if (ph == K1_CG_A) body_passA<double>(S, st, lt, acc);
+        } else {
+            if (ph == K2_CG_B) body_passB<double, double>(S, st, lt, acc);
+            else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
         }
     } else {
-        switch (ph) {
-        case K1_IR_INIT: body_ir_init(S, st, lt, acc); break;
-        case K1_IR_RESID: body_ir_resid(S, st, lt, acc); break;
-        case K1_IR_A: body_passA<float>(S, st, lt, acc); break;
-        case K2_IR_B: body_passB<float, float>(S, st, lt, acc); break;
-        case K2_IR_UPDATE: body_ir_update(S, st, lt, acc); break;
-        case K2_ZERO_X: body_zero_x(S, st, lt, acc); break;
-        default: break;
+        if (WHICH == 0) {
+            if (ph == K1_IR_INIT) body_ir_init(S, st, lt, acc);
+            else if (ph == K1_IR_RESID) body_ir_resid(S, st, lt, acc);
+        } else if (WHICH == 1) {
+            if (ph == K1_IR_A) body_passA<float>(S, st, lt, acc);
+        } else {
+            if (ph == K2_IR_B) body_passB<float, float>(S, st, lt, acc);
+            else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);
+            else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
         }
     }
 }
 
-__device__ __forceinline__ bool is_k1(int ph) { return ph >= 1 && ph <= 10; }
-__device__ __forceinline__ bool is_k2(int ph) { return ph >= 11 && ph <= 19; }
+__device__ __forceinline__ bool serves(int which, int ph)
+{
+    if (which == 0)
+        return ph == K1_INIT64 || ph == K1_CHECK64 || ph == K1_IR_INIT ||
+               ph == K1_IR_RESID;
+    if (which == 1) return ph == K1_CG_A || ph == K1_IR_A;
+    return ph >= 11 && ph <= 19;
+}
 
 // Account `run` finished tiles of slot S; the last arrival sums the slot's
 // per-tile partials in tile order and advances its state machine.
@@ -673,10 +742,12 @@ __device__ __forceinline__ void arrive(const Slot &S, int ph, uint32_t run,
     if (*s_last) {
         __threadfence();
         double tot[3] = { 0.0, 0.0, 0.0 };
+        const GLB double *__restrict__ part = gp((const double *)S.partials);
+#pragma unroll 8
         for (int64_t t = threadIdx.x; t < S.ntiles; t += kBlock) {
-            tot[0] += load_agent(S.partials + kMaxPartials * t + 0);
-            tot[1] += load_agent(S.partials + kMaxPartials * t + 1);
-            tot[2] += load_agent(S.partials + kMaxPartials * t + 2);
+            tot[0] += part[kMaxPartials * t + 0];
+            tot[1] += part[kMaxPartials * t + 1];
+            tot[2] += part[kMaxPartials * t + 2];
         }
         block_sum<3>(tot, lds);
         if (threadIdx.x == 0) {
@@ -689,10 +760,10 @@ __device__ __forceinline__ void arrive(const Slot &S, int ph, uint32_t run,
     __syncthreads();
 }
 
-template <int FAMILY>
+// WHICH = 0, 1, 2: launch position within the iteration (see run_body).
+template <int FAMILY, int WHICH>
 __global__ void __launch_bounds__(kBlock)
-k_iter(const BatchHeader *__restrict__ hdr, const Slot *__restrict__ slots,
-       int which)
+k_iter(const BatchHeader *__restrict__ hdr, const Slot *__restrict__ slots)
 {
     __shared__ double lds[kMaxPartials * 4];
     __shared__ int s_last;
@@ -712,15 +783,15 @@ k_iter(const BatchHeader *__restrict__ hdr, const Slot *__restrict__ slots,
             cur_ph = S.st->phase;
         }
         const int ph = cur_ph;
-        if (which == 1 ? !is_k1(ph) : !is_k2(ph)) continue;
+        if (!serves(WHICH, ph)) continue;
         double acc[3] = { 0.0, 0.0, 0.0 };
-        run_body<FAMILY>(ph, S, *S.st, t - S.tile_begin, acc);
+        run_body<FAMILY, WHICH>(ph, S, *S.st, t - S.tile_begin, acc);
         block_sum<3>(acc, lds);
         if (threadIdx.x == 0) {
-            double *dst = S.partials + kMaxPartials * (t - S.tile_begin);
-            store_agent(dst + 0, acc[0]);
-            store_agent(dst + 1, acc[1]);
-            store_agent(dst + 2, acc[2]);
+            GLB double *dst = gp(S.partials) + kMaxPartials * (t - S.tile_begin);
+            dst[0] = acc[0];
+            dst[1] = acc[1];
+            dst[2] = acc[2];
         }
         ++run;
     }
@@ -762,12 +833,18 @@ hipError_t launch_iter(int family, int which, int grid,
                        const BatchHeader *hdr, const Slot *slots,
                        hipStream_t s)
 {
-    if (family == PCG_PREC_FP64)
-        hipLaunchKernelGGL(k_iter<PCG_PREC_FP64>, dim3(grid), dim3(kBlock), 0, s,
-                           hdr, slots, which);
-    else
-        hipLaunchKernelGGL(k_iter<PCG_PREC_FP32_IR>, dim3(grid), dim3(kBlock), 0,
-                           s, hdr, slots, which);
+    const dim3 g(grid), b(kBlock);
+#define PCG_LAUNCH(F, W) hipLaunchKernelGGL((k_iter<F, W>), g, b, 0, s, hdr, slots)
+    if (family == PCG_PREC_FP64) {
+        if (which == 0) PCG_LAUNCH(PCG_PREC_FP64, 0);
+        else if (which == 1) PCG_LAUNCH(PCG_PREC_FP64, 1);
+        else PCG_LAUNCH(PCG_PREC_FP64, 2);
+    } else {
+        if (which == 0) PCG_LAUNCH(PCG_PREC_FP32_IR, 0);
+        else if (which == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 1);
+        else PCG_LAUNCH(PCG_PREC_FP32_IR, 2);
+    }
+#undef PCG_LAUNCH
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1410_1942_amd import _lib as L
@@ -113,3 +114,53 @@ def test_null_handles(lib):
     assert lib.pcg_last_timing(None, None, None, None) == L.EINVAL
     ms = ctypes.c_double()
     assert lib.pcg_copy_probe(None, None, 0, 1, None, ctypes.byref(ms)) == L.EINVAL
+
+
+def _connectivity(lib, mask, bc):
+    nz, ny, nx = mask.shape
+    g = L.Grid(nx, ny, nz, 1.0 / nz)
+    b = L.BC()
+    for f in range(6):
+        b.kind[f] = bc[f]
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    return lib.pcg_check_connectivity(m.ctypes.data_as(ctypes.c_void_p),
+                                      ctypes.byref(g), ctypes.byref(b))
+
+
+def test_connectivity_check_matches_reference(lib, orc):
+    """The library's run-based flood fill agrees with the reference's
+    cell-by-cell search on random hulls and on hand-made pockets."""
+    rng = np.random.default_rng(5)
+    tank = (0, 0, 0, 0, 0, 1)
+    kinds = [tank, (1, 0, 0, 0, 0, 0), (0, 0, 0, 1, 0, 0), (0,) * 6,
+             (0, 0, 0, 0, 1, 0)]
+    agree = {True: 0, False: 0}
+    for trial in range(120):
+        shape = tuple(int(v) for v in rng.integers(1, 9, size=3))
+        dens = rng.uniform(0.2, 0.7)
+        mask = (rng.random(shape) < dens).astype(np.uint8)
+        bc = kinds[trial % len(kinds)]
+        want = orc.connected(mask, bc)
+        got = _connectivity(lib, mask, bc)
+        assert got == (L.OK if want else L.ESINGULAR), (trial, shape, bc)
+        agree[want] += 1
+    assert agree[True] > 10 and agree[False] > 10
+    # a sealed one-cell pocket at the bottom of an open tank
+    m = np.zeros((6, 6, 6), np.uint8)
+    m[0:2, 1:4, 1:4] = 1
+    m[0, 2, 2] = 0
+    assert _connectivity(lib, m, tank) == L.ESINGULAR
+    m[0, 2, 2] = 1
+    assert _connectivity(lib, m, tank) == L.OK
+    # no hull: fine with any Dirichlet wall, singular with none
+    assert lib.pcg_check_connectivity(None, ctypes.byref(_g(4, 4, 4)),
+                                      ctypes.byref(_bc_of(tank))) == L.OK
+    assert lib.pcg_check_connectivity(None, ctypes.byref(_g(4, 4, 4)),
+                                      ctypes.byref(_bc_of((0,) * 6))) == L.ESINGULAR
+
+
+def _bc_of(kinds):
+    b = L.BC()
+    for f in range(6):
+        b.kind[f] = kinds[f]
+    return b
