@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--profile-iters", type=int, default=0,
+                    help="short run for counter collection: copy probe of "
+                         "1 GiB, then FP64 and FP32+IR solves capped at this "
+                         "many iterations; prints a summary and exits")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
                                                       "traffic_wedge512.txt"))
     return ap.parse_args()
@@ -91,10 +95,17 @@ def main():
     cells = case.ncells
     torch.cuda.synchronize()
 
-    # achievable bandwidth: plain copy of 4 GiB
-    log("copy probe")
-    copy_gbs = copy_probe(1 << 29, reps=10)
-    log(f"  copy {copy_gbs:.0f} GB/s")
+    if args.profile_iters:
+        copy_gbs = copy_probe(1 << 27, reps=3)
+        res = {"copy_bytes": (1 << 27) * 8, "copy_GBps": copy_gbs, "cells": cells}
+        for prec, name in ((L.PREC_FP64, "fp64"), (L.PREC_FP32_IR, "ir")):
+            s = Solver(rho, mask, case.bc, case.h, precision=prec)
+            _, st = s.solve(rhs, tol=1e-30, maxit=args.profile_iters,
+                            raise_on_error=False)
+            s.close()
+            res[name] = st
+        print(json.dumps(res), flush=True)
+        return
 
     def step(precision=L.PREC_FP64, p=None, timing=False):
         s = Solver(rho, mask, case.bc, case.h, precision=precision)
@@ -104,6 +115,11 @@ def main():
         tm = s.last_timing() if timing else None
         s.close()
         return p, st, tm
+
+    # achievable bandwidth: plain copy of 4 GiB
+    log("copy probe")
+    copy_gbs = copy_probe(1 << 29, reps=10)
+    log(f"  copy {copy_gbs:.0f} GB/s")
 
     # setup alone (density encoding + host connectivity check)
     torch.cuda.synchronize()

@@ -1,0 +1,107 @@
+"""Summaries of rocprofv3 output (kernel trace statistics and PMC counters).
+
+Reads the CSV files rocprofv3 writes (--output-format csv) and prints short
+text summaries: per-kernel launch counts and durations, and per-kernel HBM
+bytes from the FETCH_SIZE / WRITE_SIZE counters, calibrated against the plain
+copy kernel of known size that the same run launches.
+
+    python -m paper_1410_1942_amd.profiling stats <kernel_stats.csv | kernel_trace.csv>
+    python -m paper_1410_1942_amd.profiling traffic <fetch counter_collection.csv>
+        <write counter_collection.csv> --cells N --copy-bytes B [--sha S]
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import statistics
+import sys
+
+
+def _short(name: str, width: int = 70) -> str:
+    return name if len(name) <= width else name[: width - 3] + "..."
+
+
+def kernel_stats(path: str) -> str:
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    if rows and "TotalDurationNs" in rows[0]:          # *_kernel_stats.csv
+        out.append(f"{'kernel':70s} {'calls':>7s} {'avg_ms':>10s} {'min_ms':>10s} "
+                   f"{'max_ms':>10s} {'total_s':>9s} {'pct':>6s}")
+        for r in rows:
+            out.append(f"{_short(r['Name']):70s} {int(r['Calls']):7d} "
+                       f"{float(r['AverageNs'])/1e6:10.4f} {float(r['MinNs'])/1e6:10.4f} "
+                       f"{float(r['MaxNs'])/1e6:10.4f} {float(r['TotalDurationNs'])/1e9:9.3f} "
+                       f"{float(r['Percentage']):6.2f}")
+        return "\n".join(out)
+    # *_kernel_trace.csv: aggregate ourselves
+    agg = collections.defaultdict(list)
+    for r in rows:
+        agg[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    out.append(f"{'kernel':70s} {'calls':>7s} {'avg_ms':>10s} {'median_ms':>10s} {'total_s':>9s}")
+    for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"{_short(k):70s} {len(v):7d} {statistics.mean(v)/1e6:10.4f} "
+                   f"{statistics.median(v)/1e6:10.4f} {sum(v)/1e9:9.3f}")
+    return "\n".join(out)
+
+
+def _counter(path: str):
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        agg[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return agg
+
+
+def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
+            sha: str = "") -> str:
+    """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by (true bytes / counted bytes) of the copy kernel, which
+    reads and writes copy_bytes per launch."""
+    f, w = _counter(fetch_csv), _counter(write_csv)
+    copy = [k for k in f if "k_copy" in k]
+    if not copy:
+        raise SystemExit("no copy kernel in the fetch run")
+    f_copy = statistics.median(f[copy[0]]) * 1024
+    w_copy = statistics.median(w[copy[0]]) * 1024
+    sf, sw = copy_bytes / f_copy, copy_bytes / w_copy
+    lines = [f"# FETCH_SIZE scale {sf:.4f}, WRITE_SIZE scale {sw:.4f} "
+             f"(copy kernel: {copy_bytes} B read and written per launch)",
+             f"# per launch, median over launches; cells = {cells}"]
+    if sha:
+        lines.append(f"kernel_source_sha = {sha}")
+    lines.append(f"{'kernel':58s} {'n':>4s} {'fetch_B':>14s} {'write_B':>14s} "
+                 f"{'fetch/cell':>10s} {'write/cell':>10s}")
+    for k in f:
+        if k not in w:
+            continue
+        fb = statistics.median(f[k]) * 1024 * sf
+        wb = statistics.median(w[k]) * 1024 * sw
+        lines.append(f"{_short(k, 58):58s} {len(f[k]):4d} {fb:14.4e} {wb:14.4e} "
+                     f"{fb / cells:10.2f} {wb / cells:10.2f}")
+        if "k_iter<0, 2>" in k:
+            lines.append(f"k2_hbm_bytes_per_launch = {fb + wb:.6e}")
+        if "k_iter<0, 1>" in k:
+            lines.append(f"k1_hbm_bytes_per_launch = {fb + wb:.6e}")
+    return "\n".join(lines)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_csv")
+    t.add_argument("write_csv")
+    t.add_argument("--cells", type=int, required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--sha", default="")
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        print(kernel_stats(a.csv))
+    else:
+        print(traffic(a.fetch_csv, a.write_csv, a.cells, a.copy_bytes, a.sha))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
