@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--serve-n", type=int, default=160)
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="short run for counter collection: copy probe of "
                          "1 GiB, then FP64 and FP32+IR solves capped at this "
@@ -257,7 +261,105 @@ def main():
                 case.rho, case.mask, case.bc, case.h, case.rhs, pir.cpu().numpy())
         log(f"  {cpu_val:.4f} Gcell-iter/s on {oracle.threads()} threads")
 
+    if not args.no_batch:
+        out["batch"] = bench_batch(args.batch_n)
+    if not args.no_serve:
+        out["served"] = bench_serve(args.serve_n)
+
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(nsolves):
+    """64 independent solves of uneven sizes (edges log-uniform in [16,128],
+    own surface, ratio 1000/1.2, FP32+IR to 1e-8) resident in one batch:
+    every launch covers all of them.  Compared with the same solves run one
+    after another through single-solve contexts."""
+    import torch
+    from paper_1410_1942_amd import _lib as L
+    from paper_1410_1942_amd import fields as F
+    from paper_1410_1942_amd import serve
+    from paper_1410_1942_amd.solver import Batch, Solver
+    log(f"batch of {nsolves}")
+    cases = [(F.batch_member(i, keep_velocity=False), 1e-8) for i in range(nsolves)]
+    reqs = serve.make_requests(cases, [0.0] * nsolves)
+    cells = sum(r.cells for r in reqs)
+    probe = Batch(1 << 20, 1, precision=L.PREC_FP32_IR)
+    need = sum(probe.footprint(tuple(r.rho.shape), r.h) for r in reqs) + (8 << 20)
+    probe.close()
+
+    def run_batch():
+        b = Batch(need, nsolves, precision=L.PREC_FP32_IR, check_every=16)
+        slots = []
+        for r in reqs:
+            r.p = torch.empty_like(r.rhs)
+            code, sl = b.admit(r.rho, r.mask, r.bc, r.h, r.rhs, r.p, tol=r.tol)
+            assert code == L.OK
+            slots.append(sl)
+        while b.step(1):
+            pass
+        sts = [b.poll(sl)[1] for sl in slots]
+        b.close()
+        return sts
+
+    run_batch()                                   # warm
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sts = run_batch()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    cell_iters = sum(r.cells * st["iters"] for r, st in zip(reqs, sts))
+    # the same solves one at a time
+    t = time.perf_counter()
+    for r in reqs:
+        s = Solver(r.rho, r.mask, r.bc, r.h, precision=L.PREC_FP32_IR)
+        s.solve(r.rhs, tol=r.tol)
+        s.close()
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    ok = all(st["status"] == 0 and st["rel_res_true"] <= 1e-8 for st in sts)
+    log(f"  batch {tb*1e3:.0f} ms, sequential {ts*1e3:.0f} ms, all ok {ok}")
+    return {
+        "solves": nsolves, "cells": cells, "precision": "fp32+ir", "tol": 1e-8,
+        "ms": round(tb * 1e3, 2), "solves_per_s": round(nsolves / tb, 2),
+        "Gcell_iter_per_s": round(cell_iters / tb / 1e9, 3),
+        "sequential_ms": round(ts * 1e3, 2), "speedup_vs_sequential": round(ts / tb, 3),
+        "all_converged": ok,
+        "inner_iters_max": max(st["iters"] for st in sts),
+    }
+
+
+def bench_serve(nreq):
+    """Served stream: requests with edges log-uniform in [24,192], wedge hull
+    with p = 0.5, tol 1e-6 or 1e-8, FP32+IR; first a capacity run (all
+    waiting at t = 0) on a prefix, then Poisson arrivals at 75 % of that
+    capacity over the whole stream."""
+    import torch
+    from paper_1410_1942_amd import fields as F
+    from paper_1410_1942_amd import serve
+    log(f"served stream of {nreq}")
+    cases = [F.served_request(i, keep_velocity=False) for i in range(nreq)]
+    arena = 24 << 30
+    ncap = min(nreq, 48)
+    reqs = serve.make_requests(cases[:ncap], [0.0] * ncap)
+    srv = serve.Server(arena, max_slots=64)
+    srv.run(reqs[: min(8, ncap)], realtime=False)          # warm
+    cap = srv.run(reqs, realtime=False)
+    rate = 0.75 * cap.solves_per_s
+    arrivals = F.arrival_times(nreq, rate=rate, seed=7)
+    for r in reqs:
+        del r
+    reqs = serve.make_requests(cases, arrivals)
+    torch.cuda.synchronize()
+    rep = srv.run(reqs, realtime=True)
+    srv.close()
+    log(f"  capacity {cap.solves_per_s:.1f}/s; at {rate:.1f}/s arrivals: "
+        f"{rep.solves_per_s:.1f}/s, p50 {rep.p50_ms:.1f} ms, p99 {rep.p99_ms:.1f} ms")
+    d = rep.as_dict()
+    d.update({"arrival_rate_per_s": round(rate, 2),
+              "capacity_solves_per_s": round(cap.solves_per_s, 2),
+              "capacity_requests": ncap, "precision": "fp32+ir",
+              "arena_GiB": arena / 2**30})
+    return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
 
 
 def kernel_sha():
