@@ -25,7 +25,7 @@ EXPORTED = [
     "pcg_batch_footprint", "pcg_batch_admit", "pcg_batch_step",
     "pcg_batch_poll", "pcg_batch_release", "pcg_batch_destroy",
     "pcg_set_timing", "pcg_last_timing", "pcg_copy_probe",
-    "pcg_check_connectivity",
+    "pcg_check_connectivity", "pcg_set_tile_rules", "pcg_get_tile_rules",
 ]
 
 
@@ -99,6 +99,8 @@ def load(path: str = LIB_PATH):
     lib.pcg_last_timing.argtypes = [vp, P(dbl), P(dbl), P(i32)]
     lib.pcg_copy_probe.argtypes = [vp, vp, sz, i32, vp, P(dbl)]
     lib.pcg_check_connectivity.argtypes = [vp, P(Grid), P(BC)]
+    lib.pcg_set_tile_rules.argtypes = [i32, i32, vp, vp, vp]
+    lib.pcg_get_tile_rules.argtypes = [i32, i32, vp, vp, vp, P(i32)]
     for name in EXPORTED:
         if name not in ("pcg_strerror", "pcg_last_hip_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -1,0 +1,185 @@
+"""Tile-shape autotuner.
+
+For each size class the tuner times short fixed-iteration solves (graph mode,
+as served) on a synthetic two-phase + wedge field of that size, for every
+candidate tile height tz and (single-solve) workgroup count, and keeps the
+fastest per iteration.  The result is a JSON table keyed by GPU architecture:
+
+    {"gfx950": {"fp64":    [[max_cells, tz, grid], ...],
+                "fp32_ir": [[max_cells, tz, grid], ...],
+                "measured": {...}}}
+
+``install()`` hands a table to the library (pcg_set_tile_rules); the binding
+calls it once per process with the table shipped in the package
+(``tile_table.json``) unless PCGMI_TILE_TABLE names another file or "none".
+Tile height depends only on a solve's own cell count, so a tuned table never
+makes a solve's result depend on the other solves it is batched with.
+
+    python -m paper_1410_1942_amd.autotune [--out FILE] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+from . import _lib as L
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(PKG, "tile_table.json")
+PREC_KEYS = {L.PREC_FP64: "fp64", L.PREC_FP32_IR: "fp32_ir"}
+
+CLASSES = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512]
+TZS = [2, 4, 8, 16, 32, 64]
+GRIDS = [256, 512, 1024, 2048]
+
+_installed = False
+
+
+def get_rules(precision: int):
+    lib = L.load()
+    cap = 64
+    mc = (ctypes.c_int64 * cap)()
+    tz = (ctypes.c_int32 * cap)()
+    gr = (ctypes.c_int32 * cap)()
+    n = ctypes.c_int32()
+    L.check(lib.pcg_get_tile_rules(int(precision), cap, mc, tz, gr, ctypes.byref(n)),
+            "pcg_get_tile_rules")
+    return [[int(mc[i]), int(tz[i]), int(gr[i])] for i in range(n.value)]
+
+
+def set_rules(precision: int, rules):
+    lib = L.load()
+    n = len(rules)
+    mc = (ctypes.c_int64 * n)(*[int(r[0]) for r in rules])
+    tz = (ctypes.c_int32 * n)(*[int(r[1]) for r in rules])
+    gr = (ctypes.c_int32 * n)(*[int(r[2]) if len(r) > 2 else 0 for r in rules])
+    L.check(lib.pcg_set_tile_rules(int(precision), n, mc, tz, gr), "pcg_set_tile_rules")
+
+
+def device_arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def install(path: str = None, arch: str = None) -> bool:
+    """Install the table for this GPU from `path` (default: the shipped one).
+    Returns False when the file has no entry for the architecture."""
+    path = path or TABLE
+    if not os.path.exists(path):
+        return False
+    table = json.load(open(path))
+    arch = arch or device_arch()
+    if arch not in table:
+        return False
+    for prec, key in PREC_KEYS.items():
+        if key in table[arch]:
+            set_rules(prec, table[arch][key])
+    return True
+
+
+def ensure_installed():
+    """Called by the binding before creating solvers (once per process)."""
+    global _installed
+    if _installed:
+        return
+    _installed = True
+    path = os.environ.get("PCGMI_TILE_TABLE", TABLE)
+    if path.lower() == "none":
+        return
+    try:
+        install(path)
+    except Exception as e:                       # a broken table must not stop solves
+        print(f"tile table not installed: {e}", file=sys.stderr)
+
+
+def _time_per_iter(dev_case, precision, tz, grid, target_ms=25.0):
+    import torch
+    from .solver import Solver
+    rho, mask, rhs, bc, h = dev_case
+    s = Solver(rho, mask, bc, h, precision=precision, tz=tz, grid_blocks=grid,
+               flags=L.SKIP_CONNECTIVITY_CHECK, check_every=16)
+    p = torch.empty_like(rhs)
+    s.solve(rhs, p=p, tol=1e-30, maxit=16, raise_on_error=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.solve(rhs, p=p, tol=1e-30, maxit=16, raise_on_error=False)
+    torch.cuda.synchronize()
+    est = (time.perf_counter() - t) / 16
+    iters = int(min(2000, max(32, math.ceil(target_ms * 1e-3 / max(est, 1e-6)))))
+    iters = (iters + 15) // 16 * 16
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.solve(rhs, p=p, tol=1e-30, maxit=iters, raise_on_error=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / iters
+    s.close()
+    return dt * 1e3
+
+
+def tune(classes=CLASSES, precisions=(L.PREC_FP64, L.PREC_FP32_IR), tzs=TZS,
+         grids=GRIDS, log=print):
+    import torch
+    from . import fields as F
+    dev = torch.device("cuda:0")
+    best = {prec: [] for prec in precisions}
+    measured = {}
+    for n in classes:
+        case = F.make_two_phase(n, n, n, surface_seed=1, velocity_seed=2,
+                                wedge=F.Wedge(), keep_velocity=False)
+        dev_case = (torch.from_numpy(case.rho).to(dev),
+                    torch.from_numpy(case.mask).to(dev),
+                    torch.from_numpy(case.rhs).to(dev), case.bc, case.h)
+        for prec in precisions:
+            key = PREC_KEYS[prec]
+            results = []
+            for tz in tzs:
+                if tz > n:
+                    continue
+                for g in grids:
+                    results.append((_time_per_iter(dev_case, prec, tz, g), tz, g))
+            results.sort()
+            ms, tz, g = results[0]
+            measured[f"{key}/{n}"] = [[round(m, 5), t, gg] for m, t, gg in results[:5]]
+            log(f"{key} n={n}: best tz={tz} grid={g} {ms*1e3:.1f} us/iter "
+                f"({n**3 / (ms * 1e-3) / 1e9:.2f} Gcell-iter/s)", flush=True)
+            best[prec].append((n ** 3, tz, g))
+        del dev_case
+        torch.cuda.empty_cache()
+    out = {}
+    for prec in precisions:
+        b = best[prec]
+        rules = []
+        for i, (cells, tz, g) in enumerate(b):
+            hi = int(math.sqrt(cells * b[i + 1][0])) if i + 1 < len(b) else 2 ** 62
+            rules.append([hi, tz, g])
+        out[PREC_KEYS[prec]] = rules
+    out["measured"] = measured
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE)
+    ap.add_argument("--quick", action="store_true",
+                    help="fewer classes and candidates")
+    a = ap.parse_args(argv)
+    kw = {}
+    if a.quick:
+        kw = dict(classes=[24, 64, 160], tzs=[4, 16, 32], grids=[512, 1024])
+    os.environ["PCGMI_TILE_TABLE"] = "none"
+    arch = device_arch()
+    table = tune(**kw)
+    full = json.load(open(a.out)) if os.path.exists(a.out) else {}
+    full[arch] = table
+    with open(a.out, "w") as f:
+        json.dump(full, f, indent=1)
+    print(f"wrote {a.out} [{arch}]")
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -65,19 +65,25 @@ double ms_since(Clock::time_point t0)
 
 struct TileRule {
     int64_t max_cells;  // rule applies to grids with at most this many cells
-    int tz;
+    int tz;             // planes per tile
+    int grid;           // workgroups for a single-solve context (0 = default)
 };
 
-std::vector<TileRule> g_rules_fp64 = { { 1 << 16, 8 }, { 1 << 22, 16 }, { INT64_MAX, 32 } };
-std::vector<TileRule> g_rules_ir = { { 1 << 16, 8 }, { 1 << 22, 16 }, { INT64_MAX, 32 } };
+// Built-in table: the autotuner's choice on gfx950 (package tile_table.json).
+std::vector<TileRule> g_rules[2] = {
+    { { 7524, 2, 256 }, { 21283, 2, 256 }, { 60198, 4, 1024 }, { 170267, 4, 2048 }, { 481589, 8, 512 }, { 1362140, 16, 1024 }, { 3852714, 32, 256 }, { 10897121, 64, 512 }, { 30821713, 64, 512 }, { 87176971, 32, 1024 }, { INT64_MAX, 64, 1024 } },
+    { { 7524, 2, 1024 }, { 21283, 2, 2048 }, { 60198, 4, 2048 }, { 170267, 4, 2048 }, { 481589, 8, 512 }, { 1362140, 16, 2048 }, { 3852714, 16, 512 }, { 10897121, 64, 2048 }, { 30821713, 32, 1024 }, { 87176971, 32, 1024 }, { INT64_MAX, 64, 1024 } },
+};
 
-int choose_tz(int64_t n, int prec)
+const TileRule &rule_for(int64_t n, int prec)
 {
-    const auto &rules = prec == PCG_PREC_FP32_IR ? g_rules_ir : g_rules_fp64;
+    const auto &rules = g_rules[prec == PCG_PREC_FP32_IR ? 1 : 0];
     for (const auto &r : rules)
-        if (n <= r.max_cells) return r.tz;
-    return 16;
+        if (n <= r.max_cells) return r;
+    return rules.back();
 }
+
+int choose_tz(int64_t n, int prec) { return rule_for(n, prec).tz; }
 
 // ---- first-fit allocator over [0, size) ----
 
@@ -538,11 +544,12 @@ struct Engine {
 
     int choose_grid() const
     {
-        const int gmax = grid_opt > 0 ? grid_opt : kDefaultGridMax;
-        int g = gmax;
+        int g = grid_opt > 0 ? grid_opt : kDefaultGridMax;
         if (max_slots == 1) {
-            int64_t t = 0;
-            for (auto &S : slots) if (S.used) t = std::max<int64_t>(t, S.geo.ntiles);
+            int64_t t = 0, n = 0;
+            for (auto &S : slots)
+                if (S.used) { t = std::max<int64_t>(t, S.geo.ntiles); n = S.geo.n; }
+            if (grid_opt <= 0 && n > 0 && rule_for(n, prec).grid > 0) g = rule_for(n, prec).grid;
             if (t > 0 && t < g) g = (int)t;
         }
         g = std::max(8, (g + 7) / 8 * 8);
@@ -784,6 +791,39 @@ int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
     std::vector<uint8_t> m(host_mask, host_mask + n);
     return fluid_reaches_dirichlet(m, grid->nx, grid->ny, grid->nz, bm) ? PCG_OK
                                                                         : PCG_ESINGULAR;
+}
+
+int pcg_set_tile_rules(int32_t precision, int32_t n, const int64_t *max_cells,
+                       const int32_t *tz, const int32_t *grid)
+{
+    if (precision != PCG_PREC_FP64 && precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
+    if (n < 1 || n > 64 || !max_cells || !tz) return PCG_EINVAL;
+    std::vector<TileRule> rules;
+    for (int i = 0; i < n; ++i) {
+        if (tz[i] < 1 || max_cells[i] < 1) return PCG_EINVAL;
+        if (i > 0 && max_cells[i] <= max_cells[i - 1]) return PCG_EINVAL;
+        const int g = grid ? grid[i] : 0;
+        if (g < 0) return PCG_EINVAL;
+        rules.push_back({ max_cells[i], tz[i], g });
+    }
+    rules.back().max_cells = INT64_MAX;   // the last rule covers every size
+    g_rules[precision == PCG_PREC_FP32_IR ? 1 : 0] = rules;
+    return PCG_OK;
+}
+
+int pcg_get_tile_rules(int32_t precision, int32_t cap, int64_t *max_cells,
+                       int32_t *tz, int32_t *grid, int32_t *n_out)
+{
+    if (precision != PCG_PREC_FP64 && precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
+    if (!n_out || cap < 0) return PCG_EINVAL;
+    const auto &rules = g_rules[precision == PCG_PREC_FP32_IR ? 1 : 0];
+    *n_out = (int32_t)rules.size();
+    for (int i = 0; i < cap && i < (int)rules.size(); ++i) {
+        if (max_cells) max_cells[i] = rules[i].max_cells;
+        if (tz) tz[i] = rules[i].tz;
+        if (grid) grid[i] = rules[i].grid;
+    }
+    return PCG_OK;
 }
 
 int pcg_destroy(pcg_ctx_t *c)

@@ -62,6 +62,8 @@ class Solver:
                  h: float, precision: int = L.PREC_FP64, flags: int = 0,
                  stream: Optional[torch.cuda.Stream] = None, **opt_kw):
         lib = L.load()
+        from .autotune import ensure_installed
+        ensure_installed()
         _require_device(rho, mask)
         if rho.dtype != torch.float64:
             raise ValueError("rho must be float64")
@@ -133,6 +135,8 @@ class Batch:
                  precision: int = L.PREC_FP32_IR, device="cuda",
                  stream: Optional[torch.cuda.Stream] = None, **opt_kw):
         lib = L.load()
+        from .autotune import ensure_installed
+        ensure_installed()
         self.lib = lib
         self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8,
                                  device=device)

@@ -164,3 +164,35 @@ def _bc_of(kinds):
     for f in range(6):
         b.kind[f] = kinds[f]
     return b
+
+
+def test_tile_rules_roundtrip(lib):
+    """The tile table is host state: set, read back, validation, and the
+    workspace size follows the installed tile height."""
+    from paper_1410_1942_amd import autotune
+    saved = autotune.get_rules(0)
+    try:
+        autotune.set_rules(0, [[1000, 4, 256], [10**6, 8, 0], [10**9, 64, 512]])
+        got = autotune.get_rules(0)
+        assert [r[1:] for r in got] == [[4, 256], [8, 0], [64, 512]]
+        assert got[-1][0] >= 2**62                 # last rule covers every size
+        n = ctypes.c_int32()
+        bad = (ctypes.c_int64 * 2)(10, 5)          # not increasing
+        tz = (ctypes.c_int32 * 2)(4, 8)
+        assert lib.pcg_set_tile_rules(0, 2, bad, tz, None) == L.EINVAL
+        assert lib.pcg_set_tile_rules(3, 2, bad, tz, None) == L.EINVAL
+        zero = (ctypes.c_int32 * 2)(0, 8)
+        ok_mc = (ctypes.c_int64 * 2)(5, 10)
+        assert lib.pcg_set_tile_rules(0, 2, ok_mc, zero, None) == L.EINVAL
+        # workspace: partial sums scale with the number of tiles (tz = 64 -> fewer)
+        o = L.Opts()
+        w64 = ctypes.c_size_t()
+        lib.pcg_workspace_bytes(ctypes.byref(_g(128, 128, 128)), ctypes.byref(o),
+                                ctypes.byref(w64))
+        autotune.set_rules(0, [[10**9, 1, 0]])
+        w1 = ctypes.c_size_t()
+        lib.pcg_workspace_bytes(ctypes.byref(_g(128, 128, 128)), ctypes.byref(o),
+                                ctypes.byref(w1))
+        assert w1.value > w64.value
+    finally:
+        autotune.set_rules(0, saved)
