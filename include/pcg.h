@@ -96,7 +96,8 @@ enum {
  *   check_every iterations per captured graph replay between host polls [32]
  *   flags       PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK
  *   inner_maxit FP32_IR: cap on inner iterations per refinement trip [none]
- *   inner_tol   FP32_IR: relative reduction of each inner solve [1e-5]
+ *   inner_tol   FP32_IR: relative reduction asked of each inner solve, never
+ *               more than the last refinement trip needs [1e-4]
  *   tz          cells per tile along z; 0 = chosen by the autotuner table
  *   grid_blocks workgroups per launch; 0 = chosen by the autotuner table
  */

@@ -50,7 +50,7 @@ int hip_fail(hipError_t e, const char *what)
 constexpr size_t kAlign = 256;
 constexpr int kDefaultCheckEvery = 32;
 constexpr int kDefaultGridMax = 1024;
-constexpr double kDefaultInnerTol = 1e-5;
+constexpr double kDefaultInnerTol = 1e-4;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

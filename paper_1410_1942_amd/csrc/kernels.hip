@@ -315,7 +315,7 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
     for (int k = t.k0; k < t.k1; ++k, c += P) {
         const T pc = pnew(c);
         const T rc = rho[c];
-        pd[c] = pc;
+        __builtin_nontemporal_store(pc, &pd[c]);
         const T lrxm = rho[c + n.oxm], lrym = rho[c + n.oym];
         const T lpxm = pnew(c + n.oxm), lpym = pnew(c + n.oym);
         const T rxm = n.hxm ? lrxm : n.wxm, rym = n.hym ? lrym : n.wym;
@@ -368,8 +368,8 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
         const T rym = n.hym ? lrym : n.wym, ryp = n.hyp ? lryp : n.wyp;
         const T vxm = n.hxm ? lvxm : T(0), vxp = n.hxp ? lvxp : T(0);
         const T vym = n.hym ? lvym : T(0), vyp = n.hyp ? lvyp : T(0);
-        const X xc = x[c];
-        T zc = z[c];
+        const X xc = __builtin_nontemporal_load(&x[c]);
+        T zc = __builtin_nontemporal_load(&z[c]);
         const T bxm = fb(rc + rxm), bxp = fb(rc + rxp);
         const T bym = fb(rc + rym), byp = fb(rc + ryp);
         const T bzp = fb(rc + rzp);
@@ -377,10 +377,10 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
         const T q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) +
                      (bym * (vc - vym) + byp * (vc - vyp))) +
                     (bzm * (vc - vzm) + bzp * (vc - vzp));
-        x[c] = xc + (X)(alpha * vc);
+        __builtin_nontemporal_store(xc + (X)(alpha * vc), &x[c]);
         const T inv = dg > T(0) ? recip(dg) : T(0);   // hull rows keep z = 0
         zc -= alpha * q * inv;
-        z[c] = zc;
+        __builtin_nontemporal_store(zc, &z[c]);
         const double dd = (double)dg, dz = (double)zc;
         const double r = dd * dz;
         a0 += r * dz;
@@ -630,6 +630,10 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
             st.rz = tot[1];
             st.rr0_inner = tot[2];
             st.rr = tot[2];
+            // ask the inner solve for its usual reduction, but never for more
+            // than this trip needs to bring the outer residual to half of tol
+            const double need2 = 0.25 * st.tol2 / rr;
+            st.inner_goal2 = need2 > st.inner_tol2 ? need2 : st.inner_tol2;
         }
         break;
     }
@@ -664,7 +668,7 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         st.beta = tot[0] / st.rz;
         st.rz = tot[0];
         if (!isfinite(st.rr)) { finish(st, PCG_EBREAKDOWN); break; }
-        const bool inner_done = st.rr <= st.inner_tol2 * st.rr0_inner ||
+        const bool inner_done = st.rr <= st.inner_goal2 * st.rr0_inner ||
                                 st.inner_iter >= st.inner_maxit ||
                                 st.iter >= st.maxit;
         if (inner_done) {

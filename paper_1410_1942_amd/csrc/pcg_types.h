@@ -46,6 +46,7 @@ struct alignas(128) SlotState {
     double scale;     // IR: power-of-two scale of the current inner system
     double upd_s;     // IR: multiplier of the pending update x += upd_s * d
     double tol;
+    double inner_goal2; // IR: (reduction asked of the current inner solve)^2
     int32_t phase;
     int32_t after;    // K1 action after a K2_NONE
     int32_t status;   // PCG_PENDING while running, else the final code
