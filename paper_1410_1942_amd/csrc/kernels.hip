@@ -228,7 +228,7 @@ __device__ __forceinline__ double refined(double x, double s, float d)
 // ------------------------------------------------------------------------
 
 // K1_INIT64: b = -h^2 Sigma (0 on hull), r = b (cold) or b - A x0 (warm),
-// z = r / diag.  acc = [b.b, r.z, r.r].
+// z = r / diag, both direction buffers zeroed.  acc = [b.b, r.z, r.r].
 __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
                             double (&acc)[3])
 {
@@ -238,6 +238,8 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
     GLB double *__restrict__ x = gp(S.x);
     GLB double *__restrict__ z = gp((double *)S.z);
     const GLB double *__restrict__ rhs = gp(S.rhs);
+    GLB double *__restrict__ pa = gp((double *)S.pa);
+    GLB double *__restrict__ pb = gp((double *)S.pb);
     const Nbr<double> n = make_nbr<double>(t, S);
     const bool warm = st.warm != 0;
     const int64_t P = t.P;
@@ -271,6 +273,8 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
         }
         const double zc = dg > 0.0 ? r / dg : 0.0;
         z[c] = zc;
+        pa[c] = 0.0;
+        pb[c] = 0.0;
         a0 += b * b;
         a1 += r * zc;
         a2 += r * r;
@@ -297,11 +301,13 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
     const GLB T *__restrict__ z = gp((const T *)S.z);
     const GLB T *__restrict__ rho =
         gp(std::is_same<T, double>::value ? (const T *)S.rho64 : (const T *)S.rho32);
-    const bool first = st.first != 0;
-    const T beta = (T)st.beta;
+    // first direction: beta = 0.  p_old is then still read (it holds zeros
+    // from the set-up phase or a finite earlier direction), which keeps the
+    // loads unconditional and lets them all be in flight together.
+    const T beta = st.first ? T(0) : (T)st.beta;
     auto pnew = [&](int64_t m) -> T {
-        const T zz = z[m];
-        return first ? zz : zz + beta * ps[m];
+        const T zz = z[m], pp = ps[m];
+        return zz + beta * pp;
     };
     const Nbr<T> n = make_nbr<T>(t, S);
     const int bm = S.bcmask;
@@ -311,22 +317,31 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
     int64_t c = (int64_t)t.k0 * P + t.q;
     T pzm = T(0), rzm = n.wzm;
     if (t.k0 > 0) { pzm = pnew(c - P); rzm = rho[c - P]; }
+    // own values of the current plane; those of the next plane are loaded
+    // together with this plane's neighbours, so every load of an iteration
+    // is issued before any of them is used
+    T zc = z[c], qc = ps[c], rc = rho[c];
     double a = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += P) {
-        const T pc = pnew(c);
-        const T rc = rho[c];
-        __builtin_nontemporal_store(pc, &pd[c]);
-        const T lrxm = rho[c + n.oxm], lrym = rho[c + n.oym];
-        const T lpxm = pnew(c + n.oxm), lpym = pnew(c + n.oym);
+        const T zxm = z[c + n.oxm], qxm = ps[c + n.oxm], lrxm = rho[c + n.oxm];
+        const T zym = z[c + n.oym], qym = ps[c + n.oym], lrym = rho[c + n.oym];
+        const int64_t cn = k + 1 < t.k1 ? c + P : c;
+        const T zn = z[cn], qn = ps[cn], rn = rho[cn];
+        const T pc = zc + beta * qc;
         const T rxm = n.hxm ? lrxm : n.wxm, rym = n.hym ? lrym : n.wym;
-        const T pxm = n.hxm ? lpxm : T(0), pym = n.hym ? lpym : T(0);
+        const T pxm = n.hxm ? zxm + beta * qxm : T(0);
+        const T pym = n.hym ? zym + beta * qym : T(0);
         const T dx = pc - pxm, dy = pc - pym, dz = pc - pzm;
         T s = (fb(rc + rxm) * dx * dx + fb(rc + rym) * dy * dy) + fb(rc + rzm) * dz * dz;
         const int w = hw + ((k == S.nz - 1 && (bm & 32)) ? 1 : 0);
         if (w) s += (T)w * fb(rc) * (pc * pc);
         a += (double)s;
+        __builtin_nontemporal_store(pc, &pd[c]);
         pzm = pc;
         rzm = rc;
+        zc = zn;
+        qc = qn;
+        rc = rn;
     }
     acc[0] += a;
 }
@@ -427,7 +442,8 @@ __device__ void body_check64(const Slot &S, const SlotState &st, int64_t lt,
     acc[0] += a;
 }
 
-// K1_IR_INIT: x = 0 (cold) or hull entries cleared (warm), d = 0; acc = [b.b].
+// K1_IR_INIT: x = 0 (cold) or hull entries cleared (warm), d = 0, both
+// direction buffers zeroed; acc = [b.b].
 __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
                              double (&acc)[3])
 {
@@ -436,6 +452,8 @@ __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
     const GLB double *__restrict__ rho = gp(S.rho64);
     GLB double *__restrict__ x = gp(S.x);
     GLB float *__restrict__ d = gp(S.d32);
+    GLB float *__restrict__ pa = gp((float *)S.pa);
+    GLB float *__restrict__ pb = gp((float *)S.pb);
     const GLB double *__restrict__ rhs = gp(S.rhs);
     int64_t c = (int64_t)t.k0 * t.P + t.q;
     const bool warm = st.warm != 0;
@@ -444,6 +462,8 @@ __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
         const bool solid = isinf(rho[c]);
         if (!warm || solid) x[c] = 0.0;
         d[c] = 0.0f;
+        pa[c] = 0.0f;
+        pb[c] = 0.0f;
         const double b = solid ? 0.0 : -S.h2 * rhs[c];
         a += b * b;
     }
