@@ -26,9 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per cell of the two iteration kernels (FP64 / FP32 inner)
-BYTES_K1 = {"fp64": 32, "fp32": 16}   # read p_old, z, rho; write p
-BYTES_K2 = {"fp64": 48, "fp32": 24}   # read x, p, z, rho; write x, z
+# algorithmic bytes per cell of the two iteration kernels, by precision and
+# coefficient source (a one-byte density class, or the density itself)
+#   pass A: read p_old, z, coefficient key; write p
+#   pass B: read x, p, z, coefficient key; write x, z
+BYTES_K1 = {("fp64", "classes"): 25, ("fp64", "density"): 32,
+            ("fp32", "classes"): 13, ("fp32", "density"): 16}
+BYTES_K2 = {("fp64", "classes"): 41, ("fp64", "density"): 48,
+            ("fp32", "classes"): 21, ("fp32", "density"): 24}
 
 
 def log(msg):
@@ -111,8 +116,11 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
+    coef = {}
+
     def step(precision=L.PREC_FP64, p=None, timing=False):
         s = Solver(rho, mask, case.bc, case.h, precision=precision)
+        coef[precision] = "classes" if s.density_classes() else "density"
         if timing:
             s.set_timing(True)
         p, st = s.solve(rhs, p=p, tol=args.tol)
@@ -183,33 +191,35 @@ def main():
     if not args.no_roofline:
         log("event-timed solve")
         _, stt, (k1_ms, k2_ms, nlaunch) = step(p=p64, timing=True)
-        a2 = BYTES_K2["fp64"] * cells / (k2_ms * 1e-3) / 1e9
-        a1 = BYTES_K1["fp64"] * cells / (k1_ms * 1e-3) / 1e9
+        mode = coef[L.PREC_FP64]
+        b1, b2 = BYTES_K1[("fp64", mode)], BYTES_K2[("fp64", mode)]
+        a2 = b2 * cells / (k2_ms * 1e-3) / 1e9
+        a1 = b1 * cells / (k1_ms * 1e-3) / 1e9
         traffic = None
         tr = read_traffic(args.traffic)
         if tr and tr.get("kernel_source_sha") == kernel_sha():
+            key = f"bytes[k_iter<0, 2, {1 if mode == 'classes' else 0}>]"
             try:
-                traffic = float(tr["k2_hbm_bytes_per_launch"])
+                traffic = float(tr[key])
             except (KeyError, ValueError):
                 traffic = None
         out["roofline"] = {
             "bound": "hbm", "achieved": round(a2, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(a2 / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_iter<FP64,2>: operator apply + x/z update + r.z, r.r "
-                      f"({BYTES_K2['fp64']} B/cell)",
+            "kernel": f"k_iter<FP64,2,{mode}>: operator apply + x/z update + "
+                      f"r.z, r.r ({b2} B/cell)",
             "avg_ms": round(k2_ms, 4), "launches": nlaunch,
             "frac_of_copy": round(a2 / copy_gbs, 4),
         }
         out["kernel_k1"] = {
-            "kernel": "k_iter<FP64,1>: p update + p.Ap "
-                      f"({BYTES_K1['fp64']} B/cell)",
+            "kernel": f"k_iter<FP64,1,{mode}>: p update + p.Ap ({b1} B/cell)",
             "avg_ms": round(k1_ms, 4), "achieved_GBps": round(a1, 1),
             "frac": round(a1 / HBM_PEAK_GBS, 4),
         }
         per_iter_ms = k1_ms + k2_ms
-        out["iteration_GBps"] = round(
-            (BYTES_K1["fp64"] + BYTES_K2["fp64"]) * cells / (per_iter_ms * 1e-3) / 1e9, 1)
+        out["iteration_GBps"] = round((b1 + b2) * cells / (per_iter_ms * 1e-3) / 1e9, 1)
+        out["coefficients"] = mode
         log(f"  K1 {k1_ms:.3f} ms ({a1:.0f} GB/s)  K2 {k2_ms:.3f} ms ({a2:.0f} GB/s)")
 
     # mixed precision: FP32 stencil, FP64 refinement, same input and tolerance

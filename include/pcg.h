@@ -83,9 +83,15 @@ enum { PCG_PREC_FP64 = 0, PCG_PREC_FP32_IR = 1 };
 
 enum {
     PCG_WARM_START = 1,              /* p holds an initial guess on entry    */
-    PCG_SKIP_CONNECTIVITY_CHECK = 2  /* trust that every fluid region touches
+    PCG_SKIP_CONNECTIVITY_CHECK = 2, /* trust that every fluid region touches
                                         a Dirichlet wall (skips a host flood
                                         fill of the mask)                    */
+    PCG_NO_DENSITY_CLASSES = 4       /* always read the FP64/FP32 density per
+                                        cell; by default a field with at most
+                                        14 distinct fluid densities is coded
+                                        as one byte per cell plus a table of
+                                        exact face coefficients (same
+                                        operator, fewer bytes per iteration) */
 };
 
 /*
@@ -94,7 +100,8 @@ enum {
  *               and vectors inside, FP64 residual, dot products, alpha/beta
  *               and solution update (iterative refinement).
  *   check_every iterations per captured graph replay between host polls [32]
- *   flags       PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK
+ *   flags       PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK |
+ *               PCG_NO_DENSITY_CLASSES
  *   inner_maxit FP32_IR: cap on inner iterations per refinement trip [none]
  *   inner_tol   FP32_IR: relative reduction asked of each inner solve, never
  *               more than the last refinement trip needs [1e-4]
@@ -179,6 +186,13 @@ int pcg_solve(pcg_ctx_t *ctx, const double *rhs, double *p, double tol,
  */
 int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
                            const pcg_bc_t *bc);
+
+/*
+ * Number of density classes the context codes its field with (1..14), or 0
+ * when it reads a density per cell (more distinct densities than classes,
+ * or PCG_NO_DENSITY_CLASSES).
+ */
+int pcg_density_classes(const pcg_ctx_t *ctx, int32_t *nclasses);
 
 /* Release the context (not the workspace).  NULL is accepted. */
 int pcg_destroy(pcg_ctx_t *ctx);

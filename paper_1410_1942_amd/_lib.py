@@ -17,7 +17,7 @@ EINVAL, EDOMAIN, ESINGULAR, EBREAKDOWN, ENOMEM, EBUSY, EHIP, EUNSUPPORTED = \
     -1, -2, -3, -4, -5, -6, -7, -8
 BC_NEUMANN, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 PREC_FP64, PREC_FP32_IR = 0, 1
-WARM_START, SKIP_CONNECTIVITY_CHECK = 1, 2
+WARM_START, SKIP_CONNECTIVITY_CHECK, NO_DENSITY_CLASSES = 1, 2, 4
 
 EXPORTED = [
     "pcg_workspace_bytes", "pcg_setup", "pcg_solve", "pcg_destroy",
@@ -26,6 +26,7 @@ EXPORTED = [
     "pcg_batch_poll", "pcg_batch_release", "pcg_batch_destroy",
     "pcg_set_timing", "pcg_last_timing", "pcg_copy_probe",
     "pcg_check_connectivity", "pcg_set_tile_rules", "pcg_get_tile_rules",
+    "pcg_density_classes",
 ]
 
 
@@ -100,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.pcg_copy_probe.argtypes = [vp, vp, sz, i32, vp, P(dbl)]
     lib.pcg_check_connectivity.argtypes = [vp, P(Grid), P(BC)]
     lib.pcg_set_tile_rules.argtypes = [i32, i32, vp, vp, vp]
+    lib.pcg_density_classes.argtypes = [vp, P(i32)]
     lib.pcg_get_tile_rules.argtypes = [i32, i32, vp, vp, vp, P(i32)]
     for name in EXPORTED:
         if name not in ("pcg_strerror", "pcg_last_hip_error"):

@@ -22,8 +22,11 @@
 #include "pcg_types.h"
 
 namespace pcgmi {
-hipError_t launch_iter(int family, int which, int grid, const BatchHeader *hdr,
-                       const Slot *slots, hipStream_t s);
+hipError_t launch_iter(int family, int which, int mode, int grid,
+                       const BatchHeader *hdr, const Slot *slots, hipStream_t s);
+hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n,
+                           unsigned long long cand, int cls_id,
+                           unsigned long long *next, hipStream_t s);
 hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
                          float *r32, int64_t n, int *bad, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
@@ -166,6 +169,8 @@ size_t slot_bytes(const Geometry &G, int prec)
     b += 3 * align_up(es * n, kAlign);               // z, pa, pb
     if (prec == PCG_PREC_FP32_IR) b += align_up(4 * n, kAlign);  // d32
     b += align_up(kMaxPartials * 8 * (size_t)G.ntiles, kAlign);  // partials
+    b += align_up(n, kAlign);                                      // classes
+    b += align_up(kClasses * kClasses * 12, kAlign);              // tables
     return b;
 }
 
@@ -206,7 +211,8 @@ int check_opts(const pcg_opts_t *o)
     if (o->precision != PCG_PREC_FP64 && o->precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
     if (o->check_every < 0 || o->inner_maxit < 0 || o->tz < 0 || o->grid_blocks < 0) return PCG_EINVAL;
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0 || std::isnan(o->inner_tol)) return PCG_EINVAL;
-    if (o->flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK)) return PCG_EINVAL;
+    if (o->flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES))
+        return PCG_EINVAL;
     return PCG_OK;
 }
 
@@ -288,6 +294,11 @@ struct SlotHost {
     void *z = nullptr, *pa = nullptr, *pb = nullptr;
     float *d32 = nullptr;
     double *partials = nullptr;
+    uint8_t *cls = nullptr;      // arena: class per cell
+    double *tab64 = nullptr;     // arena: kClasses^2 coefficients
+    float *tab32 = nullptr;
+    bool classes = false;        // class coding in use
+    int nclasses = 0;            // fluid classes when coded
     const double *rhs = nullptr;
     double *x = nullptr;
     Clock::time_point t0;
@@ -324,6 +335,8 @@ struct Engine {
     bool table_dirty = true;
     int64_t total_tiles = 0;
     int nrunning = 0;
+    int modes = 0;          // bit 0: a running slot uses densities, bit 1: classes
+    int graph_modes = -1;   // modes the captured graph was built for
     // timing mode
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -382,7 +395,7 @@ struct Engine {
         HIP_TRY(hipHostMalloc((void **)&h_hdr, sizeof(BatchHeader), hipHostMallocDefault));
         HIP_TRY(hipHostMalloc((void **)&h_slots, sizeof(Slot) * nslots, hipHostMallocDefault));
         HIP_TRY(hipHostMalloc((void **)&h_states, sizeof(SlotState) * nslots, hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc((void **)&h_bad, sizeof(int), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void **)&h_bad, 64, hipHostMallocDefault));  // flag + class search word
         std::memset(h_states, 0, sizeof(SlotState) * nslots);
         for (int i = 0; i < nslots; ++i) h_states[i].phase = PH_IDLE;
         HIP_TRY(hipMemcpyAsync(d_states, h_states, sizeof(SlotState) * nslots,
@@ -450,6 +463,11 @@ struct Engine {
         S.pb = p; p += align_up(es * n, kAlign);
         if (prec == PCG_PREC_FP32_IR) { S.d32 = (float *)p; p += align_up(4 * n, kAlign); }
         S.partials = (double *)p;
+        p += align_up(kMaxPartials * 8 * (size_t)geo.ntiles, kAlign);
+        S.cls = (uint8_t *)p;
+        p += align_up(n, kAlign);
+        S.tab64 = (double *)p;
+        S.tab32 = (float *)(p + kClasses * kClasses * 8);
 
         *h_bad = 0;
         hipError_t e = hipMemcpyAsync(d_bad, h_bad, sizeof(int), hipMemcpyHostToDevice, stream);
@@ -458,8 +476,61 @@ struct Engine {
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) { alloc.release(off, need); return hip_fail(e, "encode"); }
         if (*h_bad) { alloc.release(off, need); return PCG_EDOMAIN; }
+        if (!(flags & PCG_NO_DENSITY_CLASSES)) {
+            st = classify(S);
+            if (st) { alloc.release(off, need); return st; }
+        }
         S.used = true;
         *slot_out = id;
+        return PCG_OK;
+    }
+
+    // Code the densities as classes when there are at most kMaxFluidClasses
+    // distinct fluid values: one device pass per class finds the next
+    // distinct value and labels the cells equal to the current one; the face
+    // coefficient table is computed here in FP64 (and FP32) exactly as
+    // 2/(rho_a + rho_b).
+    int classify(SlotHost &S)
+    {
+        unsigned long long *d_next = (unsigned long long *)(d_bad + 2);
+        unsigned long long *h_next = (unsigned long long *)(h_bad + 2);
+        std::vector<double> pal;
+        unsigned long long cand = 0;
+        for (int r = 0;; ++r) {
+            if (r - 1 >= kMaxFluidClasses) return PCG_OK;   // too many: densities
+            *h_next = ~0ull;
+            HIP_TRY(hipMemcpyAsync(d_next, h_next, 8, hipMemcpyHostToDevice, stream));
+            HIP_TRY(launch_classify(S.rho64, S.cls, S.geo.n, cand, r - 1, d_next, stream));
+            HIP_TRY(hipMemcpyAsync(h_next, d_next, 8, hipMemcpyDeviceToHost, stream));
+            HIP_TRY(hipStreamSynchronize(stream));
+            if (r > 0) {
+                double v;
+                std::memcpy(&v, &cand, 8);
+                pal.push_back(v);
+            }
+            if (*h_next == ~0ull) break;
+            cand = *h_next;
+        }
+        double rho[kClasses];
+        for (int a = 0; a < kClasses; ++a) rho[a] = 0.0;
+        for (size_t a = 0; a < pal.size(); ++a) rho[a] = pal[a];
+        rho[kClsWallD] = 0.0;
+        rho[kClsSolid] = INFINITY;
+        std::vector<double> t64(kClasses * kClasses);
+        std::vector<float> t32(kClasses * kClasses);
+        for (int a = 0; a < kClasses; ++a)
+            for (int b = 0; b < kClasses; ++b) {
+                const bool live = (a < (int)pal.size() || a >= kClsWallD) &&
+                                  (b < (int)pal.size() || b >= kClsWallD);
+                const double sum = rho[a] + rho[b];
+                t64[a * kClasses + b] = live && std::isfinite(sum) && sum > 0.0 ? 2.0 / sum : 0.0;
+                const float sf = (float)rho[a] + (float)rho[b];
+                t32[a * kClasses + b] = live && std::isfinite(sf) && sf > 0.0f ? 2.0f / sf : 0.0f;
+            }
+        HIP_TRY(hipMemcpy(S.tab64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(S.tab32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice));
+        S.classes = true;
+        S.nclasses = (int)pal.size();
         return PCG_OK;
     }
 
@@ -507,6 +578,7 @@ struct Engine {
         if (!table_dirty) return PCG_OK;
         int64_t tb = 0;
         int ns = 0;
+        int m = 0;
         for (int id = 0; id < max_slots; ++id) {
             SlotHost &S = slots[id];
             if (!S.used || !S.running) continue;
@@ -530,12 +602,17 @@ struct Engine {
             d.d32 = S.d32;
             d.partials = S.partials;
             d.st = d_states + id;
+            d.cls = S.classes ? S.cls : nullptr;
+            d.tab64 = S.tab64;
+            d.tab32 = S.tab32;
+            m |= S.classes ? 2 : 1;
             tb += S.geo.ntiles;
         }
         h_hdr->total_tiles = tb;
         h_hdr->nslots = ns;
         total_tiles = tb;
         nrunning = ns;
+        modes = m;
         if (ns) HIP_TRY(hipMemcpyAsync(d_slots, h_slots, sizeof(Slot) * ns, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipMemcpyAsync(d_hdr, h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, stream));
         table_dirty = false;
@@ -559,25 +636,36 @@ struct Engine {
     int capture()
     {
         const int g = choose_grid();
-        if (exec && g == grid) return PCG_OK;
+        if (exec && g == grid && modes == graph_modes) return PCG_OK;
         if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
         if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
         grid = g;
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
         for (int i = 0; i < check_every && err == hipSuccess; ++i)
-            for (int w = 0; w < 3 && err == hipSuccess; ++w)
-                err = launch_iter(prec, w, grid, d_hdr, d_slots, cap);
+            err = launch_iteration(cap);
         hipGraph_t gph = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &gph);
         if (err != hipSuccess) { if (gph) (void)hipGraphDestroy(gph); return hip_fail(err, "capture launch"); }
         if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
         graph = gph;
         HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        graph_modes = modes;
         return PCG_OK;
     }
 
-    // Direct launches with an event around each kernel (timing mode).
+    // One iteration: K0, then K1 and K2 of each coefficient mode in use.
+    hipError_t launch_iteration(hipStream_t s)
+    {
+        hipError_t e = launch_iter(prec, 0, 0, grid, d_hdr, d_slots, s);
+        for (int w = 1; w < 3 && e == hipSuccess; ++w)
+            for (int m = 0; m < 2 && e == hipSuccess; ++m)
+                if (modes & (1 << m)) e = launch_iter(prec, w, m, grid, d_hdr, d_slots, s);
+        return e;
+    }
+
+    // Direct launches with an event around each kernel position (timing
+    // mode): K1 and K2 durations include every coefficient mode in use.
     int timed_chunk()
     {
         const int ne = 3 * check_every + 1;
@@ -589,7 +677,9 @@ struct Engine {
         HIP_TRY(hipEventRecord(ev[0], stream));
         for (int i = 0; i < check_every; ++i)
             for (int w = 0; w < 3; ++w) {
-                HIP_TRY(launch_iter(prec, w, grid, d_hdr, d_slots, stream));
+                for (int m = 0; m < 2; ++m)
+                    if (w == 0 ? m == 0 : (modes & (1 << m)) != 0)
+                        HIP_TRY(launch_iter(prec, w, m, grid, d_hdr, d_slots, stream));
                 HIP_TRY(hipEventRecord(ev[3 * i + w + 1], stream));
             }
         HIP_TRY(hipEventSynchronize(ev[ne - 1]));
@@ -826,6 +916,14 @@ int pcg_get_tile_rules(int32_t precision, int32_t cap, int64_t *max_cells,
     return PCG_OK;
 }
 
+int pcg_density_classes(const pcg_ctx_t *c, int32_t *nclasses)
+{
+    if (!c || !nclasses) return PCG_EINVAL;
+    const SlotHost &S = c->eng.slots[c->slot];
+    *nclasses = S.classes ? std::max(1, S.nclasses) : 0;
+    return PCG_OK;
+}
+
 int pcg_destroy(pcg_ctx_t *c)
 {
     delete c;
@@ -899,7 +997,8 @@ int pcg_batch_admit(pcg_batch_t *b, const pcg_grid_t *grid, const double *rho,
 {
     if (!b || !slot || !rhs || !p) return PCG_EINVAL;
     if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0) return PCG_EINVAL;
-    if (flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK)) return PCG_EINVAL;
+    if (flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES))
+        return PCG_EINVAL;
     int id = -1;
     int st = b->eng.prepare(grid, rho, mask, bc, flags, &id);
     if (st) return st;

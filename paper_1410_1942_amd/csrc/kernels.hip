@@ -143,21 +143,57 @@ __device__ __forceinline__ T fb(T den)
     return den < inf ? T(2) * recip(den) : T(0);
 }
 
-// Per-thread neighbour description for the x/y faces of a column: offset to
-// the neighbour (0 at a wall, so the load stays in bounds) and the density
-// standing in for a missing neighbour.
+// ------------------------------------------------------------------------
+// coefficient sources
+// ------------------------------------------------------------------------
+// A body reads a "key" per cell and turns two keys into a face coefficient.
+//  * RhoCoef: the key is the density (hull cells +inf); beta = 2/(a + b).
+//    A wall stands in as a neighbour of density 0 (Dirichlet: beta = 2/rho_c,
+//    the mirrored ghost) or +inf (Neumann: beta = 0).
+//  * ClsCoef: the key is a one-byte density class; beta comes from a 16x16
+//    table of exact 2/(rho_a + rho_b) held in LDS.  Class kClsWallD stands
+//    for a Dirichlet wall, kClsSolid for the hull and Neumann walls.
+// Both give the same operator; classes move 1 byte per cell instead of 8
+// and need no reciprocal per face.
+
 template <typename T>
-struct Nbr {
-    int oxm, oxp, oym, oyp;
-    bool hxm, hxp, hym, hyp;
-    T wxm, wxp, wym, wyp, wzm, wzp;
+struct RhoCoef {
+    using Key = T;
+    const GLB T *__restrict__ rho;
+    __device__ __forceinline__ Key load(int64_t c) const { return rho[c]; }
+    __device__ __forceinline__ Key dirichlet() const { return T(0); }
+    __device__ __forceinline__ Key neumann() const { return (T)INFINITY; }
+    __device__ __forceinline__ bool solid(Key k) const { return isinf(k); }
+    __device__ __forceinline__ T beta(Key a, Key b) const { return fb(a + b); }
 };
 
 template <typename T>
-__device__ __forceinline__ Nbr<T> make_nbr(const TileCtx &t, const Slot &S)
+struct ClsCoef {
+    using Key = int;
+    const GLB uint8_t *__restrict__ cls;
+    const T *tab;   // LDS, kClasses x kClasses
+    __device__ __forceinline__ Key load(int64_t c) const { return cls[c]; }
+    __device__ __forceinline__ Key dirichlet() const { return kClsWallD; }
+    __device__ __forceinline__ Key neumann() const { return kClsSolid; }
+    __device__ __forceinline__ bool solid(Key k) const { return k == kClsSolid; }
+    __device__ __forceinline__ T beta(Key a, Key b) const { return tab[a * kClasses + b]; }
+};
+
+// Per-thread neighbour description for the x/y faces of a column: offset to
+// the neighbour (0 at a wall, so the load stays in bounds) and the key
+// standing in for a missing neighbour.
+template <typename Key>
+struct Nbr {
+    int oxm, oxp, oym, oyp;
+    bool hxm, hxp, hym, hyp;
+    Key wxm, wxp, wym, wyp, wzm, wzp;
+};
+
+template <class C>
+__device__ __forceinline__ Nbr<typename C::Key> make_nbr(const TileCtx &t,
+                                                         const Slot &S, const C &cf)
 {
-    Nbr<T> n;
-    const T inf = (T)INFINITY;
+    Nbr<typename C::Key> n;
     const int bm = S.bcmask;
     n.hxm = t.i > 0;
     n.hxp = t.i < S.nx - 1;
@@ -167,51 +203,57 @@ __device__ __forceinline__ Nbr<T> make_nbr(const TileCtx &t, const Slot &S)
     n.oxp = n.hxp ? 1 : 0;
     n.oym = n.hym ? -S.nx : 0;
     n.oyp = n.hyp ? S.nx : 0;
-    n.wxm = (bm & 1) ? T(0) : inf;
-    n.wxp = (bm & 2) ? T(0) : inf;
-    n.wym = (bm & 4) ? T(0) : inf;
-    n.wyp = (bm & 8) ? T(0) : inf;
-    n.wzm = (bm & 16) ? T(0) : inf;
-    n.wzp = (bm & 32) ? T(0) : inf;
+    n.wxm = (bm & 1) ? cf.dirichlet() : cf.neumann();
+    n.wxp = (bm & 2) ? cf.dirichlet() : cf.neumann();
+    n.wym = (bm & 4) ? cf.dirichlet() : cf.neumann();
+    n.wyp = (bm & 8) ? cf.dirichlet() : cf.neumann();
+    n.wzm = (bm & 16) ? cf.dirichlet() : cf.neumann();
+    n.wzp = (bm & 32) ? cf.dirichlet() : cf.neumann();
     return n;
 }
 
 // Full operator at one cell: q = (A v)_c, dg = A_cc, given the cell's value
-// and density, the z neighbours (already substituted at walls: value 0 and
-// wall density) and a fetch of v for the x/y neighbours.
-template <typename T, class Fetch>
-__device__ __forceinline__ void apply_cell(Fetch v, const GLB T *__restrict__ rho,
-                                           int64_t c, const Nbr<T> &n, T vc, T rc,
-                                           T vzm, T rzm, T vzp, T rzp, T &q, T &dg)
+// and key, the z neighbours (already substituted at walls: value 0 and wall
+// key) and a fetch of v for the x/y neighbours.
+template <typename T, class C, class Fetch>
+__device__ __forceinline__ void apply_cell(Fetch v, const C &cf, int64_t c,
+                                           const Nbr<typename C::Key> &n, T vc,
+                                           typename C::Key kc, T vzm,
+                                           typename C::Key kzm, T vzp,
+                                           typename C::Key kzp, T &q, T &dg)
 {
+    using K = typename C::Key;
     // loads are unconditional (wall offsets are 0); walls substituted after
-    const T lrxm = rho[c + n.oxm], lrxp = rho[c + n.oxp];
-    const T lrym = rho[c + n.oym], lryp = rho[c + n.oyp];
+    const K lkxm = cf.load(c + n.oxm), lkxp = cf.load(c + n.oxp);
+    const K lkym = cf.load(c + n.oym), lkyp = cf.load(c + n.oyp);
     const T lvxm = v(c + n.oxm), lvxp = v(c + n.oxp);
     const T lvym = v(c + n.oym), lvyp = v(c + n.oyp);
-    const T rxm = n.hxm ? lrxm : n.wxm, rxp = n.hxp ? lrxp : n.wxp;
-    const T rym = n.hym ? lrym : n.wym, ryp = n.hyp ? lryp : n.wyp;
+    const K kxm = n.hxm ? lkxm : n.wxm, kxp = n.hxp ? lkxp : n.wxp;
+    const K kym = n.hym ? lkym : n.wym, kyp = n.hyp ? lkyp : n.wyp;
     const T vxm = n.hxm ? lvxm : T(0), vxp = n.hxp ? lvxp : T(0);
     const T vym = n.hym ? lvym : T(0), vyp = n.hyp ? lvyp : T(0);
-    const T bxm = fb(rc + rxm), bxp = fb(rc + rxp);
-    const T bym = fb(rc + rym), byp = fb(rc + ryp);
-    const T bzm = fb(rc + rzm), bzp = fb(rc + rzp);
+    const T bxm = cf.beta(kc, kxm), bxp = cf.beta(kc, kxp);
+    const T bym = cf.beta(kc, kym), byp = cf.beta(kc, kyp);
+    const T bzm = cf.beta(kc, kzm), bzp = cf.beta(kc, kzp);
     dg = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
     q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) + (bym * (vc - vym) + byp * (vc - vyp))) +
         (bzm * (vc - vzm) + bzp * (vc - vzp));
 }
 
 // Diagonal only.
-template <typename T>
-__device__ __forceinline__ T diag_cell(const GLB T *__restrict__ rho, int64_t c,
-                                       const Nbr<T> &n, T rc, T rzm, T rzp)
+template <typename T, class C>
+__device__ __forceinline__ T diag_cell(const C &cf, int64_t c,
+                                       const Nbr<typename C::Key> &n,
+                                       typename C::Key kc, typename C::Key kzm,
+                                       typename C::Key kzp)
 {
-    const T lrxm = rho[c + n.oxm], lrxp = rho[c + n.oxp];
-    const T lrym = rho[c + n.oym], lryp = rho[c + n.oyp];
-    const T rxm = n.hxm ? lrxm : n.wxm, rxp = n.hxp ? lrxp : n.wxp;
-    const T rym = n.hym ? lrym : n.wym, ryp = n.hyp ? lryp : n.wyp;
-    return ((fb(rc + rxm) + fb(rc + rxp)) + (fb(rc + rym) + fb(rc + ryp))) +
-           (fb(rc + rzm) + fb(rc + rzp));
+    using K = typename C::Key;
+    const K lkxm = cf.load(c + n.oxm), lkxp = cf.load(c + n.oxp);
+    const K lkym = cf.load(c + n.oym), lkyp = cf.load(c + n.oyp);
+    const K kxm = n.hxm ? lkxm : n.wxm, kxp = n.hxp ? lkxp : n.wxp;
+    const K kym = n.hym ? lkym : n.wym, kyp = n.hyp ? lkyp : n.wyp;
+    return ((cf.beta(kc, kxm) + cf.beta(kc, kxp)) + (cf.beta(kc, kym) + cf.beta(kc, kyp))) +
+           (cf.beta(kc, kzm) + cf.beta(kc, kzp));
 }
 
 // x + s d, evaluated identically wherever the refined iterate is needed.
@@ -224,50 +266,54 @@ __device__ __forceinline__ double refined(double x, double s, float d)
 // phase bodies (one tile each); acc[] receives this thread's partial sums.
 // Every body marches its column up through planes k0..k1-1 carrying the
 // k-1 and k values; z neighbours beyond the domain are replaced by the wall
-// (value 0, density 0 for Dirichlet / +inf for Neumann).
+// (value 0 and the wall's key).
 // ------------------------------------------------------------------------
 
 // K1_INIT64: b = -h^2 Sigma (0 on hull), r = b (cold) or b - A x0 (warm),
 // z = r / diag, both direction buffers zeroed.  acc = [b.b, r.z, r.r].
+template <class C>
 __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
-                            double (&acc)[3])
+                            const C &cf, double (&acc)[3])
 {
+    using K = typename C::Key;
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const GLB double *__restrict__ rho = gp(S.rho64);
     GLB double *__restrict__ x = gp(S.x);
     GLB double *__restrict__ z = gp((double *)S.z);
     const GLB double *__restrict__ rhs = gp(S.rhs);
     GLB double *__restrict__ pa = gp((double *)S.pa);
     GLB double *__restrict__ pb = gp((double *)S.pb);
-    const Nbr<double> n = make_nbr<double>(t, S);
+    const Nbr<K> n = make_nbr(t, S, cf);
     const bool warm = st.warm != 0;
     const int64_t P = t.P;
     // warm start: hull entries of x0 are read as 0 (they are cleared here)
     auto xv = [&](int64_t m) -> double {
-        const double r = rho[m], v = x[m];
-        return isinf(r) ? 0.0 : v;
+        const K k = cf.load(m);
+        const double v = x[m];
+        return cf.solid(k) ? 0.0 : v;
     };
     int64_t c = (int64_t)t.k0 * P + t.q;
-    double rc = rho[c];
+    K kc = cf.load(c);
     double xc = warm ? xv(c) : 0.0;
-    double rzm = n.wzm, xzm = 0.0;
-    if (t.k0 > 0) { rzm = rho[c - P]; if (warm) xzm = xv(c - P); }
+    K kzm = n.wzm;
+    double xzm = 0.0;
+    if (t.k0 > 0) { kzm = cf.load(c - P); if (warm) xzm = xv(c - P); }
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += P) {
         const bool top = k == S.nz - 1;
-        double rzp = n.wzp, xzp = 0.0;
-        if (!top) { rzp = rho[c + P]; if (warm) xzp = xv(c + P); }
-        const bool solid = isinf(rc);
+        K kzp = n.wzp;
+        double xzp = 0.0;
+        if (!top) { kzp = cf.load(c + P); if (warm) xzp = xv(c + P); }
+        const bool solid = cf.solid(kc);
         const double b = solid ? 0.0 : -S.h2 * rhs[c];
         double r, dg;
         if (warm) {
             double q;
-            apply_cell<double>(xv, rho, c, n, xc, rc, xzm, rzm, xzp, rzp, q, dg);
+            apply_cell<double>(xv, cf, c, n, xc, kc, xzm, kzm, xzp, kzp, q, dg);
             r = solid ? 0.0 : b - q;
             if (solid) x[c] = 0.0;
         } else {
-            dg = diag_cell<double>(rho, c, n, rc, rzm, rzp);
+            dg = diag_cell<double>(cf, c, n, kc, kzm, kzp);
             r = b;
             x[c] = 0.0;
         }
@@ -278,70 +324,74 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
         a0 += b * b;
         a1 += r * zc;
         a2 += r * r;
-        rzm = rc; xzm = xc;
-        rc = rzp; xc = xzp;
+        kzm = kc; xzm = xc;
+        kc = kzp; xc = xzp;
     }
     acc[0] += a0;
     acc[1] += a1;
     acc[2] += a2;
 }
 
-// K1_CG_A / K1_IR_A: p_new = z + beta p_old (z when first), stored; the
-// quadratic form p.Ap = sum over faces of beta_f (p_c - p_n)^2, each face
-// counted once from the cell above it (x, y, z low faces), plus the wall
-// terms (2/rho_c) p_c^2 of the Dirichlet walls.
-template <typename T>
+// K1_CG_A / K1_IR_A: p_new = z + beta p_old, stored; the quadratic form
+// p.Ap = sum over faces of beta_f (p_c - p_n)^2, each face counted once
+// from the cell above it (x, y, z low faces), plus the wall terms
+// (2/rho_c) p_c^2 of the Dirichlet walls.
+template <typename T, class C>
 __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
-                           double (&acc)[3])
+                           const C &cf, double (&acc)[3])
 {
+    using K = typename C::Key;
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
     const GLB T *__restrict__ ps = gp((const T *)(st.pbuf ? S.pb : S.pa));
     GLB T *__restrict__ pd = gp((T *)(st.pbuf ? S.pa : S.pb));
     const GLB T *__restrict__ z = gp((const T *)S.z);
-    const GLB T *__restrict__ rho =
-        gp(std::is_same<T, double>::value ? (const T *)S.rho64 : (const T *)S.rho32);
     // first direction: beta = 0.  p_old is then still read (it holds zeros
     // from the set-up phase or a finite earlier direction), which keeps the
     // loads unconditional and lets them all be in flight together.
     const T beta = st.first ? T(0) : (T)st.beta;
-    auto pnew = [&](int64_t m) -> T {
-        const T zz = z[m], pp = ps[m];
-        return zz + beta * pp;
-    };
-    const Nbr<T> n = make_nbr<T>(t, S);
+    const Nbr<K> n = make_nbr(t, S, cf);
     const int bm = S.bcmask;
     // Dirichlet high walls of this column (x+, y+); z+ is added on the top plane
     const int hw = ((!n.hxp && (bm & 2)) ? 1 : 0) + ((!n.hyp && (bm & 8)) ? 1 : 0);
     const int64_t P = t.P;
     int64_t c = (int64_t)t.k0 * P + t.q;
-    T pzm = T(0), rzm = n.wzm;
-    if (t.k0 > 0) { pzm = pnew(c - P); rzm = rho[c - P]; }
+    T pzm = T(0);
+    K kzm = n.wzm;
+    if (t.k0 > 0) {
+        const T zz = z[c - P], qq = ps[c - P];
+        pzm = zz + beta * qq;
+        kzm = cf.load(c - P);
+    }
     // own values of the current plane; those of the next plane are loaded
     // together with this plane's neighbours, so every load of an iteration
     // is issued before any of them is used
-    T zc = z[c], qc = ps[c], rc = rho[c];
+    T zc = z[c], qc = ps[c];
+    K kc = cf.load(c);
     double a = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += P) {
-        const T zxm = z[c + n.oxm], qxm = ps[c + n.oxm], lrxm = rho[c + n.oxm];
-        const T zym = z[c + n.oym], qym = ps[c + n.oym], lrym = rho[c + n.oym];
+        const T zxm = z[c + n.oxm], qxm = ps[c + n.oxm];
+        const T zym = z[c + n.oym], qym = ps[c + n.oym];
+        const K lkxm = cf.load(c + n.oxm), lkym = cf.load(c + n.oym);
         const int64_t cn = k + 1 < t.k1 ? c + P : c;
-        const T zn = z[cn], qn = ps[cn], rn = rho[cn];
+        const T zn = z[cn], qn = ps[cn];
+        const K kn = cf.load(cn);
         const T pc = zc + beta * qc;
-        const T rxm = n.hxm ? lrxm : n.wxm, rym = n.hym ? lrym : n.wym;
+        const K kxm = n.hxm ? lkxm : n.wxm, kym = n.hym ? lkym : n.wym;
         const T pxm = n.hxm ? zxm + beta * qxm : T(0);
         const T pym = n.hym ? zym + beta * qym : T(0);
         const T dx = pc - pxm, dy = pc - pym, dz = pc - pzm;
-        T s = (fb(rc + rxm) * dx * dx + fb(rc + rym) * dy * dy) + fb(rc + rzm) * dz * dz;
+        T s = (cf.beta(kc, kxm) * dx * dx + cf.beta(kc, kym) * dy * dy) +
+              cf.beta(kc, kzm) * dz * dz;
         const int w = hw + ((k == S.nz - 1 && (bm & 32)) ? 1 : 0);
-        if (w) s += (T)w * fb(rc) * (pc * pc);
+        if (w) s += (T)w * cf.beta(kc, cf.dirichlet()) * (pc * pc);
         a += (double)s;
         __builtin_nontemporal_store(pc, &pd[c]);
         pzm = pc;
-        rzm = rc;
+        kzm = kc;
         zc = zn;
         qc = qn;
-        rc = rn;
+        kc = kn;
     }
     acc[0] += a;
 }
@@ -349,45 +399,47 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
 // K2_CG_B (T = double, X = double: x) / K2_IR_B (T = float, X = float: d):
 // q = A p, x += alpha p, z -= alpha q / diag; acc = [r.z, r.r] with
 // r = diag z.  The low z face coefficient is carried from the plane below.
-template <typename T, typename X>
+template <typename T, typename X, class C>
 __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
-                           double (&acc)[3])
+                           const C &cf, double (&acc)[3])
 {
+    using K = typename C::Key;
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
     const GLB T *__restrict__ p = gp((const T *)(st.pbuf ? S.pb : S.pa));
-    const GLB T *__restrict__ rho =
-        gp(std::is_same<T, double>::value ? (const T *)S.rho64 : (const T *)S.rho32);
     GLB T *__restrict__ z = gp((T *)S.z);
     GLB X *__restrict__ x = gp(std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32);
     const T alpha = (T)st.alpha;
-    const Nbr<T> n = make_nbr<T>(t, S);
+    const Nbr<K> n = make_nbr(t, S, cf);
     const int64_t P = t.P;
     int64_t c = (int64_t)t.k0 * P + t.q;
-    T vc = p[c], rc = rho[c];
-    T vzm = T(0), rzm = n.wzm;
-    if (t.k0 > 0) { vzm = p[c - P]; rzm = rho[c - P]; }
-    T bzm = fb(rc + rzm);
+    T vc = p[c];
+    K kc = cf.load(c);
+    T vzm = T(0);
+    K kzm = n.wzm;
+    if (t.k0 > 0) { vzm = p[c - P]; kzm = cf.load(c - P); }
+    T bzm = cf.beta(kc, kzm);
     double a0 = 0.0, a1 = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += P) {
         const bool top = k == S.nz - 1;
         const int64_t cz = top ? c : c + P;
-        const T vzp_l = p[cz], rzp_l = rho[cz];
-        const T vzp = top ? T(0) : vzp_l;
-        const T rzp = top ? n.wzp : rzp_l;
-        const T lrxm = rho[c + n.oxm], lrxp = rho[c + n.oxp];
-        const T lrym = rho[c + n.oym], lryp = rho[c + n.oyp];
+        const T vzp_l = p[cz];
+        const K kzp_l = cf.load(cz);
+        const K lkxm = cf.load(c + n.oxm), lkxp = cf.load(c + n.oxp);
+        const K lkym = cf.load(c + n.oym), lkyp = cf.load(c + n.oyp);
         const T lvxm = p[c + n.oxm], lvxp = p[c + n.oxp];
         const T lvym = p[c + n.oym], lvyp = p[c + n.oyp];
-        const T rxm = n.hxm ? lrxm : n.wxm, rxp = n.hxp ? lrxp : n.wxp;
-        const T rym = n.hym ? lrym : n.wym, ryp = n.hyp ? lryp : n.wyp;
-        const T vxm = n.hxm ? lvxm : T(0), vxp = n.hxp ? lvxp : T(0);
-        const T vym = n.hym ? lvym : T(0), vyp = n.hyp ? lvyp : T(0);
         const X xc = __builtin_nontemporal_load(&x[c]);
         T zc = __builtin_nontemporal_load(&z[c]);
-        const T bxm = fb(rc + rxm), bxp = fb(rc + rxp);
-        const T bym = fb(rc + rym), byp = fb(rc + ryp);
-        const T bzp = fb(rc + rzp);
+        const T vzp = top ? T(0) : vzp_l;
+        const K kzp = top ? n.wzp : kzp_l;
+        const K kxm = n.hxm ? lkxm : n.wxm, kxp = n.hxp ? lkxp : n.wxp;
+        const K kym = n.hym ? lkym : n.wym, kyp = n.hyp ? lkyp : n.wyp;
+        const T vxm = n.hxm ? lvxm : T(0), vxp = n.hxp ? lvxp : T(0);
+        const T vym = n.hym ? lvym : T(0), vyp = n.hyp ? lvyp : T(0);
+        const T bxm = cf.beta(kc, kxm), bxp = cf.beta(kc, kxp);
+        const T bym = cf.beta(kc, kym), byp = cf.beta(kc, kyp);
+        const T bzp = cf.beta(kc, kzp);
         const T dg = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
         const T q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) +
                      (bym * (vc - vym) + byp * (vc - vyp))) +
@@ -403,53 +455,57 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
         vzm = vc;
         bzm = bzp;
         vc = vzp;
-        rc = rzp;
+        kc = kzp;
     }
     acc[0] += a0;
     acc[1] += a1;
 }
 
 // K1_CHECK64: ||b - A x||^2 with the FP64 operator.
+template <class C>
 __device__ void body_check64(const Slot &S, const SlotState &st, int64_t lt,
-                             double (&acc)[3])
+                             const C &cf, double (&acc)[3])
 {
+    using K = typename C::Key;
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const GLB double *__restrict__ rho = gp(S.rho64);
     const GLB double *__restrict__ x = gp((const double *)S.x);
     const GLB double *__restrict__ rhs = gp(S.rhs);
-    const Nbr<double> n = make_nbr<double>(t, S);
+    const Nbr<K> n = make_nbr(t, S, cf);
     auto xv = [&](int64_t m) -> double { return x[m]; };
     const int64_t P = t.P;
     int64_t c = (int64_t)t.k0 * P + t.q;
-    double vc = x[c], rc = rho[c];
-    double vzm = 0.0, rzm = n.wzm;
-    if (t.k0 > 0) { vzm = x[c - P]; rzm = rho[c - P]; }
+    double vc = x[c];
+    K kc = cf.load(c);
+    double vzm = 0.0;
+    K kzm = n.wzm;
+    if (t.k0 > 0) { vzm = x[c - P]; kzm = cf.load(c - P); }
     double a = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += P) {
         const bool top = k == S.nz - 1;
-        double vzp = 0.0, rzp = n.wzp;
-        if (!top) { vzp = x[c + P]; rzp = rho[c + P]; }
+        double vzp = 0.0;
+        K kzp = n.wzp;
+        if (!top) { vzp = x[c + P]; kzp = cf.load(c + P); }
         double q, dg;
-        apply_cell<double>(xv, rho, c, n, vc, rc, vzm, rzm, vzp, rzp, q, dg);
-        if (!isinf(rc)) {
+        apply_cell<double>(xv, cf, c, n, vc, kc, vzm, kzm, vzp, kzp, q, dg);
+        if (!cf.solid(kc)) {
             const double r = -S.h2 * rhs[c] - q;
             a += r * r;
         }
-        vzm = vc; rzm = rc;
-        vc = vzp; rc = rzp;
+        vzm = vc; kzm = kc;
+        vc = vzp; kc = kzp;
     }
     acc[0] += a;
 }
 
 // K1_IR_INIT: x = 0 (cold) or hull entries cleared (warm), d = 0, both
 // direction buffers zeroed; acc = [b.b].
+template <class C>
 __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
-                             double (&acc)[3])
+                             const C &cf, double (&acc)[3])
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const GLB double *__restrict__ rho = gp(S.rho64);
     GLB double *__restrict__ x = gp(S.x);
     GLB float *__restrict__ d = gp(S.d32);
     GLB float *__restrict__ pa = gp((float *)S.pa);
@@ -459,7 +515,7 @@ __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
     const bool warm = st.warm != 0;
     double a = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += t.P) {
-        const bool solid = isinf(rho[c]);
+        const bool solid = cf.solid(cf.load(c));
         if (!warm || solid) x[c] = 0.0;
         d[c] = 0.0f;
         pa[c] = 0.0f;
@@ -471,50 +527,54 @@ __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
 }
 
 // K1_IR_RESID: r = b - A64 (x + s d) in FP64, and the scaled inner right-hand
-// side in z form, z32 = (scale r) / diag32.  acc = [r.r, r32.z32, r32.r32].
+// side in z form, z32 = (scale r) / diag32, with diag32 the diagonal the
+// FP32 passes use (cf32).  acc = [r.r, r32.z32, r32.r32].
+template <class C64, class C32>
 __device__ void body_ir_resid(const Slot &S, const SlotState &st, int64_t lt,
-                              double (&acc)[3])
+                              const C64 &cf, const C32 &cf32, double (&acc)[3])
 {
+    using K = typename C64::Key;
+    using KF = typename C32::Key;
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const GLB double *__restrict__ rho = gp(S.rho64);
-    const GLB float *__restrict__ rho32 = gp((const float *)S.rho32);
     const GLB double *__restrict__ x = gp((const double *)S.x);
     const GLB float *__restrict__ d = gp((const float *)S.d32);
     GLB float *__restrict__ z = gp((float *)S.z);
     const GLB double *__restrict__ rhs = gp(S.rhs);
     const double s = st.upd_s;
     const double scale = st.scale;
-    const Nbr<double> n = make_nbr<double>(t, S);
-    const Nbr<float> nf = make_nbr<float>(t, S);
+    const Nbr<K> n = make_nbr(t, S, cf);
+    const Nbr<KF> nf = make_nbr(t, S, cf32);
     auto xe = [&](int64_t m) -> double { return refined(x[m], s, d[m]); };
     const int64_t P = t.P;
     int64_t c = (int64_t)t.k0 * P + t.q;
-    double vc = xe(c), rc = rho[c];
-    float fc = rho32[c];
-    double vzm = 0.0, rzm = n.wzm;
-    float fzm = nf.wzm;
-    if (t.k0 > 0) { vzm = xe(c - P); rzm = rho[c - P]; fzm = rho32[c - P]; }
+    double vc = xe(c);
+    K kc = cf.load(c);
+    KF fc = cf32.load(c);
+    double vzm = 0.0;
+    K kzm = n.wzm;
+    KF fzm = nf.wzm;
+    if (t.k0 > 0) { vzm = xe(c - P); kzm = cf.load(c - P); fzm = cf32.load(c - P); }
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += P) {
         const bool top = k == S.nz - 1;
-        double vzp = 0.0, rzp = n.wzp;
-        float fzp = nf.wzp;
-        if (!top) { vzp = xe(c + P); rzp = rho[c + P]; fzp = rho32[c + P]; }
+        double vzp = 0.0;
+        K kzp = n.wzp;
+        KF fzp = nf.wzp;
+        if (!top) { vzp = xe(c + P); kzp = cf.load(c + P); fzp = cf32.load(c + P); }
         double q, dg;
-        apply_cell<double>(xe, rho, c, n, vc, rc, vzm, rzm, vzp, rzp, q, dg);
-        const bool solid = isinf(rc);
+        apply_cell<double>(xe, cf, c, n, vc, kc, vzm, kzm, vzp, kzp, q, dg);
+        const bool solid = cf.solid(kc);
         const double r = solid ? 0.0 : (-S.h2 * rhs[c] - q);
-        // inner diagonal from the FP32 densities, as the inner passes see it
-        const float dg32 = diag_cell<float>(rho32, c, nf, fc, fzm, fzp);
+        const float dg32 = diag_cell<float>(cf32, c, nf, fc, fzm, fzp);
         const float z32 = dg32 > 0.0f ? (float)((scale * r) / (double)dg32) : 0.0f;
         z[c] = z32;
         const double rz = (double)dg32 * (double)z32;
         a0 += r * r;
         a1 += rz * (double)z32;
         a2 += rz * rz;
-        vzm = vc; rzm = rc; fzm = fc;
-        vc = vzp; rc = rzp; fc = fzp;
+        vzm = vc; kzm = kc; fzm = fc;
+        vc = vzp; kc = kzp; fc = fzp;
     }
     acc[0] += a0;
     acc[1] += a1;
@@ -713,41 +773,70 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
 // update).  K0 and K1 serve disjoint sets of first-half actions, so a slot
 // is worked on by exactly one of them; keeping the rare actions out of K1
 // keeps its register footprint (and so its occupancy) that of pass A alone.
-template <int FAMILY, int WHICH>
+// K1 and K2 come in two coefficient modes (density, classes), each serving
+// only the slots of its mode; K0 serves both.
+template <int FAMILY, int WHICH, int MODE>
 __device__ __forceinline__ void run_body(int ph, const Slot &S,
                                          const SlotState &st, int64_t lt,
+                                         const double *tab64, const float *tab32,
                                          double (&acc)[3])
 {
+    const RhoCoef<double> r64{ gp(S.rho64) };
+    const ClsCoef<double> c64{ gp(S.cls), tab64 };
     if (FAMILY == PCG_PREC_FP64) {
         if (WHICH == 0) {
-            if (ph == K1_INIT64) body_init64(S, st, lt, acc);
-            else if (ph == K1_CHECK64) body_check64(S, st, lt, acc);
+            if (S.cls) {
+                if (ph == K1_INIT64) body_init64(S, st, lt, c64, acc);
+                else if (ph == K1_CHECK64) body_check64(S, st, lt, c64, acc);
+            } else {
+                if (ph == K1_INIT64) body_init64(S, st, lt, r64, acc);
+                else if (ph == K1_CHECK64) body_check64(S, st, lt, r64, acc);
+            }
         } else if (WHICH == 1) {
-            if (ph == K1_CG_A) body_passA<double>(S, st, lt, acc);
+            if (ph == K1_CG_A) {
+                if (MODE) body_passA<double>(S, st, lt, c64, acc);
+                else body_passA<double>(S, st, lt, r64, acc);
+            }
         } else {
-            if (ph == K2_CG_B) body_passB<double, double>(S, st, lt, acc);
-            else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
+            if (ph == K2_CG_B) {
+                if (MODE) body_passB<double, double>(S, st, lt, c64, acc);
+                else body_passB<double, double>(S, st, lt, r64, acc);
+            } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
         }
     } else {
+        const RhoCoef<float> r32{ gp(S.rho32) };
+        const ClsCoef<float> c32{ gp(S.cls), tab32 };
         if (WHICH == 0) {
-            if (ph == K1_IR_INIT) body_ir_init(S, st, lt, acc);
-            else if (ph == K1_IR_RESID) body_ir_resid(S, st, lt, acc);
+            if (S.cls) {
+                if (ph == K1_IR_INIT) body_ir_init(S, st, lt, c64, acc);
+                else if (ph == K1_IR_RESID) body_ir_resid(S, st, lt, c64, c32, acc);
+            } else {
+                if (ph == K1_IR_INIT) body_ir_init(S, st, lt, r64, acc);
+                else if (ph == K1_IR_RESID) body_ir_resid(S, st, lt, r64, r32, acc);
+            }
         } else if (WHICH == 1) {
-            if (ph == K1_IR_A) body_passA<float>(S, st, lt, acc);
+            if (ph == K1_IR_A) {
+                if (MODE) body_passA<float>(S, st, lt, c32, acc);
+                else body_passA<float>(S, st, lt, r32, acc);
+            }
         } else {
-            if (ph == K2_IR_B) body_passB<float, float>(S, st, lt, acc);
-            else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);
+            if (ph == K2_IR_B) {
+                if (MODE) body_passB<float, float>(S, st, lt, c32, acc);
+                else body_passB<float, float>(S, st, lt, r32, acc);
+            } else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);
             else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
         }
     }
 }
 
-__device__ __forceinline__ bool serves(int which, int ph)
+template <int WHICH, int MODE>
+__device__ __forceinline__ bool serves(const Slot &S, int ph)
 {
-    if (which == 0)
+    if (WHICH == 0)
         return ph == K1_INIT64 || ph == K1_CHECK64 || ph == K1_IR_INIT ||
                ph == K1_IR_RESID;
-    if (which == 1) return ph == K1_CG_A || ph == K1_IR_A;
+    if ((S.cls != nullptr) != (MODE != 0)) return false;
+    if (WHICH == 1) return ph == K1_CG_A || ph == K1_IR_A;
     return ph >= 11 && ph <= 19;
 }
 
@@ -784,18 +873,22 @@ __device__ __forceinline__ void arrive(const Slot &S, int ph, uint32_t run,
     __syncthreads();
 }
 
-// WHICH = 0, 1, 2: launch position within the iteration (see run_body).
-template <int FAMILY, int WHICH>
+// WHICH = 0, 1, 2: launch position within the iteration; MODE: coefficient
+// source of the slots served by K1/K2 (0 density, 1 classes).
+template <int FAMILY, int WHICH, int MODE>
 __global__ void __launch_bounds__(kBlock)
 k_iter(const BatchHeader *__restrict__ hdr, const Slot *__restrict__ slots)
 {
     __shared__ double lds[kMaxPartials * 4];
+    __shared__ double s_tab64[kClasses * kClasses];
+    __shared__ float s_tab32[kClasses * kClasses];
     __shared__ int s_last;
     const int64_t T = hdr->total_tiles;
     const int ns = hdr->nslots;
     const int G = (int)gridDim.x;
     const int g = xcd_major((int)blockIdx.x, G);
     int cur = -1, cur_ph = 0;
+    bool cur_served = false;
     uint32_t run = 0;
     for (int64_t t = g; t < T; t += G) {
         const int s = find_slot(slots, ns, t);
@@ -805,11 +898,21 @@ k_iter(const BatchHeader *__restrict__ hdr, const Slot *__restrict__ slots)
             cur = s;
             run = 0;
             cur_ph = S.st->phase;
+            cur_served = serves<WHICH, MODE>(S, cur_ph);
+            if (cur_served && S.cls) {   // class table of this slot into LDS
+                const bool need64 = FAMILY == PCG_PREC_FP64 || WHICH == 0;
+                const bool need32 = FAMILY == PCG_PREC_FP32_IR;
+                for (int i = threadIdx.x; i < kClasses * kClasses; i += kBlock) {
+                    if (need64) s_tab64[i] = gp(S.tab64)[i];
+                    if (need32) s_tab32[i] = gp(S.tab32)[i];
+                }
+                __syncthreads();
+            }
         }
+        if (!cur_served) continue;
         const int ph = cur_ph;
-        if (!serves(WHICH, ph)) continue;
         double acc[3] = { 0.0, 0.0, 0.0 };
-        run_body<FAMILY, WHICH>(ph, S, *S.st, t - S.tile_begin, acc);
+        run_body<FAMILY, WHICH, MODE>(ph, S, *S.st, t - S.tile_begin, s_tab64, s_tab32, acc);
         block_sum<3>(acc, lds);
         if (threadIdx.x == 0) {
             GLB double *dst = gp(S.partials) + kMaxPartials * (t - S.tile_begin);
@@ -841,6 +944,40 @@ k_encode(const double *__restrict__ rho, const uint8_t *__restrict__ mask,
     if (local_bad) atomicOr(bad, 1);
 }
 
+// One round of density classification.  Cells whose density equals `cand`
+// (bit pattern; densities are positive so bit order is numeric order) get
+// class `cls_id`; the smallest density above `cand` goes to *next.  Round 0
+// (cand = 0) also marks hull cells.
+__global__ void __launch_bounds__(256)
+k_classify(const double *__restrict__ r64, uint8_t *__restrict__ cls, int64_t n,
+           unsigned long long cand, int cls_id, unsigned long long *__restrict__ next)
+{
+    __shared__ unsigned long long wmin[4];
+    unsigned long long local = ~0ull;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const double v = r64[c];
+        if (isinf(v)) {
+            if (cand == 0ull) cls[c] = (uint8_t)kClsSolid;
+            continue;
+        }
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        if (b == cand) cls[c] = (uint8_t)cls_id;
+        else if (b > cand && b < local) local = b;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(local, off, 64);
+        local = o < local ? o : local;
+    }
+    if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = local;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = wmin[0];
+        for (int w = 1; w < 4; ++w) m = wmin[w] < m ? wmin[w] : m;
+        if (m != ~0ull) atomicMin(next, m);
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n2)
 {
@@ -853,22 +990,33 @@ k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n2)
 // host-callable launchers
 // ------------------------------------------------------------------------
 
-hipError_t launch_iter(int family, int which, int grid,
-                       const BatchHeader *hdr, const Slot *slots,
-                       hipStream_t s)
+hipError_t launch_iter(int family, int which, int mode, int grid,
+                       const BatchHeader *hdr, const Slot *slots, hipStream_t s)
 {
     const dim3 g(grid), b(kBlock);
-#define PCG_LAUNCH(F, W) hipLaunchKernelGGL((k_iter<F, W>), g, b, 0, s, hdr, slots)
+#define PCG_LAUNCH(F, W, M) hipLaunchKernelGGL((k_iter<F, W, M>), g, b, 0, s, hdr, slots)
     if (family == PCG_PREC_FP64) {
-        if (which == 0) PCG_LAUNCH(PCG_PREC_FP64, 0);
-        else if (which == 1) PCG_LAUNCH(PCG_PREC_FP64, 1);
-        else PCG_LAUNCH(PCG_PREC_FP64, 2);
+        if (which == 0) PCG_LAUNCH(PCG_PREC_FP64, 0, 0);
+        else if (which == 1) { if (mode) PCG_LAUNCH(PCG_PREC_FP64, 1, 1); else PCG_LAUNCH(PCG_PREC_FP64, 1, 0); }
+        else { if (mode) PCG_LAUNCH(PCG_PREC_FP64, 2, 1); else PCG_LAUNCH(PCG_PREC_FP64, 2, 0); }
     } else {
-        if (which == 0) PCG_LAUNCH(PCG_PREC_FP32_IR, 0);
-        else if (which == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 1);
-        else PCG_LAUNCH(PCG_PREC_FP32_IR, 2);
+        if (which == 0) PCG_LAUNCH(PCG_PREC_FP32_IR, 0, 0);
+        else if (which == 1) { if (mode) PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 1); else PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 0); }
+        else { if (mode) PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 1); else PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 0); }
     }
 #undef PCG_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n,
+                           unsigned long long cand, int cls_id,
+                           unsigned long long *next, hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)blocks), dim3(256), 0, s, r64, cls,
+                       n, cand, cls_id, next);
     return hipGetLastError();
 }
 

@@ -12,6 +12,14 @@ namespace pcgmi {
 constexpr int kBlock = 256;       // threads per workgroup = cells per plane tile
 constexpr int kMaxPartials = 3;   // reduction values per tile
 
+// Density classes: up to kMaxFluidClasses distinct fluid densities get a
+// one-byte class; kClsWallD stands for a Dirichlet wall (density 0 in the
+// face formula), kClsSolid for hull cells and Neumann walls (density +inf).
+constexpr int kClasses = 16;
+constexpr int kMaxFluidClasses = 14;
+constexpr int kClsWallD = 14;
+constexpr int kClsSolid = 15;
+
 // Next action of a slot.  Launches alternate K1, K2, K1, K2, ...; a K1
 // action is always followed by a K2 action and vice versa.
 enum Phase : int32_t {
@@ -82,6 +90,9 @@ struct Slot {
     float *d32;            // IR inner correction
     double *partials;      // kMaxPartials * ntiles
     SlotState *st;
+    const uint8_t *cls;    // density class per cell, or null (density path)
+    const double *tab64;   // kClasses^2 face coefficients 2/(rho_a + rho_b)
+    const float *tab32;    // the same in FP32 (FP32+IR only)
 };
 
 struct BatchHeader {

@@ -78,10 +78,9 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
         wb = statistics.median(w[k]) * 1024 * sw
         lines.append(f"{_short(k, 58):58s} {len(f[k]):4d} {fb:14.4e} {wb:14.4e} "
                      f"{fb / cells:10.2f} {wb / cells:10.2f}")
-        if "k_iter<0, 2>" in k:
-            lines.append(f"k2_hbm_bytes_per_launch = {fb + wb:.6e}")
-        if "k_iter<0, 1>" in k:
-            lines.append(f"k1_hbm_bytes_per_launch = {fb + wb:.6e}")
+        if "k_iter<" in k:
+            tag = k[k.index("k_iter<"):k.index(">", k.index("k_iter<")) + 1]
+            lines.append(f"bytes[{tag}] = {fb + wb:.6e}")
     return "\n".join(lines)
 
 

@@ -102,6 +102,12 @@ class Solver:
             L.check(code, "pcg_solve")
         return p, st.as_dict()
 
+    def density_classes(self) -> int:
+        """Fluid density classes in use (0: per-cell densities)."""
+        n = ctypes.c_int32()
+        L.check(self.lib.pcg_density_classes(self._ctx, ctypes.byref(n)), "classes")
+        return n.value
+
     def set_timing(self, on: bool = True):
         L.check(self.lib.pcg_set_timing(self._ctx, int(on)), "pcg_set_timing")
 

@@ -112,6 +112,8 @@ def test_null_handles(lib):
     assert lib.pcg_batch_create(ctypes.byref(b), ctypes.c_void_p(0x1000), 1 << 20, 0,
                                 None, None) == L.EINVAL
     assert lib.pcg_last_timing(None, None, None, None) == L.EINVAL
+    n = ctypes.c_int32()
+    assert lib.pcg_density_classes(None, ctypes.byref(n)) == L.EINVAL
     ms = ctypes.c_double()
     assert lib.pcg_copy_probe(None, None, 0, 1, None, ctypes.byref(ms)) == L.EINVAL
 

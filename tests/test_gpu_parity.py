@@ -279,3 +279,57 @@ def test_wedge_256_fp64_and_ir(orc, F, torch_dev):
     assert st32["status"] == 0 and rr32 <= 1e-8
     err = np.abs(p32 - p64).max() / np.abs(p64).max()
     assert err <= 1e-6, err
+
+
+# ---------------------------------------------------------------------------
+# coefficient paths: density classes (default) and per-cell densities
+# ---------------------------------------------------------------------------
+
+NO_CLASSES = 4
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "ir"])
+@pytest.mark.parametrize("shape,bc", [((37, 29, 23), TANK),
+                                      ((64, 48, 40), (1, 0, 0, 1, 0, 1))])
+def test_density_path_parity(orc, F, torch_dev, precision, shape, bc):
+    """The per-cell density path (classes switched off) meets the same bar,
+    and agrees with the class path to far below the tolerance."""
+    nx, ny, nz = shape
+    case = _two_phase(F, nx, ny, nz, bc=bc)
+    _say(f"case density path {shape} prec={precision}")
+    pd, std = gpu_solve(torch_dev, case, tol=1e-8, precision=precision,
+                        flags=NO_CLASSES)
+    _check_against_oracle(orc, case, pd, std, 1e-8)
+    pc, stc = gpu_solve(torch_dev, case, tol=1e-8, precision=precision)
+    _check_against_oracle(orc, case, pc, stc, 1e-8)
+    scale = np.abs(pc).max()
+    assert np.abs(pc - pd).max() <= 1e-6 * scale
+    if precision == 0:
+        assert abs(stc["iters"] - std["iters"]) <= 2
+
+
+def test_many_densities_use_density_path(orc, F, torch_dev):
+    """A mollified interface has more distinct densities than classes; the
+    solver falls back to per-cell densities and still meets the bar."""
+    case = F.make_two_phase(40, 36, 48, surface_seed=3, velocity_seed=4,
+                            wedge=F.Wedge(), mollify=2.5)
+    assert len(np.unique(case.rho)) > 20
+    for precision in (0, 1):
+        _say(f"case mollified prec={precision}")
+        p, st = gpu_solve(torch_dev, case, tol=1e-8, precision=precision)
+        _check_against_oracle(orc, case, p, st, 1e-8)
+
+
+def test_fourteen_classes_boundary(orc, F, torch_dev):
+    """Exactly 14 and 15 distinct fluid densities (the class limit and one
+    beyond) both solve correctly."""
+    base = _two_phase(F, 30, 26, 22)
+    for ndist in (14, 15):
+        case = _two_phase(F, 30, 26, 22)
+        levels = np.linspace(1.0, 900.0, ndist)
+        k = np.arange(case.nz) % ndist
+        case.rho = np.ascontiguousarray(np.broadcast_to(levels[k][:, None, None],
+                                                        case.shape))
+        _say(f"case {ndist} densities")
+        p, st = gpu_solve(torch_dev, case, tol=1e-8)
+        _check_against_oracle(orc, case, p, st, 1e-8)
