@@ -978,12 +978,13 @@ k_classify(const double *__restrict__ r64, uint8_t *__restrict__ cls, int64_t n,
     }
 }
 
+// Copy probe: one element per thread, one pass (the fastest plain copy
+// shape measured on this part).
 __global__ void __launch_bounds__(256)
-k_copy(const double2 *__restrict__ src, double2 *__restrict__ dst, int64_t n2)
+k_copy(const double *__restrict__ src, double *__restrict__ dst, int64_t n)
 {
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n2;
-         c += (int64_t)gridDim.x * blockDim.x)
-        dst[c] = src[c];
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) dst[c] = src[c];
 }
 
 // ------------------------------------------------------------------------
@@ -1033,12 +1034,10 @@ hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
 
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s)
 {
-    const int64_t n2 = (int64_t)(n / 2);
-    int64_t blocks = (n2 + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s,
-                       (const double2 *)src, (double2 *)dst, n2);
+    const int64_t blocks = ((int64_t)n + 255) / 256;
+    if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, src, dst,
+                       (int64_t)n);
     return hipGetLastError();
 }
 
