@@ -258,20 +258,25 @@ int pcg_batch_destroy(pcg_batch_t *b);
 /* ---- tile shapes ------------------------------------------------------- */
 
 /*
- * Table consulted when opts.tz (or opts.grid_blocks) is 0: a solve of n
+ * Tables consulted when opts.tz (or opts.grid_blocks) is 0: a solve of n
  * cells uses the first rule with n <= max_cells[i]: tile height tz[i] and,
  * for single-solve contexts, grid[i] workgroups (0 = library default).
  * Rules must be ordered by increasing max_cells, 1 <= n <= 64, tz >= 1.
- * One table per precision; contexts and batches created afterwards use it.
- * A solve's tile height depends only on its own cell count, so its result
+ * There is one table per precision for single-solve contexts
+ * (for_batches = 0) and one for batches (for_batches = 1), where many
+ * resident solves already fill the device and longer tiles cost less
+ * per-tile overhead.  Contexts and batches created afterwards use them.  A
+ * solve's tile height depends only on its own cell count, so its result
  * does not depend on the other solves of a batch.  Host-only; not
  * thread-safe against concurrent setup.  pcg_get_tile_rules copies at most
  * cap rules out and sets *n_out to the table length.
  */
-int pcg_set_tile_rules(int32_t precision, int32_t n, const int64_t *max_cells,
-                       const int32_t *tz, const int32_t *grid);
-int pcg_get_tile_rules(int32_t precision, int32_t cap, int64_t *max_cells,
-                       int32_t *tz, int32_t *grid, int32_t *n_out);
+int pcg_set_tile_rules(int32_t precision, int32_t for_batches, int32_t n,
+                       const int64_t *max_cells, const int32_t *tz,
+                       const int32_t *grid);
+int pcg_get_tile_rules(int32_t precision, int32_t for_batches, int32_t cap,
+                       int64_t *max_cells, int32_t *tz, int32_t *grid,
+                       int32_t *n_out);
 
 /* ---- measurement helpers ---------------------------------------------- */
 

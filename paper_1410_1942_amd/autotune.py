@@ -7,7 +7,12 @@ fastest per iteration.  The result is a JSON table keyed by GPU architecture:
 
     {"gfx950": {"fp64":    [[max_cells, tz, grid], ...],
                 "fp32_ir": [[max_cells, tz, grid], ...],
+                "fp64_batch": [...], "fp32_ir_batch": [...],
                 "measured": {...}}}
+
+Single-solve rules are tuned on one solve at a time; batch rules on a
+resident batch of several solves of the class size (their tiles share every
+launch, so longer tiles usually win).
 
 ``install()`` hands a table to the library (pcg_set_tile_rules); the binding
 calls it once per process with the table shipped in the package
@@ -34,31 +39,33 @@ TABLE = os.path.join(PKG, "tile_table.json")
 PREC_KEYS = {L.PREC_FP64: "fp64", L.PREC_FP32_IR: "fp32_ir"}
 
 CLASSES = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512]
+BATCH_CLASSES = [16, 24, 32, 48, 64, 96, 128, 192]
 TZS = [2, 4, 8, 16, 32, 64]
 GRIDS = [256, 512, 1024, 2048]
 
 _installed = False
 
 
-def get_rules(precision: int):
+def get_rules(precision: int, for_batches: bool = False):
     lib = L.load()
     cap = 64
     mc = (ctypes.c_int64 * cap)()
     tz = (ctypes.c_int32 * cap)()
     gr = (ctypes.c_int32 * cap)()
     n = ctypes.c_int32()
-    L.check(lib.pcg_get_tile_rules(int(precision), cap, mc, tz, gr, ctypes.byref(n)),
-            "pcg_get_tile_rules")
+    L.check(lib.pcg_get_tile_rules(int(precision), int(for_batches), cap, mc, tz, gr,
+                                   ctypes.byref(n)), "pcg_get_tile_rules")
     return [[int(mc[i]), int(tz[i]), int(gr[i])] for i in range(n.value)]
 
 
-def set_rules(precision: int, rules):
+def set_rules(precision: int, rules, for_batches: bool = False):
     lib = L.load()
     n = len(rules)
     mc = (ctypes.c_int64 * n)(*[int(r[0]) for r in rules])
     tz = (ctypes.c_int32 * n)(*[int(r[1]) for r in rules])
     gr = (ctypes.c_int32 * n)(*[int(r[2]) if len(r) > 2 else 0 for r in rules])
-    L.check(lib.pcg_set_tile_rules(int(precision), n, mc, tz, gr), "pcg_set_tile_rules")
+    L.check(lib.pcg_set_tile_rules(int(precision), int(for_batches), n, mc, tz, gr),
+            "pcg_set_tile_rules")
 
 
 def device_arch() -> str:
@@ -79,6 +86,8 @@ def install(path: str = None, arch: str = None) -> bool:
     for prec, key in PREC_KEYS.items():
         if key in table[arch]:
             set_rules(prec, table[arch][key])
+        if key + "_batch" in table[arch]:
+            set_rules(prec, table[arch][key + "_batch"], for_batches=True)
     return True
 
 
@@ -119,6 +128,71 @@ def _time_per_iter(dev_case, precision, tz, grid, target_ms=25.0):
     dt = (time.perf_counter() - t) / iters
     s.close()
     return dt * 1e3
+
+
+def _time_batch_per_iter(dev_case, precision, tz, copies, iters=64):
+    """Per-iteration time of `copies` resident copies of one case."""
+    import torch
+    from .solver import Batch
+    rho, mask, rhs, bc, h = dev_case
+    b = Batch(1 << 20, 1, precision=precision)
+    fp = b.footprint(tuple(rho.shape), h)
+    b.close()
+    ps = [torch.empty_like(rhs) for _ in range(copies)]
+
+    def run():
+        bb = Batch(copies * fp + (4 << 20), copies, precision=precision, tz=tz,
+                   check_every=16)
+        for p in ps:
+            code, _ = bb.admit(rho, mask, bc, h, rhs, p, tol=1e-30, maxit=iters,
+                               flags=L.SKIP_CONNECTIVITY_CHECK)
+            L.check(code, "admit")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        while bb.step(1):
+            pass
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        bb.close()
+        return dt
+
+    run()
+    return run() / iters * 1e3
+
+
+def tune_batches(classes=BATCH_CLASSES, precisions=(L.PREC_FP64, L.PREC_FP32_IR),
+                 tzs=TZS, log=print):
+    import torch
+    from . import fields as F
+    dev = torch.device("cuda:0")
+    best = {prec: [] for prec in precisions}
+    measured = {}
+    for n in classes:
+        case = F.make_two_phase(n, n, n, surface_seed=1, velocity_seed=2,
+                                wedge=F.Wedge(), keep_velocity=False)
+        dev_case = (torch.from_numpy(case.rho).to(dev),
+                    torch.from_numpy(case.mask).to(dev),
+                    torch.from_numpy(case.rhs).to(dev), case.bc, case.h)
+        copies = int(min(64, max(2, (4 << 20) // n ** 3)))
+        for prec in precisions:
+            key = PREC_KEYS[prec] + "_batch"
+            results = sorted((_time_batch_per_iter(dev_case, prec, tz, copies), tz)
+                             for tz in tzs if tz <= n)
+            ms, tz = results[0]
+            measured[f"{key}/{n}x{copies}"] = [[round(m, 5), t] for m, t in results]
+            log(f"{key} n={n} x{copies}: best tz={tz} {ms*1e3:.1f} us/iter "
+                f"({copies * n**3 / (ms * 1e-3) / 1e9:.2f} Gcell-iter/s)", flush=True)
+            best[prec].append((n ** 3, tz))
+        del dev_case
+        torch.cuda.empty_cache()
+    out = {}
+    for prec in precisions:
+        b = best[prec]
+        out[PREC_KEYS[prec] + "_batch"] = [
+            [int(math.sqrt(cells * b[i + 1][0])) if i + 1 < len(b) else 2 ** 62, tz, 0]
+            for i, (cells, tz) in enumerate(b)]
+    out["measured_batch"] = measured
+    return out
 
 
 def tune(classes=CLASSES, precisions=(L.PREC_FP64, L.PREC_FP32_IR), tzs=TZS,
@@ -167,14 +241,18 @@ def main(argv=None):
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--quick", action="store_true",
                     help="fewer classes and candidates")
+    ap.add_argument("--batches-only", action="store_true",
+                    help="tune only the batch tables, keep the single-solve ones")
     a = ap.parse_args(argv)
-    kw = {}
-    if a.quick:
-        kw = dict(classes=[24, 64, 160], tzs=[4, 16, 32], grids=[512, 1024])
     os.environ["PCGMI_TILE_TABLE"] = "none"
     arch = device_arch()
-    table = tune(**kw)
     full = json.load(open(a.out)) if os.path.exists(a.out) else {}
+    table = dict(full.get(arch, {}))
+    if not a.batches_only:
+        kw = dict(classes=[24, 64, 160], tzs=[4, 16, 32], grids=[512, 1024]) if a.quick else {}
+        table.update(tune(**kw))
+    kwb = dict(classes=[24, 64], tzs=[4, 16]) if a.quick else {}
+    table.update(tune_batches(**kwb))
     full[arch] = table
     with open(a.out, "w") as f:
         json.dump(full, f, indent=1)

@@ -24,9 +24,8 @@
 namespace pcgmi {
 hipError_t launch_iter(int family, int which, int mode, int grid,
                        const BatchHeader *hdr, const Slot *slots, hipStream_t s);
-hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n,
-                           unsigned long long cand, int cls_id,
-                           unsigned long long *next, hipStream_t s);
+hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n, int round,
+                           unsigned long long *words, hipStream_t s);
 hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
                          float *r32, int64_t n, int *bad, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
@@ -73,20 +72,31 @@ struct TileRule {
 };
 
 // Built-in table: the autotuner's choice on gfx950 (package tile_table.json).
-std::vector<TileRule> g_rules[2] = {
+std::vector<TileRule> g_rules[2] = {  // single solves: FP64, FP32+IR
     { { 7524, 2, 256 }, { 21283, 2, 256 }, { 60198, 4, 1024 }, { 170267, 4, 2048 }, { 481589, 8, 512 }, { 1362140, 16, 1024 }, { 3852714, 32, 256 }, { 10897121, 64, 512 }, { 30821713, 64, 512 }, { 87176971, 32, 1024 }, { INT64_MAX, 64, 1024 } },
     { { 7524, 2, 1024 }, { 21283, 2, 2048 }, { 60198, 4, 2048 }, { 170267, 4, 2048 }, { 481589, 8, 512 }, { 1362140, 16, 2048 }, { 3852714, 16, 512 }, { 10897121, 64, 2048 }, { 30821713, 32, 1024 }, { 87176971, 32, 1024 }, { INT64_MAX, 64, 1024 } },
 };
 
-const TileRule &rule_for(int64_t n, int prec)
+// Batches: longer tiles (the resident solves fill the device together).
+std::vector<TileRule> g_rules_batch[2] = {
+    { { 7524, 2, 0 }, { 21283, 8, 0 }, { 60198, 8, 0 }, { 170267, 16, 0 }, { 481589, 16, 0 }, { 1362140, 16, 0 }, { 3852714, 16, 0 }, { INT64_MAX, 64, 0 } },
+    { { 7524, 2, 0 }, { 21283, 8, 0 }, { 60198, 8, 0 }, { 170267, 16, 0 }, { 481589, 16, 0 }, { 1362140, 16, 0 }, { 3852714, 16, 0 }, { INT64_MAX, 64, 0 } },
+};
+
+std::vector<TileRule> &rules_of(int prec, bool batch)
 {
-    const auto &rules = g_rules[prec == PCG_PREC_FP32_IR ? 1 : 0];
+    return (batch ? g_rules_batch : g_rules)[prec == PCG_PREC_FP32_IR ? 1 : 0];
+}
+
+const TileRule &rule_for(int64_t n, int prec, bool batch)
+{
+    const auto &rules = rules_of(prec, batch);
     for (const auto &r : rules)
         if (n <= r.max_cells) return r;
     return rules.back();
 }
 
-int choose_tz(int64_t n, int prec) { return rule_for(n, prec).tz; }
+int choose_tz(int64_t n, int prec, bool batch) { return rule_for(n, prec, batch).tz; }
 
 // ---- first-fit allocator over [0, size) ----
 
@@ -145,12 +155,12 @@ struct Geometry {
     int64_t n, ntiles;
 };
 
-Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt)
+Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch)
 {
     Geometry G;
     G.nx = g.nx; G.ny = g.ny; G.nz = g.nz;
     G.n = (int64_t)g.nx * g.ny * g.nz;
-    G.tz = tz_opt > 0 ? tz_opt : choose_tz(G.n, prec);
+    G.tz = tz_opt > 0 ? tz_opt : choose_tz(G.n, prec, batch);
     if (G.tz > g.nz) G.tz = g.nz;
     const int64_t plane = (int64_t)g.nx * g.ny;
     G.plane_tiles = (int)((plane + kBlock - 1) / kBlock);
@@ -335,6 +345,7 @@ struct Engine {
     bool table_dirty = true;
     int64_t total_tiles = 0;
     int nrunning = 0;
+    bool is_batch = false;  // created by pcg_batch_create (batch tile table)
     int modes = 0;          // bit 0: a running slot uses densities, bit 1: classes
     int graph_modes = -1;   // modes the captured graph was built for
     // timing mode
@@ -395,7 +406,7 @@ struct Engine {
         HIP_TRY(hipHostMalloc((void **)&h_hdr, sizeof(BatchHeader), hipHostMallocDefault));
         HIP_TRY(hipHostMalloc((void **)&h_slots, sizeof(Slot) * nslots, hipHostMallocDefault));
         HIP_TRY(hipHostMalloc((void **)&h_states, sizeof(SlotState) * nslots, hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc((void **)&h_bad, 64, hipHostMallocDefault));  // flag + class search word
+        HIP_TRY(hipHostMalloc((void **)&h_bad, 256, hipHostMallocDefault));  // flag + class search words
         std::memset(h_states, 0, sizeof(SlotState) * nslots);
         for (int i = 0; i < nslots; ++i) h_states[i].phase = PH_IDLE;
         HIP_TRY(hipMemcpyAsync(d_states, h_states, sizeof(SlotState) * nslots,
@@ -408,9 +419,11 @@ struct Engine {
         return PCG_OK;
     }
 
+    bool batch_mode() const { return is_batch; }
+
     size_t footprint(const pcg_grid_t &g) const
     {
-        return slot_bytes(make_geometry(g, prec, tz_opt), prec);
+        return slot_bytes(make_geometry(g, prec, tz_opt, batch_mode()), prec);
     }
 
     // Reserve a slot and its memory, encode the density.  Does not start a solve.
@@ -427,7 +440,7 @@ struct Engine {
         for (int i = 0; i < max_slots; ++i)
             if (!slots[i].used) { id = i; break; }
         if (id < 0) return PCG_EBUSY;
-        const Geometry geo = make_geometry(*grid_, prec, tz_opt);
+        const Geometry geo = make_geometry(*grid_, prec, tz_opt, batch_mode());
         const size_t need = slot_bytes(geo, prec);
         size_t off = 0;
         if (!alloc.alloc(need, &off)) return max_slots == 1 ? PCG_ENOMEM : PCG_EBUSY;
@@ -469,15 +482,21 @@ struct Engine {
         S.tab64 = (double *)p;
         S.tab32 = (float *)(p + kClasses * kClasses * 8);
 
+        // encode and validate the densities, then (unless switched off) the
+        // chained class rounds; one host round trip reads both results
+        const bool want_classes = !(flags & PCG_NO_DENSITY_CLASSES);
         *h_bad = 0;
         hipError_t e = hipMemcpyAsync(d_bad, h_bad, sizeof(int), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) e = launch_encode(rho, mask, S.rho64, S.rho32, geo.n, d_bad, stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(h_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess && want_classes) e = classify_launch(S);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h_bad, d_bad, want_classes ? 8 + 8 * kRounds : sizeof(int),
+                               hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) { alloc.release(off, need); return hip_fail(e, "encode"); }
         if (*h_bad) { alloc.release(off, need); return PCG_EDOMAIN; }
-        if (!(flags & PCG_NO_DENSITY_CLASSES)) {
-            st = classify(S);
+        if (want_classes) {
+            st = classify_finish(S);
             if (st) { alloc.release(off, need); return st; }
         }
         S.used = true;
@@ -486,31 +505,37 @@ struct Engine {
     }
 
     // Code the densities as classes when there are at most kMaxFluidClasses
-    // distinct fluid values: one device pass per class finds the next
-    // distinct value and labels the cells equal to the current one; the face
-    // coefficient table is computed here in FP64 (and FP32) exactly as
-    // 2/(rho_a + rho_b).
-    int classify(SlotHost &S)
+    // distinct fluid values.  kMaxFluidClasses + 2 chained device rounds (no
+    // host round trip between them) find the distinct values in increasing
+    // order and label the cells; one copy brings the values back, and the
+    // face coefficient table is computed here exactly as 2/(rho_a + rho_b)
+    // in FP64 (and FP32).
+    static constexpr int kRounds = kMaxFluidClasses + 2;
+
+    hipError_t classify_launch(SlotHost &S)
     {
-        unsigned long long *d_next = (unsigned long long *)(d_bad + 2);
-        unsigned long long *h_next = (unsigned long long *)(h_bad + 2);
+        unsigned long long *d_words = (unsigned long long *)(d_bad + 2);
+        unsigned long long *h_words = (unsigned long long *)(h_bad + 2);
+        for (int r = 0; r < kRounds; ++r) h_words[r] = ~0ull;
+        hipError_t e = hipMemcpyAsync(d_words, h_words, 8 * kRounds, hipMemcpyHostToDevice, stream);
+        for (int r = 0; r < kRounds && e == hipSuccess; ++r)
+            e = launch_classify(S.rho64, S.cls, S.geo.n, r, d_words, stream);
+        return e;
+    }
+
+    // After classify_launch and a synchronize: read the distinct values and
+    // build the coefficient tables.
+    int classify_finish(SlotHost &S)
+    {
+        const unsigned long long *h_words = (const unsigned long long *)(h_bad + 2);
         std::vector<double> pal;
-        unsigned long long cand = 0;
-        for (int r = 0;; ++r) {
-            if (r - 1 >= kMaxFluidClasses) return PCG_OK;   // too many: densities
-            *h_next = ~0ull;
-            HIP_TRY(hipMemcpyAsync(d_next, h_next, 8, hipMemcpyHostToDevice, stream));
-            HIP_TRY(launch_classify(S.rho64, S.cls, S.geo.n, cand, r - 1, d_next, stream));
-            HIP_TRY(hipMemcpyAsync(h_next, d_next, 8, hipMemcpyDeviceToHost, stream));
-            HIP_TRY(hipStreamSynchronize(stream));
-            if (r > 0) {
-                double v;
-                std::memcpy(&v, &cand, 8);
-                pal.push_back(v);
-            }
-            if (*h_next == ~0ull) break;
-            cand = *h_next;
+        for (int r = 0; r < kRounds && h_words[r] != ~0ull; ++r) {
+            double v;
+            std::memcpy(&v, &h_words[r], 8);
+            pal.push_back(v);
         }
+        // a value in words[kMaxFluidClasses] means a 15th distinct density
+        if ((int)pal.size() > kMaxFluidClasses) return PCG_OK;
         double rho[kClasses];
         for (int a = 0; a < kClasses; ++a) rho[a] = 0.0;
         for (size_t a = 0; a < pal.size(); ++a) rho[a] = pal[a];
@@ -626,7 +651,8 @@ struct Engine {
             int64_t t = 0, n = 0;
             for (auto &S : slots)
                 if (S.used) { t = std::max<int64_t>(t, S.geo.ntiles); n = S.geo.n; }
-            if (grid_opt <= 0 && n > 0 && rule_for(n, prec).grid > 0) g = rule_for(n, prec).grid;
+            if (grid_opt <= 0 && n > 0 && rule_for(n, prec, false).grid > 0)
+                g = rule_for(n, prec, false).grid;
             if (t > 0 && t < g) g = (int)t;
         }
         g = std::max(8, (g + 7) / 8 * 8);
@@ -794,7 +820,7 @@ int pcg_workspace_bytes(const pcg_grid_t *grid, const pcg_opts_t *opts,
     st = check_opts(opts);
     if (st) return st;
     const int prec = opts ? opts->precision : PCG_PREC_FP64;
-    const Geometry G = make_geometry(*grid, prec, opts ? opts->tz : 0);
+    const Geometry G = make_geometry(*grid, prec, opts ? opts->tz : 0, false);
     *out_bytes = head_bytes(1) + slot_bytes(G, prec);
     return PCG_OK;
 }
@@ -883,10 +909,11 @@ int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
                                                                         : PCG_ESINGULAR;
 }
 
-int pcg_set_tile_rules(int32_t precision, int32_t n, const int64_t *max_cells,
-                       const int32_t *tz, const int32_t *grid)
+int pcg_set_tile_rules(int32_t precision, int32_t for_batches, int32_t n,
+                       const int64_t *max_cells, const int32_t *tz, const int32_t *grid)
 {
     if (precision != PCG_PREC_FP64 && precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
+    if (for_batches != 0 && for_batches != 1) return PCG_EINVAL;
     if (n < 1 || n > 64 || !max_cells || !tz) return PCG_EINVAL;
     std::vector<TileRule> rules;
     for (int i = 0; i < n; ++i) {
@@ -897,16 +924,17 @@ int pcg_set_tile_rules(int32_t precision, int32_t n, const int64_t *max_cells,
         rules.push_back({ max_cells[i], tz[i], g });
     }
     rules.back().max_cells = INT64_MAX;   // the last rule covers every size
-    g_rules[precision == PCG_PREC_FP32_IR ? 1 : 0] = rules;
+    rules_of(precision, for_batches != 0) = rules;
     return PCG_OK;
 }
 
-int pcg_get_tile_rules(int32_t precision, int32_t cap, int64_t *max_cells,
-                       int32_t *tz, int32_t *grid, int32_t *n_out)
+int pcg_get_tile_rules(int32_t precision, int32_t for_batches, int32_t cap,
+                       int64_t *max_cells, int32_t *tz, int32_t *grid, int32_t *n_out)
 {
     if (precision != PCG_PREC_FP64 && precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
+    if (for_batches != 0 && for_batches != 1) return PCG_EINVAL;
     if (!n_out || cap < 0) return PCG_EINVAL;
-    const auto &rules = g_rules[precision == PCG_PREC_FP32_IR ? 1 : 0];
+    const auto &rules = rules_of(precision, for_batches != 0);
     *n_out = (int32_t)rules.size();
     for (int i = 0; i < cap && i < (int)rules.size(); ++i) {
         if (max_cells) max_cells[i] = rules[i].max_cells;
@@ -974,6 +1002,7 @@ int pcg_batch_create(pcg_batch_t **out, void *arena, size_t arena_bytes,
     if (max_slots < 1) return PCG_EINVAL;
     pcg_batch *b = new (std::nothrow) pcg_batch();
     if (!b) return PCG_ENOMEM;
+    b->eng.is_batch = true;
     int st = b->eng.init(arena, arena_bytes, max_slots, opts, hip_stream);
     if (st) { delete b; return st; }
     *out = b;

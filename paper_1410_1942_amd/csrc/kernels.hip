@@ -944,25 +944,29 @@ k_encode(const double *__restrict__ rho, const uint8_t *__restrict__ mask,
     if (local_bad) atomicOr(bad, 1);
 }
 
-// One round of density classification.  Cells whose density equals `cand`
-// (bit pattern; densities are positive so bit order is numeric order) get
-// class `cls_id`; the smallest density above `cand` goes to *next.  Round 0
-// (cand = 0) also marks hull cells.
+// One round of density classification, chained on the device: round r reads
+// the candidate found by round r-1 (words[r-1]; round 0 uses 0), labels the
+// cells whose density equals it with class r-1, and leaves the smallest
+// density above it in words[r] (all ones when none is left, after which
+// later rounds do nothing).  Densities are positive, so the order of their
+// bit patterns is numeric order.  Round 0 also marks hull cells.
 __global__ void __launch_bounds__(256)
 k_classify(const double *__restrict__ r64, uint8_t *__restrict__ cls, int64_t n,
-           unsigned long long cand, int cls_id, unsigned long long *__restrict__ next)
+           int round, unsigned long long *__restrict__ words)
 {
     __shared__ unsigned long long wmin[4];
+    const unsigned long long cand = round > 0 ? words[round - 1] : 0ull;
+    if (cand == ~0ull) return;
     unsigned long long local = ~0ull;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
          c += (int64_t)gridDim.x * blockDim.x) {
         const double v = r64[c];
         if (isinf(v)) {
-            if (cand == 0ull) cls[c] = (uint8_t)kClsSolid;
+            if (round == 0) cls[c] = (uint8_t)kClsSolid;
             continue;
         }
         const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-        if (b == cand) cls[c] = (uint8_t)cls_id;
+        if (b == cand) cls[c] = (uint8_t)(round - 1);
         else if (b > cand && b < local) local = b;
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -974,7 +978,7 @@ k_classify(const double *__restrict__ r64, uint8_t *__restrict__ cls, int64_t n,
     if (threadIdx.x == 0) {
         unsigned long long m = wmin[0];
         for (int w = 1; w < 4; ++w) m = wmin[w] < m ? wmin[w] : m;
-        if (m != ~0ull) atomicMin(next, m);
+        if (m != ~0ull) atomicMin(&words[round], m);
     }
 }
 
@@ -1009,15 +1013,14 @@ hipError_t launch_iter(int family, int which, int mode, int grid,
     return hipGetLastError();
 }
 
-hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n,
-                           unsigned long long cand, int cls_id,
-                           unsigned long long *next, hipStream_t s)
+hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n, int round,
+                           unsigned long long *words, hipStream_t s)
 {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_classify, dim3((unsigned)blocks), dim3(256), 0, s, r64, cls,
-                       n, cand, cls_id, next);
+                       n, round, words);
     return hipGetLastError();
 }
 

@@ -181,11 +181,18 @@ def test_tile_rules_roundtrip(lib):
         n = ctypes.c_int32()
         bad = (ctypes.c_int64 * 2)(10, 5)          # not increasing
         tz = (ctypes.c_int32 * 2)(4, 8)
-        assert lib.pcg_set_tile_rules(0, 2, bad, tz, None) == L.EINVAL
-        assert lib.pcg_set_tile_rules(3, 2, bad, tz, None) == L.EINVAL
+        assert lib.pcg_set_tile_rules(0, 0, 2, bad, tz, None) == L.EINVAL
+        assert lib.pcg_set_tile_rules(3, 0, 2, bad, tz, None) == L.EINVAL
         zero = (ctypes.c_int32 * 2)(0, 8)
         ok_mc = (ctypes.c_int64 * 2)(5, 10)
-        assert lib.pcg_set_tile_rules(0, 2, ok_mc, zero, None) == L.EINVAL
+        assert lib.pcg_set_tile_rules(0, 0, 2, ok_mc, zero, None) == L.EINVAL
+        assert lib.pcg_set_tile_rules(0, 2, 2, ok_mc, tz, None) == L.EINVAL
+        # the batch table is separate from the single-solve one
+        batch_saved = autotune.get_rules(0, for_batches=True)
+        autotune.set_rules(0, [[10**9, 16, 0]], for_batches=True)
+        assert autotune.get_rules(0, for_batches=True)[0][1] == 16
+        assert [r[1:] for r in autotune.get_rules(0)] == [[4, 256], [8, 0], [64, 512]]
+        autotune.set_rules(0, batch_saved, for_batches=True)
         # workspace: partial sums scale with the number of tiles (tz = 64 -> fewer)
         o = L.Opts()
         w64 = ctypes.c_size_t()
