@@ -194,6 +194,28 @@ int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
  */
 int pcg_density_classes(const pcg_ctx_t *ctx, int32_t *nclasses);
 
+/*
+ * Velocity projection (Section 2.1: u* = u - dt (1/rho) grad P on the MAC
+ * faces), in place, with the context's face coefficients, walls and hull:
+ *   u_f -= dt * beta_f * (p_hi - p_lo) / h,
+ * Dirichlet walls with the mirrored ghost -p_c, Neumann and hull faces
+ * untouched.  With Sigma = (D u)/dt and p solved to tol, the projected field
+ * has ||D u_new|| = dt ||Sigma - L p|| <= tol dt ||Sigma||.
+ *   p  device f64[n] (pressure from pcg_solve)
+ *   u  device f64[nz][ny][nx+1], v f64[nz][ny+1][nx], w f64[nz+1][ny][nx]
+ * Stream-ordered on the context's stream; returns after the launch.
+ */
+int pcg_project(pcg_ctx_t *ctx, const double *p, double dt, double *u, double *v,
+                double *w);
+
+/*
+ * Discrete divergence of MAC face velocities over the fluid cells (the form
+ * of Eq. mass used by the projection): out[0] = ||D u||_2, out[1] =
+ * max |D u|.  out is HOST double[2].  Blocks until done.
+ */
+int pcg_divergence(pcg_ctx_t *ctx, const double *u, const double *v,
+                   const double *w, double *out);
+
 /* Release the context (not the workspace).  NULL is accepted. */
 int pcg_destroy(pcg_ctx_t *ctx);
 

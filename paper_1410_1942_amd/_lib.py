@@ -26,7 +26,7 @@ EXPORTED = [
     "pcg_batch_poll", "pcg_batch_release", "pcg_batch_destroy",
     "pcg_set_timing", "pcg_last_timing", "pcg_copy_probe",
     "pcg_check_connectivity", "pcg_set_tile_rules", "pcg_get_tile_rules",
-    "pcg_density_classes",
+    "pcg_density_classes", "pcg_project", "pcg_divergence",
 ]
 
 
@@ -102,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.pcg_check_connectivity.argtypes = [vp, P(Grid), P(BC)]
     lib.pcg_set_tile_rules.argtypes = [i32, i32, vp, vp, vp]
     lib.pcg_density_classes.argtypes = [vp, P(i32)]
+    lib.pcg_project.argtypes = [vp, vp, dbl, vp, vp, vp]
+    lib.pcg_divergence.argtypes = [vp, vp, vp, vp, P(dbl)]
     lib.pcg_get_tile_rules.argtypes = [i32, i32, vp, vp, vp, P(i32)]
     for name in EXPORTED:
         if name not in ("pcg_strerror", "pcg_last_hip_error"):

@@ -29,6 +29,11 @@ hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n, int round
 hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
                          float *r32, int64_t n, int *bad, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
+hipError_t launch_project(const Slot *slot, const double *p, double s, double *u,
+                          double *v, double *w, int blocks, hipStream_t st);
+hipError_t launch_divnorm(const Slot *slot, double inv_h, const double *u,
+                          const double *v, const double *w, double *part, int blocks,
+                          hipStream_t st);
 }  // namespace pcgmi
 
 using namespace pcgmi;
@@ -420,6 +425,28 @@ struct Engine {
     }
 
     bool batch_mode() const { return is_batch; }
+
+    // Device description of a prepared slot for the projection kernels:
+    // written into the head's spare slot entry when no solve runs.
+    int slot_view(int id, Slot **d_slot)
+    {
+        SlotHost &S = slots[id];
+        if (!S.used) return PCG_EINVAL;
+        Slot &d = h_slots[0];
+        std::memset(&d, 0, sizeof(Slot));
+        d.nx = S.geo.nx; d.ny = S.geo.ny; d.nz = S.geo.nz;
+        d.bcmask = S.bcmask;
+        d.h2 = S.h2;
+        d.rho64 = S.rho64;
+        d.cls = S.classes ? S.cls : nullptr;
+        d.tab64 = S.tab64;
+        d.ntiles = S.geo.ntiles;
+        HIP_TRY(hipMemcpyAsync(d_slots, h_slots, sizeof(Slot), hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
+        table_dirty = true;      // the solve path rebuilds the table before use
+        *d_slot = d_slots;
+        return PCG_OK;
+    }
 
     size_t footprint(const pcg_grid_t &g) const
     {
@@ -941,6 +968,49 @@ int pcg_get_tile_rules(int32_t precision, int32_t for_batches, int32_t cap,
         if (tz) tz[i] = rules[i].tz;
         if (grid) grid[i] = rules[i].grid;
     }
+    return PCG_OK;
+}
+
+int pcg_project(pcg_ctx_t *c, const double *p, double dt, double *u, double *v,
+                double *w)
+{
+    if (!c || !p || !u || !v || !w || !std::isfinite(dt)) return PCG_EINVAL;
+    Slot *ds = nullptr;
+    int st = c->eng.slot_view(c->slot, &ds);
+    if (st) return st;
+    const SlotHost &S = c->eng.slots[c->slot];
+    const double h = std::sqrt(S.h2);
+    const int64_t blocks = std::min<int64_t>((S.geo.n + 255) / 256, 4096);
+    HIP_TRY(launch_project(ds, p, dt / h, u, v, w, (int)std::max<int64_t>(1, blocks),
+                           c->eng.stream));
+    return PCG_OK;
+}
+
+int pcg_divergence(pcg_ctx_t *c, const double *u, const double *v, const double *w,
+                   double *out)
+{
+    if (!c || !u || !v || !w || !out) return PCG_EINVAL;
+    Slot *ds = nullptr;
+    int st = c->eng.slot_view(c->slot, &ds);
+    if (st) return st;
+    const SlotHost &S = c->eng.slots[c->slot];
+    // one partial pair per workgroup, in the slot's partial-sum buffer
+    const int64_t blocks = std::max<int64_t>(
+        1, std::min<int64_t>({ (S.geo.n + 255) / 256, 2048,
+                               (int64_t)(kMaxPartials * S.geo.ntiles / 2) }));
+    HIP_TRY(launch_divnorm(ds, 1.0 / std::sqrt(S.h2), u, v, w, S.partials, (int)blocks,
+                           c->eng.stream));
+    std::vector<double> part(2 * blocks);
+    HIP_TRY(hipMemcpyAsync(part.data(), S.partials, part.size() * 8, hipMemcpyDeviceToHost,
+                           c->eng.stream));
+    HIP_TRY(hipStreamSynchronize(c->eng.stream));
+    double ss = 0.0, mx = 0.0;
+    for (int64_t b = 0; b < blocks; ++b) {
+        ss += part[2 * b];
+        mx = std::max(mx, part[2 * b + 1]);
+    }
+    out[0] = std::sqrt(ss);
+    out[1] = mx;
     return PCG_OK;
 }
 

@@ -982,6 +982,101 @@ k_classify(const double *__restrict__ r64, uint8_t *__restrict__ cls, int64_t n,
     }
 }
 
+// ------------------------------------------------------------------------
+// velocity projection and divergence (the step after each pressure solve)
+// ------------------------------------------------------------------------
+
+// u_f -= dt beta_f (p_hi - p_lo) / h on every MAC face, in place, with the
+// solve's face coefficients: interior faces between cells c-1 and c are
+// updated by cell c; wall faces use the mirrored ghost -p_c (Dirichlet:
+// gradient 2 p_c / h, coefficient 1/rho_c, i.e. beta(c, wall) p_c with
+// beta = 2/rho_c) or stay (Neumann, hull: beta = 0).  Face arrays are
+// u[nz][ny][nx+1], v[nz][ny+1][nx], w[nz+1][ny][nx].
+template <class C>
+__device__ void project_cells(const Slot &S, const C &cf, const double *__restrict__ p,
+                              double s, double *__restrict__ u, double *__restrict__ v,
+                              double *__restrict__ w)
+{
+    using K = typename C::Key;
+    const int nx = S.nx, ny = S.ny, nz = S.nz;
+    const int64_t P = (int64_t)nx * ny, n = P * nz;
+    const int bm = S.bcmask;
+    const GLB double *__restrict__ pg = gp(p);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(c % nx);
+        const int j = (int)((c / nx) % ny);
+        const int k = (int)(c / P);
+        const K kc = cf.load(c);
+        const double pc = pg[c];
+        const int64_t fu = ((int64_t)k * ny + j) * (nx + 1) + i;
+        const int64_t fv = ((int64_t)k * (ny + 1) + j) * nx + i;
+        const int64_t fw = c;
+        if (i > 0) u[fu] -= s * cf.beta(cf.load(c - 1), kc) * (pc - pg[c - 1]);
+        else u[fu] -= s * cf.beta(kc, (bm & 1) ? cf.dirichlet() : cf.neumann()) * pc;
+        if (i == nx - 1) u[fu + 1] += s * cf.beta(kc, (bm & 2) ? cf.dirichlet() : cf.neumann()) * pc;
+        if (j > 0) v[fv] -= s * cf.beta(cf.load(c - nx), kc) * (pc - pg[c - nx]);
+        else v[fv] -= s * cf.beta(kc, (bm & 4) ? cf.dirichlet() : cf.neumann()) * pc;
+        if (j == ny - 1) v[fv + nx] += s * cf.beta(kc, (bm & 8) ? cf.dirichlet() : cf.neumann()) * pc;
+        if (k > 0) w[fw] -= s * cf.beta(cf.load(c - P), kc) * (pc - pg[c - P]);
+        else w[fw] -= s * cf.beta(kc, (bm & 16) ? cf.dirichlet() : cf.neumann()) * pc;
+        if (k == nz - 1) w[fw + P] += s * cf.beta(kc, (bm & 32) ? cf.dirichlet() : cf.neumann()) * pc;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_project(const Slot *__restrict__ slot, const double *__restrict__ p, double s,
+          double *__restrict__ u, double *__restrict__ v, double *__restrict__ w)
+{
+    __shared__ double s_tab64[kClasses * kClasses];
+    const Slot &S = *slot;
+    if (S.cls) {
+        for (int i = threadIdx.x; i < kClasses * kClasses; i += blockDim.x)
+            s_tab64[i] = gp(S.tab64)[i];
+        __syncthreads();
+        project_cells(S, ClsCoef<double>{ gp(S.cls), s_tab64 }, p, s, u, v, w);
+    } else {
+        project_cells(S, RhoCoef<double>{ gp(S.rho64) }, p, s, u, v, w);
+    }
+}
+
+// (D u)_c = (u_{i+1/2} - u_{i-1/2} + v_{j+1/2} - v_{j-1/2} + w_{k+1/2} -
+// w_{k-1/2}) / h over fluid cells: per-workgroup sum of squares and maximum
+// magnitude, combined on the host in workgroup order.
+__global__ void __launch_bounds__(256)
+k_divnorm(const Slot *__restrict__ slot, double inv_h, const double *__restrict__ u,
+          const double *__restrict__ v, const double *__restrict__ w,
+          double *__restrict__ part)
+{
+    __shared__ double lds[8];
+    const Slot &S = *slot;
+    const int nx = S.nx, ny = S.ny, nz = S.nz;
+    const int64_t P = (int64_t)nx * ny, n = P * nz;
+    const RhoCoef<double> cf{ gp(S.rho64) };
+    double ss = 0.0, mx = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        if (cf.solid(cf.load(c))) continue;
+        const int i = (int)(c % nx);
+        const int j = (int)((c / nx) % ny);
+        const int k = (int)(c / P);
+        const int64_t fu = ((int64_t)k * ny + j) * (nx + 1) + i;
+        const int64_t fv = ((int64_t)k * (ny + 1) + j) * nx + i;
+        const double d = ((u[fu + 1] - u[fu]) + (v[fv + nx] - v[fv]) + (w[c + P] - w[c])) * inv_h;
+        ss += d * d;
+        mx = fmax(mx, fabs(d));
+    }
+    double a[1] = { ss };
+    ss = wave_sum(a[0]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) { lds[threadIdx.x >> 6] = ss; lds[4 + (threadIdx.x >> 6)] = mx; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+        part[2 * blockIdx.x + 1] = fmax(fmax(lds[4], lds[5]), fmax(lds[6], lds[7]));
+    }
+}
+
 // Copy probe: one element per thread, one pass (the fastest plain copy
 // shape measured on this part).
 __global__ void __launch_bounds__(256)
@@ -1032,6 +1127,22 @@ hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_encode, dim3((unsigned)blocks), dim3(256), 0, s, rho,
                        mask, r64, r32, n, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const Slot *slot, const double *p, double s, double *u,
+                          double *v, double *w, int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, slot, p, s, u, v, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_divnorm(const Slot *slot, double inv_h, const double *u,
+                          const double *v, const double *w, double *part, int blocks,
+                          hipStream_t st)
+{
+    hipLaunchKernelGGL(k_divnorm, dim3(blocks), dim3(256), 0, st, slot, inv_h, u, v, w,
+                       part);
     return hipGetLastError();
 }
 

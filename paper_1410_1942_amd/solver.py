@@ -108,6 +108,26 @@ class Solver:
         L.check(self.lib.pcg_density_classes(self._ctx, ctypes.byref(n)), "classes")
         return n.value
 
+    def project(self, p: torch.Tensor, dt: float, u: torch.Tensor,
+                v: torch.Tensor, w: torch.Tensor):
+        """u -= dt (1/rho) grad p on the MAC faces, in place (pcg_project)."""
+        nz, ny, nx = self.shape
+        for t, shp in ((u, (nz, ny, nx + 1)), (v, (nz, ny + 1, nx)), (w, (nz + 1, ny, nx))):
+            _require_device(t)
+            if t.dtype != torch.float64 or tuple(t.shape) != shp:
+                raise ValueError("face arrays must be float64 u[nz,ny,nx+1], "
+                                 "v[nz,ny+1,nx], w[nz+1,ny,nx]")
+        _require_device(p)
+        L.check(self.lib.pcg_project(self._ctx, _ptr(p), float(dt), _ptr(u), _ptr(v),
+                                     _ptr(w)), "pcg_project")
+
+    def divergence(self, u, v, w):
+        """(||D u||_2, max |D u|) over fluid cells (pcg_divergence)."""
+        out = (ctypes.c_double * 2)()
+        L.check(self.lib.pcg_divergence(self._ctx, _ptr(u), _ptr(v), _ptr(w), out),
+                "pcg_divergence")
+        return out[0], out[1]
+
     def set_timing(self, on: bool = True):
         L.check(self.lib.pcg_set_timing(self._ctx, int(on)), "pcg_set_timing")
 
