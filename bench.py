@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--no-project", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batch-n", type=int, default=64)
@@ -96,7 +97,7 @@ def main():
     n = args.n
     log(f"generating wedge{n} input")
     t = time.time()
-    case = F.config_wedge(n, keep_velocity=False)
+    case = F.config_wedge(n, keep_velocity=not args.no_project and not args.profile_iters)
     log(f"  {time.time() - t:.1f} s")
     rho = torch.from_numpy(case.rho).to(dev)
     mask = torch.from_numpy(case.mask).to(dev)
@@ -271,12 +272,50 @@ def main():
                 case.rho, case.mask, case.bc, case.h, case.rhs, pir.cpu().numpy())
         log(f"  {cpu_val:.4f} Gcell-iter/s on {oracle.threads()} threads")
 
+    if not args.no_project:
+        out["projection"] = bench_project(case, rho, mask, p64, dev)
+        case.u = case.v = case.w = None
     if not args.no_batch:
         out["batch"] = bench_batch(args.batch_n)
     if not args.no_serve:
         out["served"] = bench_serve(args.serve_n)
 
     print(json.dumps(out), flush=True)
+
+
+def bench_project(case, rho, mask, p64, dev):
+    """The projection after the solve: u -= dt (1/rho) grad p on the faces
+    of the same 512^3 field, then the divergence norm of the result."""
+    import torch
+    from paper_1410_1942_amd.solver import Solver
+    log("projection")
+    s = Solver(rho, mask, case.bc, case.h)
+    u0 = torch.from_numpy(case.u).to(dev)
+    v0 = torch.from_numpy(case.v).to(dev)
+    w0 = torch.from_numpy(case.w).to(dev)
+    u, v, w = u0.clone(), v0.clone(), w0.clone()
+    d0 = s.divergence(u, v, w)
+    s.project(p64, case.dt, u, v, w)            # warm
+    u.copy_(u0); v.copy_(v0); w.copy_(w0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    s.project(p64, case.dt, u, v, w)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    t = time.perf_counter()
+    d1 = s.divergence(u, v, w)
+    td = time.perf_counter() - t
+    s.close()
+    cells = case.ncells
+    # algorithmic bytes: project reads p, the class byte and the three face
+    # arrays and writes them back; divergence reads the faces and the density
+    bp, bd = (8 + 1 + 24 + 24) * cells, (24 + 8) * cells
+    log(f"  project {tp*1e3:.2f} ms ({bp/tp/1e9:.0f} GB/s), divergence {td*1e3:.2f} ms, "
+        f"ratio {d1[0]/d0[0]:.3e}")
+    return {"project_ms": round(tp * 1e3, 3), "project_GBps": round(bp / tp / 1e9, 1),
+            "divergence_ms": round(td * 1e3, 3), "divergence_GBps": round(bd / td / 1e9, 1),
+            "div_l2_before": d0[0], "div_l2_after": d1[0],
+            "div_ratio": d1[0] / d0[0], "div_max_after": d1[1]}
 
 
 def bench_batch(nsolves):
