@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-project", action="store_true")
+    ap.add_argument("--no-rk2", action="store_true")
+    ap.add_argument("--rk2-shift", type=float, default=0.025,
+                    help="surface phase advance (rad) that gives rho(phi*); "
+                         "0.025 moves the 512^3 surface by at most about one cell")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batch-n", type=int, default=64)
@@ -274,6 +278,8 @@ def main():
 
     if not args.no_project:
         out["projection"] = bench_project(case, rho, mask, p64, dev)
+        if not args.no_rk2:
+            out["rk2_pair"] = bench_rk2(case, rho, mask, dev, args.tol, args.rk2_shift)
         case.u = case.v = case.w = None
     if not args.no_batch:
         out["batch"] = bench_batch(args.batch_n)
@@ -316,6 +322,51 @@ def bench_project(case, rho, mask, p64, dev):
             "divergence_ms": round(td * 1e3, 3), "divergence_GBps": round(bd / td / 1e9, 1),
             "div_l2_before": d0[0], "div_l2_after": d1[0],
             "div_ratio": d1[0] / d0[0], "div_max_after": d1[1]}
+
+
+def bench_rk2(case, rho, mask, dev, tol, shift):
+    """Pressure half of one two-stage Runge-Kutta step on the same field:
+    P* from rho(phi^k), u*, coefficients rebuilt for rho(phi*) (the surface
+    modes advanced by `shift` rad), P^{k+1} warm-started from P*, u^{k+1}.
+    The second stage is repeated cold to show what the warm start saves."""
+    import torch
+    from paper_1410_1942_amd import fields as F
+    from paper_1410_1942_amd import rk2
+    from paper_1410_1942_amd.solver import Solver
+    log("rk2 stage pair")
+    rho_s = torch.from_numpy(F.stage_density(case.nx, case.ny, case.nz, surface_seed=1,
+                                             velocity_seed=2, phase_shift=shift)).to(dev)
+    uk = [torch.from_numpy(a).to(dev) for a in (case.u, case.v, case.w)]
+    s = Solver(rho, mask, case.bc, case.h)
+    rhs = torch.empty_like(rho)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    p, un, info = rk2.pressure_pair(s, None, rho_s, mask, uk, case.dt, tol=tol, rhs=rhs,
+                                    timed=True)
+    torch.cuda.synchronize()
+    total = (time.perf_counter() - t) * 1e3
+    d0, _ = s.divergence(*uk)
+    d1, _ = s.divergence(*un)
+    # the same second-stage equation from x0 = 0
+    pc = torch.empty_like(p)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, stc = s.solve(rhs, p=pc, tol=tol, warm=False)
+    torch.cuda.synchronize()
+    cold_ms = (time.perf_counter() - t) * 1e3
+    s.close()
+    st1, st2, ms = info["stage1"], info["stage2"], info["ms"]
+    log(f"  stage 1 {st1['iters']} iters {ms['stage1_solve']:.0f} ms; rebuild "
+        f"{ms['rebuild_star']:.1f} ms; stage 2 warm {st2['iters']} iters "
+        f"{ms['stage2_solve']:.0f} ms (cold {stc['iters']} iters {cold_ms:.0f} ms); "
+        f"pair {total:.0f} ms, div ratio {d1 / d0:.2e}")
+    return {"phase_shift": shift, "changed_cells": int((rho_s != rho).sum().item()),
+            "stage1_iters": st1["iters"], "stage2_iters_warm": st2["iters"],
+            "stage2_iters_cold": stc["iters"],
+            "ms": {k: round(v, 2) for k, v in ms.items()}, "pair_ms": round(total, 1),
+            "stage2_cold_ms": round(cold_ms, 1),
+            "warm_saving": round(1.0 - st2["iters"] / max(stc["iters"], 1), 3),
+            "div_ratio_final": d1 / d0}
 
 
 def bench_batch(nsolves):

@@ -177,6 +177,16 @@ int pcg_solve(pcg_ctx_t *ctx, const double *rhs, double *p, double tol,
               int32_t maxit, pcg_stats_t *stats);
 
 /*
+ * pcg_solve with the warm start chosen per call: flags 0 (x0 = 0) or
+ * PCG_WARM_START (x0 = p on entry), whatever the setup flags said.  The
+ * second stage of the Runge-Kutta step (Section 2.1) starts from the
+ * first-stage pressure P*, which solves a nearby equation.  Other flag bits
+ * give PCG_EINVAL.
+ */
+int pcg_solve_ex(pcg_ctx_t *ctx, const double *rhs, double *p, double tol,
+                 int32_t maxit, int32_t flags, pcg_stats_t *stats);
+
+/*
  * Host-side check that every connected region of fluid cells (face
  * adjacency, mask == 0) touches a Dirichlet wall, which is when the
  * discrete problem has a unique solution.  host_mask is a HOST u8[n] array
@@ -207,6 +217,57 @@ int pcg_density_classes(const pcg_ctx_t *ctx, int32_t *nclasses);
  */
 int pcg_project(pcg_ctx_t *ctx, const double *p, double dt, double *u, double *v,
                 double *w);
+
+/*
+ * Both velocity updates of the two-stage Runge-Kutta step (Section 2.1,
+ * the first-stage prediction u* and the second-stage average u^{k+1}), with
+ * the context's current face coefficients:
+ *   out_f = weight * (a_f [+ b_f] - dt * beta_f * (p_hi - p_lo) / h)
+ * on every MAC face, walls and hull as in pcg_project (which is this call
+ * with b absent, weight 1 and out = a).  First stage: a = u^k, b absent,
+ * weight 1, p = P*.  Second stage (after pcg_update_density to rho(phi*)):
+ * a = u*, b = u^k, weight 1/2, p = P^{k+1}.
+ *   a, b  device face triples (u f64[nz][ny][nx+1], v f64[nz][ny+1][nx],
+ *         w f64[nz+1][ny][nx]); b all NULL or all set
+ *   out   device face triple; may be the same arrays as a (or b), not
+ *         partly overlapping them
+ * PCG_EINVAL for a NULL array, a partial b, non-finite dt or weight, or a
+ * context whose coefficients are not valid.  Stream-ordered; returns after
+ * the launch.
+ */
+int pcg_project_ex(pcg_ctx_t *ctx, const double *p, double dt, const double *au,
+                   const double *av, const double *aw, const double *bu,
+                   const double *bv, const double *bw, double weight, double *u,
+                   double *v, double *w);
+
+/*
+ * Source term of either stage's pressure equation (Section 2.1, the
+ * right-hand sides of the two Poisson equations with the remaining terms R
+ * set to zero): rhs_c = (D U)_c / dt with U = a [+ b], i.e.
+ *   rhs_c = ((U_{i+1/2} - U_{i-1/2}) + (V_{j+1/2} - V_{j-1/2})
+ *            + (W_{k+1/2} - W_{k-1/2})) / h / dt
+ * in fluid cells and 0 in hull cells.  First stage a = u^k; second stage
+ * a = u*, b = u^k.  Face triples as in pcg_project_ex; rhs device f64[n].
+ * PCG_EINVAL for NULL arrays, a partial b, dt zero or non-finite.
+ * Stream-ordered; returns after the launch.
+ */
+int pcg_rhs(pcg_ctx_t *ctx, double dt, const double *au, const double *av,
+            const double *aw, const double *bu, const double *bv, const double *bw,
+            double *rhs);
+
+/*
+ * Rebuild the context's face coefficients in place for a new density field
+ * (and hull mask) on the same grid and walls: the second stage solves with
+ * rho(phi*) instead of rho(phi^k) (Section 2.1).  Same input rules and
+ * checks as pcg_setup (flags: PCG_SKIP_CONNECTIVITY_CHECK,
+ * PCG_NO_DENSITY_CLASSES; the setup flags no longer apply to the field).
+ * The workspace and any previous solution array are untouched, so a
+ * following pcg_solve may warm-start from the last pressure.  On error the
+ * context keeps no valid coefficients and every call that needs them returns
+ * PCG_EINVAL until a rebuild succeeds.  Blocks until done.
+ */
+int pcg_update_density(pcg_ctx_t *ctx, const double *rho, const uint8_t *solid_mask,
+                       int32_t flags);
 
 /*
  * Discrete divergence of MAC face velocities over the fluid cells (the form

@@ -179,6 +179,41 @@ def divergence(u, v, w, h, lib=None):
     return out
 
 
+def source(u, v, w, h, dt, mask, lib=None):
+    """Right-hand side of either stage's pressure equation (Section 2.1, R
+    set to zero): div(u)/dt on fluid cells, 0 on hull cells."""
+    rhs = divergence(u, v, w, h, lib) / dt
+    rhs[np.asarray(mask, dtype=bool)] = 0.0
+    return rhs
+
+
+def rk2_pair(rho_k, rho_star, mask, bc, h, dt, u, v, w, tol=1e-12, maxit=100000,
+             lib=None):
+    """Pressure half of one two-stage Runge-Kutta step (Section 2.1, R = 0),
+    each solve cold-started and taken to ``tol``:
+
+    1. P*  solves div((1/rho(phi^k)) grad P*) = div(u^k)/dt;
+    2. u*  = u^k - dt (1/rho(phi^k)) grad P*;
+    3. P^{k+1} solves div((1/rho(phi*)) grad P^{k+1}) = div(u* + u^k)/dt;
+    4. u^{k+1} = (u* + u^k - dt (1/rho(phi*)) grad P^{k+1}) / 2.
+
+    Returns a dict with p_star, u_star (triple), p_next, u_next (triple) and
+    the two iteration counts."""
+    lib = lib or load()
+    r1 = pcg(rho_k, mask, bc, h, source(u, v, w, h, dt, mask, lib), tol, maxit, lib=lib)
+    if r1.status != OK:
+        raise ValueError(f"first-stage solve status {r1.status}")
+    us = project(rho_k, mask, bc, h, dt, r1.p, u, v, w, lib)
+    s = tuple(a + b for a, b in zip(us, (u, v, w)))
+    r2 = pcg(rho_star, mask, bc, h, source(*s, h, dt, mask, lib), tol, maxit, lib=lib)
+    if r2.status != OK:
+        raise ValueError(f"second-stage solve status {r2.status}")
+    un = project(rho_star, mask, bc, h, dt, r2.p, *s, lib)
+    un = tuple(0.5 * a for a in un)
+    return {"p_star": r1.p, "u_star": us, "p_next": r2.p, "u_next": un,
+            "iters": (r1.iters, r2.iters)}
+
+
 def connected(mask, bc, lib=None) -> bool:
     lib = lib or load()
     mask, mp = _u8(mask)

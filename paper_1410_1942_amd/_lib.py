@@ -27,6 +27,7 @@ EXPORTED = [
     "pcg_set_timing", "pcg_last_timing", "pcg_copy_probe",
     "pcg_check_connectivity", "pcg_set_tile_rules", "pcg_get_tile_rules",
     "pcg_density_classes", "pcg_project", "pcg_divergence",
+    "pcg_solve_ex", "pcg_project_ex", "pcg_rhs", "pcg_update_density",
 ]
 
 
@@ -100,11 +101,15 @@ def load(path: str = LIB_PATH):
     lib.pcg_last_timing.argtypes = [vp, P(dbl), P(dbl), P(i32)]
     lib.pcg_copy_probe.argtypes = [vp, vp, sz, i32, vp, P(dbl)]
     lib.pcg_check_connectivity.argtypes = [vp, P(Grid), P(BC)]
-    lib.pcg_set_tile_rules.argtypes = [i32, i32, vp, vp, vp]
+    lib.pcg_set_tile_rules.argtypes = [i32, i32, i32, vp, vp, vp]
     lib.pcg_density_classes.argtypes = [vp, P(i32)]
     lib.pcg_project.argtypes = [vp, vp, dbl, vp, vp, vp]
     lib.pcg_divergence.argtypes = [vp, vp, vp, vp, P(dbl)]
-    lib.pcg_get_tile_rules.argtypes = [i32, i32, vp, vp, vp, P(i32)]
+    lib.pcg_get_tile_rules.argtypes = [i32, i32, i32, vp, vp, vp, P(i32)]
+    lib.pcg_solve_ex.argtypes = [vp, vp, vp, dbl, i32, i32, P(Stats)]
+    lib.pcg_project_ex.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, dbl, vp, vp, vp]
+    lib.pcg_rhs.argtypes = [vp, dbl, vp, vp, vp, vp, vp, vp, vp]
+    lib.pcg_update_density.argtypes = [vp, vp, vp, i32]
     for name in EXPORTED:
         if name not in ("pcg_strerror", "pcg_last_hip_error"):
             getattr(lib, name).restype = ctypes.c_int

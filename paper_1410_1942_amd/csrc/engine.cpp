@@ -29,8 +29,11 @@ hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n, int round
 hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
                          float *r32, int64_t n, int *bad, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
-hipError_t launch_project(const Slot *slot, const double *p, double s, double *u,
-                          double *v, double *w, int blocks, hipStream_t st);
+hipError_t launch_project(const Slot *slot, const double *p, double s, double wt,
+                          const double *const a[3], const double *const b[3],
+                          double *const out[3], int blocks, hipStream_t st);
+hipError_t launch_rhs(const Slot *slot, double h, double dt, const double *const a[3],
+                      const double *const b[3], double *rhs, int blocks, hipStream_t st);
 hipError_t launch_divnorm(const Slot *slot, double inv_h, const double *u,
                           const double *v, const double *w, double *part, int blocks,
                           hipStream_t st);
@@ -298,6 +301,7 @@ bool fluid_reaches_dirichlet(const std::vector<uint8_t> &solid, int nx, int ny,
 
 struct SlotHost {
     bool used = false;      // holds a prepared density field
+    bool ready = false;     // its coefficients are valid (a failed rebuild clears it)
     bool running = false;   // in the slot table
     bool finished = false;  // completion observed on the host
     Geometry geo{};
@@ -348,6 +352,7 @@ struct Engine {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool table_dirty = true;
+    int view_id = -1;       // slot whose projection view is in d_slots[0]
     int64_t total_tiles = 0;
     int nrunning = 0;
     bool is_batch = false;  // created by pcg_batch_create (batch tile table)
@@ -431,7 +436,8 @@ struct Engine {
     int slot_view(int id, Slot **d_slot)
     {
         SlotHost &S = slots[id];
-        if (!S.used) return PCG_EINVAL;
+        if (!S.used || !S.ready) return PCG_EINVAL;
+        if (view_id == id) { *d_slot = d_slots; return PCG_OK; }
         Slot &d = h_slots[0];
         std::memset(&d, 0, sizeof(Slot));
         d.nx = S.geo.nx; d.ny = S.geo.ny; d.nz = S.geo.nz;
@@ -444,6 +450,7 @@ struct Engine {
         HIP_TRY(hipMemcpyAsync(d_slots, h_slots, sizeof(Slot), hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         table_dirty = true;      // the solve path rebuilds the table before use
+        view_id = id;
         *d_slot = d_slots;
         return PCG_OK;
     }
@@ -472,20 +479,6 @@ struct Engine {
         size_t off = 0;
         if (!alloc.alloc(need, &off)) return max_slots == 1 ? PCG_ENOMEM : PCG_EBUSY;
 
-        // connectivity: every fluid region must touch a Dirichlet wall
-        if (!(flags & PCG_SKIP_CONNECTIVITY_CHECK)) {
-            bool ok;
-            if (mask) {
-                std::vector<uint8_t> h((size_t)geo.n);
-                hipError_t e = hipMemcpy(h.data(), mask, (size_t)geo.n, hipMemcpyDeviceToHost);
-                if (e != hipSuccess) { alloc.release(off, need); return hip_fail(e, "mask copy"); }
-                ok = fluid_reaches_dirichlet(h, geo.nx, geo.ny, geo.nz, bm);
-            } else {
-                ok = bm != 0;
-            }
-            if (!ok) { alloc.release(off, need); return PCG_ESINGULAR; }
-        }
-
         SlotHost &S = slots[id];
         S = SlotHost{};
         S.geo = geo;
@@ -509,8 +502,37 @@ struct Engine {
         S.tab64 = (double *)p;
         S.tab32 = (float *)(p + kClasses * kClasses * 8);
 
-        // encode and validate the densities, then (unless switched off) the
-        // chained class rounds; one host round trip reads both results
+        st = encode_slot(S, rho, mask, flags);
+        if (st) { alloc.release(off, need); S = SlotHost{}; return st; }
+        S.used = true;
+        *slot_out = id;
+        return PCG_OK;
+    }
+
+    // Check connectivity (unless skipped), encode and validate the densities,
+    // then (unless switched off) run the chained class rounds; one host round
+    // trip reads both results.  Overwrites the slot's coefficients: on any
+    // error the slot is left not ready.
+    int encode_slot(SlotHost &S, const double *rho, const uint8_t *mask, int flags)
+    {
+        S.ready = false;
+        S.classes = false;
+        S.nclasses = 0;
+        if (view_id >= 0 && &slots[view_id] == &S) view_id = -1;
+        const Geometry &geo = S.geo;
+        // connectivity: every fluid region must touch a Dirichlet wall
+        if (!(flags & PCG_SKIP_CONNECTIVITY_CHECK)) {
+            bool ok;
+            if (mask) {
+                std::vector<uint8_t> h((size_t)geo.n);
+                hipError_t e = hipMemcpy(h.data(), mask, (size_t)geo.n, hipMemcpyDeviceToHost);
+                if (e != hipSuccess) return hip_fail(e, "mask copy");
+                ok = fluid_reaches_dirichlet(h, geo.nx, geo.ny, geo.nz, S.bcmask);
+            } else {
+                ok = S.bcmask != 0;
+            }
+            if (!ok) return PCG_ESINGULAR;
+        }
         const bool want_classes = !(flags & PCG_NO_DENSITY_CLASSES);
         *h_bad = 0;
         hipError_t e = hipMemcpyAsync(d_bad, h_bad, sizeof(int), hipMemcpyHostToDevice, stream);
@@ -520,15 +542,24 @@ struct Engine {
             e = hipMemcpyAsync(h_bad, d_bad, want_classes ? 8 + 8 * kRounds : sizeof(int),
                                hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) { alloc.release(off, need); return hip_fail(e, "encode"); }
-        if (*h_bad) { alloc.release(off, need); return PCG_EDOMAIN; }
+        if (e != hipSuccess) return hip_fail(e, "encode");
+        if (*h_bad) return PCG_EDOMAIN;
         if (want_classes) {
-            st = classify_finish(S);
-            if (st) { alloc.release(off, need); return st; }
+            int st = classify_finish(S);
+            if (st) return st;
         }
-        S.used = true;
-        *slot_out = id;
+        S.ready = true;
+        table_dirty = true;      // coefficient mode and pointers may have changed
         return PCG_OK;
+    }
+
+    // New densities (and hull) for a prepared slot that is not running.
+    int refresh(int id, const double *rho, const uint8_t *mask, int flags)
+    {
+        if (id < 0 || id >= max_slots || !slots[id].used || !rho) return PCG_EINVAL;
+        SlotHost &S = slots[id];
+        if (S.running) return PCG_EBUSY;
+        return encode_slot(S, rho, mask, flags);
     }
 
     // Code the densities as classes when there are at most kMaxFluidClasses
@@ -589,7 +620,7 @@ struct Engine {
     // Start a solve on a prepared slot.
     int start(int id, const double *rhs, double *x, double tol, int maxit, int flags)
     {
-        if (id < 0 || id >= max_slots || !slots[id].used) return PCG_EINVAL;
+        if (id < 0 || id >= max_slots || !slots[id].used || !slots[id].ready) return PCG_EINVAL;
         if (!rhs || !x) return PCG_EINVAL;
         if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0) return PCG_EINVAL;
         SlotHost &S = slots[id];
@@ -621,6 +652,7 @@ struct Engine {
         if (!S.used) return;
         alloc.release(S.off, S.bytes);
         if (S.running) table_dirty = true;
+        if (view_id == id) view_id = -1;
         S = SlotHost{};
         h_states[id].phase = PH_IDLE;
     }
@@ -665,6 +697,7 @@ struct Engine {
         total_tiles = tb;
         nrunning = ns;
         modes = m;
+        view_id = -1;
         if (ns) HIP_TRY(hipMemcpyAsync(d_slots, h_slots, sizeof(Slot) * ns, hipMemcpyHostToDevice, stream));
         HIP_TRY(hipMemcpyAsync(d_hdr, h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, stream));
         table_dirty = false;
@@ -885,8 +918,16 @@ int pcg_solve(pcg_ctx_t *c, const double *rhs, double *p, double tol,
               int32_t maxit, pcg_stats_t *stats)
 {
     if (!c) return PCG_EINVAL;
+    return pcg_solve_ex(c, rhs, p, tol, maxit, c->flags & PCG_WARM_START, stats);
+}
+
+int pcg_solve_ex(pcg_ctx_t *c, const double *rhs, double *p, double tol,
+                 int32_t maxit, int32_t flags, pcg_stats_t *stats)
+{
+    if (!c) return PCG_EINVAL;
+    if (flags & ~PCG_WARM_START) return PCG_EINVAL;
     const auto t0 = Clock::now();
-    int st = c->eng.start(c->slot, rhs, p, tol, maxit, c->flags);
+    int st = c->eng.start(c->slot, rhs, p, tol, maxit, flags);
     if (st) return st;
     c->eng.t_k1.clear();
     c->eng.t_k2.clear();
@@ -971,19 +1012,64 @@ int pcg_get_tile_rules(int32_t precision, int32_t for_batches, int32_t cap,
     return PCG_OK;
 }
 
+static int project_blocks(const SlotHost &S)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>((S.geo.n + 255) / 256, 4096));
+}
+
 int pcg_project(pcg_ctx_t *c, const double *p, double dt, double *u, double *v,
                 double *w)
 {
-    if (!c || !p || !u || !v || !w || !std::isfinite(dt)) return PCG_EINVAL;
+    return pcg_project_ex(c, p, dt, u, v, w, nullptr, nullptr, nullptr, 1.0, u, v, w);
+}
+
+int pcg_project_ex(pcg_ctx_t *c, const double *p, double dt, const double *au,
+                   const double *av, const double *aw, const double *bu,
+                   const double *bv, const double *bw, double weight, double *u,
+                   double *v, double *w)
+{
+    if (!c || !p || !au || !av || !aw || !u || !v || !w) return PCG_EINVAL;
+    if (!std::isfinite(dt) || !std::isfinite(weight)) return PCG_EINVAL;
+    const bool add = bu || bv || bw;
+    if (add && !(bu && bv && bw)) return PCG_EINVAL;
     Slot *ds = nullptr;
     int st = c->eng.slot_view(c->slot, &ds);
     if (st) return st;
     const SlotHost &S = c->eng.slots[c->slot];
     const double h = std::sqrt(S.h2);
-    const int64_t blocks = std::min<int64_t>((S.geo.n + 255) / 256, 4096);
-    HIP_TRY(launch_project(ds, p, dt / h, u, v, w, (int)std::max<int64_t>(1, blocks),
-                           c->eng.stream));
+    const double *a[3] = { au, av, aw };
+    const double *b[3] = { bu, bv, bw };
+    double *o[3] = { u, v, w };
+    HIP_TRY(launch_project(ds, p, dt / h, weight, a, add ? b : nullptr, o,
+                           project_blocks(S), c->eng.stream));
     return PCG_OK;
+}
+
+int pcg_rhs(pcg_ctx_t *c, double dt, const double *au, const double *av,
+            const double *aw, const double *bu, const double *bv, const double *bw,
+            double *rhs)
+{
+    if (!c || !au || !av || !aw || !rhs) return PCG_EINVAL;
+    if (!std::isfinite(dt) || dt == 0.0) return PCG_EINVAL;
+    const bool add = bu || bv || bw;
+    if (add && !(bu && bv && bw)) return PCG_EINVAL;
+    Slot *ds = nullptr;
+    int st = c->eng.slot_view(c->slot, &ds);
+    if (st) return st;
+    const SlotHost &S = c->eng.slots[c->slot];
+    const double *a[3] = { au, av, aw };
+    const double *b[3] = { bu, bv, bw };
+    HIP_TRY(launch_rhs(ds, std::sqrt(S.h2), dt, a, add ? b : nullptr, rhs,
+                       project_blocks(S), c->eng.stream));
+    return PCG_OK;
+}
+
+int pcg_update_density(pcg_ctx_t *c, const double *rho, const uint8_t *solid_mask,
+                       int32_t flags)
+{
+    if (!c || !rho) return PCG_EINVAL;
+    if (flags & ~(PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES)) return PCG_EINVAL;
+    return c->eng.refresh(c->slot, rho, solid_mask, flags);
 }
 
 int pcg_divergence(pcg_ctx_t *c, const double *u, const double *v, const double *w,

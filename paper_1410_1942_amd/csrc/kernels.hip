@@ -986,22 +986,43 @@ k_classify(const double *__restrict__ r64, uint8_t *__restrict__ cls, int64_t n,
 // velocity projection and divergence (the step after each pressure solve)
 // ------------------------------------------------------------------------
 
-// u_f -= dt beta_f (p_hi - p_lo) / h on every MAC face, in place, with the
-// solve's face coefficients: interior faces between cells c-1 and c are
-// updated by cell c; wall faces use the mirrored ghost -p_c (Dirichlet:
-// gradient 2 p_c / h, coefficient 1/rho_c, i.e. beta(c, wall) p_c with
-// beta = 2/rho_c) or stay (Neumann, hull: beta = 0).  Face arrays are
-// u[nz][ny][nx+1], v[nz][ny+1][nx], w[nz+1][ny][nx].
-template <class C>
+// Face-velocity correction with the solve's face coefficients, on every MAC
+// face: out_f = wt (a_f [+ b_f] - dt beta_f (p_hi - p_lo) / h).  Interior
+// faces between cells c-1 and c are written by cell c; wall faces use the
+// mirrored ghost -p_c (Dirichlet: gradient 2 p_c / h with coefficient
+// 1/rho_c, i.e. beta(c, wall) p_c with beta = 2/rho_c) or get no correction
+// (Neumann, hull: beta = 0).  wt = 1 without b is the first-stage update
+// u* = u^k - dt grad(P*)/rho; wt = 1/2 with b = u^k is the second-stage
+// average.  Face arrays are u[nz][ny][nx+1], v[nz][ny+1][nx], w[nz+1][ny][nx];
+// out may be a (each face is read and written by one thread).
+struct FaceSet {
+    const double *u, *v, *w;
+};
+struct ProjOut {
+    double *u, *v, *w;
+};
+
+template <bool ADD>
+__device__ inline double face_in(const FaceSet &a, const FaceSet &b, int axis, int64_t f)
+{
+    const double *A = axis == 0 ? a.u : axis == 1 ? a.v : a.w;
+    if (!ADD) return gp(A)[f];
+    const double *B = axis == 0 ? b.u : axis == 1 ? b.v : b.w;
+    return gp(A)[f] + gp(B)[f];
+}
+
+template <bool ADD, class C>
 __device__ void project_cells(const Slot &S, const C &cf, const double *__restrict__ p,
-                              double s, double *__restrict__ u, double *__restrict__ v,
-                              double *__restrict__ w)
+                              double s, double wt, FaceSet a, FaceSet b, ProjOut o)
 {
     using K = typename C::Key;
     const int nx = S.nx, ny = S.ny, nz = S.nz;
     const int64_t P = (int64_t)nx * ny, n = P * nz;
     const int bm = S.bcmask;
     const GLB double *__restrict__ pg = gp(p);
+    GLB double *ou = gp(o.u);
+    GLB double *ov = gp(o.v);
+    GLB double *ow = gp(o.w);
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
          c += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(c % nx);
@@ -1012,32 +1033,77 @@ __device__ void project_cells(const Slot &S, const C &cf, const double *__restri
         const int64_t fu = ((int64_t)k * ny + j) * (nx + 1) + i;
         const int64_t fv = ((int64_t)k * (ny + 1) + j) * nx + i;
         const int64_t fw = c;
-        if (i > 0) u[fu] -= s * cf.beta(cf.load(c - 1), kc) * (pc - pg[c - 1]);
-        else u[fu] -= s * cf.beta(kc, (bm & 1) ? cf.dirichlet() : cf.neumann()) * pc;
-        if (i == nx - 1) u[fu + 1] += s * cf.beta(kc, (bm & 2) ? cf.dirichlet() : cf.neumann()) * pc;
-        if (j > 0) v[fv] -= s * cf.beta(cf.load(c - nx), kc) * (pc - pg[c - nx]);
-        else v[fv] -= s * cf.beta(kc, (bm & 4) ? cf.dirichlet() : cf.neumann()) * pc;
-        if (j == ny - 1) v[fv + nx] += s * cf.beta(kc, (bm & 8) ? cf.dirichlet() : cf.neumann()) * pc;
-        if (k > 0) w[fw] -= s * cf.beta(cf.load(c - P), kc) * (pc - pg[c - P]);
-        else w[fw] -= s * cf.beta(kc, (bm & 16) ? cf.dirichlet() : cf.neumann()) * pc;
-        if (k == nz - 1) w[fw + P] += s * cf.beta(kc, (bm & 32) ? cf.dirichlet() : cf.neumann()) * pc;
+        if (i > 0) ou[fu] = wt * (face_in<ADD>(a, b, 0, fu) - s * cf.beta(cf.load(c - 1), kc) * (pc - pg[c - 1]));
+        else ou[fu] = wt * (face_in<ADD>(a, b, 0, fu) - s * cf.beta(kc, (bm & 1) ? cf.dirichlet() : cf.neumann()) * pc);
+        if (i == nx - 1)
+            ou[fu + 1] = wt * (face_in<ADD>(a, b, 0, fu + 1) + s * cf.beta(kc, (bm & 2) ? cf.dirichlet() : cf.neumann()) * pc);
+        if (j > 0) ov[fv] = wt * (face_in<ADD>(a, b, 1, fv) - s * cf.beta(cf.load(c - nx), kc) * (pc - pg[c - nx]));
+        else ov[fv] = wt * (face_in<ADD>(a, b, 1, fv) - s * cf.beta(kc, (bm & 4) ? cf.dirichlet() : cf.neumann()) * pc);
+        if (j == ny - 1)
+            ov[fv + nx] = wt * (face_in<ADD>(a, b, 1, fv + nx) + s * cf.beta(kc, (bm & 8) ? cf.dirichlet() : cf.neumann()) * pc);
+        if (k > 0) ow[fw] = wt * (face_in<ADD>(a, b, 2, fw) - s * cf.beta(cf.load(c - P), kc) * (pc - pg[c - P]));
+        else ow[fw] = wt * (face_in<ADD>(a, b, 2, fw) - s * cf.beta(kc, (bm & 16) ? cf.dirichlet() : cf.neumann()) * pc);
+        if (k == nz - 1)
+            ow[fw + P] = wt * (face_in<ADD>(a, b, 2, fw + P) + s * cf.beta(kc, (bm & 32) ? cf.dirichlet() : cf.neumann()) * pc);
     }
 }
 
-__global__ void __launch_bounds__(256)
-k_project(const Slot *__restrict__ slot, const double *__restrict__ p, double s,
-          double *__restrict__ u, double *__restrict__ v, double *__restrict__ w)
+template <bool ADD>
+__device__ void project_slot(const Slot &S, double *s_tab64, const double *p, double s,
+                             double wt, FaceSet a, FaceSet b, ProjOut o)
 {
-    __shared__ double s_tab64[kClasses * kClasses];
-    const Slot &S = *slot;
     if (S.cls) {
         for (int i = threadIdx.x; i < kClasses * kClasses; i += blockDim.x)
             s_tab64[i] = gp(S.tab64)[i];
         __syncthreads();
-        project_cells(S, ClsCoef<double>{ gp(S.cls), s_tab64 }, p, s, u, v, w);
+        project_cells<ADD>(S, ClsCoef<double>{ gp(S.cls), s_tab64 }, p, s, wt, a, b, o);
     } else {
-        project_cells(S, RhoCoef<double>{ gp(S.rho64) }, p, s, u, v, w);
+        project_cells<ADD>(S, RhoCoef<double>{ gp(S.rho64) }, p, s, wt, a, b, o);
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_project(const Slot *__restrict__ slot, const double *__restrict__ p, double s, double wt,
+          FaceSet a, FaceSet b, ProjOut o)
+{
+    __shared__ double s_tab64[kClasses * kClasses];
+    if (b.u) project_slot<true>(*slot, s_tab64, p, s, wt, a, b, o);
+    else project_slot<false>(*slot, s_tab64, p, s, wt, a, b, o);
+}
+
+// Source of the pressure equation from face velocities:
+// rhs_c = ((du + dv) + dw) / h / dt with du = U_{i+1/2} - U_{i-1/2} (and so
+// on), U = a [+ b], in fluid cells; 0 in hull cells.  With b the second-stage
+// source div(u* + u^k)/dt, without it the first-stage div(u^k)/dt.
+template <bool ADD>
+__device__ void rhs_cells(const Slot &S, double h, double dt, FaceSet a, FaceSet b,
+                          double *__restrict__ rhs)
+{
+    const int nx = S.nx, ny = S.ny, nz = S.nz;
+    const int64_t P = (int64_t)nx * ny, n = P * nz;
+    const RhoCoef<double> cf{ gp(S.rho64) };
+    GLB double *out = gp(rhs);
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        if (cf.solid(cf.load(c))) { out[c] = 0.0; continue; }
+        const int i = (int)(c % nx);
+        const int j = (int)((c / nx) % ny);
+        const int k = (int)(c / P);
+        const int64_t fu = ((int64_t)k * ny + j) * (nx + 1) + i;
+        const int64_t fv = ((int64_t)k * (ny + 1) + j) * nx + i;
+        const double du = face_in<ADD>(a, b, 0, fu + 1) - face_in<ADD>(a, b, 0, fu);
+        const double dv = face_in<ADD>(a, b, 1, fv + nx) - face_in<ADD>(a, b, 1, fv);
+        const double dw = face_in<ADD>(a, b, 2, c + P) - face_in<ADD>(a, b, 2, c);
+        out[c] = ((du + dv) + dw) / h / dt;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_rhs(const Slot *__restrict__ slot, double h, double dt, FaceSet a, FaceSet b,
+      double *__restrict__ rhs)
+{
+    if (b.u) rhs_cells<true>(*slot, h, dt, a, b, rhs);
+    else rhs_cells<false>(*slot, h, dt, a, b, rhs);
 }
 
 // (D u)_c = (u_{i+1/2} - u_{i-1/2} + v_{j+1/2} - v_{j-1/2} + w_{k+1/2} -
@@ -1130,10 +1196,23 @@ hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
     return hipGetLastError();
 }
 
-hipError_t launch_project(const Slot *slot, const double *p, double s, double *u,
-                          double *v, double *w, int blocks, hipStream_t st)
+hipError_t launch_project(const Slot *slot, const double *p, double s, double wt,
+                          const double *const a[3], const double *const b[3],
+                          double *const out[3], int blocks, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, slot, p, s, u, v, w);
+    const FaceSet fa{ a[0], a[1], a[2] };
+    const FaceSet fb{ b ? b[0] : nullptr, b ? b[1] : nullptr, b ? b[2] : nullptr };
+    const ProjOut o{ out[0], out[1], out[2] };
+    hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, st, slot, p, s, wt, fa, fb, o);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs(const Slot *slot, double h, double dt, const double *const a[3],
+                      const double *const b[3], double *rhs, int blocks, hipStream_t st)
+{
+    const FaceSet fa{ a[0], a[1], a[2] };
+    const FaceSet fb{ b ? b[0] : nullptr, b ? b[1] : nullptr, b ? b[2] : nullptr };
+    hipLaunchKernelGGL(k_rhs, dim3(blocks), dim3(256), 0, st, slot, h, dt, fa, fb, rhs);
     return hipGetLastError();
 }
 

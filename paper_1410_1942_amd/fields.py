@@ -218,17 +218,8 @@ def make_two_phase(nx, ny, nz, *, surface_seed: Optional[int],
     ``default_rng(surface_seed)`` (the same generator when both seeds match,
     modes drawn first)."""
     h = 1.0 / nz
-    Lx, Ly = nx * h, ny * h
-    xc, yc, _ = cell_centres(nx, ny, nz, h)
-    vel_rng = np.random.default_rng(velocity_seed)
-    if surface_seed is None:
-        modes = None
-    elif surface_seed == velocity_seed:
-        modes = surface_modes(vel_rng, nmodes)
-    else:
-        modes = surface_modes(np.random.default_rng(surface_seed), nmodes)
-    eta = surface_elevation(xc, yc, Lx, Ly, modes, amp=amp)
-    rho = density(nx, ny, nz, h, eta, mollify=mollify)
+    modes, vel_rng = _draw_modes(surface_seed, velocity_seed, nmodes)
+    rho = _density_from_modes(nx, ny, nz, modes, 0.0, amp, mollify)
     if wedge is not None:
         mask = wedge_mask(nx, ny, nz, h, wedge)
     else:
@@ -242,6 +233,41 @@ def make_two_phase(nx, ny, nz, *, surface_seed: Optional[int],
     return Case(nx, ny, nz, h, rho, mask, tuple(int(b) for b in bc), dt,
                 u, v, w, np.ascontiguousarray(rhs), name=name,
                 seed=velocity_seed)
+
+
+def _draw_modes(surface_seed, velocity_seed, nmodes):
+    """Surface modes and the velocity generator, drawn as make_two_phase
+    draws them (modes first when both seeds match)."""
+    vel_rng = np.random.default_rng(velocity_seed)
+    if surface_seed is None:
+        modes = None
+    elif surface_seed == velocity_seed:
+        modes = surface_modes(vel_rng, nmodes)
+    else:
+        modes = surface_modes(np.random.default_rng(surface_seed), nmodes)
+    return modes, vel_rng
+
+
+def _density_from_modes(nx, ny, nz, modes, phase_shift, amp, mollify):
+    h = 1.0 / nz
+    xc, yc, _ = cell_centres(nx, ny, nz, h)
+    if modes is not None and phase_shift:
+        kx, ky, th = modes
+        modes = (kx, ky, th + phase_shift)
+    eta = surface_elevation(xc, yc, nx * h, ny * h, modes, amp=amp)
+    return density(nx, ny, nz, h, eta, mollify=mollify)
+
+
+def stage_density(nx, ny, nz, *, surface_seed: Optional[int], velocity_seed: int,
+                  phase_shift: float, nmodes: int = 8, amp: float = 0.01,
+                  mollify: float = 0.0) -> np.ndarray:
+    """Density of the surface moved for the second Runge-Kutta stage: the
+    modes of make_two_phase with the same seeds, every phase advanced by
+    ``phase_shift`` radians (a stand-in for the volume-fraction advance,
+    which is not part of this package).  ``phase_shift = 0`` returns
+    make_two_phase's density."""
+    modes, _ = _draw_modes(surface_seed, velocity_seed, nmodes)
+    return _density_from_modes(nx, ny, nz, modes, phase_shift, amp, mollify)
 
 
 def config1(n: int = 32, **kw) -> Case:

@@ -87,20 +87,43 @@ class Solver:
         self.lib = lib
 
     def solve(self, rhs: torch.Tensor, p: Optional[torch.Tensor] = None,
-              tol: float = 1e-8, maxit: int = 1000000, raise_on_error=True):
-        """Solve L p = rhs.  Returns (p, stats dict)."""
+              tol: float = 1e-8, maxit: int = 1000000, raise_on_error=True,
+              warm: Optional[bool] = None):
+        """Solve L p = rhs.  Returns (p, stats dict).  ``warm`` True starts
+        from p's contents, False from zero, None as the setup flags say."""
         _require_device(rhs)
         if rhs.dtype != torch.float64 or tuple(rhs.shape) != self.shape:
             raise ValueError("rhs must be float64 with the grid's shape")
         if p is None:
+            if warm:
+                raise ValueError("a warm start needs p")
             p = torch.empty_like(rhs)
         _require_device(p)
+        if p.dtype != torch.float64 or tuple(p.shape) != self.shape:
+            raise ValueError("p must be float64 with the grid's shape")
         st = L.Stats()
-        code = self.lib.pcg_solve(self._ctx, _ptr(rhs), _ptr(p), float(tol),
-                                  int(maxit), ctypes.byref(st))
+        if warm is None:
+            code = self.lib.pcg_solve(self._ctx, _ptr(rhs), _ptr(p), float(tol),
+                                      int(maxit), ctypes.byref(st))
+        else:
+            code = self.lib.pcg_solve_ex(self._ctx, _ptr(rhs), _ptr(p), float(tol),
+                                         int(maxit), L.WARM_START if warm else 0,
+                                         ctypes.byref(st))
         if raise_on_error:
             L.check(code, "pcg_solve")
         return p, st.as_dict()
+
+    def update_density(self, rho: torch.Tensor, mask: Optional[torch.Tensor] = None,
+                       flags: int = 0):
+        """New density (and hull) on the same grid and walls
+        (pcg_update_density); the next solve may warm-start."""
+        _require_device(rho, mask)
+        if rho.dtype != torch.float64 or tuple(rho.shape) != self.shape:
+            raise ValueError("rho must be float64 with the grid's shape")
+        if mask is not None and (mask.dtype != torch.uint8 or tuple(mask.shape) != self.shape):
+            raise ValueError("mask must be uint8 with the grid's shape")
+        L.check(self.lib.pcg_update_density(self._ctx, _ptr(rho), _ptr(mask), int(flags)),
+                "pcg_update_density")
 
     def density_classes(self) -> int:
         """Fluid density classes in use (0: per-cell densities)."""
@@ -108,18 +131,42 @@ class Solver:
         L.check(self.lib.pcg_density_classes(self._ctx, ctypes.byref(n)), "classes")
         return n.value
 
-    def project(self, p: torch.Tensor, dt: float, u: torch.Tensor,
-                v: torch.Tensor, w: torch.Tensor):
-        """u -= dt (1/rho) grad p on the MAC faces, in place (pcg_project)."""
+    def _faces(self, faces, what):
         nz, ny, nx = self.shape
-        for t, shp in ((u, (nz, ny, nx + 1)), (v, (nz, ny + 1, nx)), (w, (nz + 1, ny, nx))):
+        if faces is None or len(faces) != 3:
+            raise ValueError(f"{what}: three face arrays (u, v, w)")
+        for t, shp in zip(faces, ((nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx))):
             _require_device(t)
             if t.dtype != torch.float64 or tuple(t.shape) != shp:
-                raise ValueError("face arrays must be float64 u[nz,ny,nx+1], "
+                raise ValueError(f"{what}: face arrays must be float64 u[nz,ny,nx+1], "
                                  "v[nz,ny+1,nx], w[nz+1,ny,nx]")
+        return [_ptr(t) for t in faces]
+
+    def project(self, p: torch.Tensor, dt: float, u: torch.Tensor,
+                v: torch.Tensor, w: torch.Tensor, add=None, weight: float = 1.0,
+                out=None):
+        """Face update out = weight (u [+ add] - dt (1/rho) grad p) on the MAC
+        faces (pcg_project_ex); out defaults to (u, v, w), i.e. in place."""
+        a = self._faces((u, v, w), "velocity")
+        b = self._faces(add, "add") if add is not None else [None, None, None]
+        o = self._faces(out, "out") if out is not None else a
         _require_device(p)
-        L.check(self.lib.pcg_project(self._ctx, _ptr(p), float(dt), _ptr(u), _ptr(v),
-                                     _ptr(w)), "pcg_project")
+        if p.dtype != torch.float64 or tuple(p.shape) != self.shape:
+            raise ValueError("p must be float64 with the grid's shape")
+        L.check(self.lib.pcg_project_ex(self._ctx, _ptr(p), float(dt), *a, *b,
+                                        float(weight), *o), "pcg_project_ex")
+
+    def rhs(self, dt: float, u, v, w, add=None, out: Optional[torch.Tensor] = None):
+        """Source div(u [+ add]) / dt in fluid cells, 0 in hull cells (pcg_rhs)."""
+        a = self._faces((u, v, w), "velocity")
+        b = self._faces(add, "add") if add is not None else [None, None, None]
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=u.device)
+        _require_device(out)
+        if out.dtype != torch.float64 or tuple(out.shape) != self.shape:
+            raise ValueError("out must be float64 with the grid's shape")
+        L.check(self.lib.pcg_rhs(self._ctx, float(dt), *a, *b, _ptr(out)), "pcg_rhs")
+        return out
 
     def divergence(self, u, v, w):
         """(||D u||_2, max |D u|) over fluid cells (pcg_divergence)."""

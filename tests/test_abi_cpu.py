@@ -205,3 +205,14 @@ def test_tile_rules_roundtrip(lib):
         assert w1.value > w64.value
     finally:
         autotune.set_rules(0, saved)
+
+
+def test_stage_entry_points_reject_null_context(lib):
+    """The Runge-Kutta stage entry points validate arguments on the host."""
+    fake = ctypes.c_void_p(0x1000)
+    st = L.Stats()
+    assert lib.pcg_solve_ex(None, fake, fake, 1e-8, 10, 0, ctypes.byref(st)) == L.EINVAL
+    assert lib.pcg_update_density(None, fake, None, 0) == L.EINVAL
+    assert lib.pcg_rhs(None, 1e-3, fake, fake, fake, None, None, None, fake) == L.EINVAL
+    assert lib.pcg_project_ex(None, fake, 1e-3, fake, fake, fake, None, None, None, 1.0,
+                              fake, fake, fake) == L.EINVAL

@@ -331,3 +331,95 @@ def test_failures(orc):
     # iteration cap
     r = orc.pcg(rho, mask, TANK, h, rhs, tol=1e-14, maxit=1)
     assert r.status == orc.MAXIT and r.iters == 1
+
+
+# --------------------------------------------------------------------------
+# the two-stage Runge-Kutta pressure pair (Section 2.1)
+# --------------------------------------------------------------------------
+
+def _pair_case(F, nx=16, ny=12, nz=14, shift=0.6):
+    c = F.make_two_phase(nx, ny, nz, surface_seed=21, velocity_seed=22,
+                         wedge=F.Wedge(), bc=TANK)
+    rho_s = F.stage_density(nx, ny, nz, surface_seed=21, velocity_seed=22,
+                            phase_shift=shift)
+    return c, rho_s
+
+
+def test_source_matches_generator(orc, F):
+    """The oracle's source is the generator's div(u)/dt (zero on the hull)."""
+    c = _two_phase_wedge(F, 12, 10, 9, bc=TANK)
+    np.testing.assert_array_equal(orc.source(c.u, c.v, c.w, c.h, c.dt, c.mask), c.rhs)
+
+
+def test_source_linear_field(orc):
+    """u = (a x, b y, c z) on the faces has divergence a + b + c in every cell."""
+    nx, ny, nz = 5, 4, 6
+    h = 1.0 / nz
+    a, b, cc, dt = 0.75, -2.0, 0.5, 1e-3
+    u = np.broadcast_to(a * np.arange(nx + 1) * h, (nz, ny, nx + 1)).copy()
+    v = np.broadcast_to((b * np.arange(ny + 1) * h)[:, None], (nz, ny + 1, nx)).copy()
+    w = np.broadcast_to((cc * np.arange(nz + 1) * h)[:, None, None], (nz + 1, ny, nx)).copy()
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    mask[2, 1, 3] = 1
+    s = orc.source(u, v, w, h, dt, mask)
+    expect = np.full((nz, ny, nx), (a + b + cc) / dt)
+    expect[2, 1, 3] = 0.0
+    np.testing.assert_allclose(s, expect, rtol=1e-12)
+
+
+def test_pair_same_density_is_idempotent(orc, F):
+    """With rho(phi*) = rho(phi^k) the second stage re-solves the first
+    stage's equation (its source differs by the first residual), so
+    P^{k+1} = P* and u^{k+1} = u* up to that residual."""
+    c, _ = _pair_case(F)
+    out = orc.rk2_pair(c.rho, c.rho, c.mask, c.bc, c.h, c.dt, c.u, c.v, c.w, tol=1e-12)
+    assert np.abs(out["p_next"] - out["p_star"]).max() <= 1e-8 * np.abs(out["p_star"]).max()
+    for a, b in zip(out["u_next"], out["u_star"]):
+        assert np.abs(a - b).max() <= 1e-8 * np.abs(b).max()
+    # a dropped one-half would double u*; a dropped u^k in the second source
+    # would leave half of u^k's divergence: both far outside these bounds
+    d0 = np.linalg.norm(orc.divergence(c.u, c.v, c.w, c.h))
+    assert np.linalg.norm(orc.divergence(*out["u_next"], c.h)) <= 1e-10 * d0
+
+
+@pytest.mark.parametrize("shift", [0.3, 1.5])
+def test_pair_divergence_free(orc, F, shift):
+    """D u^{k+1} = (dt/2) (Sigma_2 - L* P^{k+1}): solenoidal to the second
+    solve's residual, which needs rho(phi*) in both the solve and the
+    face update."""
+    c, rho_s = _pair_case(F, shift=shift)
+    assert (rho_s != c.rho).any()
+    tol = 1e-10
+    out = orc.rk2_pair(c.rho, rho_s, c.mask, c.bc, c.h, c.dt, c.u, c.v, c.w, tol=tol)
+    s2 = orc.source(*(a + b for a, b in zip(out["u_star"], (c.u, c.v, c.w))), c.h, c.dt,
+                    c.mask)
+    d1 = np.linalg.norm(orc.divergence(*out["u_next"], c.h))
+    assert d1 <= 0.5 * c.dt * tol * np.linalg.norm(s2) * 1.01
+    # u* is solenoidal under the first-stage density
+    ds = np.linalg.norm(orc.divergence(*out["u_star"], c.h))
+    assert ds <= c.dt * tol * np.linalg.norm(c.rhs) * 1.01
+
+
+def test_pair_dense(orc, F):
+    """Both stage pressures against dense Cholesky solves assembled from the
+    definition, on a tiny wedge case."""
+    nx, ny, nz = 6, 5, 8
+    c = F.make_two_phase(nx, ny, nz, surface_seed=31, velocity_seed=32, wedge=F.Wedge(),
+                         bc=TANK)
+    rho_s = F.stage_density(nx, ny, nz, surface_seed=31, velocity_seed=32, phase_shift=2.0)
+    out = orc.rk2_pair(c.rho, rho_s, c.mask, c.bc, c.h, c.dt, c.u, c.v, c.w, tol=1e-14)
+    fluid = c.mask == 0
+
+    def dense(rho, rhs):
+        A = _dense_minus_h2L(rho, c.mask, c.bc)
+        Lc = np.linalg.cholesky(A)
+        b = (-c.h**2 * rhs * fluid).ravel()
+        return scipy.linalg.solve_triangular(
+            Lc.T, scipy.linalg.solve_triangular(Lc, b, lower=True)).reshape(rho.shape)
+
+    p1 = dense(c.rho, c.rhs)
+    assert np.abs(out["p_star"] - p1).max() <= 1e-10 * np.abs(p1).max()
+    s2 = orc.source(*(a + b for a, b in zip(out["u_star"], (c.u, c.v, c.w))), c.h, c.dt,
+                    c.mask)
+    p2 = dense(rho_s, s2)
+    assert np.abs(out["p_next"] - p2).max() <= 1e-10 * np.abs(p2).max()
