@@ -40,8 +40,8 @@ PREC_KEYS = {L.PREC_FP64: "fp64", L.PREC_FP32_IR: "fp32_ir"}
 
 CLASSES = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512]
 BATCH_CLASSES = [16, 24, 32, 48, 64, 96, 128, 192]
-TZS = [2, 4, 8, 16, 32, 64]
-GRIDS = [256, 512, 1024, 2048]
+TZS = [2, 4, 8, 16, 32, 64, 128, 256]
+GRIDS = [256, 512, 768, 1024, 2048]
 
 _installed = False
 

@@ -61,6 +61,8 @@ constexpr size_t kAlign = 256;
 constexpr int kDefaultCheckEvery = 32;
 constexpr int kDefaultGridMax = 1024;
 constexpr double kDefaultInnerTol = 1e-4;
+// largest byte span pass A addresses within one tile (32-bit offsets)
+constexpr int64_t kMaxTileBytes = 0xffffffffll;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -81,8 +83,8 @@ struct TileRule {
 
 // Built-in table: the autotuner's choice on gfx950 (package tile_table.json).
 std::vector<TileRule> g_rules[2] = {  // single solves: FP64, FP32+IR
-    { { 7524, 2, 256 }, { 21283, 2, 256 }, { 60198, 4, 1024 }, { 170267, 4, 2048 }, { 481589, 8, 512 }, { 1362140, 16, 1024 }, { 3852714, 32, 256 }, { 10897121, 64, 512 }, { 30821713, 64, 512 }, { 87176971, 32, 1024 }, { INT64_MAX, 64, 1024 } },
-    { { 7524, 2, 1024 }, { 21283, 2, 2048 }, { 60198, 4, 2048 }, { 170267, 4, 2048 }, { 481589, 8, 512 }, { 1362140, 16, 2048 }, { 3852714, 16, 512 }, { 10897121, 64, 2048 }, { 30821713, 32, 1024 }, { 87176971, 32, 1024 }, { INT64_MAX, 64, 1024 } },
+    { { 7524, 2, 256 }, { 21283, 4, 768 }, { 60198, 4, 512 }, { 170267, 8, 256 }, { 481589, 8, 256 }, { 1362140, 16, 512 }, { 3852714, 32, 1024 }, { 10897121, 64, 1024 }, { 30821713, 128, 768 }, { 87176971, 64, 512 }, { INT64_MAX, 256, 512 } },
+    { { 7524, 2, 1024 }, { 21283, 4, 768 }, { 60198, 4, 1024 }, { 170267, 8, 768 }, { 481589, 8, 1024 }, { 1362140, 16, 2048 }, { 3852714, 32, 2048 }, { 10897121, 64, 2048 }, { 30821713, 128, 1024 }, { 87176971, 32, 768 }, { INT64_MAX, 128, 1024 } },
 };
 
 // Batches: longer tiles (the resident solves fill the device together).
@@ -171,6 +173,10 @@ Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch)
     G.tz = tz_opt > 0 ? tz_opt : choose_tz(G.n, prec, batch);
     if (G.tz > g.nz) G.tz = g.nz;
     const int64_t plane = (int64_t)g.nx * g.ny;
+    // pass A addresses a tile's tz + 2 planes of 8-byte values with 32-bit
+    // byte offsets
+    const int64_t tz_cap = kMaxTileBytes / (plane * 8) - 2;
+    if (G.tz > tz_cap) G.tz = (int)std::max<int64_t>(1, tz_cap);
     G.plane_tiles = (int)((plane + kBlock - 1) / kBlock);
     G.ztiles = (g.nz + G.tz - 1) / G.tz;
     G.ntiles = (int64_t)G.plane_tiles * G.ztiles;
@@ -206,6 +212,9 @@ int check_grid(const pcg_grid_t *g)
     if (!(g->h > 0.0) || !std::isfinite(g->h)) return PCG_EINVAL;
     const int64_t n = (int64_t)g->nx * g->ny * g->nz;
     if (n >= ((int64_t)1 << 31)) return PCG_EUNSUPPORTED;
+    // a tile of one plane and its two neighbours must fit pass A's 32-bit
+    // byte offsets
+    if ((int64_t)g->nx * g->ny * 8 * 3 > kMaxTileBytes) return PCG_EUNSUPPORTED;
     return PCG_OK;
 }
 

@@ -332,67 +332,189 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
     acc[2] += a2;
 }
 
+// ------------------------------------------------------------------------
+// buffer addressing for pass A
+// ------------------------------------------------------------------------
+// Each array pass A streams is reached through a buffer resource (four
+// scalar registers) based at the plane below the tile, a per-plane scalar
+// byte offset, and a per-lane 32-bit byte offset fixed for the whole tile
+// (the lane's column, or its x/y neighbour's).  Addresses then cost one
+// vector register per neighbour direction instead of a 64-bit pointer per
+// load, and the resource's record count bounds every access.  A tile spans
+// at most tz + 2 planes, which set-up keeps under 2^32 bytes of 8-byte
+// values.
+
+// Dword 3 of a raw buffer resource on this architecture: 32-bit data format,
+// no swizzle, no index stride.
+constexpr int kRawBufferWord3 = 0x00020000;
+// Cache-policy bit for streaming (non-temporal) accesses.
+constexpr int kBufNT = 2;
+
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ __forceinline__ Buf make_buf(const void *base, uint32_t bytes)
+{
+    return { __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes,
+                                               kRawBufferWord3) };
+}
+
+template <int AUX = 0>
+__device__ __forceinline__ double bld(double *, Buf b, uint32_t v, uint32_t s)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, v, s, AUX));
+}
+template <int AUX = 0>
+__device__ __forceinline__ float bld(float *, Buf b, uint32_t v, uint32_t s)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, v, s, AUX));
+}
+template <int AUX = 0>
+__device__ __forceinline__ int bld(uint8_t *, Buf b, uint32_t v, uint32_t s)
+{
+    return (int)__builtin_amdgcn_raw_buffer_load_b8(b.r, v, s, AUX);
+}
+template <typename T, int AUX = 0>
+__device__ __forceinline__ T bload(Buf b, uint32_t v, uint32_t s)
+{
+    return bld<AUX>((T *)nullptr, b, v, s);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void bstore_nt(Buf b, uint32_t v, uint32_t s, double x)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), b.r, v, s, kBufNT);
+}
+__device__ __forceinline__ void bstore_nt(Buf b, uint32_t v, uint32_t s, float x)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), b.r, v, s, kBufNT);
+}
+
+// Byte offsets of a lane's cell and its x/y neighbours within a plane
+// (wall neighbours point at the cell itself), for elements of ES bytes.
+struct LaneOff {
+    uint32_t c, xm, xp, ym, yp;
+};
+template <typename Key>
+__device__ __forceinline__ LaneOff lane_off(const TileCtx &t, const Nbr<Key> &n, int es)
+{
+    return { (uint32_t)t.q * es, (uint32_t)(t.q + n.oxm) * es, (uint32_t)(t.q + n.oxp) * es,
+             (uint32_t)(t.q + n.oym) * es, (uint32_t)(t.q + n.oyp) * es };
+}
+
+// The tile's window of an array: planes [b0, e0) with b0 the plane below
+// the tile (if any) and e0 the plane above it (if any).
+struct Window {
+    int b0, e0;
+    int64_t P;
+    template <typename T>
+    __device__ __forceinline__ Buf buf(const T *a) const
+    {
+        return make_buf(a + (int64_t)b0 * P, (uint32_t)((int64_t)(e0 - b0) * P * sizeof(T)));
+    }
+    // byte offset of plane kk for elements of ES bytes
+    __device__ __forceinline__ uint32_t so(int kk, int es) const
+    {
+        return (uint32_t)((int64_t)(kk - b0) * P * es);
+    }
+};
+
+__device__ __forceinline__ Window tile_window(const TileCtx &t, const Slot &S)
+{
+    return { t.k0 > 0 ? t.k0 - 1 : 0, t.k1 < S.nz ? t.k1 + 1 : S.nz, (int64_t)t.P };
+}
+
+// Key source of a coefficient policy through a buffer.
+template <typename T>
+__device__ __forceinline__ const void *key_array(const RhoCoef<T> &cf) { return (const void *)cf.rho; }
+template <typename T>
+__device__ __forceinline__ const void *key_array(const ClsCoef<T> &cf) { return (const void *)cf.cls; }
+template <class C> struct KeyElem;
+template <typename T> struct KeyElem<RhoCoef<T>> { using type = T; };
+template <typename T> struct KeyElem<ClsCoef<T>> { using type = uint8_t; };
+
 // K1_CG_A / K1_IR_A: p_new = z + beta p_old, stored; the quadratic form
 // p.Ap = sum over faces of beta_f (p_c - p_n)^2, each face counted once
 // from the cell above it (x, y, z low faces), plus the wall terms
-// (2/rho_c) p_c^2 of the Dirichlet walls.
+// (2/rho_c) p_c^2 of the Dirichlet walls.  Two load sets alternate, each
+// refilled for the plane after next before the other's plane is computed,
+// so a wave waits only for loads issued a plane earlier.
+template <typename T, typename K>
+struct PlaneA {
+    T zc, qc, zxm, qxm, zym, qym;
+    K kc, kxm, kym;
+};
+
 template <typename T, class C>
 __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
                            const C &cf, double (&acc)[3])
 {
     using K = typename C::Key;
+    using KE = typename KeyElem<C>::type;
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const GLB T *__restrict__ ps = gp((const T *)(st.pbuf ? S.pb : S.pa));
-    GLB T *__restrict__ pd = gp((T *)(st.pbuf ? S.pa : S.pb));
-    const GLB T *__restrict__ z = gp((const T *)S.z);
+    const Window W = tile_window(t, S);
+    // the buffer index is the same in every lane (state written by the
+    // previous launch); reading it from one lane keeps the resources scalar
+    const int pbuf = __builtin_amdgcn_readfirstlane(st.pbuf);
+    const Buf bps = W.buf((const T *)(pbuf ? S.pb : S.pa));
+    const Buf bpd = W.buf((const T *)(pbuf ? S.pa : S.pb));
+    const Buf bz = W.buf((const T *)S.z);
+    const Buf bk = W.buf((const KE *)key_array(cf));
     // first direction: beta = 0.  p_old is then still read (it holds zeros
     // from the set-up phase or a finite earlier direction), which keeps the
-    // loads unconditional and lets them all be in flight together.
+    // loads unconditional.
     const T beta = st.first ? T(0) : (T)st.beta;
     const Nbr<K> n = make_nbr(t, S, cf);
+    const LaneOff ov = lane_off(t, n, (int)sizeof(T));
+    const LaneOff ok = lane_off(t, n, (int)sizeof(KE));
     const int bm = S.bcmask;
     // Dirichlet high walls of this column (x+, y+); z+ is added on the top plane
     const int hw = ((!n.hxp && (bm & 2)) ? 1 : 0) + ((!n.hyp && (bm & 8)) ? 1 : 0);
-    const int64_t P = t.P;
-    int64_t c = (int64_t)t.k0 * P + t.q;
+    const int nz = S.nz;
+    auto load = [&](int kk) {
+        kk = kk < t.k1 ? kk : t.k1 - 1;    // past the tile's end: re-read its last plane
+        const uint32_t sv = W.so(kk, sizeof(T)), sk = W.so(kk, sizeof(KE));
+        PlaneA<T, K> L;
+        L.zxm = bload<T>(bz, ov.xm, sv); L.qxm = bload<T>(bps, ov.xm, sv);
+        L.zym = bload<T>(bz, ov.ym, sv); L.qym = bload<T>(bps, ov.ym, sv);
+        L.kxm = bload<KE>(bk, ok.xm, sk); L.kym = bload<KE>(bk, ok.ym, sk);
+        L.zc = bload<T>(bz, ov.c, sv); L.qc = bload<T>(bps, ov.c, sv);
+        L.kc = bload<KE>(bk, ok.c, sk);
+        return L;
+    };
     T pzm = T(0);
     K kzm = n.wzm;
     if (t.k0 > 0) {
-        const T zz = z[c - P], qq = ps[c - P];
-        pzm = zz + beta * qq;
-        kzm = cf.load(c - P);
+        const uint32_t sv = W.so(t.k0 - 1, sizeof(T)), sk = W.so(t.k0 - 1, sizeof(KE));
+        pzm = bload<T>(bz, ov.c, sv) + beta * bload<T>(bps, ov.c, sv);
+        kzm = bload<KE>(bk, ok.c, sk);
     }
-    // own values of the current plane; those of the next plane are loaded
-    // together with this plane's neighbours, so every load of an iteration
-    // is issued before any of them is used
-    T zc = z[c], qc = ps[c];
-    K kc = cf.load(c);
     double a = 0.0;
-    for (int k = t.k0; k < t.k1; ++k, c += P) {
-        const T zxm = z[c + n.oxm], qxm = ps[c + n.oxm];
-        const T zym = z[c + n.oym], qym = ps[c + n.oym];
-        const K lkxm = cf.load(c + n.oxm), lkym = cf.load(c + n.oym);
-        const int64_t cn = k + 1 < t.k1 ? c + P : c;
-        const T zn = z[cn], qn = ps[cn];
-        const K kn = cf.load(cn);
-        const T pc = zc + beta * qc;
-        const K kxm = n.hxm ? lkxm : n.wxm, kym = n.hym ? lkym : n.wym;
-        const T pxm = n.hxm ? zxm + beta * qxm : T(0);
-        const T pym = n.hym ? zym + beta * qym : T(0);
+    auto step = [&](const PlaneA<T, K> &L, int kk) {
+        const T pc = L.zc + beta * L.qc;
+        const K kxm = n.hxm ? L.kxm : n.wxm, kym = n.hym ? L.kym : n.wym;
+        const T pxm = n.hxm ? L.zxm + beta * L.qxm : T(0);
+        const T pym = n.hym ? L.zym + beta * L.qym : T(0);
         const T dx = pc - pxm, dy = pc - pym, dz = pc - pzm;
-        T s = (cf.beta(kc, kxm) * dx * dx + cf.beta(kc, kym) * dy * dy) +
-              cf.beta(kc, kzm) * dz * dz;
-        const int w = hw + ((k == S.nz - 1 && (bm & 32)) ? 1 : 0);
-        if (w) s += (T)w * cf.beta(kc, cf.dirichlet()) * (pc * pc);
+        T s = (cf.beta(L.kc, kxm) * dx * dx + cf.beta(L.kc, kym) * dy * dy) +
+              cf.beta(L.kc, kzm) * dz * dz;
+        const int w = hw + ((kk == nz - 1 && (bm & 32)) ? 1 : 0);
+        s += (T)w * cf.beta(L.kc, cf.dirichlet()) * (pc * pc);   // + 0 without walls
         a += (double)s;
-        __builtin_nontemporal_store(pc, &pd[c]);
+        bstore_nt(bpd, ov.c, W.so(kk, sizeof(T)), pc);
         pzm = pc;
-        kzm = kc;
-        zc = zn;
-        qc = qn;
-        kc = kn;
+        kzm = L.kc;
+    };
+    PlaneA<T, K> A = load(t.k0), B;
+    int k = t.k0;
+    for (; k + 1 < t.k1; k += 2) {
+        B = load(k + 1);
+        step(A, k);
+        A = load(k + 2);
+        step(B, k + 1);
     }
+    if (k < t.k1) step(A, k);
     acc[0] += a;
 }
 

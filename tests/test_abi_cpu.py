@@ -216,3 +216,23 @@ def test_stage_entry_points_reject_null_context(lib):
     assert lib.pcg_rhs(None, 1e-3, fake, fake, fake, None, None, None, fake) == L.EINVAL
     assert lib.pcg_project_ex(None, fake, 1e-3, fake, fake, fake, None, None, None, 1.0,
                               fake, fake, fake) == L.EINVAL
+
+
+def test_plane_and_tile_span_limits(lib):
+    """Pass A addresses a tile's planes with 32-bit byte offsets: planes
+    whose three-plane span of 8-byte values exceeds 2^32 bytes are refused,
+    and the tile height is capped so tz + 2 planes fit."""
+    out = ctypes.c_size_t()
+    huge_plane = _g(16384, 16384, 2)            # 2^28 cells per plane
+    assert lib.pcg_workspace_bytes(ctypes.byref(huge_plane), None,
+                                   ctypes.byref(out)) == L.EUNSUPPORTED
+    g = _g(4096, 4096, 64)                      # 2^27 bytes per plane: tz <= 30
+    sizes = {}
+    for tz in (16, 30, 31, 64):
+        o = L.Opts()
+        o.tz = tz
+        assert lib.pcg_workspace_bytes(ctypes.byref(g), ctypes.byref(o),
+                                       ctypes.byref(out)) == L.OK
+        sizes[tz] = out.value
+    assert sizes[31] == sizes[30] == sizes[64]  # clamped to 30
+    assert sizes[16] != sizes[30]
