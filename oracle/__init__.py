@@ -60,6 +60,8 @@ def load(path: Optional[str] = None):
     lib.oracle_divergence.restype = None
     lib.oracle_connected.argtypes = [i, i, i, up, ip]
     lib.oracle_connected.restype = i
+    lib.oracle_components.argtypes = [i, i, i, up, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.oracle_components.restype = i
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = i
     if path is None:
@@ -212,6 +214,19 @@ def rk2_pair(rho_k, rho_star, mask, bc, h, dt, u, v, w, tol=1e-12, maxit=100000,
     un = tuple(0.5 * a for a in un)
     return {"p_star": r1.p, "u_star": us, "p_next": r2.p, "u_next": un,
             "iters": (r1.iters, r2.iters)}
+
+
+def components(mask, bc, lib=None):
+    """(fluid regions, regions without a Dirichlet face); periodic faces join
+    the cells they connect."""
+    lib = lib or load()
+    mask, mp = _u8(mask)
+    nz, ny, nx = mask.shape
+    loose = ctypes.c_int(0)
+    n = lib.oracle_components(nx, ny, nz, mp, _bc(bc), ctypes.byref(loose))
+    if n < 0:
+        raise MemoryError("oracle_components")
+    return int(n), int(loose.value)
 
 
 def connected(mask, bc, lib=None) -> bool:

@@ -21,9 +21,17 @@
  *     beta = 1/rho_c with the mirrored ghost value -p_c;
  *   * (L p)_c = h^-2 [ sum_n beta_cn (p_n - p_c)
  *                      + sum_{Dirichlet faces} beta_c (-p_c - p_c) ].
+ *   * periodic walls (the strut case of Section 3, periodic along x) come in
+ *     opposite pairs on x or y: the face beyond the last cell of a row is the
+ *     face before its first cell, an ordinary face between those two cells.
+ *     An axis of one cell has no flux across its periodic face.
  * The solution is p = L^-1 Sigma on fluid cells and p = 0 on solid cells.
- * It exists and is unique iff every connected fluid region touches a
- * Dirichlet face.
+ * It exists and is unique iff every connected fluid region (periodic faces
+ * included) touches a Dirichlet face.  When there is exactly one fluid
+ * region and it touches none (no-flux and periodic walls only, as in the
+ * strut case), L is singular with the constant as its null vector: the
+ * oracle then solves for the source with its mean over fluid cells removed
+ * and returns the solution of zero mean over fluid cells.
  *
  * The Introduction states that the equation is solved by a preconditioned
  * conjugate-gradient method.  The oracle runs textbook Jacobi-preconditioned
@@ -85,23 +93,45 @@ static double wall_beta(const problem *P, size_t a, int kind)
  * Visit the six faces of cell (i,j,k).  For each face report the neighbour
  * index (or -1 for a wall) and beta.  Order: x-, x+, y-, y+, z-, z+.
  */
+/*
+ * Neighbour of (i,j,k) across face f (order x-, x+, y-, y+, z-, z+), with
+ * periodic wrap-around.  Returns 1 and the neighbour's coordinates, or 0 for
+ * a wall face.  The cell itself is never its own neighbour: on a periodic
+ * axis of one cell the face carries no flux and is reported as a wall of
+ * kind Neumann via *closed.
+ */
+static int neighbour(const problem *P, int i, int j, int k, int f, int *ni,
+                     int *nj, int *nk, int *closed)
+{
+    int ii = i + (f == 0 ? -1 : f == 1 ? 1 : 0);
+    int jj = j + (f == 2 ? -1 : f == 3 ? 1 : 0);
+    int kk = k + (f == 4 ? -1 : f == 5 ? 1 : 0);
+    *closed = 0;
+    if (P->bc[f] == O_PERIODIC) {
+        int len = f < 2 ? P->nx : P->ny;
+        if (len == 1) { *closed = 1; return 0; }
+        if (f < 2) ii = (ii + P->nx) % P->nx;
+        else jj = (jj + P->ny) % P->ny;
+    }
+    if (ii < 0 || ii >= P->nx || jj < 0 || jj >= P->ny || kk < 0 || kk >= P->nz)
+        return 0;
+    *ni = ii; *nj = jj; *nk = kk;
+    return 1;
+}
+
 static void faces_of(const problem *P, int i, int j, int k,
                      long long nb[6], double beta[6])
 {
     size_t c = cell(P, i, j, k);
-    int ii[6] = { i - 1, i + 1, i, i, i, i };
-    int jj[6] = { j, j, j - 1, j + 1, j, j };
-    int kk[6] = { k, k, k, k, k - 1, k + 1 };
     for (int f = 0; f < 6; ++f) {
-        int inside = ii[f] >= 0 && ii[f] < P->nx && jj[f] >= 0 &&
-                     jj[f] < P->ny && kk[f] >= 0 && kk[f] < P->nz;
-        if (inside) {
-            size_t n = cell(P, ii[f], jj[f], kk[f]);
+        int ni, nj, nk, closed;
+        if (neighbour(P, i, j, k, f, &ni, &nj, &nk, &closed)) {
+            size_t n = cell(P, ni, nj, nk);
             nb[f] = (long long)n;
             beta[f] = face_beta(P, c, n);
         } else {
             nb[f] = -1;
-            beta[f] = wall_beta(P, c, P->bc[f]);
+            beta[f] = closed ? 0.0 : wall_beta(P, c, P->bc[f]);
         }
     }
 }
@@ -155,10 +185,13 @@ static double dot(size_t n, const double *a, const double *b)
 static int check_problem(const problem *P)
 {
     if (P->nx < 1 || P->ny < 1 || P->nz < 1 || !(P->h > 0.0)) return O_EINVAL;
-    for (int f = 0; f < 6; ++f) {
-        if (P->bc[f] == O_PERIODIC) return O_EUNSUPPORTED;
-        if (P->bc[f] != O_NEUMANN && P->bc[f] != O_DIRICHLET) return O_EINVAL;
-    }
+    for (int f = 0; f < 6; ++f)
+        if (P->bc[f] != O_NEUMANN && P->bc[f] != O_DIRICHLET && P->bc[f] != O_PERIODIC)
+            return O_EINVAL;
+    /* periodic walls pair up; periodic z is not part of this reference */
+    for (int a = 0; a < 3; ++a)
+        if ((P->bc[2 * a] == O_PERIODIC) != (P->bc[2 * a + 1] == O_PERIODIC)) return O_EINVAL;
+    if (P->bc[4] == O_PERIODIC) return O_EUNSUPPORTED;
     size_t n = (size_t)P->nx * P->ny * P->nz;
     for (size_t c = 0; c < n; ++c)
         if (!P->solid[c] && !(P->rho[c] > 0.0 && isfinite(P->rho[c])))
@@ -167,12 +200,13 @@ static int check_problem(const problem *P)
 }
 
 /*
- * 1 if every connected region of fluid cells (face adjacency) contains a cell
- * with a Dirichlet wall face, else 0.  Breadth-first search from all such
- * cells, then a scan for unreached fluid.
+ * Connected regions of fluid cells (face adjacency, periodic faces
+ * included), by breadth-first search.  Returns the number of regions and
+ * writes to *unanchored how many of them contain no cell with a Dirichlet
+ * wall face; -1 when memory runs out.
  */
-int oracle_connected(int nx, int ny, int nz, const uint8_t *solid,
-                     const int *bc)
+int oracle_components(int nx, int ny, int nz, const uint8_t *solid, const int *bc,
+                      int *unanchored)
 {
     problem P = { nx, ny, nz, 1.0, NULL, solid, { 0 } };
     for (int f = 0; f < 6; ++f) P.bc[f] = bc[f];
@@ -180,39 +214,42 @@ int oracle_connected(int nx, int ny, int nz, const uint8_t *solid,
     uint8_t *seen = calloc(n, 1);
     size_t *queue = malloc(n * sizeof(size_t));
     if (!seen || !queue) { free(seen); free(queue); return -1; }
-    size_t head = 0, tail = 0;
-    for (int k = 0; k < nz; ++k)
-        for (int j = 0; j < ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                size_t c = cell(&P, i, j, k);
-                if (solid[c]) continue;
-                int touches = (i == 0 && bc[0] == O_DIRICHLET) ||
-                              (i == nx - 1 && bc[1] == O_DIRICHLET) ||
-                              (j == 0 && bc[2] == O_DIRICHLET) ||
-                              (j == ny - 1 && bc[3] == O_DIRICHLET) ||
-                              (k == 0 && bc[4] == O_DIRICHLET) ||
-                              (k == nz - 1 && bc[5] == O_DIRICHLET);
-                if (touches) { seen[c] = 1; queue[tail++] = c; }
+    int regions = 0, loose = 0;
+    for (size_t s0 = 0; s0 < n; ++s0) {
+        if (solid[s0] || seen[s0]) continue;
+        size_t head = 0, tail = 0;
+        int anchored = 0;
+        seen[s0] = 1;
+        queue[tail++] = s0;
+        while (head < tail) {
+            size_t c = queue[head++];
+            int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
+            for (int f = 0; f < 6; ++f) {
+                int ni, nj, nk, closed;
+                if (neighbour(&P, i, j, k, f, &ni, &nj, &nk, &closed)) {
+                    size_t m = cell(&P, ni, nj, nk);
+                    if (!solid[m] && !seen[m]) { seen[m] = 1; queue[tail++] = m; }
+                } else if (!closed && bc[f] == O_DIRICHLET) {
+                    anchored = 1;
+                }
             }
-    while (head < tail) {
-        size_t c = queue[head++];
-        int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((size_t)nx * ny));
-        int ii[6] = { i - 1, i + 1, i, i, i, i };
-        int jj[6] = { j, j, j - 1, j + 1, j, j };
-        int kk[6] = { k, k, k, k, k - 1, k + 1 };
-        for (int f = 0; f < 6; ++f) {
-            if (ii[f] < 0 || ii[f] >= nx || jj[f] < 0 || jj[f] >= ny ||
-                kk[f] < 0 || kk[f] >= nz) continue;
-            size_t m = cell(&P, ii[f], jj[f], kk[f]);
-            if (!solid[m] && !seen[m]) { seen[m] = 1; queue[tail++] = m; }
         }
+        ++regions;
+        if (!anchored) ++loose;
     }
-    int ok = 1;
-    for (size_t c = 0; c < n && ok; ++c)
-        if (!solid[c] && !seen[c]) ok = 0;
     free(seen);
     free(queue);
-    return ok;
+    *unanchored = loose;
+    return regions;
+}
+
+/* 1 if every fluid region touches a Dirichlet face, else 0 (-1: no memory). */
+int oracle_connected(int nx, int ny, int nz, const uint8_t *solid, const int *bc)
+{
+    int loose = 0;
+    int regions = oracle_components(nx, ny, nz, solid, bc, &loose);
+    if (regions < 0) return -1;
+    return loose == 0;
 }
 
 /* out = L p (the operator of Eq. pois as discretised above); 0 on solids. */
@@ -284,7 +321,13 @@ int oracle_pcg(int nx, int ny, int nz, double h, const double *rho,
     if (!(tol > 0.0) || maxit < 0) return O_EINVAL;
     int st = check_problem(&P);
     if (st != O_OK) return st;
-    if (!oracle_connected(nx, ny, nz, solid, bc)) return O_ESINGULAR;
+    int loose = 0;
+    int regions = oracle_components(nx, ny, nz, solid, bc, &loose);
+    if (regions < 0) return O_ENOMEM;
+    /* one region with no Dirichlet face: singular, solved for the mean-free
+     * source; anything else unanchored has no unique answer here */
+    int singular = loose == 1 && regions == 1;
+    if (loose && !singular) return O_ESINGULAR;
 
     size_t n = (size_t)nx * ny * nz;
     double *x = calloc(n, sizeof(double));
@@ -302,6 +345,15 @@ int oracle_pcg(int nx, int ny, int nz, double h, const double *rho,
     for (size_t c = 0; c < n; ++c) {
         b[c] = solid[c] ? 0.0 : -h2 * rhs[c];
         if (!isfinite(b[c])) st = O_EDOMAIN;
+    }
+    if (singular && st == O_OK) {
+        /* remove the source's component along the null vector */
+        double sb = 0.0, nf = 0.0;
+        for (size_t c = 0; c < n; ++c)
+            if (!solid[c]) { sb += b[c]; nf += 1.0; }
+        double mean = sb / nf;
+        for (size_t c = 0; c < n; ++c)
+            if (!solid[c]) b[c] -= mean;
     }
     diag_A(&P, d);
     double nb = sqrt(dot(n, b, b));
@@ -361,6 +413,15 @@ int oracle_pcg(int nx, int ny, int nz, double h, const double *rho,
         }
         relres = sqrt(tt) / nb;
     }
+    if (singular) {
+        /* the solution of zero mean over fluid cells */
+        double sx = 0.0, nf = 0.0;
+        for (size_t c = 0; c < n; ++c)
+            if (!solid[c]) { sx += x[c]; nf += 1.0; }
+        double mean = sx / nf;
+        for (size_t c = 0; c < n; ++c)
+            if (!solid[c]) x[c] -= mean;
+    }
     for (size_t c = 0; c < n; ++c) p_out[c] = solid[c] ? 0.0 : x[c];
     *iters_out = k;
     *relres_out = relres;
@@ -373,7 +434,9 @@ int oracle_pcg(int nx, int ny, int nz, double h, const double *rho,
  *   u_f <- u_f - dt * beta_f * (p_right - p_left) / h,
  * with beta_f as in the operator (0 on Neumann and hull faces, 1/rho_c with
  * the ghost -p_c on Dirichlet faces).  Face arrays are u[nz][ny][nx+1],
- * v[nz][ny+1][nx], w[nz+1][ny][nx].
+ * v[nz][ny+1][nx], w[nz+1][ny][nx].  With periodic x (y) walls face 0 is the
+ * face between the last and the first cell of the row, and face nx (ny) is
+ * written as a copy of it.
  */
 int oracle_project(int nx, int ny, int nz, double h, const double *rho,
                    const uint8_t *solid, const int *bc, double dt,
@@ -389,7 +452,12 @@ int oracle_project(int nx, int ny, int nz, double h, const double *rho,
         for (int j = 0; j < ny; ++j)
             for (int f = 0; f <= nx; ++f) {
                 double *uf = &u[((size_t)k * ny + j) * (nx + 1) + f];
-                if (f == 0) {
+                if (bc[0] == O_PERIODIC && (f == 0 || f == nx)) {
+                    /* face 0 is shared by cells nx-1 and 0; face nx repeats it */
+                    if (f == nx) { *uf = uf[-nx]; continue; }
+                    size_t a = cell(&P, nx - 1, j, k), b = cell(&P, 0, j, k);
+                    if (nx > 1) *uf -= s * face_beta(&P, a, b) * (p[b] - p[a]);
+                } else if (f == 0) {
                     size_t c = cell(&P, 0, j, k);
                     *uf -= s * wall_beta(&P, c, bc[0]) * (p[c] - (-p[c]));
                 } else if (f == nx) {
@@ -405,7 +473,11 @@ int oracle_project(int nx, int ny, int nz, double h, const double *rho,
         for (int f = 0; f <= ny; ++f)
             for (int i = 0; i < nx; ++i) {
                 double *vf = &v[((size_t)k * (ny + 1) + f) * nx + i];
-                if (f == 0) {
+                if (bc[2] == O_PERIODIC && (f == 0 || f == ny)) {
+                    if (f == ny) { *vf = v[((size_t)k * (ny + 1)) * nx + i]; continue; }
+                    size_t a = cell(&P, i, ny - 1, k), b = cell(&P, i, 0, k);
+                    if (ny > 1) *vf -= s * face_beta(&P, a, b) * (p[b] - p[a]);
+                } else if (f == 0) {
                     size_t c = cell(&P, i, 0, k);
                     *vf -= s * wall_beta(&P, c, bc[2]) * (p[c] - (-p[c]));
                 } else if (f == ny) {

@@ -167,7 +167,10 @@ def face_velocities(rng, nx, ny, nz):
 def close_faces(u, v, w, mask, bc):
     """Zero the normal velocity on faces that carry no flux: Neumann walls and
     every face with a solid cell on either side.  Dirichlet (open) walls keep
-    their velocity.  In place."""
+    their velocity.  A periodic pair of walls is one face between the last
+    and the first cell of a row: face 0 holds it (closed when either cell is
+    solid, or when the row has one cell) and the last face repeats it.
+    In place."""
     s = mask.astype(bool)
     # x faces: interior faces 1..nx-1 touch cells i-1 and i
     u[:, :, 1:-1][s[:, :, 1:] | s[:, :, :-1]] = 0.0
@@ -179,6 +182,14 @@ def close_faces(u, v, w, mask, bc):
     w[1:-1, :, :][s[1:, :, :] | s[:-1, :, :]] = 0.0
     w[0, :, :][s[0, :, :]] = 0.0
     w[-1, :, :][s[-1, :, :]] = 0.0
+    if bc[0] == PERIODIC:
+        shut = s[:, :, 0] | s[:, :, -1] if s.shape[2] > 1 else np.ones_like(s[:, :, 0])
+        u[:, :, 0][shut] = 0.0
+        u[:, :, -1] = u[:, :, 0]
+    if bc[2] == PERIODIC:
+        shut = s[:, 0, :] | s[:, -1, :] if s.shape[1] > 1 else np.ones_like(s[:, 0, :])
+        v[:, 0, :][shut] = 0.0
+        v[:, -1, :] = v[:, 0, :]
     if bc[0] == NEUMANN:
         u[:, :, 0] = 0.0
     if bc[1] == NEUMANN:

@@ -25,7 +25,7 @@ class Bound:
 
     def __init__(self, lib):
         for name in ("apply", "pcg", "relres", "project", "divergence",
-                     "connected"):
+                     "connected", "components"):
             setattr(self, name, functools.partial(getattr(oracle, name), lib=lib))
         for name in ("OK", "MAXIT", "EINVAL", "EDOMAIN", "ESINGULAR",
                      "EBREAKDOWN", "EUNSUPPORTED"):
@@ -52,6 +52,9 @@ PIN_RUNS = {
     "banded": lambda o: pins.test_column_reduction_banded(o),
     "divergence": lambda o: pins.test_projection_divergence(o, _F(), 1e-6),
     "termination": lambda o: pins.test_finite_termination(o, 8),
+    "eig_periodic": lambda o: pins.test_eigvec_periodic(o, (9, 14, 7), (2, 1)),
+    "eig_neumann": lambda o: pins.test_eigvec_pure_neumann(o, (7, 9, 6), (0, 3, 1), 37.0),
+    "dense_periodic": lambda o: pins.test_dense_periodic(o, _F(), (9, 6, 7), (2, 2, 0, 0, 0, 0)),
 }
 
 MUTANTS = [
@@ -65,8 +68,8 @@ MUTANTS = [
     ("hull_open", "if (P->solid[a] || P->solid[b]) return 0.0;",
      "if (P->solid[a] && P->solid[b]) return 0.0;"),
     # y- and y+ walls exchanged
-    ("y_walls_swapped", "int jj[6] = { j, j, j - 1, j + 1, j, j };\n    int kk[6] = { k, k, k, k, k - 1, k + 1 };\n    for (int f = 0; f < 6; ++f) {\n        int inside",
-     "int jj[6] = { j, j, j + 1, j - 1, j, j };\n    int kk[6] = { k, k, k, k, k - 1, k + 1 };\n    for (int f = 0; f < 6; ++f) {\n        int inside"),
+    ("y_walls_swapped", "int jj = j + (f == 2 ? -1 : f == 3 ? 1 : 0);",
+     "int jj = j + (f == 2 ? 1 : f == 3 ? -1 : 0);"),
     # conjugate direction dropped: steepest descent
     ("no_conjugation", "pp[c] = z[c] + beta * pp[c];", "pp[c] = z[c];"),
     # grid spacing not squared in the scaled right-hand side
@@ -75,8 +78,15 @@ MUTANTS = [
     ("projection_sign", "*uf -= s * face_beta(&P, a, b) * (p[b] - p[a]);",
      "*uf += s * face_beta(&P, a, b) * (p[b] - p[a]);"),
     # z face coefficient taken from the wrong neighbour
-    ("z_index", "int kk[6] = { k, k, k, k, k - 1, k + 1 };\n    for (int f = 0; f < 6; ++f) {\n        int inside",
-     "int kk[6] = { k, k, k, k, k + 1, k + 1 };\n    for (int f = 0; f < 6; ++f) {\n        int inside"),
+    ("z_index", "int kk = k + (f == 4 ? -1 : f == 5 ? 1 : 0);",
+     "int kk = k + (f == 4 ? 1 : f == 5 ? 1 : 0);"),
+    # periodic wrap lands one cell short
+    ("periodic_wrap", "if (f < 2) ii = (ii + P->nx) % P->nx;",
+     "if (f < 2) ii = (ii + P->nx - 1) % P->nx;"),
+    # singular problem: source mean not removed
+    ("source_mean_kept", "if (!solid[c]) b[c] -= mean;", "if (!solid[c]) b[c] -= 0.0 * mean;"),
+    # singular problem: solution not shifted to zero mean
+    ("solution_mean_kept", "if (!solid[c]) x[c] -= mean;", "if (!solid[c]) x[c] -= 0.0 * mean;"),
 ]
 
 

@@ -310,8 +310,13 @@ def test_failures(orc):
     mask = np.zeros((n, n, n), np.uint8)
     rhs = np.ones((n, n, n))
     h = 1.0 / n
-    assert orc.pcg(rho, mask, (N,) * 6, h, rhs).status == orc.ESINGULAR
-    assert orc.pcg(rho, mask, (2, 2, N, N, N, D), h, rhs).status == orc.EUNSUPPORTED
+    P = 2
+    # one no-flux region: singular; a constant source is all null space
+    r = orc.pcg(rho, mask, (N,) * 6, h, rhs)
+    assert r.status == orc.OK and r.iters == 0 and not r.p.any()
+    assert orc.pcg(rho, mask, (P, P, N, N, N, D), h, rhs).status == orc.OK
+    assert orc.pcg(rho, mask, (N, N, N, N, P, P), h, rhs).status == orc.EUNSUPPORTED
+    assert orc.pcg(rho, mask, (P, N, N, N, N, D), h, rhs).status == orc.EINVAL
     bad = rho.copy(); bad[1, 1, 1] = -1.0
     assert orc.pcg(bad, mask, TANK, h, rhs).status == orc.EDOMAIN
     bad[1, 1, 1] = np.nan
@@ -325,6 +330,9 @@ def test_failures(orc):
     m3[0, 1, 1] = 0
     assert not orc.connected(m3, TANK)
     assert orc.pcg(rho, m3, TANK, h, rhs).status == orc.ESINGULAR
+    # two no-flux regions: the constant on each is a null vector
+    assert orc.components(m3, (N,) * 6) == (2, 2)
+    assert orc.pcg(rho, m3, (N,) * 6, h, rhs).status == orc.ESINGULAR
     # zero source: p = 0 with no iteration
     r = orc.pcg(rho, mask, TANK, h, np.zeros_like(rhs))
     assert r.status == orc.OK and r.iters == 0 and not r.p.any()
@@ -423,3 +431,150 @@ def test_pair_dense(orc, F):
                     c.mask)
     p2 = dense(rho_s, s2)
     assert np.abs(out["p_next"] - p2).max() <= 1e-10 * np.abs(p2).max()
+
+
+# --------------------------------------------------------------------------
+# periodic walls and the singular (no Dirichlet wall) problem
+# --------------------------------------------------------------------------
+
+P_ = 2   # periodic wall kind
+
+
+@pytest.mark.parametrize("shape,modes", [((12, 10, 8), (1, 2)), ((9, 14, 7), (2, 1))])
+def test_eigvec_periodic(orc, shape, modes):
+    """Periodic x and y, p = 0 on the bottom and top faces:
+    cos(2 pi m1 x/Lx + a) cos(2 pi m2 y/Ly + b) sin(pi z/Lz) at cell centres
+    is an exact eigenvector, eigenvalue sum of 2(1 - cos(theta h))/h^2."""
+    nx, ny, nz = shape
+    h, x, y, z = _grid(nx, ny, nz)
+    Lx, Ly, Lz = nx * h, ny * h, nz * h
+    m1, m2 = modes
+    v = (np.cos(2 * math.pi * m1 * x / Lx + 0.3) * np.cos(2 * math.pi * m2 * y / Ly + 1.1)
+         * np.sin(math.pi * z / Lz))
+    lam = (2 * (1 - math.cos(2 * math.pi * m1 * h / Lx)) + 2 * (1 - math.cos(2 * math.pi * m2 * h / Ly))
+           + 2 * (1 - math.cos(math.pi * h / Lz))) / h**2
+    rho = np.ones((nz, ny, nx))
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    bc = (P_, P_, P_, P_, D, D)
+    Lv = orc.apply(rho, mask, bc, h, v)
+    assert np.abs(Lv + lam * v).max() <= 1e-10 * lam
+    r = orc.pcg(rho, mask, bc, h, -lam * v, tol=1e-13)
+    assert r.status == orc.OK
+    assert np.abs(r.p - v).max() <= 1e-9
+
+
+@pytest.mark.parametrize("shape,modes,const", [((10, 8, 12), (1, 0, 2), 0.0),
+                                               ((7, 9, 6), (0, 3, 1), 37.0)])
+def test_eigvec_pure_neumann(orc, shape, modes, const):
+    """No-flux walls only: cos(pi m x/Lx) cos(pi m y/Ly) cos(pi m z/Lz) (not
+    all m zero) is an exact eigenvector of zero mean.  A constant added to
+    the source lies along the null vector and must not change the
+    zero-mean answer."""
+    nx, ny, nz = shape
+    h, x, y, z = _grid(nx, ny, nz)
+    m1, m2, m3 = modes
+    v = (np.cos(math.pi * m1 * x / (nx * h)) * np.cos(math.pi * m2 * y / (ny * h))
+         * np.cos(math.pi * m3 * z / (nz * h)))
+    lam = sum(2 * (1 - math.cos(math.pi * m * h / (n * h))) for m, n in zip(modes, shape)) / h**2
+    rho = np.full((nz, ny, nx), 3.0)
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    bc = (N,) * 6
+    assert orc.components(mask, bc) == (1, 1)
+    r = orc.pcg(rho, mask, bc, h, -lam / 3.0 * v + const, tol=1e-13)
+    assert r.status == orc.OK
+    assert abs(r.p.mean()) <= 1e-12
+    assert np.abs(r.p - v).max() <= 1e-9
+
+
+def _dense_minus_h2L_periodic(rho, mask, bc):
+    """-h^2 L with periodic x/y wrap, assembled cell by cell from the face
+    rules (beta = 2/(rho_c + rho_n), hull faces closed, Dirichlet ghost)."""
+    nz, ny, nx = rho.shape
+    n = rho.size
+    A = np.zeros((n, n))
+    idx = lambda i, j, k: (k * ny + j) * nx + i
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                c = idx(i, j, k)
+                if mask[k, j, i]:
+                    A[c, c] = 1.0
+                    continue
+                for f, (di, dj, dk) in enumerate([(-1, 0, 0), (1, 0, 0), (0, -1, 0),
+                                                  (0, 1, 0), (0, 0, -1), (0, 0, 1)]):
+                    ii, jj, kk = i + di, j + dj, k + dk
+                    if bc[f] == P_:
+                        if (nx if f < 2 else ny) == 1:
+                            continue
+                        ii, jj = ii % nx, jj % ny
+                    if 0 <= ii < nx and 0 <= jj < ny and 0 <= kk < nz:
+                        if mask[kk, jj, ii]:
+                            continue
+                        b = 2.0 / (rho[k, j, i] + rho[kk, jj, ii])
+                        A[c, c] += b
+                        A[c, idx(ii, jj, kk)] -= b
+                    elif bc[f] == D:
+                        A[c, c] += 2.0 / rho[k, j, i]
+    return A
+
+
+@pytest.mark.parametrize("shape,bc", [
+    ((9, 6, 7), (P_, P_, N, N, N, N)),        # strut walls: singular
+    ((8, 5, 6), (P_, P_, N, N, N, D)),        # periodic x with a p = 0 top
+    ((5, 7, 6), (N, N, P_, P_, N, N)),        # periodic y, singular
+])
+def test_dense_periodic(orc, F, shape, bc):
+    """Two-phase wedge field: against a dense solve of the independently
+    assembled matrix (least-squares minimum-norm solution of the fluid block
+    for the singular cases, which is the zero-mean one)."""
+    nx, ny, nz = shape
+    c = F.make_two_phase(nx, ny, nz, surface_seed=41, velocity_seed=42,
+                         wedge=F.Wedge(), bc=bc)
+    fluid = (c.mask == 0).ravel()
+    A = _dense_minus_h2L_periodic(c.rho, c.mask, bc)[np.ix_(fluid, fluid)]
+    b = (-c.h**2 * c.rhs).ravel()[fluid]
+    singular = D not in bc
+    if singular:
+        b = b - b.mean()
+        want = np.linalg.lstsq(A, b, rcond=None)[0]
+        assert abs(want.mean()) <= 1e-10 * np.abs(want).max()
+    else:
+        want = np.linalg.solve(A, b)
+    r = orc.pcg(c.rho, c.mask, bc, c.h, c.rhs, tol=1e-14, maxit=20000)
+    assert r.status in (orc.OK, orc.MAXIT)
+    got = r.p.ravel()[fluid]
+    assert np.abs(got - want).max() <= 1e-9 * np.abs(want).max()
+
+
+def test_periodic_roll_invariance(orc, F):
+    """Rolling every input by s cells along a periodic axis rolls p."""
+    c = F.make_two_phase(12, 8, 10, surface_seed=51, velocity_seed=52, wedge=F.Wedge(),
+                         bc=(P_, P_, N, N, N, D))
+    r0 = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-12)
+    s = 5
+    roll = lambda a: np.roll(a, s, axis=2)
+    r1 = orc.pcg(roll(c.rho), roll(c.mask), c.bc, c.h, roll(c.rhs), tol=1e-12)
+    assert r0.status == r1.status == orc.OK
+    assert np.abs(roll(r0.p) - r1.p).max() <= 1e-9 * np.abs(r0.p).max()
+
+
+@pytest.mark.parametrize("bc", [(P_, P_, N, N, N, N), (N, N, P_, P_, N, D)])
+def test_projection_divergence_periodic(orc, F, bc):
+    """The projection identity with periodic faces: the shared face is
+    corrected once and its repeat copied, and D u_new / ||D u|| is the
+    relative residual."""
+    c = F.make_two_phase(14, 12, 10, surface_seed=61, velocity_seed=62,
+                         wedge=F.Wedge(), bc=bc)
+    assert np.array_equal(c.u[:, :, 0], c.u[:, :, -1]) or bc[0] != P_
+    tol = 1e-10
+    r = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=tol)
+    assert r.status == orc.OK
+    div0 = orc.divergence(c.u, c.v, c.w, c.h)
+    u, v, w = orc.project(c.rho, c.mask, c.bc, c.h, c.dt, r.p, c.u, c.v, c.w)
+    if bc[0] == P_:
+        assert np.array_equal(u[:, :, 0], u[:, :, -1])
+    if bc[2] == P_:
+        assert np.array_equal(v[:, 0, :], v[:, -1, :])
+    div1 = orc.divergence(u, v, w, c.h)
+    ratio = np.linalg.norm(div1) / np.linalg.norm(div0)
+    assert ratio <= tol * 1.01
