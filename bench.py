@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--no-project", action="store_true")
     ap.add_argument("--no-rk2", action="store_true")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the 256^3 wedge and strut single-solve legs")
     ap.add_argument("--rk2-shift", type=float, default=0.025,
                     help="surface phase advance (rad) that gives rho(phi*); "
                          "0.025 moves the 512^3 surface by at most about one cell")
@@ -276,6 +278,12 @@ def main():
                 case.rho, case.mask, case.bc, case.h, case.rhs, pir.cpu().numpy())
         log(f"  {cpu_val:.4f} Gcell-iter/s on {oracle.threads()} threads")
 
+    if not args.no_side:
+        out["wedge256"] = bench_single(F.config_wedge(256, keep_velocity=False), args.tol, dev,
+                                       "256^3 two-phase tank + wedge hull, FP64")
+        out["strut"] = bench_single(F.config_strut(keep_velocity=False), args.tol, dev,
+                                    "strut tank 512x128x128 (NACA 0024, periodic x, "
+                                    "no-flux walls: singular), FP64")
     if not args.no_project:
         out["projection"] = bench_project(case, rho, mask, p64, dev)
         if not args.no_rk2:
@@ -287,6 +295,44 @@ def main():
         out["served"] = bench_serve(args.serve_n)
 
     print(json.dumps(out), flush=True)
+
+
+def bench_single(case, tol, dev, what):
+    """One more single solve (set-up excluded, timed on the host around a
+    synchronised solve after a warm-up solve), its iteration count and the
+    oracle's recomputed residual of the answer."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1410_1942_amd.solver import Solver
+    log(what)
+    rho = torch.from_numpy(case.rho).to(dev)
+    mask = torch.from_numpy(case.mask).to(dev)
+    rhs = torch.from_numpy(case.rhs).to(dev)
+    s = Solver(rho, mask, case.bc, case.h)
+    p, st = s.solve(rhs, tol=tol)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    p, st = s.solve(rhs, p=p, tol=tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    classes = s.density_classes()
+    s.close()
+    pn = p.cpu().numpy()
+    fluid = case.mask == 0
+    ref_rhs = case.rhs.copy()
+    singular = 1 not in case.bc
+    if singular:
+        ref_rhs[fluid] -= ref_rhs[fluid].mean()
+    rr = oracle.relres(case.rho, case.mask, case.bc, case.h, ref_rhs, pn)
+    g = case.ncells * st["iters"] / dt / 1e9
+    log(f"  {st['iters']} iters, {dt*1e3:.1f} ms, {g:.2f} Gcell-iter/s, oracle relres {rr:.3e}")
+    out = {"workload": what, "grid": [case.nx, case.ny, case.nz], "cells": case.ncells,
+           "iters": st["iters"], "ms": round(dt * 1e3, 2), "Gcell_iter_per_s": round(g, 3),
+           "rel_res_oracle": rr, "density_classes": classes}
+    if singular:
+        out["fluid_mean_of_p"] = float(pn[fluid].mean())
+    return out
 
 
 def bench_project(case, rho, mask, p64, dev):

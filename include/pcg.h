@@ -55,16 +55,21 @@ enum {
     PCG_OK = 0,
     PCG_MAXIT = 1,        /* iteration cap reached; p holds the last iterate */
     PCG_PENDING = 2,      /* batched solve still running                     */
+    PCG_SINGULAR = 3,     /* pcg_check_connectivity: one fluid region and no
+                             Dirichlet wall; solvable up to a constant       */
     PCG_EINVAL = -1,      /* null pointer, n < 1, h <= 0, tol <= 0, ...      */
     PCG_EDOMAIN = -2,     /* rho <= 0 or non-finite in a fluid cell, or a
                              non-finite rhs                                  */
-    PCG_ESINGULAR = -3,   /* a fluid region touches no Dirichlet wall        */
+    PCG_ESINGULAR = -3,   /* a fluid region touches no Dirichlet wall while
+                             another region exists                           */
     PCG_EBREAKDOWN = -4,  /* p.Ap <= 0 or non-finite during the iteration    */
     PCG_ENOMEM = -5,      /* workspace / arena too small                     */
     PCG_EBUSY = -6,       /* admission refused: over the memory budget or no
                              free slot; retry after a release                */
     PCG_EHIP = -7,        /* HIP runtime failure (see pcg_last_hip_error)     */
-    PCG_EUNSUPPORTED = -8 /* periodic walls, or a grid above the size limit  */
+    PCG_EUNSUPPORTED = -8 /* periodic z walls, or a grid above the size
+                             limits (n >= 2^31 cells, or nx*ny*24 bytes
+                             above 2^32)                                     */
 };
 
 /* ---- problem description --------------------------------------------- */
@@ -73,6 +78,21 @@ typedef struct {
     double h;           /* cell edge (> 0)                                   */
 } pcg_grid_t;
 
+/*
+ * Wall kinds.  Neumann: no flux (beta = 0).  Dirichlet: p = 0 on the wall
+ * face (mirrored ghost -p_c, coefficient 1/rho_c).  Periodic (the strut case
+ * of Section 3 is periodic along x): both walls of the x or of the y axis,
+ * joining the last and the first cell of every row by an ordinary face; an
+ * axis of one cell carries no flux across it.  Periodic z is unsupported.
+ *
+ * With no Dirichlet wall reaching the fluid (no-flux and periodic walls
+ * only) the operator is singular, its null vector the constant over the
+ * fluid cells.  When all fluid cells form one region the library solves
+ * for the source with its mean over fluid cells removed and returns the
+ * solution of zero mean over fluid cells; the relative residual is measured
+ * against that mean-free source.  Several regions without a Dirichlet wall
+ * (or such a region beside an anchored one) are refused (PCG_ESINGULAR).
+ */
 enum { PCG_BC_NEUMANN = 0, PCG_BC_DIRICHLET = 1, PCG_BC_PERIODIC = 2 };
 
 typedef struct {
@@ -83,9 +103,10 @@ enum { PCG_PREC_FP64 = 0, PCG_PREC_FP32_IR = 1 };
 
 enum {
     PCG_WARM_START = 1,              /* p holds an initial guess on entry    */
-    PCG_SKIP_CONNECTIVITY_CHECK = 2, /* trust that every fluid region touches
-                                        a Dirichlet wall (skips a host flood
-                                        fill of the mask)                    */
+    PCG_SKIP_CONNECTIVITY_CHECK = 2, /* skip the host flood fill of the mask:
+                                        the problem is taken as anchored when
+                                        a Dirichlet wall exists, else as one
+                                        singular region                      */
     PCG_NO_DENSITY_CLASSES = 4       /* always read the FP64/FP32 density per
                                         cell; by default a field with at most
                                         14 distinct fluid densities is coded
@@ -187,12 +208,14 @@ int pcg_solve_ex(pcg_ctx_t *ctx, const double *rhs, double *p, double tol,
                  int32_t maxit, int32_t flags, pcg_stats_t *stats);
 
 /*
- * Host-side check that every connected region of fluid cells (face
- * adjacency, mask == 0) touches a Dirichlet wall, which is when the
- * discrete problem has a unique solution.  host_mask is a HOST u8[n] array
- * (1 = hull; NULL = no hull).  Returns PCG_OK, PCG_ESINGULAR, or PCG_EINVAL
- * / PCG_EUNSUPPORTED for a bad grid or wall kinds.  pcg_setup and
- * pcg_batch_admit run the same check unless PCG_SKIP_CONNECTIVITY_CHECK.
+ * Host-side analysis of the connected regions of fluid cells (face
+ * adjacency, periodic faces included, mask == 0).  host_mask is a HOST u8[n]
+ * array (1 = hull; NULL = no hull).  Returns PCG_OK when every region
+ * touches a Dirichlet wall (unique solution), PCG_SINGULAR for a single
+ * region touching none (solved up to a constant, see the wall kinds),
+ * PCG_ESINGULAR otherwise, or PCG_EINVAL / PCG_EUNSUPPORTED for a bad grid
+ * or wall kinds.  pcg_setup and pcg_batch_admit run the same analysis unless
+ * PCG_SKIP_CONNECTIVITY_CHECK.
  */
 int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
                            const pcg_bc_t *bc);

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # PCGMI_LIB selects another build of the same library (e.g. an install path)
 LIB_PATH = os.environ.get("PCGMI_LIB", os.path.join(PKG, "libpcgmi.so"))
 
-OK, MAXIT, PENDING = 0, 1, 2
+OK, MAXIT, PENDING, SINGULAR = 0, 1, 2, 3
 EINVAL, EDOMAIN, ESINGULAR, EBREAKDOWN, ENOMEM, EBUSY, EHIP, EUNSUPPORTED = \
     -1, -2, -3, -4, -5, -6, -7, -8
 BC_NEUMANN, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2

@@ -218,17 +218,27 @@ int check_grid(const pcg_grid_t *g)
     return PCG_OK;
 }
 
-int check_bc(const pcg_bc_t *bc, int *mask_out)
+// Dirichlet walls as a bit mask (bit f: wall f) and periodic axes (bit 0: x,
+// bit 1: y).  Periodic walls pair up on x or y; periodic z is not supported.
+int check_bc(const pcg_bc_t *bc, int *mask_out, int *per_out = nullptr)
 {
     if (!bc) return PCG_EINVAL;
-    int m = 0;
+    int m = 0, per = 0;
     for (int f = 0; f < 6; ++f) {
         const int k = bc->kind[f];
-        if (k == PCG_BC_PERIODIC) return PCG_EUNSUPPORTED;
-        if (k != PCG_BC_NEUMANN && k != PCG_BC_DIRICHLET) return PCG_EINVAL;
+        if (k != PCG_BC_NEUMANN && k != PCG_BC_DIRICHLET && k != PCG_BC_PERIODIC)
+            return PCG_EINVAL;
         if (k == PCG_BC_DIRICHLET) m |= 1 << f;
     }
+    for (int a = 0; a < 3; ++a) {
+        const bool lo = bc->kind[2 * a] == PCG_BC_PERIODIC;
+        const bool hi = bc->kind[2 * a + 1] == PCG_BC_PERIODIC;
+        if (lo != hi) return PCG_EINVAL;
+        if (lo && a == 2) return PCG_EUNSUPPORTED;
+        if (lo) per |= 1 << a;
+    }
     *mask_out = m;
+    if (per_out) *per_out = per;
     return PCG_OK;
 }
 
@@ -243,19 +253,28 @@ int check_opts(const pcg_opts_t *o)
     return PCG_OK;
 }
 
-// Every fluid region must reach a Dirichlet wall.  Flood fill over x-runs
-// of fluid cells: one scan of the mask splits every row into maximal runs,
-// then a breadth-first search moves between runs of neighbouring rows (y and
-// z) that overlap in x.  Work is linear in the cells for the scan and in
+// Connected fluid regions and how many of them touch no Dirichlet wall.
+// Flood fill over x-runs of fluid cells: one scan of the mask splits every
+// row into maximal runs, then a breadth-first search per region moves
+// between runs of neighbouring rows (y and z) that overlap in x, and across
+// periodic walls (the first and last run of a row for x, the first and last
+// row of a plane for y).  Work is linear in the cells for the scan and in
 // the runs for the search.
-bool fluid_reaches_dirichlet(const std::vector<uint8_t> &solid, int nx, int ny,
-                             int nz, int bcmask)
+struct FluidRegions {
+    int64_t regions = 0;
+    int64_t unanchored = 0;
+};
+
+FluidRegions fluid_regions(const std::vector<uint8_t> &solid, int nx, int ny, int nz,
+                           int bcmask, int permask)
 {
     const int64_t nrows = (int64_t)ny * nz;
     std::vector<int64_t> row_start(nrows + 1, 0);
     std::vector<int32_t> ra, rb;  // run [ra, rb) in x
+    std::vector<int64_t> run_row;
     ra.reserve(nrows * 2);
     rb.reserve(nrows * 2);
+    run_row.reserve(nrows * 2);
     for (int64_t r = 0; r < nrows; ++r) {
         row_start[r] = (int64_t)ra.size();
         const uint8_t *m = solid.data() + r * nx;
@@ -267,45 +286,61 @@ bool fluid_reaches_dirichlet(const std::vector<uint8_t> &solid, int nx, int ny,
             while (i < nx && !m[i]) ++i;
             ra.push_back(a);
             rb.push_back(i);
+            run_row.push_back(r);
         }
     }
     row_start[nrows] = (int64_t)ra.size();
     const int64_t nruns = (int64_t)ra.size();
-    if (nruns == 0) return true;
+    const bool perx = (permask & 1) && nx > 1, pery = (permask & 2) && ny > 1;
+    FluidRegions out;
     std::vector<uint8_t> seen(nruns, 0);
     std::vector<int64_t> queue;
     queue.reserve(1024);
     auto push = [&](int64_t u) {
         if (!seen[u]) { seen[u] = 1; queue.push_back(u); }
     };
-    for (int k = 0; k < nz; ++k)
-        for (int j = 0; j < ny; ++j) {
-            const int64_t r = (int64_t)k * ny + j;
-            const bool whole = ((bcmask & 4) && j == 0) || ((bcmask & 8) && j == ny - 1) ||
-                               ((bcmask & 16) && k == 0) || ((bcmask & 32) && k == nz - 1);
-            for (int64_t u = row_start[r]; u < row_start[r + 1]; ++u)
-                if (whole || ((bcmask & 1) && ra[u] == 0) || ((bcmask & 2) && rb[u] == nx))
-                    push(u);
+    for (int64_t u0 = 0; u0 < nruns; ++u0) {
+        if (seen[u0]) continue;
+        queue.clear();
+        push(u0);
+        bool anchored = false;
+        for (size_t h = 0; h < queue.size(); ++h) {
+            const int64_t u = queue[h];
+            const int64_t r = run_row[u];
+            const int j = (int)(r % ny), k = (int)(r / ny);
+            anchored = anchored || ((bcmask & 4) && j == 0) || ((bcmask & 8) && j == ny - 1) ||
+                       ((bcmask & 16) && k == 0) || ((bcmask & 32) && k == nz - 1) ||
+                       ((bcmask & 1) && ra[u] == 0) || ((bcmask & 2) && rb[u] == nx);
+            int64_t nb[4] = { j > 0 ? r - 1 : (pery ? r + ny - 1 : -1),
+                              j < ny - 1 ? r + 1 : (pery ? r - (ny - 1) : -1),
+                              k > 0 ? r - ny : -1, k < nz - 1 ? r + ny : -1 };
+            for (int e = 0; e < 4; ++e) {
+                if (nb[e] < 0) continue;
+                const int64_t b0 = row_start[nb[e]], b1 = row_start[nb[e] + 1];
+                // first run of the neighbouring row ending after ra[u]
+                int64_t v = std::upper_bound(rb.begin() + b0, rb.begin() + b1, ra[u]) - rb.begin();
+                for (; v < b1 && ra[v] < rb[u]; ++v) push(v);
+            }
+            if (perx) {
+                const int64_t f0 = row_start[r], f1 = row_start[r + 1] - 1;
+                if (ra[u] == 0 && rb[f1] == nx) push(f1);
+                if (rb[u] == nx && ra[f0] == 0) push(f0);
+            }
         }
-    auto row_of = [&](int64_t u) {
-        return (int64_t)(std::upper_bound(row_start.begin(), row_start.end(), u) -
-                         row_start.begin()) - 1;
-    };
-    for (size_t h = 0; h < queue.size(); ++h) {
-        const int64_t u = queue[h];
-        const int64_t r = row_of(u);
-        const int j = (int)(r % ny), k = (int)(r / ny);
-        const int64_t nb[4] = { j > 0 ? r - 1 : -1, j < ny - 1 ? r + 1 : -1,
-                                k > 0 ? r - ny : -1, k < nz - 1 ? r + ny : -1 };
-        for (int e = 0; e < 4; ++e) {
-            if (nb[e] < 0) continue;
-            const int64_t b0 = row_start[nb[e]], b1 = row_start[nb[e] + 1];
-            // first run of the neighbouring row ending after ra[u]
-            int64_t v = std::upper_bound(rb.begin() + b0, rb.begin() + b1, ra[u]) - rb.begin();
-            for (; v < b1 && ra[v] < rb[u]; ++v) push(v);
-        }
+        ++out.regions;
+        if (!anchored) ++out.unanchored;
     }
-    return (int64_t)queue.size() == nruns;
+    return out;
+}
+
+// Solvability of a wall and hull layout: 0 when every fluid region touches
+// a Dirichlet wall, 1 for a single region touching none (singular: the
+// constant is the null vector), PCG_ESINGULAR otherwise.
+int classify_regions(const FluidRegions &f)
+{
+    if (f.unanchored == 0) return 0;
+    if (f.regions == 1) return 1;
+    return PCG_ESINGULAR;
 }
 
 struct SlotHost {
@@ -315,6 +350,8 @@ struct SlotHost {
     bool finished = false;  // completion observed on the host
     Geometry geo{};
     int bcmask = 0;
+    int permask = 0;
+    bool singular = false;   // no Dirichlet wall reaches the fluid
     double h2 = 0.0;
     size_t off = 0, bytes = 0;
     double *rho64 = nullptr;
@@ -451,6 +488,7 @@ struct Engine {
         std::memset(&d, 0, sizeof(Slot));
         d.nx = S.geo.nx; d.ny = S.geo.ny; d.nz = S.geo.nz;
         d.bcmask = S.bcmask;
+        d.permask = S.permask;
         d.h2 = S.h2;
         d.rho64 = S.rho64;
         d.cls = S.classes ? S.cls : nullptr;
@@ -475,8 +513,8 @@ struct Engine {
     {
         int st = check_grid(grid_);
         if (st) return st;
-        int bm = 0;
-        st = check_bc(bc, &bm);
+        int bm = 0, per = 0;
+        st = check_bc(bc, &bm, &per);
         if (st) return st;
         if (!rho) return PCG_EINVAL;
         int id = -1;
@@ -492,6 +530,7 @@ struct Engine {
         S = SlotHost{};
         S.geo = geo;
         S.bcmask = bm;
+        S.permask = per;
         S.h2 = grid_->h * grid_->h;
         S.off = off;
         S.bytes = need;
@@ -529,18 +568,17 @@ struct Engine {
         S.nclasses = 0;
         if (view_id >= 0 && &slots[view_id] == &S) view_id = -1;
         const Geometry &geo = S.geo;
-        // connectivity: every fluid region must touch a Dirichlet wall
-        if (!(flags & PCG_SKIP_CONNECTIVITY_CHECK)) {
-            bool ok;
-            if (mask) {
-                std::vector<uint8_t> h((size_t)geo.n);
-                hipError_t e = hipMemcpy(h.data(), mask, (size_t)geo.n, hipMemcpyDeviceToHost);
-                if (e != hipSuccess) return hip_fail(e, "mask copy");
-                ok = fluid_reaches_dirichlet(h, geo.nx, geo.ny, geo.nz, S.bcmask);
-            } else {
-                ok = S.bcmask != 0;
-            }
-            if (!ok) return PCG_ESINGULAR;
+        // connectivity: every fluid region touches a Dirichlet wall, or a
+        // single region touches none (singular); unchecked, the walls decide
+        S.singular = S.bcmask == 0;
+        if (!(flags & PCG_SKIP_CONNECTIVITY_CHECK) && mask) {
+            std::vector<uint8_t> h((size_t)geo.n);
+            hipError_t e = hipMemcpy(h.data(), mask, (size_t)geo.n, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "mask copy");
+            const int kind = classify_regions(
+                fluid_regions(h, geo.nx, geo.ny, geo.nz, S.bcmask, S.permask));
+            if (kind < 0) return kind;
+            S.singular = kind == 1;
         }
         const bool want_classes = !(flags & PCG_NO_DENSITY_CLASSES);
         *h_bad = 0;
@@ -641,6 +679,11 @@ struct Engine {
         SlotState &h = h_states[id];
         std::memset(&h, 0, sizeof(SlotState));
         h.phase = prec == PCG_PREC_FP64 ? K1_INIT64 : K1_IR_INIT;
+        if (S.singular) {   // the source's fluid mean first
+            h.after = h.phase;
+            h.phase = K1_MEAN_B;
+            h.singular = 1;
+        }
         h.status = PCG_PENDING;
         h.tol = tol;
         h.maxit = maxit;
@@ -679,6 +722,7 @@ struct Engine {
             std::memset(&d, 0, sizeof(Slot));
             d.nx = S.geo.nx; d.ny = S.geo.ny; d.nz = S.geo.nz;
             d.bcmask = S.bcmask;
+        d.permask = S.permask;
             d.plane_tiles = S.geo.plane_tiles;
             d.ztiles = S.geo.ztiles;
             d.tz = S.geo.tz;
@@ -976,14 +1020,14 @@ int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
 {
     int st = check_grid(grid);
     if (st) return st;
-    int bm = 0;
-    st = check_bc(bc, &bm);
+    int bm = 0, per = 0;
+    st = check_bc(bc, &bm, &per);
     if (st) return st;
-    if (!host_mask) return bm ? PCG_OK : PCG_ESINGULAR;
+    if (!host_mask) return bm ? PCG_OK : PCG_SINGULAR;   // one region
     const size_t n = (size_t)grid->nx * grid->ny * grid->nz;
     std::vector<uint8_t> m(host_mask, host_mask + n);
-    return fluid_reaches_dirichlet(m, grid->nx, grid->ny, grid->nz, bm) ? PCG_OK
-                                                                        : PCG_ESINGULAR;
+    const int kind = classify_regions(fluid_regions(m, grid->nx, grid->ny, grid->nz, bm, per));
+    return kind < 0 ? kind : kind == 1 ? PCG_SINGULAR : PCG_OK;
 }
 
 int pcg_set_tile_rules(int32_t precision, int32_t for_batches, int32_t n,
@@ -1129,14 +1173,15 @@ const char *pcg_strerror(int code)
     case PCG_OK: return "ok";
     case PCG_MAXIT: return "iteration limit reached";
     case PCG_PENDING: return "solve still running";
+    case PCG_SINGULAR: return "one fluid region and no Dirichlet wall: solvable up to a constant";
     case PCG_EINVAL: return "invalid argument";
     case PCG_EDOMAIN: return "density not positive and finite in a fluid cell, or non-finite source";
-    case PCG_ESINGULAR: return "a fluid region touches no Dirichlet wall";
+    case PCG_ESINGULAR: return "a fluid region touches no Dirichlet wall and is not the only one";
     case PCG_EBREAKDOWN: return "conjugate-gradient breakdown (p.Ap <= 0 or not finite)";
     case PCG_ENOMEM: return "workspace or arena too small";
     case PCG_EBUSY: return "admission refused: no free slot or not enough arena memory";
     case PCG_EHIP: return "HIP runtime error";
-    case PCG_EUNSUPPORTED: return "unsupported: periodic walls or grid too large";
+    case PCG_EUNSUPPORTED: return "unsupported: periodic z walls or grid too large";
     default: return "unknown status";
     }
 }

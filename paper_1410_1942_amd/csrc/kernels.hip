@@ -180,8 +180,9 @@ struct ClsCoef {
 };
 
 // Per-thread neighbour description for the x/y faces of a column: offset to
-// the neighbour (0 at a wall, so the load stays in bounds) and the key
-// standing in for a missing neighbour.
+// the neighbour (across a periodic wall, the cell at the other end; 0 at
+// any other wall, so the load stays in bounds) and the key standing in for
+// a missing neighbour.
 template <typename Key>
 struct Nbr {
     int oxm, oxp, oym, oyp;
@@ -195,14 +196,18 @@ __device__ __forceinline__ Nbr<typename C::Key> make_nbr(const TileCtx &t,
 {
     Nbr<typename C::Key> n;
     const int bm = S.bcmask;
-    n.hxm = t.i > 0;
-    n.hxp = t.i < S.nx - 1;
-    n.hym = t.j > 0;
-    n.hyp = t.j < S.ny - 1;
-    n.oxm = n.hxm ? -1 : 0;
-    n.oxp = n.hxp ? 1 : 0;
-    n.oym = n.hym ? -S.nx : 0;
-    n.oyp = n.hyp ? S.nx : 0;
+    // periodic axes wrap to the other end of the row (x) or plane (y); an
+    // axis of one cell keeps the wall form with no flux (the wall key of a
+    // periodic wall is the Neumann one)
+    const bool px = (S.permask & 1) && S.nx > 1, py = (S.permask & 2) && S.ny > 1;
+    n.hxm = t.i > 0 || px;
+    n.hxp = t.i < S.nx - 1 || px;
+    n.hym = t.j > 0 || py;
+    n.hyp = t.j < S.ny - 1 || py;
+    n.oxm = t.i > 0 ? -1 : (px ? S.nx - 1 : 0);
+    n.oxp = t.i < S.nx - 1 ? 1 : (px ? -(S.nx - 1) : 0);
+    n.oym = t.j > 0 ? -S.nx : (py ? (S.ny - 1) * S.nx : 0);
+    n.oyp = t.j < S.ny - 1 ? S.nx : (py ? -(S.ny - 1) * S.nx : 0);
     n.wxm = (bm & 1) ? cf.dirichlet() : cf.neumann();
     n.wxp = (bm & 2) ? cf.dirichlet() : cf.neumann();
     n.wym = (bm & 4) ? cf.dirichlet() : cf.neumann();
@@ -305,7 +310,7 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
         double xzp = 0.0;
         if (!top) { kzp = cf.load(c + P); if (warm) xzp = xv(c + P); }
         const bool solid = cf.solid(kc);
-        const double b = solid ? 0.0 : -S.h2 * rhs[c];
+        const double b = solid ? 0.0 : -S.h2 * rhs[c] - st.bshift;
         double r, dg;
         if (warm) {
             double q;
@@ -611,7 +616,7 @@ __device__ void body_check64(const Slot &S, const SlotState &st, int64_t lt,
         double q, dg;
         apply_cell<double>(xv, cf, c, n, vc, kc, vzm, kzm, vzp, kzp, q, dg);
         if (!cf.solid(kc)) {
-            const double r = -S.h2 * rhs[c] - q;
+            const double r = (-S.h2 * rhs[c] - st.bshift) - q;
             a += r * r;
         }
         vzm = vc; kzm = kc;
@@ -642,7 +647,7 @@ __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
         d[c] = 0.0f;
         pa[c] = 0.0f;
         pb[c] = 0.0f;
-        const double b = solid ? 0.0 : -S.h2 * rhs[c];
+        const double b = solid ? 0.0 : -S.h2 * rhs[c] - st.bshift;
         a += b * b;
     }
     acc[0] += a;
@@ -687,7 +692,7 @@ __device__ void body_ir_resid(const Slot &S, const SlotState &st, int64_t lt,
         double q, dg;
         apply_cell<double>(xe, cf, c, n, vc, kc, vzm, kzm, vzp, kzp, q, dg);
         const bool solid = cf.solid(kc);
-        const double r = solid ? 0.0 : (-S.h2 * rhs[c] - q);
+        const double r = solid ? 0.0 : ((-S.h2 * rhs[c] - st.bshift) - q);
         const float dg32 = diag_cell<float>(cf32, c, nf, fc, fzm, fzp);
         const float z32 = dg32 > 0.0f ? (float)((scale * r) / (double)dg32) : 0.0f;
         z[c] = z32;
@@ -728,6 +733,55 @@ __device__ void body_zero_x(const Slot &S, const SlotState &st, int64_t lt,
     GLB double *__restrict__ x = gp(S.x);
     int64_t c = (int64_t)t.k0 * t.P + t.q;
     for (int k = t.k0; k < t.k1; ++k, c += t.P) x[c] = 0.0;
+}
+
+// Singular problems (no Dirichlet wall: the constant over the fluid is the
+// null vector).  K1_MEAN_B: acc = [sum of b, count] over fluid cells, so
+// the source can be made mean-free; K1_MEAN_X: acc = [sum of x] over fluid
+// cells; K2_SUB_X: x -= that mean, leaving the zero-mean solution.
+template <class C>
+__device__ void body_mean_b(const Slot &S, const SlotState &st, int64_t lt,
+                            const C &cf, double (&acc)[3])
+{
+    const TileCtx t = tile_ctx(S, lt);
+    if (!t.active) return;
+    const GLB double *__restrict__ rhs = gp(S.rhs);
+    double a = 0.0, m = 0.0;
+    int64_t c = (int64_t)t.k0 * t.P + t.q;
+    for (int k = t.k0; k < t.k1; ++k, c += t.P) {
+        if (cf.solid(cf.load(c))) continue;
+        a += -S.h2 * rhs[c];
+        m += 1.0;
+    }
+    acc[0] += a;
+    acc[1] += m;
+}
+
+template <class C>
+__device__ void body_mean_x(const Slot &S, const SlotState &st, int64_t lt,
+                            const C &cf, double (&acc)[3])
+{
+    const TileCtx t = tile_ctx(S, lt);
+    if (!t.active) return;
+    const GLB double *__restrict__ x = gp((const double *)S.x);
+    double a = 0.0;
+    int64_t c = (int64_t)t.k0 * t.P + t.q;
+    for (int k = t.k0; k < t.k1; ++k, c += t.P)
+        if (!cf.solid(cf.load(c))) a += x[c];
+    acc[0] += a;
+}
+
+template <class C>
+__device__ void body_sub_x(const Slot &S, const SlotState &st, int64_t lt,
+                           const C &cf, double (&acc)[3])
+{
+    const TileCtx t = tile_ctx(S, lt);
+    if (!t.active) return;
+    GLB double *__restrict__ x = gp(S.x);
+    const double m = st.xshift;
+    int64_t c = (int64_t)t.k0 * t.P + t.q;
+    for (int k = t.k0; k < t.k1; ++k, c += t.P)
+        if (!cf.solid(cf.load(c))) x[c] -= m;
 }
 
 // ------------------------------------------------------------------------
@@ -788,11 +842,28 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
     }
     case K1_CHECK64: {
         st.rr_true = tot[0];
-        if (tot[0] <= st.tol2) { st.phase = K2_NONE; st.after = PH_DONE; st.status = PCG_OK; }
-        else if (st.iter >= st.maxit) { st.phase = K2_NONE; st.after = PH_DONE; st.status = PCG_MAXIT; }
+        const int end = st.singular ? K1_MEAN_X : PH_DONE;
+        if (tot[0] <= st.tol2) { st.phase = K2_NONE; st.after = end; st.status = PCG_OK; }
+        else if (st.iter >= st.maxit) { st.phase = K2_NONE; st.after = end; st.status = PCG_MAXIT; }
         else { st.phase = K2_NONE; st.after = K1_CG_A; }
         break;
     }
+    case K1_MEAN_B: {
+        st.nfluid = tot[1];
+        st.bshift = tot[1] > 0.0 ? tot[0] / tot[1] : 0.0;
+        if (!isfinite(st.bshift)) { finish(st, PCG_EDOMAIN); break; }
+        st.phase = K2_NONE;   // then the initialisation held in `after`
+        break;
+    }
+    case K1_MEAN_X: {
+        st.xshift = st.nfluid > 0.0 ? tot[0] / st.nfluid : 0.0;
+        st.phase = K2_SUB_X;
+        break;
+    }
+    case K2_SUB_X:
+        st.phase = PH_DONE;
+        if (st.status == PCG_PENDING) st.status = PCG_OK;
+        break;
     case K2_NONE:
     case K2_ZERO_X:
         if (st.after == PH_DONE) {
@@ -840,7 +911,7 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         break;
     }
     case K2_IR_UPDATE: {
-        if (st.final_upd) { st.phase = PH_DONE; break; }
+        if (st.final_upd) { st.phase = st.singular ? K1_MEAN_X : PH_DONE; break; }
         st.upd_s = 1.0 / st.scale;
         st.first = 1;
         st.inner_iter = 0;
@@ -907,7 +978,9 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
     const ClsCoef<double> c64{ gp(S.cls), tab64 };
     if (FAMILY == PCG_PREC_FP64) {
         if (WHICH == 0) {
-            if (S.cls) {
+            if (ph == K1_MEAN_B) body_mean_b(S, st, lt, r64, acc);
+            else if (ph == K1_MEAN_X) body_mean_x(S, st, lt, r64, acc);
+            else if (S.cls) {
                 if (ph == K1_INIT64) body_init64(S, st, lt, c64, acc);
                 else if (ph == K1_CHECK64) body_check64(S, st, lt, c64, acc);
             } else {
@@ -924,12 +997,15 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
                 if (MODE) body_passB<double, double>(S, st, lt, c64, acc);
                 else body_passB<double, double>(S, st, lt, r64, acc);
             } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
+            else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);
         }
     } else {
         const RhoCoef<float> r32{ gp(S.rho32) };
         const ClsCoef<float> c32{ gp(S.cls), tab32 };
         if (WHICH == 0) {
-            if (S.cls) {
+            if (ph == K1_MEAN_B) body_mean_b(S, st, lt, r64, acc);
+            else if (ph == K1_MEAN_X) body_mean_x(S, st, lt, r64, acc);
+            else if (S.cls) {
                 if (ph == K1_IR_INIT) body_ir_init(S, st, lt, c64, acc);
                 else if (ph == K1_IR_RESID) body_ir_resid(S, st, lt, c64, c32, acc);
             } else {
@@ -947,6 +1023,7 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
                 else body_passB<float, float>(S, st, lt, r32, acc);
             } else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);
             else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
+            else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);
         }
     }
 }
@@ -956,7 +1033,7 @@ __device__ __forceinline__ bool serves(const Slot &S, int ph)
 {
     if (WHICH == 0)
         return ph == K1_INIT64 || ph == K1_CHECK64 || ph == K1_IR_INIT ||
-               ph == K1_IR_RESID;
+               ph == K1_IR_RESID || ph == K1_MEAN_B || ph == K1_MEAN_X;
     if ((S.cls != nullptr) != (MODE != 0)) return false;
     if (WHICH == 1) return ph == K1_CG_A || ph == K1_IR_A;
     return ph >= 11 && ph <= 19;
@@ -1116,7 +1193,9 @@ k_classify(const double *__restrict__ r64, uint8_t *__restrict__ cls, int64_t n,
 // (Neumann, hull: beta = 0).  wt = 1 without b is the first-stage update
 // u* = u^k - dt grad(P*)/rho; wt = 1/2 with b = u^k is the second-stage
 // average.  Face arrays are u[nz][ny][nx+1], v[nz][ny+1][nx], w[nz+1][ny][nx];
-// out may be a (each face is read and written by one thread).
+// out may be a (each face is read and written by one thread).  On a periodic
+// axis face 0 is the face between the last and the first cell (corrected by
+// the first cell) and the last face is written as its copy.
 struct FaceSet {
     const double *u, *v, *w;
 };
@@ -1141,6 +1220,7 @@ __device__ void project_cells(const Slot &S, const C &cf, const double *__restri
     const int nx = S.nx, ny = S.ny, nz = S.nz;
     const int64_t P = (int64_t)nx * ny, n = P * nz;
     const int bm = S.bcmask;
+    const bool perx = S.permask & 1, pery = S.permask & 2;
     const GLB double *__restrict__ pg = gp(p);
     GLB double *ou = gp(o.u);
     GLB double *ov = gp(o.v);
@@ -1155,13 +1235,31 @@ __device__ void project_cells(const Slot &S, const C &cf, const double *__restri
         const int64_t fu = ((int64_t)k * ny + j) * (nx + 1) + i;
         const int64_t fv = ((int64_t)k * (ny + 1) + j) * nx + i;
         const int64_t fw = c;
-        if (i > 0) ou[fu] = wt * (face_in<ADD>(a, b, 0, fu) - s * cf.beta(cf.load(c - 1), kc) * (pc - pg[c - 1]));
-        else ou[fu] = wt * (face_in<ADD>(a, b, 0, fu) - s * cf.beta(kc, (bm & 1) ? cf.dirichlet() : cf.neumann()) * pc);
-        if (i == nx - 1)
+        if (i > 0) {
+            ou[fu] = wt * (face_in<ADD>(a, b, 0, fu) - s * cf.beta(cf.load(c - 1), kc) * (pc - pg[c - 1]));
+        } else if (perx) {   // shared face with the row's last cell, and its repeat
+            const int64_t m = c + nx - 1;
+            const double u0 = nx > 1 ? wt * (face_in<ADD>(a, b, 0, fu) - s * cf.beta(cf.load(m), kc) * (pc - pg[m]))
+                                     : wt * face_in<ADD>(a, b, 0, fu);
+            ou[fu] = u0;
+            ou[fu + nx] = u0;
+        } else {
+            ou[fu] = wt * (face_in<ADD>(a, b, 0, fu) - s * cf.beta(kc, (bm & 1) ? cf.dirichlet() : cf.neumann()) * pc);
+        }
+        if (i == nx - 1 && !perx)
             ou[fu + 1] = wt * (face_in<ADD>(a, b, 0, fu + 1) + s * cf.beta(kc, (bm & 2) ? cf.dirichlet() : cf.neumann()) * pc);
-        if (j > 0) ov[fv] = wt * (face_in<ADD>(a, b, 1, fv) - s * cf.beta(cf.load(c - nx), kc) * (pc - pg[c - nx]));
-        else ov[fv] = wt * (face_in<ADD>(a, b, 1, fv) - s * cf.beta(kc, (bm & 4) ? cf.dirichlet() : cf.neumann()) * pc);
-        if (j == ny - 1)
+        if (j > 0) {
+            ov[fv] = wt * (face_in<ADD>(a, b, 1, fv) - s * cf.beta(cf.load(c - nx), kc) * (pc - pg[c - nx]));
+        } else if (pery) {
+            const int64_t m = c + (int64_t)(ny - 1) * nx;
+            const double v0 = ny > 1 ? wt * (face_in<ADD>(a, b, 1, fv) - s * cf.beta(cf.load(m), kc) * (pc - pg[m]))
+                                     : wt * face_in<ADD>(a, b, 1, fv);
+            ov[fv] = v0;
+            ov[fv + (int64_t)ny * nx] = v0;
+        } else {
+            ov[fv] = wt * (face_in<ADD>(a, b, 1, fv) - s * cf.beta(kc, (bm & 4) ? cf.dirichlet() : cf.neumann()) * pc);
+        }
+        if (j == ny - 1 && !pery)
             ov[fv + nx] = wt * (face_in<ADD>(a, b, 1, fv + nx) + s * cf.beta(kc, (bm & 8) ? cf.dirichlet() : cf.neumann()) * pc);
         if (k > 0) ow[fw] = wt * (face_in<ADD>(a, b, 2, fw) - s * cf.beta(cf.load(c - P), kc) * (pc - pg[c - P]));
         else ow[fw] = wt * (face_in<ADD>(a, b, 2, fw) - s * cf.beta(kc, (bm & 16) ? cf.dirichlet() : cf.neumann()) * pc);
@@ -1196,13 +1294,16 @@ k_project(const Slot *__restrict__ slot, const double *__restrict__ p, double s,
 // Source of the pressure equation from face velocities:
 // rhs_c = ((du + dv) + dw) / h / dt with du = U_{i+1/2} - U_{i-1/2} (and so
 // on), U = a [+ b], in fluid cells; 0 in hull cells.  With b the second-stage
-// source div(u* + u^k)/dt, without it the first-stage div(u^k)/dt.
+// source div(u* + u^k)/dt, without it the first-stage div(u^k)/dt.  On a
+// periodic axis the high face of the last cell is face 0 (the last face of
+// the array is not read).
 template <bool ADD>
 __device__ void rhs_cells(const Slot &S, double h, double dt, FaceSet a, FaceSet b,
                           double *__restrict__ rhs)
 {
     const int nx = S.nx, ny = S.ny, nz = S.nz;
     const int64_t P = (int64_t)nx * ny, n = P * nz;
+    const bool perx = S.permask & 1, pery = S.permask & 2;
     const RhoCoef<double> cf{ gp(S.rho64) };
     GLB double *out = gp(rhs);
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
@@ -1213,8 +1314,11 @@ __device__ void rhs_cells(const Slot &S, double h, double dt, FaceSet a, FaceSet
         const int k = (int)(c / P);
         const int64_t fu = ((int64_t)k * ny + j) * (nx + 1) + i;
         const int64_t fv = ((int64_t)k * (ny + 1) + j) * nx + i;
-        const double du = face_in<ADD>(a, b, 0, fu + 1) - face_in<ADD>(a, b, 0, fu);
-        const double dv = face_in<ADD>(a, b, 1, fv + nx) - face_in<ADD>(a, b, 1, fv);
+        // the high face of a periodic row's last cell is the row's face 0
+        const int64_t fu1 = (perx && i == nx - 1) ? fu - i : fu + 1;
+        const int64_t fv1 = (pery && j == ny - 1) ? fv - (int64_t)j * nx : fv + nx;
+        const double du = face_in<ADD>(a, b, 0, fu1) - face_in<ADD>(a, b, 0, fu);
+        const double dv = face_in<ADD>(a, b, 1, fv1) - face_in<ADD>(a, b, 1, fv);
         const double dw = face_in<ADD>(a, b, 2, c + P) - face_in<ADD>(a, b, 2, c);
         out[c] = ((du + dv) + dw) / h / dt;
     }
@@ -1229,8 +1333,9 @@ k_rhs(const Slot *__restrict__ slot, double h, double dt, FaceSet a, FaceSet b,
 }
 
 // (D u)_c = (u_{i+1/2} - u_{i-1/2} + v_{j+1/2} - v_{j-1/2} + w_{k+1/2} -
-// w_{k-1/2}) / h over fluid cells: per-workgroup sum of squares and maximum
-// magnitude, combined on the host in workgroup order.
+// w_{k-1/2}) / h over fluid cells (periodic axes as in the source kernel):
+// per-workgroup sum of squares and maximum magnitude, combined on the host in
+// workgroup order.
 __global__ void __launch_bounds__(256)
 k_divnorm(const Slot *__restrict__ slot, double inv_h, const double *__restrict__ u,
           const double *__restrict__ v, const double *__restrict__ w,
@@ -1241,6 +1346,7 @@ k_divnorm(const Slot *__restrict__ slot, double inv_h, const double *__restrict_
     const int nx = S.nx, ny = S.ny, nz = S.nz;
     const int64_t P = (int64_t)nx * ny, n = P * nz;
     const RhoCoef<double> cf{ gp(S.rho64) };
+    const bool perx = S.permask & 1, pery = S.permask & 2;
     double ss = 0.0, mx = 0.0;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n;
          c += (int64_t)gridDim.x * blockDim.x) {
@@ -1250,7 +1356,9 @@ k_divnorm(const Slot *__restrict__ slot, double inv_h, const double *__restrict_
         const int k = (int)(c / P);
         const int64_t fu = ((int64_t)k * ny + j) * (nx + 1) + i;
         const int64_t fv = ((int64_t)k * (ny + 1) + j) * nx + i;
-        const double d = ((u[fu + 1] - u[fu]) + (v[fv + nx] - v[fv]) + (w[c + P] - w[c])) * inv_h;
+        const int64_t fu1 = (perx && i == nx - 1) ? fu - i : fu + 1;
+        const int64_t fv1 = (pery && j == ny - 1) ? fv - (int64_t)j * nx : fv + nx;
+        const double d = ((u[fu1] - u[fu]) + (v[fv1] - v[fv]) + (w[c + P] - w[c])) * inv_h;
         ss += d * d;
         mx = fmax(mx, fabs(d));
     }

@@ -31,12 +31,15 @@ enum Phase : int32_t {
     K1_IR_INIT = 4,    // ||b||, x = 0 (or solids zeroed), d = 0
     K1_IR_RESID = 5,   // r = b - A (x + s d) in FP64, z32 = D32^-1 (scale r)
     K1_IR_A = 6,       // FP32 p = z + beta p ; p.Ap (FP64 sum)
+    K1_MEAN_B = 7,     // singular problem: sum of b and count of fluid cells
+    K1_MEAN_X = 8,     // singular problem: sum of x over fluid cells
     // K2 actions (second launch of an iteration)
     K2_NONE = 11,      // nothing; then the K1 action in `after`
     K2_CG_B = 12,      // q = A p, x += alpha p, z -= alpha D^-1 q ; r.z, r.r
     K2_IR_B = 13,      // FP32 d += alpha p, z -= alpha D^-1 q ; r.z, r.r (FP64)
     K2_IR_UPDATE = 14, // x += s d, d = 0
     K2_ZERO_X = 15,    // x = 0 (zero source with a warm start)
+    K2_SUB_X = 16,     // singular problem: x -= its fluid mean
     PH_DONE = 20
 };
 
@@ -55,6 +58,9 @@ struct alignas(128) SlotState {
     double upd_s;     // IR: multiplier of the pending update x += upd_s * d
     double tol;
     double inner_goal2; // IR: (reduction asked of the current inner solve)^2
+    double bshift;    // singular problem: mean of b over fluid cells (else 0)
+    double nfluid;    // singular problem: number of fluid cells
+    double xshift;    // singular problem: mean of x over fluid cells
     int32_t phase;
     int32_t after;    // K1 action after a K2_NONE
     int32_t status;   // PCG_PENDING while running, else the final code
@@ -67,7 +73,8 @@ struct alignas(128) SlotState {
     int32_t final_upd;// IR: the pending update is the last one
     uint32_t ticket;  // arrivals of the current launch
     int32_t warm;     // warm start requested
-    int32_t pad_[3];
+    int32_t singular; // no Dirichlet face: solve for the mean-free source
+    int32_t pad_[2];
 };
 
 // Read-only description of a slot (rewritten by the host between replays).
@@ -77,7 +84,7 @@ struct Slot {
     int32_t plane_tiles;   // ceil(nx*ny / kBlock)
     int32_t ztiles;        // ceil(nz / tz)
     int32_t tz;            // planes per tile
-    int32_t pad0;
+    int32_t permask;       // bit 0: periodic x walls, bit 1: periodic y walls
     int64_t tile_begin;    // first global tile of this slot
     int64_t ntiles;        // plane_tiles * ztiles
     double h2;             // h*h

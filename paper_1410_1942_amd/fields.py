@@ -281,6 +281,57 @@ def stage_density(nx, ny, nz, *, surface_seed: Optional[int], velocity_seed: int
     return _density_from_modes(nx, ny, nz, modes, phase_shift, amp, mollify)
 
 
+def naca4_half_thickness(s, t: float):
+    """Half-thickness of a NACA four-digit symmetric section at chord
+    fraction s in [0, 1] for thickness ratio t (the published four-digit
+    thickness polynomial, chord 1)."""
+    s = np.clip(s, 0.0, 1.0)
+    return 5.0 * t * (0.2969 * np.sqrt(s) - 0.1260 * s - 0.3516 * s**2
+                      + 0.2843 * s**3 - 0.1015 * s**4)
+
+
+def strut_mask(nx, ny, nz, h, le_x: float, chord: float = 1.0, t: float = 0.24):
+    """Surface-piercing vertical strut of NACA section 00(100 t): the half on
+    y >= 0 of a section whose leading edge is at x = le_x and trailing edge
+    at le_x - chord, through the whole depth (the y = 0 wall is its
+    centreplane).  A cell is solid when its centre lies inside."""
+    xc, yc, _ = cell_centres(nx, ny, nz, h)
+    s = (le_x - xc) / chord
+    inside = (s >= 0.0) & (s <= 1.0)
+    half = np.where(inside, chord * naca4_half_thickness(s, t), -1.0)
+    col = (yc[:, None] <= half[None, :])
+    return np.ascontiguousarray(np.broadcast_to(col[None, :, :], (nz, ny, nx)), dtype=np.uint8)
+
+
+STRUT_BC = (PERIODIC, PERIODIC, NEUMANN, NEUMANN, NEUMANN, NEUMANN)
+
+
+def config_strut(nx: int = 512, ny: int = 128, nz: int = 128, surface_seed: int = 3,
+                 velocity_seed: int = 4, dt: float = 1.25e-3, keep_velocity: bool = True,
+                 name: str = "") -> Case:
+    """Strut tank in the layout of the paper's NACA 0024 case (Section 3),
+    lengths in chords: 4 long (periodic along x), 1 wide from the strut's
+    centreplane, 0.8 of water under 0.2 of air (h = 1/nz, so nz = 128 gives
+    the paper's spacing 1/128 on 512 x 128 x 128 cells).  No-flux walls on
+    y, bottom and top, periodic x: a singular, compatible problem.  Leading
+    edge at x = 3.6275 (the paper's x = 0 on its [-3.6275, 0.3725] domain),
+    eight seeded surface modes of amplitude 0.01 about z = 0.8."""
+    h = 1.0 / nz
+    modes, vel_rng = _draw_modes(surface_seed, velocity_seed, 8)
+    xc, yc, _ = cell_centres(nx, ny, nz, h)
+    eta = surface_elevation(xc, yc, nx * h, ny * h, modes, amp=0.01, mean=0.8)
+    rho = density(nx, ny, nz, h, eta)
+    mask = strut_mask(nx, ny, nz, h, le_x=3.6275 * (nx * h) / 4.0, chord=(nx * h) / 4.0)
+    u, v, w = face_velocities(vel_rng, nx, ny, nz)
+    close_faces(u, v, w, mask, STRUT_BC)
+    rhs = source_from_velocity(u, v, w, h, dt)
+    rhs[mask.astype(bool)] = 0.0
+    if not keep_velocity:
+        u = v = w = None
+    return Case(nx, ny, nz, h, rho, mask, STRUT_BC, dt, u, v, w, np.ascontiguousarray(rhs),
+                name=name or f"strut{nx}x{ny}x{nz}", seed=velocity_seed)
+
+
 def config1(n: int = 32, **kw) -> Case:
     """Plain FP64 case: n^3 cells on the unit cube, flat surface z = 0.5,
     no hull, Neumann on five walls and p = 0 on top, seed 0."""

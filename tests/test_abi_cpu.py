@@ -84,12 +84,17 @@ def test_setup_validation_without_device_work(lib):
                          ctypes.byref(bc), None, fake, 1 << 20, None) == L.EINVAL
     assert lib.pcg_setup(ctypes.byref(ctx), ctypes.byref(g), fake, None,
                          ctypes.byref(bc), None, None, 1 << 20, None) == L.EINVAL
-    # periodic walls are not supported; unknown kinds are invalid
+    # periodic z walls are not supported; a periodic wall without its
+    # partner and unknown kinds are invalid
     bp = L.BC()
-    bp.kind[0] = bp.kind[1] = L.BC_PERIODIC
-    bp.kind[5] = L.BC_DIRICHLET
+    bp.kind[4] = bp.kind[5] = L.BC_PERIODIC
     assert lib.pcg_setup(ctypes.byref(ctx), ctypes.byref(g), fake, None,
                          ctypes.byref(bp), None, fake, 1 << 20, None) == L.EUNSUPPORTED
+    bq = L.BC()
+    bq.kind[2] = L.BC_PERIODIC
+    bq.kind[5] = L.BC_DIRICHLET
+    assert lib.pcg_setup(ctypes.byref(ctx), ctypes.byref(g), fake, None,
+                         ctypes.byref(bq), None, fake, 1 << 20, None) == L.EINVAL
     bx = L.BC()
     bx.kind[2] = 9
     assert lib.pcg_setup(ctypes.byref(ctx), ctypes.byref(g), fake, None,
@@ -131,22 +136,33 @@ def _connectivity(lib, mask, bc):
 
 def test_connectivity_check_matches_reference(lib, orc):
     """The library's run-based flood fill agrees with the reference's
-    cell-by-cell search on random hulls and on hand-made pockets."""
+    cell-by-cell search (regions, and regions without a Dirichlet wall) on
+    random hulls, with and without periodic walls, and on hand-made
+    pockets."""
     rng = np.random.default_rng(5)
     tank = (0, 0, 0, 0, 0, 1)
     kinds = [tank, (1, 0, 0, 0, 0, 0), (0, 0, 0, 1, 0, 0), (0,) * 6,
-             (0, 0, 0, 0, 1, 0)]
-    agree = {True: 0, False: 0}
-    for trial in range(120):
+             (0, 0, 0, 0, 1, 0), (2, 2, 0, 0, 0, 1), (2, 2, 0, 0, 0, 0),
+             (0, 0, 2, 2, 0, 0), (2, 2, 2, 2, 0, 0), (2, 2, 2, 2, 1, 0)]
+    seen = {L.OK: 0, L.SINGULAR: 0, L.ESINGULAR: 0}
+    for trial in range(300):
         shape = tuple(int(v) for v in rng.integers(1, 9, size=3))
         dens = rng.uniform(0.2, 0.7)
         mask = (rng.random(shape) < dens).astype(np.uint8)
         bc = kinds[trial % len(kinds)]
-        want = orc.connected(mask, bc)
+        regions, loose = orc.components(mask, bc)
+        want = L.OK if loose == 0 else (L.SINGULAR if regions == 1 else L.ESINGULAR)
         got = _connectivity(lib, mask, bc)
-        assert got == (L.OK if want else L.ESINGULAR), (trial, shape, bc)
-        agree[want] += 1
-    assert agree[True] > 10 and agree[False] > 10
+        assert got == want, (trial, shape, bc, regions, loose)
+        seen[want] += 1
+    assert min(seen.values()) > 10, seen
+    # periodic x joins the two ends of a row: a hull wall across the middle
+    # of a periodic tank leaves one region
+    m = np.zeros((4, 3, 8), np.uint8)
+    m[:, :, 3] = 1
+    assert _connectivity(lib, m, (0,) * 6) == L.ESINGULAR
+    assert _connectivity(lib, m, (2, 2, 0, 0, 0, 0)) == L.SINGULAR
+    assert orc.components(m, (2, 2, 0, 0, 0, 0)) == (1, 1)
     # a sealed one-cell pocket at the bottom of an open tank
     m = np.zeros((6, 6, 6), np.uint8)
     m[0:2, 1:4, 1:4] = 1
@@ -158,7 +174,7 @@ def test_connectivity_check_matches_reference(lib, orc):
     assert lib.pcg_check_connectivity(None, ctypes.byref(_g(4, 4, 4)),
                                       ctypes.byref(_bc_of(tank))) == L.OK
     assert lib.pcg_check_connectivity(None, ctypes.byref(_g(4, 4, 4)),
-                                      ctypes.byref(_bc_of((0,) * 6))) == L.ESINGULAR
+                                      ctypes.byref(_bc_of((0,) * 6))) == L.SINGULAR
 
 
 def _bc_of(kinds):

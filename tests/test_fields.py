@@ -64,3 +64,39 @@ def test_batch_and_stream_members(F):
     assert tol in (1e-6, 1e-8)
     t = F.arrival_times(100, rate=10.0)
     assert np.all(np.diff(t) > 0) and 5 < t[-1] < 20
+
+
+def test_strut_layout():
+    """The strut tank: NACA 0024 half-section through the whole depth,
+    periodic x, no-flux elsewhere, surface about z = 0.8, the paper's
+    spacing 1/128 on 512 x 128 x 128 cells."""
+    from paper_1410_1942_amd import fields as F
+    # four-digit thickness polynomial: zero at the leading edge, about t/2
+    # at 30 % chord, a small open trailing edge
+    assert F.naca4_half_thickness(0.0, 0.24) == 0.0
+    assert abs(F.naca4_half_thickness(0.3, 0.24) - 0.12) < 2e-3
+    assert 0.0 < F.naca4_half_thickness(1.0, 0.24) < 0.01
+    c = F.config_strut(128, 32, 32)
+    assert c.h == 1 / 32 and c.bc == F.STRUT_BC
+    for a in (c.rho, c.mask, c.rhs, c.u, c.v, c.w):
+        assert a.flags["C_CONTIGUOUS"]
+    assert (c.mask == c.mask[0]).all()                 # vertical, surface piercing
+    xc = (np.arange(128) + 0.5) * c.h
+    for s in (0.1, 0.3, 0.7):
+        i = int(np.argmin(np.abs((3.6275 - xc) - s)))
+        width = c.mask[0, :, i].sum() * c.h              # solid cells from y = 0
+        want = F.naca4_half_thickness(3.6275 - xc[i], 0.24)
+        assert abs(width - want) <= c.h, (s, width, want)
+    assert not c.mask[:, :, xc > 3.6275 + c.h].any() and not c.mask[:, :, xc < 2.6275 - c.h].any()
+    # water below the mean level 0.8 away from the surface, air above
+    assert (c.rho[int(0.5 / c.h)] == F.RHO_WATER).all()
+    assert (c.rho[int(0.95 / c.h)] == F.RHO_AIR).all()
+    # periodic faces consistent; no flux through the other walls
+    assert np.array_equal(c.u[:, :, 0], c.u[:, :, -1])
+    assert not c.v[:, 0].any() and not c.v[:, -1].any()
+    assert not c.w[0].any() and not c.w[-1].any()
+    # compatible: the source sums to zero over the fluid
+    fl = c.mask == 0
+    assert abs(c.rhs[fl].sum()) <= 1e-9 * np.abs(c.rhs[fl]).sum()
+    full = F.config_strut(keep_velocity=False)
+    assert full.ncells == 8388608 and full.h == 0.0078125
