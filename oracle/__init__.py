@@ -48,15 +48,16 @@ def load(path: Optional[str] = None):
     up = ctypes.POINTER(ctypes.c_uint8)
     ip = ctypes.POINTER(ctypes.c_int)
     i, d = ctypes.c_int, ctypes.c_double
-    lib.oracle_apply.argtypes = [i, i, i, d, dp, up, ip, dp, dp]
+    fr = [dp, dp, dp, dp]   # optional area/volume fractions
+    lib.oracle_apply.argtypes = [i, i, i, d, dp, up, ip, dp, dp] + fr
     lib.oracle_apply.restype = i
-    lib.oracle_relres.argtypes = [i, i, i, d, dp, up, ip, dp, dp]
+    lib.oracle_relres.argtypes = [i, i, i, d, dp, up, ip, dp, dp] + fr
     lib.oracle_relres.restype = d
-    lib.oracle_pcg.argtypes = [i, i, i, d, dp, up, ip, dp, d, i, dp, ip, dp, dp]
+    lib.oracle_pcg.argtypes = [i, i, i, d, dp, up, ip, dp, d, i, dp, ip, dp, dp] + fr
     lib.oracle_pcg.restype = i
     lib.oracle_project.argtypes = [i, i, i, d, dp, up, ip, d, dp, dp, dp, dp]
     lib.oracle_project.restype = i
-    lib.oracle_divergence.argtypes = [i, i, i, d, dp, dp, dp, dp]
+    lib.oracle_divergence.argtypes = [i, i, i, d, dp, dp, dp, dp] + fr
     lib.oracle_divergence.restype = None
     lib.oracle_connected.argtypes = [i, i, i, up, ip]
     lib.oracle_connected.restype = i
@@ -89,7 +90,16 @@ def _dims(rho):
     return nx, ny, nz
 
 
-def apply(rho, mask, bc, h, p, lib=None):
+def _frac(frac):
+    """(ax, ay, az, vol) area and volume fractions, or None: returns the
+    kept arrays and the four pointers (NULL without fractions)."""
+    if frac is None:
+        return (), [None] * 4
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in frac]
+    return arrs, [a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs]
+
+
+def apply(rho, mask, bc, h, p, lib=None, frac=None):
     """L p per Eq. (pois) with the face rules of the module docstring."""
     lib = lib or load()
     rho, rp = _f64(rho)
@@ -97,22 +107,25 @@ def apply(rho, mask, bc, h, p, lib=None):
     p, pp = _f64(p)
     out = np.empty_like(rho)
     nx, ny, nz = _dims(rho)
+    keep, fp = _frac(frac)
     st = lib.oracle_apply(nx, ny, nz, float(h), rp, mp, _bc(bc), pp,
-                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), *fp)
     if st != OK:
         raise ValueError(f"oracle_apply status {st}")
     return out
 
 
-def relres(rho, mask, bc, h, rhs, p, lib=None) -> float:
-    """||rhs - L p||_2 / ||rhs||_2 over fluid cells."""
+def relres(rho, mask, bc, h, rhs, p, lib=None, frac=None) -> float:
+    """||rhs - L p||_2 / ||rhs||_2 over fluid cells (with fractions, the
+    volume-weighted norms of the scaled system)."""
     lib = lib or load()
     rho, rp = _f64(rho)
     mask, mp = _u8(mask)
     rhs, bp = _f64(rhs)
     p, pp = _f64(p)
     nx, ny, nz = _dims(rho)
-    return float(lib.oracle_relres(nx, ny, nz, float(h), rp, mp, _bc(bc), bp, pp))
+    keep, fp = _frac(frac)
+    return float(lib.oracle_relres(nx, ny, nz, float(h), rp, mp, _bc(bc), bp, pp, *fp))
 
 
 class PCGResult:
@@ -126,7 +139,7 @@ class PCGResult:
 
 
 def pcg(rho, mask, bc, h, rhs, tol=1e-8, maxit=100000, history=False,
-        lib=None) -> PCGResult:
+        lib=None, frac=None) -> PCGResult:
     """Jacobi-PCG solve of L p = rhs (cold start); see oracle.c."""
     lib = lib or load()
     rho, rp = _f64(rho)
@@ -139,10 +152,11 @@ def pcg(rho, mask, bc, h, rhs, tol=1e-8, maxit=100000, history=False,
     hist = np.zeros(maxit + 1) if history else None
     hp = (hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
           if history else None)
+    keep, fp = _frac(frac)
     st = lib.oracle_pcg(nx, ny, nz, float(h), rp, mp, _bc(bc), bp, float(tol),
                         int(maxit),
                         p.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                        ctypes.byref(it), ctypes.byref(rr), hp)
+                        ctypes.byref(it), ctypes.byref(rr), hp, *fp)
     if history:
         hist = hist[: it.value + 1]
     return PCGResult(p, st, it.value, rr.value, hist)
@@ -167,8 +181,9 @@ def project(rho, mask, bc, h, dt, p, u, v, w, lib=None):
     return u, v, w
 
 
-def divergence(u, v, w, h, lib=None):
-    """Face-difference divergence of MAC velocities."""
+def divergence(u, v, w, h, lib=None, frac=None):
+    """Face-difference divergence of MAC velocities (with fractions, area-
+    weighted and divided by the volume fraction)."""
     lib = lib or load()
     nz, ny, nx1 = u.shape
     nx = nx1 - 1
@@ -176,15 +191,16 @@ def divergence(u, v, w, h, lib=None):
     v, vp = _f64(v)
     w, wp = _f64(w)
     out = np.empty((nz, ny, nx))
+    keep, fp = _frac(frac)
     lib.oracle_divergence(nx, ny, nz, float(h), up_, vp, wp,
-                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), *fp)
     return out
 
 
-def source(u, v, w, h, dt, mask, lib=None):
+def source(u, v, w, h, dt, mask, lib=None, frac=None):
     """Right-hand side of either stage's pressure equation (Section 2.1, R
     set to zero): div(u)/dt on fluid cells, 0 on hull cells."""
-    rhs = divergence(u, v, w, h, lib) / dt
+    rhs = divergence(u, v, w, h, lib, frac) / dt
     rhs[np.asarray(mask, dtype=bool)] = 0.0
     return rhs
 

@@ -40,6 +40,15 @@
  * with b = 0.  The stop rule is ||b - A x||_2 <= tol ||b||_2, tested on the
  * recursive residual and confirmed on the recomputed one.
  *
+ * Free-slip cut cells (Section 2.2.1): optional area fractions A on every
+ * MAC face (arrays shaped like the face velocities) and volume fractions V
+ * per cell enter the finite-volume form of the same equation,
+ *     (1/(V_c h^2)) sum_f A_f beta_f (p_n - p_c) = Sigma_c,
+ * i.e. every face coefficient (walls included) is weighted by its area
+ * fraction and the scaled right-hand side is b_c = -h^2 V_c Sigma_c; the
+ * divergence becomes (1/(V_c h)) sum_f A_f u_f n_f.  Without fractions
+ * A = V = 1 and everything reduces to the binary form above.
+ *
  * The velocity projection of Section 2.1 (u* = u - dt (1/rho) grad P on the
  * faces) and the face divergence are included so the divergence-free result
  * of the projection can be checked.
@@ -68,7 +77,38 @@ typedef struct {
     const double *rho;
     const uint8_t *solid;
     int bc[6]; /* x-, x+, y-, y+, z-, z+ */
+    /* optional fractions (NULL: 1): faces u-, v-, w-shaped, cells */
+    const double *ax, *ay, *az, *vol;
 } problem;
+
+/* area fraction of face f (order x-, x+, y-, y+, z-, z+) of cell (i,j,k);
+ * on a periodic axis the face beyond the last cell is the row's face 0 */
+static double area(const problem *P, int i, int j, int k, int f)
+{
+    int nx = P->nx, ny = P->ny;
+    switch (f) {
+    case 0: case 1: {
+        if (!P->ax) return 1.0;
+        int fi = i + (f == 1);
+        if (fi == nx && P->bc[1] == O_PERIODIC) fi = 0;
+        return P->ax[((size_t)k * ny + j) * (nx + 1) + fi];
+    }
+    case 2: case 3: {
+        if (!P->ay) return 1.0;
+        int fj = j + (f == 3);
+        if (fj == ny && P->bc[3] == O_PERIODIC) fj = 0;
+        return P->ay[((size_t)k * (ny + 1) + fj) * nx + i];
+    }
+    default:
+        if (!P->az) return 1.0;
+        return P->az[((size_t)(k + (f == 5)) * ny + j) * nx + i];
+    }
+}
+
+static double volume(const problem *P, size_t c)
+{
+    return P->vol ? P->vol[c] : 1.0;
+}
 
 static size_t cell(const problem *P, int i, int j, int k)
 {
@@ -128,10 +168,10 @@ static void faces_of(const problem *P, int i, int j, int k,
         if (neighbour(P, i, j, k, f, &ni, &nj, &nk, &closed)) {
             size_t n = cell(P, ni, nj, nk);
             nb[f] = (long long)n;
-            beta[f] = face_beta(P, c, n);
+            beta[f] = area(P, i, j, k, f) * face_beta(P, c, n);
         } else {
             nb[f] = -1;
-            beta[f] = closed ? 0.0 : wall_beta(P, c, P->bc[f]);
+            beta[f] = closed ? 0.0 : area(P, i, j, k, f) * wall_beta(P, c, P->bc[f]);
         }
     }
 }
@@ -196,6 +236,18 @@ static int check_problem(const problem *P)
     for (size_t c = 0; c < n; ++c)
         if (!P->solid[c] && !(P->rho[c] > 0.0 && isfinite(P->rho[c])))
             return O_EDOMAIN;
+    /* fractions come as a set: areas in [0, 1], fluid volumes in (0, 1] */
+    int given = (P->ax != NULL) + (P->ay != NULL) + (P->az != NULL) + (P->vol != NULL);
+    if (given != 0 && given != 4) return O_EINVAL;
+    if (given) {
+        size_t nfx = (size_t)P->nz * P->ny * (P->nx + 1), nfy = (size_t)P->nz * (P->ny + 1) * P->nx,
+               nfz = (size_t)(P->nz + 1) * P->ny * P->nx;
+        for (size_t f = 0; f < nfx; ++f) if (!(P->ax[f] >= 0.0 && P->ax[f] <= 1.0)) return O_EDOMAIN;
+        for (size_t f = 0; f < nfy; ++f) if (!(P->ay[f] >= 0.0 && P->ay[f] <= 1.0)) return O_EDOMAIN;
+        for (size_t f = 0; f < nfz; ++f) if (!(P->az[f] >= 0.0 && P->az[f] <= 1.0)) return O_EDOMAIN;
+        for (size_t c = 0; c < n; ++c)
+            if (!P->solid[c] && !(P->vol[c] > 0.0 && P->vol[c] <= 1.0)) return O_EDOMAIN;
+    }
     return O_OK;
 }
 
@@ -255,9 +307,9 @@ int oracle_connected(int nx, int ny, int nz, const uint8_t *solid, const int *bc
 /* out = L p (the operator of Eq. pois as discretised above); 0 on solids. */
 int oracle_apply(int nx, int ny, int nz, double h, const double *rho,
                  const uint8_t *solid, const int *bc, const double *p,
-                 double *out)
+                 double *out, const double *ax, const double *ay, const double *az, const double *vol)
 {
-    problem P = { nx, ny, nz, h, rho, solid, { 0 } };
+    problem P = { nx, ny, nz, h, rho, solid, { 0 }, ax, ay, az, vol };
     for (int f = 0; f < 6; ++f) P.bc[f] = bc[f];
     int st = check_problem(&P);
     if (st != O_OK) return st;
@@ -266,22 +318,23 @@ int oracle_apply(int nx, int ny, int nz, double h, const double *rho,
     double s = -1.0 / (h * h);
 #pragma omp parallel for schedule(static)
     for (long long c = 0; c < (long long)n; ++c)
-        out[c] = solid[c] ? 0.0 : s * out[c];
+        out[c] = solid[c] ? 0.0 : s * out[c] / volume(&P, (size_t)c);
     return O_OK;
 }
 
 /*
- * Relative residual ||Sigma - L p||_2 / ||Sigma||_2 over fluid cells (the
- * same number as ||b - A p|| / ||b|| for the scaled SPD system).
+ * Relative residual of the scaled SPD system, ||b - A p||_2 / ||b||_2 over
+ * fluid cells, i.e. ||V (Sigma - L p)|| / ||V Sigma|| (without fractions
+ * ||Sigma - L p|| / ||Sigma||).
  */
 double oracle_relres(int nx, int ny, int nz, double h, const double *rho,
                      const uint8_t *solid, const int *bc, const double *rhs,
-                     const double *p)
+                     const double *p, const double *ax, const double *ay, const double *az, const double *vol)
 {
     size_t n = (size_t)nx * ny * nz;
     double *Lp = malloc(n * sizeof(double));
     if (!Lp) return NAN;
-    if (oracle_apply(nx, ny, nz, h, rho, solid, bc, p, Lp) != O_OK) {
+    if (oracle_apply(nx, ny, nz, h, rho, solid, bc, p, Lp, ax, ay, az, vol) != O_OK) {
         free(Lp);
         return NAN;
     }
@@ -289,17 +342,18 @@ double oracle_relres(int nx, int ny, int nz, double h, const double *rho,
 #pragma omp parallel for reduction(+ : rr, bb) schedule(static)
     for (long long c = 0; c < (long long)n; ++c) {
         if (solid[c]) continue;
-        double r = rhs[c] - Lp[c];
+        double v = vol ? vol[c] : 1.0;
+        double r = v * (rhs[c] - Lp[c]);
         rr += r * r;
-        bb += rhs[c] * rhs[c];
+        bb += (v * rhs[c]) * (v * rhs[c]);
     }
     free(Lp);
     return bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
 }
 
 /*
- * Jacobi-preconditioned conjugate gradients on A x = b, A = -h^2 L,
- * b = -h^2 Sigma (fluid), 0 (solid).  Cold start x0 = 0.
+ * Jacobi-preconditioned conjugate gradients on A x = b, A = -h^2 V L,
+ * b = -h^2 V Sigma (fluid), 0 (solid).  Cold start x0 = 0.
  *   r = b, z = D^-1 r, p = z, rz = r.z
  *   repeat: q = A p; pq = p.q (breakdown if <= 0 or not finite);
  *           alpha = rz/pq; x += alpha p; r -= alpha q;
@@ -312,9 +366,9 @@ double oracle_relres(int nx, int ny, int nz, double h, const double *rho,
 int oracle_pcg(int nx, int ny, int nz, double h, const double *rho,
                const uint8_t *solid, const int *bc, const double *rhs,
                double tol, int maxit, double *p_out, int *iters_out,
-               double *relres_out, double *hist)
+               double *relres_out, double *hist, const double *ax, const double *ay, const double *az, const double *vol)
 {
-    problem P = { nx, ny, nz, h, rho, solid, { 0 } };
+    problem P = { nx, ny, nz, h, rho, solid, { 0 }, ax, ay, az, vol };
     for (int f = 0; f < 6; ++f) P.bc[f] = bc[f];
     *iters_out = 0;
     *relres_out = NAN;
@@ -343,7 +397,7 @@ int oracle_pcg(int nx, int ny, int nz, double h, const double *rho,
     }
     double h2 = h * h;
     for (size_t c = 0; c < n; ++c) {
-        b[c] = solid[c] ? 0.0 : -h2 * rhs[c];
+        b[c] = solid[c] ? 0.0 : -h2 * volume(&P, c) * rhs[c];
         if (!isfinite(b[c])) st = O_EDOMAIN;
     }
     if (singular && st == O_OK) {
@@ -508,21 +562,33 @@ int oracle_project(int nx, int ny, int nz, double h, const double *rho,
 }
 
 /* (D u)_c = (u_{i+1/2} - u_{i-1/2} + v_{j+1/2} - v_{j-1/2}
- *           + w_{k+1/2} - w_{k-1/2}) / h  -- the discrete form of Eq. (mass). */
+ *           + w_{k+1/2} - w_{k-1/2}) / h  -- the discrete form of Eq. (mass);
+ * with fractions every face velocity is weighted by its area fraction and
+ * the sum divided by V_c.  Arrays are used as given (on a periodic axis the
+ * last face must repeat face 0). */
 void oracle_divergence(int nx, int ny, int nz, double h, const double *u,
-                       const double *v, const double *w, double *out)
+                       const double *v, const double *w, double *out, const double *ax, const double *ay, const double *az, const double *vol)
 {
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
-                double du = u[((size_t)k * ny + j) * (nx + 1) + i + 1] -
-                            u[((size_t)k * ny + j) * (nx + 1) + i];
-                double dv = v[((size_t)k * (ny + 1) + j + 1) * nx + i] -
-                            v[((size_t)k * (ny + 1) + j) * nx + i];
-                double dw = w[((size_t)(k + 1) * ny + j) * nx + i] -
-                            w[((size_t)k * ny + j) * nx + i];
-                out[((size_t)k * ny + j) * nx + i] = (du + dv + dw) / h;
+                size_t u0 = ((size_t)k * ny + j) * (nx + 1) + i;
+                size_t v0 = ((size_t)k * (ny + 1) + j) * nx + i;
+                size_t w0 = ((size_t)k * ny + j) * nx + i;
+                size_t v1 = v0 + nx, w1 = w0 + (size_t)nx * ny;
+                double du, dv, dw, vc = 1.0;
+                if (ax) {
+                    du = ax[u0 + 1] * u[u0 + 1] - ax[u0] * u[u0];
+                    dv = ay[v1] * v[v1] - ay[v0] * v[v0];
+                    dw = az[w1] * w[w1] - az[w0] * w[w0];
+                    vc = vol[w0];
+                } else {
+                    du = u[u0 + 1] - u[u0];
+                    dv = v[v1] - v[v0];
+                    dw = w[w1] - w[w0];
+                }
+                out[w0] = ax ? (du + dv + dw) / (vc * h) : (du + dv + dw) / h;
             }
 }
 

@@ -71,6 +71,8 @@ class Case:
     rhs: np.ndarray          # f64 [nz, ny, nx]; the source Sigma
     name: str = ""
     seed: int = 0
+    # free-slip cut cells: (ax u-shaped, ay v-shaped, az w-shaped, vol cell)
+    frac: Optional[tuple] = None
 
     @property
     def shape(self):
@@ -135,6 +137,77 @@ def wedge_mask(nx, ny, nz, h, wedge: Wedge):
     psi = wedge_psi(xc[None, None, :], yc[None, :, None], zc[:, None, None],
                     nx * h, ny * h, wedge)
     return (psi < 0.0).astype(np.uint8)
+
+
+def _sampled_fraction(psi, centres, spans, near, sub):
+    """Fraction of sub x ... sub sample points with psi >= 0 (outside the
+    body) around each centre, over the spans given per axis (0 for an axis
+    the sample set does not extend along); only `near` entries are sampled,
+    the others take the sign of psi at the centre."""
+    x0, y0, z0 = centres
+    frac = (psi(x0, y0, z0) >= 0.0).astype(np.float64)
+    idx = np.nonzero(near)
+    if idx[0].size == 0:
+        return frac
+    offs = (np.arange(sub) + 0.5) / sub - 0.5
+    grids = [offs * sp if sp > 0 else np.zeros(1) for sp in spans]
+    ox, oy, oz = np.meshgrid(*grids, indexing="ij")
+    ox, oy, oz = ox.ravel(), oy.ravel(), oz.ravel()
+    xs = np.broadcast_to(x0, near.shape)[idx][:, None] + ox[None, :]
+    ys = np.broadcast_to(y0, near.shape)[idx][:, None] + oy[None, :]
+    zs = np.broadcast_to(z0, near.shape)[idx][:, None] + oz[None, :]
+    frac[idx] = (psi(xs, ys, zs) >= 0.0).mean(axis=1)
+    return frac
+
+
+def wedge_fractions(nx, ny, nz, h, wedge: Wedge, sub: int = 4):
+    """Area fractions of every MAC face and volume fractions of every cell
+    open to the fluid around the wedge (the finite-volume free-slip hull of
+    Section 2.2.1): the share of sub^2 (faces) or sub^3 (cells) sample points
+    outside the body.  Only faces and cells within reach of the surface are
+    sampled (the max of the half-space distances never exceeds the true
+    distance for this convex body, so larger |psi| decides by sign).  Faces
+    touching a cell with no fluid are closed."""
+    Lx, Ly = nx * h, ny * h
+    psi = lambda x, y, z: wedge_psi(x, y, z, Lx, Ly, wedge)
+    xc, yc, zc = cell_centres(nx, ny, nz, h)
+    xf = np.arange(nx + 1) * h
+    yf = np.arange(ny + 1) * h
+    zf = np.arange(nz + 1) * h
+    X, Y, Z = xc[None, None, :], yc[None, :, None], zc[:, None, None]
+    r_cell, r_face = 0.87 * h, 0.71 * h
+    shape_c = (nz, ny, nx)
+    pc = np.broadcast_to(psi(X, Y, Z), shape_c)
+    vol = _sampled_fraction(psi, (X, Y, Z), (h, h, h), np.abs(pc) < r_cell, sub)
+    pu = np.broadcast_to(psi(xf[None, None, :], Y, Z), (nz, ny, nx + 1))
+    ax = _sampled_fraction(psi, (xf[None, None, :], Y, Z), (0, h, h), np.abs(pu) < r_face, sub)
+    pv = np.broadcast_to(psi(X, yf[None, :, None], Z), (nz, ny + 1, nx))
+    ay = _sampled_fraction(psi, (X, yf[None, :, None], Z), (h, 0, h), np.abs(pv) < r_face, sub)
+    pw = np.broadcast_to(psi(X, Y, zf[:, None, None]), (nz + 1, ny, nx))
+    az = _sampled_fraction(psi, (X, Y, zf[:, None, None]), (h, h, 0), np.abs(pw) < r_face, sub)
+    ax, ay, az, vol = (np.array(np.broadcast_to(a, sh), dtype=np.float64, order="C")
+                       for a, sh in ((ax, (nz, ny, nx + 1)), (ay, (nz, ny + 1, nx)),
+                                     (az, (nz + 1, ny, nx)), (vol, shape_c)))
+    solid = vol == 0.0
+    ax[:, :, 1:][solid] = 0.0
+    ax[:, :, :-1][solid] = 0.0
+    ay[:, 1:, :][solid] = 0.0
+    ay[:, :-1, :][solid] = 0.0
+    az[1:, :, :][solid] = 0.0
+    az[:-1, :, :][solid] = 0.0
+    return ax, ay, az, vol
+
+
+def source_with_fractions(u, v, w, h, dt, frac):
+    """Sigma = div_A(u)/dt: face velocities weighted by their area fractions,
+    summed, divided by the cell's volume fraction (0 where it is 0)."""
+    ax, ay, az, vol = frac
+    fu, fv, fw = ax * u, ay * v, az * w
+    d = ((fu[:, :, 1:] - fu[:, :, :-1]) + (fv[:, 1:, :] - fv[:, :-1, :])
+         + (fw[1:, :, :] - fw[:-1, :, :]))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out = np.where(vol > 0.0, d / (vol * h), 0.0)
+    return out / dt
 
 
 def density(nx, ny, nz, h, eta, rho_w=RHO_WATER, rho_a=RHO_AIR,
@@ -221,7 +294,8 @@ def make_two_phase(nx, ny, nz, *, surface_seed: Optional[int],
                    velocity_seed: int, wedge: Optional[Wedge] = None,
                    bc: Sequence[int] = TANK_BC, dt: float = 1e-3,
                    nmodes: int = 8, amp: float = 0.01, mollify: float = 0.0,
-                   keep_velocity: bool = True, name: str = "") -> Case:
+                   keep_velocity: bool = True, name: str = "",
+                   fractions: bool = False) -> Case:
     """Two-phase tank: water below eta(x, y), air above, optional wedge hull.
 
     ``surface_seed=None`` gives the flat surface z = 0.5.  Velocities come
@@ -231,19 +305,30 @@ def make_two_phase(nx, ny, nz, *, surface_seed: Optional[int],
     h = 1.0 / nz
     modes, vel_rng = _draw_modes(surface_seed, velocity_seed, nmodes)
     rho = _density_from_modes(nx, ny, nz, modes, 0.0, amp, mollify)
-    if wedge is not None:
+    frac = None
+    if wedge is not None and fractions:
+        frac = wedge_fractions(nx, ny, nz, h, wedge)
+        mask = (frac[3] == 0.0).astype(np.uint8)
+    elif wedge is not None:
         mask = wedge_mask(nx, ny, nz, h, wedge)
     else:
         mask = np.zeros((nz, ny, nx), dtype=np.uint8)
     u, v, w = face_velocities(vel_rng, nx, ny, nz)
     close_faces(u, v, w, mask, bc)
-    rhs = source_from_velocity(u, v, w, h, dt)
+    if frac is not None:
+        # no flow through fully blocked faces
+        u[frac[0] == 0.0] = 0.0
+        v[frac[1] == 0.0] = 0.0
+        w[frac[2] == 0.0] = 0.0
+        rhs = source_with_fractions(u, v, w, h, dt, frac)
+    else:
+        rhs = source_from_velocity(u, v, w, h, dt)
     rhs[mask.astype(bool)] = 0.0
     if not keep_velocity:
         u = v = w = None
     return Case(nx, ny, nz, h, rho, mask, tuple(int(b) for b in bc), dt,
                 u, v, w, np.ascontiguousarray(rhs), name=name,
-                seed=velocity_seed)
+                seed=velocity_seed, frac=frac)
 
 
 def _draw_modes(surface_seed, velocity_seed, nmodes):

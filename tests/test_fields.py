@@ -100,3 +100,32 @@ def test_strut_layout():
     assert abs(c.rhs[fl].sum()) <= 1e-9 * np.abs(c.rhs[fl]).sum()
     full = F.config_strut(keep_velocity=False)
     assert full.ncells == 8388608 and full.h == 0.0078125
+
+
+def test_wedge_fractions():
+    """Sampled cut-cell fractions of the wedge: the solid volume sum(1 - V) h^3
+    matches the prism's closed form (triangle of side 0.5 Lx and half-angle
+    15 degrees, from the keel at 0.3 to the top), fractions lie in [0, 1],
+    partial values only near the surface, and faces of empty cells closed."""
+    import math
+    from paper_1410_1942_amd import fields as F
+    n = 48
+    h = 1.0 / n
+    ax, ay, az, vol = F.wedge_fractions(n, n, n, h, F.Wedge())
+    want = 0.5**2 * math.tan(math.radians(15.0)) * 0.7
+    got = (1.0 - vol).sum() * h**3
+    assert abs(got - want) <= 0.01 * want, (got, want)
+    for a in (ax, ay, az, vol):
+        assert a.min() >= 0.0 and a.max() <= 1.0
+    cut = (vol > 0) & (vol < 1)
+    assert cut.sum() > 100
+    xc, yc, zc = F.cell_centres(n, n, n, h)
+    psi = F.wedge_psi(xc[None, None, :], yc[None, :, None], zc[:, None, None], 1.0, 1.0, F.Wedge())
+    assert np.all(np.abs(np.broadcast_to(psi, vol.shape)[cut]) < 0.87 * h)
+    solid = vol == 0
+    assert not ax[:, :, 1:][solid].any() and not ax[:, :, :-1][solid].any()
+    assert not az[1:][solid].any() and not az[:-1][solid].any()
+    c = F.make_two_phase(24, 20, 18, surface_seed=1, velocity_seed=2, wedge=F.Wedge(),
+                         fractions=True)
+    assert np.array_equal(c.mask, (c.frac[3] == 0).astype(np.uint8))
+    assert not c.u[c.frac[0] == 0].any()

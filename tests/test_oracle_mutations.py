@@ -25,7 +25,7 @@ class Bound:
 
     def __init__(self, lib):
         for name in ("apply", "pcg", "relres", "project", "divergence",
-                     "connected", "components"):
+                     "connected", "components", "source"):
             setattr(self, name, functools.partial(getattr(oracle, name), lib=lib))
         for name in ("OK", "MAXIT", "EINVAL", "EDOMAIN", "ESINGULAR",
                      "EBREAKDOWN", "EUNSUPPORTED"):
@@ -55,6 +55,9 @@ PIN_RUNS = {
     "eig_periodic": lambda o: pins.test_eigvec_periodic(o, (9, 14, 7), (2, 1)),
     "eig_neumann": lambda o: pins.test_eigvec_pure_neumann(o, (7, 9, 6), (0, 3, 1), 37.0),
     "dense_periodic": lambda o: pins.test_dense_periodic(o, _F(), (9, 6, 7), (2, 2, 0, 0, 0, 0)),
+    "dense_fractions": lambda o: pins.test_dense_with_fractions(o, _F()),
+    "volume_scaling": lambda o: pins.test_uniform_volume_scales_the_answer(o, _F()),
+    "divergence_fractions": lambda o: pins.test_projection_divergence_with_fractions(o, _F()),
 }
 
 MUTANTS = [
@@ -87,6 +90,14 @@ MUTANTS = [
     ("source_mean_kept", "if (!solid[c]) b[c] -= mean;", "if (!solid[c]) b[c] -= 0.0 * mean;"),
     # singular problem: solution not shifted to zero mean
     ("solution_mean_kept", "if (!solid[c]) x[c] -= mean;", "if (!solid[c]) x[c] -= 0.0 * mean;"),
+    # x area fractions ignored
+    ("x_area_ignored", "return P->ax[((size_t)k * ny + j) * (nx + 1) + fi];", "return 1.0;"),
+    # volume fraction left out of the right-hand side
+    ("volume_off_source", "b[c] = solid[c] ? 0.0 : -h2 * volume(&P, c) * rhs[c];",
+     "b[c] = solid[c] ? 0.0 : -h2 * rhs[c];"),
+    # area divergence not divided by the volume fraction
+    ("divergence_no_volume", "out[w0] = ax ? (du + dv + dw) / (vc * h) : (du + dv + dw) / h;",
+     "out[w0] = (du + dv + dw) / h;"),
 ]
 
 

@@ -578,3 +578,130 @@ def test_projection_divergence_periodic(orc, F, bc):
     div1 = orc.divergence(u, v, w, c.h)
     ratio = np.linalg.norm(div1) / np.linalg.norm(div0)
     assert ratio <= tol * 1.01
+
+
+# --------------------------------------------------------------------------
+# free-slip cut cells: area and volume fractions (Section 2.2.1)
+# --------------------------------------------------------------------------
+
+def _ones_frac(nx, ny, nz):
+    return (np.ones((nz, ny, nx + 1)), np.ones((nz, ny + 1, nx)),
+            np.ones((nz + 1, ny, nx)), np.ones((nz, ny, nx)))
+
+
+def test_fractions_of_one_are_the_binary_form(orc, F):
+    """Fractions of one give the binary operator (to the rounding of the
+    reference's threaded dot products, which are not bit-reproducible)."""
+    c = _two_phase_wedge(F, 14, 12, 10, bc=TANK)
+    r0 = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-10)
+    r1 = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-10, frac=_ones_frac(14, 12, 10))
+    assert r0.iters == r1.iters
+    assert np.abs(r0.p - r1.p).max() <= 1e-13 * np.abs(r0.p).max()
+    Lp0 = orc.apply(c.rho, c.mask, c.bc, c.h, r0.p)
+    Lp1 = orc.apply(c.rho, c.mask, c.bc, c.h, r0.p, frac=_ones_frac(14, 12, 10))
+    assert np.array_equal(Lp0, Lp1)
+
+
+@pytest.mark.parametrize("alpha", [0.25, 0.8])
+def test_eigvec_anisotropic_area(orc, alpha):
+    """Every z face (walls included) open to the fraction alpha: the operator
+    is Lx + Ly + alpha Lz, so the all-Dirichlet sine product stays an exact
+    eigenvector with eigenvalue lx + ly + alpha lz."""
+    nx, ny, nz = 10, 8, 12
+    h, x, y, z = _grid(nx, ny, nz)
+    Lx, Ly, Lz = nx * h, ny * h, nz * h
+    v = np.sin(math.pi * x / Lx) * np.sin(2 * math.pi * y / Ly) * np.sin(math.pi * z / Lz)
+    l1 = lambda m, L: 2 * (1 - math.cos(m * math.pi * h / L)) / h**2
+    lam = l1(1, Lx) + l1(2, Ly) + alpha * l1(1, Lz)
+    ax, ay, az, vol = _ones_frac(nx, ny, nz)
+    az = az * alpha
+    rho = np.ones((nz, ny, nx))
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    Lv = orc.apply(rho, mask, ALL_D, h, v, frac=(ax, ay, az, vol))
+    assert np.abs(Lv + lam * v).max() <= 1e-10 * lam
+    r = orc.pcg(rho, mask, ALL_D, h, -lam * v, tol=1e-13, frac=(ax, ay, az, vol))
+    assert r.status == orc.OK and np.abs(r.p - v).max() <= 1e-9
+
+
+def test_uniform_volume_scales_the_answer(orc, F):
+    """V = v everywhere divides the operator by v, so p = v p(V = 1)."""
+    c = _two_phase_wedge(F, 12, 10, 9, bc=TANK)
+    ax, ay, az, vol = _ones_frac(12, 10, 9)
+    r0 = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-12)
+    r1 = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-12, frac=(ax, ay, az, 0.37 * vol))
+    assert np.abs(r1.p - 0.37 * r0.p).max() <= 1e-9 * np.abs(r0.p).max()
+
+
+def _random_frac(rng, mask):
+    nz, ny, nx = mask.shape
+    ax = rng.uniform(0.05, 1.0, (nz, ny, nx + 1))
+    ay = rng.uniform(0.05, 1.0, (nz, ny + 1, nx))
+    az = rng.uniform(0.05, 1.0, (nz + 1, ny, nx))
+    vol = rng.uniform(0.1, 1.0, (nz, ny, nx))
+    return ax, ay, az, vol
+
+
+def test_dense_with_fractions(orc, F):
+    """Against a dense solve of sum_f A_f beta_f (p_c - p_n) = -h^2 V Sigma
+    assembled here face by face."""
+    nx, ny, nz = 7, 6, 8
+    c = F.make_two_phase(nx, ny, nz, surface_seed=91, velocity_seed=92, wedge=F.Wedge(),
+                         bc=(D, N, N, D, N, D))
+    rng = np.random.default_rng(93)
+    ax, ay, az, vol = _random_frac(rng, c.mask)
+    n = nx * ny * nz
+    A = np.zeros((n, n))
+    idx = lambda i, j, k: (k * ny + j) * nx + i
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                ci = idx(i, j, k)
+                if c.mask[k, j, i]:
+                    A[ci, ci] = 1.0
+                    continue
+                faces = [(-1, 0, 0, ax[k, j, i]), (1, 0, 0, ax[k, j, i + 1]),
+                         (0, -1, 0, ay[k, j, i]), (0, 1, 0, ay[k, j + 1, i]),
+                         (0, 0, -1, az[k, j, i]), (0, 0, 1, az[k + 1, j, i])]
+                for f, (di, dj, dk, a) in enumerate(faces):
+                    ii, jj, kk = i + di, j + dj, k + dk
+                    if 0 <= ii < nx and 0 <= jj < ny and 0 <= kk < nz:
+                        if c.mask[kk, jj, ii]:
+                            continue
+                        b = a * 2.0 / (c.rho[k, j, i] + c.rho[kk, jj, ii])
+                        A[ci, ci] += b
+                        A[ci, idx(ii, jj, kk)] -= b
+                    elif c.bc[f] == D:
+                        A[ci, ci] += a * 2.0 / c.rho[k, j, i]
+    b = (-c.h**2 * vol * c.rhs * (c.mask == 0)).ravel()
+    want = np.linalg.solve(A, b)
+    r = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-14, maxit=5000,
+                frac=(ax, ay, az, vol))
+    assert r.status in (orc.OK, orc.MAXIT)
+    assert np.abs(r.p.ravel() - want).max() <= 1e-10 * np.abs(want).max()
+    # symmetric positive definite on the fluid block
+    fl = (c.mask == 0).ravel()
+    Af = A[np.ix_(fl, fl)]
+    assert np.abs(Af - Af.T).max() <= 1e-14 * np.abs(Af).max()
+    assert np.linalg.eigvalsh(Af).min() > 0.0
+
+
+def test_projection_divergence_with_fractions(orc, F):
+    """Cut-cell wedge: the volume-weighted area divergence of the projected
+    velocity, relative to that of the input, is the relative residual."""
+    c = F.make_two_phase(24, 20, 18, surface_seed=95, velocity_seed=96, wedge=F.Wedge(),
+                         bc=TANK, fractions=True)
+    ax, ay, az, vol = c.frac
+    assert ((vol > 0) & (vol < 1)).sum() > 50
+    tol = 1e-10
+    r = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=tol, frac=c.frac)
+    assert r.status == orc.OK
+    d0 = vol * orc.divergence(c.u, c.v, c.w, c.h, frac=c.frac)
+    u, v, w = orc.project(c.rho, c.mask, c.bc, c.h, c.dt, r.p, c.u, c.v, c.w)
+    d1 = vol * orc.divergence(u, v, w, c.h, frac=c.frac)
+    fl = c.mask == 0
+    ratio = np.linalg.norm(d1[fl]) / np.linalg.norm(d0[fl])
+    assert ratio <= tol * 1.01
+    assert abs(ratio - r.relres) <= 1e-6 * r.relres
+    # the source is the generator's area divergence
+    np.testing.assert_allclose(orc.source(c.u, c.v, c.w, c.h, c.dt, c.mask, frac=c.frac),
+                               c.rhs, rtol=1e-12, atol=1e-12 * np.abs(c.rhs).max())
