@@ -107,12 +107,15 @@ enum {
                                         the problem is taken as anchored when
                                         a Dirichlet wall exists, else as one
                                         singular region                      */
-    PCG_NO_DENSITY_CLASSES = 4       /* always read the FP64/FP32 density per
+    PCG_NO_DENSITY_CLASSES = 4,      /* always read the FP64/FP32 density per
                                         cell; by default a field with at most
                                         14 distinct fluid densities is coded
                                         as one byte per cell plus a table of
                                         exact face coefficients (same
                                         operator, fewer bytes per iteration) */
+    PCG_FRACTIONS = 8                /* reserve workspace for free-slip cut-cell
+                                        fractions (pcg_set_fractions; single
+                                        contexts only)                       */
 };
 
 /*
@@ -277,6 +280,31 @@ int pcg_project_ex(pcg_ctx_t *ctx, const double *p, double dt, const double *au,
 int pcg_rhs(pcg_ctx_t *ctx, double dt, const double *au, const double *av,
             const double *aw, const double *bu, const double *bv, const double *bw,
             double *rhs);
+
+/*
+ * Free-slip cut cells (Section 2.2.1: the hull's area fractions A and volume
+ * fractions V enter the Poisson equation and the projection).  With
+ * fractions every face coefficient, wall faces included, is weighted by the
+ * face's open area and the equation holds in finite-volume form,
+ *   (1/(V_c h^2)) sum_f A_f beta_f (p_n - p_c) = Sigma_c,
+ * so the scaled system is sum_f A_f beta_f (p_c - p_n) = -h^2 V_c Sigma_c
+ * and the reported relative residual is its (volume-weighted) one.  The
+ * source and divergence entry points then weight every face velocity by its
+ * area fraction and divide the cell sum by V_c; the projection keeps its
+ * form.  The hull mask still marks the cells with no fluid; fractions
+ * describe the rest.
+ *   ax device f64[nz][ny][nx+1], ay f64[nz][ny+1][nx], az f64[nz+1][ny][nx]:
+ *      area fractions in [0, 1] of the MAC faces (same layout as the face
+ *      velocities; on a periodic axis face 0 is the shared face)
+ *   vol device f64[n]: volume fractions, in (0, 1] on fluid cells
+ * The arrays are copied into the workspace (set up with PCG_FRACTIONS, else
+ * PCG_EINVAL) and validated on the device (PCG_EDOMAIN when out of range, and
+ * the context then has no fractions).  All four NULL returns the context to
+ * the binary hull.  While fractions are set the density is read per cell
+ * (no density classes).  Blocks until done.
+ */
+int pcg_set_fractions(pcg_ctx_t *ctx, const double *ax, const double *ay, const double *az,
+                      const double *vol);
 
 /*
  * Rebuild the context's face coefficients in place for a new density field

@@ -17,7 +17,7 @@ EINVAL, EDOMAIN, ESINGULAR, EBREAKDOWN, ENOMEM, EBUSY, EHIP, EUNSUPPORTED = \
     -1, -2, -3, -4, -5, -6, -7, -8
 BC_NEUMANN, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 PREC_FP64, PREC_FP32_IR = 0, 1
-WARM_START, SKIP_CONNECTIVITY_CHECK, NO_DENSITY_CLASSES = 1, 2, 4
+WARM_START, SKIP_CONNECTIVITY_CHECK, NO_DENSITY_CLASSES, FRACTIONS = 1, 2, 4, 8
 
 EXPORTED = [
     "pcg_workspace_bytes", "pcg_setup", "pcg_solve", "pcg_destroy",
@@ -28,6 +28,7 @@ EXPORTED = [
     "pcg_check_connectivity", "pcg_set_tile_rules", "pcg_get_tile_rules",
     "pcg_density_classes", "pcg_project", "pcg_divergence",
     "pcg_solve_ex", "pcg_project_ex", "pcg_rhs", "pcg_update_density",
+    "pcg_set_fractions",
 ]
 
 
@@ -110,6 +111,7 @@ def load(path: str = LIB_PATH):
     lib.pcg_project_ex.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp, vp, dbl, vp, vp, vp]
     lib.pcg_rhs.argtypes = [vp, dbl, vp, vp, vp, vp, vp, vp, vp]
     lib.pcg_update_density.argtypes = [vp, vp, vp, i32]
+    lib.pcg_set_fractions.argtypes = [vp, vp, vp, vp, vp]
     for name in EXPORTED:
         if name not in ("pcg_strerror", "pcg_last_hip_error"):
             getattr(lib, name).restype = ctypes.c_int

@@ -29,6 +29,9 @@ hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n, int round
 hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
                          float *r32, int64_t n, int *bad, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
+hipError_t launch_check_frac(const double *ax, const double *ay, const double *az,
+                             const double *vol, const double *rho64, int64_t nu, int64_t nv,
+                             int64_t nw, int64_t n, int *bad, hipStream_t s);
 hipError_t launch_project(const Slot *slot, const double *p, double s, double wt,
                           const double *const a[3], const double *const b[3],
                           double *const out[3], int blocks, hipStream_t st);
@@ -183,11 +186,19 @@ Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch)
     return G;
 }
 
-size_t slot_bytes(const Geometry &G, int prec)
+// Bytes of the four fraction arrays of a grid (FP64 MAC faces and cells).
+size_t frac_bytes(const Geometry &G)
+{
+    const size_t nx = G.nx, ny = G.ny, nz = G.nz;
+    return align_up(8 * (nx + 1) * ny * nz, kAlign) + align_up(8 * nx * (ny + 1) * nz, kAlign) +
+           align_up(8 * nx * ny * (nz + 1), kAlign) + align_up(8 * nx * ny * nz, kAlign);
+}
+
+size_t slot_bytes(const Geometry &G, int prec, bool frac = false)
 {
     const size_t n = (size_t)G.n;
     const size_t es = prec == PCG_PREC_FP32_IR ? 4 : 8;
-    size_t b = 0;
+    size_t b = frac ? frac_bytes(G) : 0;
     b += align_up(8 * n, kAlign);                    // rho64
     if (prec == PCG_PREC_FP32_IR) b += align_up(4 * n, kAlign);  // rho32
     b += 3 * align_up(es * n, kAlign);               // z, pa, pb
@@ -248,7 +259,8 @@ int check_opts(const pcg_opts_t *o)
     if (o->precision != PCG_PREC_FP64 && o->precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
     if (o->check_every < 0 || o->inner_maxit < 0 || o->tz < 0 || o->grid_blocks < 0) return PCG_EINVAL;
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0 || std::isnan(o->inner_tol)) return PCG_EINVAL;
-    if (o->flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES))
+    if (o->flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES |
+                     PCG_FRACTIONS))
         return PCG_EINVAL;
     return PCG_OK;
 }
@@ -364,6 +376,8 @@ struct SlotHost {
     float *tab32 = nullptr;
     bool classes = false;        // class coding in use
     int nclasses = 0;            // fluid classes when coded
+    double *ax = nullptr, *ay = nullptr, *az = nullptr, *vol = nullptr;  // arena, if reserved
+    bool has_frac = false;       // cut-cell fractions in use (coefficient mode 2)
     const double *rhs = nullptr;
     double *x = nullptr;
     Clock::time_point t0;
@@ -382,6 +396,7 @@ struct Engine {
     int tz_opt = 0;
     int inner_maxit = 0;
     double inner_tol = kDefaultInnerTol;
+    bool frac_space = false;  // slots reserve room for cut-cell fractions
     char *arena = nullptr;
     size_t arena_bytes = 0;
     int max_slots = 0;
@@ -402,7 +417,8 @@ struct Engine {
     int64_t total_tiles = 0;
     int nrunning = 0;
     bool is_batch = false;  // created by pcg_batch_create (batch tile table)
-    int modes = 0;          // bit 0: a running slot uses densities, bit 1: classes
+    int modes = 0;          // bit m: a running slot uses coefficient mode m
+                            // (0 densities, 1 classes, 2 densities + fractions)
     int graph_modes = -1;   // modes the captured graph was built for
     // timing mode
     bool timing = false;
@@ -442,6 +458,7 @@ struct Engine {
             if (o->inner_tol > 0.0) inner_tol = o->inner_tol;
             tz_opt = o->tz;
             grid_opt = o->grid_blocks;
+            frac_space = (o->flags & PCG_FRACTIONS) != 0;
         }
         arena = (char *)arena_ptr;
         arena_bytes = bytes;
@@ -477,6 +494,50 @@ struct Engine {
 
     bool batch_mode() const { return is_batch; }
 
+    static void set_frac(Slot &d, const SlotHost &S)
+    {
+        d.ax = S.has_frac ? S.ax : nullptr;
+        d.ay = S.has_frac ? S.ay : nullptr;
+        d.az = S.has_frac ? S.az : nullptr;
+        d.vol = S.has_frac ? S.vol : nullptr;
+    }
+
+    // Cut-cell fractions for a prepared slot that is not running: copy the
+    // caller's arrays into the slot's reserved space and validate them on the
+    // device (areas in [0, 1], fluid volumes in (0, 1]); all NULL clears.
+    int set_fractions(int id, const double *ax, const double *ay, const double *az,
+                      const double *vol)
+    {
+        if (id < 0 || id >= max_slots || !slots[id].used) return PCG_EINVAL;
+        SlotHost &S = slots[id];
+        if (S.running) return PCG_EBUSY;
+        const int given = (ax != nullptr) + (ay != nullptr) + (az != nullptr) + (vol != nullptr);
+        if (given != 0 && given != 4) return PCG_EINVAL;
+        if (view_id == id) view_id = -1;
+        table_dirty = true;
+        S.has_frac = false;
+        if (!given) return PCG_OK;
+        if (!S.ax) return PCG_EINVAL;   // no room reserved (PCG_FRACTIONS not set)
+        const size_t nx = S.geo.nx, ny = S.geo.ny, nz = S.geo.nz;
+        const size_t nu = (nx + 1) * ny * nz, nv = nx * (ny + 1) * nz, nw = nx * ny * (nz + 1),
+                     n = nx * ny * nz;
+        *h_bad = 0;
+        hipError_t e = hipMemcpyAsync(d_bad, h_bad, sizeof(int), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(S.ax, ax, 8 * nu, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(S.ay, ay, 8 * nv, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(S.az, az, 8 * nw, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(S.vol, vol, 8 * n, hipMemcpyDeviceToDevice, stream);
+        if (e == hipSuccess)
+            e = launch_check_frac(S.ax, S.ay, S.az, S.vol, S.rho64, (int64_t)nu, (int64_t)nv,
+                                  (int64_t)nw, (int64_t)n, d_bad, stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(h_bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "fractions");
+        if (*h_bad) return PCG_EDOMAIN;
+        S.has_frac = true;
+        return PCG_OK;
+    }
+
     // Device description of a prepared slot for the projection kernels:
     // written into the head's spare slot entry when no solve runs.
     int slot_view(int id, Slot **d_slot)
@@ -491,9 +552,10 @@ struct Engine {
         d.permask = S.permask;
         d.h2 = S.h2;
         d.rho64 = S.rho64;
-        d.cls = S.classes ? S.cls : nullptr;
+        d.cls = S.classes && !S.has_frac ? S.cls : nullptr;
         d.tab64 = S.tab64;
         d.ntiles = S.geo.ntiles;
+        set_frac(d, S);
         HIP_TRY(hipMemcpyAsync(d_slots, h_slots, sizeof(Slot), hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         table_dirty = true;      // the solve path rebuilds the table before use
@@ -504,7 +566,7 @@ struct Engine {
 
     size_t footprint(const pcg_grid_t &g) const
     {
-        return slot_bytes(make_geometry(g, prec, tz_opt, batch_mode()), prec);
+        return slot_bytes(make_geometry(g, prec, tz_opt, batch_mode()), prec, frac_space);
     }
 
     // Reserve a slot and its memory, encode the density.  Does not start a solve.
@@ -522,7 +584,7 @@ struct Engine {
             if (!slots[i].used) { id = i; break; }
         if (id < 0) return PCG_EBUSY;
         const Geometry geo = make_geometry(*grid_, prec, tz_opt, batch_mode());
-        const size_t need = slot_bytes(geo, prec);
+        const size_t need = slot_bytes(geo, prec, frac_space);
         size_t off = 0;
         if (!alloc.alloc(need, &off)) return max_slots == 1 ? PCG_ENOMEM : PCG_EBUSY;
 
@@ -549,6 +611,14 @@ struct Engine {
         p += align_up(n, kAlign);
         S.tab64 = (double *)p;
         S.tab32 = (float *)(p + kClasses * kClasses * 8);
+        p += align_up(kClasses * kClasses * 12, kAlign);
+        if (frac_space) {
+            const size_t nx = geo.nx, ny = geo.ny, nz = geo.nz;
+            S.ax = (double *)p; p += align_up(8 * (nx + 1) * ny * nz, kAlign);
+            S.ay = (double *)p; p += align_up(8 * nx * (ny + 1) * nz, kAlign);
+            S.az = (double *)p; p += align_up(8 * nx * ny * (nz + 1), kAlign);
+            S.vol = (double *)p;
+        }
 
         st = encode_slot(S, rho, mask, flags);
         if (st) { alloc.release(off, need); S = SlotHost{}; return st; }
@@ -739,10 +809,11 @@ struct Engine {
             d.d32 = S.d32;
             d.partials = S.partials;
             d.st = d_states + id;
-            d.cls = S.classes ? S.cls : nullptr;
+            d.cls = S.classes && !S.has_frac ? S.cls : nullptr;
+            set_frac(d, S);
             d.tab64 = S.tab64;
             d.tab32 = S.tab32;
-            m |= S.classes ? 2 : 1;
+            m |= S.has_frac ? 4 : S.classes ? 2 : 1;
             tb += S.geo.ntiles;
         }
         h_hdr->total_tiles = tb;
@@ -798,7 +869,7 @@ struct Engine {
     {
         hipError_t e = launch_iter(prec, 0, 0, grid, d_hdr, d_slots, s);
         for (int w = 1; w < 3 && e == hipSuccess; ++w)
-            for (int m = 0; m < 2 && e == hipSuccess; ++m)
+            for (int m = 0; m < 3 && e == hipSuccess; ++m)
                 if (modes & (1 << m)) e = launch_iter(prec, w, m, grid, d_hdr, d_slots, s);
         return e;
     }
@@ -816,7 +887,7 @@ struct Engine {
         HIP_TRY(hipEventRecord(ev[0], stream));
         for (int i = 0; i < check_every; ++i)
             for (int w = 0; w < 3; ++w) {
-                for (int m = 0; m < 2; ++m)
+                for (int m = 0; m < 3; ++m)
                     if (w == 0 ? m == 0 : (modes & (1 << m)) != 0)
                         HIP_TRY(launch_iter(prec, w, m, grid, d_hdr, d_slots, stream));
                 HIP_TRY(hipEventRecord(ev[3 * i + w + 1], stream));
@@ -934,7 +1005,7 @@ int pcg_workspace_bytes(const pcg_grid_t *grid, const pcg_opts_t *opts,
     if (st) return st;
     const int prec = opts ? opts->precision : PCG_PREC_FP64;
     const Geometry G = make_geometry(*grid, prec, opts ? opts->tz : 0, false);
-    *out_bytes = head_bytes(1) + slot_bytes(G, prec);
+    *out_bytes = head_bytes(1) + slot_bytes(G, prec, opts && (opts->flags & PCG_FRACTIONS));
     return PCG_OK;
 }
 
@@ -1117,6 +1188,13 @@ int pcg_rhs(pcg_ctx_t *c, double dt, const double *au, const double *av,
     return PCG_OK;
 }
 
+int pcg_set_fractions(pcg_ctx_t *c, const double *ax, const double *ay, const double *az,
+                      const double *vol)
+{
+    if (!c) return PCG_EINVAL;
+    return c->eng.set_fractions(c->slot, ax, ay, az, vol);
+}
+
 int pcg_update_density(pcg_ctx_t *c, const double *rho, const uint8_t *solid_mask,
                        int32_t flags)
 {
@@ -1157,7 +1235,7 @@ int pcg_density_classes(const pcg_ctx_t *c, int32_t *nclasses)
 {
     if (!c || !nclasses) return PCG_EINVAL;
     const SlotHost &S = c->eng.slots[c->slot];
-    *nclasses = S.classes ? std::max(1, S.nclasses) : 0;
+    *nclasses = S.classes && !S.has_frac ? std::max(1, S.nclasses) : 0;
     return PCG_OK;
 }
 
@@ -1210,6 +1288,7 @@ int pcg_batch_create(pcg_batch_t **out, void *arena, size_t arena_bytes,
     if (!out) return PCG_EINVAL;
     *out = nullptr;
     if (max_slots < 1) return PCG_EINVAL;
+    if (opts && (opts->flags & PCG_FRACTIONS)) return PCG_EINVAL;   // contexts only
     pcg_batch *b = new (std::nothrow) pcg_batch();
     if (!b) return PCG_ENOMEM;
     b->eng.is_batch = true;

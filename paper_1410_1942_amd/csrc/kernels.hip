@@ -156,6 +156,15 @@ __device__ __forceinline__ T fb(T den)
 // Both give the same operator; classes move 1 byte per cell instead of 8
 // and need no reciprocal per face.
 
+// Area fractions of the six faces of a cell (x-, x+, y-, y+, z-, z+): the
+// weights of the face coefficients (and of the Dirichlet wall terms) in the
+// finite-volume form with free-slip cut cells.  Without cut cells they are 1
+// at compile time and the multiplications vanish.
+template <typename T>
+struct Areas6 {
+    T xm, xp, ym, yp, zm, zp;
+};
+
 template <typename T>
 struct RhoCoef {
     using Key = T;
@@ -165,6 +174,10 @@ struct RhoCoef {
     __device__ __forceinline__ Key neumann() const { return (T)INFINITY; }
     __device__ __forceinline__ bool solid(Key k) const { return isinf(k); }
     __device__ __forceinline__ T beta(Key a, Key b) const { return fb(a + b); }
+    __device__ __forceinline__ Areas6<T> areas(int, int, int, int64_t) const
+    {
+        return { T(1), T(1), T(1), T(1), T(1), T(1) };
+    }
 };
 
 template <typename T>
@@ -177,7 +190,57 @@ struct ClsCoef {
     __device__ __forceinline__ Key neumann() const { return kClsSolid; }
     __device__ __forceinline__ bool solid(Key k) const { return k == kClsSolid; }
     __device__ __forceinline__ T beta(Key a, Key b) const { return tab[a * kClasses + b]; }
+    __device__ __forceinline__ Areas6<T> areas(int, int, int, int64_t) const
+    {
+        return { T(1), T(1), T(1), T(1), T(1), T(1) };
+    }
 };
+
+// Per-cell density with free-slip cut cells: the density key of RhoCoef and
+// the area fractions of the MAC faces (FP64, converted for FP32 passes).  On
+// a periodic axis the face beyond the last cell is the row's face 0.
+template <typename T>
+struct FracCoef {
+    using Key = T;
+    const GLB T *__restrict__ rho;
+    const GLB double *__restrict__ ax;
+    const GLB double *__restrict__ ay;
+    const GLB double *__restrict__ az;
+    int nx, ny;
+    int64_t P;
+    bool perx, pery;
+    __device__ __forceinline__ Key load(int64_t c) const { return rho[c]; }
+    __device__ __forceinline__ Key dirichlet() const { return T(0); }
+    __device__ __forceinline__ Key neumann() const { return (T)INFINITY; }
+    __device__ __forceinline__ bool solid(Key k) const { return isinf(k); }
+    __device__ __forceinline__ T beta(Key a, Key b) const { return fb(a + b); }
+    __device__ __forceinline__ Areas6<T> areas(int i, int j, int k, int64_t c) const
+    {
+        const int64_t fu = ((int64_t)k * ny + j) * (nx + 1) + i;
+        const int64_t fv = ((int64_t)k * (ny + 1) + j) * nx + i;
+        Areas6<T> a;
+        a.xm = (T)ax[fu];
+        a.xp = (T)ax[(perx && i == nx - 1) ? fu - i : fu + 1];
+        a.ym = (T)ay[fv];
+        a.yp = (T)ay[(pery && j == ny - 1) ? fv - (int64_t)j * nx : fv + nx];
+        a.zm = (T)az[c];
+        a.zp = (T)az[c + P];
+        return a;
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ FracCoef<T> frac_coef(const Slot &S, const T *rho)
+{
+    return { gp(rho), gp(S.ax), gp(S.ay), gp(S.az), S.nx, S.ny, (int64_t)S.nx * S.ny,
+             (S.permask & 1) != 0, (S.permask & 2) != 0 };
+}
+
+// Volume fraction of cell c (1 without cut cells): weights the source.
+__device__ __forceinline__ double vol_at(const Slot &S, int64_t c)
+{
+    return S.vol ? gp(S.vol)[c] : 1.0;
+}
 
 // Per-thread neighbour description for the x/y faces of a column: offset to
 // the neighbour (across a periodic wall, the cell at the other end; 0 at
@@ -225,7 +288,8 @@ __device__ __forceinline__ void apply_cell(Fetch v, const C &cf, int64_t c,
                                            const Nbr<typename C::Key> &n, T vc,
                                            typename C::Key kc, T vzm,
                                            typename C::Key kzm, T vzp,
-                                           typename C::Key kzp, T &q, T &dg)
+                                           typename C::Key kzp, const Areas6<T> &ar,
+                                           T &q, T &dg)
 {
     using K = typename C::Key;
     // loads are unconditional (wall offsets are 0); walls substituted after
@@ -237,9 +301,9 @@ __device__ __forceinline__ void apply_cell(Fetch v, const C &cf, int64_t c,
     const K kym = n.hym ? lkym : n.wym, kyp = n.hyp ? lkyp : n.wyp;
     const T vxm = n.hxm ? lvxm : T(0), vxp = n.hxp ? lvxp : T(0);
     const T vym = n.hym ? lvym : T(0), vyp = n.hyp ? lvyp : T(0);
-    const T bxm = cf.beta(kc, kxm), bxp = cf.beta(kc, kxp);
-    const T bym = cf.beta(kc, kym), byp = cf.beta(kc, kyp);
-    const T bzm = cf.beta(kc, kzm), bzp = cf.beta(kc, kzp);
+    const T bxm = cf.beta(kc, kxm) * ar.xm, bxp = cf.beta(kc, kxp) * ar.xp;
+    const T bym = cf.beta(kc, kym) * ar.ym, byp = cf.beta(kc, kyp) * ar.yp;
+    const T bzm = cf.beta(kc, kzm) * ar.zm, bzp = cf.beta(kc, kzp) * ar.zp;
     dg = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
     q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) + (bym * (vc - vym) + byp * (vc - vyp))) +
         (bzm * (vc - vzm) + bzp * (vc - vzp));
@@ -250,15 +314,16 @@ template <typename T, class C>
 __device__ __forceinline__ T diag_cell(const C &cf, int64_t c,
                                        const Nbr<typename C::Key> &n,
                                        typename C::Key kc, typename C::Key kzm,
-                                       typename C::Key kzp)
+                                       typename C::Key kzp, const Areas6<T> &ar)
 {
     using K = typename C::Key;
     const K lkxm = cf.load(c + n.oxm), lkxp = cf.load(c + n.oxp);
     const K lkym = cf.load(c + n.oym), lkyp = cf.load(c + n.oyp);
     const K kxm = n.hxm ? lkxm : n.wxm, kxp = n.hxp ? lkxp : n.wxp;
     const K kym = n.hym ? lkym : n.wym, kyp = n.hyp ? lkyp : n.wyp;
-    return ((cf.beta(kc, kxm) + cf.beta(kc, kxp)) + (cf.beta(kc, kym) + cf.beta(kc, kyp))) +
-           (cf.beta(kc, kzm) + cf.beta(kc, kzp));
+    return ((cf.beta(kc, kxm) * ar.xm + cf.beta(kc, kxp) * ar.xp) +
+            (cf.beta(kc, kym) * ar.ym + cf.beta(kc, kyp) * ar.yp)) +
+           (cf.beta(kc, kzm) * ar.zm + cf.beta(kc, kzp) * ar.zp);
 }
 
 // x + s d, evaluated identically wherever the refined iterate is needed.
@@ -310,15 +375,16 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
         double xzp = 0.0;
         if (!top) { kzp = cf.load(c + P); if (warm) xzp = xv(c + P); }
         const bool solid = cf.solid(kc);
-        const double b = solid ? 0.0 : -S.h2 * rhs[c] - st.bshift;
+        const double b = solid ? 0.0 : -S.h2 * vol_at(S, c) * rhs[c] - st.bshift;
         double r, dg;
         if (warm) {
             double q;
-            apply_cell<double>(xv, cf, c, n, xc, kc, xzm, kzm, xzp, kzp, q, dg);
+            apply_cell<double>(xv, cf, c, n, xc, kc, xzm, kzm, xzp, kzp,
+                               cf.areas(t.i, t.j, k, c), q, dg);
             r = solid ? 0.0 : b - q;
             if (solid) x[c] = 0.0;
         } else {
-            dg = diag_cell<double>(cf, c, n, kc, kzm, kzp);
+            dg = diag_cell<double>(cf, c, n, kc, kzm, kzp, cf.areas(t.i, t.j, k, c));
             r = b;
             x[c] = 0.0;
         }
@@ -434,9 +500,12 @@ template <typename T>
 __device__ __forceinline__ const void *key_array(const RhoCoef<T> &cf) { return (const void *)cf.rho; }
 template <typename T>
 __device__ __forceinline__ const void *key_array(const ClsCoef<T> &cf) { return (const void *)cf.cls; }
+template <typename T>
+__device__ __forceinline__ const void *key_array(const FracCoef<T> &cf) { return (const void *)cf.rho; }
 template <class C> struct KeyElem;
 template <typename T> struct KeyElem<RhoCoef<T>> { using type = T; };
 template <typename T> struct KeyElem<ClsCoef<T>> { using type = uint8_t; };
+template <typename T> struct KeyElem<FracCoef<T>> { using type = T; };
 
 // K1_CG_A / K1_IR_A: p_new = z + beta p_old, stored; the quadratic form
 // p.Ap = sum over faces of beta_f (p_c - p_n)^2, each face counted once
@@ -475,7 +544,7 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
     const LaneOff ok = lane_off(t, n, (int)sizeof(KE));
     const int bm = S.bcmask;
     // Dirichlet high walls of this column (x+, y+); z+ is added on the top plane
-    const int hw = ((!n.hxp && (bm & 2)) ? 1 : 0) + ((!n.hyp && (bm & 8)) ? 1 : 0);
+    const bool hwx = !n.hxp && (bm & 2), hwy = !n.hyp && (bm & 8);
     const int nz = S.nz;
     auto load = [&](int kk) {
         kk = kk < t.k1 ? kk : t.k1 - 1;    // past the tile's end: re-read its last plane
@@ -502,10 +571,14 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
         const T pxm = n.hxm ? L.zxm + beta * L.qxm : T(0);
         const T pym = n.hym ? L.zym + beta * L.qym : T(0);
         const T dx = pc - pxm, dy = pc - pym, dz = pc - pzm;
-        T s = (cf.beta(L.kc, kxm) * dx * dx + cf.beta(L.kc, kym) * dy * dy) +
-              cf.beta(L.kc, kzm) * dz * dz;
-        const int w = hw + ((kk == nz - 1 && (bm & 32)) ? 1 : 0);
-        s += (T)w * cf.beta(L.kc, cf.dirichlet()) * (pc * pc);   // + 0 without walls
+        const Areas6<T> ar = cf.areas(t.i, t.j, kk, (int64_t)kk * t.P + t.q);
+        T s = (cf.beta(L.kc, kxm) * ar.xm * dx * dx + cf.beta(L.kc, kym) * ar.ym * dy * dy) +
+              cf.beta(L.kc, kzm) * ar.zm * dz * dz;
+        // Dirichlet high walls (x+, y+ of this column, z+ on the top plane),
+        // each weighted by its area
+        const T w = (hwx ? ar.xp : T(0)) + (hwy ? ar.yp : T(0)) +
+                    ((kk == nz - 1 && (bm & 32)) ? ar.zp : T(0));
+        s += w * cf.beta(L.kc, cf.dirichlet()) * (pc * pc);   // + 0 without walls
         a += (double)s;
         bstore_nt(bpd, ov.c, W.so(kk, sizeof(T)), pc);
         pzm = pc;
@@ -545,7 +618,7 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
     T vzm = T(0);
     K kzm = n.wzm;
     if (t.k0 > 0) { vzm = p[c - P]; kzm = cf.load(c - P); }
-    T bzm = cf.beta(kc, kzm);
+    T bzm = cf.beta(kc, kzm) * cf.areas(t.i, t.j, t.k0, c).zm;
     double a0 = 0.0, a1 = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += P) {
         const bool top = k == S.nz - 1;
@@ -564,9 +637,10 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
         const K kym = n.hym ? lkym : n.wym, kyp = n.hyp ? lkyp : n.wyp;
         const T vxm = n.hxm ? lvxm : T(0), vxp = n.hxp ? lvxp : T(0);
         const T vym = n.hym ? lvym : T(0), vyp = n.hyp ? lvyp : T(0);
-        const T bxm = cf.beta(kc, kxm), bxp = cf.beta(kc, kxp);
-        const T bym = cf.beta(kc, kym), byp = cf.beta(kc, kyp);
-        const T bzp = cf.beta(kc, kzp);
+        const Areas6<T> ar = cf.areas(t.i, t.j, k, c);
+        const T bxm = cf.beta(kc, kxm) * ar.xm, bxp = cf.beta(kc, kxp) * ar.xp;
+        const T bym = cf.beta(kc, kym) * ar.ym, byp = cf.beta(kc, kyp) * ar.yp;
+        const T bzp = cf.beta(kc, kzp) * ar.zp;
         const T dg = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
         const T q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) +
                      (bym * (vc - vym) + byp * (vc - vyp))) +
@@ -614,9 +688,10 @@ __device__ void body_check64(const Slot &S, const SlotState &st, int64_t lt,
         K kzp = n.wzp;
         if (!top) { vzp = x[c + P]; kzp = cf.load(c + P); }
         double q, dg;
-        apply_cell<double>(xv, cf, c, n, vc, kc, vzm, kzm, vzp, kzp, q, dg);
+        apply_cell<double>(xv, cf, c, n, vc, kc, vzm, kzm, vzp, kzp,
+                           cf.areas(t.i, t.j, k, c), q, dg);
         if (!cf.solid(kc)) {
-            const double r = (-S.h2 * rhs[c] - st.bshift) - q;
+            const double r = (-S.h2 * vol_at(S, c) * rhs[c] - st.bshift) - q;
             a += r * r;
         }
         vzm = vc; kzm = kc;
@@ -647,7 +722,7 @@ __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
         d[c] = 0.0f;
         pa[c] = 0.0f;
         pb[c] = 0.0f;
-        const double b = solid ? 0.0 : -S.h2 * rhs[c] - st.bshift;
+        const double b = solid ? 0.0 : -S.h2 * vol_at(S, c) * rhs[c] - st.bshift;
         a += b * b;
     }
     acc[0] += a;
@@ -690,10 +765,12 @@ __device__ void body_ir_resid(const Slot &S, const SlotState &st, int64_t lt,
         KF fzp = nf.wzp;
         if (!top) { vzp = xe(c + P); kzp = cf.load(c + P); fzp = cf32.load(c + P); }
         double q, dg;
-        apply_cell<double>(xe, cf, c, n, vc, kc, vzm, kzm, vzp, kzp, q, dg);
+        apply_cell<double>(xe, cf, c, n, vc, kc, vzm, kzm, vzp, kzp,
+                           cf.areas(t.i, t.j, k, c), q, dg);
         const bool solid = cf.solid(kc);
-        const double r = solid ? 0.0 : ((-S.h2 * rhs[c] - st.bshift) - q);
-        const float dg32 = diag_cell<float>(cf32, c, nf, fc, fzm, fzp);
+        const double r = solid ? 0.0 : ((-S.h2 * vol_at(S, c) * rhs[c] - st.bshift) - q);
+        const float dg32 = diag_cell<float>(cf32, c, nf, fc, fzm, fzp,
+                                            cf32.areas(t.i, t.j, k, c));
         const float z32 = dg32 > 0.0f ? (float)((scale * r) / (double)dg32) : 0.0f;
         z[c] = z32;
         const double rz = (double)dg32 * (double)z32;
@@ -750,7 +827,7 @@ __device__ void body_mean_b(const Slot &S, const SlotState &st, int64_t lt,
     int64_t c = (int64_t)t.k0 * t.P + t.q;
     for (int k = t.k0; k < t.k1; ++k, c += t.P) {
         if (cf.solid(cf.load(c))) continue;
-        a += -S.h2 * rhs[c];
+        a += -S.h2 * vol_at(S, c) * rhs[c];
         m += 1.0;
     }
     acc[0] += a;
@@ -968,6 +1045,31 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
 // keeps its register footprint (and so its occupancy) that of pass A alone.
 // K1 and K2 come in two coefficient modes (density, classes), each serving
 // only the slots of its mode; K0 serves both.
+// Coefficient mode of a slot: 0 per-cell density, 1 density classes,
+// 2 per-cell density with free-slip cut cells (area/volume fractions).
+__device__ __forceinline__ int slot_mode(const Slot &S)
+{
+    return S.ax ? 2 : (S.cls ? 1 : 0);
+}
+
+// The first-half actions of K0 in one coefficient source.
+template <class C>
+__device__ __forceinline__ void run_k0_fp64(int ph, const Slot &S, const SlotState &st,
+                                            int64_t lt, const C &cf, double (&acc)[3])
+{
+    if (ph == K1_INIT64) body_init64(S, st, lt, cf, acc);
+    else if (ph == K1_CHECK64) body_check64(S, st, lt, cf, acc);
+}
+
+template <class C64, class C32>
+__device__ __forceinline__ void run_k0_ir(int ph, const Slot &S, const SlotState &st,
+                                          int64_t lt, const C64 &cf, const C32 &cf32,
+                                          double (&acc)[3])
+{
+    if (ph == K1_IR_INIT) body_ir_init(S, st, lt, cf, acc);
+    else if (ph == K1_IR_RESID) body_ir_resid(S, st, lt, cf, cf32, acc);
+}
+
 template <int FAMILY, int WHICH, int MODE>
 __device__ __forceinline__ void run_body(int ph, const Slot &S,
                                          const SlotState &st, int64_t lt,
@@ -976,25 +1078,35 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
 {
     const RhoCoef<double> r64{ gp(S.rho64) };
     const ClsCoef<double> c64{ gp(S.cls), tab64 };
+    if (WHICH == 0) {
+        // rare actions: every slot, whatever its coefficient source
+        if (ph == K1_MEAN_B) { body_mean_b(S, st, lt, r64, acc); return; }
+        if (ph == K1_MEAN_X) { body_mean_x(S, st, lt, r64, acc); return; }
+        const int m = slot_mode(S);
+        if (FAMILY == PCG_PREC_FP64) {
+            if (m == 2) run_k0_fp64(ph, S, st, lt, frac_coef<double>(S, S.rho64), acc);
+            else if (m == 1) run_k0_fp64(ph, S, st, lt, c64, acc);
+            else run_k0_fp64(ph, S, st, lt, r64, acc);
+        } else {
+            if (m == 2)
+                run_k0_ir(ph, S, st, lt, frac_coef<double>(S, S.rho64),
+                          frac_coef<float>(S, S.rho32), acc);
+            else if (m == 1) run_k0_ir(ph, S, st, lt, c64, ClsCoef<float>{ gp(S.cls), tab32 }, acc);
+            else run_k0_ir(ph, S, st, lt, r64, RhoCoef<float>{ gp(S.rho32) }, acc);
+        }
+        return;
+    }
     if (FAMILY == PCG_PREC_FP64) {
-        if (WHICH == 0) {
-            if (ph == K1_MEAN_B) body_mean_b(S, st, lt, r64, acc);
-            else if (ph == K1_MEAN_X) body_mean_x(S, st, lt, r64, acc);
-            else if (S.cls) {
-                if (ph == K1_INIT64) body_init64(S, st, lt, c64, acc);
-                else if (ph == K1_CHECK64) body_check64(S, st, lt, c64, acc);
-            } else {
-                if (ph == K1_INIT64) body_init64(S, st, lt, r64, acc);
-                else if (ph == K1_CHECK64) body_check64(S, st, lt, r64, acc);
-            }
-        } else if (WHICH == 1) {
+        if (WHICH == 1) {
             if (ph == K1_CG_A) {
-                if (MODE) body_passA<double>(S, st, lt, c64, acc);
+                if (MODE == 2) body_passA<double>(S, st, lt, frac_coef<double>(S, S.rho64), acc);
+                else if (MODE == 1) body_passA<double>(S, st, lt, c64, acc);
                 else body_passA<double>(S, st, lt, r64, acc);
             }
         } else {
             if (ph == K2_CG_B) {
-                if (MODE) body_passB<double, double>(S, st, lt, c64, acc);
+                if (MODE == 2) body_passB<double, double>(S, st, lt, frac_coef<double>(S, S.rho64), acc);
+                else if (MODE == 1) body_passB<double, double>(S, st, lt, c64, acc);
                 else body_passB<double, double>(S, st, lt, r64, acc);
             } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
             else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);
@@ -1002,24 +1114,16 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
     } else {
         const RhoCoef<float> r32{ gp(S.rho32) };
         const ClsCoef<float> c32{ gp(S.cls), tab32 };
-        if (WHICH == 0) {
-            if (ph == K1_MEAN_B) body_mean_b(S, st, lt, r64, acc);
-            else if (ph == K1_MEAN_X) body_mean_x(S, st, lt, r64, acc);
-            else if (S.cls) {
-                if (ph == K1_IR_INIT) body_ir_init(S, st, lt, c64, acc);
-                else if (ph == K1_IR_RESID) body_ir_resid(S, st, lt, c64, c32, acc);
-            } else {
-                if (ph == K1_IR_INIT) body_ir_init(S, st, lt, r64, acc);
-                else if (ph == K1_IR_RESID) body_ir_resid(S, st, lt, r64, r32, acc);
-            }
-        } else if (WHICH == 1) {
+        if (WHICH == 1) {
             if (ph == K1_IR_A) {
-                if (MODE) body_passA<float>(S, st, lt, c32, acc);
+                if (MODE == 2) body_passA<float>(S, st, lt, frac_coef<float>(S, S.rho32), acc);
+                else if (MODE == 1) body_passA<float>(S, st, lt, c32, acc);
                 else body_passA<float>(S, st, lt, r32, acc);
             }
         } else {
             if (ph == K2_IR_B) {
-                if (MODE) body_passB<float, float>(S, st, lt, c32, acc);
+                if (MODE == 2) body_passB<float, float>(S, st, lt, frac_coef<float>(S, S.rho32), acc);
+                else if (MODE == 1) body_passB<float, float>(S, st, lt, c32, acc);
                 else body_passB<float, float>(S, st, lt, r32, acc);
             } else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);
             else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
@@ -1034,7 +1138,7 @@ __device__ __forceinline__ bool serves(const Slot &S, int ph)
     if (WHICH == 0)
         return ph == K1_INIT64 || ph == K1_CHECK64 || ph == K1_IR_INIT ||
                ph == K1_IR_RESID || ph == K1_MEAN_B || ph == K1_MEAN_X;
-    if ((S.cls != nullptr) != (MODE != 0)) return false;
+    if (slot_mode(S) != MODE) return false;
     if (WHICH == 1) return ph == K1_CG_A || ph == K1_IR_A;
     return ph >= 11 && ph <= 19;
 }
@@ -1293,7 +1397,9 @@ k_project(const Slot *__restrict__ slot, const double *__restrict__ p, double s,
 
 // Source of the pressure equation from face velocities:
 // rhs_c = ((du + dv) + dw) / h / dt with du = U_{i+1/2} - U_{i-1/2} (and so
-// on), U = a [+ b], in fluid cells; 0 in hull cells.  With b the second-stage
+// on), U = a [+ b], in fluid cells; 0 in hull cells.  With cut cells every
+// face value is weighted by its area fraction and the sum divided by the
+// cell's volume fraction.  With b the second-stage
 // source div(u* + u^k)/dt, without it the first-stage div(u^k)/dt.  On a
 // periodic axis the high face of the last cell is face 0 (the last face of
 // the array is not read).
@@ -1317,6 +1423,14 @@ __device__ void rhs_cells(const Slot &S, double h, double dt, FaceSet a, FaceSet
         // the high face of a periodic row's last cell is the row's face 0
         const int64_t fu1 = (perx && i == nx - 1) ? fu - i : fu + 1;
         const int64_t fv1 = (pery && j == ny - 1) ? fv - (int64_t)j * nx : fv + nx;
+        if (S.ax) {   // cut cells: area-weighted faces over the volume fraction
+            const GLB double *ax = gp(S.ax), *ay = gp(S.ay), *az = gp(S.az);
+            const double du = ax[fu1] * face_in<ADD>(a, b, 0, fu1) - ax[fu] * face_in<ADD>(a, b, 0, fu);
+            const double dv = ay[fv1] * face_in<ADD>(a, b, 1, fv1) - ay[fv] * face_in<ADD>(a, b, 1, fv);
+            const double dw = az[c + P] * face_in<ADD>(a, b, 2, c + P) - az[c] * face_in<ADD>(a, b, 2, c);
+            out[c] = ((du + dv) + dw) / (gp(S.vol)[c] * h) / dt;
+            continue;
+        }
         const double du = face_in<ADD>(a, b, 0, fu1) - face_in<ADD>(a, b, 0, fu);
         const double dv = face_in<ADD>(a, b, 1, fv1) - face_in<ADD>(a, b, 1, fv);
         const double dw = face_in<ADD>(a, b, 2, c + P) - face_in<ADD>(a, b, 2, c);
@@ -1333,7 +1447,8 @@ k_rhs(const Slot *__restrict__ slot, double h, double dt, FaceSet a, FaceSet b,
 }
 
 // (D u)_c = (u_{i+1/2} - u_{i-1/2} + v_{j+1/2} - v_{j-1/2} + w_{k+1/2} -
-// w_{k-1/2}) / h over fluid cells (periodic axes as in the source kernel):
+// w_{k-1/2}) / h over fluid cells (periodic axes and cut cells as in the
+// source kernel):
 // per-workgroup sum of squares and maximum magnitude, combined on the host in
 // workgroup order.
 __global__ void __launch_bounds__(256)
@@ -1358,7 +1473,14 @@ k_divnorm(const Slot *__restrict__ slot, double inv_h, const double *__restrict_
         const int64_t fv = ((int64_t)k * (ny + 1) + j) * nx + i;
         const int64_t fu1 = (perx && i == nx - 1) ? fu - i : fu + 1;
         const int64_t fv1 = (pery && j == ny - 1) ? fv - (int64_t)j * nx : fv + nx;
-        const double d = ((u[fu1] - u[fu]) + (v[fv1] - v[fv]) + (w[c + P] - w[c])) * inv_h;
+        double d;
+        if (S.ax) {   // cut cells: area-weighted faces over the volume fraction
+            const GLB double *ax = gp(S.ax), *ay = gp(S.ay), *az = gp(S.az);
+            d = ((ax[fu1] * u[fu1] - ax[fu] * u[fu]) + (ay[fv1] * v[fv1] - ay[fv] * v[fv]) +
+                 (az[c + P] * w[c + P] - az[c] * w[c])) / gp(S.vol)[c] * inv_h;
+        } else {
+            d = ((u[fu1] - u[fu]) + (v[fv1] - v[fv]) + (w[c + P] - w[c])) * inv_h;
+        }
         ss += d * d;
         mx = fmax(mx, fabs(d));
     }
@@ -1371,6 +1493,25 @@ k_divnorm(const Slot *__restrict__ slot, double inv_h, const double *__restrict_
         part[2 * blockIdx.x] = (lds[0] + lds[1]) + (lds[2] + lds[3]);
         part[2 * blockIdx.x + 1] = fmax(fmax(lds[4], lds[5]), fmax(lds[6], lds[7]));
     }
+}
+
+// Validation of cut-cell fractions: every area in [0, 1] and every fluid
+// cell's volume in (0, 1] (NaN fails both); sets *bad otherwise.
+__global__ void __launch_bounds__(256)
+k_check_frac(const double *__restrict__ ax, const double *__restrict__ ay,
+             const double *__restrict__ az, const double *__restrict__ vol,
+             const double *__restrict__ rho64, int64_t nu, int64_t nv, int64_t nw,
+             int64_t n, int *bad)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = true;
+    for (int64_t f = i0; f < nu; f += stride) ok = ok && ax[f] >= 0.0 && ax[f] <= 1.0;
+    for (int64_t f = i0; f < nv; f += stride) ok = ok && ay[f] >= 0.0 && ay[f] <= 1.0;
+    for (int64_t f = i0; f < nw; f += stride) ok = ok && az[f] >= 0.0 && az[f] <= 1.0;
+    for (int64_t c = i0; c < n; c += stride)
+        ok = ok && (isinf(rho64[c]) || (vol[c] > 0.0 && vol[c] <= 1.0));
+    if (!ok) atomicOr(bad, 1);
 }
 
 // Copy probe: one element per thread, one pass (the fastest plain copy
@@ -1393,12 +1534,26 @@ hipError_t launch_iter(int family, int which, int mode, int grid,
 #define PCG_LAUNCH(F, W, M) hipLaunchKernelGGL((k_iter<F, W, M>), g, b, 0, s, hdr, slots)
     if (family == PCG_PREC_FP64) {
         if (which == 0) PCG_LAUNCH(PCG_PREC_FP64, 0, 0);
-        else if (which == 1) { if (mode) PCG_LAUNCH(PCG_PREC_FP64, 1, 1); else PCG_LAUNCH(PCG_PREC_FP64, 1, 0); }
-        else { if (mode) PCG_LAUNCH(PCG_PREC_FP64, 2, 1); else PCG_LAUNCH(PCG_PREC_FP64, 2, 0); }
+        else if (which == 1) {
+            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP64, 1, 2);
+            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP64, 1, 1);
+            else PCG_LAUNCH(PCG_PREC_FP64, 1, 0);
+        } else {
+            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP64, 2, 2);
+            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP64, 2, 1);
+            else PCG_LAUNCH(PCG_PREC_FP64, 2, 0);
+        }
     } else {
         if (which == 0) PCG_LAUNCH(PCG_PREC_FP32_IR, 0, 0);
-        else if (which == 1) { if (mode) PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 1); else PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 0); }
-        else { if (mode) PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 1); else PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 0); }
+        else if (which == 1) {
+            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 2);
+            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 1);
+            else PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 0);
+        } else {
+            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 2);
+            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 1);
+            else PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 0);
+        }
     }
 #undef PCG_LAUNCH
     return hipGetLastError();
@@ -1452,6 +1607,18 @@ hipError_t launch_divnorm(const Slot *slot, double inv_h, const double *u,
 {
     hipLaunchKernelGGL(k_divnorm, dim3(blocks), dim3(256), 0, st, slot, inv_h, u, v, w,
                        part);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_frac(const double *ax, const double *ay, const double *az,
+                             const double *vol, const double *rho64, int64_t nu, int64_t nv,
+                             int64_t nw, int64_t n, int *bad, hipStream_t s)
+{
+    int64_t blocks = (nw + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_check_frac, dim3((unsigned)blocks), dim3(256), 0, s, ax, ay, az, vol,
+                       rho64, nu, nv, nw, n, bad);
     return hipGetLastError();
 }
 

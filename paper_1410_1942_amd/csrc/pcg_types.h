@@ -100,6 +100,10 @@ struct Slot {
     const uint8_t *cls;    // density class per cell, or null (density path)
     const double *tab64;   // kClasses^2 face coefficients 2/(rho_a + rho_b)
     const float *tab32;    // the same in FP32 (FP32+IR only)
+    // free-slip cut cells, or null: area fractions on the MAC faces
+    // (ax [nz][ny][nx+1], ay [nz][ny+1][nx], az [nz+1][ny][nx]) and volume
+    // fractions per cell
+    const double *ax, *ay, *az, *vol;
 };
 
 struct BatchHeader {

@@ -131,6 +131,21 @@ class Solver:
         L.check(self.lib.pcg_density_classes(self._ctx, ctypes.byref(n)), "classes")
         return n.value
 
+    def set_fractions(self, ax=None, ay=None, az=None, vol=None):
+        """Free-slip cut-cell fractions (pcg_set_fractions): MAC face area
+        fractions ax[nz,ny,nx+1], ay[nz,ny+1,nx], az[nz+1,ny,nx] and cell
+        volume fractions vol[nz,ny,nx], float64 device tensors; no arguments
+        clears them.  Needs a Solver created with flags including FRACTIONS."""
+        if ax is None and ay is None and az is None and vol is None:
+            L.check(self.lib.pcg_set_fractions(self._ctx, None, None, None, None),
+                    "pcg_set_fractions")
+            return
+        a = self._faces((ax, ay, az), "fractions")
+        _require_device(vol)
+        if vol.dtype != torch.float64 or tuple(vol.shape) != self.shape:
+            raise ValueError("vol must be float64 with the grid's shape")
+        L.check(self.lib.pcg_set_fractions(self._ctx, *a, _ptr(vol)), "pcg_set_fractions")
+
     def _faces(self, faces, what):
         nz, ny, nx = self.shape
         if faces is None or len(faces) != 3:

@@ -252,3 +252,20 @@ def test_plane_and_tile_span_limits(lib):
         sizes[tz] = out.value
     assert sizes[31] == sizes[30] == sizes[64]  # clamped to 30
     assert sizes[16] != sizes[30]
+
+
+def test_fraction_flag_host_rules(lib):
+    """PCG_FRACTIONS reserves workspace for the four fraction arrays, is
+    refused by batches, and pcg_set_fractions checks its context."""
+    o = L.Opts()
+    base, more = ctypes.c_size_t(), ctypes.c_size_t()
+    g = _g(20, 16, 12)
+    assert lib.pcg_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ctypes.byref(base)) == L.OK
+    o.flags = L.FRACTIONS
+    assert lib.pcg_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ctypes.byref(more)) == L.OK
+    faces = 21 * 16 * 12 + 20 * 17 * 12 + 20 * 16 * 13 + 20 * 16 * 12
+    assert 8 * faces <= more.value - base.value <= 8 * faces + 4 * 256
+    b = ctypes.c_void_p()
+    assert lib.pcg_batch_create(ctypes.byref(b), ctypes.c_void_p(0x1000), 1 << 20, 2,
+                                ctypes.byref(o), None) == L.EINVAL
+    assert lib.pcg_set_fractions(None, None, None, None, None) == L.EINVAL
