@@ -277,8 +277,22 @@ struct FluidRegions {
     int64_t unanchored = 0;
 };
 
-FluidRegions fluid_regions(const std::vector<uint8_t> &solid, int nx, int ny, int nz,
-                           int bcmask, int permask)
+// First index >= i of a nonzero (solid) byte in m[0, nx), or nx; fluid rows
+// are mostly zeros, so whole 8-byte words are skipped at a time.
+static int next_solid(const uint8_t *m, int i, int nx)
+{
+    while (i + 8 <= nx) {
+        uint64_t w;
+        std::memcpy(&w, m + i, 8);
+        if (w) break;
+        i += 8;
+    }
+    while (i < nx && !m[i]) ++i;
+    return i;
+}
+
+FluidRegions fluid_regions(const uint8_t *solid, int nx, int ny, int nz, int bcmask,
+                           int permask)
 {
     const int64_t nrows = (int64_t)ny * nz;
     std::vector<int64_t> row_start(nrows + 1, 0);
@@ -289,13 +303,13 @@ FluidRegions fluid_regions(const std::vector<uint8_t> &solid, int nx, int ny, in
     run_row.reserve(nrows * 2);
     for (int64_t r = 0; r < nrows; ++r) {
         row_start[r] = (int64_t)ra.size();
-        const uint8_t *m = solid.data() + r * nx;
+        const uint8_t *m = solid + r * nx;
         int i = 0;
         while (i < nx) {
             while (i < nx && m[i]) ++i;
             if (i >= nx) break;
             const int a = i;
-            while (i < nx && !m[i]) ++i;
+            i = next_solid(m, i, nx);
             ra.push_back(a);
             rb.push_back(i);
             run_row.push_back(r);
@@ -646,7 +660,7 @@ struct Engine {
             hipError_t e = hipMemcpy(h.data(), mask, (size_t)geo.n, hipMemcpyDeviceToHost);
             if (e != hipSuccess) return hip_fail(e, "mask copy");
             const int kind = classify_regions(
-                fluid_regions(h, geo.nx, geo.ny, geo.nz, S.bcmask, S.permask));
+                fluid_regions(h.data(), geo.nx, geo.ny, geo.nz, S.bcmask, S.permask));
             if (kind < 0) return kind;
             S.singular = kind == 1;
         }
@@ -1095,9 +1109,8 @@ int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
     st = check_bc(bc, &bm, &per);
     if (st) return st;
     if (!host_mask) return bm ? PCG_OK : PCG_SINGULAR;   // one region
-    const size_t n = (size_t)grid->nx * grid->ny * grid->nz;
-    std::vector<uint8_t> m(host_mask, host_mask + n);
-    const int kind = classify_regions(fluid_regions(m, grid->nx, grid->ny, grid->nz, bm, per));
+    const int kind = classify_regions(
+        fluid_regions(host_mask, grid->nx, grid->ny, grid->nz, bm, per));
     return kind < 0 ? kind : kind == 1 ? PCG_SINGULAR : PCG_OK;
 }
 

@@ -597,9 +597,13 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
 }
 
 // K2_CG_B (T = double, X = double: x) / K2_IR_B (T = float, X = float: d):
-// q = A p, x += alpha p, z -= alpha q / diag; acc = [r.z, r.r] with
-// r = diag z.  The low z face coefficient is carried from the plane below.
-template <typename T, typename X, class C>
+// q = A p, z -= alpha q / diag; acc = [r.z, r.r] with r = diag z.  The low z
+// face coefficient is carried from the plane below.  XM says what happens to
+// x: 1 x += alpha p (every iteration, the FP32 inner solve); 0 nothing (the
+// update is left pending); 2 x += alpha_prev p_prev, then += alpha p, with
+// p_prev still in the other direction buffer.  FP64 solves alternate 0 and 2,
+// reading and writing x every second iteration only.
+template <typename T, typename X, class C, int XM = 1>
 __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
                            const C &cf, double (&acc)[3])
 {
@@ -607,9 +611,11 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
     const GLB T *__restrict__ p = gp((const T *)(st.pbuf ? S.pb : S.pa));
+    const GLB T *__restrict__ pprev = gp((const T *)(st.pbuf ? S.pa : S.pb));
     GLB T *__restrict__ z = gp((T *)S.z);
     GLB X *__restrict__ x = gp(std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32);
     const T alpha = (T)st.alpha;
+    const T alpha_prev = (T)st.alpha_prev;
     const Nbr<K> n = make_nbr(t, S, cf);
     const int64_t P = t.P;
     int64_t c = (int64_t)t.k0 * P + t.q;
@@ -629,7 +635,8 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
         const K lkym = cf.load(c + n.oym), lkyp = cf.load(c + n.oyp);
         const T lvxm = p[c + n.oxm], lvxp = p[c + n.oxp];
         const T lvym = p[c + n.oym], lvyp = p[c + n.oyp];
-        const X xc = __builtin_nontemporal_load(&x[c]);
+        const X xc = XM ? __builtin_nontemporal_load(&x[c]) : X(0);
+        const T pp = XM == 2 ? __builtin_nontemporal_load(&pprev[c]) : T(0);
         T zc = __builtin_nontemporal_load(&z[c]);
         const T vzp = top ? T(0) : vzp_l;
         const K kzp = top ? n.wzp : kzp_l;
@@ -645,7 +652,9 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
         const T q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) +
                      (bym * (vc - vym) + byp * (vc - vyp))) +
                     (bzm * (vc - vzm) + bzp * (vc - vzp));
-        __builtin_nontemporal_store(xc + (X)(alpha * vc), &x[c]);
+        if (XM == 1) __builtin_nontemporal_store(xc + (X)(alpha * vc), &x[c]);
+        if (XM == 2)
+            __builtin_nontemporal_store(fma((X)alpha, (X)vc, fma((X)alpha_prev, (X)pp, xc)), &x[c]);
         const T inv = dg > T(0) ? recip(dg) : T(0);   // hull rows keep z = 0
         zc -= alpha * q * inv;
         __builtin_nontemporal_store(zc, &z[c]);
@@ -785,6 +794,19 @@ __device__ void body_ir_resid(const Slot &S, const SlotState &st, int64_t lt,
     acc[2] += a2;
 }
 
+// K1_FLUSH_X: x += alpha p with the current direction (the update the last
+// iteration left pending), before x is used.
+__device__ void body_flush_x(const Slot &S, const SlotState &st, int64_t lt, double (&acc)[3])
+{
+    const TileCtx t = tile_ctx(S, lt);
+    if (!t.active) return;
+    GLB double *__restrict__ x = gp(S.x);
+    const GLB double *__restrict__ p = gp((const double *)(st.pbuf ? S.pb : S.pa));
+    const double alpha = st.alpha;
+    int64_t c = (int64_t)t.k0 * t.P + t.q;
+    for (int k = t.k0; k < t.k1; ++k, c += t.P) x[c] = fma(alpha, p[c], x[c]);
+}
+
 // K2_IR_UPDATE: x += s d, d = 0.
 __device__ void body_ir_update(const Slot &S, const SlotState &st, int64_t lt,
                                double (&acc)[3])
@@ -900,7 +922,12 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
     }
     case K1_CG_A: {
         const double pap = tot[0];
-        if (!(pap > 0.0) || !isfinite(pap)) { finish(st, PCG_EBREAKDOWN); break; }
+        if (!(pap > 0.0) || !isfinite(pap)) {
+            // x keeps the last iterate: apply a pending update first
+            if (st.xpend) { st.status = PCG_EBREAKDOWN; st.phase = K1_FLUSH_X; }
+            else finish(st, PCG_EBREAKDOWN);
+            break;
+        }
         st.pap = pap;
         st.alpha = st.rz / pap;
         st.pbuf ^= 1;
@@ -913,8 +940,20 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         st.rr = tot[1];
         st.beta = tot[0] / st.rz;
         st.rz = tot[0];
+        // the pass just run left x alone (xpend 0) or caught it up (xpend 1)
+        if (st.xpend) st.xpend = 0;
+        else { st.xpend = 1; st.alpha_prev = st.alpha; }
         if (!isfinite(st.rr) || !isfinite(st.rz)) { finish(st, PCG_EBREAKDOWN); break; }
-        st.phase = (st.rr <= st.tol2 || st.iter >= st.maxit) ? K1_CHECK64 : K1_CG_A;
+        if (st.rr <= st.tol2 || st.iter >= st.maxit)
+            st.phase = st.xpend ? K1_FLUSH_X : K1_CHECK64;
+        else
+            st.phase = K1_CG_A;
+        break;
+    }
+    case K1_FLUSH_X: {
+        st.xpend = 0;
+        st.phase = K2_NONE;
+        st.after = st.status == PCG_PENDING ? K1_CHECK64 : PH_DONE;
         break;
     }
     case K1_CHECK64: {
@@ -1082,6 +1121,7 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
         // rare actions: every slot, whatever its coefficient source
         if (ph == K1_MEAN_B) { body_mean_b(S, st, lt, r64, acc); return; }
         if (ph == K1_MEAN_X) { body_mean_x(S, st, lt, r64, acc); return; }
+        if (ph == K1_FLUSH_X) { body_flush_x(S, st, lt, acc); return; }
         const int m = slot_mode(S);
         if (FAMILY == PCG_PREC_FP64) {
             if (m == 2) run_k0_fp64(ph, S, st, lt, frac_coef<double>(S, S.rho64), acc);
@@ -1105,9 +1145,19 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
             }
         } else {
             if (ph == K2_CG_B) {
-                if (MODE == 2) body_passB<double, double>(S, st, lt, frac_coef<double>(S, S.rho64), acc);
-                else if (MODE == 1) body_passB<double, double>(S, st, lt, c64, acc);
-                else body_passB<double, double>(S, st, lt, r64, acc);
+                // x is read and written every second iteration (XM 0, then 2)
+                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) != 0;
+                if (MODE == 2) {
+                    const FracCoef<double> f = frac_coef<double>(S, S.rho64);
+                    if (catch_up) body_passB<double, double, FracCoef<double>, 2>(S, st, lt, f, acc);
+                    else body_passB<double, double, FracCoef<double>, 0>(S, st, lt, f, acc);
+                } else if (MODE == 1) {
+                    if (catch_up) body_passB<double, double, ClsCoef<double>, 2>(S, st, lt, c64, acc);
+                    else body_passB<double, double, ClsCoef<double>, 0>(S, st, lt, c64, acc);
+                } else {
+                    if (catch_up) body_passB<double, double, RhoCoef<double>, 2>(S, st, lt, r64, acc);
+                    else body_passB<double, double, RhoCoef<double>, 0>(S, st, lt, r64, acc);
+                }
             } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
             else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);
         }
@@ -1137,7 +1187,8 @@ __device__ __forceinline__ bool serves(const Slot &S, int ph)
 {
     if (WHICH == 0)
         return ph == K1_INIT64 || ph == K1_CHECK64 || ph == K1_IR_INIT ||
-               ph == K1_IR_RESID || ph == K1_MEAN_B || ph == K1_MEAN_X;
+               ph == K1_IR_RESID || ph == K1_MEAN_B || ph == K1_MEAN_X ||
+               ph == K1_FLUSH_X;
     if (slot_mode(S) != MODE) return false;
     if (WHICH == 1) return ph == K1_CG_A || ph == K1_IR_A;
     return ph >= 11 && ph <= 19;

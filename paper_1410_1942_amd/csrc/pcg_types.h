@@ -33,6 +33,7 @@ enum Phase : int32_t {
     K1_IR_A = 6,       // FP32 p = z + beta p ; p.Ap (FP64 sum)
     K1_MEAN_B = 7,     // singular problem: sum of b and count of fluid cells
     K1_MEAN_X = 8,     // singular problem: sum of x over fluid cells
+    K1_FLUSH_X = 9,    // x += alpha p: the update an iteration left pending
     // K2 actions (second launch of an iteration)
     K2_NONE = 11,      // nothing; then the K1 action in `after`
     K2_CG_B = 12,      // q = A p, x += alpha p, z -= alpha D^-1 q ; r.z, r.r
@@ -61,6 +62,7 @@ struct alignas(128) SlotState {
     double bshift;    // singular problem: mean of b over fluid cells (else 0)
     double nfluid;    // singular problem: number of fluid cells
     double xshift;    // singular problem: mean of x over fluid cells
+    double alpha_prev;// alpha of the direction whose x update is pending
     int32_t phase;
     int32_t after;    // K1 action after a K2_NONE
     int32_t status;   // PCG_PENDING while running, else the final code
@@ -74,7 +76,8 @@ struct alignas(128) SlotState {
     uint32_t ticket;  // arrivals of the current launch
     int32_t warm;     // warm start requested
     int32_t singular; // no Dirichlet face: solve for the mean-free source
-    int32_t pad_[2];
+    int32_t xpend;    // FP64: x lacks alpha_prev p_prev (updates go in pairs)
+    int32_t pad_[1];
 };
 
 // Read-only description of a slot (rewritten by the host between replays).

@@ -66,7 +66,8 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
     sf, sw = copy_bytes / f_copy, copy_bytes / w_copy
     lines = [f"# FETCH_SIZE scale {sf:.4f}, WRITE_SIZE scale {sw:.4f} "
              f"(copy kernel: {copy_bytes} B read and written per launch)",
-             f"# per launch, median over launches; cells = {cells}"]
+             f"# per launch, mean over launches (FP64 pass B alternates two forms); "
+             f"cells = {cells}"]
     if sha:
         lines.append(f"kernel_source_sha = {sha}")
     lines.append(f"{'kernel':58s} {'n':>4s} {'fetch_B':>14s} {'write_B':>14s} "
@@ -74,8 +75,8 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
     for k in f:
         if k not in w:
             continue
-        fb = statistics.median(f[k]) * 1024 * sf
-        wb = statistics.median(w[k]) * 1024 * sw
+        fb = statistics.mean(f[k]) * 1024 * sf
+        wb = statistics.mean(w[k]) * 1024 * sw
         lines.append(f"{_short(k, 58):58s} {len(f[k]):4d} {fb:14.4e} {wb:14.4e} "
                      f"{fb / cells:10.2f} {wb / cells:10.2f}")
         if "k_iter<" in k:
