@@ -34,15 +34,27 @@ def kernel_stats(path: str) -> str:
                        f"{float(r['MaxNs'])/1e6:10.4f} {float(r['TotalDurationNs'])/1e9:9.3f} "
                        f"{float(r['Percentage']):6.2f}")
         return "\n".join(out)
-    # *_kernel_trace.csv: aggregate ourselves
+    # *_kernel_trace.csv: aggregate ourselves; `large` averages the launches
+    # of at least a quarter of the longest one (the largest problem's
+    # launches, both forms of an alternating kernel; not the empty launches
+    # at the end of a captured chunk nor those of smaller problems)
     agg = collections.defaultdict(list)
     for r in rows:
         agg[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-    out.append(f"{'kernel':70s} {'calls':>7s} {'avg_ms':>10s} {'median_ms':>10s} {'total_s':>9s}")
+    out.append(f"{'kernel':70s} {'calls':>7s} {'avg_ms':>10s} {'median_ms':>10s} "
+               f"{'large_n':>8s} {'large_avg_ms':>12s} {'total_s':>9s}")
     for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        big = _large(v)
         out.append(f"{_short(k):70s} {len(v):7d} {statistics.mean(v)/1e6:10.4f} "
-                   f"{statistics.median(v)/1e6:10.4f} {sum(v)/1e9:9.3f}")
+                   f"{statistics.median(v)/1e6:10.4f} {len(big):8d} "
+                   f"{statistics.mean(big)/1e6:12.4f} {sum(v)/1e9:9.3f}")
     return "\n".join(out)
+
+
+def _large(values, share=0.25):
+    """The values of at least `share` of the largest."""
+    top = max(values)
+    return [v for v in values if v >= share * top]
 
 
 def _counter(path: str):
@@ -66,8 +78,9 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
     sf, sw = copy_bytes / f_copy, copy_bytes / w_copy
     lines = [f"# FETCH_SIZE scale {sf:.4f}, WRITE_SIZE scale {sw:.4f} "
              f"(copy kernel: {copy_bytes} B read and written per launch)",
-             f"# per launch, mean over launches (FP64 pass B alternates two forms); "
-             f"cells = {cells}"]
+             f"# per launch, mean over the launches fetching at least a quarter of the "
+             f"largest (empty launches at the end of a captured chunk excluded; FP64 pass B "
+             f"alternates two forms, both kept); cells = {cells}"]
     if sha:
         lines.append(f"kernel_source_sha = {sha}")
     lines.append(f"{'kernel':58s} {'n':>4s} {'fetch_B':>14s} {'write_B':>14s} "
@@ -75,8 +88,8 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
     for k in f:
         if k not in w:
             continue
-        fb = statistics.mean(f[k]) * 1024 * sf
-        wb = statistics.mean(w[k]) * 1024 * sw
+        fb = statistics.mean(_large(f[k])) * 1024 * sf
+        wb = statistics.mean(_large(w[k])) * 1024 * sw
         lines.append(f"{_short(k, 58):58s} {len(f[k]):4d} {fb:14.4e} {wb:14.4e} "
                      f"{fb / cells:10.2f} {wb / cells:10.2f}")
         if "k_iter<" in k:
