@@ -29,13 +29,15 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell of the two iteration kernels, by precision and
 # coefficient source (a one-byte density class, or the density itself)
 #   pass A: read p_old, z, coefficient key; write p
-#   pass B: read x, p, z, coefficient key; write x, z
+#   pass B: read p, z, coefficient key (+ x or d, p_prev); write z (+ x or d)
 BYTES_K1 = {("fp64", "classes"): 25, ("fp64", "density"): 32,
             ("fp32", "classes"): 13, ("fp32", "density"): 16}
-# FP64 pass B reads and writes x every second launch only (25 and 49 B/cell
-# with classes, 32 and 56 with densities): the per-launch average
+# pass B reads and writes x (FP64) or the inner correction d (FP32) every
+# second launch only, together with the previous direction (FP64 25 and 49
+# B/cell with classes, 32 and 56 with densities; FP32 13 and 25, 16 and 28):
+# the per-launch average
 BYTES_K2 = {("fp64", "classes"): 37, ("fp64", "density"): 44,
-            ("fp32", "classes"): 21, ("fp32", "density"): 24}
+            ("fp32", "classes"): 19, ("fp32", "density"): 22}
 
 
 def log(msg):

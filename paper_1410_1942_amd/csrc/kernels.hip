@@ -794,16 +794,24 @@ __device__ void body_ir_resid(const Slot &S, const SlotState &st, int64_t lt,
     acc[2] += a2;
 }
 
-// K1_FLUSH_X: x += alpha p with the current direction (the update the last
-// iteration left pending), before x is used.
+// K1_FLUSH_X: the update the last iteration left pending, with the current
+// direction: x += alpha p (FP64), or the inner solve's correction d += alpha
+// p (FP32+IR).
 __device__ void body_flush_x(const Slot &S, const SlotState &st, int64_t lt, double (&acc)[3])
 {
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
+    int64_t c = (int64_t)t.k0 * t.P + t.q;
+    if (S.d32) {
+        GLB float *__restrict__ d = gp(S.d32);
+        const GLB float *__restrict__ p = gp((const float *)(st.pbuf ? S.pb : S.pa));
+        const float alpha = (float)st.alpha;
+        for (int k = t.k0; k < t.k1; ++k, c += t.P) d[c] = fmaf(alpha, p[c], d[c]);
+        return;
+    }
     GLB double *__restrict__ x = gp(S.x);
     const GLB double *__restrict__ p = gp((const double *)(st.pbuf ? S.pb : S.pa));
     const double alpha = st.alpha;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
     for (int k = t.k0; k < t.k1; ++k, c += t.P) x[c] = fma(alpha, p[c], x[c]);
 }
 
@@ -944,16 +952,19 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         if (st.xpend) st.xpend = 0;
         else { st.xpend = 1; st.alpha_prev = st.alpha; }
         if (!isfinite(st.rr) || !isfinite(st.rz)) { finish(st, PCG_EBREAKDOWN); break; }
-        if (st.rr <= st.tol2 || st.iter >= st.maxit)
+        if (st.rr <= st.tol2 || st.iter >= st.maxit) {
             st.phase = st.xpend ? K1_FLUSH_X : K1_CHECK64;
-        else
+            st.after = K1_CHECK64;   // after the flush
+        } else {
             st.phase = K1_CG_A;
+        }
         break;
     }
     case K1_FLUSH_X: {
+        // then the action its scheduler left in `after`; nothing after an error
         st.xpend = 0;
         st.phase = K2_NONE;
-        st.after = st.status == PCG_PENDING ? K1_CHECK64 : PH_DONE;
+        if (st.status != PCG_PENDING) st.after = PH_DONE;
         break;
     }
     case K1_CHECK64: {
@@ -1039,7 +1050,7 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         if (!isfinite(pap)) { finish(st, PCG_EBREAKDOWN); break; }
         if (!(pap > 0.0)) {  // the inner direction vanished: refine now
             st.scale = pow2_scale(sqrt(st.rr_true * st.inner_tol2));
-            st.phase = K2_NONE;
+            st.phase = st.xpend ? K1_FLUSH_X : K2_NONE;   // d complete first
             st.after = K1_IR_RESID;
             break;
         }
@@ -1056,13 +1067,18 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         st.rr = tot[1];
         st.beta = tot[0] / st.rz;
         st.rz = tot[0];
+        // as in FP64: the pass left d alone (xpend 0) or caught it up (1)
+        if (st.xpend) st.xpend = 0;
+        else { st.xpend = 1; st.alpha_prev = st.alpha; }
         if (!isfinite(st.rr)) { finish(st, PCG_EBREAKDOWN); break; }
         const bool inner_done = st.rr <= st.inner_goal2 * st.rr0_inner ||
                                 st.inner_iter >= st.inner_maxit ||
                                 st.iter >= st.maxit;
         if (inner_done) {
+            // the outer residual reads x + s d: d complete first
             st.scale = pow2_scale(sqrt(st.rr_true * st.inner_tol2));
-            st.phase = K1_IR_RESID;
+            st.phase = st.xpend ? K1_FLUSH_X : K1_IR_RESID;
+            st.after = K1_IR_RESID;
         } else {
             st.phase = K1_IR_A;
         }
@@ -1172,9 +1188,19 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
             }
         } else {
             if (ph == K2_IR_B) {
-                if (MODE == 2) body_passB<float, float>(S, st, lt, frac_coef<float>(S, S.rho32), acc);
-                else if (MODE == 1) body_passB<float, float>(S, st, lt, c32, acc);
-                else body_passB<float, float>(S, st, lt, r32, acc);
+                // d is read and written every second iteration, as x in FP64
+                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) != 0;
+                if (MODE == 2) {
+                    const FracCoef<float> f = frac_coef<float>(S, S.rho32);
+                    if (catch_up) body_passB<float, float, FracCoef<float>, 2>(S, st, lt, f, acc);
+                    else body_passB<float, float, FracCoef<float>, 0>(S, st, lt, f, acc);
+                } else if (MODE == 1) {
+                    if (catch_up) body_passB<float, float, ClsCoef<float>, 2>(S, st, lt, c32, acc);
+                    else body_passB<float, float, ClsCoef<float>, 0>(S, st, lt, c32, acc);
+                } else {
+                    if (catch_up) body_passB<float, float, RhoCoef<float>, 2>(S, st, lt, r32, acc);
+                    else body_passB<float, float, RhoCoef<float>, 0>(S, st, lt, r32, acc);
+                }
             } else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);
             else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
             else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);

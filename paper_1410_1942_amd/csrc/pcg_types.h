@@ -37,7 +37,7 @@ enum Phase : int32_t {
     // K2 actions (second launch of an iteration)
     K2_NONE = 11,      // nothing; then the K1 action in `after`
     K2_CG_B = 12,      // q = A p, x += alpha p, z -= alpha D^-1 q ; r.z, r.r
-    K2_IR_B = 13,      // FP32 d += alpha p, z -= alpha D^-1 q ; r.z, r.r (FP64)
+    K2_IR_B = 13,      // FP32 q = A p, d += alpha p (in pairs), z -= alpha D^-1 q ; r.z, r.r (FP64)
     K2_IR_UPDATE = 14, // x += s d, d = 0
     K2_ZERO_X = 15,    // x = 0 (zero source with a warm start)
     K2_SUB_X = 16,     // singular problem: x -= its fluid mean
@@ -76,7 +76,7 @@ struct alignas(128) SlotState {
     uint32_t ticket;  // arrivals of the current launch
     int32_t warm;     // warm start requested
     int32_t singular; // no Dirichlet face: solve for the mean-free source
-    int32_t xpend;    // FP64: x lacks alpha_prev p_prev (updates go in pairs)
+    int32_t xpend;    // x (FP64) or d (IR) lacks alpha_prev p_prev (updates go in pairs)
     int32_t pad_[1];
 };
 
