@@ -65,7 +65,10 @@ def parse():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--batch-n", type=int, default=64)
-    ap.add_argument("--serve-n", type=int, default=160)
+    ap.add_argument("--serve-n", type=int, default=1000,
+                    help="reported requests of the served stream")
+    ap.add_argument("--serve-warmup", type=int, default=100,
+                    help="warm-up requests served before the reported ones")
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="short run for counter collection: copy probe of "
                          "1 GiB, then FP64 and FP32+IR solves capped at this "
@@ -100,7 +103,7 @@ def main():
 
     from paper_1410_1942_amd import _lib as L
     from paper_1410_1942_amd import fields as F
-    from paper_1410_1942_amd.solver import Solver, copy_probe
+    from paper_1410_1942_amd.solver import Solver, copy_probe, triad_probe
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     dev = torch.device("cuda:0")
@@ -139,10 +142,12 @@ def main():
         s.close()
         return p, st, tm
 
-    # achievable bandwidth: plain copy of 4 GiB
-    log("copy probe")
+    # achievable bandwidth: plain copy of 4 GiB, STREAM triad on 3 x 4 GiB
+    log("copy and triad probes")
     copy_gbs = copy_probe(1 << 29, reps=10)
-    log(f"  copy {copy_gbs:.0f} GB/s")
+    triad_gbs = triad_probe(1 << 29, reps=10)
+    torch.cuda.empty_cache()
+    log(f"  copy {copy_gbs:.0f} GB/s, triad {triad_gbs:.0f} GB/s")
 
     # setup alone (density encoding + host connectivity check)
     torch.cuda.synchronize()
@@ -196,6 +201,7 @@ def main():
         "rel_res_true": st64["rel_res_true"],
         "setup_ms": round(setup_ms, 2),
         "copy_GBps": round(copy_gbs, 1),
+        "triad_GBps": round(triad_gbs, 1),
     }
 
     # roofline of the dominant kernel, hipEvent-timed on the solver's stream
@@ -222,6 +228,10 @@ def main():
                       f"x updated every second launch ({b2} B/cell per launch on average)",
             "avg_ms": round(k2_ms, 4), "launches": nlaunch,
             "frac_of_copy": round(a2 / copy_gbs, 4),
+            "frac_of_triad": round(a2 / triad_gbs, 4),
+            # counted HBM bytes per launch over the same event-timed duration
+            "traffic_GBps": (round(traffic / (k2_ms * 1e-3) / 1e9, 1)
+                             if traffic is not None else None),
         }
         out["kernel_k1"] = {
             "kernel": f"k_iter<FP64,1,{mode}>: p update + p.Ap ({b1} B/cell)",
@@ -273,6 +283,9 @@ def main():
             "sample": f"wedge{n} input, {k} PCG iterations timed as the "
                       f"difference of a {1 + k}- and a 1-iteration run "
                       f"(setup {ta:.1f} s excluded)",
+            "cpu_model": host_cpu_model(),
+            "host_cpus": len(os.sched_getaffinity(0)),
+            "host_triad_GBps": round(oracle.host_triad(), 1),
         }
         # relative residual of the GPU solutions recomputed by the reference
         out["rel_res_oracle"] = oracle.relres(case.rho, case.mask, case.bc, case.h,
@@ -300,7 +313,7 @@ def main():
     if not args.no_batch:
         out["batch"] = bench_batch(args.batch_n)
     if not args.no_serve:
-        out["served"] = bench_serve(args.serve_n)
+        out["served"] = bench_serve(args.serve_n, args.serve_warmup)
 
     print(json.dumps(out), flush=True)
 
@@ -487,38 +500,58 @@ def bench_batch(nsolves):
     }
 
 
-def bench_serve(nreq):
+def bench_serve(nreq, nwarm):
     """Served stream: requests with edges log-uniform in [24,192], wedge hull
     with p = 0.5, tol 1e-6 or 1e-8, FP32+IR; first a capacity run (all
     waiting at t = 0) on a prefix, then Poisson arrivals at 75 % of that
-    capacity over the whole stream."""
+    capacity: nwarm warm-up requests, then nreq reported ones.  Requests
+    are generated one at a time and uploaded at once (host copies dropped)."""
     import torch
     from paper_1410_1942_amd import fields as F
     from paper_1410_1942_amd import serve
-    log(f"served stream of {nreq}")
-    cases = [F.served_request(i, keep_velocity=False) for i in range(nreq)]
-    arena = 24 << 30
-    ncap = min(nreq, 48)
-    reqs = serve.make_requests(cases[:ncap], [0.0] * ncap)
-    srv = serve.Server(arena, max_slots=64)
-    srv.run(reqs[: min(8, ncap)], realtime=False)          # warm
-    cap = srv.run(reqs, realtime=False)
-    rate = 0.75 * cap.solves_per_s
-    arrivals = F.arrival_times(nreq, rate=rate, seed=7)
-    for r in reqs:
-        del r
-    reqs = serve.make_requests(cases, arrivals)
+    total = nwarm + nreq
+    log(f"served stream of {nwarm} + {nreq}")
+    reqs = [serve.make_requests([F.served_request(i, keep_velocity=False)], [0.0])[0]
+            for i in range(total)]
     torch.cuda.synchronize()
-    rep = srv.run(reqs, realtime=True)
+    arena = 24 << 30
+    ncap = min(total, 48)
+    srv = serve.Server(arena, max_slots=64)
+    srv.run([_fresh(r, 0.0) for r in reqs[: min(8, ncap)]], realtime=False)   # warm
+    cap = srv.run([_fresh(r, 0.0) for r in reqs[:ncap]], realtime=False)
+    rate = 0.75 * cap.solves_per_s
+    arrivals = F.arrival_times(total, rate=rate, seed=7)
+    reqs = [_fresh(r, float(t)) for r, t in zip(reqs, arrivals)]
+    torch.cuda.synchronize()
+    rep = srv.run(reqs, realtime=True, warmup=nwarm)
     srv.close()
     log(f"  capacity {cap.solves_per_s:.1f}/s; at {rate:.1f}/s arrivals: "
         f"{rep.solves_per_s:.1f}/s, p50 {rep.p50_ms:.1f} ms, p99 {rep.p99_ms:.1f} ms")
     d = rep.as_dict()
-    d.update({"arrival_rate_per_s": round(rate, 2),
+    d.update({"arrival_rate_per_s": round(rate, 2), "warmup_requests": nwarm,
               "capacity_solves_per_s": round(cap.solves_per_s, 2),
               "capacity_requests": ncap, "precision": "fp32+ir",
               "arena_GiB": arena / 2**30})
     return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+
+
+def host_cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _fresh(r, arrival):
+    """The same request (shared device inputs) with no result yet."""
+    import dataclasses
+    from paper_1410_1942_amd import _lib as L
+    return dataclasses.replace(r, arrival=arrival, p=None, admitted=float("nan"),
+                               done=float("nan"), status=L.PENDING, iters=0, outer=0,
+                               rel_res=float("nan"))
 
 
 def kernel_sha():

@@ -434,6 +434,17 @@ int pcg_last_timing(pcg_ctx_t *ctx, double *ms_k1, double *ms_k2,
 int pcg_copy_probe(const double *src, double *dst, size_t n, int32_t reps,
                    void *hip_stream, double *ms_per_copy);
 
+/*
+ * Triad bandwidth probe (the STREAM triad a = b + scalar * c, read 16 B and
+ * write 8 B per element): runs it `reps` times on n doubles on the given
+ * stream after one untimed launch and returns the average ms per triad.
+ * All three are device arrays of n doubles owned by the caller; a must not
+ * alias b or c.  PCG_EINVAL for null pointers, n < 2, reps < 1 or aliasing;
+ * PCG_EHIP for a runtime error.
+ */
+int pcg_triad_probe(double *a, const double *b, const double *c, size_t n, double scalar,
+                    int32_t reps, void *hip_stream, double *ms_per_triad);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,8 @@ def load(path: Optional[str] = None):
     lib.oracle_components.restype = i
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = i
+    lib.oracle_host_triad.argtypes = [ctypes.c_long, i]
+    lib.oracle_host_triad.restype = d
     if path is None:
         _lib = lib
     return lib
@@ -255,3 +257,10 @@ def connected(mask, bc, lib=None) -> bool:
 def threads(lib=None) -> int:
     lib = lib or load()
     return int(lib.oracle_threads())
+
+
+def host_triad(n: int = 1 << 26, reps: int = 5, lib=None) -> float:
+    """Host STREAM-triad bandwidth (GB/s) on the oracle's threads: context
+    for the oracle's timing, not part of the method."""
+    lib = lib or load()
+    return float(lib.oracle_host_triad(int(n), int(reps)))

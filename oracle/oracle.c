@@ -60,9 +60,18 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
+
+/* wall-clock seconds (used by the host bandwidth probe only) */
+static double omp_now(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
 
 enum { O_NEUMANN = 0, O_DIRICHLET = 1, O_PERIODIC = 2 };
 enum {
@@ -590,6 +599,35 @@ void oracle_divergence(int nx, int ny, int nz, double h, const double *u,
                 }
                 out[w0] = ax ? (du + dv + dw) / (vc * h) : (du + dv + dw) / h;
             }
+}
+
+/*
+ * Host memory bandwidth of the threads the oracle runs on: the STREAM triad
+ * a = b + 3 c over n doubles (24 B per element), best of `reps` passes after
+ * a first-touch initialisation by the same threads.  Context for the
+ * oracle's timing only; no part of the method.  GB/s, or -1 if the arrays
+ * cannot be allocated.
+ */
+double oracle_host_triad(long n, int reps)
+{
+    double *a = malloc(sizeof(double) * (size_t)n);
+    double *b = malloc(sizeof(double) * (size_t)n);
+    double *c = malloc(sizeof(double) * (size_t)n);
+    if (!a || !b || !c) { free(a); free(b); free(c); return -1.0; }
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) { a[i] = 0.0; b[i] = 1.0; c[i] = 2.0; }
+    double best = 1e300;
+    for (int r = 0; r < reps; ++r) {
+        const double t0 = omp_now();
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) a[i] = b[i] + 3.0 * c[i];
+        const double t = omp_now() - t0;
+        if (t < best) best = t;
+    }
+    const double check = a[n / 2];
+    free(a); free(b); free(c);
+    if (check != 7.0) return -1.0;
+    return 24.0 * (double)n / best / 1e9;
 }
 
 int oracle_threads(void)

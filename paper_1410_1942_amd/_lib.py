@@ -28,7 +28,7 @@ EXPORTED = [
     "pcg_check_connectivity", "pcg_set_tile_rules", "pcg_get_tile_rules",
     "pcg_density_classes", "pcg_project", "pcg_divergence",
     "pcg_solve_ex", "pcg_project_ex", "pcg_rhs", "pcg_update_density",
-    "pcg_set_fractions",
+    "pcg_set_fractions", "pcg_triad_probe",
 ]
 
 
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.pcg_set_timing.argtypes = [vp, i32]
     lib.pcg_last_timing.argtypes = [vp, P(dbl), P(dbl), P(i32)]
     lib.pcg_copy_probe.argtypes = [vp, vp, sz, i32, vp, P(dbl)]
+    lib.pcg_triad_probe.argtypes = [vp, vp, vp, sz, dbl, i32, vp, P(dbl)]
     lib.pcg_check_connectivity.argtypes = [vp, P(Grid), P(BC)]
     lib.pcg_set_tile_rules.argtypes = [i32, i32, i32, vp, vp, vp]
     lib.pcg_density_classes.argtypes = [vp, P(i32)]

@@ -29,6 +29,8 @@ hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n, int round
 hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
                          float *r32, int64_t n, int *bad, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
+hipError_t launch_triad(double *a, const double *b, const double *c, double sc, size_t n,
+                        hipStream_t s);
 hipError_t launch_check_frac(const double *ax, const double *ay, const double *az,
                              const double *vol, const double *rho64, int64_t nu, int64_t nv,
                              int64_t nw, int64_t n, int *bad, hipStream_t s);
@@ -59,6 +61,27 @@ int hip_fail(hipError_t e, const char *what)
         hipError_t _e = (expr);                            \
         if (_e != hipSuccess) return hip_fail(_e, #expr);  \
     } while (0)
+
+// Average ms of `reps` launches after one untimed launch, on stream s.
+template <class F>
+int time_launches(hipStream_t s, int32_t reps, F &&launch, double *ms_out)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "timed probe launches");
+    *ms_out = ms / reps;
+    return PCG_OK;
+}
 
 constexpr size_t kAlign = 256;
 constexpr int kDefaultCheckEvery = 32;
@@ -1383,20 +1406,17 @@ int pcg_copy_probe(const double *src, double *dst, size_t n, int32_t reps,
 {
     if (!src || !dst || n < 2 || reps < 1 || !ms_per_copy) return PCG_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(launch_copy(src, dst, n, s));
-    HIP_TRY(hipEventRecord(e0, s));
-    for (int r = 0; r < reps; ++r) HIP_TRY(launch_copy(src, dst, n, s));
-    HIP_TRY(hipEventRecord(e1, s));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    *ms_per_copy = ms / reps;
-    return PCG_OK;
+    return time_launches(s, reps, [&] { return launch_copy(src, dst, n, s); }, ms_per_copy);
+}
+
+int pcg_triad_probe(double *a, const double *b, const double *c, size_t n, double scalar,
+                    int32_t reps, void *hip_stream, double *ms_per_triad)
+{
+    if (!a || !b || !c || n < 2 || reps < 1 || !ms_per_triad) return PCG_EINVAL;
+    if (a == b || a == c) return PCG_EINVAL;
+    hipStream_t s = (hipStream_t)hip_stream;
+    return time_launches(s, reps, [&] { return launch_triad(a, b, c, scalar, n, s); },
+                         ms_per_triad);
 }
 
 }  // extern "C"

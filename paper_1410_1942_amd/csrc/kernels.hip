@@ -1600,6 +1600,15 @@ k_copy(const double *__restrict__ src, double *__restrict__ dst, int64_t n)
     if (c < n) dst[c] = src[c];
 }
 
+// Triad probe (STREAM's a = b + s c), one element per thread like the copy.
+__global__ void __launch_bounds__(256)
+k_triad(double *__restrict__ a, const double *__restrict__ b, const double *__restrict__ c,
+        double s, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = fma(s, c[i], b[i]);
+}
+
 // ------------------------------------------------------------------------
 // host-callable launchers
 // ------------------------------------------------------------------------
@@ -1696,6 +1705,16 @@ hipError_t launch_check_frac(const double *ax, const double *ay, const double *a
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_check_frac, dim3((unsigned)blocks), dim3(256), 0, s, ax, ay, az, vol,
                        rho64, nu, nv, nw, n, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_triad(double *a, const double *b, const double *c, double sc, size_t n,
+                        hipStream_t s)
+{
+    const int64_t blocks = ((int64_t)n + 255) / 256;
+    if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_triad, dim3((unsigned)blocks), dim3(256), 0, s, a, b, c, sc,
+                       (int64_t)n);
     return hipGetLastError();
 }
 

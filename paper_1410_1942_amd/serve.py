@@ -82,9 +82,12 @@ class Server:
         self.batch.close()
 
     def run(self, requests: Sequence[Request], clock=time.perf_counter,
-            realtime: bool = True) -> ServeReport:
+            realtime: bool = True, warmup: int = 0) -> ServeReport:
         """Serve every request; with realtime=False all requests are treated
-        as already waiting at t = 0 (capacity measurement)."""
+        as already waiting at t = 0 (capacity measurement).  The first
+        `warmup` requests (in arrival order) are served but left out of the
+        report, whose window runs from the first reported arrival to the
+        last reported completion."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         waiting: collections.deque = collections.deque()
         resident = {}                       # slot -> request
@@ -140,12 +143,13 @@ class Server:
                 r.outer = st["outer_iters"]
                 r.rel_res = st["rel_res_true"]
                 self.batch.release(slot)
-        wall = max(r.done for r in reqs) - min(r.arrival for r in reqs)
-        lat = np.array([r.latency for r in reqs]) * 1e3
-        statuses = collections.Counter(int(r.status) for r in reqs)
-        cell_iters = sum(r.cells * r.iters for r in reqs)
+        rep = reqs[warmup:] if warmup < len(reqs) else reqs
+        wall = max(r.done for r in rep) - min(r.arrival for r in rep)
+        lat = np.array([r.latency for r in rep]) * 1e3
+        statuses = collections.Counter(int(r.status) for r in rep)
+        cell_iters = sum(r.cells * r.iters for r in rep)
         return ServeReport(
-            n=len(reqs), wall_s=wall, solves_per_s=len(reqs) / wall,
+            n=len(rep), wall_s=wall, solves_per_s=len(rep) / wall,
             p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
             mean_ms=float(lat.mean()), max_resident=max_res,
             cell_iters_per_s=cell_iters / wall, statuses=dict(statuses))

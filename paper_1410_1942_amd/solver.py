@@ -287,6 +287,20 @@ class Batch:
             pass
 
 
+def triad_probe(n_doubles: int, reps: int = 10, device="cuda") -> float:
+    """Achieved triad bandwidth (GB/s, 24 B per element) of a plain
+    a = b + s c kernel on three arrays of n_doubles."""
+    lib = L.load()
+    b = torch.ones(n_doubles, dtype=torch.float64, device=device)
+    c = torch.ones(n_doubles, dtype=torch.float64, device=device)
+    a = torch.empty_like(b)
+    ms = ctypes.c_double()
+    L.check(lib.pcg_triad_probe(_ptr(a), _ptr(b), _ptr(c), n_doubles, 3.0, int(reps),
+                                _stream_handle(None), ctypes.byref(ms)), "triad probe")
+    del a, b, c
+    return 24 * n_doubles / (ms.value * 1e-3) / 1e9
+
+
 def copy_probe(n_doubles: int, reps: int = 20, device="cuda") -> float:
     """Achieved copy bandwidth (GB/s, read + write) of a plain copy kernel."""
     lib = L.load()

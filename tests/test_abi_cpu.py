@@ -121,6 +121,10 @@ def test_null_handles(lib):
     assert lib.pcg_density_classes(None, ctypes.byref(n)) == L.EINVAL
     ms = ctypes.c_double()
     assert lib.pcg_copy_probe(None, None, 0, 1, None, ctypes.byref(ms)) == L.EINVAL
+    assert lib.pcg_triad_probe(None, None, None, 0, 1.0, 1, None, ctypes.byref(ms)) == L.EINVAL
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.pcg_triad_probe(fake, fake, ctypes.c_void_p(0x2000), 16, 1.0, 1, None,
+                               ctypes.byref(ms)) == L.EINVAL        # a aliases b
 
 
 def _connectivity(lib, mask, bc):
