@@ -86,6 +86,7 @@ int time_launches(hipStream_t s, int32_t reps, F &&launch, double *ms_out)
 constexpr size_t kAlign = 256;
 constexpr int kDefaultCheckEvery = 32;
 constexpr int kDefaultGridMax = 1024;
+constexpr int kBatchGrid = 512;
 constexpr double kDefaultInnerTol = 1e-4;
 // largest byte span pass A addresses within one tile (32-bit offsets)
 constexpr int64_t kMaxTileBytes = 0xffffffffll;
@@ -523,6 +524,7 @@ struct Engine {
                                hipMemcpyHostToDevice, stream));
         h_hdr->total_tiles = 0;
         h_hdr->nslots = 0;
+        h_hdr->chunked = 0;
         HIP_TRY(hipMemcpyAsync(d_hdr, h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
         HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
@@ -855,6 +857,7 @@ struct Engine {
         }
         h_hdr->total_tiles = tb;
         h_hdr->nslots = ns;
+        h_hdr->chunked = ns > 1 ? 1 : 0;
         total_tiles = tb;
         nrunning = ns;
         modes = m;
@@ -867,7 +870,9 @@ struct Engine {
 
     int choose_grid() const
     {
-        int g = grid_opt > 0 ? grid_opt : kDefaultGridMax;
+        // batches: workgroups take contiguous tile ranges when several solves
+        // are resident; two workgroups per CU measured best there
+        int g = grid_opt > 0 ? grid_opt : (max_slots == 1 ? kDefaultGridMax : kBatchGrid);
         if (max_slots == 1) {
             int64_t t = 0, n = 0;
             for (auto &S : slots)

@@ -1267,15 +1267,23 @@ k_iter(const BatchHeader *__restrict__ hdr, const Slot *__restrict__ slots)
     const int ns = hdr->nslots;
     const int G = (int)gridDim.x;
     const int g = xcd_major((int)blockIdx.x, G);
+    // strided: tiles g, g + G, ...; chunked: tiles [g T / G, (g + 1) T / G)
+    const bool chunked = hdr->chunked != 0;
+    const int64_t t_first = chunked ? (T * g) / G : g;
+    const int64_t t_end = chunked ? (T * (g + 1)) / G : T;
+    const int64_t t_step = chunked ? 1 : G;
     int cur = -1, cur_ph = 0;
+    int64_t cur_end = 0;
     bool cur_served = false;
     uint32_t run = 0;
-    for (int64_t t = g; t < T; t += G) {
-        const int s = find_slot(slots, ns, t);
+    for (int64_t t = t_first; t < t_end; t += t_step) {
+        // tiles only increase: search again only when t leaves the slot
+        const int s = (cur >= 0 && t < cur_end) ? cur : find_slot(slots, ns, t);
         const Slot &S = slots[s];
         if (s != cur) {
             if (run) arrive(slots[cur], cur_ph, run, lds, &s_last);
             cur = s;
+            cur_end = S.tile_begin + S.ntiles;
             run = 0;
             cur_ph = S.st->phase;
             cur_served = serves<WHICH, MODE>(S, cur_ph);

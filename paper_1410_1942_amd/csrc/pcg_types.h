@@ -112,7 +112,11 @@ struct Slot {
 struct BatchHeader {
     int64_t total_tiles;
     int32_t nslots;
-    int32_t pad;
+    // 0: workgroups stride over the tiles (tiles running at the same time
+    // are neighbours, sharing y-halo rows in L2; one solve); 1: each
+    // workgroup takes a contiguous range of tiles, so it meets few slots
+    // per launch (several solves)
+    int32_t chunked;
 };
 
 }  // namespace pcgmi
