@@ -97,19 +97,32 @@ struct TileCtx {
     bool active;
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const Slot &S, int64_t lt)
+// Column of this thread in tile lt.  Without pairs a tile holds kBlock
+// consecutive cells of the plane, one per thread; with pairs (nx even) it
+// holds 2 kBlock, thread l owning cells 2l (r = 0) and 2l + 1 (r = 1) of the
+// tile, which share a row.
+__device__ __forceinline__ TileCtx tile_ctx(const Slot &S, int64_t lt, int r = 0)
 {
     TileCtx t;
     const int pt = (int)(lt % S.plane_tiles);
     const int zt = (int)(lt / S.plane_tiles);
     t.P = S.nx * S.ny;
-    t.q = pt * kBlock + (int)threadIdx.x;
+    t.q = S.pairs ? pt * (2 * kBlock) + 2 * (int)threadIdx.x + r
+                  : pt * kBlock + (int)threadIdx.x;
     t.active = t.q < t.P;
     t.i = t.q % S.nx;
     t.j = t.q / S.nx;
     t.k0 = zt * S.tz;
     t.k1 = min(S.nz, t.k0 + S.tz);
     return t;
+}
+
+// f(t) for each column of the thread in tile lt (two with pairs).
+template <class F>
+__device__ __forceinline__ void for_rows(const Slot &S, int64_t lt, F &&f)
+{
+    f(tile_ctx(S, lt, 0));
+    if (S.pairs) f(tile_ctx(S, lt, 1));
 }
 
 // Global-address-space views: pointers read from the slot table are
@@ -165,11 +178,25 @@ struct Areas6 {
     T xm, xp, ym, yp, zm, zp;
 };
 
+// Two consecutive values of T in one load.
+typedef double vec2d __attribute__((ext_vector_type(2)));
+typedef float vec2f __attribute__((ext_vector_type(2)));
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = vec2d; };
+template <> struct Vec2<float> { using type = vec2f; };
+
 template <typename T>
 struct RhoCoef {
     using Key = T;
     const GLB T *__restrict__ rho;
     __device__ __forceinline__ Key load(int64_t c) const { return rho[c]; }
+    __device__ __forceinline__ void load2(int64_t c, Key &a, Key &b) const
+    {
+        using V = typename Vec2<T>::type;
+        const V v = ((const GLB V *)rho)[c >> 1];
+        a = v.x;
+        b = v.y;
+    }
     __device__ __forceinline__ Key dirichlet() const { return T(0); }
     __device__ __forceinline__ Key neumann() const { return (T)INFINITY; }
     __device__ __forceinline__ bool solid(Key k) const { return isinf(k); }
@@ -186,6 +213,13 @@ struct ClsCoef {
     const GLB uint8_t *__restrict__ cls;
     const T *tab;   // LDS, kClasses x kClasses
     __device__ __forceinline__ Key load(int64_t c) const { return cls[c]; }
+    // the keys of cells c and c + 1, c even (one 16-bit load)
+    __device__ __forceinline__ void load2(int64_t c, Key &a, Key &b) const
+    {
+        const unsigned h = ((const GLB uint16_t *)cls)[c >> 1];
+        a = (int)(h & 0xffu);
+        b = (int)(h >> 8);
+    }
     __device__ __forceinline__ Key dirichlet() const { return kClsWallD; }
     __device__ __forceinline__ Key neumann() const { return kClsSolid; }
     __device__ __forceinline__ bool solid(Key k) const { return k == kClsSolid; }
@@ -210,6 +244,13 @@ struct FracCoef {
     int64_t P;
     bool perx, pery;
     __device__ __forceinline__ Key load(int64_t c) const { return rho[c]; }
+    __device__ __forceinline__ void load2(int64_t c, Key &a, Key &b) const
+    {
+        using V = typename Vec2<T>::type;
+        const V v = ((const GLB V *)rho)[c >> 1];
+        a = v.x;
+        b = v.y;
+    }
     __device__ __forceinline__ Key dirichlet() const { return T(0); }
     __device__ __forceinline__ Key neumann() const { return (T)INFINITY; }
     __device__ __forceinline__ bool solid(Key k) const { return isinf(k); }
@@ -346,61 +387,62 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
                             const C &cf, double (&acc)[3])
 {
     using K = typename C::Key;
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    GLB double *__restrict__ x = gp(S.x);
-    GLB double *__restrict__ z = gp((double *)S.z);
-    const GLB double *__restrict__ rhs = gp(S.rhs);
-    GLB double *__restrict__ pa = gp((double *)S.pa);
-    GLB double *__restrict__ pb = gp((double *)S.pb);
-    const Nbr<K> n = make_nbr(t, S, cf);
-    const bool warm = st.warm != 0;
-    const int64_t P = t.P;
-    // warm start: hull entries of x0 are read as 0 (they are cleared here)
-    auto xv = [&](int64_t m) -> double {
-        const K k = cf.load(m);
-        const double v = x[m];
-        return cf.solid(k) ? 0.0 : v;
-    };
-    int64_t c = (int64_t)t.k0 * P + t.q;
-    K kc = cf.load(c);
-    double xc = warm ? xv(c) : 0.0;
-    K kzm = n.wzm;
-    double xzm = 0.0;
-    if (t.k0 > 0) { kzm = cf.load(c - P); if (warm) xzm = xv(c - P); }
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int k = t.k0; k < t.k1; ++k, c += P) {
-        const bool top = k == S.nz - 1;
-        K kzp = n.wzp;
-        double xzp = 0.0;
-        if (!top) { kzp = cf.load(c + P); if (warm) xzp = xv(c + P); }
-        const bool solid = cf.solid(kc);
-        const double b = solid ? 0.0 : -S.h2 * vol_at(S, c) * rhs[c] - st.bshift;
-        double r, dg;
-        if (warm) {
-            double q;
-            apply_cell<double>(xv, cf, c, n, xc, kc, xzm, kzm, xzp, kzp,
-                               cf.areas(t.i, t.j, k, c), q, dg);
-            r = solid ? 0.0 : b - q;
-            if (solid) x[c] = 0.0;
-        } else {
-            dg = diag_cell<double>(cf, c, n, kc, kzm, kzp, cf.areas(t.i, t.j, k, c));
-            r = b;
-            x[c] = 0.0;
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        GLB double *__restrict__ x = gp(S.x);
+        GLB double *__restrict__ z = gp((double *)S.z);
+        const GLB double *__restrict__ rhs = gp(S.rhs);
+        GLB double *__restrict__ pa = gp((double *)S.pa);
+        GLB double *__restrict__ pb = gp((double *)S.pb);
+        const Nbr<K> n = make_nbr(t, S, cf);
+        const bool warm = st.warm != 0;
+        const int64_t P = t.P;
+        // warm start: hull entries of x0 are read as 0 (they are cleared here)
+        auto xv = [&](int64_t m) -> double {
+            const K k = cf.load(m);
+            const double v = x[m];
+            return cf.solid(k) ? 0.0 : v;
+        };
+        int64_t c = (int64_t)t.k0 * P + t.q;
+        K kc = cf.load(c);
+        double xc = warm ? xv(c) : 0.0;
+        K kzm = n.wzm;
+        double xzm = 0.0;
+        if (t.k0 > 0) { kzm = cf.load(c - P); if (warm) xzm = xv(c - P); }
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int k = t.k0; k < t.k1; ++k, c += P) {
+            const bool top = k == S.nz - 1;
+            K kzp = n.wzp;
+            double xzp = 0.0;
+            if (!top) { kzp = cf.load(c + P); if (warm) xzp = xv(c + P); }
+            const bool solid = cf.solid(kc);
+            const double b = solid ? 0.0 : -S.h2 * vol_at(S, c) * rhs[c] - st.bshift;
+            double r, dg;
+            if (warm) {
+                double q;
+                apply_cell<double>(xv, cf, c, n, xc, kc, xzm, kzm, xzp, kzp,
+                                   cf.areas(t.i, t.j, k, c), q, dg);
+                r = solid ? 0.0 : b - q;
+                if (solid) x[c] = 0.0;
+            } else {
+                dg = diag_cell<double>(cf, c, n, kc, kzm, kzp, cf.areas(t.i, t.j, k, c));
+                r = b;
+                x[c] = 0.0;
+            }
+            const double zc = dg > 0.0 ? r / dg : 0.0;
+            z[c] = zc;
+            pa[c] = 0.0;
+            pb[c] = 0.0;
+            a0 += b * b;
+            a1 += r * zc;
+            a2 += r * r;
+            kzm = kc; xzm = xc;
+            kc = kzp; xc = xzp;
         }
-        const double zc = dg > 0.0 ? r / dg : 0.0;
-        z[c] = zc;
-        pa[c] = 0.0;
-        pb[c] = 0.0;
-        a0 += b * b;
-        a1 += r * zc;
-        a2 += r * r;
-        kzm = kc; xzm = xc;
-        kc = kzp; xc = xzp;
-    }
-    acc[0] += a0;
-    acc[1] += a1;
-    acc[2] += a2;
+        acc[0] += a0;
+        acc[1] += a1;
+        acc[2] += a2;
+    });
 }
 
 // ------------------------------------------------------------------------
@@ -459,6 +501,46 @@ __device__ __forceinline__ void bstore_nt(Buf b, uint32_t v, uint32_t s, double 
 __device__ __forceinline__ void bstore_nt(Buf b, uint32_t v, uint32_t s, float x)
 {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), b.r, v, s, kBufNT);
+}
+
+// Two consecutive elements at byte offset v + s (v + s a multiple of twice
+// the element size): 16 B for doubles, 8 B for floats, 2 B for class bytes.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <int AUX = 0>
+__device__ __forceinline__ void bld2(double *, Buf b, uint32_t v, uint32_t s, double &a0, double &a1)
+{
+    const double2 d = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(b.r, v, s, AUX));
+    a0 = d.x;
+    a1 = d.y;
+}
+template <int AUX = 0>
+__device__ __forceinline__ void bld2(float *, Buf b, uint32_t v, uint32_t s, float &a0, float &a1)
+{
+    const float2 f = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(b.r, v, s, AUX));
+    a0 = f.x;
+    a1 = f.y;
+}
+template <int AUX = 0>
+__device__ __forceinline__ void bld2(uint8_t *, Buf b, uint32_t v, uint32_t s, int &a0, int &a1)
+{
+    const unsigned h = __builtin_amdgcn_raw_buffer_load_b16(b.r, v, s, AUX);
+    a0 = (int)(h & 0xffu);
+    a1 = (int)(h >> 8);
+}
+template <typename E, typename K, int AUX = 0>
+__device__ __forceinline__ void bload2(Buf b, uint32_t v, uint32_t s, K &a0, K &a1)
+{
+    bld2<AUX>((E *)nullptr, b, v, s, a0, a1);
+}
+__device__ __forceinline__ void bstore2_nt(Buf b, uint32_t v, uint32_t s, double a0, double a1)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, make_double2(a0, a1)), b.r, v, s,
+                                           kBufNT);
+}
+__device__ __forceinline__ void bstore2_nt(Buf b, uint32_t v, uint32_t s, float a0, float a1)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(a0, a1)), b.r, v, s,
+                                          kBufNT);
 }
 
 // Byte offsets of a lane's cell and its x/y neighbours within a plane
@@ -671,42 +753,295 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
     acc[1] += a1;
 }
 
+// ------------------------------------------------------------------------
+// pair tiles: passes A and B on two adjacent columns per thread
+// ------------------------------------------------------------------------
+// With nx even a thread owns cells c (even i) and c + 1 of a row: every
+// neighbour pair along y and z, the pair itself and its keys come in one
+// load each (16 B of doubles, 8 B of floats, 2 B of classes); inside the
+// pair the cells are each other's x neighbours, so only the column before
+// the pair (pass A) and the one after it (pass B) are single loads.  That
+// halves the vector memory instructions per cell.
+
+template <typename T, typename K>
+struct PairA {
+    T z0, z1, q0, q1, zy0, zy1, qy0, qy1, zx, qx;
+    K k0, k1, ky0, ky1, kx;
+};
+
+template <typename T, class C>
+__device__ void pair_passA(const Slot &S, const SlotState &st, int64_t lt,
+                           const C &cf, double (&acc)[3])
+{
+    using K = typename C::Key;
+    using KE = typename KeyElem<C>::type;
+    const TileCtx t = tile_ctx(S, lt, 0);   // the pair's first cell (even i)
+    if (!t.active) return;                  // the plane has an even cell count
+    const Window W = tile_window(t, S);
+    const int pbuf = __builtin_amdgcn_readfirstlane(st.pbuf);
+    const Buf bps = W.buf((const T *)(pbuf ? S.pb : S.pa));
+    const Buf bpd = W.buf((const T *)(pbuf ? S.pa : S.pb));
+    const Buf bz = W.buf((const T *)S.z);
+    const Buf bk = W.buf((const KE *)key_array(cf));
+    const T beta = st.first ? T(0) : (T)st.beta;
+    const int nx = S.nx, ny = S.ny, nz = S.nz, bm = S.bcmask;
+    const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
+    const int i0 = t.i, j = t.j;
+    // the column before the pair (across a periodic x wall: the row's last)
+    const bool hxm = i0 > 0 || px;
+    const int oxm = i0 > 0 ? -1 : (px ? nx - 1 : 0);
+    const bool hym = j > 0 || py;
+    const int oym = j > 0 ? -nx : (py ? (ny - 1) * nx : 0);
+    // Dirichlet high walls: x+ of the second cell, y+ of both
+    const bool hwx = !(i0 + 1 < nx - 1 || px) && (bm & 2);
+    const bool hwy = !(j < ny - 1 || py) && (bm & 8);
+    const K wxm = (bm & 1) ? cf.dirichlet() : cf.neumann();
+    const K wym = (bm & 4) ? cf.dirichlet() : cf.neumann();
+    const K wzm = (bm & 16) ? cf.dirichlet() : cf.neumann();
+    const uint32_t vc = (uint32_t)t.q * sizeof(T), vy = (uint32_t)(t.q + oym) * sizeof(T);
+    const uint32_t vx = (uint32_t)(t.q + oxm) * sizeof(T);
+    const uint32_t kc = (uint32_t)t.q * sizeof(KE), ky = (uint32_t)(t.q + oym) * sizeof(KE);
+    const uint32_t kx = (uint32_t)(t.q + oxm) * sizeof(KE);
+    auto load = [&](int kk) {
+        kk = kk < t.k1 ? kk : t.k1 - 1;    // past the tile's end: re-read its last plane
+        const uint32_t sv = W.so(kk, sizeof(T)), sk = W.so(kk, sizeof(KE));
+        PairA<T, K> L;
+        bload2<T>(bz, vc, sv, L.z0, L.z1);
+        bload2<T>(bps, vc, sv, L.q0, L.q1);
+        bload2<KE>(bk, kc, sk, L.k0, L.k1);
+        bload2<T>(bz, vy, sv, L.zy0, L.zy1);
+        bload2<T>(bps, vy, sv, L.qy0, L.qy1);
+        bload2<KE>(bk, ky, sk, L.ky0, L.ky1);
+        L.zx = bload<T>(bz, vx, sv);
+        L.qx = bload<T>(bps, vx, sv);
+        L.kx = bload<KE>(bk, kx, sk);
+        return L;
+    };
+    T pzm0 = T(0), pzm1 = T(0);
+    K kzm0 = wzm, kzm1 = wzm;
+    if (t.k0 > 0) {
+        const uint32_t sv = W.so(t.k0 - 1, sizeof(T)), sk = W.so(t.k0 - 1, sizeof(KE));
+        T z0, z1, q0, q1;
+        bload2<T>(bz, vc, sv, z0, z1);
+        bload2<T>(bps, vc, sv, q0, q1);
+        bload2<KE>(bk, kc, sk, kzm0, kzm1);
+        pzm0 = z0 + beta * q0;
+        pzm1 = z1 + beta * q1;
+    }
+    double a = 0.0;
+    auto step = [&](const PairA<T, K> &L, int kk) {
+        const T p0 = L.z0 + beta * L.q0, p1 = L.z1 + beta * L.q1;
+        const T pxm = hxm ? L.zx + beta * L.qx : T(0);
+        const K kxm = hxm ? L.kx : wxm;
+        const T pym0 = hym ? L.zy0 + beta * L.qy0 : T(0), pym1 = hym ? L.zy1 + beta * L.qy1 : T(0);
+        const K kym0 = hym ? L.ky0 : wym, kym1 = hym ? L.ky1 : wym;
+        const int64_t c0 = (int64_t)kk * t.P + t.q;
+        const Areas6<T> ar0 = cf.areas(i0, j, kk, c0), ar1 = cf.areas(i0 + 1, j, kk, c0 + 1);
+        const bool top = kk == nz - 1 && (bm & 32);
+        const T dx0 = p0 - pxm, dy0 = p0 - pym0, dz0 = p0 - pzm0;
+        T s0 = (cf.beta(L.k0, kxm) * ar0.xm * dx0 * dx0 + cf.beta(L.k0, kym0) * ar0.ym * dy0 * dy0) +
+               cf.beta(L.k0, kzm0) * ar0.zm * dz0 * dz0;
+        const T w0 = (hwy ? ar0.yp : T(0)) + (top ? ar0.zp : T(0));
+        s0 += w0 * cf.beta(L.k0, cf.dirichlet()) * (p0 * p0);
+        const T dx1 = p1 - p0, dy1 = p1 - pym1, dz1 = p1 - pzm1;
+        T s1 = (cf.beta(L.k1, L.k0) * ar1.xm * dx1 * dx1 + cf.beta(L.k1, kym1) * ar1.ym * dy1 * dy1) +
+               cf.beta(L.k1, kzm1) * ar1.zm * dz1 * dz1;
+        const T w1 = (hwx ? ar1.xp : T(0)) + (hwy ? ar1.yp : T(0)) + (top ? ar1.zp : T(0));
+        s1 += w1 * cf.beta(L.k1, cf.dirichlet()) * (p1 * p1);
+        a += (double)s0;
+        a += (double)s1;
+        bstore2_nt(bpd, vc, W.so(kk, sizeof(T)), p0, p1);
+        pzm0 = p0; pzm1 = p1;
+        kzm0 = L.k0; kzm1 = L.k1;
+    };
+    PairA<T, K> A = load(t.k0), B;
+    int k = t.k0;
+    for (; k + 1 < t.k1; k += 2) {
+        B = load(k + 1);
+        step(A, k);
+        A = load(k + 2);
+        step(B, k + 1);
+    }
+    if (k < t.k1) step(A, k);
+    acc[0] += a;
+}
+
+template <typename T, typename X, class C, int XM>
+__device__ void pair_passB(const Slot &S, const SlotState &st, int64_t lt,
+                           const C &cf, double (&acc)[3])
+{
+    using K = typename C::Key;
+    using V = typename Vec2<T>::type;
+    const TileCtx t = tile_ctx(S, lt, 0);
+    if (!t.active) return;
+    const GLB T *__restrict__ p = gp((const T *)(st.pbuf ? S.pb : S.pa));
+    const GLB T *__restrict__ pprev = gp((const T *)(st.pbuf ? S.pa : S.pb));
+    GLB T *__restrict__ z = gp((T *)S.z);
+    // x is the caller's array (FP64): element accesses only
+    GLB X *__restrict__ x = gp(std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32);
+    const GLB V *__restrict__ p2 = (const GLB V *)p;
+    const GLB V *__restrict__ pp2 = (const GLB V *)pprev;
+    GLB V *__restrict__ z2 = (GLB V *)z;
+    const T alpha = (T)st.alpha;
+    const T alpha_prev = (T)st.alpha_prev;
+    const int nx = S.nx, ny = S.ny, bm = S.bcmask;
+    const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
+    const int i0 = t.i, j = t.j;
+    const bool hxm = i0 > 0 || px, hxp = i0 + 1 < nx - 1 || px;
+    const int oxm = i0 > 0 ? -1 : (px ? nx - 1 : 0);
+    const int oxp = i0 + 1 < nx - 1 ? 1 : (px ? -(nx - 1) : 0);   // from the second cell
+    const bool hym = j > 0 || py, hyp = j < ny - 1 || py;
+    const int oym = j > 0 ? -nx : (py ? (ny - 1) * nx : 0);
+    const int oyp = j < ny - 1 ? nx : (py ? -(ny - 1) * nx : 0);
+    const K wxm = (bm & 1) ? cf.dirichlet() : cf.neumann();
+    const K wxp = (bm & 2) ? cf.dirichlet() : cf.neumann();
+    const K wym = (bm & 4) ? cf.dirichlet() : cf.neumann();
+    const K wyp = (bm & 8) ? cf.dirichlet() : cf.neumann();
+    const K wzm = (bm & 16) ? cf.dirichlet() : cf.neumann();
+    const K wzp = (bm & 32) ? cf.dirichlet() : cf.neumann();
+    const int64_t P = t.P;
+    int64_t c = (int64_t)t.k0 * P + t.q;   // even
+    V vc = p2[c >> 1];
+    K kc0, kc1;
+    cf.load2(c, kc0, kc1);
+    T vzm0 = T(0), vzm1 = T(0);
+    K kzm0 = wzm, kzm1 = wzm;
+    if (t.k0 > 0) {
+        const V v = p2[(c - P) >> 1];
+        vzm0 = v.x; vzm1 = v.y;
+        cf.load2(c - P, kzm0, kzm1);
+    }
+    T bzm0 = cf.beta(kc0, kzm0) * cf.areas(i0, j, t.k0, c).zm;
+    T bzm1 = cf.beta(kc1, kzm1) * cf.areas(i0 + 1, j, t.k0, c + 1).zm;
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = t.k0; k < t.k1; ++k, c += P) {
+        const bool top = k == S.nz - 1;
+        const int64_t cz = top ? c : c + P;
+        const V vzp_l = p2[cz >> 1];
+        K kzp0_l, kzp1_l;
+        cf.load2(cz, kzp0_l, kzp1_l);
+        const V vy_m = p2[(c + oym) >> 1], vy_p = p2[(c + oyp) >> 1];
+        K kym0, kym1, kyp0, kyp1;
+        cf.load2(c + oym, kym0, kym1);
+        cf.load2(c + oyp, kyp0, kyp1);
+        const T lvxm = p[c + oxm], lvxp = p[c + 1 + oxp];
+        const K lkxm = cf.load(c + oxm), lkxp = cf.load(c + 1 + oxp);
+        const V zc = __builtin_nontemporal_load(&z2[c >> 1]);
+        const X x0 = XM ? __builtin_nontemporal_load(&x[c]) : X(0);
+        const X x1 = XM ? __builtin_nontemporal_load(&x[c + 1]) : X(0);
+        V ppv;
+        ppv.x = T(0); ppv.y = T(0);
+        if (XM == 2) ppv = __builtin_nontemporal_load(&pp2[c >> 1]);
+        const T vzp0 = top ? T(0) : vzp_l.x, vzp1 = top ? T(0) : vzp_l.y;
+        const K kzp0 = top ? wzp : kzp0_l, kzp1 = top ? wzp : kzp1_l;
+        const Areas6<T> ar0 = cf.areas(i0, j, k, c), ar1 = cf.areas(i0 + 1, j, k, c + 1);
+        // first cell: x- outside the pair, x+ the second cell
+        const K kxm0 = hxm ? lkxm : wxm;
+        const T vxm0 = hxm ? lvxm : T(0);
+        const T bxm0 = cf.beta(kc0, kxm0) * ar0.xm, bxp0 = cf.beta(kc0, kc1) * ar0.xp;
+        const T bym0 = cf.beta(kc0, hym ? kym0 : wym) * ar0.ym;
+        const T byp0 = cf.beta(kc0, hyp ? kyp0 : wyp) * ar0.yp;
+        const T bzp0 = cf.beta(kc0, kzp0) * ar0.zp;
+        const T vym0 = hym ? vy_m.x : T(0), vyp0 = hyp ? vy_p.x : T(0);
+        const T dg0 = ((bxm0 + bxp0) + (bym0 + byp0)) + (bzm0 + bzp0);
+        const T q0 = ((bxm0 * (vc.x - vxm0) + bxp0 * (vc.x - vc.y)) +
+                      (bym0 * (vc.x - vym0) + byp0 * (vc.x - vyp0))) +
+                     (bzm0 * (vc.x - vzm0) + bzp0 * (vc.x - vzp0));
+        // second cell: x- the first cell, x+ outside the pair
+        const K kxp1 = hxp ? lkxp : wxp;
+        const T vxp1 = hxp ? lvxp : T(0);
+        const T bxm1 = cf.beta(kc1, kc0) * ar1.xm, bxp1 = cf.beta(kc1, kxp1) * ar1.xp;
+        const T bym1 = cf.beta(kc1, hym ? kym1 : wym) * ar1.ym;
+        const T byp1 = cf.beta(kc1, hyp ? kyp1 : wyp) * ar1.yp;
+        const T bzp1 = cf.beta(kc1, kzp1) * ar1.zp;
+        const T vym1 = hym ? vy_m.y : T(0), vyp1 = hyp ? vy_p.y : T(0);
+        const T dg1 = ((bxm1 + bxp1) + (bym1 + byp1)) + (bzm1 + bzp1);
+        const T q1 = ((bxm1 * (vc.y - vc.x) + bxp1 * (vc.y - vxp1)) +
+                      (bym1 * (vc.y - vym1) + byp1 * (vc.y - vyp1))) +
+                     (bzm1 * (vc.y - vzm1) + bzp1 * (vc.y - vzp1));
+        if (XM == 1) {
+            __builtin_nontemporal_store(x0 + (X)(alpha * vc.x), &x[c]);
+            __builtin_nontemporal_store(x1 + (X)(alpha * vc.y), &x[c + 1]);
+        }
+        if (XM == 2) {
+            __builtin_nontemporal_store(fma((X)alpha, (X)vc.x, fma((X)alpha_prev, (X)ppv.x, x0)), &x[c]);
+            __builtin_nontemporal_store(fma((X)alpha, (X)vc.y, fma((X)alpha_prev, (X)ppv.y, x1)),
+                                        &x[c + 1]);
+        }
+        const T inv0 = dg0 > T(0) ? recip(dg0) : T(0);   // hull rows keep z = 0
+        const T inv1 = dg1 > T(0) ? recip(dg1) : T(0);
+        V zn;
+        zn.x = zc.x - alpha * q0 * inv0;
+        zn.y = zc.y - alpha * q1 * inv1;
+        __builtin_nontemporal_store(zn, &z2[c >> 1]);
+        const double r0 = (double)dg0 * (double)zn.x, r1 = (double)dg1 * (double)zn.y;
+        a0 += r0 * (double)zn.x;
+        a0 += r1 * (double)zn.y;
+        a1 += r0 * r0;
+        a1 += r1 * r1;
+        vzm0 = vc.x; vzm1 = vc.y;
+        bzm0 = bzp0; bzm1 = bzp1;
+        vc.x = vzp0; vc.y = vzp1;
+        kc0 = kzp0; kc1 = kzp1;
+    }
+    acc[0] += a0;
+    acc[1] += a1;
+}
+
+// Pass A / pass B for the tile form of the slot.
+template <typename T, class C>
+__device__ __forceinline__ void passA(const Slot &S, const SlotState &st, int64_t lt,
+                                      const C &cf, double (&acc)[3])
+{
+    if (S.pairs) pair_passA<T>(S, st, lt, cf, acc);
+    else body_passA<T>(S, st, lt, cf, acc);
+}
+
+template <typename T, typename X, class C, int XM = 1>
+__device__ __forceinline__ void passB(const Slot &S, const SlotState &st, int64_t lt,
+                                      const C &cf, double (&acc)[3])
+{
+    if (S.pairs) pair_passB<T, X, C, XM>(S, st, lt, cf, acc);
+    else body_passB<T, X, C, XM>(S, st, lt, cf, acc);
+}
+
 // K1_CHECK64: ||b - A x||^2 with the FP64 operator.
 template <class C>
 __device__ void body_check64(const Slot &S, const SlotState &st, int64_t lt,
                              const C &cf, double (&acc)[3])
 {
     using K = typename C::Key;
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    const GLB double *__restrict__ x = gp((const double *)S.x);
-    const GLB double *__restrict__ rhs = gp(S.rhs);
-    const Nbr<K> n = make_nbr(t, S, cf);
-    auto xv = [&](int64_t m) -> double { return x[m]; };
-    const int64_t P = t.P;
-    int64_t c = (int64_t)t.k0 * P + t.q;
-    double vc = x[c];
-    K kc = cf.load(c);
-    double vzm = 0.0;
-    K kzm = n.wzm;
-    if (t.k0 > 0) { vzm = x[c - P]; kzm = cf.load(c - P); }
-    double a = 0.0;
-    for (int k = t.k0; k < t.k1; ++k, c += P) {
-        const bool top = k == S.nz - 1;
-        double vzp = 0.0;
-        K kzp = n.wzp;
-        if (!top) { vzp = x[c + P]; kzp = cf.load(c + P); }
-        double q, dg;
-        apply_cell<double>(xv, cf, c, n, vc, kc, vzm, kzm, vzp, kzp,
-                           cf.areas(t.i, t.j, k, c), q, dg);
-        if (!cf.solid(kc)) {
-            const double r = (-S.h2 * vol_at(S, c) * rhs[c] - st.bshift) - q;
-            a += r * r;
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        const GLB double *__restrict__ x = gp((const double *)S.x);
+        const GLB double *__restrict__ rhs = gp(S.rhs);
+        const Nbr<K> n = make_nbr(t, S, cf);
+        auto xv = [&](int64_t m) -> double { return x[m]; };
+        const int64_t P = t.P;
+        int64_t c = (int64_t)t.k0 * P + t.q;
+        double vc = x[c];
+        K kc = cf.load(c);
+        double vzm = 0.0;
+        K kzm = n.wzm;
+        if (t.k0 > 0) { vzm = x[c - P]; kzm = cf.load(c - P); }
+        double a = 0.0;
+        for (int k = t.k0; k < t.k1; ++k, c += P) {
+            const bool top = k == S.nz - 1;
+            double vzp = 0.0;
+            K kzp = n.wzp;
+            if (!top) { vzp = x[c + P]; kzp = cf.load(c + P); }
+            double q, dg;
+            apply_cell<double>(xv, cf, c, n, vc, kc, vzm, kzm, vzp, kzp,
+                               cf.areas(t.i, t.j, k, c), q, dg);
+            if (!cf.solid(kc)) {
+                const double r = (-S.h2 * vol_at(S, c) * rhs[c] - st.bshift) - q;
+                a += r * r;
+            }
+            vzm = vc; kzm = kc;
+            vc = vzp; kc = kzp;
         }
-        vzm = vc; kzm = kc;
-        vc = vzp; kc = kzp;
-    }
-    acc[0] += a;
+        acc[0] += a;
+    });
 }
 
 // K1_IR_INIT: x = 0 (cold) or hull entries cleared (warm), d = 0, both
@@ -715,26 +1050,27 @@ template <class C>
 __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
                              const C &cf, double (&acc)[3])
 {
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    GLB double *__restrict__ x = gp(S.x);
-    GLB float *__restrict__ d = gp(S.d32);
-    GLB float *__restrict__ pa = gp((float *)S.pa);
-    GLB float *__restrict__ pb = gp((float *)S.pb);
-    const GLB double *__restrict__ rhs = gp(S.rhs);
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    const bool warm = st.warm != 0;
-    double a = 0.0;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) {
-        const bool solid = cf.solid(cf.load(c));
-        if (!warm || solid) x[c] = 0.0;
-        d[c] = 0.0f;
-        pa[c] = 0.0f;
-        pb[c] = 0.0f;
-        const double b = solid ? 0.0 : -S.h2 * vol_at(S, c) * rhs[c] - st.bshift;
-        a += b * b;
-    }
-    acc[0] += a;
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        GLB double *__restrict__ x = gp(S.x);
+        GLB float *__restrict__ d = gp(S.d32);
+        GLB float *__restrict__ pa = gp((float *)S.pa);
+        GLB float *__restrict__ pb = gp((float *)S.pb);
+        const GLB double *__restrict__ rhs = gp(S.rhs);
+        int64_t c = (int64_t)t.k0 * t.P + t.q;
+        const bool warm = st.warm != 0;
+        double a = 0.0;
+        for (int k = t.k0; k < t.k1; ++k, c += t.P) {
+            const bool solid = cf.solid(cf.load(c));
+            if (!warm || solid) x[c] = 0.0;
+            d[c] = 0.0f;
+            pa[c] = 0.0f;
+            pb[c] = 0.0f;
+            const double b = solid ? 0.0 : -S.h2 * vol_at(S, c) * rhs[c] - st.bshift;
+            a += b * b;
+        }
+        acc[0] += a;
+    });
 }
 
 // K1_IR_RESID: r = b - A64 (x + s d) in FP64, and the scaled inner right-hand
@@ -746,52 +1082,53 @@ __device__ void body_ir_resid(const Slot &S, const SlotState &st, int64_t lt,
 {
     using K = typename C64::Key;
     using KF = typename C32::Key;
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    const GLB double *__restrict__ x = gp((const double *)S.x);
-    const GLB float *__restrict__ d = gp((const float *)S.d32);
-    GLB float *__restrict__ z = gp((float *)S.z);
-    const GLB double *__restrict__ rhs = gp(S.rhs);
-    const double s = st.upd_s;
-    const double scale = st.scale;
-    const Nbr<K> n = make_nbr(t, S, cf);
-    const Nbr<KF> nf = make_nbr(t, S, cf32);
-    auto xe = [&](int64_t m) -> double { return refined(x[m], s, d[m]); };
-    const int64_t P = t.P;
-    int64_t c = (int64_t)t.k0 * P + t.q;
-    double vc = xe(c);
-    K kc = cf.load(c);
-    KF fc = cf32.load(c);
-    double vzm = 0.0;
-    K kzm = n.wzm;
-    KF fzm = nf.wzm;
-    if (t.k0 > 0) { vzm = xe(c - P); kzm = cf.load(c - P); fzm = cf32.load(c - P); }
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int k = t.k0; k < t.k1; ++k, c += P) {
-        const bool top = k == S.nz - 1;
-        double vzp = 0.0;
-        K kzp = n.wzp;
-        KF fzp = nf.wzp;
-        if (!top) { vzp = xe(c + P); kzp = cf.load(c + P); fzp = cf32.load(c + P); }
-        double q, dg;
-        apply_cell<double>(xe, cf, c, n, vc, kc, vzm, kzm, vzp, kzp,
-                           cf.areas(t.i, t.j, k, c), q, dg);
-        const bool solid = cf.solid(kc);
-        const double r = solid ? 0.0 : ((-S.h2 * vol_at(S, c) * rhs[c] - st.bshift) - q);
-        const float dg32 = diag_cell<float>(cf32, c, nf, fc, fzm, fzp,
-                                            cf32.areas(t.i, t.j, k, c));
-        const float z32 = dg32 > 0.0f ? (float)((scale * r) / (double)dg32) : 0.0f;
-        z[c] = z32;
-        const double rz = (double)dg32 * (double)z32;
-        a0 += r * r;
-        a1 += rz * (double)z32;
-        a2 += rz * rz;
-        vzm = vc; kzm = kc; fzm = fc;
-        vc = vzp; kc = kzp; fc = fzp;
-    }
-    acc[0] += a0;
-    acc[1] += a1;
-    acc[2] += a2;
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        const GLB double *__restrict__ x = gp((const double *)S.x);
+        const GLB float *__restrict__ d = gp((const float *)S.d32);
+        GLB float *__restrict__ z = gp((float *)S.z);
+        const GLB double *__restrict__ rhs = gp(S.rhs);
+        const double s = st.upd_s;
+        const double scale = st.scale;
+        const Nbr<K> n = make_nbr(t, S, cf);
+        const Nbr<KF> nf = make_nbr(t, S, cf32);
+        auto xe = [&](int64_t m) -> double { return refined(x[m], s, d[m]); };
+        const int64_t P = t.P;
+        int64_t c = (int64_t)t.k0 * P + t.q;
+        double vc = xe(c);
+        K kc = cf.load(c);
+        KF fc = cf32.load(c);
+        double vzm = 0.0;
+        K kzm = n.wzm;
+        KF fzm = nf.wzm;
+        if (t.k0 > 0) { vzm = xe(c - P); kzm = cf.load(c - P); fzm = cf32.load(c - P); }
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int k = t.k0; k < t.k1; ++k, c += P) {
+            const bool top = k == S.nz - 1;
+            double vzp = 0.0;
+            K kzp = n.wzp;
+            KF fzp = nf.wzp;
+            if (!top) { vzp = xe(c + P); kzp = cf.load(c + P); fzp = cf32.load(c + P); }
+            double q, dg;
+            apply_cell<double>(xe, cf, c, n, vc, kc, vzm, kzm, vzp, kzp,
+                               cf.areas(t.i, t.j, k, c), q, dg);
+            const bool solid = cf.solid(kc);
+            const double r = solid ? 0.0 : ((-S.h2 * vol_at(S, c) * rhs[c] - st.bshift) - q);
+            const float dg32 = diag_cell<float>(cf32, c, nf, fc, fzm, fzp,
+                                                cf32.areas(t.i, t.j, k, c));
+            const float z32 = dg32 > 0.0f ? (float)((scale * r) / (double)dg32) : 0.0f;
+            z[c] = z32;
+            const double rz = (double)dg32 * (double)z32;
+            a0 += r * r;
+            a1 += rz * (double)z32;
+            a2 += rz * rz;
+            vzm = vc; kzm = kc; fzm = fc;
+            vc = vzp; kc = kzp; fc = fzp;
+        }
+        acc[0] += a0;
+        acc[1] += a1;
+        acc[2] += a2;
+    });
 }
 
 // K1_FLUSH_X: the update the last iteration left pending, with the current
@@ -799,47 +1136,50 @@ __device__ void body_ir_resid(const Slot &S, const SlotState &st, int64_t lt,
 // p (FP32+IR).
 __device__ void body_flush_x(const Slot &S, const SlotState &st, int64_t lt, double (&acc)[3])
 {
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    if (S.d32) {
-        GLB float *__restrict__ d = gp(S.d32);
-        const GLB float *__restrict__ p = gp((const float *)(st.pbuf ? S.pb : S.pa));
-        const float alpha = (float)st.alpha;
-        for (int k = t.k0; k < t.k1; ++k, c += t.P) d[c] = fmaf(alpha, p[c], d[c]);
-        return;
-    }
-    GLB double *__restrict__ x = gp(S.x);
-    const GLB double *__restrict__ p = gp((const double *)(st.pbuf ? S.pb : S.pa));
-    const double alpha = st.alpha;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) x[c] = fma(alpha, p[c], x[c]);
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        int64_t c = (int64_t)t.k0 * t.P + t.q;
+        if (S.d32) {
+            GLB float *__restrict__ d = gp(S.d32);
+            const GLB float *__restrict__ p = gp((const float *)(st.pbuf ? S.pb : S.pa));
+            const float alpha = (float)st.alpha;
+            for (int k = t.k0; k < t.k1; ++k, c += t.P) d[c] = fmaf(alpha, p[c], d[c]);
+            return;
+        }
+        GLB double *__restrict__ x = gp(S.x);
+        const GLB double *__restrict__ p = gp((const double *)(st.pbuf ? S.pb : S.pa));
+        const double alpha = st.alpha;
+        for (int k = t.k0; k < t.k1; ++k, c += t.P) x[c] = fma(alpha, p[c], x[c]);
+    });
 }
 
 // K2_IR_UPDATE: x += s d, d = 0.
 __device__ void body_ir_update(const Slot &S, const SlotState &st, int64_t lt,
                                double (&acc)[3])
 {
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    GLB double *__restrict__ x = gp(S.x);
-    GLB float *__restrict__ d = gp(S.d32);
-    const double s = st.upd_s;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) {
-        x[c] = refined(x[c], s, d[c]);
-        d[c] = 0.0f;
-    }
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        GLB double *__restrict__ x = gp(S.x);
+        GLB float *__restrict__ d = gp(S.d32);
+        const double s = st.upd_s;
+        int64_t c = (int64_t)t.k0 * t.P + t.q;
+        for (int k = t.k0; k < t.k1; ++k, c += t.P) {
+            x[c] = refined(x[c], s, d[c]);
+            d[c] = 0.0f;
+        }
+    });
 }
 
 // K2_ZERO_X: x = 0 (zero source with a warm start).
 __device__ void body_zero_x(const Slot &S, const SlotState &st, int64_t lt,
                             double (&acc)[3])
 {
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    GLB double *__restrict__ x = gp(S.x);
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) x[c] = 0.0;
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        GLB double *__restrict__ x = gp(S.x);
+        int64_t c = (int64_t)t.k0 * t.P + t.q;
+        for (int k = t.k0; k < t.k1; ++k, c += t.P) x[c] = 0.0;
+    });
 }
 
 // Singular problems (no Dirichlet wall: the constant over the fluid is the
@@ -850,45 +1190,48 @@ template <class C>
 __device__ void body_mean_b(const Slot &S, const SlotState &st, int64_t lt,
                             const C &cf, double (&acc)[3])
 {
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    const GLB double *__restrict__ rhs = gp(S.rhs);
-    double a = 0.0, m = 0.0;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P) {
-        if (cf.solid(cf.load(c))) continue;
-        a += -S.h2 * vol_at(S, c) * rhs[c];
-        m += 1.0;
-    }
-    acc[0] += a;
-    acc[1] += m;
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        const GLB double *__restrict__ rhs = gp(S.rhs);
+        double a = 0.0, m = 0.0;
+        int64_t c = (int64_t)t.k0 * t.P + t.q;
+        for (int k = t.k0; k < t.k1; ++k, c += t.P) {
+            if (cf.solid(cf.load(c))) continue;
+            a += -S.h2 * vol_at(S, c) * rhs[c];
+            m += 1.0;
+        }
+        acc[0] += a;
+        acc[1] += m;
+    });
 }
 
 template <class C>
 __device__ void body_mean_x(const Slot &S, const SlotState &st, int64_t lt,
                             const C &cf, double (&acc)[3])
 {
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    const GLB double *__restrict__ x = gp((const double *)S.x);
-    double a = 0.0;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P)
-        if (!cf.solid(cf.load(c))) a += x[c];
-    acc[0] += a;
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        const GLB double *__restrict__ x = gp((const double *)S.x);
+        double a = 0.0;
+        int64_t c = (int64_t)t.k0 * t.P + t.q;
+        for (int k = t.k0; k < t.k1; ++k, c += t.P)
+            if (!cf.solid(cf.load(c))) a += x[c];
+        acc[0] += a;
+    });
 }
 
 template <class C>
 __device__ void body_sub_x(const Slot &S, const SlotState &st, int64_t lt,
                            const C &cf, double (&acc)[3])
 {
-    const TileCtx t = tile_ctx(S, lt);
-    if (!t.active) return;
-    GLB double *__restrict__ x = gp(S.x);
-    const double m = st.xshift;
-    int64_t c = (int64_t)t.k0 * t.P + t.q;
-    for (int k = t.k0; k < t.k1; ++k, c += t.P)
-        if (!cf.solid(cf.load(c))) x[c] -= m;
+    for_rows(S, lt, [&](const TileCtx &t) {
+        if (!t.active) return;
+        GLB double *__restrict__ x = gp(S.x);
+        const double m = st.xshift;
+        int64_t c = (int64_t)t.k0 * t.P + t.q;
+        for (int k = t.k0; k < t.k1; ++k, c += t.P)
+            if (!cf.solid(cf.load(c))) x[c] -= m;
+    });
 }
 
 // ------------------------------------------------------------------------
@@ -1155,9 +1498,9 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
     if (FAMILY == PCG_PREC_FP64) {
         if (WHICH == 1) {
             if (ph == K1_CG_A) {
-                if (MODE == 2) body_passA<double>(S, st, lt, frac_coef<double>(S, S.rho64), acc);
-                else if (MODE == 1) body_passA<double>(S, st, lt, c64, acc);
-                else body_passA<double>(S, st, lt, r64, acc);
+                if (MODE == 2) passA<double>(S, st, lt, frac_coef<double>(S, S.rho64), acc);
+                else if (MODE == 1) passA<double>(S, st, lt, c64, acc);
+                else passA<double>(S, st, lt, r64, acc);
             }
         } else {
             if (ph == K2_CG_B) {
@@ -1165,14 +1508,14 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
                 const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) != 0;
                 if (MODE == 2) {
                     const FracCoef<double> f = frac_coef<double>(S, S.rho64);
-                    if (catch_up) body_passB<double, double, FracCoef<double>, 2>(S, st, lt, f, acc);
-                    else body_passB<double, double, FracCoef<double>, 0>(S, st, lt, f, acc);
+                    if (catch_up) passB<double, double, FracCoef<double>, 2>(S, st, lt, f, acc);
+                    else passB<double, double, FracCoef<double>, 0>(S, st, lt, f, acc);
                 } else if (MODE == 1) {
-                    if (catch_up) body_passB<double, double, ClsCoef<double>, 2>(S, st, lt, c64, acc);
-                    else body_passB<double, double, ClsCoef<double>, 0>(S, st, lt, c64, acc);
+                    if (catch_up) passB<double, double, ClsCoef<double>, 2>(S, st, lt, c64, acc);
+                    else passB<double, double, ClsCoef<double>, 0>(S, st, lt, c64, acc);
                 } else {
-                    if (catch_up) body_passB<double, double, RhoCoef<double>, 2>(S, st, lt, r64, acc);
-                    else body_passB<double, double, RhoCoef<double>, 0>(S, st, lt, r64, acc);
+                    if (catch_up) passB<double, double, RhoCoef<double>, 2>(S, st, lt, r64, acc);
+                    else passB<double, double, RhoCoef<double>, 0>(S, st, lt, r64, acc);
                 }
             } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
             else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);
@@ -1182,9 +1525,9 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
         const ClsCoef<float> c32{ gp(S.cls), tab32 };
         if (WHICH == 1) {
             if (ph == K1_IR_A) {
-                if (MODE == 2) body_passA<float>(S, st, lt, frac_coef<float>(S, S.rho32), acc);
-                else if (MODE == 1) body_passA<float>(S, st, lt, c32, acc);
-                else body_passA<float>(S, st, lt, r32, acc);
+                if (MODE == 2) passA<float>(S, st, lt, frac_coef<float>(S, S.rho32), acc);
+                else if (MODE == 1) passA<float>(S, st, lt, c32, acc);
+                else passA<float>(S, st, lt, r32, acc);
             }
         } else {
             if (ph == K2_IR_B) {
@@ -1192,14 +1535,14 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
                 const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) != 0;
                 if (MODE == 2) {
                     const FracCoef<float> f = frac_coef<float>(S, S.rho32);
-                    if (catch_up) body_passB<float, float, FracCoef<float>, 2>(S, st, lt, f, acc);
-                    else body_passB<float, float, FracCoef<float>, 0>(S, st, lt, f, acc);
+                    if (catch_up) passB<float, float, FracCoef<float>, 2>(S, st, lt, f, acc);
+                    else passB<float, float, FracCoef<float>, 0>(S, st, lt, f, acc);
                 } else if (MODE == 1) {
-                    if (catch_up) body_passB<float, float, ClsCoef<float>, 2>(S, st, lt, c32, acc);
-                    else body_passB<float, float, ClsCoef<float>, 0>(S, st, lt, c32, acc);
+                    if (catch_up) passB<float, float, ClsCoef<float>, 2>(S, st, lt, c32, acc);
+                    else passB<float, float, ClsCoef<float>, 0>(S, st, lt, c32, acc);
                 } else {
-                    if (catch_up) body_passB<float, float, RhoCoef<float>, 2>(S, st, lt, r32, acc);
-                    else body_passB<float, float, RhoCoef<float>, 0>(S, st, lt, r32, acc);
+                    if (catch_up) passB<float, float, RhoCoef<float>, 2>(S, st, lt, r32, acc);
+                    else passB<float, float, RhoCoef<float>, 0>(S, st, lt, r32, acc);
                 }
             } else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);
             else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);

@@ -84,10 +84,12 @@ struct alignas(128) SlotState {
 struct Slot {
     int32_t nx, ny, nz;
     int32_t bcmask;        // bit f set: wall f is Dirichlet (x-,x+,y-,y+,z-,z+)
-    int32_t plane_tiles;   // ceil(nx*ny / kBlock)
+    int32_t plane_tiles;   // ceil(nx*ny / (kBlock or 2 kBlock with pairs))
     int32_t ztiles;        // ceil(nz / tz)
     int32_t tz;            // planes per tile
     int32_t permask;       // bit 0: periodic x walls, bit 1: periodic y walls
+    int32_t pairs;         // 1: a thread owns two adjacent columns (nx even)
+    int32_t pad_;
     int64_t tile_begin;    // first global tile of this slot
     int64_t ntiles;        // plane_tiles * ztiles
     double h2;             // h*h
