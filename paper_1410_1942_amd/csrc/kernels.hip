@@ -99,22 +99,33 @@ struct TileCtx {
 
 // Column of this thread in tile lt.  Without pairs a tile holds kBlock
 // consecutive cells of the plane, one per thread; with pairs (nx even) it
-// holds 2 kBlock, thread l owning cells 2l (r = 0) and 2l + 1 (r = 1) of the
-// tile, which share a row.
-__device__ __forceinline__ TileCtx tile_ctx(const Slot &S, int64_t lt, int r = 0)
+// holds 2 kBlock.  Phases that treat cells one by one take them in two
+// coalesced halves (r = 0: cells l, r = 1: cells kBlock + l of the tile);
+// passes A and B give thread l the adjacent cells 2l and 2l + 1 (pair_ctx).
+__device__ __forceinline__ TileCtx tile_at(const Slot &S, int64_t lt, int q_in_tile)
 {
     TileCtx t;
     const int pt = (int)(lt % S.plane_tiles);
     const int zt = (int)(lt / S.plane_tiles);
     t.P = S.nx * S.ny;
-    t.q = S.pairs ? pt * (2 * kBlock) + 2 * (int)threadIdx.x + r
-                  : pt * kBlock + (int)threadIdx.x;
+    t.q = pt * (S.pairs ? 2 * kBlock : kBlock) + q_in_tile;
     t.active = t.q < t.P;
     t.i = t.q % S.nx;
     t.j = t.q / S.nx;
     t.k0 = zt * S.tz;
     t.k1 = min(S.nz, t.k0 + S.tz);
     return t;
+}
+
+__device__ __forceinline__ TileCtx tile_ctx(const Slot &S, int64_t lt, int r = 0)
+{
+    return tile_at(S, lt, r * kBlock + (int)threadIdx.x);
+}
+
+// The first of the two adjacent cells of this thread (pair tiles).
+__device__ __forceinline__ TileCtx pair_ctx(const Slot &S, int64_t lt)
+{
+    return tile_at(S, lt, 2 * (int)threadIdx.x);
 }
 
 // f(t) for each column of the thread in tile lt (two with pairs).
@@ -775,7 +786,7 @@ __device__ void pair_passA(const Slot &S, const SlotState &st, int64_t lt,
 {
     using K = typename C::Key;
     using KE = typename KeyElem<C>::type;
-    const TileCtx t = tile_ctx(S, lt, 0);   // the pair's first cell (even i)
+    const TileCtx t = pair_ctx(S, lt);      // the pair's first cell (even i)
     if (!t.active) return;                  // the plane has an even cell count
     const Window W = tile_window(t, S);
     const int pbuf = __builtin_amdgcn_readfirstlane(st.pbuf);
@@ -872,13 +883,16 @@ __device__ void pair_passB(const Slot &S, const SlotState &st, int64_t lt,
 {
     using K = typename C::Key;
     using V = typename Vec2<T>::type;
-    const TileCtx t = tile_ctx(S, lt, 0);
+    const TileCtx t = pair_ctx(S, lt);
     if (!t.active) return;
     const GLB T *__restrict__ p = gp((const T *)(st.pbuf ? S.pb : S.pa));
     const GLB T *__restrict__ pprev = gp((const T *)(st.pbuf ? S.pa : S.pb));
     GLB T *__restrict__ z = gp((T *)S.z);
-    // x is the caller's array (FP64): element accesses only
+    // x is the caller's array (FP64), read and written element by element;
+    // the FP32 correction d is ours (aligned), in pairs
     GLB X *__restrict__ x = gp(std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32);
+    constexpr bool kXPair = std::is_same<X, float>::value;
+    using XV = typename Vec2<X>::type;
     const GLB V *__restrict__ p2 = (const GLB V *)p;
     const GLB V *__restrict__ pp2 = (const GLB V *)pprev;
     GLB V *__restrict__ z2 = (GLB V *)z;
@@ -927,8 +941,16 @@ __device__ void pair_passB(const Slot &S, const SlotState &st, int64_t lt,
         const T lvxm = p[c + oxm], lvxp = p[c + 1 + oxp];
         const K lkxm = cf.load(c + oxm), lkxp = cf.load(c + 1 + oxp);
         const V zc = __builtin_nontemporal_load(&z2[c >> 1]);
-        const X x0 = XM ? __builtin_nontemporal_load(&x[c]) : X(0);
-        const X x1 = XM ? __builtin_nontemporal_load(&x[c + 1]) : X(0);
+        X x0 = X(0), x1 = X(0);
+        if (XM) {
+            if constexpr (kXPair) {
+                const XV xv = __builtin_nontemporal_load(&((GLB XV *)x)[c >> 1]);
+                x0 = xv.x; x1 = xv.y;
+            } else {
+                x0 = __builtin_nontemporal_load(&x[c]);
+                x1 = __builtin_nontemporal_load(&x[c + 1]);
+            }
+        }
         V ppv;
         ppv.x = T(0); ppv.y = T(0);
         if (XM == 2) ppv = __builtin_nontemporal_load(&pp2[c >> 1]);
@@ -959,14 +981,23 @@ __device__ void pair_passB(const Slot &S, const SlotState &st, int64_t lt,
         const T q1 = ((bxm1 * (vc.y - vc.x) + bxp1 * (vc.y - vxp1)) +
                       (bym1 * (vc.y - vym1) + byp1 * (vc.y - vyp1))) +
                      (bzm1 * (vc.y - vzm1) + bzp1 * (vc.y - vzp1));
-        if (XM == 1) {
-            __builtin_nontemporal_store(x0 + (X)(alpha * vc.x), &x[c]);
-            __builtin_nontemporal_store(x1 + (X)(alpha * vc.y), &x[c + 1]);
-        }
-        if (XM == 2) {
-            __builtin_nontemporal_store(fma((X)alpha, (X)vc.x, fma((X)alpha_prev, (X)ppv.x, x0)), &x[c]);
-            __builtin_nontemporal_store(fma((X)alpha, (X)vc.y, fma((X)alpha_prev, (X)ppv.y, x1)),
-                                        &x[c + 1]);
+        if (XM) {
+            X xn0, xn1;
+            if (XM == 1) {
+                xn0 = x0 + (X)(alpha * vc.x);
+                xn1 = x1 + (X)(alpha * vc.y);
+            } else {
+                xn0 = fma((X)alpha, (X)vc.x, fma((X)alpha_prev, (X)ppv.x, x0));
+                xn1 = fma((X)alpha, (X)vc.y, fma((X)alpha_prev, (X)ppv.y, x1));
+            }
+            if constexpr (kXPair) {
+                XV xv;
+                xv.x = xn0; xv.y = xn1;
+                __builtin_nontemporal_store(xv, &((GLB XV *)x)[c >> 1]);
+            } else {
+                __builtin_nontemporal_store(xn0, &x[c]);
+                __builtin_nontemporal_store(xn1, &x[c + 1]);
+            }
         }
         const T inv0 = dg0 > T(0) ? recip(dg0) : T(0);   // hull rows keep z = 0
         const T inv1 = dg1 > T(0) ? recip(dg1) : T(0);
