@@ -110,14 +110,14 @@ struct TileRule {
 
 // Built-in table: the autotuner's choice on gfx950 (package tile_table.json).
 std::vector<TileRule> g_rules[2] = {  // single solves: FP64, FP32+IR
-    { { 7524, 2, 256 }, { 21283, 2, 256 }, { 60198, 8, 768 }, { 170267, 4, 768 }, { 481589, 8, 768 }, { 1362140, 8, 768 }, { 3852714, 16, 256 }, { 10897121, 64, 512 }, { 30821713, 64, 2048 }, { 87176971, 32, 512 }, { INT64_MAX, 256, 512 } },
-    { { 7524, 2, 512 }, { 21283, 2, 1024 }, { 60198, 2, 2048 }, { 170267, 4, 768 }, { 481589, 8, 1024 }, { 1362140, 16, 256 }, { 3852714, 16, 512 }, { 10897121, 64, 1024 }, { 30821713, 64, 768 }, { 87176971, 32, 512 }, { INT64_MAX, 256, 512 } },
+    { { 7524, 4, 1024 }, { 21283, 2, 512 }, { 60198, 8, 1024 }, { 170267, 4, 2048 }, { 481589, 8, 2048 }, { 1362140, 8, 768 }, { 3852714, 16, 2048 }, { 10897121, 64, 768 }, { 30821713, 64, 768 }, { 87176971, 32, 512 }, { INT64_MAX, 256, 512 } },
+    { { 7524, 2, 2048 }, { 21283, 2, 768 }, { 60198, 2, 2048 }, { 170267, 2, 512 }, { 481589, 4, 768 }, { 1362140, 8, 512 }, { 3852714, 16, 512 }, { 10897121, 32, 512 }, { 30821713, 16, 512 }, { 87176971, 16, 512 }, { INT64_MAX, 256, 768 } },
 };
 
 // Batches: longer tiles (the resident solves fill the device together).
 std::vector<TileRule> g_rules_batch[2] = {
-    { { 7524, 8, 0 }, { 21283, 16, 0 }, { 60198, 16, 0 }, { 170267, 32, 0 }, { 481589, 32, 0 }, { 1362140, 32, 0 }, { 3852714, 16, 0 }, { INT64_MAX, 64, 0 } },
-    { { 7524, 8, 0 }, { 21283, 16, 0 }, { 60198, 16, 0 }, { 170267, 32, 0 }, { 481589, 32, 0 }, { 1362140, 32, 0 }, { 3852714, 32, 0 }, { INT64_MAX, 64, 0 } },
+    { { 7524, 8, 0 }, { 21283, 16, 0 }, { 60198, 16, 0 }, { 170267, 32, 0 }, { 481589, 16, 0 }, { 1362140, 32, 0 }, { 3852714, 16, 0 }, { INT64_MAX, 64, 0 } },
+    { { 7524, 8, 0 }, { 21283, 8, 0 }, { 60198, 8, 0 }, { 170267, 16, 0 }, { 481589, 16, 0 }, { 1362140, 16, 0 }, { 3852714, 16, 0 }, { INT64_MAX, 32, 0 } },
 };
 
 std::vector<TileRule> &rules_of(int prec, bool batch)
@@ -188,7 +188,7 @@ private:
 };
 
 struct Geometry {
-    int nx, ny, nz, tz, plane_tiles, ztiles, pairs;
+    int nx, ny, nz, tz, plane_tiles, ztiles, cpt;
     int64_t n, ntiles;
 };
 
@@ -204,9 +204,10 @@ Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch)
     // byte offsets
     const int64_t tz_cap = kMaxTileBytes / (plane * 8) - 2;
     if (G.tz > tz_cap) G.tz = (int)std::max<int64_t>(1, tz_cap);
-    // two adjacent columns per thread when rows have an even length
-    G.pairs = g.nx % 2 == 0 ? 1 : 0;
-    const int64_t per_tile = G.pairs ? 2 * kBlock : kBlock;
+    // adjacent columns per thread: two when rows have an even length, four
+    // for FP32 passes when it is a multiple of four
+    G.cpt = (prec == PCG_PREC_FP32_IR && g.nx % 4 == 0) ? 4 : (g.nx % 2 == 0 ? 2 : 1);
+    const int64_t per_tile = (int64_t)G.cpt * kBlock;
     G.plane_tiles = (int)((plane + per_tile - 1) / per_tile);
     G.ztiles = (g.nz + G.tz - 1) / G.tz;
     G.ntiles = (int64_t)G.plane_tiles * G.ztiles;
@@ -836,7 +837,7 @@ struct Engine {
             d.bcmask = S.bcmask;
         d.permask = S.permask;
             d.plane_tiles = S.geo.plane_tiles;
-            d.pairs = S.geo.pairs;
+            d.cpt = S.geo.cpt;
             d.ztiles = S.geo.ztiles;
             d.tz = S.geo.tz;
             d.tile_begin = tb;

@@ -97,18 +97,19 @@ struct TileCtx {
     bool active;
 };
 
-// Column of this thread in tile lt.  Without pairs a tile holds kBlock
-// consecutive cells of the plane, one per thread; with pairs (nx even) it
-// holds 2 kBlock.  Phases that treat cells one by one take them in two
-// coalesced halves (r = 0: cells l, r = 1: cells kBlock + l of the tile);
-// passes A and B give thread l the adjacent cells 2l and 2l + 1 (pair_ctx).
+// Column of this thread in tile lt.  A tile holds S.cpt kBlock consecutive
+// cells of a plane (S.cpt = 1, 2 or 4 cells per thread; 2 and 4 need a row
+// length divisible by them).  Phases that treat cells one by one take them
+// in S.cpt coalesced runs (r: cells r kBlock + l of the tile); passes A and
+// B give thread l the adjacent cells S.cpt l .. S.cpt l + S.cpt - 1 of one
+// row (group_ctx).
 __device__ __forceinline__ TileCtx tile_at(const Slot &S, int64_t lt, int q_in_tile)
 {
     TileCtx t;
     const int pt = (int)(lt % S.plane_tiles);
     const int zt = (int)(lt / S.plane_tiles);
     t.P = S.nx * S.ny;
-    t.q = pt * (S.pairs ? 2 * kBlock : kBlock) + q_in_tile;
+    t.q = pt * (S.cpt * kBlock) + q_in_tile;
     t.active = t.q < t.P;
     t.i = t.q % S.nx;
     t.j = t.q / S.nx;
@@ -122,18 +123,17 @@ __device__ __forceinline__ TileCtx tile_ctx(const Slot &S, int64_t lt, int r = 0
     return tile_at(S, lt, r * kBlock + (int)threadIdx.x);
 }
 
-// The first of the two adjacent cells of this thread (pair tiles).
-__device__ __forceinline__ TileCtx pair_ctx(const Slot &S, int64_t lt)
+// The first of this thread's adjacent cells (S.cpt > 1).
+__device__ __forceinline__ TileCtx group_ctx(const Slot &S, int64_t lt)
 {
-    return tile_at(S, lt, 2 * (int)threadIdx.x);
+    return tile_at(S, lt, S.cpt * (int)threadIdx.x);
 }
 
-// f(t) for each column of the thread in tile lt (two with pairs).
+// f(t) for each column of the thread in tile lt (S.cpt of them).
 template <class F>
 __device__ __forceinline__ void for_rows(const Slot &S, int64_t lt, F &&f)
 {
-    f(tile_ctx(S, lt, 0));
-    if (S.pairs) f(tile_ctx(S, lt, 1));
+    for (int r = 0; r < S.cpt; ++r) f(tile_ctx(S, lt, r));
 }
 
 // Global-address-space views: pointers read from the slot table are
@@ -190,23 +190,23 @@ struct Areas6 {
 };
 
 // Two consecutive values of T in one load.
-typedef double vec2d __attribute__((ext_vector_type(2)));
-typedef float vec2f __attribute__((ext_vector_type(2)));
-template <typename T> struct Vec2;
-template <> struct Vec2<double> { using type = vec2d; };
-template <> struct Vec2<float> { using type = vec2f; };
+// N consecutive values of T in one load.
+template <typename T, int N> struct VecN {
+    typedef T type __attribute__((ext_vector_type(N)));
+};
 
 template <typename T>
 struct RhoCoef {
     using Key = T;
     const GLB T *__restrict__ rho;
     __device__ __forceinline__ Key load(int64_t c) const { return rho[c]; }
-    __device__ __forceinline__ void load2(int64_t c, Key &a, Key &b) const
+    template <int N>
+    __device__ __forceinline__ void loadN(int64_t c, Key (&k)[N]) const
     {
-        using V = typename Vec2<T>::type;
-        const V v = ((const GLB V *)rho)[c >> 1];
-        a = v.x;
-        b = v.y;
+        using V = typename VecN<T, N>::type;
+        const V v = ((const GLB V *)rho)[c / N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) k[n] = v[n];
     }
     __device__ __forceinline__ Key dirichlet() const { return T(0); }
     __device__ __forceinline__ Key neumann() const { return (T)INFINITY; }
@@ -224,12 +224,15 @@ struct ClsCoef {
     const GLB uint8_t *__restrict__ cls;
     const T *tab;   // LDS, kClasses x kClasses
     __device__ __forceinline__ Key load(int64_t c) const { return cls[c]; }
-    // the keys of cells c and c + 1, c even (one 16-bit load)
-    __device__ __forceinline__ void load2(int64_t c, Key &a, Key &b) const
+    // the keys of cells c .. c + N - 1, c a multiple of N (one load)
+    template <int N>
+    __device__ __forceinline__ void loadN(int64_t c, Key (&k)[N]) const
     {
-        const unsigned h = ((const GLB uint16_t *)cls)[c >> 1];
-        a = (int)(h & 0xffu);
-        b = (int)(h >> 8);
+        static_assert(N == 2 || N == 4, "two or four cells");
+        using W = typename std::conditional<N == 2, uint16_t, uint32_t>::type;
+        const unsigned h = ((const GLB W *)cls)[c / N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) k[n] = (int)((h >> (8 * n)) & 0xffu);
     }
     __device__ __forceinline__ Key dirichlet() const { return kClsWallD; }
     __device__ __forceinline__ Key neumann() const { return kClsSolid; }
@@ -255,12 +258,13 @@ struct FracCoef {
     int64_t P;
     bool perx, pery;
     __device__ __forceinline__ Key load(int64_t c) const { return rho[c]; }
-    __device__ __forceinline__ void load2(int64_t c, Key &a, Key &b) const
+    template <int N>
+    __device__ __forceinline__ void loadN(int64_t c, Key (&k)[N]) const
     {
-        using V = typename Vec2<T>::type;
-        const V v = ((const GLB V *)rho)[c >> 1];
-        a = v.x;
-        b = v.y;
+        using V = typename VecN<T, N>::type;
+        const V v = ((const GLB V *)rho)[c / N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) k[n] = v[n];
     }
     __device__ __forceinline__ Key dirichlet() const { return T(0); }
     __device__ __forceinline__ Key neumann() const { return (T)INFINITY; }
@@ -514,44 +518,42 @@ __device__ __forceinline__ void bstore_nt(Buf b, uint32_t v, uint32_t s, float x
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, x), b.r, v, s, kBufNT);
 }
 
-// Two consecutive elements at byte offset v + s (v + s a multiple of twice
-// the element size): 16 B for doubles, 8 B for floats, 2 B for class bytes.
+// N consecutive elements at byte offset v + s (a multiple of their total
+// size): 8 or 16 B of floats or doubles, 2 or 4 class bytes.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-template <int AUX = 0>
-__device__ __forceinline__ void bld2(double *, Buf b, uint32_t v, uint32_t s, double &a0, double &a1)
+template <int BYTES, int AUX>
+__device__ __forceinline__ auto braw(Buf b, uint32_t v, uint32_t s)
 {
-    const double2 d = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(b.r, v, s, AUX));
-    a0 = d.x;
-    a1 = d.y;
+    if constexpr (BYTES == 16) return __builtin_amdgcn_raw_buffer_load_b128(b.r, v, s, AUX);
+    else if constexpr (BYTES == 8) return __builtin_amdgcn_raw_buffer_load_b64(b.r, v, s, AUX);
+    else if constexpr (BYTES == 4) return __builtin_amdgcn_raw_buffer_load_b32(b.r, v, s, AUX);
+    else return (unsigned)__builtin_amdgcn_raw_buffer_load_b16(b.r, v, s, AUX);
 }
-template <int AUX = 0>
-__device__ __forceinline__ void bld2(float *, Buf b, uint32_t v, uint32_t s, float &a0, float &a1)
+template <typename E, int N, int AUX = 0, typename K>
+__device__ __forceinline__ void bloadN(Buf b, uint32_t v, uint32_t s, K (&out)[N])
 {
-    const float2 f = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(b.r, v, s, AUX));
-    a0 = f.x;
-    a1 = f.y;
+    if constexpr (std::is_same<E, uint8_t>::value) {
+        const unsigned h = braw<N, AUX>(b, v, s);
+#pragma unroll
+        for (int n = 0; n < N; ++n) out[n] = (K)((h >> (8 * n)) & 0xffu);
+    } else {
+        using V = typename VecN<E, N>::type;
+        const V x = __builtin_bit_cast(V, braw<N * (int)sizeof(E), AUX>(b, v, s));
+#pragma unroll
+        for (int n = 0; n < N; ++n) out[n] = x[n];
+    }
 }
-template <int AUX = 0>
-__device__ __forceinline__ void bld2(uint8_t *, Buf b, uint32_t v, uint32_t s, int &a0, int &a1)
+template <typename T, int N>
+__device__ __forceinline__ void bstoreN_nt(Buf b, uint32_t v, uint32_t s, const T (&in)[N])
 {
-    const unsigned h = __builtin_amdgcn_raw_buffer_load_b16(b.r, v, s, AUX);
-    a0 = (int)(h & 0xffu);
-    a1 = (int)(h >> 8);
-}
-template <typename E, typename K, int AUX = 0>
-__device__ __forceinline__ void bload2(Buf b, uint32_t v, uint32_t s, K &a0, K &a1)
-{
-    bld2<AUX>((E *)nullptr, b, v, s, a0, a1);
-}
-__device__ __forceinline__ void bstore2_nt(Buf b, uint32_t v, uint32_t s, double a0, double a1)
-{
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, make_double2(a0, a1)), b.r, v, s,
-                                           kBufNT);
-}
-__device__ __forceinline__ void bstore2_nt(Buf b, uint32_t v, uint32_t s, float a0, float a1)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, make_float2(a0, a1)), b.r, v, s,
-                                          kBufNT);
+    using V = typename VecN<T, N>::type;
+    V x;
+#pragma unroll
+    for (int n = 0; n < N; ++n) x[n] = in[n];
+    if constexpr (sizeof(V) == 16)
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), b.r, v, s, kBufNT);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), b.r, v, s, kBufNT);
 }
 
 // Byte offsets of a lane's cell and its x/y neighbours within a plane
@@ -765,29 +767,30 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
 }
 
 // ------------------------------------------------------------------------
-// pair tiles: passes A and B on two adjacent columns per thread
+// grouped tiles: passes A and B on N adjacent columns per thread
 // ------------------------------------------------------------------------
-// With nx even a thread owns cells c (even i) and c + 1 of a row: every
-// neighbour pair along y and z, the pair itself and its keys come in one
-// load each (16 B of doubles, 8 B of floats, 2 B of classes); inside the
-// pair the cells are each other's x neighbours, so only the column before
-// the pair (pass A) and the one after it (pass B) are single loads.  That
-// halves the vector memory instructions per cell.
+// With the row length divisible by N (2, or 4 for floats), a thread owns
+// cells c .. c + N - 1 of a row: the group, its y and z neighbour groups
+// and their class bytes come in one load each (16 B of doubles or 8/16 B of
+// floats, 2/4 B of classes); inside the group the cells are each other's x
+// neighbours, so only the column before the group (pass A) and the one after
+// it (pass B) are element loads.  That divides the vector memory
+// instructions per cell by about N.
 
-template <typename T, typename K>
-struct PairA {
-    T z0, z1, q0, q1, zy0, zy1, qy0, qy1, zx, qx;
-    K k0, k1, ky0, ky1, kx;
+template <typename T, typename K, int N>
+struct GroupA {
+    T z[N], q[N], zy[N], qy[N], zx, qx;
+    K k[N], ky[N], kx;
 };
 
-template <typename T, class C>
-__device__ void pair_passA(const Slot &S, const SlotState &st, int64_t lt,
-                           const C &cf, double (&acc)[3])
+template <typename T, class C, int N>
+__device__ void group_passA(const Slot &S, const SlotState &st, int64_t lt,
+                            const C &cf, double (&acc)[3])
 {
     using K = typename C::Key;
     using KE = typename KeyElem<C>::type;
-    const TileCtx t = pair_ctx(S, lt);      // the pair's first cell (even i)
-    if (!t.active) return;                  // the plane has an even cell count
+    const TileCtx t = group_ctx(S, lt);     // the group's first cell
+    if (!t.active) return;                  // planes hold whole groups
     const Window W = tile_window(t, S);
     const int pbuf = __builtin_amdgcn_readfirstlane(st.pbuf);
     const Buf bps = W.buf((const T *)(pbuf ? S.pb : S.pa));
@@ -798,13 +801,13 @@ __device__ void pair_passA(const Slot &S, const SlotState &st, int64_t lt,
     const int nx = S.nx, ny = S.ny, nz = S.nz, bm = S.bcmask;
     const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
     const int i0 = t.i, j = t.j;
-    // the column before the pair (across a periodic x wall: the row's last)
+    // the column before the group (across a periodic x wall: the row's last)
     const bool hxm = i0 > 0 || px;
     const int oxm = i0 > 0 ? -1 : (px ? nx - 1 : 0);
     const bool hym = j > 0 || py;
     const int oym = j > 0 ? -nx : (py ? (ny - 1) * nx : 0);
-    // Dirichlet high walls: x+ of the second cell, y+ of both
-    const bool hwx = !(i0 + 1 < nx - 1 || px) && (bm & 2);
+    // Dirichlet high walls: x+ of the last cell, y+ of all
+    const bool hwx = !(i0 + N - 1 < nx - 1 || px) && (bm & 2);
     const bool hwy = !(j < ny - 1 || py) && (bm & 8);
     const K wxm = (bm & 1) ? cf.dirichlet() : cf.neumann();
     const K wym = (bm & 4) ? cf.dirichlet() : cf.neumann();
@@ -816,56 +819,59 @@ __device__ void pair_passA(const Slot &S, const SlotState &st, int64_t lt,
     auto load = [&](int kk) {
         kk = kk < t.k1 ? kk : t.k1 - 1;    // past the tile's end: re-read its last plane
         const uint32_t sv = W.so(kk, sizeof(T)), sk = W.so(kk, sizeof(KE));
-        PairA<T, K> L;
-        bload2<T>(bz, vc, sv, L.z0, L.z1);
-        bload2<T>(bps, vc, sv, L.q0, L.q1);
-        bload2<KE>(bk, kc, sk, L.k0, L.k1);
-        bload2<T>(bz, vy, sv, L.zy0, L.zy1);
-        bload2<T>(bps, vy, sv, L.qy0, L.qy1);
-        bload2<KE>(bk, ky, sk, L.ky0, L.ky1);
+        GroupA<T, K, N> L;
+        bloadN<T>(bz, vc, sv, L.z);
+        bloadN<T>(bps, vc, sv, L.q);
+        bloadN<KE>(bk, kc, sk, L.k);
+        bloadN<T>(bz, vy, sv, L.zy);
+        bloadN<T>(bps, vy, sv, L.qy);
+        bloadN<KE>(bk, ky, sk, L.ky);
         L.zx = bload<T>(bz, vx, sv);
         L.qx = bload<T>(bps, vx, sv);
         L.kx = bload<KE>(bk, kx, sk);
         return L;
     };
-    T pzm0 = T(0), pzm1 = T(0);
-    K kzm0 = wzm, kzm1 = wzm;
+    T pzm[N];
+    K kzm[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) { pzm[n] = T(0); kzm[n] = wzm; }
     if (t.k0 > 0) {
         const uint32_t sv = W.so(t.k0 - 1, sizeof(T)), sk = W.so(t.k0 - 1, sizeof(KE));
-        T z0, z1, q0, q1;
-        bload2<T>(bz, vc, sv, z0, z1);
-        bload2<T>(bps, vc, sv, q0, q1);
-        bload2<KE>(bk, kc, sk, kzm0, kzm1);
-        pzm0 = z0 + beta * q0;
-        pzm1 = z1 + beta * q1;
+        T z[N], q[N];
+        bloadN<T>(bz, vc, sv, z);
+        bloadN<T>(bps, vc, sv, q);
+        bloadN<KE>(bk, kc, sk, kzm);
+#pragma unroll
+        for (int n = 0; n < N; ++n) pzm[n] = z[n] + beta * q[n];
     }
     double a = 0.0;
-    auto step = [&](const PairA<T, K> &L, int kk) {
-        const T p0 = L.z0 + beta * L.q0, p1 = L.z1 + beta * L.q1;
-        const T pxm = hxm ? L.zx + beta * L.qx : T(0);
-        const K kxm = hxm ? L.kx : wxm;
-        const T pym0 = hym ? L.zy0 + beta * L.qy0 : T(0), pym1 = hym ? L.zy1 + beta * L.qy1 : T(0);
-        const K kym0 = hym ? L.ky0 : wym, kym1 = hym ? L.ky1 : wym;
+    auto step = [&](const GroupA<T, K, N> &L, int kk) {
         const int64_t c0 = (int64_t)kk * t.P + t.q;
-        const Areas6<T> ar0 = cf.areas(i0, j, kk, c0), ar1 = cf.areas(i0 + 1, j, kk, c0 + 1);
         const bool top = kk == nz - 1 && (bm & 32);
-        const T dx0 = p0 - pxm, dy0 = p0 - pym0, dz0 = p0 - pzm0;
-        T s0 = (cf.beta(L.k0, kxm) * ar0.xm * dx0 * dx0 + cf.beta(L.k0, kym0) * ar0.ym * dy0 * dy0) +
-               cf.beta(L.k0, kzm0) * ar0.zm * dz0 * dz0;
-        const T w0 = (hwy ? ar0.yp : T(0)) + (top ? ar0.zp : T(0));
-        s0 += w0 * cf.beta(L.k0, cf.dirichlet()) * (p0 * p0);
-        const T dx1 = p1 - p0, dy1 = p1 - pym1, dz1 = p1 - pzm1;
-        T s1 = (cf.beta(L.k1, L.k0) * ar1.xm * dx1 * dx1 + cf.beta(L.k1, kym1) * ar1.ym * dy1 * dy1) +
-               cf.beta(L.k1, kzm1) * ar1.zm * dz1 * dz1;
-        const T w1 = (hwx ? ar1.xp : T(0)) + (hwy ? ar1.yp : T(0)) + (top ? ar1.zp : T(0));
-        s1 += w1 * cf.beta(L.k1, cf.dirichlet()) * (p1 * p1);
-        a += (double)s0;
-        a += (double)s1;
-        bstore2_nt(bpd, vc, W.so(kk, sizeof(T)), p0, p1);
-        pzm0 = p0; pzm1 = p1;
-        kzm0 = L.k0; kzm1 = L.k1;
+        T pl = hxm ? L.zx + beta * L.qx : T(0);   // x- value of the next cell
+        K kl = hxm ? L.kx : wxm;
+        T p[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            p[n] = L.z[n] + beta * L.q[n];
+            const T pym = hym ? L.zy[n] + beta * L.qy[n] : T(0);
+            const K kym = hym ? L.ky[n] : wym;
+            const Areas6<T> ar = cf.areas(i0 + n, j, kk, c0 + n);
+            const T dx = p[n] - pl, dy = p[n] - pym, dz = p[n] - pzm[n];
+            T sn = (cf.beta(L.k[n], kl) * ar.xm * dx * dx + cf.beta(L.k[n], kym) * ar.ym * dy * dy) +
+                   cf.beta(L.k[n], kzm[n]) * ar.zm * dz * dz;
+            const T w = ((n == N - 1 && hwx) ? ar.xp : T(0)) + (hwy ? ar.yp : T(0)) +
+                        (top ? ar.zp : T(0));
+            sn += w * cf.beta(L.k[n], cf.dirichlet()) * (p[n] * p[n]);
+            a += (double)sn;
+            pzm[n] = p[n];
+            kzm[n] = L.k[n];
+            pl = p[n];
+            kl = L.k[n];
+        }
+        bstoreN_nt<T, N>(bpd, vc, W.so(kk, sizeof(T)), p);
     };
-    PairA<T, K> A = load(t.k0), B;
+    GroupA<T, K, N> A = load(t.k0), B;
     int k = t.k0;
     for (; k + 1 < t.k1; k += 2) {
         B = load(k + 1);
@@ -877,33 +883,33 @@ __device__ void pair_passA(const Slot &S, const SlotState &st, int64_t lt,
     acc[0] += a;
 }
 
-template <typename T, typename X, class C, int XM>
-__device__ void pair_passB(const Slot &S, const SlotState &st, int64_t lt,
-                           const C &cf, double (&acc)[3])
+template <typename T, typename X, class C, int XM, int N>
+__device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
+                            const C &cf, double (&acc)[3])
 {
     using K = typename C::Key;
-    using V = typename Vec2<T>::type;
-    const TileCtx t = pair_ctx(S, lt);
+    using V = typename VecN<T, N>::type;
+    const TileCtx t = group_ctx(S, lt);
     if (!t.active) return;
     const GLB T *__restrict__ p = gp((const T *)(st.pbuf ? S.pb : S.pa));
     const GLB T *__restrict__ pprev = gp((const T *)(st.pbuf ? S.pa : S.pb));
     GLB T *__restrict__ z = gp((T *)S.z);
     // x is the caller's array (FP64), read and written element by element;
-    // the FP32 correction d is ours (aligned), in pairs
+    // the FP32 correction d is ours (aligned), in groups
     GLB X *__restrict__ x = gp(std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32);
-    constexpr bool kXPair = std::is_same<X, float>::value;
-    using XV = typename Vec2<X>::type;
-    const GLB V *__restrict__ p2 = (const GLB V *)p;
-    const GLB V *__restrict__ pp2 = (const GLB V *)pprev;
-    GLB V *__restrict__ z2 = (GLB V *)z;
+    constexpr bool kXGroup = std::is_same<X, float>::value;
+    using XV = typename VecN<X, N>::type;
+    const GLB V *__restrict__ pv = (const GLB V *)p;
+    const GLB V *__restrict__ ppv = (const GLB V *)pprev;
+    GLB V *__restrict__ zv = (GLB V *)z;
     const T alpha = (T)st.alpha;
     const T alpha_prev = (T)st.alpha_prev;
     const int nx = S.nx, ny = S.ny, bm = S.bcmask;
     const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
     const int i0 = t.i, j = t.j;
-    const bool hxm = i0 > 0 || px, hxp = i0 + 1 < nx - 1 || px;
+    const bool hxm = i0 > 0 || px, hxp = i0 + N - 1 < nx - 1 || px;
     const int oxm = i0 > 0 ? -1 : (px ? nx - 1 : 0);
-    const int oxp = i0 + 1 < nx - 1 ? 1 : (px ? -(nx - 1) : 0);   // from the second cell
+    const int oxp = i0 + N - 1 < nx - 1 ? 1 : (px ? -(nx - 1) : 0);   // from the last cell
     const bool hym = j > 0 || py, hyp = j < ny - 1 || py;
     const int oym = j > 0 ? -nx : (py ? (ny - 1) * nx : 0);
     const int oyp = j < ny - 1 ? nx : (py ? -(ny - 1) * nx : 0);
@@ -914,117 +920,129 @@ __device__ void pair_passB(const Slot &S, const SlotState &st, int64_t lt,
     const K wzm = (bm & 16) ? cf.dirichlet() : cf.neumann();
     const K wzp = (bm & 32) ? cf.dirichlet() : cf.neumann();
     const int64_t P = t.P;
-    int64_t c = (int64_t)t.k0 * P + t.q;   // even
-    V vc = p2[c >> 1];
-    K kc0, kc1;
-    cf.load2(c, kc0, kc1);
-    T vzm0 = T(0), vzm1 = T(0);
-    K kzm0 = wzm, kzm1 = wzm;
-    if (t.k0 > 0) {
-        const V v = p2[(c - P) >> 1];
-        vzm0 = v.x; vzm1 = v.y;
-        cf.load2(c - P, kzm0, kzm1);
+    int64_t c = (int64_t)t.k0 * P + t.q;   // a multiple of N
+    T vc[N], vzm[N], bzm[N];
+    K kc[N];
+    {
+        const V v = pv[c / N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) { vc[n] = v[n]; vzm[n] = T(0); }
     }
-    T bzm0 = cf.beta(kc0, kzm0) * cf.areas(i0, j, t.k0, c).zm;
-    T bzm1 = cf.beta(kc1, kzm1) * cf.areas(i0 + 1, j, t.k0, c + 1).zm;
+    cf.template loadN<N>(c, kc);
+    K kzm[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) kzm[n] = wzm;
+    if (t.k0 > 0) {
+        const V v = pv[(c - P) / N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) vzm[n] = v[n];
+        cf.template loadN<N>(c - P, kzm);
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        bzm[n] = cf.beta(kc[n], kzm[n]) * cf.areas(i0 + n, j, t.k0, c + n).zm;
     double a0 = 0.0, a1 = 0.0;
     for (int k = t.k0; k < t.k1; ++k, c += P) {
         const bool top = k == S.nz - 1;
         const int64_t cz = top ? c : c + P;
-        const V vzp_l = p2[cz >> 1];
-        K kzp0_l, kzp1_l;
-        cf.load2(cz, kzp0_l, kzp1_l);
-        const V vy_m = p2[(c + oym) >> 1], vy_p = p2[(c + oyp) >> 1];
-        K kym0, kym1, kyp0, kyp1;
-        cf.load2(c + oym, kym0, kym1);
-        cf.load2(c + oyp, kyp0, kyp1);
-        const T lvxm = p[c + oxm], lvxp = p[c + 1 + oxp];
-        const K lkxm = cf.load(c + oxm), lkxp = cf.load(c + 1 + oxp);
-        const V zc = __builtin_nontemporal_load(&z2[c >> 1]);
-        X x0 = X(0), x1 = X(0);
+        const V vzp_v = pv[cz / N];
+        K kzp[N], kym[N], kyp[N];
+        cf.template loadN<N>(cz, kzp);
+        const V vym_v = pv[(c + oym) / N], vyp_v = pv[(c + oyp) / N];
+        cf.template loadN<N>(c + oym, kym);
+        cf.template loadN<N>(c + oyp, kyp);
+        const T lvxm = p[c + oxm], lvxp = p[c + N - 1 + oxp];
+        const K lkxm = cf.load(c + oxm), lkxp = cf.load(c + N - 1 + oxp);
+        const V zc = __builtin_nontemporal_load(&zv[c / N]);
+        X xo[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) xo[n] = X(0);
         if (XM) {
-            if constexpr (kXPair) {
-                const XV xv = __builtin_nontemporal_load(&((GLB XV *)x)[c >> 1]);
-                x0 = xv.x; x1 = xv.y;
+            if constexpr (kXGroup) {
+                const XV xv = __builtin_nontemporal_load(&((GLB XV *)x)[c / N]);
+#pragma unroll
+                for (int n = 0; n < N; ++n) xo[n] = xv[n];
             } else {
-                x0 = __builtin_nontemporal_load(&x[c]);
-                x1 = __builtin_nontemporal_load(&x[c + 1]);
+#pragma unroll
+                for (int n = 0; n < N; ++n) xo[n] = __builtin_nontemporal_load(&x[c + n]);
             }
         }
-        V ppv;
-        ppv.x = T(0); ppv.y = T(0);
-        if (XM == 2) ppv = __builtin_nontemporal_load(&pp2[c >> 1]);
-        const T vzp0 = top ? T(0) : vzp_l.x, vzp1 = top ? T(0) : vzp_l.y;
-        const K kzp0 = top ? wzp : kzp0_l, kzp1 = top ? wzp : kzp1_l;
-        const Areas6<T> ar0 = cf.areas(i0, j, k, c), ar1 = cf.areas(i0 + 1, j, k, c + 1);
-        // first cell: x- outside the pair, x+ the second cell
-        const K kxm0 = hxm ? lkxm : wxm;
-        const T vxm0 = hxm ? lvxm : T(0);
-        const T bxm0 = cf.beta(kc0, kxm0) * ar0.xm, bxp0 = cf.beta(kc0, kc1) * ar0.xp;
-        const T bym0 = cf.beta(kc0, hym ? kym0 : wym) * ar0.ym;
-        const T byp0 = cf.beta(kc0, hyp ? kyp0 : wyp) * ar0.yp;
-        const T bzp0 = cf.beta(kc0, kzp0) * ar0.zp;
-        const T vym0 = hym ? vy_m.x : T(0), vyp0 = hyp ? vy_p.x : T(0);
-        const T dg0 = ((bxm0 + bxp0) + (bym0 + byp0)) + (bzm0 + bzp0);
-        const T q0 = ((bxm0 * (vc.x - vxm0) + bxp0 * (vc.x - vc.y)) +
-                      (bym0 * (vc.x - vym0) + byp0 * (vc.x - vyp0))) +
-                     (bzm0 * (vc.x - vzm0) + bzp0 * (vc.x - vzp0));
-        // second cell: x- the first cell, x+ outside the pair
-        const K kxp1 = hxp ? lkxp : wxp;
-        const T vxp1 = hxp ? lvxp : T(0);
-        const T bxm1 = cf.beta(kc1, kc0) * ar1.xm, bxp1 = cf.beta(kc1, kxp1) * ar1.xp;
-        const T bym1 = cf.beta(kc1, hym ? kym1 : wym) * ar1.ym;
-        const T byp1 = cf.beta(kc1, hyp ? kyp1 : wyp) * ar1.yp;
-        const T bzp1 = cf.beta(kc1, kzp1) * ar1.zp;
-        const T vym1 = hym ? vy_m.y : T(0), vyp1 = hyp ? vy_p.y : T(0);
-        const T dg1 = ((bxm1 + bxp1) + (bym1 + byp1)) + (bzm1 + bzp1);
-        const T q1 = ((bxm1 * (vc.y - vc.x) + bxp1 * (vc.y - vxp1)) +
-                      (bym1 * (vc.y - vym1) + byp1 * (vc.y - vyp1))) +
-                     (bzm1 * (vc.y - vzm1) + bzp1 * (vc.y - vzp1));
+        T pp[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) pp[n] = T(0);
+        if (XM == 2) {
+            const V v = __builtin_nontemporal_load(&ppv[c / N]);
+#pragma unroll
+            for (int n = 0; n < N; ++n) pp[n] = v[n];
+        }
+        T zn[N];
+        X xn[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const T vzp = top ? T(0) : vzp_v[n];
+            const K kz = top ? wzp : kzp[n];
+            const Areas6<T> ar = cf.areas(i0 + n, j, k, c + n);
+            // x neighbours: inside the group, or the columns around it
+            const T vxm = n > 0 ? vc[n - 1] : (hxm ? lvxm : T(0));
+            const K kxm = n > 0 ? kc[n - 1] : (hxm ? lkxm : wxm);
+            const T vxp = n < N - 1 ? vc[n + 1] : (hxp ? lvxp : T(0));
+            const K kxp = n < N - 1 ? kc[n + 1] : (hxp ? lkxp : wxp);
+            const T vym = hym ? vym_v[n] : T(0), vyp = hyp ? vyp_v[n] : T(0);
+            const T bxm = cf.beta(kc[n], kxm) * ar.xm, bxp = cf.beta(kc[n], kxp) * ar.xp;
+            const T bym = cf.beta(kc[n], hym ? kym[n] : wym) * ar.ym;
+            const T byp = cf.beta(kc[n], hyp ? kyp[n] : wyp) * ar.yp;
+            const T bzp = cf.beta(kc[n], kz) * ar.zp;
+            const T dg = ((bxm + bxp) + (bym + byp)) + (bzm[n] + bzp);
+            const T q = ((bxm * (vc[n] - vxm) + bxp * (vc[n] - vxp)) +
+                         (bym * (vc[n] - vym) + byp * (vc[n] - vyp))) +
+                        (bzm[n] * (vc[n] - vzm[n]) + bzp * (vc[n] - vzp));
+            if (XM == 1) xn[n] = xo[n] + (X)(alpha * vc[n]);
+            if (XM == 2) xn[n] = fma((X)alpha, (X)vc[n], fma((X)alpha_prev, (X)pp[n], xo[n]));
+            const T inv = dg > T(0) ? recip(dg) : T(0);   // hull rows keep z = 0
+            zn[n] = zc[n] - alpha * q * inv;
+            const double r = (double)dg * (double)zn[n];
+            a0 += r * (double)zn[n];
+            a1 += r * r;
+            bzm[n] = bzp;
+        }
         if (XM) {
-            X xn0, xn1;
-            if (XM == 1) {
-                xn0 = x0 + (X)(alpha * vc.x);
-                xn1 = x1 + (X)(alpha * vc.y);
-            } else {
-                xn0 = fma((X)alpha, (X)vc.x, fma((X)alpha_prev, (X)ppv.x, x0));
-                xn1 = fma((X)alpha, (X)vc.y, fma((X)alpha_prev, (X)ppv.y, x1));
-            }
-            if constexpr (kXPair) {
+            if constexpr (kXGroup) {
                 XV xv;
-                xv.x = xn0; xv.y = xn1;
-                __builtin_nontemporal_store(xv, &((GLB XV *)x)[c >> 1]);
+#pragma unroll
+                for (int n = 0; n < N; ++n) xv[n] = xn[n];
+                __builtin_nontemporal_store(xv, &((GLB XV *)x)[c / N]);
             } else {
-                __builtin_nontemporal_store(xn0, &x[c]);
-                __builtin_nontemporal_store(xn1, &x[c + 1]);
+#pragma unroll
+                for (int n = 0; n < N; ++n) __builtin_nontemporal_store(xn[n], &x[c + n]);
             }
         }
-        const T inv0 = dg0 > T(0) ? recip(dg0) : T(0);   // hull rows keep z = 0
-        const T inv1 = dg1 > T(0) ? recip(dg1) : T(0);
-        V zn;
-        zn.x = zc.x - alpha * q0 * inv0;
-        zn.y = zc.y - alpha * q1 * inv1;
-        __builtin_nontemporal_store(zn, &z2[c >> 1]);
-        const double r0 = (double)dg0 * (double)zn.x, r1 = (double)dg1 * (double)zn.y;
-        a0 += r0 * (double)zn.x;
-        a0 += r1 * (double)zn.y;
-        a1 += r0 * r0;
-        a1 += r1 * r1;
-        vzm0 = vc.x; vzm1 = vc.y;
-        bzm0 = bzp0; bzm1 = bzp1;
-        vc.x = vzp0; vc.y = vzp1;
-        kc0 = kzp0; kc1 = kzp1;
+        {
+            V zv_n;
+#pragma unroll
+            for (int n = 0; n < N; ++n) zv_n[n] = zn[n];
+            __builtin_nontemporal_store(zv_n, &zv[c / N]);
+        }
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            vzm[n] = vc[n];
+            vc[n] = top ? T(0) : vzp_v[n];
+            kc[n] = top ? wzp : kzp[n];
+        }
     }
     acc[0] += a0;
     acc[1] += a1;
 }
 
-// Pass A / pass B for the tile form of the slot.
+// Pass A / pass B for the tile form of the slot (four cells per thread for
+// FP32 only: FP64 kernels do not carry its registers).
 template <typename T, class C>
 __device__ __forceinline__ void passA(const Slot &S, const SlotState &st, int64_t lt,
                                       const C &cf, double (&acc)[3])
 {
-    if (S.pairs) pair_passA<T>(S, st, lt, cf, acc);
+    if constexpr (std::is_same<T, float>::value) {
+        if (S.cpt == 4) { group_passA<T, C, 4>(S, st, lt, cf, acc); return; }
+    }
+    if (S.cpt == 2) group_passA<T, C, 2>(S, st, lt, cf, acc);
     else body_passA<T>(S, st, lt, cf, acc);
 }
 
@@ -1032,7 +1050,10 @@ template <typename T, typename X, class C, int XM = 1>
 __device__ __forceinline__ void passB(const Slot &S, const SlotState &st, int64_t lt,
                                       const C &cf, double (&acc)[3])
 {
-    if (S.pairs) pair_passB<T, X, C, XM>(S, st, lt, cf, acc);
+    if constexpr (std::is_same<T, float>::value) {
+        if (S.cpt == 4) { group_passB<T, X, C, XM, 4>(S, st, lt, cf, acc); return; }
+    }
+    if (S.cpt == 2) group_passB<T, X, C, XM, 2>(S, st, lt, cf, acc);
     else body_passB<T, X, C, XM>(S, st, lt, cf, acc);
 }
 

@@ -37,7 +37,7 @@ enum Phase : int32_t {
     // K2 actions (second launch of an iteration)
     K2_NONE = 11,      // nothing; then the K1 action in `after`
     K2_CG_B = 12,      // q = A p, x += alpha p, z -= alpha D^-1 q ; r.z, r.r
-    K2_IR_B = 13,      // FP32 q = A p, d += alpha p (in pairs), z -= alpha D^-1 q ; r.z, r.r (FP64)
+    K2_IR_B = 13,      // FP32 q = A p, d += alpha p (two at a time), z -= alpha D^-1 q ; r.z, r.r (FP64)
     K2_IR_UPDATE = 14, // x += s d, d = 0
     K2_ZERO_X = 15,    // x = 0 (zero source with a warm start)
     K2_SUB_X = 16,     // singular problem: x -= its fluid mean
@@ -84,11 +84,11 @@ struct alignas(128) SlotState {
 struct Slot {
     int32_t nx, ny, nz;
     int32_t bcmask;        // bit f set: wall f is Dirichlet (x-,x+,y-,y+,z-,z+)
-    int32_t plane_tiles;   // ceil(nx*ny / (kBlock or 2 kBlock with pairs))
+    int32_t plane_tiles;   // ceil(nx*ny / (cpt kBlock))
     int32_t ztiles;        // ceil(nz / tz)
     int32_t tz;            // planes per tile
     int32_t permask;       // bit 0: periodic x walls, bit 1: periodic y walls
-    int32_t pairs;         // 1: a thread owns two adjacent columns (nx even)
+    int32_t cpt;           // cells per thread: 1, or 2/4 adjacent columns (nx divisible)
     int32_t pad_;
     int64_t tile_begin;    // first global tile of this slot
     int64_t ntiles;        // plane_tiles * ztiles
