@@ -555,10 +555,16 @@ def _fresh(r, arrival):
 
 
 def kernel_sha():
+    """Hash of the device source with comments and blank lines removed, so
+    that a counter summary stays matched across comment-only edits."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hip", "pcg_types.h"):
-        h.update(open(os.path.join(ROOT, "paper_1410_1942_amd", "csrc", f), "rb").read())
+        src = open(os.path.join(ROOT, "paper_1410_1942_amd", "csrc", f)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("\n".join(l.strip() for l in src.splitlines() if l.strip()).encode())
     return h.hexdigest()[:16]
 
 

@@ -20,12 +20,15 @@
 // per-tile partial sums written to memory and added in tile order by the
 // last workgroup to arrive, which also advances the solve's state machine.
 //
-// Work decomposition: a tile is kBlock consecutive cells of an x-y plane
-// (x fastest) times tz planes; each thread owns one (i,j) column of the tile
-// and marches up in z keeping the k-1, k, k+1 values in registers.  A launch
-// grid-strides over the tiles of all active solves; workgroup ids are
-// remapped so each of the 8 XCDs walks a contiguous range of tiles, keeping
-// the y-neighbour rows of concurrently running tiles in that XCD's L2.
+// Work decomposition: a tile is cpt * kBlock consecutive cells of an x-y
+// plane (x fastest) times tz planes, cpt = 1, or 2 / 4 when the row length
+// allows; in passes A and B each thread owns cpt adjacent (i,j) columns of a
+// row and marches up in z keeping the k-1, k, k+1 values in registers, so
+// its loads are cpt elements wide.  With one resident solve a launch
+// grid-strides over the tiles (workgroup ids remapped so each of the 8 XCDs
+// walks a contiguous range, keeping the y-neighbour rows of concurrently
+// running tiles in that XCD's L2); with several, each workgroup takes a
+// contiguous range of tiles.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <type_traits>
