@@ -296,6 +296,16 @@ def main():
         log(f"  {cpu_val:.4f} Gcell-iter/s on {oracle.threads()} threads")
 
     if not args.no_side:
+        # the 32^3 parity case: launch-bound on the GPU; the oracle's full
+        # solve of it timed on the host beside it
+        c1 = F.config1(32, keep_velocity=False)
+        out["flat32"] = bench_single(c1, args.tol, dev, "32^3 flat two-phase tank, FP64")
+        if not args.no_cpu:
+            import oracle
+            t = time.perf_counter()
+            ref = oracle.pcg(c1.rho, c1.mask, c1.bc, c1.h, c1.rhs, tol=args.tol)
+            out["flat32"]["oracle_solve_ms"] = round((time.perf_counter() - t) * 1e3, 2)
+            out["flat32"]["oracle_iters"] = int(ref.iters)
         out["wedge256"] = bench_single(F.config_wedge(256, keep_velocity=False), args.tol, dev,
                                        "256^3 two-phase tank + wedge hull, FP64")
         out["strut"] = bench_single(F.config_strut(keep_velocity=False), args.tol, dev,
