@@ -71,6 +71,8 @@ CASES = [
     ((1, 16, 12), PX_TOP, False),           # one cell along the periodic axis
     ((2, 9, 7), STRUT, False),              # two cells along it
     ((21, 11, 9), (P, P, P, P, 0, 0), True),    # doubly periodic, singular
+    ((4, 10, 6), STRUT, False),             # one four-cell group per row (FP32), both x edges wrap
+    ((12, 1, 9), PX_TOP, False),            # a single row: y walls on both sides of every group
 ]
 
 
