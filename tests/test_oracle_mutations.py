@@ -58,6 +58,9 @@ PIN_RUNS = {
     "dense_fractions": lambda o: pins.test_dense_with_fractions(o, _F()),
     "volume_scaling": lambda o: pins.test_uniform_volume_scales_the_answer(o, _F()),
     "divergence_fractions": lambda o: pins.test_projection_divergence_with_fractions(o, _F()),
+    "textbook_iters": lambda o: [pins.test_pcg_iterations_match_textbook(o, _F(), *case)
+                                 for case in (((8, 8, 8), (1, 0, 0, 1, 0, 1), True, 11),
+                                              ((16, 4, 2), (1, 1, 0, 0, 1, 1), True, 7))],
 }
 
 MUTANTS = [
@@ -95,6 +98,11 @@ MUTANTS = [
     # volume fraction left out of the right-hand side
     ("volume_off_source", "b[c] = solid[c] ? 0.0 : -h2 * volume(&P, c) * rhs[c];",
      "b[c] = solid[c] ? 0.0 : -h2 * rhs[c];"),
+    # periodic y wrap lands one row short
+    ("periodic_wrap_y", "else jj = (jj + P->ny) % P->ny;", "else jj = (jj + P->ny - 1) % P->ny;"),
+    # Jacobi diagonal without the doubled Dirichlet ghost term (same answers,
+    # other iteration counts)
+    ("jacobi_diag_ghost", "s += nb[f] >= 0 ? beta[f] : 2.0 * beta[f];", "s += beta[f];"),
     # area divergence not divided by the volume fraction
     ("divergence_no_volume", "out[w0] = ax ? (du + dv + dw) / (vc * h) : (du + dv + dw) / h;",
      "out[w0] = (du + dv + dw) / h;"),

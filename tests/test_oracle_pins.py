@@ -203,6 +203,55 @@ def test_dense_cholesky(orc, F, shape, bc, wedge):
     assert np.abs(r.p.ravel() - p).max() <= 1e-10 * scale
 
 
+def _textbook_jacobi_pcg_iters(A, b, tol, maxit=10000):
+    """Hestenes-Stiefel conjugate gradients preconditioned by the diagonal of
+    A (Saad, Iterative Methods for Sparse Linear Systems, Alg. 9.1), on a
+    dense matrix: the iteration at which ||r|| <= tol ||b|| first holds."""
+    d = np.diag(A).copy()
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = r / d
+    p = z.copy()
+    rz = r @ z
+    nb = np.linalg.norm(b)
+    for k in range(1, maxit + 1):
+        q = A @ p
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        if np.linalg.norm(r) <= tol * nb:
+            return k
+        z = r / d
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return maxit
+
+
+@pytest.mark.parametrize("shape,bc,wedge,seed", [
+    ((6, 5, 8), TANK, True, 11),
+    ((8, 8, 8), (D, N, N, D, N, D), True, 11),
+    ((12, 6, 3), ALL_D, True, 11),
+    ((16, 4, 2), (D, D, N, N, D, D), True, 7),
+])
+def test_pcg_iterations_match_textbook(orc, F, shape, bc, wedge, seed):
+    """The reference's iteration count equals that of textbook Jacobi-PCG on
+    the independently assembled matrix.  This pins the preconditioner
+    (Jacobi, reading R9), which the solution pins cannot see since any
+    diagonal leads to the same answer.  In these cases the relative residual
+    is at least 1.1 tol one iteration before the stop and at most 0.97 tol
+    at it, so rounding differences between the two cannot move the count."""
+    nx, ny, nz = shape
+    c = F.make_two_phase(nx, ny, nz, surface_seed=seed, velocity_seed=seed + 1,
+                         wedge=F.Wedge() if wedge else None, bc=bc)
+    A = _dense_minus_h2L(c.rho, c.mask, c.bc)
+    b = (-c.h**2 * c.rhs * (c.mask == 0)).ravel()
+    k_ref = _textbook_jacobi_pcg_iters(A, b, 1e-8)
+    r = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-8)
+    assert r.status == orc.OK
+    assert r.iters == k_ref, (r.iters, k_ref)
+
+
 # --------------------------------------------------------------------------
 # 1-D reduction: flat interface, Neumann sides, source depending on z only
 # --------------------------------------------------------------------------
