@@ -58,6 +58,8 @@ PIN_RUNS = {
     "dense_fractions": lambda o: pins.test_dense_with_fractions(o, _F()),
     "volume_scaling": lambda o: pins.test_uniform_volume_scales_the_answer(o, _F()),
     "divergence_fractions": lambda o: pins.test_projection_divergence_with_fractions(o, _F()),
+    "divergence_periodic": lambda o: pins.test_projection_divergence_periodic(
+        o, _F(), (2, 2, 0, 0, 0, 0)),
     "textbook_iters": lambda o: [pins.test_pcg_iterations_match_textbook(o, _F(), *case)
                                  for case in (((8, 8, 8), (1, 0, 0, 1, 0, 1), True, 11),
                                               ((16, 4, 2), (1, 1, 0, 0, 1, 1), True, 7))],
@@ -103,6 +105,9 @@ MUTANTS = [
     # Jacobi diagonal without the doubled Dirichlet ghost term (same answers,
     # other iteration counts)
     ("jacobi_diag_ghost", "s += nb[f] >= 0 ? beta[f] : 2.0 * beta[f];", "s += beta[f];"),
+    # shared periodic x face corrected up the pressure gradient
+    ("periodic_face_sign", "if (nx > 1) *uf -= s * face_beta(&P, a, b) * (p[b] - p[a]);",
+     "if (nx > 1) *uf += s * face_beta(&P, a, b) * (p[b] - p[a]);"),
     # area divergence not divided by the volume fraction
     ("divergence_no_volume", "out[w0] = ax ? (du + dv + dw) / (vc * h) : (du + dv + dw) / h;",
      "out[w0] = (du + dv + dw) / h;"),
