@@ -29,15 +29,15 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell of the two iteration kernels, by precision and
 # coefficient source (a one-byte density class, or the density itself)
 #   pass A: read p_old, z, coefficient key; write p
-#   pass B: read p, z, coefficient key (+ x or d, p_prev); write z (+ x or d)
+#   pass B: read p, z, coefficient key (+ x or d, p_prev, p_prev2); write z (+ x or d)
 BYTES_K1 = {("fp64", "classes"): 25, ("fp64", "density"): 32,
             ("fp32", "classes"): 13, ("fp32", "density"): 16}
 # pass B reads and writes x (FP64) or the inner correction d (FP32) every
-# second launch only, together with the previous direction (FP64 25 and 49
-# B/cell with classes, 32 and 56 with densities; FP32 13 and 25, 16 and 28):
-# the per-launch average
-BYTES_K2 = {("fp64", "classes"): 37, ("fp64", "density"): 44,
-            ("fp32", "classes"): 19, ("fp32", "density"): 22}
+# third launch only, together with the two previous directions (FP64 25, 25,
+# 57 B/cell with classes, 32, 32, 64 with densities; FP32 13, 13, 29 and 16,
+# 16, 32): the per-launch average
+BYTES_K2 = {("fp64", "classes"): 107 / 3, ("fp64", "density"): 128 / 3,
+            ("fp32", "classes"): 55 / 3, ("fp32", "density"): 64 / 3}
 
 
 def log(msg):
@@ -225,7 +225,7 @@ def main():
             "unit": "GB/s", "frac": round(a2 / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "kernel": f"k_iter<FP64,2,{mode}>: operator apply + z update + r.z, r.r, "
-                      f"x updated every second launch ({b2} B/cell per launch on average)",
+                      f"x updated every third launch ({b2:.2f} B/cell per launch on average)",
             "avg_ms": round(k2_ms, 4), "launches": nlaunch,
             "frac_of_copy": round(a2 / copy_gbs, 4),
             "frac_of_triad": round(a2 / triad_gbs, 4),

@@ -229,7 +229,7 @@ size_t slot_bytes(const Geometry &G, int prec, bool frac = false)
     size_t b = frac ? frac_bytes(G) : 0;
     b += align_up(8 * n, kAlign);                    // rho64
     if (prec == PCG_PREC_FP32_IR) b += align_up(4 * n, kAlign);  // rho32
-    b += 3 * align_up(es * n, kAlign);               // z, pa, pb
+    b += 4 * align_up(es * n, kAlign);               // z and three directions
     if (prec == PCG_PREC_FP32_IR) b += align_up(4 * n, kAlign);  // d32
     b += align_up(kMaxPartials * 8 * (size_t)G.ntiles, kAlign);  // partials
     b += align_up(n, kAlign);                                      // classes
@@ -410,7 +410,7 @@ struct SlotHost {
     size_t off = 0, bytes = 0;
     double *rho64 = nullptr;
     float *rho32 = nullptr;
-    void *z = nullptr, *pa = nullptr, *pb = nullptr;
+    void *z = nullptr, *dir0 = nullptr, *dir1 = nullptr, *dir2 = nullptr;
     float *d32 = nullptr;
     double *partials = nullptr;
     uint8_t *cls = nullptr;      // arena: class per cell
@@ -645,8 +645,9 @@ struct Engine {
         S.rho64 = (double *)p; p += align_up(8 * n, kAlign);
         if (prec == PCG_PREC_FP32_IR) { S.rho32 = (float *)p; p += align_up(4 * n, kAlign); }
         S.z = p; p += align_up(es * n, kAlign);
-        S.pa = p; p += align_up(es * n, kAlign);
-        S.pb = p; p += align_up(es * n, kAlign);
+        S.dir0 = p; p += align_up(es * n, kAlign);
+        S.dir1 = p; p += align_up(es * n, kAlign);
+        S.dir2 = p; p += align_up(es * n, kAlign);
         if (prec == PCG_PREC_FP32_IR) { S.d32 = (float *)p; p += align_up(4 * n, kAlign); }
         S.partials = (double *)p;
         p += align_up(kMaxPartials * 8 * (size_t)geo.ntiles, kAlign);
@@ -848,8 +849,9 @@ struct Engine {
             d.rho64 = S.rho64;
             d.rho32 = S.rho32;
             d.z = S.z;
-            d.pa = S.pa;
-            d.pb = S.pb;
+            d.dir0 = S.dir0;
+            d.dir1 = S.dir1;
+            d.dir2 = S.dir2;
             d.d32 = S.d32;
             d.partials = S.partials;
             d.st = d_states + id;

@@ -147,6 +147,16 @@ __device__ __forceinline__ GLB T *gp(T *p) { return (GLB T *)p; }
 template <typename T>
 __device__ __forceinline__ const GLB T *gp(const T *p) { return (const GLB T *)p; }
 
+// The three direction buffers rotate: pass A reads buffer b (p_old) and
+// writes b + 1 mod 3, so the two directions before the current one are
+// still there when their x updates are applied.
+__device__ __forceinline__ int dir_next(int b) { return b == 2 ? 0 : b + 1; }
+__device__ __forceinline__ int dir_prev(int b) { return b == 0 ? 2 : b - 1; }
+__device__ __forceinline__ void *dir_buf(const Slot &S, int b)
+{
+    return b == 0 ? S.dir0 : (b == 1 ? S.dir1 : S.dir2);
+}
+
 // Reciprocal of a positive finite value: hardware estimate refined by two
 // Newton-Raphson steps (quadratic convergence from the ~2^-23 estimate).
 __device__ __forceinline__ double recip(double d)
@@ -399,7 +409,7 @@ __device__ __forceinline__ double refined(double x, double s, float d)
 // ------------------------------------------------------------------------
 
 // K1_INIT64: b = -h^2 Sigma (0 on hull), r = b (cold) or b - A x0 (warm),
-// z = r / diag, both direction buffers zeroed.  acc = [b.b, r.z, r.r].
+// z = r / diag, the direction buffers zeroed.  acc = [b.b, r.z, r.r].
 template <class C>
 __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
                             const C &cf, double (&acc)[3])
@@ -410,8 +420,9 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
         GLB double *__restrict__ x = gp(S.x);
         GLB double *__restrict__ z = gp((double *)S.z);
         const GLB double *__restrict__ rhs = gp(S.rhs);
-        GLB double *__restrict__ pa = gp((double *)S.pa);
-        GLB double *__restrict__ pb = gp((double *)S.pb);
+        GLB double *__restrict__ pa = gp((double *)S.dir0);
+        GLB double *__restrict__ pb = gp((double *)S.dir1);
+        GLB double *__restrict__ pc = gp((double *)S.dir2);
         const Nbr<K> n = make_nbr(t, S, cf);
         const bool warm = st.warm != 0;
         const int64_t P = t.P;
@@ -451,6 +462,7 @@ __device__ void body_init64(const Slot &S, const SlotState &st, int64_t lt,
             z[c] = zc;
             pa[c] = 0.0;
             pb[c] = 0.0;
+            pc[c] = 0.0;
             a0 += b * b;
             a1 += r * zc;
             a2 += r * r;
@@ -629,8 +641,8 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
     // the buffer index is the same in every lane (state written by the
     // previous launch); reading it from one lane keeps the resources scalar
     const int pbuf = __builtin_amdgcn_readfirstlane(st.pbuf);
-    const Buf bps = W.buf((const T *)(pbuf ? S.pb : S.pa));
-    const Buf bpd = W.buf((const T *)(pbuf ? S.pa : S.pb));
+    const Buf bps = W.buf((const T *)dir_buf(S, pbuf));
+    const Buf bpd = W.buf((const T *)dir_buf(S, dir_next(pbuf)));
     const Buf bz = W.buf((const T *)S.z);
     const Buf bk = W.buf((const KE *)key_array(cf));
     // first direction: beta = 0.  p_old is then still read (it holds zeros
@@ -697,10 +709,11 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
 // K2_CG_B (T = double, X = double: x) / K2_IR_B (T = float, X = float: d):
 // q = A p, z -= alpha q / diag; acc = [r.z, r.r] with r = diag z.  The low z
 // face coefficient is carried from the plane below.  XM says what happens to
-// x: 1 x += alpha p (every iteration, the FP32 inner solve); 0 nothing (the
-// update is left pending); 2 x += alpha_prev p_prev, then += alpha p, with
-// p_prev still in the other direction buffer.  FP64 solves alternate 0 and 2,
-// reading and writing x every second iteration only.
+// x: 1 x += alpha p; 0 nothing (the update is left pending); 3 the two
+// pending updates, then this one: x += alpha_p0 p_p0, += alpha_p1 p_p1,
+// += alpha p, with p_p0 and p_p1 still in the other two direction buffers.
+// Solves run 0, 0, 3, reading and writing x every third iteration only; the
+// fused multiply-adds are those of one update per iteration, in order.
 template <typename T, typename X, class C, int XM = 1>
 __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
                            const C &cf, double (&acc)[3])
@@ -708,12 +721,15 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
     using K = typename C::Key;
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
-    const GLB T *__restrict__ p = gp((const T *)(st.pbuf ? S.pb : S.pa));
-    const GLB T *__restrict__ pprev = gp((const T *)(st.pbuf ? S.pa : S.pb));
+    const int pbuf = st.pbuf;
+    const GLB T *__restrict__ p = gp((const T *)dir_buf(S, pbuf));
+    // the directions one and two iterations back
+    const GLB T *__restrict__ pp1 = gp((const T *)dir_buf(S, dir_prev(pbuf)));
+    const GLB T *__restrict__ pp0 = gp((const T *)dir_buf(S, dir_next(pbuf)));
     GLB T *__restrict__ z = gp((T *)S.z);
     GLB X *__restrict__ x = gp(std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32);
     const T alpha = (T)st.alpha;
-    const T alpha_prev = (T)st.alpha_prev;
+    const T alpha_p0 = (T)st.alpha_p0, alpha_p1 = (T)st.alpha_p1;
     const Nbr<K> n = make_nbr(t, S, cf);
     const int64_t P = t.P;
     int64_t c = (int64_t)t.k0 * P + t.q;
@@ -734,7 +750,8 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
         const T lvxm = p[c + n.oxm], lvxp = p[c + n.oxp];
         const T lvym = p[c + n.oym], lvyp = p[c + n.oyp];
         const X xc = XM ? __builtin_nontemporal_load(&x[c]) : X(0);
-        const T pp = XM == 2 ? __builtin_nontemporal_load(&pprev[c]) : T(0);
+        const T po0 = XM == 3 ? __builtin_nontemporal_load(&pp0[c]) : T(0);
+        const T po1 = XM == 3 ? __builtin_nontemporal_load(&pp1[c]) : T(0);
         T zc = __builtin_nontemporal_load(&z[c]);
         const T vzp = top ? T(0) : vzp_l;
         const K kzp = top ? n.wzp : kzp_l;
@@ -751,8 +768,9 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
                      (bym * (vc - vym) + byp * (vc - vyp))) +
                     (bzm * (vc - vzm) + bzp * (vc - vzp));
         if (XM == 1) __builtin_nontemporal_store(xc + (X)(alpha * vc), &x[c]);
-        if (XM == 2)
-            __builtin_nontemporal_store(fma((X)alpha, (X)vc, fma((X)alpha_prev, (X)pp, xc)), &x[c]);
+        if (XM == 3)
+            __builtin_nontemporal_store(
+                fma((X)alpha, (X)vc, fma((X)alpha_p1, (X)po1, fma((X)alpha_p0, (X)po0, xc))), &x[c]);
         const T inv = dg > T(0) ? recip(dg) : T(0);   // hull rows keep z = 0
         zc -= alpha * q * inv;
         __builtin_nontemporal_store(zc, &z[c]);
@@ -796,8 +814,8 @@ __device__ void group_passA(const Slot &S, const SlotState &st, int64_t lt,
     if (!t.active) return;                  // planes hold whole groups
     const Window W = tile_window(t, S);
     const int pbuf = __builtin_amdgcn_readfirstlane(st.pbuf);
-    const Buf bps = W.buf((const T *)(pbuf ? S.pb : S.pa));
-    const Buf bpd = W.buf((const T *)(pbuf ? S.pa : S.pb));
+    const Buf bps = W.buf((const T *)dir_buf(S, pbuf));
+    const Buf bpd = W.buf((const T *)dir_buf(S, dir_next(pbuf)));
     const Buf bz = W.buf((const T *)S.z);
     const Buf bk = W.buf((const KE *)key_array(cf));
     const T beta = st.first ? T(0) : (T)st.beta;
@@ -894,8 +912,11 @@ __device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
     using V = typename VecN<T, N>::type;
     const TileCtx t = group_ctx(S, lt);
     if (!t.active) return;
-    const GLB T *__restrict__ p = gp((const T *)(st.pbuf ? S.pb : S.pa));
-    const GLB T *__restrict__ pprev = gp((const T *)(st.pbuf ? S.pa : S.pb));
+    const int pbuf = st.pbuf;
+    const GLB T *__restrict__ p = gp((const T *)dir_buf(S, pbuf));
+    // the directions one and two iterations back
+    const GLB T *__restrict__ pp1 = gp((const T *)dir_buf(S, dir_prev(pbuf)));
+    const GLB T *__restrict__ pp0 = gp((const T *)dir_buf(S, dir_next(pbuf)));
     GLB T *__restrict__ z = gp((T *)S.z);
     // x is the caller's array (FP64), read and written element by element;
     // the FP32 correction d is ours (aligned), in groups
@@ -903,10 +924,11 @@ __device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
     constexpr bool kXGroup = std::is_same<X, float>::value;
     using XV = typename VecN<X, N>::type;
     const GLB V *__restrict__ pv = (const GLB V *)p;
-    const GLB V *__restrict__ ppv = (const GLB V *)pprev;
+    const GLB V *__restrict__ pv0 = (const GLB V *)pp0;
+    const GLB V *__restrict__ pv1 = (const GLB V *)pp1;
     GLB V *__restrict__ zv = (GLB V *)z;
     const T alpha = (T)st.alpha;
-    const T alpha_prev = (T)st.alpha_prev;
+    const T alpha_p0 = (T)st.alpha_p0, alpha_p1 = (T)st.alpha_p1;
     const int nx = S.nx, ny = S.ny, bm = S.bcmask;
     const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
     const int i0 = t.i, j = t.j;
@@ -970,13 +992,14 @@ __device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
                 for (int n = 0; n < N; ++n) xo[n] = __builtin_nontemporal_load(&x[c + n]);
             }
         }
-        T pp[N];
+        T po0[N], po1[N];
 #pragma unroll
-        for (int n = 0; n < N; ++n) pp[n] = T(0);
-        if (XM == 2) {
-            const V v = __builtin_nontemporal_load(&ppv[c / N]);
+        for (int n = 0; n < N; ++n) po0[n] = po1[n] = T(0);
+        if (XM == 3) {
+            const V v0 = __builtin_nontemporal_load(&pv0[c / N]);
+            const V v1 = __builtin_nontemporal_load(&pv1[c / N]);
 #pragma unroll
-            for (int n = 0; n < N; ++n) pp[n] = v[n];
+            for (int n = 0; n < N; ++n) { po0[n] = v0[n]; po1[n] = v1[n]; }
         }
         T zn[N];
         X xn[N];
@@ -1000,7 +1023,9 @@ __device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
                          (bym * (vc[n] - vym) + byp * (vc[n] - vyp))) +
                         (bzm[n] * (vc[n] - vzm[n]) + bzp * (vc[n] - vzp));
             if (XM == 1) xn[n] = xo[n] + (X)(alpha * vc[n]);
-            if (XM == 2) xn[n] = fma((X)alpha, (X)vc[n], fma((X)alpha_prev, (X)pp[n], xo[n]));
+            if (XM == 3)
+                xn[n] = fma((X)alpha, (X)vc[n],
+                            fma((X)alpha_p1, (X)po1[n], fma((X)alpha_p0, (X)po0[n], xo[n])));
             const T inv = dg > T(0) ? recip(dg) : T(0);   // hull rows keep z = 0
             zn[n] = zc[n] - alpha * q * inv;
             const double r = (double)dg * (double)zn[n];
@@ -1099,7 +1124,7 @@ __device__ void body_check64(const Slot &S, const SlotState &st, int64_t lt,
     });
 }
 
-// K1_IR_INIT: x = 0 (cold) or hull entries cleared (warm), d = 0, both
+// K1_IR_INIT: x = 0 (cold) or hull entries cleared (warm), d = 0, the
 // direction buffers zeroed; acc = [b.b].
 template <class C>
 __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
@@ -1109,8 +1134,9 @@ __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
         if (!t.active) return;
         GLB double *__restrict__ x = gp(S.x);
         GLB float *__restrict__ d = gp(S.d32);
-        GLB float *__restrict__ pa = gp((float *)S.pa);
-        GLB float *__restrict__ pb = gp((float *)S.pb);
+        GLB float *__restrict__ pa = gp((float *)S.dir0);
+        GLB float *__restrict__ pb = gp((float *)S.dir1);
+        GLB float *__restrict__ pc = gp((float *)S.dir2);
         const GLB double *__restrict__ rhs = gp(S.rhs);
         int64_t c = (int64_t)t.k0 * t.P + t.q;
         const bool warm = st.warm != 0;
@@ -1121,6 +1147,7 @@ __device__ void body_ir_init(const Slot &S, const SlotState &st, int64_t lt,
             d[c] = 0.0f;
             pa[c] = 0.0f;
             pb[c] = 0.0f;
+            pc[c] = 0.0f;
             const double b = solid ? 0.0 : -S.h2 * vol_at(S, c) * rhs[c] - st.bshift;
             a += b * b;
         }
@@ -1186,25 +1213,36 @@ __device__ void body_ir_resid(const Slot &S, const SlotState &st, int64_t lt,
     });
 }
 
-// K1_FLUSH_X: the update the last iteration left pending, with the current
-// direction: x += alpha p (FP64), or the inner solve's correction d += alpha
-// p (FP32+IR).
+// K1_FLUSH_X: the updates the last one or two iterations left pending, in
+// order: x += alpha_p0 p_p0 (+= alpha_p1 p_p1) (FP64), or the same on the
+// inner solve's correction d (FP32+IR).  The latest pending direction is the
+// current buffer, the one before it the previous buffer.
 __device__ void body_flush_x(const Slot &S, const SlotState &st, int64_t lt, double (&acc)[3])
 {
+    const int two = st.xpend == 2;
+    const int b0 = two ? dir_prev(st.pbuf) : st.pbuf;
     for_rows(S, lt, [&](const TileCtx &t) {
         if (!t.active) return;
         int64_t c = (int64_t)t.k0 * t.P + t.q;
         if (S.d32) {
             GLB float *__restrict__ d = gp(S.d32);
-            const GLB float *__restrict__ p = gp((const float *)(st.pbuf ? S.pb : S.pa));
-            const float alpha = (float)st.alpha;
-            for (int k = t.k0; k < t.k1; ++k, c += t.P) d[c] = fmaf(alpha, p[c], d[c]);
+            const GLB float *__restrict__ p0 = gp((const float *)dir_buf(S, b0));
+            const GLB float *__restrict__ p1 = gp((const float *)dir_buf(S, st.pbuf));
+            const float a0 = (float)st.alpha_p0, a1 = (float)st.alpha_p1;
+            for (int k = t.k0; k < t.k1; ++k, c += t.P) {
+                const float v = fmaf(a0, p0[c], d[c]);
+                d[c] = two ? fmaf(a1, p1[c], v) : v;
+            }
             return;
         }
         GLB double *__restrict__ x = gp(S.x);
-        const GLB double *__restrict__ p = gp((const double *)(st.pbuf ? S.pb : S.pa));
-        const double alpha = st.alpha;
-        for (int k = t.k0; k < t.k1; ++k, c += t.P) x[c] = fma(alpha, p[c], x[c]);
+        const GLB double *__restrict__ p0 = gp((const double *)dir_buf(S, b0));
+        const GLB double *__restrict__ p1 = gp((const double *)dir_buf(S, st.pbuf));
+        const double a0 = st.alpha_p0, a1 = st.alpha_p1;
+        for (int k = t.k0; k < t.k1; ++k, c += t.P) {
+            const double v = fma(a0, p0[c], x[c]);
+            x[c] = two ? fma(a1, p1[c], v) : v;
+        }
     });
 }
 
@@ -1306,6 +1344,16 @@ __device__ double pow2_scale(double norm)
     return ldexp(1.0, -ilogb(norm));
 }
 
+// After pass B: it caught x up (two updates were pending: none now) or left
+// this iteration's update pending beside the ones before it.
+__device__ __forceinline__ void note_x_update(SlotState &st)
+{
+    if (st.xpend == 2) { st.xpend = 0; return; }
+    if (st.xpend == 0) st.alpha_p0 = st.alpha;
+    else st.alpha_p1 = st.alpha;
+    st.xpend += 1;
+}
+
 __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
 {
     switch (phase) {
@@ -1329,14 +1377,14 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
     case K1_CG_A: {
         const double pap = tot[0];
         if (!(pap > 0.0) || !isfinite(pap)) {
-            // x keeps the last iterate: apply a pending update first
+            // x keeps the last iterate: apply the pending updates first
             if (st.xpend) { st.status = PCG_EBREAKDOWN; st.phase = K1_FLUSH_X; }
             else finish(st, PCG_EBREAKDOWN);
             break;
         }
         st.pap = pap;
         st.alpha = st.rz / pap;
-        st.pbuf ^= 1;
+        st.pbuf = dir_next(st.pbuf);
         st.first = 0;
         st.phase = K2_CG_B;
         break;
@@ -1346,9 +1394,7 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         st.rr = tot[1];
         st.beta = tot[0] / st.rz;
         st.rz = tot[0];
-        // the pass just run left x alone (xpend 0) or caught it up (xpend 1)
-        if (st.xpend) st.xpend = 0;
-        else { st.xpend = 1; st.alpha_prev = st.alpha; }
+        note_x_update(st);
         if (!isfinite(st.rr) || !isfinite(st.rz)) { finish(st, PCG_EBREAKDOWN); break; }
         if (st.rr <= st.tol2 || st.iter >= st.maxit) {
             st.phase = st.xpend ? K1_FLUSH_X : K1_CHECK64;
@@ -1454,7 +1500,7 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         }
         st.pap = pap;
         st.alpha = st.rz / pap;
-        st.pbuf ^= 1;
+        st.pbuf = dir_next(st.pbuf);
         st.first = 0;
         st.phase = K2_IR_B;
         break;
@@ -1465,9 +1511,7 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         st.rr = tot[1];
         st.beta = tot[0] / st.rz;
         st.rz = tot[0];
-        // as in FP64: the pass left d alone (xpend 0) or caught it up (1)
-        if (st.xpend) st.xpend = 0;
-        else { st.xpend = 1; st.alpha_prev = st.alpha; }
+        note_x_update(st);   // d, as x in FP64
         if (!isfinite(st.rr)) { finish(st, PCG_EBREAKDOWN); break; }
         const bool inner_done = st.rr <= st.inner_goal2 * st.rr0_inner ||
                                 st.inner_iter >= st.inner_maxit ||
@@ -1559,17 +1603,17 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
             }
         } else {
             if (ph == K2_CG_B) {
-                // x is read and written every second iteration (XM 0, then 2)
-                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) != 0;
+                // x is read and written every third iteration (XM 0, 0, 3)
+                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
                 if (MODE == 2) {
                     const FracCoef<double> f = frac_coef<double>(S, S.rho64);
-                    if (catch_up) passB<double, double, FracCoef<double>, 2>(S, st, lt, f, acc);
+                    if (catch_up) passB<double, double, FracCoef<double>, 3>(S, st, lt, f, acc);
                     else passB<double, double, FracCoef<double>, 0>(S, st, lt, f, acc);
                 } else if (MODE == 1) {
-                    if (catch_up) passB<double, double, ClsCoef<double>, 2>(S, st, lt, c64, acc);
+                    if (catch_up) passB<double, double, ClsCoef<double>, 3>(S, st, lt, c64, acc);
                     else passB<double, double, ClsCoef<double>, 0>(S, st, lt, c64, acc);
                 } else {
-                    if (catch_up) passB<double, double, RhoCoef<double>, 2>(S, st, lt, r64, acc);
+                    if (catch_up) passB<double, double, RhoCoef<double>, 3>(S, st, lt, r64, acc);
                     else passB<double, double, RhoCoef<double>, 0>(S, st, lt, r64, acc);
                 }
             } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
@@ -1586,17 +1630,17 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
             }
         } else {
             if (ph == K2_IR_B) {
-                // d is read and written every second iteration, as x in FP64
-                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) != 0;
+                // d is read and written every third iteration, as x in FP64
+                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
                 if (MODE == 2) {
                     const FracCoef<float> f = frac_coef<float>(S, S.rho32);
-                    if (catch_up) passB<float, float, FracCoef<float>, 2>(S, st, lt, f, acc);
+                    if (catch_up) passB<float, float, FracCoef<float>, 3>(S, st, lt, f, acc);
                     else passB<float, float, FracCoef<float>, 0>(S, st, lt, f, acc);
                 } else if (MODE == 1) {
-                    if (catch_up) passB<float, float, ClsCoef<float>, 2>(S, st, lt, c32, acc);
+                    if (catch_up) passB<float, float, ClsCoef<float>, 3>(S, st, lt, c32, acc);
                     else passB<float, float, ClsCoef<float>, 0>(S, st, lt, c32, acc);
                 } else {
-                    if (catch_up) passB<float, float, RhoCoef<float>, 2>(S, st, lt, r32, acc);
+                    if (catch_up) passB<float, float, RhoCoef<float>, 3>(S, st, lt, r32, acc);
                     else passB<float, float, RhoCoef<float>, 0>(S, st, lt, r32, acc);
                 }
             } else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);

@@ -33,7 +33,7 @@ enum Phase : int32_t {
     K1_IR_A = 6,       // FP32 p = z + beta p ; p.Ap (FP64 sum)
     K1_MEAN_B = 7,     // singular problem: sum of b and count of fluid cells
     K1_MEAN_X = 8,     // singular problem: sum of x over fluid cells
-    K1_FLUSH_X = 9,    // x += alpha p: the update an iteration left pending
+    K1_FLUSH_X = 9,    // x += alpha p: the updates the last iterations left pending
     // K2 actions (second launch of an iteration)
     K2_NONE = 11,      // nothing; then the K1 action in `after`
     K2_CG_B = 12,      // q = A p, x += alpha p, z -= alpha D^-1 q ; r.z, r.r
@@ -62,7 +62,8 @@ struct alignas(128) SlotState {
     double bshift;    // singular problem: mean of b over fluid cells (else 0)
     double nfluid;    // singular problem: number of fluid cells
     double xshift;    // singular problem: mean of x over fluid cells
-    double alpha_prev;// alpha of the direction whose x update is pending
+    // alphas of the directions whose x updates are pending, oldest first
+    double alpha_p0, alpha_p1;
     int32_t phase;
     int32_t after;    // K1 action after a K2_NONE
     int32_t status;   // PCG_PENDING while running, else the final code
@@ -71,12 +72,12 @@ struct alignas(128) SlotState {
     int32_t inner_iter;
     int32_t maxit, inner_maxit;
     int32_t first;    // next pass A uses beta = 0
-    int32_t pbuf;     // which p buffer holds the current direction
+    int32_t pbuf;     // which of the three p buffers holds the current direction
     int32_t final_upd;// IR: the pending update is the last one
     uint32_t ticket;  // arrivals of the current launch
     int32_t warm;     // warm start requested
     int32_t singular; // no Dirichlet face: solve for the mean-free source
-    int32_t xpend;    // x (FP64) or d (IR) lacks alpha_prev p_prev (updates go in pairs)
+    int32_t xpend;    // earlier iterations whose x (FP64) or d (IR) update is pending: 0..2
     int32_t pad_[1];
 };
 
@@ -98,7 +99,9 @@ struct Slot {
     const double *rho64;   // density, +inf in solid cells
     const float *rho32;    // IR only
     void *z;               // D^-1 r   (double, or float for IR)
-    void *pa, *pb;         // search direction, ping-pong
+    // search directions, rotating: pass A reads buffer b and writes b + 1
+    // (mod 3), so the two directions before the current one stay readable
+    void *dir0, *dir1, *dir2;
     float *d32;            // IR inner correction
     double *partials;      // kMaxPartials * ntiles
     SlotState *st;
