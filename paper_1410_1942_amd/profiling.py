@@ -36,7 +36,7 @@ def kernel_stats(path: str) -> str:
         return "\n".join(out)
     # *_kernel_trace.csv: aggregate ourselves; `large` averages the launches
     # of at least a quarter of the longest one (the largest problem's
-    # launches, both forms of an alternating kernel; not the empty launches
+    # launches, every form of a kernel whose launches vary; not the empty launches
     # at the end of a captured chunk nor those of smaller problems)
     agg = collections.defaultdict(list)
     for r in rows:
@@ -79,8 +79,8 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
     lines = [f"# FETCH_SIZE scale {sf:.4f}, WRITE_SIZE scale {sw:.4f} "
              f"(copy kernel: {copy_bytes} B read and written per launch)",
              f"# per launch, mean over the launches fetching at least a quarter of the "
-             f"largest (empty launches at the end of a captured chunk excluded; FP64 pass B "
-             f"alternates two forms, both kept); cells = {cells}"]
+             f"largest (empty launches at the end of a captured chunk excluded; both forms "
+             f"of pass B, with and without the x update, kept); cells = {cells}"]
     if sha:
         lines.append(f"kernel_source_sha = {sha}")
     lines.append(f"{'kernel':58s} {'n':>4s} {'fetch_B':>14s} {'write_B':>14s} "
