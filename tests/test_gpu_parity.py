@@ -191,6 +191,33 @@ def test_maxit_and_warm_resume(orc, F, torch_dev):
     assert rr <= 1e-8
 
 
+# k = 13..17 covers every residue modulo 3; a row length of 32 runs the
+# grouped passes, 33 the one-cell ones
+@pytest.mark.parametrize("k,nx", [(13, 32), (14, 32), (15, 32), (16, 32), (17, 32),
+                                  (13, 33), (14, 33)])
+def test_capped_iterate_is_the_kth_iterate(orc, F, torch_dev, k, nx):
+    """Stopped by the iteration cap, x is the reference's k-th PCG iterate,
+    whatever k is modulo the interval at which pass B updates x: updates still
+    pending at the cap are applied before the solve returns.  The FP32 inner
+    solve of the refinement, capped the same way, returns its k-th iterate
+    of the same system (its correction d is flushed the same way)."""
+    case = _two_phase(F, nx, 24, 20)
+    _say(f"case capped k={k} nx={nx}")
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=k)
+    prev = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=k - 1)
+    assert ref.status == 1 and ref.iters == k
+    scale = np.abs(ref.p).max()
+    # one update more or less moves the iterate by about 1 %: far outside both bars
+    assert np.abs(ref.p - prev.p).max() > 1e-3 * scale
+    p, st = gpu_solve(torch_dev, case, tol=1e-30, maxit=k)
+    assert st["status"] == 1 and st["iters"] == k, st
+    assert np.abs(p - ref.p).max() <= 1e-10 * scale
+    p32, st32 = gpu_solve(torch_dev, case, tol=1e-30, maxit=k, precision=1)
+    # two FP64 residuals: the initial one and the one after the single inner solve
+    assert st32["status"] == 1 and st32["iters"] == k and st32["outer_iters"] == 2, st32
+    assert np.abs(p32 - ref.p).max() <= 1e-4 * scale
+
+
 def test_warm_start_with_solution(orc, F, torch_dev):
     case = _two_phase(F, 24, 20, 16)
     ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-12).p
