@@ -709,15 +709,16 @@ __device__ void body_passA(const Slot &S, const SlotState &st, int64_t lt,
 // K2_CG_B (T = double, X = double: x) / K2_IR_B (T = float, X = float: d):
 // q = A p, z -= alpha q / diag; acc = [r.z, r.r] with r = diag z.  The low z
 // face coefficient is carried from the plane below.  XM says what happens to
-// x: 1 x += alpha p; 0 nothing (the update is left pending); 3 the two
-// pending updates, then this one: x += alpha_p0 p_p0, += alpha_p1 p_p1,
+// x: 0 nothing (the update is left pending); 3 the two pending updates, then
+// this one: x += alpha_p0 p_p0, += alpha_p1 p_p1,
 // += alpha p, with p_p0 and p_p1 still in the other two direction buffers.
 // Solves run 0, 0, 3, reading and writing x every third iteration only; the
 // fused multiply-adds are those of one update per iteration, in order.
-template <typename T, typename X, class C, int XM = 1>
+template <typename T, typename X, class C, int XM>
 __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
                            const C &cf, double (&acc)[3])
 {
+    static_assert(XM == 0 || XM == 3, "x left pending, or caught up");
     using K = typename C::Key;
     const TileCtx t = tile_ctx(S, lt);
     if (!t.active) return;
@@ -767,7 +768,6 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
         const T q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) +
                      (bym * (vc - vym) + byp * (vc - vyp))) +
                     (bzm * (vc - vzm) + bzp * (vc - vzp));
-        if (XM == 1) __builtin_nontemporal_store(xc + (X)(alpha * vc), &x[c]);
         if (XM == 3)
             __builtin_nontemporal_store(
                 fma((X)alpha, (X)vc, fma((X)alpha_p1, (X)po1, fma((X)alpha_p0, (X)po0, xc))), &x[c]);
@@ -1022,7 +1022,6 @@ __device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
             const T q = ((bxm * (vc[n] - vxm) + bxp * (vc[n] - vxp)) +
                          (bym * (vc[n] - vym) + byp * (vc[n] - vyp))) +
                         (bzm[n] * (vc[n] - vzm[n]) + bzp * (vc[n] - vzp));
-            if (XM == 1) xn[n] = xo[n] + (X)(alpha * vc[n]);
             if (XM == 3)
                 xn[n] = fma((X)alpha, (X)vc[n],
                             fma((X)alpha_p1, (X)po1[n], fma((X)alpha_p0, (X)po0[n], xo[n])));
@@ -1074,7 +1073,7 @@ __device__ __forceinline__ void passA(const Slot &S, const SlotState &st, int64_
     else body_passA<T>(S, st, lt, cf, acc);
 }
 
-template <typename T, typename X, class C, int XM = 1>
+template <typename T, typename X, class C, int XM>
 __device__ __forceinline__ void passB(const Slot &S, const SlotState &st, int64_t lt,
                                       const C &cf, double (&acc)[3])
 {
