@@ -43,12 +43,28 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _require_device(*ts):
-    for t in ts:
-        if t is None:
-            continue
-        if not t.is_cuda or not t.is_contiguous():
-            raise ValueError("arrays must be contiguous device tensors")
+def _check(t: Optional[torch.Tensor], shape, dtype, name: str, device=None,
+           optional: bool = False):
+    """The library reads and writes exactly the grid's extent through raw
+    pointers: refuse anything that is not a contiguous device tensor of the
+    expected dtype, shape and device before it gets there."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name}: a device tensor is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: must be a contiguous device tensor")
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: must be {dtype} of shape {tuple(shape)}, "
+                         f"got {t.dtype} of shape {tuple(t.shape)}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name}: must be on {device}, got {t.device}")
+
+
+def _field_shape(rho: torch.Tensor):
+    if not isinstance(rho, torch.Tensor) or rho.dim() != 3:
+        raise ValueError("rho: a 3-D [nz, ny, nx] tensor")
+    return tuple(rho.shape)
 
 
 class Solver:
@@ -64,12 +80,11 @@ class Solver:
         lib = L.load()
         from .autotune import ensure_installed
         ensure_installed()
-        _require_device(rho, mask)
-        if rho.dtype != torch.float64:
-            raise ValueError("rho must be float64")
-        if mask is not None and mask.dtype != torch.uint8:
-            raise ValueError("mask must be uint8")
-        self.shape = tuple(rho.shape)
+        shape = _field_shape(rho)
+        _check(rho, shape, torch.float64, "rho")
+        _check(mask, shape, torch.uint8, "mask", rho.device, optional=True)
+        self.shape = shape
+        self.device = rho.device
         self.grid = _grid(self.shape, h)
         self.opts = make_opts(precision=precision, flags=flags, **opt_kw)
         nbytes = ctypes.c_size_t(0)
@@ -91,16 +106,12 @@ class Solver:
               warm: Optional[bool] = None):
         """Solve L p = rhs.  Returns (p, stats dict).  ``warm`` True starts
         from p's contents, False from zero, None as the setup flags say."""
-        _require_device(rhs)
-        if rhs.dtype != torch.float64 or tuple(rhs.shape) != self.shape:
-            raise ValueError("rhs must be float64 with the grid's shape")
+        _check(rhs, self.shape, torch.float64, "rhs", self.device)
         if p is None:
             if warm:
                 raise ValueError("a warm start needs p")
             p = torch.empty_like(rhs)
-        _require_device(p)
-        if p.dtype != torch.float64 or tuple(p.shape) != self.shape:
-            raise ValueError("p must be float64 with the grid's shape")
+        _check(p, self.shape, torch.float64, "p", self.device)
         st = L.Stats()
         if warm is None:
             code = self.lib.pcg_solve(self._ctx, _ptr(rhs), _ptr(p), float(tol),
@@ -117,11 +128,8 @@ class Solver:
                        flags: int = 0):
         """New density (and hull) on the same grid and walls
         (pcg_update_density); the next solve may warm-start."""
-        _require_device(rho, mask)
-        if rho.dtype != torch.float64 or tuple(rho.shape) != self.shape:
-            raise ValueError("rho must be float64 with the grid's shape")
-        if mask is not None and (mask.dtype != torch.uint8 or tuple(mask.shape) != self.shape):
-            raise ValueError("mask must be uint8 with the grid's shape")
+        _check(rho, self.shape, torch.float64, "rho", self.device)
+        _check(mask, self.shape, torch.uint8, "mask", self.device, optional=True)
         L.check(self.lib.pcg_update_density(self._ctx, _ptr(rho), _ptr(mask), int(flags)),
                 "pcg_update_density")
 
@@ -141,20 +149,16 @@ class Solver:
                     "pcg_set_fractions")
             return
         a = self._faces((ax, ay, az), "fractions")
-        _require_device(vol)
-        if vol.dtype != torch.float64 or tuple(vol.shape) != self.shape:
-            raise ValueError("vol must be float64 with the grid's shape")
+        _check(vol, self.shape, torch.float64, "vol", self.device)
         L.check(self.lib.pcg_set_fractions(self._ctx, *a, _ptr(vol)), "pcg_set_fractions")
 
     def _faces(self, faces, what):
         nz, ny, nx = self.shape
         if faces is None or len(faces) != 3:
             raise ValueError(f"{what}: three face arrays (u, v, w)")
-        for t, shp in zip(faces, ((nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx))):
-            _require_device(t)
-            if t.dtype != torch.float64 or tuple(t.shape) != shp:
-                raise ValueError(f"{what}: face arrays must be float64 u[nz,ny,nx+1], "
-                                 "v[nz,ny+1,nx], w[nz+1,ny,nx]")
+        for t, shp, c in zip(faces, ((nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)),
+                             "uvw"):
+            _check(t, shp, torch.float64, f"{what} {c}", self.device)
         return [_ptr(t) for t in faces]
 
     def project(self, p: torch.Tensor, dt: float, u: torch.Tensor,
@@ -165,9 +169,7 @@ class Solver:
         a = self._faces((u, v, w), "velocity")
         b = self._faces(add, "add") if add is not None else [None, None, None]
         o = self._faces(out, "out") if out is not None else a
-        _require_device(p)
-        if p.dtype != torch.float64 or tuple(p.shape) != self.shape:
-            raise ValueError("p must be float64 with the grid's shape")
+        _check(p, self.shape, torch.float64, "p", self.device)
         L.check(self.lib.pcg_project_ex(self._ctx, _ptr(p), float(dt), *a, *b,
                                         float(weight), *o), "pcg_project_ex")
 
@@ -176,18 +178,16 @@ class Solver:
         a = self._faces((u, v, w), "velocity")
         b = self._faces(add, "add") if add is not None else [None, None, None]
         if out is None:
-            out = torch.empty(self.shape, dtype=torch.float64, device=u.device)
-        _require_device(out)
-        if out.dtype != torch.float64 or tuple(out.shape) != self.shape:
-            raise ValueError("out must be float64 with the grid's shape")
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        _check(out, self.shape, torch.float64, "out", self.device)
         L.check(self.lib.pcg_rhs(self._ctx, float(dt), *a, *b, _ptr(out)), "pcg_rhs")
         return out
 
     def divergence(self, u, v, w):
         """(||D u||_2, max |D u|) over fluid cells (pcg_divergence)."""
+        a = self._faces((u, v, w), "velocity")
         out = (ctypes.c_double * 2)()
-        L.check(self.lib.pcg_divergence(self._ctx, _ptr(u), _ptr(v), _ptr(w), out),
-                "pcg_divergence")
+        L.check(self.lib.pcg_divergence(self._ctx, *a, out), "pcg_divergence")
         return out[0], out[1]
 
     def set_timing(self, on: bool = True):
@@ -246,8 +246,13 @@ class Batch:
     def admit(self, rho, mask, bc, h, rhs, p, tol=1e-8, maxit=1000000,
               flags=0):
         """Returns (status, slot).  status PCG_EBUSY means "try later"."""
-        _require_device(rho, mask, rhs, p)
-        g = _grid(tuple(rho.shape), h)
+        shape = _field_shape(rho)
+        dev = self.arena.device
+        _check(rho, shape, torch.float64, "rho", dev)
+        _check(mask, shape, torch.uint8, "mask", dev, optional=True)
+        _check(rhs, shape, torch.float64, "rhs", dev)
+        _check(p, shape, torch.float64, "p", dev)
+        g = _grid(shape, h)
         slot = ctypes.c_int32(-1)
         code = self.lib.pcg_batch_admit(self._b, ctypes.byref(g), _ptr(rho),
                                         _ptr(mask), ctypes.byref(_bc(bc)),

@@ -225,6 +225,55 @@ def test_warm_start_with_solution(orc, F, torch_dev):
     assert st["status"] == 0 and st["iters"] == 0
 
 
+def test_binding_refuses_mismatched_arrays(F, torch_dev):
+    """The library works through raw pointers over the grid's extent: the
+    binding refuses arrays of the wrong shape, dtype, layout or device
+    before any of them reaches it."""
+    torch, dev = torch_dev
+    from paper_1410_1942_amd.solver import Batch, Solver
+    case = _two_phase(F, 12, 10, 8, wedge=False)
+    rho = _to(torch, dev, case.rho)
+    mask = _to(torch, dev, case.mask)
+    rhs = _to(torch, dev, case.rhs)
+    with pytest.raises(ValueError):
+        Solver(rho, mask[:, :, :-1].contiguous(), case.bc, case.h)
+    with pytest.raises(ValueError):
+        Solver(rho[0], None, case.bc, case.h)
+    with pytest.raises(ValueError):
+        Solver(rho, mask.to(torch.int32), case.bc, case.h)
+    with pytest.raises(ValueError):
+        Solver(rho.cpu(), None, case.bc, case.h)
+    s = Solver(rho, mask, case.bc, case.h)
+    try:
+        for bad in (rhs.float(), rhs[:-1].contiguous(), rhs.transpose(0, 2),
+                    rhs.cpu()):
+            with pytest.raises(ValueError):
+                s.solve(bad)
+        with pytest.raises(ValueError):
+            s.solve(rhs, p=torch.empty(case.shape, dtype=torch.float32, device=dev))
+        nz, ny, nx = case.shape
+        u = torch.zeros((nz, ny, nx + 1), dtype=torch.float64, device=dev)
+        v = torch.zeros((nz, ny + 1, nx), dtype=torch.float64, device=dev)
+        w = torch.zeros((nz + 1, ny, nx), dtype=torch.float64, device=dev)
+        with pytest.raises(ValueError):
+            s.divergence(u[:, :, :-1].contiguous(), v, w)
+        with pytest.raises(ValueError):
+            s.project(rhs, 1e-3, u, w, v)
+        _, st = s.solve(rhs)          # the context is still usable
+        assert st["status"] == 0
+    finally:
+        s.close()
+    b = Batch(64 << 20, 4, precision=0)
+    try:
+        p = torch.empty_like(rhs)
+        with pytest.raises(ValueError):
+            b.admit(rho, mask[:-1].contiguous(), case.bc, case.h, rhs, p)
+        with pytest.raises(ValueError):
+            b.admit(rho, mask, case.bc, case.h, rhs.float(), p)
+    finally:
+        b.close()
+
+
 def test_errors(F, torch_dev):
     from paper_1410_1942_amd import _lib as L
     case = _two_phase(F, 12, 10, 8, wedge=False)
