@@ -29,6 +29,8 @@ hipError_t launch_classify(const double *r64, uint8_t *cls, int64_t n, int round
 hipError_t launch_encode(const double *rho, const uint8_t *mask, double *r64,
                          float *r32, int64_t n, int *bad, hipStream_t s);
 hipError_t launch_copy(const double *src, double *dst, size_t n, hipStream_t s);
+hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int nx,
+                            int words_per_row, int64_t nwords, hipStream_t s);
 hipError_t launch_triad(double *a, const double *b, const double *c, double sc, size_t n,
                         hipStream_t s);
 hipError_t launch_check_frac(const double *ax, const double *ay, const double *az,
@@ -294,35 +296,56 @@ int check_opts(const pcg_opts_t *o)
 }
 
 // Connected fluid regions and how many of them touch no Dirichlet wall.
-// Flood fill over x-runs of fluid cells: one scan of the mask splits every
-// row into maximal runs, then a breadth-first search per region moves
-// between runs of neighbouring rows (y and z) that overlap in x, and across
-// periodic walls (the first and last run of a row for x, the first and last
-// row of a plane for y).  Work is linear in the cells for the scan and in
-// the runs for the search.
+// Flood fill over x-runs of fluid cells: the mask, one bit per cell, is split
+// row by row into maximal runs a 32-bit word at a time, then a breadth-first
+// search per region moves between runs of neighbouring rows (y and z) that
+// overlap in x, and across periodic walls (the first and last run of a row
+// for x, the first and last row of a plane for y).  Work is linear in the
+// words for the split and in the runs for the search.
 struct FluidRegions {
     int64_t regions = 0;
     int64_t unanchored = 0;
 };
 
-// First index >= i of a nonzero (solid) byte in m[0, nx), or nx; fluid rows
-// are mostly zeros, so whole 8-byte words are skipped at a time.
-static int next_solid(const uint8_t *m, int i, int nx)
+// Bit layout of a packed mask: words_per_row(nx) 32-bit words per row, bit j
+// of word w the cell x = 32 w + j, 1 = hull, the bits past the row's end set.
+int words_per_row(int nx) { return (nx + 31) / 32; }
+
+// The same packing on the host (for a host mask).
+std::vector<uint32_t> pack_mask_host(const uint8_t *m, int nx, int64_t nrows)
 {
-    while (i + 8 <= nx) {
-        uint64_t w;
-        std::memcpy(&w, m + i, 8);
-        if (w) break;
-        i += 8;
-    }
-    while (i < nx && !m[i]) ++i;
-    return i;
+    const int wpr = words_per_row(nx);
+    std::vector<uint32_t> bits((size_t)(nrows * wpr));
+    for (int64_t r = 0; r < nrows; ++r)
+        for (int w = 0; w < wpr; ++w) {
+            const int x0 = 32 * w, cnt = std::min(32, nx - x0);
+            const uint8_t *row = m + r * nx + x0;
+            uint32_t v = cnt < 32 ? ~0u << cnt : 0u;
+            for (int j = 0; j < cnt; ++j) v |= (uint32_t)(row[j] != 0) << j;
+            bits[(size_t)(r * wpr + w)] = v;
+        }
+    return bits;
 }
 
-FluidRegions fluid_regions(const uint8_t *solid, int nx, int ny, int nz, int bcmask,
+// First cell >= i of a row whose bit is `hull` (1) or fluid (0), or the end
+// of the row's words.
+static int next_cell(const uint32_t *w, int wpr, int i, bool hull)
+{
+    int iw = i >> 5;
+    if (iw >= wpr) return 32 * wpr;
+    uint32_t v = (hull ? w[iw] : ~w[iw]) & (~0u << (i & 31));
+    while (!v) {
+        if (++iw == wpr) return 32 * wpr;
+        v = hull ? w[iw] : ~w[iw];
+    }
+    return 32 * iw + __builtin_ctz(v);
+}
+
+FluidRegions fluid_regions(const uint32_t *bits, int nx, int ny, int nz, int bcmask,
                            int permask)
 {
     const int64_t nrows = (int64_t)ny * nz;
+    const int wpr = words_per_row(nx);
     std::vector<int64_t> row_start(nrows + 1, 0);
     std::vector<int32_t> ra, rb;  // run [ra, rb) in x
     std::vector<int64_t> run_row;
@@ -331,13 +354,12 @@ FluidRegions fluid_regions(const uint8_t *solid, int nx, int ny, int nz, int bcm
     run_row.reserve(nrows * 2);
     for (int64_t r = 0; r < nrows; ++r) {
         row_start[r] = (int64_t)ra.size();
-        const uint8_t *m = solid + r * nx;
+        const uint32_t *w = bits + r * wpr;
         int i = 0;
-        while (i < nx) {
-            while (i < nx && m[i]) ++i;
-            if (i >= nx) break;
-            const int a = i;
-            i = next_solid(m, i, nx);
+        while (true) {
+            const int a = next_cell(w, wpr, i, false);
+            if (a >= nx) break;
+            i = std::min(next_cell(w, wpr, a, true), nx);
             ra.push_back(a);
             rb.push_back(i);
             run_row.push_back(r);
@@ -686,9 +708,18 @@ struct Engine {
         // single region touches none (singular); unchecked, the walls decide
         S.singular = S.bcmask == 0;
         if (!(flags & PCG_SKIP_CONNECTIVITY_CHECK) && mask) {
-            std::vector<uint8_t> h((size_t)geo.n);
-            hipError_t e = hipMemcpy(h.data(), mask, (size_t)geo.n, hipMemcpyDeviceToHost);
-            if (e != hipSuccess) return hip_fail(e, "mask copy");
+            // packed on the device into the slot's z vector (4 n bytes or
+            // more; unused until the solve initialises it), then read back
+            const int wpr = words_per_row(geo.nx);
+            const int64_t nwords = (int64_t)geo.ny * geo.nz * wpr;
+            std::vector<uint32_t> h((size_t)nwords);
+            uint32_t *dbits = (uint32_t *)S.z;
+            hipError_t e = launch_pack_mask(mask, dbits, geo.nx, wpr, nwords, stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(h.data(), dbits, (size_t)nwords * 4, hipMemcpyDeviceToHost,
+                                   stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_fail(e, "mask bits");
             const int kind = classify_regions(
                 fluid_regions(h.data(), geo.nx, geo.ny, geo.nz, S.bcmask, S.permask));
             if (kind < 0) return kind;
@@ -1144,8 +1175,10 @@ int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
     st = check_bc(bc, &bm, &per);
     if (st) return st;
     if (!host_mask) return bm ? PCG_OK : PCG_SINGULAR;   // one region
+    const std::vector<uint32_t> bits =
+        pack_mask_host(host_mask, grid->nx, (int64_t)grid->ny * grid->nz);
     const int kind = classify_regions(
-        fluid_regions(host_mask, grid->nx, grid->ny, grid->nz, bm, per));
+        fluid_regions(bits.data(), grid->nx, grid->ny, grid->nz, bm, per));
     return kind < 0 ? kind : kind == 1 ? PCG_SINGULAR : PCG_OK;
 }
 

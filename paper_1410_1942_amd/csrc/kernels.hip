@@ -1773,6 +1773,27 @@ k_encode(const double *__restrict__ rho, const uint8_t *__restrict__ mask,
     if (local_bad) atomicOr(bad, 1);
 }
 
+// The hull mask one bit per cell for the host's connectivity check: row r
+// takes words_per_row 32-bit words from bits[r * words_per_row], bit j of
+// word w the cell x = 32 w + j (1 = hull); the bits past the row's end are
+// set, so every row ends in a hull bit.  An eighth of the mask's bytes
+// cross to the host, and the host finds fluid runs a word at a time.
+__global__ void __launch_bounds__(256)
+k_pack_mask(const uint8_t *__restrict__ mask, uint32_t *__restrict__ bits, int nx,
+            int words_per_row, int64_t nwords)
+{
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nwords;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = t / words_per_row;
+        const int x0 = (int)(t - r * words_per_row) * 32;   // < nx
+        const int cnt = nx - x0 < 32 ? nx - x0 : 32;
+        const uint8_t *__restrict__ m = mask + r * nx + x0;
+        uint32_t v = cnt < 32 ? ~0u << cnt : 0u;
+        for (int j = 0; j < cnt; ++j) v |= (uint32_t)(m[j] != 0) << j;
+        bits[t] = v;
+    }
+}
+
 // One round of density classification, chained on the device: round r reads
 // the candidate found by round r-1 (words[r-1]; round 0 uses 0), labels the
 // cells whose density equals it with class r-1, and leaves the smallest
@@ -2164,6 +2185,17 @@ hipError_t launch_triad(double *a, const double *b, const double *c, double sc, 
     if (blocks < 1 || blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_triad, dim3((unsigned)blocks), dim3(256), 0, s, a, b, c, sc,
                        (int64_t)n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_mask(const uint8_t *mask, uint32_t *bits, int nx,
+                            int words_per_row, int64_t nwords, hipStream_t s)
+{
+    int64_t blocks = (nwords + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_pack_mask, dim3((unsigned)blocks), dim3(256), 0, s, mask, bits,
+                       nx, words_per_row, nwords);
     return hipGetLastError();
 }
 

@@ -160,6 +160,23 @@ def test_connectivity_check_matches_reference(lib, orc):
         assert got == want, (trial, shape, bc, regions, loose)
         seen[want] += 1
     assert min(seen.values()) > 10, seen
+    # rows longer than one 32-cell word of the packed mask: runs that cross
+    # word boundaries, end on the row's last cell or exactly at a word end
+    seen = {L.OK: 0, L.SINGULAR: 0, L.ESINGULAR: 0}
+    for trial in range(120):
+        nx = (31, 32, 33, 63, 64, 65, 97)[trial % 7]
+        shape = (int(rng.integers(1, 5)), int(rng.integers(1, 5)), nx)
+        dens = 0.04 if trial % 3 == 0 else rng.uniform(0.3, 0.75)   # sparse: one region
+        mask = (rng.random(shape) < dens).astype(np.uint8)
+        if trial % 5 == 0:
+            mask[..., -1] = 0              # fluid up to the row's end
+        bc = kinds[trial % len(kinds)]
+        regions, loose = orc.components(mask, bc)
+        want = L.OK if loose == 0 else (L.SINGULAR if regions == 1 else L.ESINGULAR)
+        got = _connectivity(lib, mask, bc)
+        assert got == want, (trial, shape, bc, regions, loose)
+        seen[want] += 1
+    assert min(seen.values()) > 3, seen
     # periodic x joins the two ends of a row: a hull wall across the middle
     # of a periodic tank leaves one region
     m = np.zeros((4, 3, 8), np.uint8)

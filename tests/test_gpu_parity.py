@@ -274,6 +274,57 @@ def test_binding_refuses_mismatched_arrays(F, torch_dev):
         b.close()
 
 
+def test_device_packed_connectivity_matches_host(orc, torch_dev):
+    """Set-up packs the hull mask into bits on the device for its
+    connectivity check; its verdict equals the host check's (and the
+    reference's region count) on rows of one to three 32-cell words: a
+    layout with an unanchored region among several is refused, a single
+    unanchored region is solved for its mean-free solution, an anchored one
+    plainly."""
+    torch, dev = torch_dev
+    import ctypes
+    from paper_1410_1942_amd import _lib as L
+    from paper_1410_1942_amd.solver import Solver
+    lib = L.load()
+    rng = np.random.default_rng(11)
+    kinds = [(0, 0, 0, 0, 0, 1), (0,) * 6, (2, 2, 0, 0, 0, 0), (1, 0, 0, 0, 0, 0)]
+    seen = set()
+    for trial in range(24):
+        shape = (int(rng.integers(2, 5)), int(rng.integers(2, 5)), (33, 64, 70)[trial % 3])
+        dens = 0.03 if trial % 2 else 0.55
+        mask = (rng.random(shape) < dens).astype(np.uint8)
+        bc = kinds[trial % len(kinds)]
+        nz, ny, nx = shape
+        g = L.Grid(nx, ny, nz, 1.0 / nz)
+        b = L.BC()
+        for f in range(6):
+            b.kind[f] = bc[f]
+        host = lib.pcg_check_connectivity(mask.ctypes.data_as(ctypes.c_void_p),
+                                          ctypes.byref(g), ctypes.byref(b))
+        regions, loose = orc.components(mask, bc)
+        assert host == (L.OK if loose == 0 else L.SINGULAR if regions == 1 else L.ESINGULAR)
+        seen.add(host)
+        _say(f"case connectivity {shape} bc={bc} host={host}")
+        rho = torch.full(shape, 1000.0, dtype=torch.float64, device=dev)
+        m = _to(torch, dev, mask)
+        if host == L.ESINGULAR:
+            with pytest.raises(L.PCGError) as e:
+                Solver(rho, m, bc, 1.0 / nz)
+            assert e.value.code == L.ESINGULAR
+            continue
+        s = Solver(rho, m, bc, 1.0 / nz)
+        try:
+            rhs = _to(torch, dev, rng.standard_normal(shape))
+            p, st = s.solve(rhs, tol=1e-8)
+        finally:
+            s.close()
+        assert st["status"] == 0, (trial, st)
+        pf = p.cpu().numpy()[mask == 0]
+        if host == L.SINGULAR:
+            assert abs(pf.mean()) <= 1e-10 * np.abs(pf).max()
+    assert seen == {L.OK, L.SINGULAR, L.ESINGULAR}, seen
+
+
 def test_errors(F, torch_dev):
     from paper_1410_1942_amd import _lib as L
     case = _two_phase(F, 12, 10, 8, wedge=False)
