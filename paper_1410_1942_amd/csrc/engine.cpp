@@ -944,13 +944,30 @@ struct Engine {
         return PCG_OK;
     }
 
+    // The launches of iteration position w: 0 set-up and residual actions
+    // (K0), 1 pass A (K1), 2 pass B (K2), the last two once per coefficient
+    // mode in use.  With several resident solves the K0 actions ride in the
+    // first K1 launch (kernel position 3): one launch less per iteration.
+    hipError_t launch_position(int w, hipStream_t s)
+    {
+        const bool fused = max_slots > 1 && modes != 0;
+        if (w == 0) return fused ? hipSuccess : launch_iter(prec, 0, 0, grid, d_hdr, d_slots, s);
+        hipError_t e = hipSuccess;
+        bool first = true;
+        for (int m = 0; m < 3 && e == hipSuccess; ++m) {
+            if (!(modes & (1 << m))) continue;
+            const int which = (w == 1 && fused && first) ? 3 : w;
+            first = false;
+            e = launch_iter(prec, which, m, grid, d_hdr, d_slots, s);
+        }
+        return e;
+    }
+
     // One iteration: K0, then K1 and K2 of each coefficient mode in use.
     hipError_t launch_iteration(hipStream_t s)
     {
-        hipError_t e = launch_iter(prec, 0, 0, grid, d_hdr, d_slots, s);
-        for (int w = 1; w < 3 && e == hipSuccess; ++w)
-            for (int m = 0; m < 3 && e == hipSuccess; ++m)
-                if (modes & (1 << m)) e = launch_iter(prec, w, m, grid, d_hdr, d_slots, s);
+        hipError_t e = hipSuccess;
+        for (int w = 0; w < 3 && e == hipSuccess; ++w) e = launch_position(w, s);
         return e;
     }
 
@@ -967,9 +984,7 @@ struct Engine {
         HIP_TRY(hipEventRecord(ev[0], stream));
         for (int i = 0; i < check_every; ++i)
             for (int w = 0; w < 3; ++w) {
-                for (int m = 0; m < 3; ++m)
-                    if (w == 0 ? m == 0 : (modes & (1 << m)) != 0)
-                        HIP_TRY(launch_iter(prec, w, m, grid, d_hdr, d_slots, stream));
+                HIP_TRY(launch_position(w, stream));
                 HIP_TRY(hipEventRecord(ev[3 * i + w + 1], stream));
             }
         HIP_TRY(hipEventSynchronize(ev[ne - 1]));

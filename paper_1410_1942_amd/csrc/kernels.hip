@@ -1539,8 +1539,11 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
 // update).  K0 and K1 serve disjoint sets of first-half actions, so a slot
 // is worked on by exactly one of them; keeping the rare actions out of K1
 // keeps its register footprint (and so its occupancy) that of pass A alone.
-// K1 and K2 come in two coefficient modes (density, classes), each serving
-// only the slots of its mode; K0 serves both.
+// K1 and K2 come in three coefficient modes (density, classes, cut cells),
+// each serving only the slots of its mode; K0 serves all.  Position 3 is K0
+// and K1 of one mode in a single launch, for resident batches: the launch
+// saved per iteration matters there, and their grid of two workgroups per
+// CU leaves room for the larger register footprint.
 // Coefficient mode of a slot: 0 per-cell density, 1 density classes,
 // 2 per-cell density with free-slip cut cells (area/volume fractions).
 __device__ __forceinline__ int slot_mode(const Slot &S)
@@ -1566,12 +1569,24 @@ __device__ __forceinline__ void run_k0_ir(int ph, const Slot &S, const SlotState
     else if (ph == K1_IR_RESID) body_ir_resid(S, st, lt, cf, cf32, acc);
 }
 
+// First-half actions outside pass A (set-up, FP64 residuals, flushes).
+__device__ __forceinline__ bool k0_phase(int ph)
+{
+    return ph == K1_INIT64 || ph == K1_CHECK64 || ph == K1_IR_INIT ||
+           ph == K1_IR_RESID || ph == K1_MEAN_B || ph == K1_MEAN_X || ph == K1_FLUSH_X;
+}
+
 template <int FAMILY, int WHICH, int MODE>
 __device__ __forceinline__ void run_body(int ph, const Slot &S,
                                          const SlotState &st, int64_t lt,
                                          const double *tab64, const float *tab32,
                                          double (&acc)[3])
 {
+    if (WHICH == 3) {   // K0 and K1 of MODE in one launch
+        if (k0_phase(ph)) run_body<FAMILY, 0, 0>(ph, S, st, lt, tab64, tab32, acc);
+        else run_body<FAMILY, 1, MODE>(ph, S, st, lt, tab64, tab32, acc);
+        return;
+    }
     const RhoCoef<double> r64{ gp(S.rho64) };
     const ClsCoef<double> c64{ gp(S.cls), tab64 };
     if (WHICH == 0) {
@@ -1652,12 +1667,10 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
 template <int WHICH, int MODE>
 __device__ __forceinline__ bool serves(const Slot &S, int ph)
 {
-    if (WHICH == 0)
-        return ph == K1_INIT64 || ph == K1_CHECK64 || ph == K1_IR_INIT ||
-               ph == K1_IR_RESID || ph == K1_MEAN_B || ph == K1_MEAN_X ||
-               ph == K1_FLUSH_X;
+    if (WHICH == 0) return k0_phase(ph);
+    if (WHICH == 3 && k0_phase(ph)) return true;
     if (slot_mode(S) != MODE) return false;
-    if (WHICH == 1) return ph == K1_CG_A || ph == K1_IR_A;
+    if (WHICH == 1 || WHICH == 3) return ph == K1_CG_A || ph == K1_IR_A;
     return ph >= 11 && ph <= 19;
 }
 
@@ -1729,7 +1742,8 @@ k_iter(const BatchHeader *__restrict__ hdr, const Slot *__restrict__ slots)
             cur_ph = S.st->phase;
             cur_served = serves<WHICH, MODE>(S, cur_ph);
             if (cur_served && S.cls) {   // class table of this slot into LDS
-                const bool need64 = FAMILY == PCG_PREC_FP64 || WHICH == 0;
+                const bool need64 = FAMILY == PCG_PREC_FP64 || WHICH == 0 ||
+                                    (WHICH == 3 && k0_phase(cur_ph));
                 const bool need32 = FAMILY == PCG_PREC_FP32_IR;
                 for (int i = threadIdx.x; i < kClasses * kClasses; i += kBlock) {
                     if (need64) s_tab64[i] = gp(S.tab64)[i];
@@ -2090,7 +2104,11 @@ hipError_t launch_iter(int family, int which, int mode, int grid,
 #define PCG_LAUNCH(F, W, M) hipLaunchKernelGGL((k_iter<F, W, M>), g, b, 0, s, hdr, slots)
     if (family == PCG_PREC_FP64) {
         if (which == 0) PCG_LAUNCH(PCG_PREC_FP64, 0, 0);
-        else if (which == 1) {
+        else if (which == 3) {
+            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP64, 3, 2);
+            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP64, 3, 1);
+            else PCG_LAUNCH(PCG_PREC_FP64, 3, 0);
+        } else if (which == 1) {
             if (mode == 2) PCG_LAUNCH(PCG_PREC_FP64, 1, 2);
             else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP64, 1, 1);
             else PCG_LAUNCH(PCG_PREC_FP64, 1, 0);
@@ -2101,7 +2119,11 @@ hipError_t launch_iter(int family, int which, int mode, int grid,
         }
     } else {
         if (which == 0) PCG_LAUNCH(PCG_PREC_FP32_IR, 0, 0);
-        else if (which == 1) {
+        else if (which == 3) {
+            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP32_IR, 3, 2);
+            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 3, 1);
+            else PCG_LAUNCH(PCG_PREC_FP32_IR, 3, 0);
+        } else if (which == 1) {
             if (mode == 2) PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 2);
             else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 1);
             else PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 0);
