@@ -364,9 +364,12 @@ int pcg_batch_footprint(const pcg_batch_t *b, const pcg_grid_t *grid,
 
 /*
  * Admit one solve.  rho, mask (NULL = none) are read during the call;
- * rhs and p must stay valid until the solve is released.  Returns PCG_EBUSY
- * when the footprint does not fit in the free arena space or no slot is
- * free, and validation errors as pcg_setup.  On success *slot names it.
+ * rhs and p must stay valid until the solve is released.  flags: any of
+ * PCG_WARM_START, PCG_SKIP_CONNECTIVITY_CHECK and PCG_NO_DENSITY_CLASSES,
+ * with their pcg_setup / pcg_solve_ex meanings; others are PCG_EINVAL.
+ * Returns PCG_EBUSY when the footprint does not fit in the free arena space
+ * or no slot is free, and validation errors as pcg_setup.  On success *slot
+ * names it.
  */
 int pcg_batch_admit(pcg_batch_t *b, const pcg_grid_t *grid, const double *rho,
                     const uint8_t *mask, const pcg_bc_t *bc, const double *rhs,

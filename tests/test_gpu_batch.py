@@ -25,8 +25,8 @@ def torch_dev():
 
 
 class Req:
-    def __init__(self, torch, dev, case, tol):
-        self.case, self.tol = case, tol
+    def __init__(self, torch, dev, case, tol, flags=0):
+        self.case, self.tol, self.flags = case, tol, flags
         self.rho = torch.from_numpy(case.rho).to(dev)
         self.mask = torch.from_numpy(case.mask).to(dev)
         self.rhs = torch.from_numpy(case.rhs).to(dev)
@@ -57,7 +57,7 @@ def _run_batch(torch_dev, reqs, precision, arena=1 << 30, max_slots=64,
             i = pending.pop(0)
             r = reqs[i]
             code, s = b.admit(r.rho, r.mask, r.case.bc, r.case.h, r.rhs, r.p,
-                              tol=r.tol)
+                              tol=r.tol, flags=r.flags)
             assert code == L.OK, code
             slots[i] = s
     assert not pending
@@ -76,7 +76,7 @@ def _run_batch(torch_dev, reqs, precision, arena=1 << 30, max_slots=64,
 
 def _solo(torch_dev, req, precision, **kw):
     torch, dev = torch_dev
-    r2 = Req(torch, dev, req.case, req.tol)
+    r2 = Req(torch, dev, req.case, req.tol, req.flags)
     st = _run_batch(torch_dev, [r2], precision, max_slots=1, **kw)[0]
     return r2.p.cpu().numpy(), st
 
@@ -115,6 +115,30 @@ def test_staggered_admission_and_mixed_tolerances(orc, F, torch_dev):
         rr = orc.relres(r.case.rho, r.case.mask, r.case.bc, r.case.h, r.case.rhs, p)
         assert rr <= r.tol
         alone, _ = _solo(torch_dev, r, 1)
+        assert np.array_equal(alone, p), i
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "ir"])
+def test_mixed_coefficient_modes(orc, F, torch_dev, precision):
+    """Solves coded by density class and solves reading per-cell densities
+    in one batch: the set-up and residual actions of every slot run in the
+    first coefficient mode's launch, pass A and B in each slot's own.  Each
+    result is bitwise its solo run's (a batch of one launches the set-up
+    actions on their own)."""
+    torch, dev = torch_dev
+    from paper_1410_1942_amd import _lib as L
+    cases = _members(F, range(20, 26), lo=18, hi=44)
+    reqs = [Req(torch, dev, c, 1e-8, L.NO_DENSITY_CLASSES if i % 2 else 0)
+            for i, c in enumerate(cases)]
+    _say(f"mixed modes precision={precision}: " + " ".join(str(c.shape) for c in cases))
+    stats = _run_batch(torch_dev, reqs, precision, stagger=[(0, 2), (3, 2), (2, 2)])
+    for i, r in enumerate(reqs):
+        assert stats[i]["status"] == 0, (i, stats[i])
+        p = r.p.cpu().numpy()
+        rr = orc.relres(r.case.rho, r.case.mask, r.case.bc, r.case.h, r.case.rhs, p)
+        assert rr <= 1e-8, (i, rr)
+        alone, st1 = _solo(torch_dev, r, precision)
+        assert st1["iters"] == stats[i]["iters"], (i, st1, stats[i])
         assert np.array_equal(alone, p), i
 
 
