@@ -89,9 +89,6 @@ constexpr size_t kAlign = 256;
 constexpr int kDefaultCheckEvery = 32;
 constexpr int kDefaultGridMax = 1024;
 constexpr int kBatchGrid = 512;
-// single solves up to this many cells launch K0 inside K1 (iterations of a
-// few tens of microseconds, where a launch is a large share)
-constexpr int64_t kFuseMaxCells = int64_t(1) << 22;
 constexpr double kDefaultInnerTol = 1e-4;
 // largest byte span pass A addresses within one tile (32-bit offsets)
 constexpr int64_t kMaxTileBytes = 0xffffffffll;
@@ -487,7 +484,6 @@ struct Engine {
     int modes = 0;          // bit m: a running slot uses coefficient mode m
                             // (0 densities, 1 classes, 2 densities + fractions)
     int graph_modes = -1;   // modes the captured graph was built for
-    bool fuse_k0 = false;   // K0 actions ride in the first K1 launch
     // timing mode
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -927,30 +923,13 @@ struct Engine {
         return g;
     }
 
-    // K0 actions in the first K1 launch (kernel position 3): always with
-    // several resident solves; for one solve when it is small, so its
-    // iterations are launch-bound, and its grid is at most two workgroups
-    // per CU, which the fused kernel's register footprint allows.  Large
-    // single solves keep K0 apart: their pass A runs at its own footprint.
-    bool want_fused(int g) const
-    {
-        if (modes == 0) return false;
-        if (max_slots > 1) return true;
-        int64_t n = 0;
-        for (auto &S : slots)
-            if (S.used) n = S.geo.n;
-        return g <= kBatchGrid && n <= kFuseMaxCells;
-    }
-
     int capture()
     {
         const int g = choose_grid();
-        const bool f = want_fused(g);
-        if (exec && g == grid && modes == graph_modes && f == fuse_k0) return PCG_OK;
+        if (exec && g == grid && modes == graph_modes) return PCG_OK;
         if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
         if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
         grid = g;
-        fuse_k0 = f;
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
         for (int i = 0; i < check_every && err == hipSuccess; ++i)
@@ -965,25 +944,25 @@ struct Engine {
         return PCG_OK;
     }
 
-    // The launches of iteration position w: 0 set-up and residual actions
-    // (K0), 1 pass A (K1), 2 pass B (K2), the last two once per coefficient
-    // mode in use; with fuse_k0 the K0 actions ride in the first K1 launch.
+    // The launches of iteration position w, once per coefficient mode in
+    // use: 1 the first-half actions (K1: pass A; the first mode's launch,
+    // kernel position 3, also serves every slot's set-up, FP64 residual and
+    // flush actions), 2 pass B (K2).  Position 0 launches nothing: a kernel
+    // boundary of its own measured 1-12 % of an iteration (512^3 .. 160^3).
     hipError_t launch_position(int w, hipStream_t s)
     {
-        const bool fused = fuse_k0;
-        if (w == 0) return fused ? hipSuccess : launch_iter(prec, 0, 0, grid, d_hdr, d_slots, s);
         hipError_t e = hipSuccess;
+        if (w == 0) return e;
         bool first = true;
         for (int m = 0; m < 3 && e == hipSuccess; ++m) {
             if (!(modes & (1 << m))) continue;
-            const int which = (w == 1 && fused && first) ? 3 : w;
+            e = launch_iter(prec, (w == 1 && first) ? 3 : w, m, grid, d_hdr, d_slots, s);
             first = false;
-            e = launch_iter(prec, which, m, grid, d_hdr, d_slots, s);
         }
         return e;
     }
 
-    // One iteration: K0, then K1 and K2 of each coefficient mode in use.
+    // One iteration: K1, then K2, of each coefficient mode in use.
     hipError_t launch_iteration(hipStream_t s)
     {
         hipError_t e = hipSuccess;

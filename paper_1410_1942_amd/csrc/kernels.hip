@@ -1534,16 +1534,18 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
 // launch skeleton
 // ------------------------------------------------------------------------
 
-// Launch positions of an iteration: K0 (rare first-half actions: set-up and
-// FP64 residuals), K1 (direction update), K2 (operator apply and vector
-// update).  K0 and K1 serve disjoint sets of first-half actions, so a slot
-// is worked on by exactly one of them; keeping the rare actions out of K1
-// keeps its register footprint (and so its occupancy) that of pass A alone.
-// K1 and K2 come in three coefficient modes (density, classes, cut cells),
-// each serving only the slots of its mode; K0 serves all.  Position 3 is K0
-// and K1 of one mode in a single launch, for resident batches: the launch
-// saved per iteration matters there, and their grid of two workgroups per
-// CU leaves room for the larger register footprint.
+// An iteration is two launches per coefficient mode in use: the first-half
+// actions, then K2 (operator apply and vector update).  The first-half
+// actions are pass A (K1, per mode) and the rare ones (set-up, FP64
+// residuals, flushes: the "K0" actions, any mode); kernel position 3 serves
+// both for one mode and the K0 actions of every slot, position 1 pass A
+// alone for the other modes in use.  A slot is in exactly one first-half
+// phase, so it is worked on by exactly one launch.  Position 0 (the K0
+// actions alone) is kept for the body dispatch but not launched: a kernel
+// boundary of its own cost more than the fused kernel's larger register
+// footprint (at most 232 VGPRs, two waves per SIMD, what the grids of two
+// workgroups per CU use).  K1 and K2 come in three coefficient modes
+// (density, classes, cut cells), each serving only the slots of its mode.
 // Coefficient mode of a slot: 0 per-cell density, 1 density classes,
 // 2 per-cell density with free-slip cut cells (area/volume fractions).
 __device__ __forceinline__ int slot_mode(const Slot &S)
@@ -2103,8 +2105,7 @@ hipError_t launch_iter(int family, int which, int mode, int grid,
     const dim3 g(grid), b(kBlock);
 #define PCG_LAUNCH(F, W, M) hipLaunchKernelGGL((k_iter<F, W, M>), g, b, 0, s, hdr, slots)
     if (family == PCG_PREC_FP64) {
-        if (which == 0) PCG_LAUNCH(PCG_PREC_FP64, 0, 0);
-        else if (which == 3) {
+        if (which == 3) {
             if (mode == 2) PCG_LAUNCH(PCG_PREC_FP64, 3, 2);
             else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP64, 3, 1);
             else PCG_LAUNCH(PCG_PREC_FP64, 3, 0);
@@ -2118,8 +2119,7 @@ hipError_t launch_iter(int family, int which, int mode, int grid,
             else PCG_LAUNCH(PCG_PREC_FP64, 2, 0);
         }
     } else {
-        if (which == 0) PCG_LAUNCH(PCG_PREC_FP32_IR, 0, 0);
-        else if (which == 3) {
+        if (which == 3) {
             if (mode == 2) PCG_LAUNCH(PCG_PREC_FP32_IR, 3, 2);
             else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 3, 1);
             else PCG_LAUNCH(PCG_PREC_FP32_IR, 3, 0);

@@ -34,10 +34,8 @@ def kernel_stats(path: str) -> str:
                        f"{float(r['MaxNs'])/1e6:10.4f} {float(r['TotalDurationNs'])/1e9:9.3f} "
                        f"{float(r['Percentage']):6.2f}")
         return "\n".join(out)
-    # *_kernel_trace.csv: aggregate ourselves; `large` averages the launches
-    # of at least a quarter of the longest one (the largest problem's
-    # launches, every form of a kernel whose launches vary; not the empty launches
-    # at the end of a captured chunk nor those of smaller problems)
+    # *_kernel_trace.csv: aggregate ourselves; `large` averages the typical
+    # launches of the problem launched most (see _large)
     agg = collections.defaultdict(list)
     for r in rows:
         agg[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
@@ -51,10 +49,15 @@ def kernel_stats(path: str) -> str:
     return "\n".join(out)
 
 
-def _large(values, share=0.25):
-    """The values of at least `share` of the largest."""
-    top = max(values)
-    return [v for v in values if v >= share * top]
+def _large(values, lo=0.25, hi=3.0):
+    """The values within [lo, hi] times the median: the launches of the
+    problem a run launches most (its median), every form of a kernel whose
+    launches alternate (pass B with and without the x update, within a
+    factor of about 2.3 of each other); not the empty launches at the end
+    of a captured chunk, those of much smaller problems, nor the rare
+    set-up and residual launches of the first-half kernel."""
+    med = statistics.median(values)
+    return [v for v in values if lo * med <= v <= hi * med]
 
 
 def _counter(path: str):
@@ -78,9 +81,10 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
     sf, sw = copy_bytes / f_copy, copy_bytes / w_copy
     lines = [f"# FETCH_SIZE scale {sf:.4f}, WRITE_SIZE scale {sw:.4f} "
              f"(copy kernel: {copy_bytes} B read and written per launch)",
-             f"# per launch, mean over the launches fetching at least a quarter of the "
-             f"largest (empty launches at the end of a captured chunk excluded; both forms "
-             f"of pass B, with and without the x update, kept); cells = {cells}"]
+             f"# per launch, mean over the launches within a quarter to three times the "
+             f"median (empty launches at the end of a captured chunk and the rare set-up "
+             f"launches excluded; both forms of pass B, with and without the x update, "
+             f"kept); cells = {cells}"]
     if sha:
         lines.append(f"kernel_source_sha = {sha}")
     lines.append(f"{'kernel':58s} {'n':>4s} {'fetch_B':>14s} {'write_B':>14s} "
