@@ -49,7 +49,7 @@ def kernel_stats(path: str) -> str:
     return "\n".join(out)
 
 
-def _large(values, lo=0.25, hi=3.0):
+def _large(values, lo=0.5, hi=3.0):
     """The values within [lo, hi] times the median: the launches of the
     problem a run launches most (its median), every form of a kernel whose
     launches alternate (pass B with and without the x update, within a
@@ -81,7 +81,7 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
     sf, sw = copy_bytes / f_copy, copy_bytes / w_copy
     lines = [f"# FETCH_SIZE scale {sf:.4f}, WRITE_SIZE scale {sw:.4f} "
              f"(copy kernel: {copy_bytes} B read and written per launch)",
-             f"# per launch, mean over the launches within a quarter to three times the "
+             f"# per launch, mean over the launches within half to three times the "
              f"median (empty launches at the end of a captured chunk and the rare set-up "
              f"launches excluded; both forms of pass B, with and without the x update, "
              f"kept); cells = {cells}"]
