@@ -112,13 +112,13 @@ struct TileRule {
 
 // Built-in table: the autotuner's choice on gfx950 (package tile_table.json).
 std::vector<TileRule> g_rules[2] = {  // single solves: FP64, FP32+IR
-    { { 7524, 4, 1024 }, { 21283, 2, 512 }, { 60198, 8, 1024 }, { 170267, 4, 2048 }, { 481589, 8, 2048 }, { 1362140, 8, 768 }, { 3852714, 16, 2048 }, { 10897121, 64, 768 }, { 30821713, 64, 768 }, { 87176971, 32, 512 }, { INT64_MAX, 256, 512 } },
-    { { 7524, 2, 2048 }, { 21283, 2, 768 }, { 60198, 2, 2048 }, { 170267, 2, 512 }, { 481589, 4, 768 }, { 1362140, 8, 512 }, { 3852714, 16, 512 }, { 10897121, 32, 512 }, { 30821713, 16, 512 }, { 87176971, 16, 512 }, { INT64_MAX, 256, 768 } },
+    { { 7524, 2, 256 }, { 21283, 2, 256 }, { 60198, 4, 1024 }, { 170267, 4, 768 }, { 481589, 8, 1024 }, { 1362140, 16, 2048 }, { 3852714, 16, 768 }, { 10897121, 64, 512 }, { 30821713, 128, 768 }, { 87176971, 32, 512 }, { INT64_MAX, 256, 512 } },
+    { { 7524, 2, 256 }, { 21283, 2, 1024 }, { 60198, 2, 2048 }, { 170267, 4, 768 }, { 481589, 4, 1024 }, { 1362140, 8, 256 }, { 3852714, 16, 256 }, { 10897121, 32, 768 }, { 30821713, 32, 768 }, { 87176971, 16, 512 }, { INT64_MAX, 256, 1024 } },
 };
 
 // Batches: longer tiles (the resident solves fill the device together).
 std::vector<TileRule> g_rules_batch[2] = {
-    { { 7524, 8, 0 }, { 21283, 16, 0 }, { 60198, 16, 0 }, { 170267, 32, 0 }, { 481589, 16, 0 }, { 1362140, 32, 0 }, { 3852714, 16, 0 }, { INT64_MAX, 64, 0 } },
+    { { 7524, 8, 0 }, { 21283, 16, 0 }, { 60198, 16, 0 }, { 170267, 32, 0 }, { 481589, 32, 0 }, { 1362140, 32, 0 }, { 3852714, 16, 0 }, { INT64_MAX, 64, 0 } },
     { { 7524, 8, 0 }, { 21283, 8, 0 }, { 60198, 8, 0 }, { 170267, 16, 0 }, { 481589, 16, 0 }, { 1362140, 16, 0 }, { 3852714, 16, 0 }, { INT64_MAX, 32, 0 } },
 };
 

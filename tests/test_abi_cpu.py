@@ -290,3 +290,23 @@ def test_fraction_flag_host_rules(lib):
     assert lib.pcg_batch_create(ctypes.byref(b), ctypes.c_void_p(0x1000), 1 << 20, 2,
                                 ctypes.byref(o), None) == L.EINVAL
     assert lib.pcg_set_fractions(None, None, None, None, None) == L.EINVAL
+
+
+def test_built_in_tile_rules_match_the_shipped_table():
+    """The library's built-in rules (used when no table is installed) are
+    the autotuner's table shipped with the package."""
+    import json
+    import subprocess
+    import sys
+    code = ("import json; from paper_1410_1942_amd import autotune, _lib as L; "
+            "print(json.dumps({k: [list(r) for r in autotune.get_rules(p, b)] "
+            "for k, p, b in (('fp64', L.PREC_FP64, False), ('fp32_ir', L.PREC_FP32_IR, False), "
+            "('fp64_batch', L.PREC_FP64, True), ('fp32_ir_batch', L.PREC_FP32_IR, True))}))")
+    env = dict(os.environ, PCGMI_TILE_TABLE="none")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, check=True,
+                         capture_output=True, text=True).stdout
+    built_in = json.loads(out.strip().splitlines()[-1])
+    table = json.load(open(os.path.join(ROOT, "paper_1410_1942_amd", "tile_table.json")))["gfx950"]
+    unbounded = lambda rules: [[None if r[0] >= 2**62 else r[0], r[1], r[2]] for r in rules]
+    for k, rules in built_in.items():
+        assert unbounded(rules) == unbounded(table[k]), k
