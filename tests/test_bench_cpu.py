@@ -1,0 +1,29 @@
+"""bench.py's contract that needs no GPU: more than one GPU is refused with
+a message before any device work, and the committed counter summary that
+feeds the roofline's traffic field parses."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+def test_committed_traffic_summary_parses():
+    sys.path.insert(0, ROOT)
+    import bench
+    tr = bench.read_traffic(os.path.join(ROOT, "profiles", "traffic_wedge512.txt"))
+    assert tr is not None
+    assert len(tr["kernel_source_sha"]) == 16
+    # pass B with density classes, the kernel the roofline reports
+    assert float(tr["bytes[k_iter<0, 2, 1>]"]) > 0
+    # the kernel-trace summary gives the command it came from
+    stats = open(os.path.join(ROOT, "profiles", "kernel_stats_wedge512.txt")).read()
+    assert "rocprofv3 --kernel-trace --stats" in stats and "k_iter<0, 2, 1>" in stats
