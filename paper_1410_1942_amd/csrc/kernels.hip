@@ -16,6 +16,8 @@
 //   pass A:  p = z + beta p                 and  p.Ap = sum_f beta_f (dp_f)^2
 //   pass B:  q = A p (recomputed), x += alpha p, z -= alpha q / diag
 //            r.z = sum diag z^2,  r.r = sum (diag z)^2
+// where x += alpha p is applied every third pass B, the two deferred
+// updates first and in order (the directions rotate through three buffers).
 // Each pass is one HBM sweep; the two global reductions per iteration are
 // per-tile partial sums written to memory and added in tile order by the
 // last workgroup to arrive, which also advances the solve's state machine.

@@ -36,8 +36,8 @@ enum Phase : int32_t {
     K1_FLUSH_X = 9,    // x += alpha p: the updates the last iterations left pending
     // K2 actions (second launch of an iteration)
     K2_NONE = 11,      // nothing; then the K1 action in `after`
-    K2_CG_B = 12,      // q = A p, x += alpha p, z -= alpha D^-1 q ; r.z, r.r
-    K2_IR_B = 13,      // FP32 q = A p, d += alpha p (two at a time), z -= alpha D^-1 q ; r.z, r.r (FP64)
+    K2_CG_B = 12,      // q = A p, x += alpha p (three at a time), z -= alpha D^-1 q ; r.z, r.r
+    K2_IR_B = 13,      // FP32 q = A p, d += alpha p (three at a time), z -= alpha D^-1 q ; r.z, r.r (FP64)
     K2_IR_UPDATE = 14, // x += s d, d = 0
     K2_ZERO_X = 15,    // x = 0 (zero source with a warm start)
     K2_SUB_X = 16,     // singular problem: x -= its fluid mean
