@@ -50,3 +50,81 @@ def test_wedge_512_fp64_and_ir(orc, F):
     err = np.abs(out["fp32+ir"] - out["fp64"]).max() / np.abs(out["fp64"]).max()
     _say(f"  max |p_ir - p_fp64| / max |p_fp64| = {err:.3e}")
     assert err <= 1e-6, err
+
+
+def _batch_run(reqs, max_slots):
+    """Admit every request into one batch of max_slots and step to the end;
+    returns the statuses."""
+    import torch
+    from paper_1410_1942_amd import _lib as L
+    from paper_1410_1942_amd.solver import Batch
+    probe = Batch(1 << 20, 1, precision=L.PREC_FP32_IR)
+    need = sum(probe.footprint(tuple(r.rho.shape), r.h) for r in reqs) + (16 << 20)
+    probe.close()
+    b = Batch(need, max_slots, precision=L.PREC_FP32_IR)
+    try:
+        slots = []
+        for r in reqs:
+            r.p = torch.empty_like(r.rhs)
+            code, s = b.admit(r.rho, r.mask, r.bc, r.h, r.rhs, r.p, tol=r.tol)
+            assert code == L.OK, code
+            slots.append(s)
+        while b.step(1):
+            pass
+        sts = [b.poll(s)[1] for s in slots]
+        torch.cuda.synchronize()
+    finally:
+        b.close()
+    return sts
+
+
+def test_batch_of_64_full_size(orc, F):
+    """The benchmark's batch: 64 solves with edges log-uniform in [16, 128],
+    FP32+IR to 1e-8, in one resident batch.  Each meets the reference's
+    residual; the smallest, the median and the largest equal their solo
+    runs (a batch of one) bit for bit."""
+    import torch
+    from paper_1410_1942_amd import serve
+    assert torch.cuda.is_available()
+    cases = [(F.batch_member(i, keep_velocity=False), 1e-8) for i in range(64)]
+    reqs = serve.make_requests(cases, [0.0] * 64)
+    _say("case batch of 64: " + " ".join("x".join(map(str, c.shape)) for c, _ in cases[:8]) + " ...")
+    sts = _batch_run(reqs, 64)
+    for i, ((case, tol), r, st) in enumerate(zip(cases, reqs, sts)):
+        assert st["status"] == 0, (i, st)
+        rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, r.p.cpu().numpy())
+        assert rr <= tol, (i, rr)
+    order = sorted(range(64), key=lambda i: reqs[i].cells)
+    for i in (order[0], order[32], order[-1]):
+        _say(f"  solo run of member {i} ({reqs[i].cells} cells)")
+        solo = serve.make_requests([cases[i]], [0.0])
+        st1 = _batch_run(solo, 1)[0]
+        assert st1["iters"] == sts[i]["iters"], (i, st1, sts[i])
+        assert torch.equal(solo[0].p, reqs[i].p), i
+
+
+def test_served_requests_full_size(orc, F):
+    """The served recipe at its real sizes (edges log-uniform in [24, 192],
+    a wedge hull on half of the requests, tolerance 1e-6 or 1e-8): 40
+    requests through the server, all waiting at the start.  Each meets its
+    own tolerance by the reference's residual, hull cells 0."""
+    import torch
+    from paper_1410_1942_amd import serve
+    assert torch.cuda.is_available()
+    cases = [F.served_request(i, keep_velocity=False) for i in range(40)]
+    assert any(c.mask.any() for c, _ in cases) and not all(c.mask.any() for c, _ in cases)
+    reqs = serve.make_requests(cases, [0.0] * 40)
+    _say("case served 40: largest " + str(max(c.shape for c, _ in cases)))
+    srv = serve.Server(24 << 30, max_slots=64)
+    try:
+        srv.run(reqs, realtime=False)
+    finally:
+        srv.close()
+    torch.cuda.synchronize()
+    for i, ((case, tol), r) in enumerate(zip(cases, reqs)):
+        assert r.status == 0, (i, r.status)
+        p = r.p.cpu().numpy()
+        rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p)
+        assert rr <= tol, (i, rr, tol)
+        if case.mask is not None:
+            assert not p[case.mask.astype(bool)].any()
