@@ -40,13 +40,27 @@ def kernel_stats(path: str) -> str:
     for r in rows:
         agg[r["Kernel_Name"]].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     out.append(f"{'kernel':70s} {'calls':>7s} {'avg_ms':>10s} {'median_ms':>10s} "
-               f"{'large_n':>8s} {'large_avg_ms':>12s} {'total_s':>9s}")
+               f"{'large_n':>8s} {'large_avg_ms':>12s} {'short_n':>8s} {'short_ms':>9s} "
+               f"{'long_n':>7s} {'long_ms':>8s} {'total_s':>9s}")
     for k, v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
         big = _large(v)
+        (sn, sm), (ln, lm) = _two_forms(big)
         out.append(f"{_short(k):70s} {len(v):7d} {statistics.mean(v)/1e6:10.4f} "
                    f"{statistics.median(v)/1e6:10.4f} {len(big):8d} "
-                   f"{statistics.mean(big)/1e6:12.4f} {sum(v)/1e9:9.3f}")
+                   f"{statistics.mean(big)/1e6:12.4f} {sn:8d} {sm/1e6:9.4f} "
+                   f"{ln:7d} {lm/1e6:8.4f} {sum(v)/1e9:9.3f}")
     return "\n".join(out)
+
+
+def _two_forms(values):
+    """Count and mean of the launches below and above the midpoint of the
+    range: the two forms of pass B (without and with the x update); a
+    kernel with one form splits into two near-equal halves."""
+    lo, hi = min(values), max(values)
+    mid = 0.5 * (lo + hi)
+    a = [v for v in values if v <= mid]
+    b = [v for v in values if v > mid] or a
+    return (len(a), statistics.mean(a)), (len(b), statistics.mean(b))
 
 
 def _large(values, lo=0.5, hi=3.0):
