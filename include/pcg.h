@@ -384,12 +384,29 @@ int pcg_batch_admit(pcg_batch_t *b, const pcg_grid_t *grid, const double *rho,
  */
 int pcg_batch_step(pcg_batch_t *b, int32_t replays, int32_t *active_out);
 
-/* Status of one solve: PCG_PENDING while running, else its final code. */
+/*
+ * Status of one admitted solve, as of the last pcg_batch_step: returns
+ * PCG_PENDING while it runs, else its final code (PCG_OK, PCG_MAXIT or an
+ * error), and fills *stats (host; may be NULL) with its iterations, outer
+ * trips, residuals and wall time (status PCG_PENDING and zeros while it
+ * runs).  A finished solve's p holds its result.  PCG_EINVAL for a null
+ * batch or a slot that is not admitted.
+ */
 int pcg_batch_poll(pcg_batch_t *b, int32_t slot, pcg_stats_t *stats);
 
-/* Free a slot and its arena space (finished or not). */
+/*
+ * Free a slot and its arena space, finished or not (a running solve is
+ * dropped: its p is left as the last step wrote it).  The slot number may
+ * be reused by a later admission.  PCG_EINVAL for a null batch or a slot
+ * that is not admitted.
+ */
 int pcg_batch_release(pcg_batch_t *b, int32_t slot);
 
+/*
+ * Wait for the batch's stream, then free the batch and its host and graph
+ * resources; the arena belongs to the caller and is not freed.  NULL is
+ * accepted.
+ */
 int pcg_batch_destroy(pcg_batch_t *b);
 
 /* ---- tile shapes ------------------------------------------------------- */
