@@ -328,7 +328,8 @@ int pcg_update_density(pcg_ctx_t *ctx, const double *rho, const uint8_t *solid_m
 int pcg_divergence(pcg_ctx_t *ctx, const double *u, const double *v,
                    const double *w, double *out);
 
-/* Release the context (not the workspace).  NULL is accepted. */
+/* Wait for the context's stream, then release the context (not the
+ * workspace).  NULL is accepted. */
 int pcg_destroy(pcg_ctx_t *ctx);
 
 /* Static text for a status code. */

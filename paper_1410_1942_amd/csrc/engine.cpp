@@ -493,6 +493,9 @@ struct Engine {
 
     void teardown()
     {
+        // copies staged through the pinned host buffers may still be queued
+        // on the caller's stream: let them finish before the buffers go
+        if (h_hdr || h_slots || h_states || h_bad) (void)hipStreamSynchronize(stream);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         exec = nullptr;
@@ -1455,8 +1458,7 @@ int pcg_batch_release(pcg_batch_t *b, int32_t slot)
 
 int pcg_batch_destroy(pcg_batch_t *b)
 {
-    if (b) (void)hipStreamSynchronize(b->eng.stream);
-    delete b;
+    delete b;   // the engine waits for its stream first
     return PCG_OK;
 }
 
