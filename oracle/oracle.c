@@ -332,29 +332,45 @@ int oracle_apply(int nx, int ny, int nz, double h, const double *rho,
 }
 
 /*
- * Relative residual of the scaled SPD system, ||b - A p||_2 / ||b||_2 over
- * fluid cells, i.e. ||V (Sigma - L p)|| / ||V Sigma|| (without fractions
- * ||Sigma - L p|| / ||Sigma||).
+ * Relative residual of a pressure p for the source Sigma, measured as the
+ * solver measures it: ||w - V L p||_2 / ||w||_2 over fluid cells, with
+ * w = V Sigma the volume-weighted source (w = Sigma without fractions).
+ * When the problem is singular (one fluid region, no Dirichlet face: the
+ * constant is in the null space of L) w first loses its mean over fluid
+ * cells, exactly the source oracle_pcg solves for; hull cells are skipped,
+ * so whatever the caller holds there does not count.  NAN on invalid input.
  */
 double oracle_relres(int nx, int ny, int nz, double h, const double *rho,
                      const uint8_t *solid, const int *bc, const double *rhs,
                      const double *p, const double *ax, const double *ay, const double *az, const double *vol)
 {
     size_t n = (size_t)nx * ny * nz;
+    int loose = 0;
+    int regions = oracle_components(nx, ny, nz, solid, bc, &loose);
+    if (regions < 0) return NAN;
+    int singular = loose == 1 && regions == 1;
     double *Lp = malloc(n * sizeof(double));
     if (!Lp) return NAN;
     if (oracle_apply(nx, ny, nz, h, rho, solid, bc, p, Lp, ax, ay, az, vol) != O_OK) {
         free(Lp);
         return NAN;
     }
+    double mean = 0.0;
+    if (singular) {
+        double sw = 0.0, nf = 0.0;
+        for (size_t c = 0; c < n; ++c)
+            if (!solid[c]) { sw += (vol ? vol[c] : 1.0) * rhs[c]; nf += 1.0; }
+        mean = sw / nf;
+    }
     double rr = 0.0, bb = 0.0;
 #pragma omp parallel for reduction(+ : rr, bb) schedule(static)
     for (long long c = 0; c < (long long)n; ++c) {
         if (solid[c]) continue;
         double v = vol ? vol[c] : 1.0;
-        double r = v * (rhs[c] - Lp[c]);
+        double w = v * rhs[c] - mean;
+        double r = w - v * Lp[c];
         rr += r * r;
-        bb += (v * rhs[c]) * (v * rhs[c]);
+        bb += w * w;
     }
     free(Lp);
     return bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);

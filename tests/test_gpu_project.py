@@ -46,8 +46,9 @@ def test_projection_matches_reference(orc, F, torch_dev, shape, bc, flags):
     assert abs(d0[0] - np.linalg.norm(div0)) <= 1e-12 * np.linalg.norm(div0)
     assert abs(d0[1] - np.abs(div0).max()) <= 1e-12 * np.abs(div0).max()
     assert abs(d1[0] - np.linalg.norm(div1)) <= 1e-6 * np.linalg.norm(div1) + 1e-12 * d0[0]
-    # the projected field is divergence-free to the solve's tolerance
-    assert d1[0] <= 1e-10 * d0[0] * 1.0001
+    # the projected field is divergence-free to the solve's tolerance: its
+    # divergence ratio is the relative residual, recomputed here by the oracle
     rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, pn)
+    assert rr <= 1e-10
     assert abs(d1[0] / d0[0] - rr) <= 1e-3 * rr
     s.close()

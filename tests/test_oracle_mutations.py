@@ -63,6 +63,11 @@ PIN_RUNS = {
     "textbook_iters": lambda o: [pins.test_pcg_iterations_match_textbook(o, _F(), *case)
                                  for case in (((8, 8, 8), (1, 0, 0, 1, 0, 1), True, 11),
                                               ((16, 4, 2), (1, 1, 0, 0, 1, 1), True, 7))],
+    "relres_cut_cells": lambda o: pins.test_relres_cut_cells_by_hand(o),
+    "relres_singular": lambda o: pins.test_relres_singular_by_hand(o),
+    "relres_hull": lambda o: pins.test_relres_ignores_hull_entries(o, _F(), pins.TANK),
+    "relres_vs_pcg": lambda o: pins.test_relres_matches_what_pcg_stops_on(
+        o, _F(), (2, 2, 0, 0, 0, 0), True),
 }
 
 MUTANTS = [
@@ -111,6 +116,17 @@ MUTANTS = [
     # area divergence not divided by the volume fraction
     ("divergence_no_volume", "out[w0] = ax ? (du + dv + dw) / (vc * h) : (du + dv + dw) / h;",
      "out[w0] = (du + dv + dw) / h;"),
+    # residual checker: volume weight dropped
+    ("relres_no_volume", "double v = vol ? vol[c] : 1.0;\n        double w = v * rhs[c] - mean;",
+     "double v = 1.0;\n        double w = v * rhs[c] - mean;"),
+    # residual checker: hull cells counted
+    ("relres_hull_counted", "if (solid[c]) continue;\n        double v = vol",
+     "double v = vol"),
+    # residual checker: singular source keeps its mean
+    ("relres_mean_kept", "mean = sw / nf;", "mean = 0.0 * sw / nf;"),
+    # residual checker: ratio of squared norms
+    ("relres_squared", "return bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);",
+     "return bb > 0.0 ? rr / bb : rr;"),
 ]
 
 

@@ -754,3 +754,140 @@ def test_projection_divergence_with_fractions(orc, F):
     # the source is the generator's area divergence
     np.testing.assert_allclose(orc.source(c.u, c.v, c.w, c.h, c.dt, c.mask, frac=c.frac),
                                c.rhs, rtol=1e-12, atol=1e-12 * np.abs(c.rhs).max())
+
+
+# --------------------------------------------------------------------------
+# the residual checker (relres): Eq. (pois) residual, volume-weighted for cut
+# cells (Section 2.2.1), mean-free source for singular problems
+# --------------------------------------------------------------------------
+
+def test_relres_of_zero_pressure_is_one(orc, F):
+    """p = 0 leaves the whole source as residual, with or without fractions,
+    in anchored and singular problems alike."""
+    rng = np.random.default_rng(41)
+    for bc in (TANK, (2, 2, N, N, N, N)):
+        c = _two_phase_wedge(F, 12, 10, 9, bc=bc)
+        z = np.zeros_like(c.rho)
+        assert orc.relres(c.rho, c.mask, c.bc, c.h, c.rhs, z) == 1.0
+        fr = _random_frac(rng, c.mask)
+        assert orc.relres(c.rho, c.mask, c.bc, c.h, c.rhs, z, frac=fr) == 1.0
+
+
+@pytest.mark.parametrize("case", _gold_cases(), ids=lambda c: c["name"])
+def test_relres_of_hand_solutions(orc, case):
+    """The hand-solved answers leave no residual (to the rounding of their
+    decimal digits)."""
+    shp = (case["nz"], case["ny"], case["nx"])
+    rho = np.array(case["rho"], float).reshape(shp)
+    mask = np.array(case["mask"], np.uint8).reshape(shp)
+    rhs = np.array(case["rhs"], float).reshape(shp)
+    want = np.array(case["p"], float).reshape(shp)
+    assert orc.relres(rho, mask, case["bc"], case["h"], rhs, want) <= 1e-14
+    assert orc.relres(rho, mask, case["bc"], case["h"], rhs, 0.5 * want) > 0.1
+
+
+def test_relres_cut_cells_by_hand(orc):
+    """A two-cell water column (rho = 1, h = 1, p = 0 on top, Neumann
+    elsewhere), lower cell of volume fraction 1/2, all faces open.  For
+    p = (1, 0) the finite-volume rows give sum_f A beta (p_c - p_n) = (1, -1),
+    so L p = -(1, -1) / V = (-2, 1).  With Sigma = (2, 4) the weighted
+    residual V (Sigma - L p) is (0.5 * 4, 1 * 3) = (2, 3) against the
+    weighted source V Sigma = (1, 4): relres = sqrt(13 / 17).  (Dropping V
+    would give sqrt(25 / 20).)"""
+    rho = np.ones((2, 1, 1))
+    mask = np.zeros((2, 1, 1), np.uint8)
+    frac = (np.ones((2, 1, 2)), np.ones((2, 2, 1)), np.ones((3, 1, 1)),
+            np.array([0.5, 1.0]).reshape(2, 1, 1))
+    rhs = np.array([2.0, 4.0]).reshape(2, 1, 1)
+    p = np.array([1.0, 0.0]).reshape(2, 1, 1)
+    rr = orc.relres(rho, mask, TANK, 1.0, rhs, p, frac=frac)
+    assert abs(rr - math.sqrt(13.0 / 17.0)) <= 1e-15
+
+
+def test_relres_singular_by_hand(orc):
+    """Two cells in a row, every wall Neumann (singular: constants are in
+    the null space).  L p = (p1 - p0, p0 - p1); the source (3, 1) is solved
+    with its mean removed, (1, -1).  p = (0, 1) solves it exactly; p = (0, 2)
+    leaves (-1, 1), as large as the mean-free source; p = 0 leaves all of
+    it.  (Keeping the mean would give sqrt(8 / 10) for p = (0, 1).)"""
+    rho = np.ones((1, 1, 2))
+    mask = np.zeros((1, 1, 2), np.uint8)
+    bc = (N, N, N, N, N, N)
+    rhs = np.array([3.0, 1.0]).reshape(1, 1, 2)
+    pv = lambda a, b: np.array([a, b], float).reshape(1, 1, 2)
+    assert orc.relres(rho, mask, bc, 1.0, rhs, pv(0, 1)) == 0.0
+    assert orc.relres(rho, mask, bc, 1.0, rhs, pv(0, 2)) == 1.0
+    assert orc.relres(rho, mask, bc, 1.0, rhs, pv(0, 0)) == 1.0
+    assert orc.relres(rho, mask, bc, 1.0, rhs, pv(5, 6)) == 0.0
+
+
+@pytest.mark.parametrize("bc", [TANK, (2, 2, N, N, N, N)], ids=["anchored", "singular"])
+def test_relres_ignores_hull_entries(orc, F, bc):
+    """Whatever a caller holds in hull cells, of the source or of the
+    pressure, does not change the residual (to the rounding of the threaded
+    sums, whose order is not fixed)."""
+    c = _two_phase_wedge(F, 16, 12, 10, bc=bc)
+    hull = c.mask == 1
+    assert hull.sum() > 10
+    rng = np.random.default_rng(43)
+    p = rng.standard_normal(c.shape) * (c.mask == 0)
+    r0 = orc.relres(c.rho, c.mask, c.bc, c.h, c.rhs, p)
+    rhs_g, p_g = c.rhs.copy(), p.copy()
+    rhs_g[hull] = 1e6 * rng.standard_normal(hull.sum())
+    p_g[hull] = 1e6 * rng.standard_normal(hull.sum())
+    assert abs(orc.relres(c.rho, c.mask, c.bc, c.h, rhs_g, p_g) - r0) <= 1e-13 * r0
+
+
+def test_relres_is_the_weighted_residual(orc, F):
+    """Against the norms written out here from the (separately pinned)
+    operator: ||V (Sigma - L p)|| / ||V Sigma|| over fluid cells, for a
+    random p on a hull with random fractions."""
+    c = _two_phase_wedge(F, 14, 11, 9, bc=TANK)
+    rng = np.random.default_rng(44)
+    fr = _random_frac(rng, c.mask)
+    vol = fr[3]
+    fl = c.mask == 0
+    for frac, v in ((None, np.ones_like(vol)), (fr, vol)):
+        p = 1e-3 * rng.standard_normal(c.shape)
+        Lp = orc.apply(c.rho, c.mask, c.bc, c.h, p, frac=frac)
+        want = (np.linalg.norm((v * (c.rhs - Lp))[fl])
+                / np.linalg.norm((v * c.rhs)[fl]))
+        got = orc.relres(c.rho, c.mask, c.bc, c.h, c.rhs, p, frac=frac)
+        assert abs(got - want) <= 1e-12 * want
+
+
+@pytest.mark.parametrize("bc,with_frac", [(TANK, False), (TANK, True),
+                                          ((2, 2, N, N, N, N), False),
+                                          ((2, 2, N, N, N, N), True)])
+def test_relres_matches_what_pcg_stops_on(orc, F, bc, with_frac):
+    """The residual of pcg's answer is the one pcg reports (the scaled
+    system's, recomputed at exit), in anchored and singular problems, with
+    and without fractions."""
+    c = _two_phase_wedge(F, 15, 12, 11, bc=bc)
+    frac = _random_frac(np.random.default_rng(45), c.mask) if with_frac else None
+    for tol in (1e-6, 1e-9):
+        r = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=tol, frac=frac)
+        assert r.status == orc.OK
+        rr = orc.relres(c.rho, c.mask, c.bc, c.h, c.rhs, r.p, frac=frac)
+        assert rr <= tol
+        assert abs(rr - r.relres) <= 1e-5 * r.relres
+
+
+def test_relres_singular_source_mean(orc, F):
+    """In a singular problem the residual is blind to a constant added to
+    the source (its mean is removed) and to a constant added to the
+    pressure (the null vector); in an anchored problem it is not."""
+    for bc, singular in (((2, 2, N, N, N, N), True), (TANK, False)):
+        c = _two_phase_wedge(F, 13, 12, 10, bc=bc)
+        fl = c.mask == 0
+        r = orc.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-9)
+        assert r.status == orc.OK
+        r0 = orc.relres(c.rho, c.mask, c.bc, c.h, c.rhs, r.p)
+        shift = 0.3 * np.abs(c.rhs).max()
+        r1 = orc.relres(c.rho, c.mask, c.bc, c.h, c.rhs + shift * fl, r.p)
+        p_shift = r.p + 0.1 * np.abs(r.p).max() * fl
+        r2 = orc.relres(c.rho, c.mask, c.bc, c.h, c.rhs, p_shift)
+        if singular:
+            assert abs(r1 - r0) <= 1e-4 * r0 and abs(r2 - r0) <= 1e-4 * r0
+        else:
+            assert r1 > 1e3 * r0 and r2 > 1e3 * r0
