@@ -433,6 +433,18 @@ int pcg_get_tile_rules(int32_t precision, int32_t for_batches, int32_t cap,
                        int64_t *max_cells, int32_t *tz, int32_t *grid,
                        int32_t *n_out);
 
+/*
+ * Test hook for the error path of pcg_solve / pcg_solve_ex: the
+ * after_steps-th host polling step of the next solve on this context reports
+ * PCG_EHIP (message "failure injected by pcg_inject_failure") without
+ * touching the device; 0 disarms it.  A solve that ends in a host-side
+ * error (this one, a runtime error, or a solve that stopped advancing)
+ * waits for the context's stream and leaves the context usable: the next
+ * pcg_solve starts normally.  PCG_EINVAL for a null context or
+ * after_steps < 0.
+ */
+int pcg_inject_failure(pcg_ctx_t *ctx, int32_t after_steps);
+
 /* ---- measurement helpers ---------------------------------------------- */
 
 /*

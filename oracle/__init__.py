@@ -63,6 +63,8 @@ def load(path: Optional[str] = None):
     lib.oracle_connected.restype = i
     lib.oracle_components.argtypes = [i, i, i, up, ip, ctypes.POINTER(ctypes.c_int)]
     lib.oracle_components.restype = i
+    lib.oracle_set_threads.argtypes = [i]
+    lib.oracle_set_threads.restype = None
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = i
     lib.oracle_host_triad.argtypes = [ctypes.c_long, i]
@@ -119,7 +121,9 @@ def apply(rho, mask, bc, h, p, lib=None, frac=None):
 
 def relres(rho, mask, bc, h, rhs, p, lib=None, frac=None) -> float:
     """||rhs - L p||_2 / ||rhs||_2 over fluid cells (with fractions, the
-    volume-weighted norms of the scaled system)."""
+    volume-weighted norms of the scaled system).  In a singular problem (one
+    fluid region, no Dirichlet wall) the source is measured with its fluid
+    mean removed, the source ``pcg`` solves for."""
     lib = lib or load()
     rho, rp = _f64(rho)
     mask, mp = _u8(mask)
@@ -252,6 +256,12 @@ def connected(mask, bc, lib=None) -> bool:
     mask, mp = _u8(mask)
     nz, ny, nx = mask.shape
     return bool(lib.oracle_connected(nx, ny, nz, mp, _bc(bc)))
+
+
+def set_threads(n: int, lib=None) -> None:
+    """Threads of the oracle's loops started from the calling thread."""
+    lib = lib or load()
+    lib.oracle_set_threads(int(n))
 
 
 def threads(lib=None) -> int:

@@ -646,6 +646,17 @@ double oracle_host_triad(long n, int reps)
     return 24.0 * (double)n / best / 1e9;
 }
 
+/* Threads of the oracle's parallel loops started from the calling thread
+ * (each host thread that calls the oracle keeps its own setting). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int oracle_threads(void)
 {
 #ifdef _OPENMP

@@ -28,7 +28,7 @@ EXPORTED = [
     "pcg_check_connectivity", "pcg_set_tile_rules", "pcg_get_tile_rules",
     "pcg_density_classes", "pcg_project", "pcg_divergence",
     "pcg_solve_ex", "pcg_project_ex", "pcg_rhs", "pcg_update_density",
-    "pcg_set_fractions", "pcg_triad_probe",
+    "pcg_set_fractions", "pcg_triad_probe", "pcg_inject_failure",
 ]
 
 
@@ -113,6 +113,7 @@ def load(path: str = LIB_PATH):
     lib.pcg_rhs.argtypes = [vp, dbl, vp, vp, vp, vp, vp, vp, vp]
     lib.pcg_update_density.argtypes = [vp, vp, vp, i32]
     lib.pcg_set_fractions.argtypes = [vp, vp, vp, vp, vp]
+    lib.pcg_inject_failure.argtypes = [vp, i32]
     for name in EXPORTED:
         if name not in ("pcg_strerror", "pcg_last_hip_error"):
             getattr(lib, name).restype = ctypes.c_int

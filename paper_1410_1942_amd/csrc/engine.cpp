@@ -484,6 +484,7 @@ struct Engine {
     int modes = 0;          // bit m: a running slot uses coefficient mode m
                             // (0 densities, 1 classes, 2 densities + fractions)
     int graph_modes = -1;   // modes the captured graph was built for
+    int fail_after = 0;     // test hook: the step call that reports a failure
     // timing mode
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -1000,9 +1001,29 @@ struct Engine {
         return PCG_OK;
     }
 
+    // Stop tracking a solve the host gave up on (a runtime error, or a solve
+    // that stopped advancing): wait for the stream, then mark the slot not
+    // running with `code` as its final status, so the slot can start again.
+    void abandon(int id, int code)
+    {
+        (void)hipStreamSynchronize(stream);
+        SlotHost &S = slots[id];
+        if (!S.running) return;
+        S.running = false;
+        S.finished = true;
+        S.ms = ms_since(S.t0);
+        h_states[id].status = code;
+        h_states[id].phase = PH_DONE;
+        table_dirty = true;
+    }
+
     // Run `replays` graphs (or timed chunks), then refresh the status mirror.
     int step(int replays)
     {
+        if (fail_after > 0 && --fail_after == 0) {
+            g_hip_err = "failure injected by pcg_inject_failure";
+            return PCG_EHIP;
+        }
         int st = upload_table();
         if (st) return st;
         if (nrunning == 0) return PCG_OK;
@@ -1154,15 +1175,24 @@ int pcg_solve_ex(pcg_ctx_t *c, const double *rhs, double *p, double tol,
     c->eng.t_k2.clear();
     // every replay advances a running solve (its iteration count or its
     // phase); a solve that stops moving is reported instead of polled forever
+    // a host-side failure ends the solve with that status (stats included)
+    auto fail = [&](int code) {
+        c->eng.abandon(c->slot, code);
+        if (stats) {
+            c->eng.fill_stats(c->slot, stats);
+            stats->ms = ms_since(t0);
+        }
+        return code;
+    };
     int last_iter = -1, last_phase = -1, still = 0;
     while (c->eng.slots[c->slot].running) {
         st = c->eng.step(1);
-        if (st) return st;
+        if (st) return fail(st);
         const SlotState &h = c->eng.h_states[c->slot];
         if (h.iter == last_iter && h.phase == last_phase) {
             if (++still >= 4) {
                 g_hip_err = "solve made no progress";
-                return PCG_EHIP;
+                return fail(PCG_EHIP);
             }
         } else {
             still = 0;
@@ -1363,6 +1393,13 @@ const char *pcg_strerror(int code)
 }
 
 const char *pcg_last_hip_error(void) { return g_hip_err.c_str(); }
+
+int pcg_inject_failure(pcg_ctx_t *c, int32_t after_steps)
+{
+    if (!c || after_steps < 0) return PCG_EINVAL;
+    c->eng.fail_after = after_steps;
+    return PCG_OK;
+}
 
 int pcg_set_timing(pcg_ctx_t *c, int32_t on)
 {

@@ -190,6 +190,12 @@ class Solver:
         L.check(self.lib.pcg_divergence(self._ctx, *a, out), "pcg_divergence")
         return out[0], out[1]
 
+    def inject_failure(self, after_steps: int):
+        """Test hook: the after_steps-th polling step of the next solve
+        reports a runtime failure (pcg_inject_failure); 0 disarms."""
+        L.check(self.lib.pcg_inject_failure(self._ctx, int(after_steps)),
+                "pcg_inject_failure")
+
     def set_timing(self, on: bool = True):
         L.check(self.lib.pcg_set_timing(self._ctx, int(on)), "pcg_set_timing")
 

@@ -358,6 +358,31 @@ def test_errors(F, torch_dev):
     assert e.value.code == L.ESINGULAR
 
 
+def test_context_usable_after_failed_solve(orc, F, torch_dev):
+    """A solve that ends in a host-side failure (forced from the host after
+    a few polling steps; the kernels run normally) leaves the context
+    usable: the next solve on it starts and meets the bar, in both
+    precisions."""
+    torch, dev = torch_dev
+    from paper_1410_1942_amd import _lib as L
+    from paper_1410_1942_amd.solver import Solver
+    case = _two_phase(F, 24, 20, 18)
+    for prec in (0, 1):
+        _say(f"case failed-then-retried prec={prec}")
+        s = Solver(_to(torch, dev, case.rho), _to(torch, dev, case.mask), case.bc, case.h,
+                   precision=prec)
+        try:
+            rhs = _to(torch, dev, case.rhs)
+            s.inject_failure(3)
+            p, st = s.solve(rhs, tol=1e-8, raise_on_error=False)
+            assert st["status"] == L.EHIP, st
+            p, st = s.solve(rhs, tol=1e-8, raise_on_error=False)
+            torch.cuda.synchronize()
+        finally:
+            s.close()
+        _check_against_oracle(orc, case, p.cpu().numpy(), st, 1e-8)
+
+
 # ---------------------------------------------------------------------------
 # FP32 stencil with FP64 iterative refinement
 # ---------------------------------------------------------------------------
@@ -395,21 +420,29 @@ def test_ir_deterministic(F, torch_dev):
 # ---------------------------------------------------------------------------
 
 def test_wedge_256_fp64_and_ir(orc, F, torch_dev):
-    """256^3 two-phase + wedge: both forms reach 1e-8 by the reference's
-    residual, and agree with each other to 1e-6."""
-    case = F.config_wedge(256)
-    _say("case wedge256 fp64")
-    p64, st64 = gpu_solve(torch_dev, case, tol=1e-8)
-    rr64 = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p64)
-    _say(f"  fp64 iters={st64['iters']} rr={rr64:.3e}")
-    assert st64["status"] == 0 and rr64 <= 1e-8
-    _say("case wedge256 ir")
-    p32, st32 = gpu_solve(torch_dev, case, tol=1e-8, precision=1)
-    rr32 = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p32)
-    _say(f"  ir iters={st32['iters']} outer={st32['outer_iters']} rr={rr32:.3e}")
-    assert st32["status"] == 0 and rr32 <= 1e-8
-    err = np.abs(p32 - p64).max() / np.abs(p64).max()
-    assert err <= 1e-6, err
+    """256^3 two-phase + wedge, both forms: the oracle's recomputed residual
+    within tol, and the error against the oracle's 1e-12 solution (stored
+    sample) stated at 1e-8 and held to 1e-6 at 1e-9."""
+    from tests import _ref
+    case = F.config_wedge(256, keep_velocity=False)
+    meta, ref = _ref.golden(256)
+    assert _ref.input_digest(case) == meta["input_sha256"]
+    out = {}
+    for tol in (1e-8, 1e-9):
+        for prec, name in ((0, "fp64"), (1, "fp32+ir")):
+            _say(f"case wedge256 {name} tol={tol:g}")
+            p, st = gpu_solve(torch_dev, case, tol=tol, precision=prec)
+            assert st["status"] == 0, st
+            rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p)
+            err = _ref.err_vs_golden(p, meta, ref)
+            _say(f"  iters={st['iters']} outer={st['outer_iters']} rr={rr:.3e} "
+                 f"err_vs_oracle={err:.3e}")
+            assert rr <= tol, rr
+            assert np.all(p[case.mask.astype(bool)] == 0.0)
+            out[(name, tol)] = err
+    for name in ("fp64", "fp32+ir"):
+        assert out[(name, 1e-8)] <= 1e-5, out
+        assert out[(name, 1e-9)] <= 1e-6, out
 
 
 # ---------------------------------------------------------------------------
