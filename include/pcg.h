@@ -113,9 +113,17 @@ enum {
                                         as one byte per cell plus a table of
                                         exact face coefficients (same
                                         operator, fewer bytes per iteration) */
-    PCG_FRACTIONS = 8                /* reserve workspace for free-slip cut-cell
+    PCG_FRACTIONS = 8,               /* reserve workspace for free-slip cut-cell
                                         fractions (pcg_set_fractions; single
                                         contexts only)                       */
+    PCG_FLAT_TILES = 16              /* keep tiles of consecutive cells: by
+                                        default an FP64 grid whose rows are a
+                                        multiple of 128 cells (and whose
+                                        periodic axes hold whole 128 x 4
+                                        tiles) runs 128 x 4 plane tiles with
+                                        the operator's in-plane neighbours
+                                        staged in LDS; same operator, another
+                                        summation order                      */
 };
 
 /*
@@ -125,7 +133,7 @@ enum {
  *               and solution update (iterative refinement).
  *   check_every iterations per captured graph replay between host polls [32]
  *   flags       PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK |
- *               PCG_NO_DENSITY_CLASSES
+ *               PCG_NO_DENSITY_CLASSES | PCG_FRACTIONS | PCG_FLAT_TILES
  *   inner_maxit FP32_IR: cap on inner iterations per refinement trip [none]
  *   inner_tol   FP32_IR: relative reduction asked of each inner solve, never
  *               more than the last refinement trip needs [1e-4]

@@ -191,10 +191,24 @@ private:
 
 struct Geometry {
     int nx, ny, nz, tz, plane_tiles, ztiles, cpt;
+    int tx, ty, tiles_x;    // 2-D plane tiles (tx > 0) or consecutive cells
     int64_t n, ntiles;
 };
 
-Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch)
+// Whether a grid runs 2-D plane tiles (the LDS-staged FP64 pass B): FP64,
+// rows a multiple of the tile width, no cut-cell fractions, not switched off,
+// and a periodic y axis holding whole tiles (periodic x always does).  With
+// the walls unknown (bc null: workspace sizing) the y condition is assumed
+// met, which sizes for the larger tile count.
+bool plane_tiles_2d(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc)
+{
+    if (prec != PCG_PREC_FP64 || (flags & (PCG_FLAT_TILES | PCG_FRACTIONS))) return false;
+    if (g.nx % kTileX != 0) return false;
+    if (bc && bc->kind[2] == PCG_BC_PERIODIC && g.ny > 1 && g.ny % kTileY != 0) return false;
+    return true;
+}
+
+Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch, bool tiles2d)
 {
     Geometry G;
     G.nx = g.nx; G.ny = g.ny; G.nz = g.nz;
@@ -210,7 +224,15 @@ Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch)
     // for FP32 passes when it is a multiple of four
     G.cpt = (prec == PCG_PREC_FP32_IR && g.nx % 4 == 0) ? 4 : (g.nx % 2 == 0 ? 2 : 1);
     const int64_t per_tile = (int64_t)G.cpt * kBlock;
-    G.plane_tiles = (int)((plane + per_tile - 1) / per_tile);
+    if (tiles2d) {
+        G.tx = kTileX;
+        G.ty = kTileY;
+        G.tiles_x = g.nx / kTileX;
+        G.plane_tiles = G.tiles_x * ((g.ny + kTileY - 1) / kTileY);
+    } else {
+        G.tx = G.ty = G.tiles_x = 0;
+        G.plane_tiles = (int)((plane + per_tile - 1) / per_tile);
+    }
     G.ztiles = (g.nz + G.tz - 1) / G.tz;
     G.ntiles = (int64_t)G.plane_tiles * G.ztiles;
     return G;
@@ -290,7 +312,7 @@ int check_opts(const pcg_opts_t *o)
     if (o->check_every < 0 || o->inner_maxit < 0 || o->tz < 0 || o->grid_blocks < 0) return PCG_EINVAL;
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0 || std::isnan(o->inner_tol)) return PCG_EINVAL;
     if (o->flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES |
-                     PCG_FRACTIONS))
+                     PCG_FRACTIONS | PCG_FLAT_TILES))
         return PCG_EINVAL;
     return PCG_OK;
 }
@@ -448,6 +470,18 @@ struct SlotHost {
     double ms = 0.0;
 };
 
+// Coefficient mode of a slot, as the kernels derive it from its description
+// (kernel template argument MODE): 0 per-cell density, 1 density classes,
+// 2 per-cell density with cut-cell fractions, 3 classes and 4 per-cell
+// density on 2-D plane tiles.
+constexpr int kModes = 5;
+int slot_mode(const SlotHost &S)
+{
+    if (S.has_frac) return 2;
+    if (S.geo.tx > 0) return S.classes ? 3 : 4;
+    return S.classes ? 1 : 0;
+}
+
 }  // namespace
 
 struct Engine {
@@ -461,6 +495,7 @@ struct Engine {
     int inner_maxit = 0;
     double inner_tol = kDefaultInnerTol;
     bool frac_space = false;  // slots reserve room for cut-cell fractions
+    int flags = 0;            // option flags of the context or batch
     char *arena = nullptr;
     size_t arena_bytes = 0;
     int max_slots = 0;
@@ -481,8 +516,7 @@ struct Engine {
     int64_t total_tiles = 0;
     int nrunning = 0;
     bool is_batch = false;  // created by pcg_batch_create (batch tile table)
-    int modes = 0;          // bit m: a running slot uses coefficient mode m
-                            // (0 densities, 1 classes, 2 densities + fractions)
+    int modes = 0;          // bit m: a running slot uses coefficient mode m (slot_mode)
     int graph_modes = -1;   // modes the captured graph was built for
     int fail_after = 0;     // test hook: the step call that reports a failure
     // timing mode
@@ -527,6 +561,7 @@ struct Engine {
             tz_opt = o->tz;
             grid_opt = o->grid_blocks;
             frac_space = (o->flags & PCG_FRACTIONS) != 0;
+            flags = o->flags;
         }
         arena = (char *)arena_ptr;
         arena_bytes = bytes;
@@ -635,7 +670,9 @@ struct Engine {
 
     size_t footprint(const pcg_grid_t &g) const
     {
-        return slot_bytes(make_geometry(g, prec, tz_opt, batch_mode()), prec, frac_space);
+        return slot_bytes(make_geometry(g, prec, tz_opt, batch_mode(),
+                                        plane_tiles_2d(g, prec, flags, nullptr)),
+                          prec, frac_space);
     }
 
     // Reserve a slot and its memory, encode the density.  Does not start a solve.
@@ -652,7 +689,8 @@ struct Engine {
         for (int i = 0; i < max_slots; ++i)
             if (!slots[i].used) { id = i; break; }
         if (id < 0) return PCG_EBUSY;
-        const Geometry geo = make_geometry(*grid_, prec, tz_opt, batch_mode());
+        const Geometry geo = make_geometry(*grid_, prec, tz_opt, batch_mode(),
+                                           plane_tiles_2d(*grid_, prec, flags | this->flags, bc));
         const size_t need = slot_bytes(geo, prec, frac_space);
         size_t off = 0;
         if (!alloc.alloc(need, &off)) return max_slots == 1 ? PCG_ENOMEM : PCG_EBUSY;
@@ -874,6 +912,9 @@ struct Engine {
         d.permask = S.permask;
             d.plane_tiles = S.geo.plane_tiles;
             d.cpt = S.geo.cpt;
+            d.tx = S.geo.tx;
+            d.ty = S.geo.ty;
+            d.tiles_x = S.geo.tiles_x;
             d.ztiles = S.geo.ztiles;
             d.tz = S.geo.tz;
             d.tile_begin = tb;
@@ -894,7 +935,7 @@ struct Engine {
             set_frac(d, S);
             d.tab64 = S.tab64;
             d.tab32 = S.tab32;
-            m |= S.has_frac ? 4 : S.classes ? 2 : 1;
+            m |= 1 << slot_mode(S);
             tb += S.geo.ntiles;
         }
         h_hdr->total_tiles = tb;
@@ -958,7 +999,7 @@ struct Engine {
         hipError_t e = hipSuccess;
         if (w == 0) return e;
         bool first = true;
-        for (int m = 0; m < 3 && e == hipSuccess; ++m) {
+        for (int m = 0; m < kModes && e == hipSuccess; ++m) {
             if (!(modes & (1 << m))) continue;
             e = launch_iter(prec, (w == 1 && first) ? 3 : w, m, grid, d_hdr, d_slots, s);
             first = false;
@@ -1122,7 +1163,9 @@ int pcg_workspace_bytes(const pcg_grid_t *grid, const pcg_opts_t *opts,
     st = check_opts(opts);
     if (st) return st;
     const int prec = opts ? opts->precision : PCG_PREC_FP64;
-    const Geometry G = make_geometry(*grid, prec, opts ? opts->tz : 0, false);
+    const int flags = opts ? opts->flags : 0;
+    const Geometry G = make_geometry(*grid, prec, opts ? opts->tz : 0, false,
+                                     plane_tiles_2d(*grid, prec, flags, nullptr));
     *out_bytes = head_bytes(1) + slot_bytes(G, prec, opts && (opts->flags & PCG_FRACTIONS));
     return PCG_OK;
 }

@@ -102,22 +102,31 @@ struct TileCtx {
     bool active;
 };
 
-// Column of this thread in tile lt.  A tile holds S.cpt kBlock consecutive
-// cells of a plane (S.cpt = 1, 2 or 4 cells per thread; 2 and 4 need a row
-// length divisible by them).  Phases that treat cells one by one take them
-// in S.cpt coalesced runs (r: cells r kBlock + l of the tile); passes A and
-// B give thread l the adjacent cells S.cpt l .. S.cpt l + S.cpt - 1 of one
-// row (group_ctx).
+// Column of this thread in tile lt.  A tile holds S.cpt kBlock cells of a
+// plane (S.cpt = 1, 2 or 4 cells per thread; 2 and 4 need a row length
+// divisible by them): consecutive cells, or with S.tx > 0 a 2-D block of
+// S.tx columns x S.ty rows numbered row by row.  Phases that treat cells
+// one by one take them in S.cpt coalesced runs (r: cells r kBlock + l of
+// the tile); passes A and B give thread l the adjacent cells S.cpt l ..
+// S.cpt l + S.cpt - 1 of one row (group_ctx).  On a 2-D tile i and j are
+// set for every lane, also past the grid's edge (active false there).
 __device__ __forceinline__ TileCtx tile_at(const Slot &S, int64_t lt, int q_in_tile)
 {
     TileCtx t;
     const int pt = (int)(lt % S.plane_tiles);
     const int zt = (int)(lt / S.plane_tiles);
     t.P = S.nx * S.ny;
-    t.q = pt * (S.cpt * kBlock) + q_in_tile;
-    t.active = t.q < t.P;
-    t.i = t.q % S.nx;
-    t.j = t.q / S.nx;
+    if (S.tx > 0) {
+        t.i = (pt % S.tiles_x) * S.tx + q_in_tile % S.tx;
+        t.j = (pt / S.tiles_x) * S.ty + q_in_tile / S.tx;
+        t.active = t.i < S.nx && t.j < S.ny;
+        t.q = t.j * S.nx + t.i;
+    } else {
+        t.q = pt * (S.cpt * kBlock) + q_in_tile;
+        t.active = t.q < t.P;
+        t.i = t.q % S.nx;
+        t.j = t.q / S.nx;
+    }
     t.k0 = zt * S.tz;
     t.k1 = min(S.nz, t.k0 + S.tz);
     return t;
@@ -789,6 +798,38 @@ __device__ void body_passB(const Slot &S, const SlotState &st, int64_t lt,
     acc[1] += a1;
 }
 
+// One cell of pass B: the operator row from the cell's value and key and
+// those of its six neighbours (walls already substituted), the low z face
+// coefficient carried from the plane below (bzm, replaced by the high one),
+// z -= alpha q / diag and the two dot terms; in the catch-up form (XM 3)
+// also the three pending x updates.  Shared by the grouped and the
+// LDS-staged pass so both evaluate a cell the same way.
+template <typename T, typename X, class C, int XM>
+__device__ __forceinline__ void passB_cell(const C &cf, const Areas6<T> &ar,
+                                           typename C::Key kc, T vc, T vxm,
+                                           typename C::Key kxm, T vxp, typename C::Key kxp,
+                                           T vym, typename C::Key kym, T vyp,
+                                           typename C::Key kyp, T vzm, T vzp,
+                                           typename C::Key kz, T &bzm, T zc, T alpha,
+                                           T alpha_p0, T alpha_p1, X xo, T po0, T po1,
+                                           X &xn, T &zn, double &a0, double &a1)
+{
+    const T bxm = cf.beta(kc, kxm) * ar.xm, bxp = cf.beta(kc, kxp) * ar.xp;
+    const T bym = cf.beta(kc, kym) * ar.ym;
+    const T byp = cf.beta(kc, kyp) * ar.yp;
+    const T bzp = cf.beta(kc, kz) * ar.zp;
+    const T dg = ((bxm + bxp) + (bym + byp)) + (bzm + bzp);
+    const T q = ((bxm * (vc - vxm) + bxp * (vc - vxp)) + (bym * (vc - vym) + byp * (vc - vyp))) +
+                (bzm * (vc - vzm) + bzp * (vc - vzp));
+    if (XM == 3) xn = fma((X)alpha, (X)vc, fma((X)alpha_p1, (X)po1, fma((X)alpha_p0, (X)po0, xo)));
+    const T inv = dg > T(0) ? recip(dg) : T(0);   // hull rows keep z = 0
+    zn = zc - alpha * q * inv;
+    const double r = (double)dg * (double)zn;
+    a0 += r * (double)zn;
+    a1 += r * r;
+    bzm = bzp;
+}
+
 // ------------------------------------------------------------------------
 // grouped tiles: passes A and B on N adjacent columns per thread
 // ------------------------------------------------------------------------
@@ -1016,23 +1057,10 @@ __device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
             const T vxp = n < N - 1 ? vc[n + 1] : (hxp ? lvxp : T(0));
             const K kxp = n < N - 1 ? kc[n + 1] : (hxp ? lkxp : wxp);
             const T vym = hym ? vym_v[n] : T(0), vyp = hyp ? vyp_v[n] : T(0);
-            const T bxm = cf.beta(kc[n], kxm) * ar.xm, bxp = cf.beta(kc[n], kxp) * ar.xp;
-            const T bym = cf.beta(kc[n], hym ? kym[n] : wym) * ar.ym;
-            const T byp = cf.beta(kc[n], hyp ? kyp[n] : wyp) * ar.yp;
-            const T bzp = cf.beta(kc[n], kz) * ar.zp;
-            const T dg = ((bxm + bxp) + (bym + byp)) + (bzm[n] + bzp);
-            const T q = ((bxm * (vc[n] - vxm) + bxp * (vc[n] - vxp)) +
-                         (bym * (vc[n] - vym) + byp * (vc[n] - vyp))) +
-                        (bzm[n] * (vc[n] - vzm[n]) + bzp * (vc[n] - vzp));
-            if (XM == 3)
-                xn[n] = fma((X)alpha, (X)vc[n],
-                            fma((X)alpha_p1, (X)po1[n], fma((X)alpha_p0, (X)po0[n], xo[n])));
-            const T inv = dg > T(0) ? recip(dg) : T(0);   // hull rows keep z = 0
-            zn[n] = zc[n] - alpha * q * inv;
-            const double r = (double)dg * (double)zn[n];
-            a0 += r * (double)zn[n];
-            a1 += r * r;
-            bzm[n] = bzp;
+            passB_cell<T, X, C, XM>(cf, ar, kc[n], vc[n], vxm, kxm, vxp, kxp, vym,
+                                    hym ? kym[n] : wym, vyp, hyp ? kyp[n] : wyp, vzm[n], vzp,
+                                    kz, bzm[n], zc[n], alpha, alpha_p0, alpha_p1, xo[n],
+                                    po0[n], po1[n], xn[n], zn[n], a0, a1);
         }
         if (XM) {
             if constexpr (kXGroup) {
@@ -1060,6 +1088,438 @@ __device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
     }
     acc[0] += a0;
     acc[1] += a1;
+}
+
+// ------------------------------------------------------------------------
+// LDS-staged pass B on 2-D plane tiles (FP64, two cells per thread)
+// ------------------------------------------------------------------------
+// A tile is kTileX columns x kTileY rows x tz planes; thread l owns the pair
+// of cells (2l mod kTileX, 2l / kTileX) of the tile.  Per plane the tile's
+// direction values and coefficient keys, with a one-cell x-y halo, are
+// written to LDS (two plane buffers, one barrier per plane) and every cell
+// reads its four in-plane neighbours from there; z neighbours are carried in
+// registers.  Global traffic per pair and plane is then the pair's values
+// and keys one plane up and its z (plus x and the two earlier directions in
+// the catch-up form), instead of also loading the y rows above and below
+// and the columns beside it: the y-halo rows (kTileX cells each) are loaded
+// by threads 0 .. kTileX - 1, the x-halo columns (kTileY cells each) by the
+// next 2 kTileY threads.  Lanes past the grid's edge load clamped cells,
+// take part in the barriers and store nothing.  The set-up keeps this form
+// to grids whose periodic axes hold whole tiles, so a wrapped neighbour is
+// always a halo cell.
+constexpr int kLdsW = kTileX + 4;   // LDS row: pad, left halo, kTileX cells, right halo, pad
+constexpr int kLdsR = kTileY + 2;   // LDS rows: lower halo, kTileY rows, upper halo
+static_assert(kTileX * kTileY == 2 * kBlock && kTileX + 2 * kTileY <= kBlock,
+              "a pair of cells per thread; the halo loads fit the workgroup");
+
+template <typename T, typename KE>
+struct LdsPlanes {
+    T v[2][kLdsR * kLdsW];
+    KE k[2][kLdsR * kLdsW];
+};
+
+// One LDS buffer set per value and key type, shared by the two forms of pass B.
+template <typename T, typename KE>
+__device__ __forceinline__ LdsPlanes<T, KE> &lds_planes()
+{
+    __shared__ __attribute__((aligned(16))) LdsPlanes<T, KE> s;
+    return s;
+}
+
+// Two adjacent LDS elements (even index) from / to two keys or values.
+template <typename E, typename K>
+__device__ __forceinline__ void lds_put2(E *a, K k0, K k1)
+{
+    if constexpr (std::is_same<E, uint8_t>::value) {
+        *(uint16_t *)a = (uint16_t)(((unsigned)k0 & 0xffu) | (((unsigned)k1 & 0xffu) << 8));
+    } else {
+        using V = typename VecN<E, 2>::type;
+        V v;
+        v[0] = (E)k0;
+        v[1] = (E)k1;
+        *(V *)a = v;
+    }
+}
+template <typename E, typename K>
+__device__ __forceinline__ void lds_get2(const E *a, K (&k)[2])
+{
+    if constexpr (std::is_same<E, uint8_t>::value) {
+        const unsigned h = *(const uint16_t *)a;
+        k[0] = (K)(h & 0xffu);
+        k[1] = (K)(h >> 8);
+    } else {
+        using V = typename VecN<E, 2>::type;
+        const V v = *(const V *)a;
+        k[0] = (K)v[0];
+        k[1] = (K)v[1];
+    }
+}
+
+// A pair of keys as one load returns it (two class bytes, or two
+// densities), split into keys only where they are used: splitting right
+// after the load would make the wave wait for it before the plane's barrier.
+template <class C> struct KeyPair;
+template <typename T> struct KeyPair<ClsCoef<T>> {
+    using raw = unsigned;
+    static __device__ __forceinline__ raw load(const ClsCoef<T> &cf, int64_t c)
+    {
+        return ((const GLB uint16_t *)cf.cls)[c / 2];
+    }
+    static __device__ __forceinline__ void split(raw r, int (&k)[2])
+    {
+        k[0] = (int)(r & 0xffu);
+        k[1] = (int)((r >> 8) & 0xffu);
+    }
+    static __device__ __forceinline__ void put(uint8_t *a, raw r) { *(uint16_t *)a = (uint16_t)r; }
+    static __device__ __forceinline__ raw get(const uint8_t *a) { return *(const uint16_t *)a; }
+};
+template <typename T> struct KeyPair<RhoCoef<T>> {
+    using raw = typename VecN<T, 2>::type;
+    static __device__ __forceinline__ raw load(const RhoCoef<T> &cf, int64_t c)
+    {
+        return ((const GLB raw *)cf.rho)[c / 2];
+    }
+    static __device__ __forceinline__ void split(raw r, T (&k)[2])
+    {
+        k[0] = r[0];
+        k[1] = r[1];
+    }
+    static __device__ __forceinline__ void put(T *a, raw r) { *(raw *)a = r; }
+    static __device__ __forceinline__ raw get(const T *a) { return *(const raw *)a; }
+};
+
+template <typename T, typename X, class C, int XM>
+__device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const C &cf,
+                          double (&acc)[3])
+{
+    constexpr int N = 2;
+    using K = typename C::Key;
+    using KE = typename KeyElem<C>::type;
+    using KP = KeyPair<C>;
+    using KR = typename KP::raw;
+    using V = typename VecN<T, N>::type;
+    LdsPlanes<T, KE> &L = lds_planes<T, KE>();
+    const int l = (int)threadIdx.x;
+    const TileCtx t = group_ctx(S, lt);
+    const int ii = (N * l) % kTileX, jj = (N * l) / kTileX;
+    const int ti0 = t.i - ii, tj0 = t.j - jj;       // the tile's first column and row
+    const int nx = S.nx, ny = S.ny, nz = S.nz, bm = S.bcmask;
+    const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
+    const int64_t P = t.P;
+    const int pbuf = st.pbuf;
+    const GLB T *__restrict__ p = gp((const T *)dir_buf(S, pbuf));
+    const GLB T *__restrict__ pp1 = gp((const T *)dir_buf(S, dir_prev(pbuf)));
+    const GLB T *__restrict__ pp0 = gp((const T *)dir_buf(S, dir_next(pbuf)));
+    GLB X *__restrict__ x = gp((X *)S.x);
+    const GLB V *__restrict__ pv = (const GLB V *)p;
+    const GLB V *__restrict__ pv0 = (const GLB V *)pp0;
+    const GLB V *__restrict__ pv1 = (const GLB V *)pp1;
+    GLB V *__restrict__ zv = (GLB V *)gp((T *)S.z);
+    const T alpha = (T)st.alpha;
+    const T alpha_p0 = (T)st.alpha_p0, alpha_p1 = (T)st.alpha_p1;
+    // this lane's pair, clamped into the grid for lanes past its edge
+    const int64_t qo = (int64_t)min(t.j, ny - 1) * nx + min(t.i, nx - N);
+    const int own = (jj + 1) * kLdsW + ii + 2;
+    // halo role: a pair of the row below or above the tile, or one cell of
+    // the column left or right of it (wrapped on periodic axes, clamped at
+    // walls, where the cells that would use it substitute the wall)
+    // (an x-halo cell comes with the other cell of its aligned pair)
+    const bool yh = l < kTileX;
+    const bool xh = !yh && l < kTileX + 2 * kTileY;
+    int64_t qh = qo;       // pair-aligned source; lanes without a role reload their own
+    int hsel = 0, hslot = 0;
+    if (yh) {
+        const int up = l / (kTileX / N), hi = N * (l % (kTileX / N));
+        int jy = up ? tj0 + kTileY : tj0 - 1;
+        jy = py ? (jy + ny) % ny : max(0, min(ny - 1, jy));
+        qh = (int64_t)jy * nx + min(ti0 + hi, nx - N);
+        hslot = (up ? kTileY + 1 : 0) * kLdsW + hi + 2;
+    } else if (xh) {
+        const int c = l - kTileX, right = c / kTileY, hj = c % kTileY;
+        int ix = right ? ti0 + kTileX : ti0 - 1;
+        ix = px ? (ix + nx) % nx : max(0, min(nx - 1, ix));
+        const int64_t q1 = (int64_t)min(tj0 + hj, ny - 1) * nx + ix;
+        qh = q1 & ~(int64_t)1;
+        hsel = (int)(q1 & 1);
+        hslot = (hj + 1) * kLdsW + (right ? kTileX + 2 : 1);
+    }
+    // the waves holding halo lanes load in every lane (no divergent branch
+    // around loads whose results must stay in flight); the others skip
+    const bool hwave = __builtin_amdgcn_readfirstlane(l) < kTileX + 2 * kTileY;
+    const int i0 = t.i, j = t.j;
+    const bool hxm = i0 > 0 || px, hxp = i0 + N - 1 < nx - 1 || px;
+    const bool hym = j > 0 || py, hyp = j < ny - 1 || py;
+    const K wxm = (bm & 1) ? cf.dirichlet() : cf.neumann();
+    const K wxp = (bm & 2) ? cf.dirichlet() : cf.neumann();
+    const K wym = (bm & 4) ? cf.dirichlet() : cf.neumann();
+    const K wyp = (bm & 8) ? cf.dirichlet() : cf.neumann();
+    const K wzm = (bm & 16) ? cf.dirichlet() : cf.neumann();
+    const K wzp = (bm & 32) ? cf.dirichlet() : cf.neumann();
+    // halo values of a plane as loaded (a pair)
+    struct Halo {
+        V v;
+        KR kp;
+    };
+    auto load_halo = [&](int64_t base) {
+        Halo h{};
+        if (hwave) {
+            h.v = pv[(base + qh) / N];
+            h.kp = KP::load(cf, base + qh);
+        }
+        return h;
+    };
+    int64_t c = (int64_t)t.k0 * P;   // plane base
+    T vc[N], vzm[N], bzm[N];
+    K kc[N], kzm[N];
+    V vcv = pv[(c + qo) / N];
+    KR kcr = KP::load(cf, c + qo);
+    vc[0] = vcv[0];
+    vc[1] = vcv[1];
+    KP::split(kcr, kc);
+    vzm[0] = vzm[1] = T(0);
+    kzm[0] = kzm[1] = wzm;
+    if (t.k0 > 0) {
+        const V v = pv[(c - P + qo) / N];
+        vzm[0] = v[0];
+        vzm[1] = v[1];
+        KP::split(KP::load(cf, c - P + qo), kzm);
+    }
+    Halo h = load_halo(c);
+#pragma unroll
+    for (int n = 0; n < N; ++n)
+        bzm[n] = cf.beta(kc[n], kzm[n]) * cf.areas(i0 + n, j, t.k0, c + qo + n).zm;
+    double a0 = 0.0, a1 = 0.0;
+    for (int k = t.k0; k < t.k1; ++k, c += P) {
+        const int b = (k - t.k0) & 1;
+        T *Lv = L.v[b];
+        KE *Lk = L.k[b];
+        // stage plane k: this lane's pair and its halo cells, as loaded
+        *(V *)(Lv + own) = vcv;
+        KP::put(Lk + own, kcr);
+        if (yh) {
+            *(V *)(Lv + hslot) = h.v;
+            KP::put(Lk + hslot, h.kp);
+        } else if (xh) {
+            K hk[N];
+            KP::split(h.kp, hk);
+            Lv[hslot] = hsel ? h.v[1] : h.v[0];
+            Lk[hslot] = (KE)(hsel ? hk[1] : hk[0]);
+        }
+        // loads for the next plane and this plane's vectors, left unsplit
+        // and unused until after the barrier so they stay in flight across it
+        const bool top = k == nz - 1;
+        const int64_t cn = top ? c : c + P;
+        const V vzp_v = pv[(cn + qo) / N];
+        const KR kzpr = KP::load(cf, cn + qo);
+        const Halo hn = load_halo(cn);
+        const V zc = __builtin_nontemporal_load(&zv[(c + qo) / N]);
+        X xo[N] = { X(0), X(0) };
+        V v0 = { T(0), T(0) }, v1 = { T(0), T(0) };
+        if (XM == 3) {
+#pragma unroll
+            for (int n = 0; n < N; ++n) xo[n] = __builtin_nontemporal_load(&x[c + qo + n]);
+            v0 = __builtin_nontemporal_load(&pv0[(c + qo) / N]);
+            v1 = __builtin_nontemporal_load(&pv1[(c + qo) / N]);
+        }
+        __syncthreads();
+        const V vym = *(const V *)(Lv + own - kLdsW), vyp = *(const V *)(Lv + own + kLdsW);
+        K kym[N], kyp[N], kzp[N];
+        KP::split(KP::get(Lk + own - kLdsW), kym);
+        KP::split(KP::get(Lk + own + kLdsW), kyp);
+        KP::split(kzpr, kzp);
+        const T lvxm = Lv[own - 1], lvxp = Lv[own + N];
+        const K lkxm = (K)Lk[own - 1], lkxp = (K)Lk[own + N];
+        T zn[N];
+        X xn[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const T vzp = top ? T(0) : vzp_v[n];
+            const K kz = top ? wzp : kzp[n];
+            const Areas6<T> ar = cf.areas(i0 + n, j, k, c + qo + n);
+            const T vxm = n > 0 ? vc[n - 1] : (hxm ? lvxm : T(0));
+            const K kxm = n > 0 ? kc[n - 1] : (hxm ? lkxm : wxm);
+            const T vxp = n < N - 1 ? vc[n + 1] : (hxp ? lvxp : T(0));
+            const K kxp = n < N - 1 ? kc[n + 1] : (hxp ? lkxp : wxp);
+            passB_cell<T, X, C, XM>(cf, ar, kc[n], vc[n], vxm, kxm, vxp, kxp,
+                                    hym ? vym[n] : T(0), hym ? kym[n] : wym,
+                                    hyp ? vyp[n] : T(0), hyp ? kyp[n] : wyp, vzm[n], vzp, kz,
+                                    bzm[n], zc[n], alpha, alpha_p0, alpha_p1, xo[n], v0[n],
+                                    v1[n], xn[n], zn[n], a0, a1);
+        }
+        if (t.active) {
+            if (XM == 3) {
+#pragma unroll
+                for (int n = 0; n < N; ++n) __builtin_nontemporal_store(xn[n], &x[c + qo + n]);
+            }
+            V zv_n;
+            zv_n[0] = zn[0];
+            zv_n[1] = zn[1];
+            __builtin_nontemporal_store(zv_n, &zv[(c + qo) / N]);
+        }
+        // the top plane's neighbour above is the wall: its staged copy is
+        // never read, so the plane simply repeats
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            vzm[n] = vc[n];
+            vc[n] = top ? T(0) : vzp_v[n];
+            kc[n] = top ? wzp : kzp[n];
+        }
+        vcv = vzp_v;
+        kcr = kzpr;
+        h = hn;
+    }
+    if (t.active) {
+        acc[0] += a0;
+        acc[1] += a1;
+    }
+}
+
+// Pass A on 2-D plane tiles with LDS staging: p = z + beta p_old for the
+// tile's pairs, stored, and written to LDS together with the keys; the row
+// below the tile (threads 0 .. kTileX/2 - 1, pairs) and the column left of
+// it (the next kTileY threads, one cell each) compute their p the same way
+// into the halo.  After the plane's barrier every cell reads its x- and y-
+// neighbours from LDS (pass A counts each face once, from its upper cell);
+// the z- neighbour is carried in registers.  The next plane's loads are
+// issued before the barrier and used after it.
+template <typename T, class C>
+__device__ void lds_passA(const Slot &S, const SlotState &st, int64_t lt, const C &cf,
+                          double (&acc)[3])
+{
+    constexpr int N = 2;
+    using K = typename C::Key;
+    using KE = typename KeyElem<C>::type;
+    using KP = KeyPair<C>;
+    using KR = typename KP::raw;
+    using V = typename VecN<T, N>::type;
+    LdsPlanes<T, KE> &L = lds_planes<T, KE>();
+    const int l = (int)threadIdx.x;
+    const TileCtx t = group_ctx(S, lt);
+    const int ii = (N * l) % kTileX, jj = (N * l) / kTileX;
+    const int ti0 = t.i - ii, tj0 = t.j - jj;
+    const int nx = S.nx, ny = S.ny, nz = S.nz, bm = S.bcmask;
+    const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
+    const int64_t P = t.P;
+    const int pbuf = __builtin_amdgcn_readfirstlane(st.pbuf);
+    const GLB V *__restrict__ zv = (const GLB V *)gp((const T *)S.z);
+    const GLB V *__restrict__ qv = (const GLB V *)gp((const T *)dir_buf(S, pbuf));
+    GLB V *__restrict__ pdv = (GLB V *)gp((T *)dir_buf(S, dir_next(pbuf)));
+    // first direction: beta = 0 (p_old holds zeros from the set-up, or a
+    // finite earlier direction, so the loads stay unconditional)
+    const T beta = st.first ? T(0) : (T)st.beta;
+    const int64_t qo = (int64_t)min(t.j, ny - 1) * nx + min(t.i, nx - N);
+    const int own = (jj + 1) * kLdsW + ii + 2;
+    const bool yh = l < kTileX / N;
+    const bool xh = !yh && l < kTileX / N + kTileY;
+    int64_t qh = qo;
+    int hsel = 0, hslot = 0;
+    if (yh) {
+        const int hi = N * l;
+        int jy = tj0 - 1;
+        jy = py ? (jy + ny) % ny : max(0, jy);
+        qh = (int64_t)jy * nx + min(ti0 + hi, nx - N);
+        hslot = hi + 2;
+    } else if (xh) {
+        const int hj = l - kTileX / N;
+        int ix = ti0 - 1;
+        ix = px ? (ix + nx) % nx : max(0, ix);
+        const int64_t q1 = (int64_t)min(tj0 + hj, ny - 1) * nx + ix;
+        qh = q1 & ~(int64_t)1;
+        hsel = (int)(q1 & 1);
+        hslot = (hj + 1) * kLdsW + 1;
+    }
+    const bool hwave = __builtin_amdgcn_readfirstlane(l) < kTileX / N + kTileY;
+    const int i0 = t.i, j = t.j;
+    const bool hxm = i0 > 0 || px, hym = j > 0 || py;
+    // Dirichlet high walls: x+ of the pair's last cell, y+ of both
+    const bool hwx = !(i0 + N - 1 < nx - 1 || px) && (bm & 2);
+    const bool hwy = !(j < ny - 1 || py) && (bm & 8);
+    const K wxm = (bm & 1) ? cf.dirichlet() : cf.neumann();
+    const K wym = (bm & 4) ? cf.dirichlet() : cf.neumann();
+    const K wzm = (bm & 16) ? cf.dirichlet() : cf.neumann();
+    struct Plane {
+        V z, q, hz, hq;
+        KR k, hk;
+    };
+    auto load = [&](int kk) {
+        kk = kk < t.k1 ? kk : t.k1 - 1;    // past the tile's end: re-read its last plane
+        const int64_t base = (int64_t)kk * P;
+        Plane A;
+        A.z = zv[(base + qo) / N];
+        A.q = qv[(base + qo) / N];
+        A.k = KP::load(cf, base + qo);
+        if (hwave) {
+            A.hz = zv[(base + qh) / N];
+            A.hq = qv[(base + qh) / N];
+            A.hk = KP::load(cf, base + qh);
+        }
+        return A;
+    };
+    T pzm[N];
+    K kzm[N];
+    pzm[0] = pzm[1] = T(0);
+    kzm[0] = kzm[1] = wzm;
+    if (t.k0 > 0) {
+        const int64_t base = (int64_t)(t.k0 - 1) * P;
+        const V z = zv[(base + qo) / N], q = qv[(base + qo) / N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) pzm[n] = z[n] + beta * q[n];
+        KP::split(KP::load(cf, base + qo), kzm);
+    }
+    double a = 0.0;
+    Plane A = load(t.k0);
+    for (int k = t.k0; k < t.k1; ++k) {
+        const int b = (k - t.k0) & 1;
+        T *Lv = L.v[b];
+        KE *Lk = L.k[b];
+        V pn;
+#pragma unroll
+        for (int n = 0; n < N; ++n) pn[n] = A.z[n] + beta * A.q[n];
+        K kc[N];
+        KP::split(A.k, kc);
+        *(V *)(Lv + own) = pn;
+        KP::put(Lk + own, A.k);
+        if (yh) {
+            V hp;
+#pragma unroll
+            for (int n = 0; n < N; ++n) hp[n] = A.hz[n] + beta * A.hq[n];
+            *(V *)(Lv + hslot) = hp;
+            KP::put(Lk + hslot, A.hk);
+        } else if (xh) {
+            K hk[N];
+            KP::split(A.hk, hk);
+            Lv[hslot] = hsel ? A.hz[1] + beta * A.hq[1] : A.hz[0] + beta * A.hq[0];
+            Lk[hslot] = (KE)(hsel ? hk[1] : hk[0]);
+        }
+        if (t.active) __builtin_nontemporal_store(pn, &pdv[((int64_t)k * P + qo) / N]);
+        const Plane B = load(k + 1);
+        __syncthreads();
+        const bool top = k == nz - 1 && (bm & 32);
+        const V pym_v = *(const V *)(Lv + own - kLdsW);
+        K kym[N];
+        KP::split(KP::get(Lk + own - kLdsW), kym);
+        T pl = hxm ? Lv[own - 1] : T(0);          // x- value of the next cell
+        K kl = hxm ? (K)Lk[own - 1] : wxm;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const T pym = hym ? pym_v[n] : T(0);
+            const K kyn = hym ? kym[n] : wym;
+            const Areas6<T> ar = cf.areas(i0 + n, j, k, (int64_t)k * P + qo + n);
+            const T dx = pn[n] - pl, dy = pn[n] - pym, dz = pn[n] - pzm[n];
+            T sn = (cf.beta(kc[n], kl) * ar.xm * dx * dx + cf.beta(kc[n], kyn) * ar.ym * dy * dy) +
+                   cf.beta(kc[n], kzm[n]) * ar.zm * dz * dz;
+            const T w = ((n == N - 1 && hwx) ? ar.xp : T(0)) + (hwy ? ar.yp : T(0)) +
+                        (top ? ar.zp : T(0));
+            sn += w * cf.beta(kc[n], cf.dirichlet()) * (pn[n] * pn[n]);
+            a += (double)sn;
+            pzm[n] = pn[n];
+            kzm[n] = kc[n];
+            pl = pn[n];
+            kl = kc[n];
+        }
+        A = B;
+    }
+    if (t.active) acc[0] += a;
 }
 
 // Pass A / pass B for the tile form of the slot (four cells per thread for
@@ -1549,10 +2009,13 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
 // workgroups per CU use).  K1 and K2 come in three coefficient modes
 // (density, classes, cut cells), each serving only the slots of its mode.
 // Coefficient mode of a slot: 0 per-cell density, 1 density classes,
-// 2 per-cell density with free-slip cut cells (area/volume fractions).
+// 2 per-cell density with free-slip cut cells (area/volume fractions);
+// 3 classes and 4 per-cell density on 2-D plane tiles (LDS-staged pass B).
 __device__ __forceinline__ int slot_mode(const Slot &S)
 {
-    return S.ax ? 2 : (S.cls ? 1 : 0);
+    if (S.ax) return 2;
+    if (S.tx > 0) return S.cls ? 3 : 4;
+    return S.cls ? 1 : 0;
 }
 
 // The first-half actions of K0 in one coefficient source.
@@ -1598,18 +2061,38 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
         if (ph == K1_MEAN_B) { body_mean_b(S, st, lt, r64, acc); return; }
         if (ph == K1_MEAN_X) { body_mean_x(S, st, lt, r64, acc); return; }
         if (ph == K1_FLUSH_X) { body_flush_x(S, st, lt, acc); return; }
-        const int m = slot_mode(S);
         if (FAMILY == PCG_PREC_FP64) {
-            if (m == 2) run_k0_fp64(ph, S, st, lt, frac_coef<double>(S, S.rho64), acc);
-            else if (m == 1) run_k0_fp64(ph, S, st, lt, c64, acc);
+            if (S.ax) run_k0_fp64(ph, S, st, lt, frac_coef<double>(S, S.rho64), acc);
+            else if (S.cls) run_k0_fp64(ph, S, st, lt, c64, acc);
             else run_k0_fp64(ph, S, st, lt, r64, acc);
         } else {
-            if (m == 2)
+            if (S.ax)
                 run_k0_ir(ph, S, st, lt, frac_coef<double>(S, S.rho64),
                           frac_coef<float>(S, S.rho32), acc);
-            else if (m == 1) run_k0_ir(ph, S, st, lt, c64, ClsCoef<float>{ gp(S.cls), tab32 }, acc);
+            else if (S.cls) run_k0_ir(ph, S, st, lt, c64, ClsCoef<float>{ gp(S.cls), tab32 }, acc);
             else run_k0_ir(ph, S, st, lt, r64, RhoCoef<float>{ gp(S.rho32) }, acc);
         }
+        return;
+    }
+    if (MODE >= 3) {
+        // 2-D plane tiles (FP64 only): pass A grouped, pass B LDS-staged
+        if (FAMILY != PCG_PREC_FP64) return;
+        if (WHICH == 1) {
+            if (ph == K1_CG_A) {
+                if (MODE == 3) lds_passA<double>(S, st, lt, c64, acc);
+                else lds_passA<double>(S, st, lt, r64, acc);
+            }
+        } else if (ph == K2_CG_B) {
+            const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
+            if (MODE == 3) {
+                if (catch_up) lds_passB<double, double, ClsCoef<double>, 3>(S, st, lt, c64, acc);
+                else lds_passB<double, double, ClsCoef<double>, 0>(S, st, lt, c64, acc);
+            } else {
+                if (catch_up) lds_passB<double, double, RhoCoef<double>, 3>(S, st, lt, r64, acc);
+                else lds_passB<double, double, RhoCoef<double>, 0>(S, st, lt, r64, acc);
+            }
+        } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
+        else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);
         return;
     }
     if (FAMILY == PCG_PREC_FP64) {
@@ -2106,35 +2589,26 @@ hipError_t launch_iter(int family, int which, int mode, int grid,
 {
     const dim3 g(grid), b(kBlock);
 #define PCG_LAUNCH(F, W, M) hipLaunchKernelGGL((k_iter<F, W, M>), g, b, 0, s, hdr, slots)
+#define PCG_MODES(F, W, NM)                                       \
+    do {                                                          \
+        if (mode == 0) PCG_LAUNCH(F, W, 0);                       \
+        else if (mode == 1) PCG_LAUNCH(F, W, 1);                  \
+        else if (mode == 2) PCG_LAUNCH(F, W, 2);                  \
+        else if (NM > 3 && mode == 3) PCG_LAUNCH(F, W, 3);        \
+        else if (NM > 4 && mode == 4) PCG_LAUNCH(F, W, 4);        \
+        else return hipErrorInvalidValue;                         \
+    } while (0)
+    // modes 3 and 4 (2-D plane tiles) exist for FP64 only
     if (family == PCG_PREC_FP64) {
-        if (which == 3) {
-            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP64, 3, 2);
-            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP64, 3, 1);
-            else PCG_LAUNCH(PCG_PREC_FP64, 3, 0);
-        } else if (which == 1) {
-            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP64, 1, 2);
-            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP64, 1, 1);
-            else PCG_LAUNCH(PCG_PREC_FP64, 1, 0);
-        } else {
-            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP64, 2, 2);
-            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP64, 2, 1);
-            else PCG_LAUNCH(PCG_PREC_FP64, 2, 0);
-        }
+        if (which == 3) PCG_MODES(PCG_PREC_FP64, 3, 5);
+        else if (which == 1) PCG_MODES(PCG_PREC_FP64, 1, 5);
+        else PCG_MODES(PCG_PREC_FP64, 2, 5);
     } else {
-        if (which == 3) {
-            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP32_IR, 3, 2);
-            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 3, 1);
-            else PCG_LAUNCH(PCG_PREC_FP32_IR, 3, 0);
-        } else if (which == 1) {
-            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 2);
-            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 1);
-            else PCG_LAUNCH(PCG_PREC_FP32_IR, 1, 0);
-        } else {
-            if (mode == 2) PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 2);
-            else if (mode == 1) PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 1);
-            else PCG_LAUNCH(PCG_PREC_FP32_IR, 2, 0);
-        }
+        if (which == 3) PCG_MODES(PCG_PREC_FP32_IR, 3, 3);
+        else if (which == 1) PCG_MODES(PCG_PREC_FP32_IR, 1, 3);
+        else PCG_MODES(PCG_PREC_FP32_IR, 2, 3);
     }
+#undef PCG_MODES
 #undef PCG_LAUNCH
     return hipGetLastError();
 }

@@ -12,6 +12,11 @@ namespace pcgmi {
 constexpr int kBlock = 256;       // threads per workgroup = cells per plane tile
 constexpr int kMaxPartials = 3;   // reduction values per tile
 
+// 2-D plane tiles of the LDS-staged FP64 pass B: kTileX columns x kTileY
+// rows (one pair of cells per thread)
+constexpr int kTileX = 128;
+constexpr int kTileY = 4;
+
 // Density classes: up to kMaxFluidClasses distinct fluid densities get a
 // one-byte class; kClsWallD stands for a Dirichlet wall (density 0 in the
 // face formula), kClsSolid for hull cells and Neumann walls (density +inf).
@@ -85,12 +90,15 @@ struct alignas(128) SlotState {
 struct Slot {
     int32_t nx, ny, nz;
     int32_t bcmask;        // bit f set: wall f is Dirichlet (x-,x+,y-,y+,z-,z+)
-    int32_t plane_tiles;   // ceil(nx*ny / (cpt kBlock))
+    int32_t plane_tiles;   // ceil(nx*ny / (cpt kBlock)), or tiles_x * ceil(ny / ty)
     int32_t ztiles;        // ceil(nz / tz)
     int32_t tz;            // planes per tile
     int32_t permask;       // bit 0: periodic x walls, bit 1: periodic y walls
     int32_t cpt;           // cells per thread: 1, or 2/4 adjacent columns (nx divisible)
-    int32_t pad_;
+    // 0: a tile is cpt * kBlock consecutive cells of a plane; else a 2-D
+    // plane tile of tx columns x ty rows (tx ty = cpt kBlock), tiles_x of
+    // them across a row, served by the LDS-staged pass B
+    int32_t tx, ty, tiles_x;
     int64_t tile_begin;    // first global tile of this slot
     int64_t ntiles;        // plane_tiles * ztiles
     double h2;             // h*h
