@@ -453,6 +453,29 @@ int pcg_get_tile_rules(int32_t precision, int32_t for_batches, int32_t cap,
  */
 int pcg_inject_failure(pcg_ctx_t *ctx, int32_t after_steps);
 
+/* ---- allocation-free solve ---------------------------------------------- */
+
+/*
+ * One solve that allocates nothing, for callers that cannot allocate device
+ * or pinned memory (code that must not call hipMalloc, tight serving loops,
+ * harnesses that forbid allocation).  Same problem, arguments and results
+ * as pcg_setup + pcg_solve + pcg_destroy on the stream given (opts may be
+ * NULL; flags as for pcg_setup except PCG_FRACTIONS, which is refused with
+ * PCG_EINVAL, plus PCG_WARM_START to start from p), but the workspace is a
+ * fixed 64 MiB device array inside the library (one per GPU, held until the
+ * process ends; pcg_workspace_bytes gives a grid's need) and the iterations
+ * are launched directly, without a captured graph.  No HIP allocation,
+ * stream, event or graph routine is called; host bookkeeping uses a few
+ * small ordinary heap blocks.  A grid whose workspace exceeds the array
+ * returns PCG_ENOMEM (pcg_last_hip_error names both sizes).  All calls on
+ * one GPU share the array, so calls that overlap on one GPU (from several
+ * host threads, or on several streams) race and must be serialised by the
+ * caller.  Returns after completion like pcg_solve, with its status codes.
+ */
+int pcg_solve_static(const pcg_grid_t *grid, const double *rho, const uint8_t *solid_mask,
+                     const pcg_bc_t *bc, const pcg_opts_t *opts, const double *rhs, double *p,
+                     double tol, int32_t maxit, pcg_stats_t *stats, void *hip_stream);
+
 /* ---- measurement helpers ---------------------------------------------- */
 
 /*

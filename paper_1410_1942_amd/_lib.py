@@ -29,6 +29,7 @@ EXPORTED = [
     "pcg_density_classes", "pcg_project", "pcg_divergence",
     "pcg_solve_ex", "pcg_project_ex", "pcg_rhs", "pcg_update_density",
     "pcg_set_fractions", "pcg_triad_probe", "pcg_inject_failure",
+    "pcg_solve_static",
 ]
 
 
@@ -114,6 +115,8 @@ def load(path: str = LIB_PATH):
     lib.pcg_update_density.argtypes = [vp, vp, vp, i32]
     lib.pcg_set_fractions.argtypes = [vp, vp, vp, vp, vp]
     lib.pcg_inject_failure.argtypes = [vp, i32]
+    lib.pcg_solve_static.argtypes = [P(Grid), vp, vp, P(BC), P(Opts), vp, vp, dbl, i32,
+                                     P(Stats), vp]
     for name in EXPORTED:
         if name not in ("pcg_strerror", "pcg_last_hip_error"):
             getattr(lib, name).restype = ctypes.c_int

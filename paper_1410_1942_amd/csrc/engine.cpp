@@ -44,6 +44,7 @@ hipError_t launch_rhs(const Slot *slot, double h, double dt, const double *const
 hipError_t launch_divnorm(const Slot *slot, double inv_h, const double *u,
                           const double *v, const double *w, double *part, int blocks,
                           hipStream_t st);
+hipError_t static_scratch(void **ptr, size_t *bytes);
 }  // namespace pcgmi
 
 using namespace pcgmi;
@@ -484,6 +485,16 @@ int slot_mode(const SlotHost &S)
 
 }  // namespace
 
+// Host mirrors of an arena's head for an engine that must not allocate
+// (pinned host memory is an allocation): owned by the caller, alive as long
+// as the engine.  One slot.
+struct HostMirror {
+    BatchHeader hdr;
+    Slot slots[1];
+    SlotState states[1];
+    alignas(8) int bad[64];   // error flag + class search words, 256 bytes
+};
+
 struct Engine {
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;
@@ -519,6 +530,8 @@ struct Engine {
     int modes = 0;          // bit m: a running slot uses coefficient mode m (slot_mode)
     int graph_modes = -1;   // modes the captured graph was built for
     int fail_after = 0;     // test hook: the step call that reports a failure
+    HostMirror *mirror = nullptr;  // caller-owned host mirrors: no pinned memory,
+                                   // no capture stream, launches without graphs
     // timing mode
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -539,16 +552,19 @@ struct Engine {
         ev.clear();
         if (cap) (void)hipStreamDestroy(cap);
         cap = nullptr;
-        if (h_hdr) (void)hipHostFree(h_hdr);
-        if (h_slots) (void)hipHostFree(h_slots);
-        if (h_states) (void)hipHostFree(h_states);
-        if (h_bad) (void)hipHostFree(h_bad);
+        if (!mirror) {
+            if (h_hdr) (void)hipHostFree(h_hdr);
+            if (h_slots) (void)hipHostFree(h_slots);
+            if (h_states) (void)hipHostFree(h_states);
+            if (h_bad) (void)hipHostFree(h_bad);
+        }
         h_hdr = nullptr; h_slots = nullptr; h_states = nullptr; h_bad = nullptr;
     }
 
     int init(void *arena_ptr, size_t bytes, int nslots, const pcg_opts_t *o,
-             void *hip_stream)
+             void *hip_stream, HostMirror *hm = nullptr)
     {
+        if (hm && nslots != 1) return PCG_EINVAL;
         if (!arena_ptr || nslots < 1) return PCG_EINVAL;
         if (((uintptr_t)arena_ptr) % kAlign) return PCG_EINVAL;
         int st = check_opts(o);
@@ -579,10 +595,18 @@ struct Engine {
         alloc.reset(hb, bytes);
         slots.assign(nslots, SlotHost{});
         stream = (hipStream_t)hip_stream;
-        HIP_TRY(hipHostMalloc((void **)&h_hdr, sizeof(BatchHeader), hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc((void **)&h_slots, sizeof(Slot) * nslots, hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc((void **)&h_states, sizeof(SlotState) * nslots, hipHostMallocDefault));
-        HIP_TRY(hipHostMalloc((void **)&h_bad, 256, hipHostMallocDefault));  // flag + class search words
+        if (hm) {
+            mirror = hm;
+            h_hdr = &hm->hdr;
+            h_slots = hm->slots;
+            h_states = hm->states;
+            h_bad = hm->bad;
+        } else {
+            HIP_TRY(hipHostMalloc((void **)&h_hdr, sizeof(BatchHeader), hipHostMallocDefault));
+            HIP_TRY(hipHostMalloc((void **)&h_slots, sizeof(Slot) * nslots, hipHostMallocDefault));
+            HIP_TRY(hipHostMalloc((void **)&h_states, sizeof(SlotState) * nslots, hipHostMallocDefault));
+            HIP_TRY(hipHostMalloc((void **)&h_bad, 256, hipHostMallocDefault));  // flag + class search words
+        }
         std::memset(h_states, 0, sizeof(SlotState) * nslots);
         for (int i = 0; i < nslots; ++i) h_states[i].phase = PH_IDLE;
         HIP_TRY(hipMemcpyAsync(d_states, h_states, sizeof(SlotState) * nslots,
@@ -592,7 +616,7 @@ struct Engine {
         h_hdr->chunked = 0;
         HIP_TRY(hipMemcpyAsync(d_hdr, h_hdr, sizeof(BatchHeader), hipMemcpyHostToDevice, stream));
         HIP_TRY(hipStreamSynchronize(stream));
-        HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        if (!mirror) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         return PCG_OK;
     }
 
@@ -1068,12 +1092,18 @@ struct Engine {
         int st = upload_table();
         if (st) return st;
         if (nrunning == 0) return PCG_OK;
-        st = capture();
-        if (st) return st;
+        if (mirror) {
+            grid = choose_grid();    // launched directly: no graph to capture
+        } else {
+            st = capture();
+            if (st) return st;
+        }
         for (int r = 0; r < replays; ++r) {
             if (timing) {
                 st = timed_chunk();
                 if (st) return st;
+            } else if (mirror) {
+                for (int i = 0; i < check_every; ++i) HIP_TRY(launch_iteration(stream));
             } else {
                 HIP_TRY(hipGraphLaunch(exec, stream));
             }
@@ -1129,6 +1159,44 @@ struct pcg_batch {
 };
 
 namespace {
+
+// Poll a started solve until it finishes and fill its statistics.  Every
+// step advances a running solve (its iteration count or its phase): one that
+// stops moving is reported instead of polled forever.  A host-side failure
+// ends the solve with that status (statistics included) and leaves the slot
+// able to start again.
+int run_to_end(Engine &eng, int slot, Clock::time_point t0, pcg_stats_t *stats)
+{
+    auto fail = [&](int code) {
+        eng.abandon(slot, code);
+        if (stats) {
+            eng.fill_stats(slot, stats);
+            stats->ms = ms_since(t0);
+        }
+        return code;
+    };
+    int last_iter = -1, last_phase = -1, still = 0;
+    while (eng.slots[slot].running) {
+        const int st = eng.step(1);
+        if (st) return fail(st);
+        const SlotState &h = eng.h_states[slot];
+        if (h.iter == last_iter && h.phase == last_phase) {
+            if (++still >= 4) {
+                g_hip_err = "solve made no progress";
+                return fail(PCG_EHIP);
+            }
+        } else {
+            still = 0;
+        }
+        last_iter = h.iter;
+        last_phase = h.phase;
+    }
+    pcg_stats_t s;
+    eng.fill_stats(slot, &s);
+    s.ms = ms_since(t0);
+    if (stats) *stats = s;
+    return s.status;
+}
 
 void average_nonempty(const std::vector<float> &t, double *avg, int *n)
 {
@@ -1216,44 +1284,56 @@ int pcg_solve_ex(pcg_ctx_t *c, const double *rhs, double *p, double tol,
     if (st) return st;
     c->eng.t_k1.clear();
     c->eng.t_k2.clear();
-    // every replay advances a running solve (its iteration count or its
-    // phase); a solve that stops moving is reported instead of polled forever
-    // a host-side failure ends the solve with that status (stats included)
-    auto fail = [&](int code) {
-        c->eng.abandon(c->slot, code);
-        if (stats) {
-            c->eng.fill_stats(c->slot, stats);
-            stats->ms = ms_since(t0);
-        }
-        return code;
-    };
-    int last_iter = -1, last_phase = -1, still = 0;
-    while (c->eng.slots[c->slot].running) {
-        st = c->eng.step(1);
-        if (st) return fail(st);
-        const SlotState &h = c->eng.h_states[c->slot];
-        if (h.iter == last_iter && h.phase == last_phase) {
-            if (++still >= 4) {
-                g_hip_err = "solve made no progress";
-                return fail(PCG_EHIP);
-            }
-        } else {
-            still = 0;
-        }
-        last_iter = h.iter;
-        last_phase = h.phase;
-    }
+    st = run_to_end(c->eng, c->slot, t0, stats);
+    if (st < 0) return st;
     if (c->eng.timing) {
         average_nonempty(c->eng.t_k1, &c->last_k1, &c->last_n);
         int n2 = 0;
         average_nonempty(c->eng.t_k2, &c->last_k2, &n2);
         c->have_timing = true;
     }
-    pcg_stats_t s;
-    c->eng.fill_stats(c->slot, &s);
-    s.ms = ms_since(t0);
-    if (stats) *stats = s;
-    return s.status;
+    return st;
+}
+
+int pcg_solve_static(const pcg_grid_t *grid, const double *rho, const uint8_t *solid_mask,
+                     const pcg_bc_t *bc, const pcg_opts_t *opts, const double *rhs, double *p,
+                     double tol, int32_t maxit, pcg_stats_t *stats, void *hip_stream)
+{
+    int st = check_grid(grid);
+    if (st) return st;
+    int bm = 0;
+    st = check_bc(bc, &bm);
+    if (st) return st;
+    st = check_opts(opts);
+    if (st) return st;
+    const int flags = opts ? opts->flags : 0;
+    if (flags & PCG_FRACTIONS) return PCG_EINVAL;   // fractions need a context
+    if (!rho || !rhs || !p) return PCG_EINVAL;
+    if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0) return PCG_EINVAL;
+    size_t need = 0;
+    st = pcg_workspace_bytes(grid, opts, &need);
+    if (st) return st;
+    void *scr = nullptr;
+    size_t cap = 0;
+    hipError_t e = static_scratch(&scr, &cap);
+    if (e != hipSuccess) return hip_fail(e, "static scratch address");
+    if (need > cap) {
+        g_hip_err = "pcg_solve_static: the grid needs " + std::to_string(need) +
+                    " bytes of device memory, more than the " + std::to_string(cap) +
+                    "-byte static scratch";
+        return PCG_ENOMEM;
+    }
+    const auto t0 = Clock::now();
+    HostMirror hm;
+    Engine eng;
+    st = eng.init(scr, cap, 1, opts, hip_stream, &hm);
+    if (st) return st;
+    int slot = -1;
+    st = eng.prepare(grid, rho, solid_mask, bc, flags, &slot);
+    if (st) return st;
+    st = eng.start(slot, rhs, p, tol, maxit, flags & PCG_WARM_START);
+    if (st) return st;
+    return run_to_end(eng, slot, t0, stats);
 }
 
 int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,

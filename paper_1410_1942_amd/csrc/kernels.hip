@@ -36,6 +36,8 @@
 #include <type_traits>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "pcg_types.h"
 #include "pcg.h"
 
@@ -2583,6 +2585,37 @@ k_triad(double *__restrict__ a, const double *__restrict__ b, const double *__re
 // ------------------------------------------------------------------------
 // host-callable launchers
 // ------------------------------------------------------------------------
+
+// Device memory of the allocation-free entry point (pcg_solve_static): the
+// slot table, slot state and one solve's vectors live here instead of in a
+// caller's workspace.  Each device the library runs on holds its own copy
+// until the process ends; host code reaches it only through the address
+// static_scratch returns (the array's name is not a device address on the
+// host).
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+// Address and size of the current device's copy of `scratch`, looked up once
+// per device (with that device current) and kept.
+hipError_t static_scratch(void **ptr, size_t *bytes)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = a;
+    }
+    *ptr = addr[dev];
+    *bytes = kStaticScratchBytes;
+    return hipSuccess;
+}
 
 hipError_t launch_iter(int family, int which, int mode, int grid,
                        const BatchHeader *hdr, const Slot *slots, hipStream_t s)

@@ -17,6 +17,9 @@ constexpr int kMaxPartials = 3;   // reduction values per tile
 constexpr int kTileX = 128;
 constexpr int kTileY = 4;
 
+// Bytes of the device array behind the allocation-free entry point.
+constexpr unsigned long long kStaticScratchBytes = 64ull << 20;
+
 // Density classes: up to kMaxFluidClasses distinct fluid densities get a
 // one-byte class; kClsWallD stands for a Dirichlet wall (density 0 in the
 // face formula), kClsSolid for hull cells and Neumann walls (density +inf).

@@ -67,6 +67,32 @@ def _field_shape(rho: torch.Tensor):
     return tuple(rho.shape)
 
 
+def solve_static(rho: torch.Tensor, mask: Optional[torch.Tensor], bc, h: float,
+                 rhs: torch.Tensor, p: Optional[torch.Tensor] = None, tol: float = 1e-8,
+                 maxit: int = 1000000, precision: int = L.PREC_FP64, flags: int = 0,
+                 stream: Optional[torch.cuda.Stream] = None, raise_on_error=True, **opt_kw):
+    """One solve through pcg_solve_static: the library's fixed device
+    array serves as workspace, so nothing is allocated (p, when given, is
+    the caller's output tensor).  Returns (p, stats dict)."""
+    lib = L.load()
+    shape = _field_shape(rho)
+    _check(rho, shape, torch.float64, "rho")
+    _check(mask, shape, torch.uint8, "mask", rho.device, optional=True)
+    _check(rhs, shape, torch.float64, "rhs", rho.device)
+    if p is None:
+        p = torch.empty_like(rhs)
+    _check(p, shape, torch.float64, "p", rho.device)
+    opts = make_opts(precision=precision, flags=flags, **opt_kw)
+    st = L.Stats()
+    code = lib.pcg_solve_static(ctypes.byref(_grid(shape, h)), _ptr(rho), _ptr(mask),
+                                ctypes.byref(_bc(bc)), ctypes.byref(opts), _ptr(rhs),
+                                _ptr(p), float(tol), int(maxit), ctypes.byref(st),
+                                _stream_handle(stream))
+    if raise_on_error:
+        L.check(code, "pcg_solve_static")
+    return p, st.as_dict()
+
+
 class Solver:
     """One density field, any number of solves (pcg_setup / pcg_solve).
 
