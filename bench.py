@@ -40,6 +40,22 @@ BYTES_K2 = {("fp64", "classes"): 107 / 3, ("fp64", "density"): 128 / 3,
             ("fp32", "classes"): 55 / 3, ("fp32", "density"): 64 / 3}
 
 
+# Timings the paper reports (Section 3), as context only: whole time steps of
+# the full flow solver (two pressure solves plus advection, interface
+# capturing and the rest), on its machines; no Poisson-level number is
+# given, so no ratio to them is formed.
+PAPER_CONTEXT = [
+    {"case": "NACA 0024 strut, 512x128x128 cells", "seconds_per_time_step": 60,
+     "hardware": "512 Cray T3E processors"},
+    {"case": "DDG 5415, 2,097,152 cells", "seconds_per_time_step": 376,
+     "hardware": "32 IBM processors"},
+    {"case": "DDG 5415 with AMR, 5,324,800 cells", "seconds_per_time_step": 1300,
+     "hardware": "32 IBM processors"},
+    {"case": "DDG 5415 with AMR, 17,940,480 cells", "seconds_per_time_step": 3000,
+     "hardware": "64 IBM processors"},
+]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -54,11 +70,19 @@ def parse():
     ap.add_argument("--no-ir", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters", type=int, default=40,
+                    help="oracle iterations timed on the full-size input")
+    ap.add_argument("--cpu-iters-256", type=int, default=100,
+                    help="oracle iterations timed on the 256^3 wedge input")
     ap.add_argument("--no-project", action="store_true")
     ap.add_argument("--no-rk2", action="store_true")
     ap.add_argument("--no-side", action="store_true",
                     help="skip the 256^3 wedge and strut single-solve legs")
+    ap.add_argument("--no-tight", action="store_true",
+                    help="skip the solves at the tolerance that meets the 1e-6 error bar")
+    ap.add_argument("--tight-tol", type=float, default=1e-9)
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the mollified-interface (per-cell density) leg")
     ap.add_argument("--rk2-shift", type=float, default=0.025,
                     help="surface phase advance (rad) that gives rho(phi*); "
                          "0.025 moves the 512^3 surface by at most about one cell")
@@ -256,6 +280,7 @@ def main():
         ir_ms = (time.perf_counter() - t) * 1e3
         err = (pir - p64).abs().max().item() / p64.abs().max().item()
         out["ir"] = {
+            "tol": args.tol,
             "ms_per_step": round(ir_ms, 2),
             "inner_iters": stir["iters"], "outer_iters": stir["outer_iters"],
             "rel_res_true": stir["rel_res_true"],
@@ -266,18 +291,40 @@ def main():
         log(f"  {ir_ms:.1f} ms, {stir['iters']} inner / {stir['outer_iters']} outer, "
             f"err vs fp64 {err:.2e}")
 
+    # error against the oracle's own 1e-12 solution, read at its stored
+    # strided sample (written by tests/golden/make_fullsize_golden.py)
+    gold = golden_reference(n, case)
+    if gold is not None:
+        meta, ref = gold
+        out["max_err_vs_oracle"] = err_vs_golden(p64, meta, ref)
+        if "ir" in out:
+            out["ir"]["max_err_vs_oracle"] = err_vs_golden(pir, meta, ref)
+        out["oracle_reference"] = {"tol": meta["tol"], "iters": meta["iters"],
+                                   "relres": meta["relres"],
+                                   "sample": f"every {meta['stride']}th cell per axis"}
+        log(f"  max err vs oracle: fp64 {out['max_err_vs_oracle']:.2e}"
+            + (f", ir {out['ir']['max_err_vs_oracle']:.2e}" if "ir" in out else ""))
+        if not args.no_tight:
+            out["tight_tol"] = bench_tight(rho, mask, rhs, case, args.tight_tol, meta, ref,
+                                           not args.no_ir)
+    out["paper_context"] = PAPER_CONTEXT
+
     # CPU reference on the host cores: a bounded number of iterations
     if not args.no_cpu:
         import oracle
         log("cpu baseline")
+
+        def cpu_rate(c, k):
+            t = time.perf_counter()
+            oracle.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-30, maxit=1)
+            ta = time.perf_counter() - t
+            t = time.perf_counter()
+            oracle.pcg(c.rho, c.mask, c.bc, c.h, c.rhs, tol=1e-30, maxit=1 + k)
+            tb = time.perf_counter() - t
+            return c.ncells * k / max(tb - ta, 1e-9) / 1e9, ta
+
         k = args.cpu_iters
-        t = time.perf_counter()
-        oracle.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=1)
-        ta = time.perf_counter() - t
-        t = time.perf_counter()
-        oracle.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=1 + k)
-        tb = time.perf_counter() - t
-        cpu_val = cells * k / max(tb - ta, 1e-9) / 1e9
+        cpu_val, ta = cpu_rate(case, k)
         out["cpu_baseline"] = {
             "value": round(cpu_val, 5), "unit": "Gcell-iter/s",
             "cores": oracle.threads(), "kind": "oracle",
@@ -288,6 +335,13 @@ def main():
             "host_cpus": len(os.sched_getaffinity(0)),
             "host_triad_GBps": round(oracle.host_triad(), 1),
         }
+        if args.cpu_iters_256 > 0:
+            c2 = F.config_wedge(256, keep_velocity=False)
+            v2, _ = cpu_rate(c2, args.cpu_iters_256)
+            out["cpu_baseline"]["wedge256_Gcell_iter_per_s"] = round(v2, 5)
+            out["cpu_baseline"]["wedge256_sample"] = (
+                f"{args.cpu_iters_256} PCG iterations on the 256^3 wedge input")
+            del c2
         # relative residual of the GPU solutions recomputed by the reference
         out["rel_res_oracle"] = oracle.relres(case.rho, case.mask, case.bc, case.h,
                                               case.rhs, p64.cpu().numpy())
@@ -307,8 +361,14 @@ def main():
             ref = oracle.pcg(c1.rho, c1.mask, c1.bc, c1.h, c1.rhs, tol=args.tol)
             out["flat32"]["oracle_solve_ms"] = round((time.perf_counter() - t) * 1e3, 2)
             out["flat32"]["oracle_iters"] = int(ref.iters)
-        out["wedge256"] = bench_single(F.config_wedge(256, keep_velocity=False), args.tol, dev,
-                                       "256^3 two-phase tank + wedge hull, FP64")
+        c256 = F.config_wedge(256, keep_velocity=False)
+        out["wedge256"], p256 = bench_single(c256, args.tol, dev,
+                                             "256^3 two-phase tank + wedge hull, FP64",
+                                             want_p=True)
+        g256 = golden_reference(256, c256)
+        if g256 is not None:
+            out["wedge256"]["max_err_vs_oracle"] = err_vs_golden(p256, *g256)
+        del c256, p256
         out["strut"] = bench_single(F.config_strut(keep_velocity=False), args.tol, dev,
                                     "strut tank 512x128x128 (NACA 0024, periodic x, "
                                     "no-flux walls: singular), FP64")
@@ -316,6 +376,8 @@ def main():
             F.make_two_phase(256, 256, 256, surface_seed=1, velocity_seed=2, wedge=F.Wedge(),
                              keep_velocity=False, fractions=True), args.tol, dev,
             "256^3 two-phase tank + wedge as free-slip cut cells (area/volume fractions), FP64")
+    if not args.no_density:
+        out["density512"] = bench_density(n, args.tol, dev, not args.no_ir)
     if not args.no_project:
         out["projection"] = bench_project(case, rho, mask, p64, dev)
         if not args.no_rk2:
@@ -329,7 +391,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_single(case, tol, dev, what):
+def bench_single(case, tol, dev, what, want_p=False):
     """One more single solve (set-up excluded, timed on the host around a
     synchronised solve after a warm-up solve), its iteration count and the
     oracle's recomputed residual of the answer."""
@@ -356,12 +418,8 @@ def bench_single(case, tol, dev, what):
     s.close()
     pn = p.cpu().numpy()
     fluid = case.mask == 0
-    ref_rhs = case.rhs.copy()
     singular = 1 not in case.bc
-    if singular:
-        vol = frac[3] if frac is not None else np.ones_like(ref_rhs)
-        ref_rhs[fluid] -= (vol * ref_rhs)[fluid].mean() / vol[fluid]
-    rr = oracle.relres(case.rho, case.mask, case.bc, case.h, ref_rhs, pn, frac=frac)
+    rr = oracle.relres(case.rho, case.mask, case.bc, case.h, case.rhs, pn, frac=frac)
     g = case.ncells * st["iters"] / dt / 1e9
     log(f"  {st['iters']} iters, {dt*1e3:.1f} ms, {g:.2f} Gcell-iter/s, oracle relres {rr:.3e}")
     out = {"workload": what, "grid": [case.nx, case.ny, case.nz], "cells": case.ncells,
@@ -369,6 +427,116 @@ def bench_single(case, tol, dev, what):
            "rel_res_oracle": rr, "density_classes": classes}
     if singular:
         out["fluid_mean_of_p"] = float(pn[fluid].mean())
+    return (out, pn) if want_p else out
+
+
+def golden_reference(n, case):
+    """(metadata, sample) of the oracle's stored 1e-12 solution of the n^3
+    wedge tank, or None when none is stored or its inputs differ from
+    `case` (checked by digest)."""
+    import hashlib
+    import numpy as np
+    base = os.path.join(ROOT, "tests", "golden", f"wedge{n}_oracle")
+    if not (os.path.exists(base + ".json") and os.path.exists(base + ".npy")):
+        return None
+    meta = json.load(open(base + ".json"))
+    if case is not None:
+        h = hashlib.sha256()
+        for a in (case.rho, case.mask, case.rhs):
+            h.update(np.ascontiguousarray(a).tobytes())
+        if h.hexdigest() != meta["input_sha256"]:
+            return None
+    return meta, np.load(base + ".npy")
+
+
+def err_vs_golden(p, meta, ref):
+    """max |p - p_oracle| / max |p_oracle| over the stored sample cells."""
+    import numpy as np
+    import torch
+    o, st = meta["offset"], meta["stride"]
+    if isinstance(p, torch.Tensor):
+        p = p[o::st, o::st, o::st].cpu().numpy()
+    else:
+        p = p[o::st, o::st, o::st]
+    return float(np.abs(p - ref).max() / meta["p_max_abs"])
+
+
+def bench_tight(rho, mask, rhs, case, tol, meta, ref, with_ir):
+    """Both forms at the tighter tolerance that meets the 1e-6 error bar at
+    this size (1e-8 does not bound the max-norm error that far here)."""
+    import torch
+    from paper_1410_1942_amd import _lib as L
+    from paper_1410_1942_amd.solver import Solver
+    log(f"tolerance {tol:g}")
+    out = {"tol": tol}
+    for prec, name in ((L.PREC_FP64, "fp64"), (L.PREC_FP32_IR, "ir")):
+        if prec == L.PREC_FP32_IR and not with_ir:
+            continue
+        s = Solver(rho, mask, case.bc, case.h, precision=prec)
+        p = torch.empty_like(rhs)
+        s.solve(rhs, p=p, tol=tol)                       # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = s.solve(rhs, p=p, tol=tol)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        s.close()
+        e = err_vs_golden(p, meta, ref)
+        out[name] = {"ms": round(ms, 2), "iters": st["iters"], "outer_iters": st["outer_iters"],
+                     "rel_res_true": st["rel_res_true"], "max_err_vs_oracle": e,
+                     "Gcell_iter_per_s": round(case.ncells * st["iters"] / (ms * 1e-3) / 1e9, 3)}
+        log(f"  {name}: {st['iters']} iters, {ms:.0f} ms, err vs oracle {e:.2e}")
+        del p
+    return out
+
+
+def bench_density(n, tol, dev, with_ir):
+    """The same tank with the interface smoothed over about 1.5 cells (the
+    paper's mollified step): more distinct densities than classes, so every
+    pass reads the FP64 (FP32) density per cell.  Whole solves plus the
+    event-timed passes and their roofline."""
+    import torch
+    from paper_1410_1942_amd import _lib as L
+    from paper_1410_1942_amd import fields as F
+    from paper_1410_1942_amd.solver import Solver
+    log(f"mollified interface {n}^3")
+    case = F.make_two_phase(n, n, n, surface_seed=1, velocity_seed=2, wedge=F.Wedge(),
+                            mollify=1.5, keep_velocity=False)
+    rho = torch.from_numpy(case.rho).to(dev)
+    mask = torch.from_numpy(case.mask).to(dev)
+    rhs = torch.from_numpy(case.rhs).to(dev)
+    out = {"workload": f"{n}^3 two-phase tank + wedge, interface smoothed over 1.5 cells",
+           "distinct_densities": int(len(torch.unique(rho)))}
+    for prec, name in ((L.PREC_FP64, "fp64"), (L.PREC_FP32_IR, "ir")):
+        if prec == L.PREC_FP32_IR and not with_ir:
+            continue
+        s = Solver(rho, mask, case.bc, case.h, precision=prec)
+        p = torch.empty_like(rhs)
+        s.solve(rhs, p=p, tol=tol)                       # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st = s.solve(rhs, p=p, tol=tol)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3
+        d = {"ms": round(ms, 2), "iters": st["iters"], "outer_iters": st["outer_iters"],
+             "rel_res_true": st["rel_res_true"], "coefficients":
+             "classes" if s.density_classes() else "density",
+             "Gcell_iter_per_s": round(case.ncells * st["iters"] / (ms * 1e-3) / 1e9, 3)}
+        if prec == L.PREC_FP64:
+            s.set_timing(True)
+            s.solve(rhs, p=p, tol=tol, maxit=300)
+            k1, k2, _ = s.last_timing()
+            mode = d["coefficients"]
+            b1, b2 = BYTES_K1[("fp64", mode)], BYTES_K2[("fp64", mode)]
+            d["kernel_k1"] = {"avg_ms": round(k1, 4),
+                              "achieved_GBps": round(b1 * case.ncells / (k1 * 1e-3) / 1e9, 1)}
+            d["kernel_k2"] = {"avg_ms": round(k2, 4),
+                              "achieved_GBps": round(b2 * case.ncells / (k2 * 1e-3) / 1e9, 1)}
+            d["frac_k2"] = round(d["kernel_k2"]["achieved_GBps"] / HBM_PEAK_GBS, 4)
+        s.close()
+        out[name] = d
+        log(f"  {name}: {st['iters']} iters, {ms:.0f} ms, {d['Gcell_iter_per_s']:.1f} Gcell-iter/s")
+        del p
     return out
 
 

@@ -116,14 +116,18 @@ enum {
     PCG_FRACTIONS = 8,               /* reserve workspace for free-slip cut-cell
                                         fractions (pcg_set_fractions; single
                                         contexts only)                       */
-    PCG_FLAT_TILES = 16              /* keep tiles of consecutive cells: by
-                                        default an FP64 grid whose rows are a
-                                        multiple of 128 cells (and whose
-                                        periodic axes hold whole 128 x 4
-                                        tiles) runs 128 x 4 plane tiles with
-                                        the operator's in-plane neighbours
-                                        staged in LDS; same operator, another
-                                        summation order                      */
+    PCG_FLAT_TILES = 16,             /* keep tiles of consecutive cells: by
+                                        default an FP64 grid of at least 2^25
+                                        cells whose rows are a multiple of 128
+                                        cells (and whose periodic axes hold
+                                        whole 128 x 4 tiles) runs 128 x 4
+                                        plane tiles with the operator's
+                                        in-plane neighbours staged in LDS;
+                                        same operator, another summation
+                                        order                                */
+    PCG_PLANE_TILES = 32             /* use the 128 x 4 plane tiles on any
+                                        grid that allows them, whatever its
+                                        size (PCG_FLAT_TILES wins if both)   */
 };
 
 /*
@@ -133,7 +137,8 @@ enum {
  *               and solution update (iterative refinement).
  *   check_every iterations per captured graph replay between host polls [32]
  *   flags       PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK |
- *               PCG_NO_DENSITY_CLASSES | PCG_FRACTIONS | PCG_FLAT_TILES
+ *               PCG_NO_DENSITY_CLASSES | PCG_FRACTIONS | PCG_FLAT_TILES |
+ *               PCG_PLANE_TILES
  *   inner_maxit FP32_IR: cap on inner iterations per refinement trip [none]
  *   inner_tol   FP32_IR: relative reduction asked of each inner solve, never
  *               more than the last refinement trip needs [1e-4]

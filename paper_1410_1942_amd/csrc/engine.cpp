@@ -201,9 +201,16 @@ struct Geometry {
 // and a periodic y axis holding whole tiles (periodic x always does).  With
 // the walls unknown (bc null: workspace sizing) the y condition is assumed
 // met, which sizes for the larger tile count.
+// Smallest grid that takes the plane tiles by default: measured on the
+// 512^3 wedge they save 6 % of an iteration; on 256^3 they tie with the
+// consecutive-cell tiles and on the 512 x 128 x 128 strut they lose 11 %.
+constexpr int64_t kPlaneTileMinCells = int64_t(1) << 25;
+
 bool plane_tiles_2d(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc)
 {
     if (prec != PCG_PREC_FP64 || (flags & (PCG_FLAT_TILES | PCG_FRACTIONS))) return false;
+    if (!(flags & PCG_PLANE_TILES) && (int64_t)g.nx * g.ny * g.nz < kPlaneTileMinCells)
+        return false;
     if (g.nx % kTileX != 0) return false;
     if (bc && bc->kind[2] == PCG_BC_PERIODIC && g.ny > 1 && g.ny % kTileY != 0) return false;
     return true;
@@ -313,7 +320,7 @@ int check_opts(const pcg_opts_t *o)
     if (o->check_every < 0 || o->inner_maxit < 0 || o->tz < 0 || o->grid_blocks < 0) return PCG_EINVAL;
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0 || std::isnan(o->inner_tol)) return PCG_EINVAL;
     if (o->flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES |
-                     PCG_FRACTIONS | PCG_FLAT_TILES))
+                     PCG_FRACTIONS | PCG_FLAT_TILES | PCG_PLANE_TILES))
         return PCG_EINVAL;
     return PCG_OK;
 }
@@ -868,8 +875,12 @@ struct Engine {
                 const float sf = (float)rho[a] + (float)rho[b];
                 t32[a * kClasses + b] = live && std::isfinite(sf) && sf > 0.0f ? 2.0f / sf : 0.0f;
             }
-        HIP_TRY(hipMemcpy(S.tab64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(S.tab32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice));
+        // on the engine's stream (not the null stream, which would wait for
+        // every other stream of the device); the host tables live until the
+        // copies have finished
+        HIP_TRY(hipMemcpyAsync(S.tab64, t64.data(), t64.size() * 8, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipMemcpyAsync(S.tab32, t32.data(), t32.size() * 4, hipMemcpyHostToDevice, stream));
+        HIP_TRY(hipStreamSynchronize(stream));
         S.classes = true;
         S.nclasses = (int)pal.size();
         return PCG_OK;
@@ -1573,7 +1584,8 @@ int pcg_batch_admit(pcg_batch_t *b, const pcg_grid_t *grid, const double *rho,
 {
     if (!b || !slot || !rhs || !p) return PCG_EINVAL;
     if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0) return PCG_EINVAL;
-    if (flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES))
+    if (flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES |
+                  PCG_FLAT_TILES | PCG_PLANE_TILES))
         return PCG_EINVAL;
     int id = -1;
     int st = b->eng.prepare(grid, rho, mask, bc, flags, &id);

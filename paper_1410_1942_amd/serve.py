@@ -3,7 +3,9 @@
 Requests (a density field, optional hull mask, source and tolerance) arrive
 at given times.  The loop admits waiting requests first-in first-out while
 the batch's arena has room for their footprint and a slot is free
-(``pcg_batch_admit`` refuses with PCG_EBUSY otherwise), replays the captured
+(``pcg_batch_admit`` refuses with PCG_EBUSY otherwise), with a bounded
+bypass: requests behind a head that does not fit may go first, a limited
+number of times per head (``AdmissionQueue``).  It replays the captured
 iterations of every resident solve together (``pcg_batch_step``), and
 retires finished solves as soon as their status turns final, recording the
 latency from arrival to completion.  The pressure of each request stays a
@@ -53,6 +55,56 @@ class Request:
         return self.done - self.arrival
 
 
+ADMITTED, BUSY, REFUSED = "admitted", "busy", "refused"
+
+
+class AdmissionQueue:
+    """Waiting requests, admitted first-in first-out with a bounded bypass.
+
+    ``admit(try_admit)`` offers requests to ``try_admit(r)``, which answers
+    ADMITTED, BUSY (no room or slot now) or REFUSED (the request is invalid
+    and fails alone).  The head is offered first, then the next ones while
+    they are admitted or refused.  When the head is BUSY, up to ``lookahead``
+    requests behind it are offered and those that fit go first; each one
+    that passes counts against the head, and once ``max_bypass`` have passed
+    it nothing more is admitted before it, so a large request cannot starve.
+    Returns the (request, answer) pairs of the requests that left the queue,
+    in the order they left.  Host logic only: no device work."""
+
+    def __init__(self, lookahead: int = 8, max_bypass: int = 16):
+        self.q: collections.deque = collections.deque()
+        self.lookahead = lookahead
+        self.max_bypass = max_bypass
+        self.passed = 0          # requests admitted ahead of the current head
+
+    def __len__(self):
+        return len(self.q)
+
+    def push(self, r):
+        self.q.append(r)
+
+    def admit(self, try_admit):
+        out = []
+        while self.q:
+            ans = try_admit(self.q[0])
+            if ans == BUSY:
+                break
+            out.append((self.q.popleft(), ans))
+            self.passed = 0
+        i = 1
+        while (self.q and i < len(self.q) and i <= self.lookahead
+               and self.passed < self.max_bypass):
+            ans = try_admit(self.q[i])
+            if ans == BUSY:
+                i += 1
+                continue
+            out.append((self.q[i], ans))
+            del self.q[i]
+            if ans == ADMITTED:
+                self.passed += 1
+        return out
+
+
 @dataclasses.dataclass
 class ServeReport:
     n: int
@@ -72,11 +124,14 @@ class ServeReport:
 class Server:
     def __init__(self, arena_bytes: int, max_slots: int = 64,
                  precision: int = L.PREC_FP32_IR, replays_per_step: int = 1,
-                 check_every: int = 16, flags: int = 0, **opt_kw):
+                 check_every: int = 16, flags: int = 0, lookahead: int = 8,
+                 max_bypass: int = 16, **opt_kw):
         self.batch = Batch(arena_bytes, max_slots, precision=precision,
                            check_every=check_every, **opt_kw)
         self.replays = replays_per_step
         self.flags = flags
+        self.lookahead = lookahead
+        self.max_bypass = max_bypass
 
     def close(self):
         self.batch.close()
@@ -89,7 +144,7 @@ class Server:
         report, whose window runs from the first reported arrival to the
         last reported completion."""
         reqs = sorted(requests, key=lambda r: r.arrival)
-        waiting: collections.deque = collections.deque()
+        waiting = AdmissionQueue(self.lookahead, self.max_bypass)
         resident = {}                       # slot -> request
         nxt = 0
         max_res = 0
@@ -100,11 +155,10 @@ class Server:
             while nxt < len(reqs) and (not realtime or reqs[nxt].arrival <= now):
                 if not realtime:
                     reqs[nxt].arrival = 0.0
-                waiting.append(reqs[nxt])
+                waiting.push(reqs[nxt])
                 nxt += 1
-            # admit first-in first-out while memory and slots allow
-            while waiting:
-                r = waiting[0]
+
+            def try_admit(r):
                 if r.p is None:
                     r.p = torch.empty_like(r.rhs)
                 try:
@@ -112,17 +166,18 @@ class Server:
                                                   r.p, tol=r.tol, maxit=r.maxit,
                                                   flags=self.flags)
                 except L.PCGError as e:      # refused request fails alone
-                    waiting.popleft()
                     r.status = e.code
                     r.admitted = r.done = clock() - t0
-                    continue
+                    return REFUSED
                 if code == L.EBUSY:
-                    if not resident:
-                        raise RuntimeError("request larger than the arena")
-                    break
-                waiting.popleft()
+                    return BUSY
                 r.admitted = clock() - t0
                 resident[slot] = r
+                return ADMITTED
+
+            waiting.admit(try_admit)
+            if waiting and not resident:
+                raise RuntimeError("request larger than the arena")
             max_res = max(max_res, len(resident))
             if not resident:
                 if nxt < len(reqs):          # idle until the next arrival

@@ -1,8 +1,9 @@
 """The 2-D plane-tile form (128 x 4 tiles, in-plane neighbours staged in
 LDS) of the FP64 passes, through the C ABI, against the oracle.
 
-FP64 grids whose rows are a multiple of 128 cells take this form by default
-(PCG_FLAT_TILES keeps the consecutive-cell tiles).  The cases cover ragged
+FP64 grids of at least 2^25 cells whose rows are a multiple of 128 cells
+take this form by default; PCG_PLANE_TILES asks for it on smaller grids (as
+here) and PCG_FLAT_TILES keeps the consecutive-cell tiles.  The cases cover ragged
 tile rows (ny not a multiple of 4), a single row, every wall kind on every
 side, periodic axes (and the fall-back to consecutive-cell tiles when a
 periodic y axis does not hold whole tiles), hulls, both coefficient sources,
@@ -20,6 +21,7 @@ pytestmark = pytest.mark.gpu
 TANK = (0, 0, 0, 0, 0, 1)
 P = 2
 FLAT_TILES = 16
+PLANE = 32
 NO_CLASSES = 4
 
 
@@ -39,7 +41,7 @@ def _to(torch, dev, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-def _solve(torch_dev, case, tol=1e-8, flags=0, maxit=1000000, **kw):
+def _solve(torch_dev, case, tol=1e-8, flags=PLANE, maxit=1000000, **kw):
     torch, dev = torch_dev
     from paper_1410_1942_amd.solver import Solver
     s = Solver(_to(torch, dev, case.rho), _to(torch, dev, case.mask), case.bc, case.h,
@@ -68,7 +70,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("shape,bc,wedge", CASES, ids=lambda v: str(v))
-@pytest.mark.parametrize("flags", [0, NO_CLASSES], ids=["classes", "density"])
+@pytest.mark.parametrize("flags", [PLANE, PLANE | NO_CLASSES], ids=["classes", "density"])
 def test_plane_tile_parity(orc, F, torch_dev, shape, bc, wedge, flags):
     case = _case(F, shape, bc, wedge)
     _say(f"case plane tiles {shape} bc={bc} wedge={wedge} flags={flags}")
@@ -145,7 +147,7 @@ def test_plane_tiles_in_a_batch(F, torch_dev):
             for c in members:
                 p = torch.empty(c.shape, dtype=torch.float64, device=dev)
                 code, slot = b.admit(_to(torch_, dev, c.rho), _to(torch_, dev, c.mask), c.bc,
-                                     c.h, _to(torch_, dev, c.rhs), p, tol=1e-8)
+                                     c.h, _to(torch_, dev, c.rhs), p, tol=1e-8, flags=PLANE)
                 assert code == L.OK, code
                 outs.append((slot, p))
             while b.step(1):
