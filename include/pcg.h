@@ -118,16 +118,17 @@ enum {
                                         contexts only)                       */
     PCG_FLAT_TILES = 16,             /* keep tiles of consecutive cells: by
                                         default an FP64 grid of at least 2^25
-                                        cells whose rows are a multiple of 128
-                                        cells (and whose periodic axes hold
-                                        whole 128 x 4 tiles) runs 128 x 4
-                                        plane tiles with the operator's
-                                        in-plane neighbours staged in LDS;
-                                        same operator, another summation
-                                        order                                */
-    PCG_PLANE_TILES = 32             /* use the 128 x 4 plane tiles on any
-                                        grid that allows them, whatever its
-                                        size (PCG_FLAT_TILES wins if both)   */
+                                        cells whose rows are a multiple of
+                                        128 cells and whose periodic axes
+                                        hold whole tiles runs 128 x 4 plane
+                                        tiles with the operator's in-plane
+                                        neighbours staged in LDS; same
+                                        operator, another summation order   */
+    PCG_PLANE_TILES = 32             /* use the plane tiles on any grid that
+                                        allows them, whatever its size, also
+                                        for FP32_IR (256 x 4 tiles, rows a
+                                        multiple of 256; PCG_FLAT_TILES wins
+                                        if both)                             */
 };
 
 /*

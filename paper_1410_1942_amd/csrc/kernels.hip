@@ -1093,117 +1093,107 @@ __device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
 }
 
 // ------------------------------------------------------------------------
-// LDS-staged pass B on 2-D plane tiles (FP64, two cells per thread)
+// LDS-staged passes on 2-D plane tiles (N = 2 FP64 or 4 FP32 cells per thread)
 // ------------------------------------------------------------------------
-// A tile is kTileX columns x kTileY rows x tz planes; thread l owns the pair
-// of cells (2l mod kTileX, 2l / kTileX) of the tile.  Per plane the tile's
+// A tile is TX = N kBlock / kTileY columns x kTileY rows x tz planes (128 x 4
+// for FP64, 256 x 4 for FP32); thread l owns the group of N cells
+// (N l mod TX, N l / TX) of the tile.  Per plane the tile's
 // direction values and coefficient keys, with a one-cell x-y halo, are
 // written to LDS (two plane buffers, one barrier per plane) and every cell
 // reads its four in-plane neighbours from there; z neighbours are carried in
 // registers.  Global traffic per pair and plane is then the pair's values
 // and keys one plane up and its z (plus x and the two earlier directions in
 // the catch-up form), instead of also loading the y rows above and below
-// and the columns beside it: the y-halo rows (kTileX cells each) are loaded
-// by threads 0 .. kTileX - 1, the x-halo columns (kTileY cells each) by the
+// and the columns beside it: the y-halo rows (TX cells each) are loaded by
+// threads 0 .. 2 TX / N - 1, the x-halo columns (kTileY cells each) by the
 // next 2 kTileY threads.  Lanes past the grid's edge load clamped cells,
 // take part in the barriers and store nothing.  The set-up keeps this form
 // to grids whose periodic axes hold whole tiles, so a wrapped neighbour is
 // always a halo cell.
-constexpr int kLdsW = kTileX + 4;   // LDS row: pad, left halo, kTileX cells, right halo, pad
+template <int N> constexpr int tile_x() { return N * kBlock / kTileY; }
+// LDS row: N - 1 pad cells, the left halo, TX cells, the right halo, N - 1
+// pad cells, so every group of N cells is aligned to its size
+template <int N> constexpr int lds_w() { return tile_x<N>() + 2 * N; }
 constexpr int kLdsR = kTileY + 2;   // LDS rows: lower halo, kTileY rows, upper halo
-static_assert(kTileX * kTileY == 2 * kBlock && kTileX + 2 * kTileY <= kBlock,
-              "a pair of cells per thread; the halo loads fit the workgroup");
+static_assert(tile_x<2>() == kTileX && 2 * tile_x<2>() / 2 + 2 * kTileY <= kBlock &&
+              2 * tile_x<4>() / 4 + 2 * kTileY <= kBlock,
+              "the halo loads fit the workgroup");
 
-template <typename T, typename KE>
+template <typename T, typename KE, int N>
 struct LdsPlanes {
-    T v[2][kLdsR * kLdsW];
-    KE k[2][kLdsR * kLdsW];
+    T v[2][kLdsR * lds_w<N>()];
+    KE k[2][kLdsR * lds_w<N>()];
 };
 
-// One LDS buffer set per value and key type, shared by the two forms of pass B.
-template <typename T, typename KE>
-__device__ __forceinline__ LdsPlanes<T, KE> &lds_planes()
+// One LDS buffer set per value type, key type and group width, shared by
+// the forms of the passes in one kernel.
+template <typename T, typename KE, int N>
+__device__ __forceinline__ LdsPlanes<T, KE, N> &lds_planes()
 {
-    __shared__ __attribute__((aligned(16))) LdsPlanes<T, KE> s;
+    __shared__ __attribute__((aligned(16))) LdsPlanes<T, KE, N> s;
     return s;
 }
 
-// Two adjacent LDS elements (even index) from / to two keys or values.
-template <typename E, typename K>
-__device__ __forceinline__ void lds_put2(E *a, K k0, K k1)
-{
-    if constexpr (std::is_same<E, uint8_t>::value) {
-        *(uint16_t *)a = (uint16_t)(((unsigned)k0 & 0xffu) | (((unsigned)k1 & 0xffu) << 8));
-    } else {
-        using V = typename VecN<E, 2>::type;
-        V v;
-        v[0] = (E)k0;
-        v[1] = (E)k1;
-        *(V *)a = v;
-    }
-}
-template <typename E, typename K>
-__device__ __forceinline__ void lds_get2(const E *a, K (&k)[2])
-{
-    if constexpr (std::is_same<E, uint8_t>::value) {
-        const unsigned h = *(const uint16_t *)a;
-        k[0] = (K)(h & 0xffu);
-        k[1] = (K)(h >> 8);
-    } else {
-        using V = typename VecN<E, 2>::type;
-        const V v = *(const V *)a;
-        k[0] = (K)v[0];
-        k[1] = (K)v[1];
-    }
-}
-
-// A pair of keys as one load returns it (two class bytes, or two
+// A group of N keys as one load returns it (N class bytes, or N
 // densities), split into keys only where they are used: splitting right
 // after the load would make the wave wait for it before the plane's barrier.
-template <class C> struct KeyPair;
-template <typename T> struct KeyPair<ClsCoef<T>> {
+template <class C, int N> struct KeyGroup;
+template <typename T, int N> struct KeyGroup<ClsCoef<T>, N> {
+    using W = typename std::conditional<N == 2, uint16_t, uint32_t>::type;
     using raw = unsigned;
     static __device__ __forceinline__ raw load(const ClsCoef<T> &cf, int64_t c)
     {
-        return ((const GLB uint16_t *)cf.cls)[c / 2];
+        return ((const GLB W *)cf.cls)[c / N];
     }
-    static __device__ __forceinline__ void split(raw r, int (&k)[2])
+    static __device__ __forceinline__ void split(raw r, int (&k)[N])
     {
-        k[0] = (int)(r & 0xffu);
-        k[1] = (int)((r >> 8) & 0xffu);
+#pragma unroll
+        for (int n = 0; n < N; ++n) k[n] = (int)((r >> (8 * n)) & 0xffu);
     }
-    static __device__ __forceinline__ void put(uint8_t *a, raw r) { *(uint16_t *)a = (uint16_t)r; }
-    static __device__ __forceinline__ raw get(const uint8_t *a) { return *(const uint16_t *)a; }
+    static __device__ __forceinline__ void put(uint8_t *a, raw r) { *(W *)a = (W)r; }
+    static __device__ __forceinline__ raw get(const uint8_t *a) { return *(const W *)a; }
 };
-template <typename T> struct KeyPair<RhoCoef<T>> {
-    using raw = typename VecN<T, 2>::type;
+template <typename T, int N> struct KeyGroup<RhoCoef<T>, N> {
+    using raw = typename VecN<T, N>::type;
     static __device__ __forceinline__ raw load(const RhoCoef<T> &cf, int64_t c)
     {
-        return ((const GLB raw *)cf.rho)[c / 2];
+        return ((const GLB raw *)cf.rho)[c / N];
     }
-    static __device__ __forceinline__ void split(raw r, T (&k)[2])
+    static __device__ __forceinline__ void split(raw r, T (&k)[N])
     {
-        k[0] = r[0];
-        k[1] = r[1];
+#pragma unroll
+        for (int n = 0; n < N; ++n) k[n] = r[n];
     }
     static __device__ __forceinline__ void put(T *a, raw r) { *(raw *)a = r; }
     static __device__ __forceinline__ raw get(const T *a) { return *(const raw *)a; }
 };
 
-template <typename T, typename X, class C, int XM>
+// Element `sel` of a group (a select chain, no indexed register access).
+template <typename E, int N, typename G>
+__device__ __forceinline__ E pick(const G &g, int sel)
+{
+    E e = g[0];
+#pragma unroll
+    for (int n = 1; n < N; ++n) e = sel == n ? g[n] : e;
+    return e;
+}
+
+template <typename T, typename X, class C, int XM, int N>
 __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const C &cf,
                           double (&acc)[3])
 {
-    constexpr int N = 2;
+    constexpr int TX = tile_x<N>(), W = lds_w<N>();
     using K = typename C::Key;
     using KE = typename KeyElem<C>::type;
-    using KP = KeyPair<C>;
+    using KP = KeyGroup<C, N>;
     using KR = typename KP::raw;
     using V = typename VecN<T, N>::type;
-    LdsPlanes<T, KE> &L = lds_planes<T, KE>();
+    using XV = typename VecN<X, N>::type;
+    constexpr bool kXGroup = std::is_same<X, float>::value;   // d: ours, aligned
+    LdsPlanes<T, KE, N> &L = lds_planes<T, KE, N>();
     const int l = (int)threadIdx.x;
     const TileCtx t = group_ctx(S, lt);
-    const int ii = (N * l) % kTileX, jj = (N * l) / kTileX;
+    const int ii = (N * l) % TX, jj = (N * l) / TX;
     const int ti0 = t.i - ii, tj0 = t.j - jj;       // the tile's first column and row
     const int nx = S.nx, ny = S.ny, nz = S.nz, bm = S.bcmask;
     const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
@@ -1212,42 +1202,42 @@ __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const 
     const GLB T *__restrict__ p = gp((const T *)dir_buf(S, pbuf));
     const GLB T *__restrict__ pp1 = gp((const T *)dir_buf(S, dir_prev(pbuf)));
     const GLB T *__restrict__ pp0 = gp((const T *)dir_buf(S, dir_next(pbuf)));
-    GLB X *__restrict__ x = gp((X *)S.x);
+    GLB X *__restrict__ x = gp(std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32);
     const GLB V *__restrict__ pv = (const GLB V *)p;
     const GLB V *__restrict__ pv0 = (const GLB V *)pp0;
     const GLB V *__restrict__ pv1 = (const GLB V *)pp1;
     GLB V *__restrict__ zv = (GLB V *)gp((T *)S.z);
     const T alpha = (T)st.alpha;
     const T alpha_p0 = (T)st.alpha_p0, alpha_p1 = (T)st.alpha_p1;
-    // this lane's pair, clamped into the grid for lanes past its edge
+    // this lane's group, clamped into the grid for lanes past its edge
     const int64_t qo = (int64_t)min(t.j, ny - 1) * nx + min(t.i, nx - N);
-    const int own = (jj + 1) * kLdsW + ii + 2;
-    // halo role: a pair of the row below or above the tile, or one cell of
+    const int own = (jj + 1) * W + ii + N;
+    // halo role: a group of the row below or above the tile, or one cell of
     // the column left or right of it (wrapped on periodic axes, clamped at
-    // walls, where the cells that would use it substitute the wall)
-    // (an x-halo cell comes with the other cell of its aligned pair)
-    const bool yh = l < kTileX;
-    const bool xh = !yh && l < kTileX + 2 * kTileY;
-    int64_t qh = qo;       // pair-aligned source; lanes without a role reload their own
+    // walls, where the cells that would use it substitute the wall); an
+    // x-halo cell comes with the other cells of its aligned group
+    const bool yh = l < 2 * TX / N;
+    const bool xh = !yh && l < 2 * TX / N + 2 * kTileY;
+    int64_t qh = qo;       // group-aligned source; lanes without a role reload their own
     int hsel = 0, hslot = 0;
     if (yh) {
-        const int up = l / (kTileX / N), hi = N * (l % (kTileX / N));
+        const int up = l / (TX / N), hi = N * (l % (TX / N));
         int jy = up ? tj0 + kTileY : tj0 - 1;
         jy = py ? (jy + ny) % ny : max(0, min(ny - 1, jy));
         qh = (int64_t)jy * nx + min(ti0 + hi, nx - N);
-        hslot = (up ? kTileY + 1 : 0) * kLdsW + hi + 2;
+        hslot = (up ? kTileY + 1 : 0) * W + hi + N;
     } else if (xh) {
-        const int c = l - kTileX, right = c / kTileY, hj = c % kTileY;
-        int ix = right ? ti0 + kTileX : ti0 - 1;
+        const int c = l - 2 * TX / N, right = c / kTileY, hj = c % kTileY;
+        int ix = right ? ti0 + TX : ti0 - 1;
         ix = px ? (ix + nx) % nx : max(0, min(nx - 1, ix));
         const int64_t q1 = (int64_t)min(tj0 + hj, ny - 1) * nx + ix;
-        qh = q1 & ~(int64_t)1;
-        hsel = (int)(q1 & 1);
-        hslot = (hj + 1) * kLdsW + (right ? kTileX + 2 : 1);
+        qh = q1 & ~(int64_t)(N - 1);
+        hsel = (int)(q1 & (N - 1));
+        hslot = (hj + 1) * W + (right ? TX + N : N - 1);
     }
     // the waves holding halo lanes load in every lane (no divergent branch
     // around loads whose results must stay in flight); the others skip
-    const bool hwave = __builtin_amdgcn_readfirstlane(l) < kTileX + 2 * kTileY;
+    const bool hwave = __builtin_amdgcn_readfirstlane(l) < 2 * TX / N + 2 * kTileY;
     const int i0 = t.i, j = t.j;
     const bool hxm = i0 > 0 || px, hxp = i0 + N - 1 < nx - 1 || px;
     const bool hym = j > 0 || py, hyp = j < ny - 1 || py;
@@ -1257,7 +1247,7 @@ __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const 
     const K wyp = (bm & 8) ? cf.dirichlet() : cf.neumann();
     const K wzm = (bm & 16) ? cf.dirichlet() : cf.neumann();
     const K wzp = (bm & 32) ? cf.dirichlet() : cf.neumann();
-    // halo values of a plane as loaded (a pair)
+    // halo values of a plane as loaded (a group)
     struct Halo {
         V v;
         KR kp;
@@ -1275,15 +1265,17 @@ __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const 
     K kc[N], kzm[N];
     V vcv = pv[(c + qo) / N];
     KR kcr = KP::load(cf, c + qo);
-    vc[0] = vcv[0];
-    vc[1] = vcv[1];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        vc[n] = vcv[n];
+        vzm[n] = T(0);
+        kzm[n] = wzm;
+    }
     KP::split(kcr, kc);
-    vzm[0] = vzm[1] = T(0);
-    kzm[0] = kzm[1] = wzm;
     if (t.k0 > 0) {
         const V v = pv[(c - P + qo) / N];
-        vzm[0] = v[0];
-        vzm[1] = v[1];
+#pragma unroll
+        for (int n = 0; n < N; ++n) vzm[n] = v[n];
         KP::split(KP::load(cf, c - P + qo), kzm);
     }
     Halo h = load_halo(c);
@@ -1295,7 +1287,7 @@ __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const 
         const int b = (k - t.k0) & 1;
         T *Lv = L.v[b];
         KE *Lk = L.k[b];
-        // stage plane k: this lane's pair and its halo cells, as loaded
+        // stage plane k: this lane's group and its halo cells, as loaded
         *(V *)(Lv + own) = vcv;
         KP::put(Lk + own, kcr);
         if (yh) {
@@ -1304,8 +1296,8 @@ __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const 
         } else if (xh) {
             K hk[N];
             KP::split(h.kp, hk);
-            Lv[hslot] = hsel ? h.v[1] : h.v[0];
-            Lk[hslot] = (KE)(hsel ? hk[1] : hk[0]);
+            Lv[hslot] = pick<T, N>(h.v, hsel);
+            Lk[hslot] = (KE)pick<K, N>(hk, hsel);
         }
         // loads for the next plane and this plane's vectors, left unsplit
         // and unused until after the barrier so they stay in flight across it
@@ -1315,19 +1307,30 @@ __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const 
         const KR kzpr = KP::load(cf, cn + qo);
         const Halo hn = load_halo(cn);
         const V zc = __builtin_nontemporal_load(&zv[(c + qo) / N]);
-        X xo[N] = { X(0), X(0) };
-        V v0 = { T(0), T(0) }, v1 = { T(0), T(0) };
-        if (XM == 3) {
+        X xo[N];
+        V v0, v1;
 #pragma unroll
-            for (int n = 0; n < N; ++n) xo[n] = __builtin_nontemporal_load(&x[c + qo + n]);
+        for (int n = 0; n < N; ++n) {
+            xo[n] = X(0);
+            v0[n] = v1[n] = T(0);
+        }
+        if (XM == 3) {
+            if constexpr (kXGroup) {
+                const XV xv = __builtin_nontemporal_load(&((GLB XV *)x)[(c + qo) / N]);
+#pragma unroll
+                for (int n = 0; n < N; ++n) xo[n] = xv[n];
+            } else {
+#pragma unroll
+                for (int n = 0; n < N; ++n) xo[n] = __builtin_nontemporal_load(&x[c + qo + n]);
+            }
             v0 = __builtin_nontemporal_load(&pv0[(c + qo) / N]);
             v1 = __builtin_nontemporal_load(&pv1[(c + qo) / N]);
         }
         __syncthreads();
-        const V vym = *(const V *)(Lv + own - kLdsW), vyp = *(const V *)(Lv + own + kLdsW);
+        const V vym = *(const V *)(Lv + own - W), vyp = *(const V *)(Lv + own + W);
         K kym[N], kyp[N], kzp[N];
-        KP::split(KP::get(Lk + own - kLdsW), kym);
-        KP::split(KP::get(Lk + own + kLdsW), kyp);
+        KP::split(KP::get(Lk + own - W), kym);
+        KP::split(KP::get(Lk + own + W), kyp);
         KP::split(kzpr, kzp);
         const T lvxm = Lv[own - 1], lvxp = Lv[own + N];
         const K lkxm = (K)Lk[own - 1], lkxp = (K)Lk[own + N];
@@ -1350,12 +1353,19 @@ __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const 
         }
         if (t.active) {
             if (XM == 3) {
+                if constexpr (kXGroup) {
+                    XV xv;
 #pragma unroll
-                for (int n = 0; n < N; ++n) __builtin_nontemporal_store(xn[n], &x[c + qo + n]);
+                    for (int n = 0; n < N; ++n) xv[n] = xn[n];
+                    __builtin_nontemporal_store(xv, &((GLB XV *)x)[(c + qo) / N]);
+                } else {
+#pragma unroll
+                    for (int n = 0; n < N; ++n) __builtin_nontemporal_store(xn[n], &x[c + qo + n]);
+                }
             }
             V zv_n;
-            zv_n[0] = zn[0];
-            zv_n[1] = zn[1];
+#pragma unroll
+            for (int n = 0; n < N; ++n) zv_n[n] = zn[n];
             __builtin_nontemporal_store(zv_n, &zv[(c + qo) / N]);
         }
         // the top plane's neighbour above is the wall: its staged copy is
@@ -1377,27 +1387,27 @@ __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const 
 }
 
 // Pass A on 2-D plane tiles with LDS staging: p = z + beta p_old for the
-// tile's pairs, stored, and written to LDS together with the keys; the row
-// below the tile (threads 0 .. kTileX/2 - 1, pairs) and the column left of
+// tile's groups, stored, and written to LDS together with the keys; the
+// row below the tile (threads 0 .. TX/N - 1, groups) and the column left of
 // it (the next kTileY threads, one cell each) compute their p the same way
 // into the halo.  After the plane's barrier every cell reads its x- and y-
 // neighbours from LDS (pass A counts each face once, from its upper cell);
 // the z- neighbour is carried in registers.  The next plane's loads are
 // issued before the barrier and used after it.
-template <typename T, class C>
+template <typename T, class C, int N>
 __device__ void lds_passA(const Slot &S, const SlotState &st, int64_t lt, const C &cf,
                           double (&acc)[3])
 {
-    constexpr int N = 2;
+    constexpr int TX = tile_x<N>(), W = lds_w<N>();
     using K = typename C::Key;
     using KE = typename KeyElem<C>::type;
-    using KP = KeyPair<C>;
+    using KP = KeyGroup<C, N>;
     using KR = typename KP::raw;
     using V = typename VecN<T, N>::type;
-    LdsPlanes<T, KE> &L = lds_planes<T, KE>();
+    LdsPlanes<T, KE, N> &L = lds_planes<T, KE, N>();
     const int l = (int)threadIdx.x;
     const TileCtx t = group_ctx(S, lt);
-    const int ii = (N * l) % kTileX, jj = (N * l) / kTileX;
+    const int ii = (N * l) % TX, jj = (N * l) / TX;
     const int ti0 = t.i - ii, tj0 = t.j - jj;
     const int nx = S.nx, ny = S.ny, nz = S.nz, bm = S.bcmask;
     const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
@@ -1410,9 +1420,9 @@ __device__ void lds_passA(const Slot &S, const SlotState &st, int64_t lt, const 
     // finite earlier direction, so the loads stay unconditional)
     const T beta = st.first ? T(0) : (T)st.beta;
     const int64_t qo = (int64_t)min(t.j, ny - 1) * nx + min(t.i, nx - N);
-    const int own = (jj + 1) * kLdsW + ii + 2;
-    const bool yh = l < kTileX / N;
-    const bool xh = !yh && l < kTileX / N + kTileY;
+    const int own = (jj + 1) * W + ii + N;
+    const bool yh = l < TX / N;
+    const bool xh = !yh && l < TX / N + kTileY;
     int64_t qh = qo;
     int hsel = 0, hslot = 0;
     if (yh) {
@@ -1420,20 +1430,20 @@ __device__ void lds_passA(const Slot &S, const SlotState &st, int64_t lt, const 
         int jy = tj0 - 1;
         jy = py ? (jy + ny) % ny : max(0, jy);
         qh = (int64_t)jy * nx + min(ti0 + hi, nx - N);
-        hslot = hi + 2;
+        hslot = hi + N;
     } else if (xh) {
-        const int hj = l - kTileX / N;
+        const int hj = l - TX / N;
         int ix = ti0 - 1;
         ix = px ? (ix + nx) % nx : max(0, ix);
         const int64_t q1 = (int64_t)min(tj0 + hj, ny - 1) * nx + ix;
-        qh = q1 & ~(int64_t)1;
-        hsel = (int)(q1 & 1);
-        hslot = (hj + 1) * kLdsW + 1;
+        qh = q1 & ~(int64_t)(N - 1);
+        hsel = (int)(q1 & (N - 1));
+        hslot = (hj + 1) * W + N - 1;
     }
-    const bool hwave = __builtin_amdgcn_readfirstlane(l) < kTileX / N + kTileY;
+    const bool hwave = __builtin_amdgcn_readfirstlane(l) < TX / N + kTileY;
     const int i0 = t.i, j = t.j;
     const bool hxm = i0 > 0 || px, hym = j > 0 || py;
-    // Dirichlet high walls: x+ of the pair's last cell, y+ of both
+    // Dirichlet high walls: x+ of the group's last cell, y+ of all
     const bool hwx = !(i0 + N - 1 < nx - 1 || px) && (bm & 2);
     const bool hwy = !(j < ny - 1 || py) && (bm & 8);
     const K wxm = (bm & 1) ? cf.dirichlet() : cf.neumann();
@@ -1459,8 +1469,11 @@ __device__ void lds_passA(const Slot &S, const SlotState &st, int64_t lt, const 
     };
     T pzm[N];
     K kzm[N];
-    pzm[0] = pzm[1] = T(0);
-    kzm[0] = kzm[1] = wzm;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        pzm[n] = T(0);
+        kzm[n] = wzm;
+    }
     if (t.k0 > 0) {
         const int64_t base = (int64_t)(t.k0 - 1) * P;
         const V z = zv[(base + qo) / N], q = qv[(base + qo) / N];
@@ -1490,16 +1503,16 @@ __device__ void lds_passA(const Slot &S, const SlotState &st, int64_t lt, const 
         } else if (xh) {
             K hk[N];
             KP::split(A.hk, hk);
-            Lv[hslot] = hsel ? A.hz[1] + beta * A.hq[1] : A.hz[0] + beta * A.hq[0];
-            Lk[hslot] = (KE)(hsel ? hk[1] : hk[0]);
+            Lv[hslot] = pick<T, N>(A.hz, hsel) + beta * pick<T, N>(A.hq, hsel);
+            Lk[hslot] = (KE)pick<K, N>(hk, hsel);
         }
         if (t.active) __builtin_nontemporal_store(pn, &pdv[((int64_t)k * P + qo) / N]);
         const Plane B = load(k + 1);
         __syncthreads();
         const bool top = k == nz - 1 && (bm & 32);
-        const V pym_v = *(const V *)(Lv + own - kLdsW);
+        const V pym_v = *(const V *)(Lv + own - W);
         K kym[N];
-        KP::split(KP::get(Lk + own - kLdsW), kym);
+        KP::split(KP::get(Lk + own - W), kym);
         T pl = hxm ? Lv[own - 1] : T(0);          // x- value of the next cell
         K kl = hxm ? (K)Lk[own - 1] : wxm;
 #pragma unroll
@@ -2077,24 +2090,45 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
         return;
     }
     if (MODE >= 3) {
-        // 2-D plane tiles (FP64 only): pass A grouped, pass B LDS-staged
-        if (FAMILY != PCG_PREC_FP64) return;
-        if (WHICH == 1) {
-            if (ph == K1_CG_A) {
-                if (MODE == 3) lds_passA<double>(S, st, lt, c64, acc);
-                else lds_passA<double>(S, st, lt, r64, acc);
-            }
-        } else if (ph == K2_CG_B) {
-            const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
-            if (MODE == 3) {
-                if (catch_up) lds_passB<double, double, ClsCoef<double>, 3>(S, st, lt, c64, acc);
-                else lds_passB<double, double, ClsCoef<double>, 0>(S, st, lt, c64, acc);
-            } else {
-                if (catch_up) lds_passB<double, double, RhoCoef<double>, 3>(S, st, lt, r64, acc);
-                else lds_passB<double, double, RhoCoef<double>, 0>(S, st, lt, r64, acc);
-            }
-        } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
-        else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);
+        // 2-D plane tiles: both passes LDS-staged (two FP64 or four FP32 cells a thread)
+        if (FAMILY == PCG_PREC_FP64) {
+            if (WHICH == 1) {
+                if (ph == K1_CG_A) {
+                    if (MODE == 3) lds_passA<double, ClsCoef<double>, 2>(S, st, lt, c64, acc);
+                    else lds_passA<double, RhoCoef<double>, 2>(S, st, lt, r64, acc);
+                }
+            } else if (ph == K2_CG_B) {
+                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
+                if (MODE == 3) {
+                    if (catch_up) lds_passB<double, double, ClsCoef<double>, 3, 2>(S, st, lt, c64, acc);
+                    else lds_passB<double, double, ClsCoef<double>, 0, 2>(S, st, lt, c64, acc);
+                } else {
+                    if (catch_up) lds_passB<double, double, RhoCoef<double>, 3, 2>(S, st, lt, r64, acc);
+                    else lds_passB<double, double, RhoCoef<double>, 0, 2>(S, st, lt, r64, acc);
+                }
+            } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
+            else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);
+        } else {
+            const RhoCoef<float> r32{ gp(S.rho32) };
+            const ClsCoef<float> c32{ gp(S.cls), tab32 };
+            if (WHICH == 1) {
+                if (ph == K1_IR_A) {
+                    if (MODE == 3) lds_passA<float, ClsCoef<float>, 4>(S, st, lt, c32, acc);
+                    else lds_passA<float, RhoCoef<float>, 4>(S, st, lt, r32, acc);
+                }
+            } else if (ph == K2_IR_B) {
+                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
+                if (MODE == 3) {
+                    if (catch_up) lds_passB<float, float, ClsCoef<float>, 3, 4>(S, st, lt, c32, acc);
+                    else lds_passB<float, float, ClsCoef<float>, 0, 4>(S, st, lt, c32, acc);
+                } else {
+                    if (catch_up) lds_passB<float, float, RhoCoef<float>, 3, 4>(S, st, lt, r32, acc);
+                    else lds_passB<float, float, RhoCoef<float>, 0, 4>(S, st, lt, r32, acc);
+                }
+            } else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);
+            else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
+            else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);
+        }
         return;
     }
     if (FAMILY == PCG_PREC_FP64) {
@@ -2631,15 +2665,14 @@ hipError_t launch_iter(int family, int which, int mode, int grid,
         else if (NM > 4 && mode == 4) PCG_LAUNCH(F, W, 4);        \
         else return hipErrorInvalidValue;                         \
     } while (0)
-    // modes 3 and 4 (2-D plane tiles) exist for FP64 only
     if (family == PCG_PREC_FP64) {
         if (which == 3) PCG_MODES(PCG_PREC_FP64, 3, 5);
         else if (which == 1) PCG_MODES(PCG_PREC_FP64, 1, 5);
         else PCG_MODES(PCG_PREC_FP64, 2, 5);
     } else {
-        if (which == 3) PCG_MODES(PCG_PREC_FP32_IR, 3, 3);
-        else if (which == 1) PCG_MODES(PCG_PREC_FP32_IR, 1, 3);
-        else PCG_MODES(PCG_PREC_FP32_IR, 2, 3);
+        if (which == 3) PCG_MODES(PCG_PREC_FP32_IR, 3, 5);
+        else if (which == 1) PCG_MODES(PCG_PREC_FP32_IR, 1, 5);
+        else PCG_MODES(PCG_PREC_FP32_IR, 2, 5);
     }
 #undef PCG_MODES
 #undef PCG_LAUNCH

@@ -12,8 +12,8 @@ namespace pcgmi {
 constexpr int kBlock = 256;       // threads per workgroup = cells per plane tile
 constexpr int kMaxPartials = 3;   // reduction values per tile
 
-// 2-D plane tiles of the LDS-staged FP64 pass B: kTileX columns x kTileY
-// rows (one pair of cells per thread)
+// 2-D plane tiles of the LDS-staged passes: kTileY rows of kTileX columns
+// for FP64 (two cells per thread), of 2 kTileX columns for FP32 (four)
 constexpr int kTileX = 128;
 constexpr int kTileY = 4;
 

@@ -1,8 +1,9 @@
-"""The 2-D plane-tile form (128 x 4 tiles, in-plane neighbours staged in
-LDS) of the FP64 passes, through the C ABI, against the oracle.
+"""The 2-D plane-tile form (128 x 4 FP64 or 256 x 4 FP32 tiles, in-plane
+neighbours staged in LDS) of the two passes, through the C ABI, against the
+oracle.
 
-FP64 grids of at least 2^25 cells whose rows are a multiple of 128 cells
-take this form by default; PCG_PLANE_TILES asks for it on smaller grids (as
+Grids of at least 2^25 cells whose rows are a multiple of the tile width
+(128 cells for FP64, 256 for the FP32 inner solve) take this form by default; PCG_PLANE_TILES asks for it on smaller grids (as
 here) and PCG_FLAT_TILES keeps the consecutive-cell tiles.  The cases cover ragged
 tile rows (ny not a multiple of 4), a single row, every wall kind on every
 side, periodic axes (and the fall-back to consecutive-cell tiles when a
@@ -90,6 +91,46 @@ def test_plane_tile_parity(orc, F, torch_dev, shape, bc, wedge, flags):
     pf, stf = _solve(torch_dev, case, flags=flags | FLAT_TILES)
     assert abs(stf["iters"] - st["iters"]) <= 1, (st, stf)
     assert np.abs(pf - p).max() <= 1e-6 * scale
+
+
+CASES_IR = [
+    ((256, 9, 7), TANK, True),                  # one tile across, ragged tile rows
+    ((256, 8, 6), (P, P, P, P, 0, 1), False),   # periodic x and y holding whole tiles
+    ((512, 5, 4), (1, 1, 1, 1, 1, 1), True),    # Dirichlet everywhere, two tiles across
+    ((256, 6, 5), (P, P, 0, 0, 0, 0), True),    # periodic x, no-flux: singular
+    ((256, 13, 5), (0, 0, P, P, 0, 1), False),  # periodic y, 13 rows: consecutive-cell tiles
+]
+
+
+@pytest.mark.parametrize("shape,bc,wedge", CASES_IR, ids=lambda v: str(v))
+@pytest.mark.parametrize("flags", [PLANE, PLANE | NO_CLASSES], ids=["classes", "density"])
+def test_plane_tile_parity_ir(orc, F, torch_dev, shape, bc, wedge, flags):
+    """FP32 stencil with FP64 refinement on 256 x 4 plane tiles (four cells a
+    thread): the oracle's bar, and the consecutive-cell tiles' answer."""
+    case = _case(F, shape, bc, wedge)
+    _say(f"case plane tiles ir {shape} bc={bc} wedge={wedge} flags={flags}")
+    p, st = _solve(torch_dev, case, flags=flags, precision=1)
+    assert st["status"] == 0, st
+    rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p)
+    assert rr <= 1e-8, (rr, st)
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-12)
+    scale = np.abs(ref.p).max()
+    assert np.abs(p - ref.p).max() <= 1e-6 * scale
+    assert np.all(p[case.mask.astype(bool)] == 0.0)
+    pf, stf = _solve(torch_dev, case, flags=flags | FLAT_TILES, precision=1)
+    assert np.abs(pf - p).max() <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("k", [13, 14, 15])
+def test_plane_tile_capped_iterate_ir(orc, F, torch_dev, k):
+    """The FP32 inner solve on plane tiles, capped at k iterations, returns
+    its k-th iterate of the same system (the deferred correction flushed)."""
+    case = _case(F, (256, 6, 9), TANK)
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=k)
+    scale = np.abs(ref.p).max()
+    p, st = _solve(torch_dev, case, tol=1e-30, maxit=k, precision=1)
+    assert st["status"] == 1 and st["iters"] == k and st["outer_iters"] == 2, st
+    assert np.abs(p - ref.p).max() <= 1e-4 * scale
 
 
 @pytest.mark.parametrize("tz", [1, 3, 8])
