@@ -154,11 +154,12 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
-    coef = {}
+    coef, form = {}, {}
 
     def step(precision=L.PREC_FP64, p=None, timing=False):
         s = Solver(rho, mask, case.bc, case.h, precision=precision)
         coef[precision] = "classes" if s.density_classes() else "density"
+        form[precision] = s.tile_form()
         if timing:
             s.set_timing(True)
         p, st = s.solve(rhs, p=p, tol=args.tol)
@@ -234,12 +235,17 @@ def main():
         _, stt, (k1_ms, k2_ms, nlaunch) = step(p=p64, timing=True)
         mode = coef[L.PREC_FP64]
         b1, b2 = BYTES_K1[("fp64", mode)], BYTES_K2[("fp64", mode)]
+        # kernel template argument of the coefficient mode (plane tiles: 3, 4)
+        plane = form[L.PREC_FP64][0] > 0
+        kmode = (3 if mode == "classes" else 4) if plane else (1 if mode == "classes" else 0)
+        tiles = (f"{form[L.PREC_FP64][0]}x{form[L.PREC_FP64][1]} plane tiles, LDS-staged"
+                 if plane else "tiles of consecutive cells")
         a2 = b2 * cells / (k2_ms * 1e-3) / 1e9
         a1 = b1 * cells / (k1_ms * 1e-3) / 1e9
         traffic = None
         tr = read_traffic(args.traffic)
         if tr and tr.get("kernel_source_sha") == kernel_sha():
-            key = f"bytes[k_iter<0, 2, {1 if mode == 'classes' else 0}>]"
+            key = f"bytes[k_iter<0, 2, {kmode}>]"
             try:
                 traffic = float(tr[key])
             except (KeyError, ValueError):
@@ -248,8 +254,9 @@ def main():
             "bound": "hbm", "achieved": round(a2, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(a2 / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"k_iter<FP64,2,{mode}>: operator apply + z update + r.z, r.r, "
-                      f"x updated every third launch ({b2:.2f} B/cell per launch on average)",
+            "kernel": f"k_iter<0,2,{kmode}> (FP64 pass B, {mode}, {tiles}): operator apply + "
+                      f"z update + r.z, r.r, x updated every third launch "
+                      f"({b2:.2f} B/cell per launch on average)",
             "avg_ms": round(k2_ms, 4), "launches": nlaunch,
             "frac_of_copy": round(a2 / copy_gbs, 4),
             "frac_of_triad": round(a2 / triad_gbs, 4),
@@ -258,8 +265,8 @@ def main():
                              if traffic is not None else None),
         }
         out["kernel_k1"] = {
-            "kernel": f"k_iter<FP64,3,{mode}>: p update + p.Ap, and the rare set-up and residual "
-                      f"actions ({b1} B/cell)",
+            "kernel": f"k_iter<0,3,{kmode}> (FP64 pass A, {mode}, {tiles}): p update + p.Ap, "
+                      f"and the rare set-up and residual actions ({b1} B/cell)",
             "avg_ms": round(k1_ms, 4), "achieved_GBps": round(a1, 1),
             "frac": round(a1 / HBM_PEAK_GBS, 4),
         }

@@ -245,6 +245,13 @@ int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
 int pcg_density_classes(const pcg_ctx_t *ctx, int32_t *nclasses);
 
 /*
+ * Tile form of a context: *tx, *ty = columns and rows of its 2-D plane tiles
+ * (128 x 4 FP64, 256 x 4 FP32), or 0, 0 when its tiles are runs of
+ * consecutive cells.  PCG_EINVAL for null arguments.
+ */
+int pcg_tile_form(const pcg_ctx_t *ctx, int32_t *tx, int32_t *ty);
+
+/*
  * Velocity projection (Section 2.1: u* = u - dt (1/rho) grad P on the MAC
  * faces), in place, with the context's face coefficients, walls and hull:
  *   u_f -= dt * beta_f * (p_hi - p_lo) / h,

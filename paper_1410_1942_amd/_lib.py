@@ -30,7 +30,7 @@ EXPORTED = [
     "pcg_density_classes", "pcg_project", "pcg_divergence",
     "pcg_solve_ex", "pcg_project_ex", "pcg_rhs", "pcg_update_density",
     "pcg_set_fractions", "pcg_triad_probe", "pcg_inject_failure",
-    "pcg_solve_static",
+    "pcg_solve_static", "pcg_tile_form",
 ]
 
 
@@ -107,6 +107,7 @@ def load(path: str = LIB_PATH):
     lib.pcg_check_connectivity.argtypes = [vp, P(Grid), P(BC)]
     lib.pcg_set_tile_rules.argtypes = [i32, i32, i32, vp, vp, vp]
     lib.pcg_density_classes.argtypes = [vp, P(i32)]
+    lib.pcg_tile_form.argtypes = [vp, P(i32), P(i32)]
     lib.pcg_project.argtypes = [vp, vp, dbl, vp, vp, vp]
     lib.pcg_divergence.argtypes = [vp, vp, vp, vp, P(dbl)]
     lib.pcg_get_tile_rules.argtypes = [i32, i32, i32, vp, vp, vp, P(i32)]

@@ -1508,6 +1508,15 @@ int pcg_density_classes(const pcg_ctx_t *c, int32_t *nclasses)
     return PCG_OK;
 }
 
+int pcg_tile_form(const pcg_ctx_t *c, int32_t *tx, int32_t *ty)
+{
+    if (!c || !tx || !ty) return PCG_EINVAL;
+    const SlotHost &S = c->eng.slots[c->slot];
+    *tx = S.geo.tx;
+    *ty = S.geo.ty;
+    return PCG_OK;
+}
+
 int pcg_destroy(pcg_ctx_t *c)
 {
     delete c;

@@ -165,6 +165,14 @@ class Solver:
         L.check(self.lib.pcg_density_classes(self._ctx, ctypes.byref(n)), "classes")
         return n.value
 
+    def tile_form(self):
+        """(columns, rows) of the context's plane tiles, or (0, 0) for tiles
+        of consecutive cells (pcg_tile_form)."""
+        tx, ty = ctypes.c_int32(), ctypes.c_int32()
+        L.check(self.lib.pcg_tile_form(self._ctx, ctypes.byref(tx), ctypes.byref(ty)),
+                "pcg_tile_form")
+        return tx.value, ty.value
+
     def set_fractions(self, ax=None, ay=None, az=None, vol=None):
         """Free-slip cut-cell fractions (pcg_set_fractions): MAC face area
         fractions ax[nz,ny,nx+1], ay[nz,ny+1,nx], az[nz+1,ny,nx] and cell

@@ -205,3 +205,23 @@ def test_plane_tiles_in_a_batch(F, torch_dev):
         assert mixed[i][0]["status"] == 0 and st1["status"] == 0
         assert mixed[i][0]["iters"] == st1["iters"], i
         assert np.array_equal(mixed[i][1], p1), i
+
+
+def test_tile_form_reported(F, torch_dev):
+    """pcg_tile_form names the tile form each context took."""
+    torch, dev = torch_dev
+    from paper_1410_1942_amd.solver import Solver
+    t = lambda a: _to(torch, dev, a)
+    for shape, bc, flags, prec, want in [
+            ((128, 8, 6), TANK, PLANE, 0, (128, 4)),
+            ((256, 8, 6), TANK, PLANE, 1, (256, 4)),
+            ((128, 8, 6), TANK, PLANE | FLAT_TILES, 0, (0, 0)),
+            ((128, 8, 6), TANK, 0, 0, (0, 0)),              # below the size threshold
+            ((128, 13, 6), (0, 0, P, P, 0, 1), PLANE, 0, (0, 0)),   # ragged periodic y
+            ((96, 8, 6), TANK, PLANE, 0, (0, 0))]:          # rows not a multiple of 128
+        case = _case(F, shape, bc, wedge=False)
+        s = Solver(t(case.rho), t(case.mask), case.bc, case.h, precision=prec, flags=flags)
+        try:
+            assert s.tile_form() == want, (shape, bc, flags, prec)
+        finally:
+            s.close()
