@@ -22,8 +22,9 @@ def test_committed_traffic_summary_parses():
     tr = bench.read_traffic(os.path.join(ROOT, "profiles", "traffic_wedge512.txt"))
     assert tr is not None
     assert len(tr["kernel_source_sha"]) == 16
-    # pass B with density classes, the kernel the roofline reports
-    assert float(tr["bytes[k_iter<0, 2, 1>]"]) > 0
+    # pass B with density classes on 128x4 plane tiles, the kernel the
+    # roofline reports at 512^3
+    assert float(tr["bytes[k_iter<0, 2, 3>]"]) > 0
     # the kernel-trace summary gives the command it came from
     stats = open(os.path.join(ROOT, "profiles", "kernel_stats_wedge512.txt")).read()
-    assert "rocprofv3 --kernel-trace --stats" in stats and "k_iter<0, 2, 1>" in stats
+    assert "rocprofv3 --kernel-trace --stats" in stats and "k_iter<0, 2, 3>" in stats
