@@ -124,11 +124,20 @@ enum {
                                         tiles with the operator's in-plane
                                         neighbours staged in LDS; same
                                         operator, another summation order   */
-    PCG_PLANE_TILES = 32             /* use the plane tiles on any grid that
+    PCG_PLANE_TILES = 32,            /* use the plane tiles on any grid that
                                         allows them, whatever its size, also
                                         for FP32_IR (256 x 4 tiles, rows a
                                         multiple of 256; PCG_FLAT_TILES wins
                                         if both)                             */
+    PCG_TWO_SWEEPS = 64              /* FP64 on plane tiles: keep two sweeps
+                                        per iteration.  By default such a
+                                        solve runs one sweep per iteration
+                                        (the Chronopoulos-Gear recurrences:
+                                        the same iterates up to rounding, 33
+                                        instead of 50 bytes per cell and
+                                        iteration before the x updates) with
+                                        a second z vector in the workspace
+                                        (8 bytes per cell)                   */
 };
 
 /*
@@ -139,7 +148,7 @@ enum {
  *   check_every iterations per captured graph replay between host polls [32]
  *   flags       PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK |
  *               PCG_NO_DENSITY_CLASSES | PCG_FRACTIONS | PCG_FLAT_TILES |
- *               PCG_PLANE_TILES
+ *               PCG_PLANE_TILES | PCG_TWO_SWEEPS
  *   inner_maxit FP32_IR: cap on inner iterations per refinement trip [none]
  *   inner_tol   FP32_IR: relative reduction asked of each inner solve, never
  *               more than the last refinement trip needs [1e-4]
@@ -247,9 +256,11 @@ int pcg_density_classes(const pcg_ctx_t *ctx, int32_t *nclasses);
 /*
  * Tile form of a context: *tx, *ty = columns and rows of its 2-D plane tiles
  * (128 x 4 FP64, 256 x 4 FP32), or 0, 0 when its tiles are runs of
- * consecutive cells.  PCG_EINVAL for null arguments.
+ * consecutive cells; *sweeps = passes over the grid per iteration (1: the
+ * one-sweep FP64 iteration on plane tiles, else 2).  PCG_EINVAL for null
+ * arguments.
  */
-int pcg_tile_form(const pcg_ctx_t *ctx, int32_t *tx, int32_t *ty);
+int pcg_tile_form(const pcg_ctx_t *ctx, int32_t *tx, int32_t *ty, int32_t *sweeps);
 
 /*
  * Velocity projection (Section 2.1: u* = u - dt (1/rho) grad P on the MAC
@@ -438,19 +449,20 @@ int pcg_batch_destroy(pcg_batch_t *b);
  * cells uses the first rule with n <= max_cells[i]: tile height tz[i] and,
  * for single-solve contexts, grid[i] workgroups (0 = library default).
  * Rules must be ordered by increasing max_cells, 1 <= n <= 64, tz >= 1.
- * There is one table per precision for single-solve contexts
- * (for_batches = 0) and one for batches (for_batches = 1), where many
- * resident solves already fill the device and longer tiles cost less
- * per-tile overhead.  Contexts and batches created afterwards use them.  A
+ * There are three tables per precision: table = 0 for single-solve
+ * contexts on tiles of consecutive cells, 1 for batches (any tile form),
+ * where many resident solves already fill the device and longer tiles cost
+ * less per-tile overhead, and 2 for single-solve contexts on 2-D plane
+ * tiles.  Contexts and batches created afterwards use them.  A
  * solve's tile height depends only on its own cell count, so its result
  * does not depend on the other solves of a batch.  Host-only; not
  * thread-safe against concurrent setup.  pcg_get_tile_rules copies at most
  * cap rules out and sets *n_out to the table length.
  */
-int pcg_set_tile_rules(int32_t precision, int32_t for_batches, int32_t n,
+int pcg_set_tile_rules(int32_t precision, int32_t table, int32_t n,
                        const int64_t *max_cells, const int32_t *tz,
                        const int32_t *grid);
-int pcg_get_tile_rules(int32_t precision, int32_t for_batches, int32_t cap,
+int pcg_get_tile_rules(int32_t precision, int32_t table, int32_t cap,
                        int64_t *max_cells, int32_t *tz, int32_t *grid,
                        int32_t *n_out);
 

@@ -18,7 +18,7 @@ EINVAL, EDOMAIN, ESINGULAR, EBREAKDOWN, ENOMEM, EBUSY, EHIP, EUNSUPPORTED = \
 BC_NEUMANN, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 PREC_FP64, PREC_FP32_IR = 0, 1
 WARM_START, SKIP_CONNECTIVITY_CHECK, NO_DENSITY_CLASSES, FRACTIONS = 1, 2, 4, 8
-FLAT_TILES, PLANE_TILES = 16, 32
+FLAT_TILES, PLANE_TILES, TWO_SWEEPS = 16, 32, 64
 
 EXPORTED = [
     "pcg_workspace_bytes", "pcg_setup", "pcg_solve", "pcg_destroy",
@@ -107,7 +107,7 @@ def load(path: str = LIB_PATH):
     lib.pcg_check_connectivity.argtypes = [vp, P(Grid), P(BC)]
     lib.pcg_set_tile_rules.argtypes = [i32, i32, i32, vp, vp, vp]
     lib.pcg_density_classes.argtypes = [vp, P(i32)]
-    lib.pcg_tile_form.argtypes = [vp, P(i32), P(i32)]
+    lib.pcg_tile_form.argtypes = [vp, P(i32), P(i32), P(i32)]
     lib.pcg_project.argtypes = [vp, vp, dbl, vp, vp, vp]
     lib.pcg_divergence.argtypes = [vp, vp, vp, vp, P(dbl)]
     lib.pcg_get_tile_rules.argtypes = [i32, i32, i32, vp, vp, vp, P(i32)]

@@ -8,11 +8,14 @@ fastest per iteration.  The result is a JSON table keyed by GPU architecture:
     {"gfx950": {"fp64":    [[max_cells, tz, grid], ...],
                 "fp32_ir": [[max_cells, tz, grid], ...],
                 "fp64_batch": [...], "fp32_ir_batch": [...],
+                "fp64_plane": [...], "fp32_ir_plane": [...],
                 "measured": {...}}}
 
-Single-solve rules are tuned on one solve at a time; batch rules on a
-resident batch of several solves of the class size (their tiles share every
-launch, so longer tiles usually win).
+Single-solve rules are tuned on one solve at a time, on tiles of consecutive
+cells ("fp64", "fp32_ir") and on 2-D plane tiles ("*_plane", grids whose
+rows hold whole tiles; FP64 plane tiles run one sweep per iteration); batch
+rules on a resident batch of several solves of the class size (their tiles
+share every launch, so longer tiles usually win).
 
 ``install()`` hands a table to the library (pcg_set_tile_rules); the binding
 calls it once per process with the table shipped in the package
@@ -20,7 +23,7 @@ calls it once per process with the table shipped in the package
 Tile height depends only on a solve's own cell count, so a tuned table never
 makes a solve's result depend on the other solves it is batched with.
 
-    python -m paper_1410_1942_amd.autotune [--out FILE] [--quick]
+    python -m paper_1410_1942_amd.autotune [--out FILE] [--quick] [--plane-only]
 """
 from __future__ import annotations
 
@@ -40,31 +43,45 @@ PREC_KEYS = {L.PREC_FP64: "fp64", L.PREC_FP32_IR: "fp32_ir"}
 
 CLASSES = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512]
 BATCH_CLASSES = [16, 24, 32, 48, 64, 96, 128, 192]
+# plane-tile classes as grid shapes (nx, ny, nz): rows of whole tiles, and
+# for FP64 a 256 x 256 x 128 grid, whose tile count per plane and height
+# are those of the 512 x 128 x 128 strut tank
+PLANE_CLASSES = {L.PREC_FP64: [(128, 128, 128), (256, 256, 128), (256, 256, 256),
+                               (384, 384, 384), (512, 512, 512)],
+                 L.PREC_FP32_IR: [(256, 256, 256), (512, 256, 256), (512, 512, 512)]}
+# pcg_set_tile_rules table kinds
+SINGLE, BATCH, PLANE = 0, 1, 2
 TZS = [2, 4, 8, 16, 32, 64, 128, 256]
 GRIDS = [256, 512, 768, 1024, 2048]
 
 _installed = False
 
 
-def get_rules(precision: int, for_batches: bool = False):
+def _kind(for_batches, table):
+    return int(table) if table is not None else (BATCH if for_batches else SINGLE)
+
+
+def get_rules(precision: int, for_batches: bool = False, table=None):
+    """Rules of one table: single solves (default), batches, or (table =
+    PLANE) single solves on plane tiles."""
     lib = L.load()
     cap = 64
     mc = (ctypes.c_int64 * cap)()
     tz = (ctypes.c_int32 * cap)()
     gr = (ctypes.c_int32 * cap)()
     n = ctypes.c_int32()
-    L.check(lib.pcg_get_tile_rules(int(precision), int(for_batches), cap, mc, tz, gr,
+    L.check(lib.pcg_get_tile_rules(int(precision), _kind(for_batches, table), cap, mc, tz, gr,
                                    ctypes.byref(n)), "pcg_get_tile_rules")
     return [[int(mc[i]), int(tz[i]), int(gr[i])] for i in range(n.value)]
 
 
-def set_rules(precision: int, rules, for_batches: bool = False):
+def set_rules(precision: int, rules, for_batches: bool = False, table=None):
     lib = L.load()
     n = len(rules)
     mc = (ctypes.c_int64 * n)(*[int(r[0]) for r in rules])
     tz = (ctypes.c_int32 * n)(*[int(r[1]) for r in rules])
     gr = (ctypes.c_int32 * n)(*[int(r[2]) if len(r) > 2 else 0 for r in rules])
-    L.check(lib.pcg_set_tile_rules(int(precision), int(for_batches), n, mc, tz, gr),
+    L.check(lib.pcg_set_tile_rules(int(precision), _kind(for_batches, table), n, mc, tz, gr),
             "pcg_set_tile_rules")
 
 
@@ -88,6 +105,8 @@ def install(path: str = None, arch: str = None) -> bool:
             set_rules(prec, table[arch][key])
         if key + "_batch" in table[arch]:
             set_rules(prec, table[arch][key + "_batch"], for_batches=True)
+        if key + "_plane" in table[arch]:
+            set_rules(prec, table[arch][key + "_plane"], table=PLANE)
     return True
 
 
@@ -106,12 +125,12 @@ def ensure_installed():
         print(f"tile table not installed: {e}", file=sys.stderr)
 
 
-def _time_per_iter(dev_case, precision, tz, grid, target_ms=25.0):
+def _time_per_iter(dev_case, precision, tz, grid, target_ms=25.0, flags=L.FLAT_TILES):
     import torch
     from .solver import Solver
     rho, mask, rhs, bc, h = dev_case
     s = Solver(rho, mask, bc, h, precision=precision, tz=tz, grid_blocks=grid,
-               flags=L.SKIP_CONNECTIVITY_CHECK, check_every=16)
+               flags=L.SKIP_CONNECTIVITY_CHECK | flags, check_every=16)
     p = torch.empty_like(rhs)
     s.solve(rhs, p=p, tol=1e-30, maxit=16, raise_on_error=False)
     torch.cuda.synchronize()
@@ -236,23 +255,61 @@ def tune(classes=CLASSES, precisions=(L.PREC_FP64, L.PREC_FP32_IR), tzs=TZS,
     return out
 
 
+def tune_plane(classes=PLANE_CLASSES, tzs=TZS, grids=(512, 768, 1024), log=print):
+    """Single solves on plane tiles, per grid shape; rules split at the
+    geometric means of the shapes' cell counts."""
+    import torch
+    from . import fields as F
+    dev = torch.device("cuda:0")
+    out, measured = {}, {}
+    for prec, shapes in classes.items():
+        key = PREC_KEYS[prec] + "_plane"
+        best = []
+        for nx, ny, nz in shapes:
+            case = F.make_two_phase(nx, ny, nz, surface_seed=1, velocity_seed=2,
+                                    wedge=F.Wedge(), keep_velocity=False)
+            dev_case = (torch.from_numpy(case.rho).to(dev),
+                        torch.from_numpy(case.mask).to(dev),
+                        torch.from_numpy(case.rhs).to(dev), case.bc, case.h)
+            results = sorted((_time_per_iter(dev_case, prec, tz, g, flags=L.PLANE_TILES), tz, g)
+                             for tz in tzs if tz <= nz for g in grids)
+            ms, tz, g = results[0]
+            measured[f"{key}/{nx}x{ny}x{nz}"] = [[round(m, 5), t, gg] for m, t, gg in results[:5]]
+            cells = nx * ny * nz
+            log(f"{key} {nx}x{ny}x{nz}: best tz={tz} grid={g} {ms*1e3:.1f} us/iter "
+                f"({cells / (ms * 1e-3) / 1e9:.2f} Gcell-iter/s)", flush=True)
+            best.append((cells, tz, g))
+            del dev_case
+            torch.cuda.empty_cache()
+        out[key] = [[int(math.sqrt(c * best[i + 1][0])) if i + 1 < len(best) else 2 ** 62, t, g]
+                    for i, (c, t, g) in enumerate(best)]
+    out["measured_plane"] = measured
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE)
     ap.add_argument("--quick", action="store_true",
                     help="fewer classes and candidates")
     ap.add_argument("--batches-only", action="store_true",
-                    help="tune only the batch tables, keep the single-solve ones")
+                    help="tune only the batch tables, keep the others")
+    ap.add_argument("--plane-only", action="store_true",
+                    help="tune only the plane-tile tables, keep the others")
     a = ap.parse_args(argv)
     os.environ["PCGMI_TILE_TABLE"] = "none"
     arch = device_arch()
     full = json.load(open(a.out)) if os.path.exists(a.out) else {}
     table = dict(full.get(arch, {}))
-    if not a.batches_only:
+    if not (a.batches_only or a.plane_only):
         kw = dict(classes=[24, 64, 160], tzs=[4, 16, 32], grids=[512, 1024]) if a.quick else {}
         table.update(tune(**kw))
-    kwb = dict(classes=[24, 64], tzs=[4, 16]) if a.quick else {}
-    table.update(tune_batches(**kwb))
+    if not a.batches_only:
+        kwp = dict(classes={L.PREC_FP64: [(128, 64, 64)]}, tzs=[8, 32]) if a.quick else {}
+        table.update(tune_plane(**kwp))
+    if not a.plane_only:
+        kwb = dict(classes=[24, 64], tzs=[4, 16]) if a.quick else {}
+        table.update(tune_batches(**kwb))
     full[arch] = table
     with open(a.out, "w") as f:
         json.dump(full, f, indent=1)

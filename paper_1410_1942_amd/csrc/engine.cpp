@@ -123,20 +123,31 @@ std::vector<TileRule> g_rules_batch[2] = {
     { { 7524, 8, 0 }, { 21283, 8, 0 }, { 60198, 8, 0 }, { 170267, 16, 0 }, { 481589, 16, 0 }, { 1362140, 16, 0 }, { 3852714, 16, 0 }, { INT64_MAX, 32, 0 } },
 };
 
-std::vector<TileRule> &rules_of(int prec, bool batch)
+// Single solves on 2-D plane tiles (their own optimum: a tile also runs the
+// plane below it in the one-sweep form, and its plane holds 512 cells).
+std::vector<TileRule> g_rules_plane[2] = {
+    { { 4194304, 16, 512 }, { 11863283, 32, 512 }, { 30821713, 64, 512 }, { 87176971, 32, 512 }, { INT64_MAX, 256, 512 } },
+    { { 10897121, 32, 768 }, { 30821713, 32, 768 }, { 87176971, 16, 512 }, { INT64_MAX, 256, 1024 } },
+};
+
+// Table kinds: 0 single solves, 1 batches, 2 single solves on plane tiles.
+enum { kTableSingle = 0, kTableBatch = 1, kTablePlane = 2 };
+
+std::vector<TileRule> &rules_of(int prec, int table)
 {
-    return (batch ? g_rules_batch : g_rules)[prec == PCG_PREC_FP32_IR ? 1 : 0];
+    std::vector<TileRule> *t = table == kTableBatch ? g_rules_batch
+                               : table == kTablePlane ? g_rules_plane : g_rules;
+    return t[prec == PCG_PREC_FP32_IR ? 1 : 0];
 }
 
-const TileRule &rule_for(int64_t n, int prec, bool batch)
+// Batches use the batch table whatever their tile form.
+const TileRule &rule_for(int64_t n, int prec, bool batch, bool plane)
 {
-    const auto &rules = rules_of(prec, batch);
+    const auto &rules = rules_of(prec, batch ? kTableBatch : plane ? kTablePlane : kTableSingle);
     for (const auto &r : rules)
         if (n <= r.max_cells) return r;
     return rules.back();
 }
-
-int choose_tz(int64_t n, int prec, bool batch) { return rule_for(n, prec, batch).tz; }
 
 // ---- first-fit allocator over [0, size) ----
 
@@ -198,24 +209,24 @@ struct Geometry {
 
 // Whether a grid runs 2-D plane tiles (the LDS-staged passes): rows a
 // multiple of the tile width (128 cells for FP64, two per thread; 256 for
-// FP32, four), no cut-cell fractions, asked for or (FP64) large enough, not
-// switched off, and a periodic y axis holding whole tiles (periodic x always
-// does).
+// FP32, four), no cut-cell fractions, not switched off, a periodic y axis
+// holding whole tiles (periodic x always does), and FP64, or FP32 asked for
+// or large enough.
 // With the walls unknown (bc null: workspace sizing) the y condition is
 // assumed met, which sizes for the larger tile count.
-// Smallest grid that takes the plane tiles by default: measured on the
-// 512^3 wedge they save 6 % of an iteration; on 256^3 they tie with the
-// consecutive-cell tiles and on the 512 x 128 x 128 strut they lose 11 %.
-constexpr int64_t kPlaneTileMinCells = int64_t(1) << 25;
+// FP64 takes them on every grid that allows them: with one sweep per
+// iteration they measured faster than the consecutive-cell tiles on every
+// grid tried (per iteration: 128^3 48 against 62 us, 256^3 187 against 239,
+// the 512 x 128 x 128 strut 113 against 137, 384^3 555 against 761, 512^3
+// 1167 against 1650).  The FP32 inner passes gain only on the largest
+// grids (512^3: 0.83 against 0.86 ms per inner iteration).
+constexpr int64_t kPlaneTileMinCells32 = int64_t(1) << 25;
 
 bool plane_tiles_2d(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc)
 {
     if (flags & (PCG_FLAT_TILES | PCG_FRACTIONS)) return false;
-    // by default FP64 only: the FP32 inner passes on 256 x 4 plane tiles
-    // measured 1.01 ms per iteration at 512^3 against 0.89 on four-cell
-    // consecutive tiles
-    if (!(flags & PCG_PLANE_TILES) &&
-        (prec != PCG_PREC_FP64 || (int64_t)g.nx * g.ny * g.nz < kPlaneTileMinCells))
+    if (!(flags & PCG_PLANE_TILES) && prec == PCG_PREC_FP32_IR &&
+        (int64_t)g.nx * g.ny * g.nz < kPlaneTileMinCells32)
         return false;
     const int width = (prec == PCG_PREC_FP32_IR ? 4 : 2) * kBlock / kTileY;
     if (g.nx % width != 0) return false;
@@ -228,7 +239,7 @@ Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch, bo
     Geometry G;
     G.nx = g.nx; G.ny = g.ny; G.nz = g.nz;
     G.n = (int64_t)g.nx * g.ny * g.nz;
-    G.tz = tz_opt > 0 ? tz_opt : choose_tz(G.n, prec, batch);
+    G.tz = tz_opt > 0 ? tz_opt : rule_for(G.n, prec, batch, tiles2d).tz;
     if (G.tz > g.nz) G.tz = g.nz;
     const int64_t plane = (int64_t)g.nx * g.ny;
     // pass A addresses a tile's tz + 2 planes of 8-byte values with 32-bit
@@ -261,7 +272,15 @@ size_t frac_bytes(const Geometry &G)
            align_up(8 * nx * ny * (nz + 1), kAlign) + align_up(8 * nx * ny * nz, kAlign);
 }
 
-size_t slot_bytes(const Geometry &G, int prec, bool frac = false)
+// Whether the FP64 iterations of a grid run as one sweep each: on plane
+// tiles unless switched off.  Measured on the 512^3 wedge: 1.167 ms per
+// iteration against 1.559 for the two LDS-staged passes.
+bool one_sweep(const Geometry &G, int prec, int flags)
+{
+    return !(flags & PCG_TWO_SWEEPS) && G.tx > 0 && prec == PCG_PREC_FP64;
+}
+
+size_t slot_bytes(const Geometry &G, int prec, bool frac = false, bool sweep = false)
 {
     const size_t n = (size_t)G.n;
     const size_t es = prec == PCG_PREC_FP32_IR ? 4 : 8;
@@ -269,10 +288,26 @@ size_t slot_bytes(const Geometry &G, int prec, bool frac = false)
     b += align_up(8 * n, kAlign);                    // rho64
     if (prec == PCG_PREC_FP32_IR) b += align_up(4 * n, kAlign);  // rho32
     b += 4 * align_up(es * n, kAlign);               // z and three directions
+    if (sweep) b += align_up(es * n, kAlign);        // second z of the one-sweep form
     if (prec == PCG_PREC_FP32_IR) b += align_up(4 * n, kAlign);  // d32
     b += align_up(kMaxPartials * 8 * (size_t)G.ntiles, kAlign);  // partials
     b += align_up(n, kAlign);                                      // classes
     b += align_up(kClasses * kClasses * 12, kAlign);              // tables
+    return b;
+}
+
+// Workspace of one solve of a grid whose walls are not known yet: a
+// periodic y axis may still send a grid that allows plane tiles to
+// consecutive-cell tiles, whose tile count (and so partial sums) differs,
+// so the larger of the two forms.
+size_t grid_bytes(const pcg_grid_t &g, int prec, int tz_opt, bool batch, int flags, bool frac)
+{
+    const Geometry flat = make_geometry(g, prec, tz_opt, batch, false);
+    size_t b = slot_bytes(flat, prec, frac, false);
+    if (plane_tiles_2d(g, prec, flags, nullptr)) {
+        const Geometry G = make_geometry(g, prec, tz_opt, batch, true);
+        b = std::max(b, slot_bytes(G, prec, frac, one_sweep(G, prec, flags)));
+    }
     return b;
 }
 
@@ -327,7 +362,7 @@ int check_opts(const pcg_opts_t *o)
     if (o->check_every < 0 || o->inner_maxit < 0 || o->tz < 0 || o->grid_blocks < 0) return PCG_EINVAL;
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0 || std::isnan(o->inner_tol)) return PCG_EINVAL;
     if (o->flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES |
-                     PCG_FRACTIONS | PCG_FLAT_TILES | PCG_PLANE_TILES))
+                     PCG_FRACTIONS | PCG_FLAT_TILES | PCG_PLANE_TILES | PCG_TWO_SWEEPS))
         return PCG_EINVAL;
     return PCG_OK;
 }
@@ -470,6 +505,7 @@ struct SlotHost {
     double *rho64 = nullptr;
     float *rho32 = nullptr;
     void *z = nullptr, *dir0 = nullptr, *dir1 = nullptr, *dir2 = nullptr;
+    void *z2 = nullptr;          // one-sweep iterations only
     float *d32 = nullptr;
     double *partials = nullptr;
     uint8_t *cls = nullptr;      // arena: class per cell
@@ -708,9 +744,7 @@ struct Engine {
 
     size_t footprint(const pcg_grid_t &g) const
     {
-        return slot_bytes(make_geometry(g, prec, tz_opt, batch_mode(),
-                                        plane_tiles_2d(g, prec, flags, nullptr)),
-                          prec, frac_space);
+        return grid_bytes(g, prec, tz_opt, batch_mode(), flags, frac_space);
     }
 
     // Reserve a slot and its memory, encode the density.  Does not start a solve.
@@ -729,7 +763,8 @@ struct Engine {
         if (id < 0) return PCG_EBUSY;
         const Geometry geo = make_geometry(*grid_, prec, tz_opt, batch_mode(),
                                            plane_tiles_2d(*grid_, prec, flags | this->flags, bc));
-        const size_t need = slot_bytes(geo, prec, frac_space);
+        const bool sweep = one_sweep(geo, prec, flags | this->flags);
+        const size_t need = slot_bytes(geo, prec, frac_space, sweep);
         size_t off = 0;
         if (!alloc.alloc(need, &off)) return max_slots == 1 ? PCG_ENOMEM : PCG_EBUSY;
 
@@ -747,6 +782,7 @@ struct Engine {
         S.rho64 = (double *)p; p += align_up(8 * n, kAlign);
         if (prec == PCG_PREC_FP32_IR) { S.rho32 = (float *)p; p += align_up(4 * n, kAlign); }
         S.z = p; p += align_up(es * n, kAlign);
+        if (sweep) { S.z2 = p; p += align_up(es * n, kAlign); }
         S.dir0 = p; p += align_up(es * n, kAlign);
         S.dir1 = p; p += align_up(es * n, kAlign);
         S.dir2 = p; p += align_up(es * n, kAlign);
@@ -919,6 +955,7 @@ struct Engine {
         h.inner_maxit = inner_maxit > 0 ? inner_maxit : INT32_MAX;
         h.inner_tol2 = inner_tol * inner_tol;
         h.warm = (flags & PCG_WARM_START) ? 1 : 0;
+        h.fused = S.z2 ? 1 : 0;
         h.scale = 1.0;
         HIP_TRY(hipMemcpyAsync(d_states + id, &h, sizeof(SlotState), hipMemcpyHostToDevice, stream));
         S.running = true;
@@ -967,6 +1004,7 @@ struct Engine {
             d.rho64 = S.rho64;
             d.rho32 = S.rho32;
             d.z = S.z;
+            d.z2 = S.z2;
             d.dir0 = S.dir0;
             d.dir1 = S.dir1;
             d.dir2 = S.dir2;
@@ -1000,10 +1038,15 @@ struct Engine {
         int g = grid_opt > 0 ? grid_opt : (max_slots == 1 ? kDefaultGridMax : kBatchGrid);
         if (max_slots == 1) {
             int64_t t = 0, n = 0;
+            bool plane = false;
             for (auto &S : slots)
-                if (S.used) { t = std::max<int64_t>(t, S.geo.ntiles); n = S.geo.n; }
-            if (grid_opt <= 0 && n > 0 && rule_for(n, prec, false).grid > 0)
-                g = rule_for(n, prec, false).grid;
+                if (S.used) {
+                    t = std::max<int64_t>(t, S.geo.ntiles);
+                    n = S.geo.n;
+                    plane = S.geo.tx > 0;
+                }
+            if (grid_opt <= 0 && n > 0 && rule_for(n, prec, false, plane).grid > 0)
+                g = rule_for(n, prec, false, plane).grid;
             if (t > 0 && t < g) g = (int)t;
         }
         g = std::max(8, (g + 7) / 8 * 8);
@@ -1250,9 +1293,8 @@ int pcg_workspace_bytes(const pcg_grid_t *grid, const pcg_opts_t *opts,
     if (st) return st;
     const int prec = opts ? opts->precision : PCG_PREC_FP64;
     const int flags = opts ? opts->flags : 0;
-    const Geometry G = make_geometry(*grid, prec, opts ? opts->tz : 0, false,
-                                     plane_tiles_2d(*grid, prec, flags, nullptr));
-    *out_bytes = head_bytes(1) + slot_bytes(G, prec, opts && (opts->flags & PCG_FRACTIONS));
+    *out_bytes = head_bytes(1) + grid_bytes(*grid, prec, opts ? opts->tz : 0, false, flags,
+                                            (flags & PCG_FRACTIONS) != 0);
     return PCG_OK;
 }
 
@@ -1370,11 +1412,11 @@ int pcg_check_connectivity(const uint8_t *host_mask, const pcg_grid_t *grid,
     return kind < 0 ? kind : kind == 1 ? PCG_SINGULAR : PCG_OK;
 }
 
-int pcg_set_tile_rules(int32_t precision, int32_t for_batches, int32_t n,
+int pcg_set_tile_rules(int32_t precision, int32_t table, int32_t n,
                        const int64_t *max_cells, const int32_t *tz, const int32_t *grid)
 {
     if (precision != PCG_PREC_FP64 && precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
-    if (for_batches != 0 && for_batches != 1) return PCG_EINVAL;
+    if (table < kTableSingle || table > kTablePlane) return PCG_EINVAL;
     if (n < 1 || n > 64 || !max_cells || !tz) return PCG_EINVAL;
     std::vector<TileRule> rules;
     for (int i = 0; i < n; ++i) {
@@ -1385,17 +1427,17 @@ int pcg_set_tile_rules(int32_t precision, int32_t for_batches, int32_t n,
         rules.push_back({ max_cells[i], tz[i], g });
     }
     rules.back().max_cells = INT64_MAX;   // the last rule covers every size
-    rules_of(precision, for_batches != 0) = rules;
+    rules_of(precision, table) = rules;
     return PCG_OK;
 }
 
-int pcg_get_tile_rules(int32_t precision, int32_t for_batches, int32_t cap,
+int pcg_get_tile_rules(int32_t precision, int32_t table, int32_t cap,
                        int64_t *max_cells, int32_t *tz, int32_t *grid, int32_t *n_out)
 {
     if (precision != PCG_PREC_FP64 && precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
-    if (for_batches != 0 && for_batches != 1) return PCG_EINVAL;
+    if (table < kTableSingle || table > kTablePlane) return PCG_EINVAL;
     if (!n_out || cap < 0) return PCG_EINVAL;
-    const auto &rules = rules_of(precision, for_batches != 0);
+    const auto &rules = rules_of(precision, table);
     *n_out = (int32_t)rules.size();
     for (int i = 0; i < cap && i < (int)rules.size(); ++i) {
         if (max_cells) max_cells[i] = rules[i].max_cells;
@@ -1508,12 +1550,13 @@ int pcg_density_classes(const pcg_ctx_t *c, int32_t *nclasses)
     return PCG_OK;
 }
 
-int pcg_tile_form(const pcg_ctx_t *c, int32_t *tx, int32_t *ty)
+int pcg_tile_form(const pcg_ctx_t *c, int32_t *tx, int32_t *ty, int32_t *sweeps)
 {
-    if (!c || !tx || !ty) return PCG_EINVAL;
+    if (!c || !tx || !ty || !sweeps) return PCG_EINVAL;
     const SlotHost &S = c->eng.slots[c->slot];
     *tx = S.geo.tx;
     *ty = S.geo.ty;
+    *sweeps = S.z2 ? 1 : 2;
     return PCG_OK;
 }
 
@@ -1601,7 +1644,7 @@ int pcg_batch_admit(pcg_batch_t *b, const pcg_grid_t *grid, const double *rho,
     if (!b || !slot || !rhs || !p) return PCG_EINVAL;
     if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0) return PCG_EINVAL;
     if (flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES |
-                  PCG_FLAT_TILES | PCG_PLANE_TILES))
+                  PCG_FLAT_TILES | PCG_PLANE_TILES | PCG_TWO_SWEEPS))
         return PCG_EINVAL;
     int id = -1;
     int st = b->eng.prepare(grid, rho, mask, bc, flags, &id);

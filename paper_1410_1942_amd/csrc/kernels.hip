@@ -1152,6 +1152,12 @@ template <typename T, int N> struct KeyGroup<ClsCoef<T>, N> {
     }
     static __device__ __forceinline__ void put(uint8_t *a, raw r) { *(W *)a = (W)r; }
     static __device__ __forceinline__ raw get(const uint8_t *a) { return *(const W *)a; }
+    // key `sel` of a group by shifts: a select over split keys is turned
+    // back into an indexed (scratch) array
+    static __device__ __forceinline__ uint8_t elem(raw r, int sel)
+    {
+        return (uint8_t)((r >> (8 * sel)) & 0xffu);
+    }
 };
 template <typename T, int N> struct KeyGroup<RhoCoef<T>, N> {
     using raw = typename VecN<T, N>::type;
@@ -1166,6 +1172,13 @@ template <typename T, int N> struct KeyGroup<RhoCoef<T>, N> {
     }
     static __device__ __forceinline__ void put(T *a, raw r) { *(raw *)a = r; }
     static __device__ __forceinline__ raw get(const T *a) { return *(const raw *)a; }
+    static __device__ __forceinline__ T elem(raw r, int sel)
+    {
+        T e = r[0];
+#pragma unroll
+        for (int n = 1; n < N; ++n) e = sel == n ? r[n] : e;
+        return e;
+    }
 };
 
 // Element `sel` of a group (a select chain, no indexed register access).
@@ -1294,10 +1307,8 @@ __device__ void lds_passB(const Slot &S, const SlotState &st, int64_t lt, const 
             *(V *)(Lv + hslot) = h.v;
             KP::put(Lk + hslot, h.kp);
         } else if (xh) {
-            K hk[N];
-            KP::split(h.kp, hk);
             Lv[hslot] = pick<T, N>(h.v, hsel);
-            Lk[hslot] = (KE)pick<K, N>(hk, hsel);
+            Lk[hslot] = KP::elem(h.kp, hsel);
         }
         // loads for the next plane and this plane's vectors, left unsplit
         // and unused until after the barrier so they stay in flight across it
@@ -1501,10 +1512,8 @@ __device__ void lds_passA(const Slot &S, const SlotState &st, int64_t lt, const 
             *(V *)(Lv + hslot) = hp;
             KP::put(Lk + hslot, A.hk);
         } else if (xh) {
-            K hk[N];
-            KP::split(A.hk, hk);
             Lv[hslot] = pick<T, N>(A.hz, hsel) + beta * pick<T, N>(A.hq, hsel);
-            Lk[hslot] = (KE)pick<K, N>(hk, hsel);
+            Lk[hslot] = KP::elem(A.hk, hsel);
         }
         if (t.active) __builtin_nontemporal_store(pn, &pdv[((int64_t)k * P + qo) / N]);
         const Plane B = load(k + 1);
@@ -1535,6 +1544,387 @@ __device__ void lds_passA(const Slot &S, const SlotState &st, int64_t lt, const 
         A = B;
     }
     if (t.active) acc[0] += a;
+}
+
+// ------------------------------------------------------------------------
+// One-sweep iteration on plane tiles
+// ------------------------------------------------------------------------
+// The Chronopoulos-Gear form of the iteration: with alpha and beta known at
+// the start of a sweep (both from the previous sweep's sums), one pass over
+// the grid forms p = z + beta p_old, q = A p, z' = z - alpha D^-1 q and x +=
+// alpha p (three directions at a time, as in pass B), and sums r.z = z'.D z',
+// r.r and delta = z'.A z'.  The next step length is alpha' = (r.z)' / (delta
+// - beta' (r.z)' / alpha), equal to (r.z)' / p'.A p' in exact arithmetic, so
+// the iterates are those of the two-sweep iteration up to rounding, for 17
+// bytes read and 16 written per cell instead of 34 and 16.  delta is summed
+// over faces, each from its upper cell as in pass A, which needs z' in the
+// column left of the tile and the row below it, and those cells' q needs p
+// one cell further out: per plane the tile's groups and a halo two cells
+// deep on the low sides and one deep on the high sides stage p and the keys
+// in LDS, the row below the tile (threads 0 .. TX/N - 1) and the column left
+// of it (groups of N cells ending there, kTileY threads) compute z' as the
+// tile's own groups do, and z' is staged in a second LDS plane; one barrier
+// per plane.  z is read from one buffer and written to the other, since a
+// sweep reads z in the tiles beside its own while they are written.  A tile
+// above the bottom of the grid starts one plane low: that plane's z' serves
+// the faces below the tile and nothing is stored or summed for it.
+constexpr int kLdsS = kTileY + 3;   // LDS rows: y0 - 2 .. y0 + kTileY
+
+template <typename T, typename KE, int N>
+struct LdsSweep {
+    T p[2][kLdsS * lds_w<N>()];
+    T z[2][kLdsS * lds_w<N>()];
+    KE k[2][kLdsS * lds_w<N>()];
+};
+
+template <typename T, typename KE, int N>
+__device__ __forceinline__ LdsSweep<T, KE, N> &lds_sweep()
+{
+    __shared__ __attribute__((aligned(16))) LdsSweep<T, KE, N> s;
+    return s;
+}
+
+template <typename T, typename X, class C, int XM, int N>
+__device__ void lds_sweep_cg(const Slot &S, const SlotState &st, int64_t lt, const C &cf,
+                             double (&acc)[3])
+{
+    constexpr int TX = tile_x<N>(), W = lds_w<N>(), G = TX / N;
+    static_assert(3 * G + 2 * kTileY + 3 <= kBlock, "the halo roles fit the workgroup");
+    using K = typename C::Key;
+    using KE = typename KeyElem<C>::type;
+    using KP = KeyGroup<C, N>;
+    using KR = typename KP::raw;
+    using V = typename VecN<T, N>::type;
+    LdsSweep<T, KE, N> &L = lds_sweep<T, KE, N>();
+    const int l = (int)threadIdx.x;
+    const TileCtx t = group_ctx(S, lt);
+    const int ii = (N * l) % TX, jj = (N * l) / TX;
+    const int ti0 = t.i - ii, tj0 = t.j - jj;
+    const int nx = S.nx, ny = S.ny, nz = S.nz, bm = S.bcmask;
+    const bool px = (S.permask & 1) && nx > 1, py = (S.permask & 2) && ny > 1;
+    const int64_t P = t.P;
+    const int pbuf = __builtin_amdgcn_readfirstlane(st.pbuf);
+    const int zsel = __builtin_amdgcn_readfirstlane(st.zsel);
+    const GLB V *__restrict__ zin = (const GLB V *)gp((const T *)(zsel ? S.z2 : S.z));
+    GLB V *__restrict__ zout = (GLB V *)gp((T *)(zsel ? S.z : S.z2));
+    const GLB V *__restrict__ qv = (const GLB V *)gp((const T *)dir_buf(S, pbuf));
+    GLB V *__restrict__ pdv = (GLB V *)gp((T *)dir_buf(S, dir_next(pbuf)));
+    const GLB V *__restrict__ pv0 = (const GLB V *)gp((const T *)dir_buf(S, dir_prev(pbuf)));
+    GLB X *__restrict__ x = gp(std::is_same<X, double>::value ? (X *)S.x : (X *)S.d32);
+    const T beta = (T)st.beta, alpha = (T)st.alpha;
+    const T alpha_p0 = (T)st.alpha_p0, alpha_p1 = (T)st.alpha_p1;
+    const int64_t qo = (int64_t)min(t.j, ny - 1) * nx + min(t.i, nx - N);
+    const int own = (jj + 2) * W + ii + N;
+    // halo role of this lane: a group of the rows below (two) or above the
+    // tile, of the two columns left of it (the right one of which also gets
+    // z'), or one cell (with its group) of the column right of it; wrapped
+    // on periodic axes, clamped at walls, where the cells that would use it
+    // substitute the wall.  role 2: p and z', role 1: p only.
+    int dx = 0, dy = 0, role = 0;
+    if (l < G) { dx = N * l; dy = -1; role = 2; }
+    else if (l < 2 * G) { dx = N * (l - G); dy = -2; role = 1; }
+    else if (l < 3 * G) { dx = N * (l - 2 * G); dy = kTileY; role = 1; }
+    else {
+        const int m = l - 3 * G;
+        if (m < kTileY) { dx = -N; dy = m; role = 2; }
+        else if (m < kTileY + 2) { dx = -N; dy = m == kTileY ? -1 : kTileY; role = 1; }
+        else if (m < 2 * kTileY + 3) { dx = TX; dy = m - kTileY - 3; role = 1; }
+    }
+    int64_t qh = qo;
+    int hslot = own, hi = t.i, hj = t.j;
+    if (role) {
+        int ix = ti0 + dx, jy = tj0 + dy;
+        ix = px ? (ix + nx) % nx : max(0, min(nx - N, ix));
+        jy = py ? (jy + ny) % ny : max(0, min(ny - 1, jy));
+        qh = (int64_t)jy * nx + ix;
+        hslot = (dy + 2) * W + dx + N;
+        hi = ix;
+        hj = jy;
+    }
+    // lanes of the z' halo waves without a z' role evaluate at their own
+    // group's place (in bounds; the result is dropped)
+    const int hs = role == 2 ? hslot : own;
+    const int lw = __builtin_amdgcn_readfirstlane(l);
+    // the waves holding halo lanes load in every lane; those holding z'
+    // halo lanes evaluate the halo groups in every lane
+    const bool hwave = lw < 3 * G + 2 * kTileY + 3;
+    const bool swave = lw < G || (lw >= 3 * G && lw < 3 * G + kTileY);
+    const int i0 = t.i, j = t.j;
+    const bool hxm = i0 > 0 || px, hxp = i0 + N - 1 < nx - 1 || px;
+    const bool hym = j > 0 || py, hyp = j < ny - 1 || py;
+    const bool gxm = hi > 0 || px, gxp = hi + N - 1 < nx - 1 || px;
+    const bool gym = hj > 0 || py, gyp = hj < ny - 1 || py;
+    // Dirichlet high walls in delta: x+ of the group's last cell, y+ of all
+    const bool hwx = !hxp && (bm & 2), hwy = !hyp && (bm & 8);
+    const K wxm = (bm & 1) ? cf.dirichlet() : cf.neumann();
+    const K wxp = (bm & 2) ? cf.dirichlet() : cf.neumann();
+    const K wym = (bm & 4) ? cf.dirichlet() : cf.neumann();
+    const K wyp = (bm & 8) ? cf.dirichlet() : cf.neumann();
+    const K wzm = (bm & 16) ? cf.dirichlet() : cf.neumann();
+    const K wzp = (bm & 32) ? cf.dirichlet() : cf.neumann();
+    struct Raw {
+        V z, q, hz, hq;
+        KR k, hk;
+    };
+    // loads past the tile re-read a plane inside the tile and the grid
+    const int klast = min(t.k1, nz - 1);
+    auto load = [&](int kk) {
+        kk = min(kk, klast);
+        const int64_t base = (int64_t)kk * P;
+        Raw R{};
+        R.z = zin[(base + qo) / N];
+        R.q = qv[(base + qo) / N];
+        R.k = KP::load(cf, base + qo);
+        if (hwave) {
+            R.hz = zin[(base + qh) / N];
+            R.hq = qv[(base + qh) / N];
+            R.hk = KP::load(cf, base + qh);
+        }
+        return R;
+    };
+    // delta's terms of one plane's groups: faces toward x-, y- and z- and the
+    // Dirichlet high walls; the x-/y- neighbours' z' from LDS, their keys as
+    // the operator row read them
+    auto delta = [&](const T *Lz, const T (&zc)[N], const T (&zd)[N], const T (&bd)[N],
+                     const K (&kd)[N], K kxl, const K (&kyd)[N],
+                     bool dtop) __attribute__((always_inline)) {
+        const V zym = *(const V *)(Lz + own - W);
+        T zl = hxm ? Lz[own - 1] : T(0);
+        K kl = kxl;
+        double d = 0.0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const Areas6<T> ar = cf.areas(i0 + n, j, 0, 0);
+            const T ex = zc[n] - zl, ey = zc[n] - (hym ? zym[n] : T(0)), ez = zc[n] - zd[n];
+            T sn = (cf.beta(kd[n], kl) * ar.xm * ex * ex + cf.beta(kd[n], kyd[n]) * ar.ym * ey * ey) +
+                   bd[n] * ez * ez;
+            const T w = ((n == N - 1 && hwx) ? ar.xp : T(0)) + (hwy ? ar.yp : T(0)) +
+                        (dtop ? ar.zp : T(0));
+            sn += w * cf.beta(kd[n], cf.dirichlet()) * (zc[n] * zc[n]);
+            d += (double)sn;
+            zl = zc[n];
+            kl = kd[n];
+        }
+        return d;
+    };
+    const int kb = t.k0 > 0 ? t.k0 - 1 : 0;
+    // carried per group: p one plane down (vzm) and at this plane (vc), the
+    // key (kc, and as loaded: kr), the low z face coefficient (bzm), z at
+    // this plane (uc), the previous direction at this plane (qc, also the
+    // catch-up form's direction one back); for the previous plane's delta
+    // its z' (z1), z' one more plane down (z2), its low z face coefficient
+    // (bd1), its keys and those of its x-/y- neighbours; the same for the
+    // halo group (h*) without delta
+    T vzm[N], vc[N], bzm[N], uc[N], qc[N], z1[N], z2[N], bd1[N];
+    T hvzm[N], hvc[N], hbzm[N], huc[N];
+    K kc[N], k1[N], ky1[N], hkc[N];
+    K kx1 = wxm;
+    KR kr, hkr;
+    {
+        K kzm[N], hkzm[N];
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            vzm[n] = hvzm[n] = z1[n] = z2[n] = bd1[n] = T(0);
+            kzm[n] = hkzm[n] = wzm;
+            k1[n] = ky1[n] = wzm;
+        }
+        if (kb > 0) {
+            const Raw R = load(kb - 1);
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                vzm[n] = R.z[n] + beta * R.q[n];
+                hvzm[n] = R.hz[n] + beta * R.hq[n];
+            }
+            KP::split(R.k, kzm);
+            KP::split(R.hk, hkzm);
+        }
+        const Raw A = load(kb);
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            vc[n] = A.z[n] + beta * A.q[n];
+            hvc[n] = A.hz[n] + beta * A.hq[n];
+            uc[n] = A.z[n];
+            huc[n] = A.hz[n];
+            qc[n] = A.q[n];
+        }
+        kr = A.k;
+        hkr = A.hk;
+        KP::split(kr, kc);
+        KP::split(hkr, hkc);
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            bzm[n] = cf.beta(kc[n], kzm[n]) * cf.areas(i0 + n, j, kb, 0).zm;
+            hbzm[n] = cf.beta(hkc[n], hkzm[n]) * cf.areas(hi + n, hj, kb, 0).zm;
+        }
+    }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    int b = 0;
+    for (int k = kb; k < t.k1; ++k, b ^= 1) {
+        const bool emit = k >= t.k0;
+        const bool top = k == nz - 1;
+        const int64_t c = (int64_t)k * P;
+        // stage plane k's p and keys
+        {
+            V pv_n, hv_n;
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                pv_n[n] = vc[n];
+                hv_n[n] = hvc[n];
+            }
+            *(V *)(L.p[b] + own) = pv_n;
+            KP::put(L.k[b] + own, kr);
+            if (role) {
+                *(V *)(L.p[b] + hslot) = hv_n;
+                KP::put(L.k[b] + hslot, hkr);
+            }
+        }
+        // plane k + 1 (z neighbours now, staged next), and this plane's
+        // catch-up operands, in flight across the barrier
+        const Raw Rn = load(k + 1);
+        X xo[N];
+        V v0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            xo[n] = X(0);
+            v0[n] = T(0);
+        }
+        if (XM == 3 && emit) {
+#pragma unroll
+            for (int n = 0; n < N; ++n) xo[n] = __builtin_nontemporal_load(&x[c + qo + n]);
+            v0 = __builtin_nontemporal_load(&pv0[(c + qo) / N]);
+        }
+        __syncthreads();
+        // the previous plane's delta (its z' staged before this barrier)
+        if (k - 1 >= t.k0) {
+            const double d = delta(L.z[b ^ 1], z1, z2, bd1, k1, kx1, ky1, false);
+            if (t.active) a2 += d;
+        }
+        const T *Lp = L.p[b];
+        const KE *Lk = L.k[b];
+        T *Lz = L.z[b];
+        V pn, hpn;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            pn[n] = top ? T(0) : Rn.z[n] + beta * Rn.q[n];
+            hpn[n] = top ? T(0) : Rn.hz[n] + beta * Rn.hq[n];
+        }
+        K kzp[N], hkzp[N];
+        KP::split(Rn.k, kzp);
+        KP::split(Rn.hk, hkzp);
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            kzp[n] = top ? wzp : kzp[n];
+            hkzp[n] = top ? wzp : hkzp[n];
+        }
+        // this plane's groups: q, z', the x update and the dot terms
+        const V vym = *(const V *)(Lp + own - W), vyp = *(const V *)(Lp + own + W);
+        K kym[N], kyp[N];
+        KP::split(KP::get(Lk + own - W), kym);
+        KP::split(KP::get(Lk + own + W), kyp);
+        const T lvxm = Lp[own - 1], lvxp = Lp[own + N];
+        const K lkxm = (K)Lk[own - 1], lkxp = (K)Lk[own + N];
+        T zn[N];
+        X xn[N];
+        double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            kym[n] = hym ? kym[n] : wym;
+            bd1[n] = bzm[n];   // this plane's low z face, for its delta
+            const Areas6<T> ar = cf.areas(i0 + n, j, k, c + qo + n);
+            const T vxm = n > 0 ? vc[n - 1] : (hxm ? lvxm : T(0));
+            const K kxm = n > 0 ? kc[n - 1] : (hxm ? lkxm : wxm);
+            const T vxp = n < N - 1 ? vc[n + 1] : (hxp ? lvxp : T(0));
+            const K kxp = n < N - 1 ? kc[n + 1] : (hxp ? lkxp : wxp);
+            passB_cell<T, X, C, XM>(cf, ar, kc[n], vc[n], vxm, kxm, vxp, kxp,
+                                    hym ? vym[n] : T(0), kym[n],
+                                    hyp ? vyp[n] : T(0), hyp ? kyp[n] : wyp, vzm[n], pn[n],
+                                    kzp[n], bzm[n], uc[n], alpha, alpha_p0, alpha_p1, xo[n],
+                                    v0[n], qc[n], xn[n], zn[n], g0, g1);
+        }
+        {
+            V zv_n;
+#pragma unroll
+            for (int n = 0; n < N; ++n) zv_n[n] = zn[n];
+            *(V *)(Lz + own) = zv_n;
+            if (emit && t.active) {
+                a0 += g0;
+                a1 += g1;
+                V pv_n;
+#pragma unroll
+                for (int n = 0; n < N; ++n) pv_n[n] = vc[n];
+                __builtin_nontemporal_store(pv_n, &pdv[(c + qo) / N]);
+                __builtin_nontemporal_store(zv_n, &zout[(c + qo) / N]);
+                if (XM == 3) {
+#pragma unroll
+                    for (int n = 0; n < N; ++n) __builtin_nontemporal_store(xn[n], &x[c + qo + n]);
+                }
+            }
+        }
+        // the halo groups that need z': the row below the tile, the column left of it
+        if (swave) {
+            const V hym_v = *(const V *)(Lp + hs - W), hyp_v = *(const V *)(Lp + hs + W);
+            K hkym[N], hkyp[N];
+            KP::split(KP::get(Lk + hs - W), hkym);
+            KP::split(KP::get(Lk + hs + W), hkyp);
+            const T hlvxm = Lp[hs - 1], hlvxp = Lp[hs + N];
+            const K hlkxm = (K)Lk[hs - 1], hlkxp = (K)Lk[hs + N];
+            T hz[N];
+            X hx[N];
+            double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+            for (int n = 0; n < N; ++n) {
+                const Areas6<T> ar = cf.areas(hi + n, hj, k, 0);
+                const T vxm = n > 0 ? hvc[n - 1] : (gxm ? hlvxm : T(0));
+                const K kxm = n > 0 ? hkc[n - 1] : (gxm ? hlkxm : wxm);
+                const T vxp = n < N - 1 ? hvc[n + 1] : (gxp ? hlvxp : T(0));
+                const K kxp = n < N - 1 ? hkc[n + 1] : (gxp ? hlkxp : wxp);
+                passB_cell<T, X, C, 0>(cf, ar, hkc[n], hvc[n], vxm, kxm, vxp, kxp,
+                                       gym ? hym_v[n] : T(0), gym ? hkym[n] : wym,
+                                       gyp ? hyp_v[n] : T(0), gyp ? hkyp[n] : wyp, hvzm[n],
+                                       hpn[n], hkzp[n], hbzm[n], huc[n], alpha, alpha_p0,
+                                       alpha_p1, X(0), T(0), T(0), hx[n], hz[n], d0, d1);
+            }
+            if (role == 2) {
+                V hv;
+#pragma unroll
+                for (int n = 0; n < N; ++n) hv[n] = hz[n];
+                *(V *)(Lz + hslot) = hv;
+            }
+        }
+        // carry up one plane
+        kx1 = hxm ? lkxm : wxm;
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            z2[n] = z1[n];
+            z1[n] = zn[n];
+            k1[n] = kc[n];
+            ky1[n] = kym[n];
+            vzm[n] = vc[n];
+            vc[n] = pn[n];
+            kc[n] = kzp[n];
+            uc[n] = Rn.z[n];
+            qc[n] = Rn.q[n];
+            hvzm[n] = hvc[n];
+            hvc[n] = hpn[n];
+            hkc[n] = hkzp[n];
+            huc[n] = Rn.hz[n];
+        }
+        kr = Rn.k;
+        hkr = Rn.hk;
+    }
+    // the last plane's delta
+    __syncthreads();
+    if (t.k1 - 1 >= t.k0) {
+        const double d = delta(L.z[b ^ 1], z1, z2, bd1, k1, kx1, ky1,
+                               t.k1 == nz && (bm & 32));
+        if (t.active) a2 += d;
+    }
+    // (a0, a1, a2 hold only active lanes' terms; acc[2] first, so that the
+    // stores ending this form and pass B address the same elements and their
+    // merged tail stays out of scratch)
+    acc[2] += a2;
+    acc[0] += a0;
+    acc[1] += a1;
 }
 
 // Pass A / pass B for the tile form of the slot (four cells per thread for
@@ -1862,7 +2252,39 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         st.alpha = st.rz / pap;
         st.pbuf = dir_next(st.pbuf);
         st.first = 0;
-        st.phase = K2_CG_B;
+        // one-sweep iterations: this pass A gave the first p.A p; the first
+        // sweep forms the same direction again (beta = 0)
+        if (st.fused) { st.beta = 0.0; st.phase = K2_CG_F; }
+        else st.phase = K2_CG_B;
+        break;
+    }
+    case K2_CG_F: {
+        // tot = [r.z, r.r, z.A z] of the new residual
+        st.iter += 1;
+        st.rr = tot[1];
+        note_x_update(st);   // with the alpha this sweep used
+        st.pbuf = dir_next(st.pbuf);
+        st.zsel ^= 1;
+        if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2])) {
+            finish(st, PCG_EBREAKDOWN);
+            break;
+        }
+        const double beta = tot[0] / st.rz;
+        const double pap = tot[2] - beta * tot[0] / st.alpha;
+        st.beta = beta;
+        st.rz = tot[0];
+        st.pap = pap;
+        const bool ok = pap > 0.0 && isfinite(pap);
+        if (ok) st.alpha = tot[0] / pap;
+        if (st.rr <= st.tol2 || st.iter >= st.maxit) {
+            st.phase = st.xpend ? K1_FLUSH_X : K1_CHECK64;
+            st.after = K1_CHECK64;
+        } else if (!ok) {
+            if (st.xpend) { st.status = PCG_EBREAKDOWN; st.phase = K1_FLUSH_X; }
+            else finish(st, PCG_EBREAKDOWN);
+        } else {
+            st.phase = K2_CG_F;   // the next K1 launch passes this slot by
+        }
         break;
     }
     case K2_CG_B: {
@@ -1892,7 +2314,11 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         const int end = st.singular ? K1_MEAN_X : PH_DONE;
         if (tot[0] <= st.tol2) { st.phase = K2_NONE; st.after = end; st.status = PCG_OK; }
         else if (st.iter >= st.maxit) { st.phase = K2_NONE; st.after = end; st.status = PCG_MAXIT; }
-        else { st.phase = K2_NONE; st.after = K1_CG_A; }
+        else if (st.fused && st.iter > 0) {
+            // the last sweep left alpha and beta for the next one
+            if (st.pap > 0.0 && isfinite(st.pap)) st.phase = K2_CG_F;
+            else finish(st, PCG_EBREAKDOWN);
+        } else { st.phase = K2_NONE; st.after = K1_CG_A; }
         break;
     }
     case K1_MEAN_B: {
@@ -2105,6 +2531,15 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
                 } else {
                     if (catch_up) lds_passB<double, double, RhoCoef<double>, 3, 2>(S, st, lt, r64, acc);
                     else lds_passB<double, double, RhoCoef<double>, 0, 2>(S, st, lt, r64, acc);
+                }
+            } else if (ph == K2_CG_F) {
+                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
+                if (MODE == 3) {
+                    if (catch_up) lds_sweep_cg<double, double, ClsCoef<double>, 3, 2>(S, st, lt, c64, acc);
+                    else lds_sweep_cg<double, double, ClsCoef<double>, 0, 2>(S, st, lt, c64, acc);
+                } else {
+                    if (catch_up) lds_sweep_cg<double, double, RhoCoef<double>, 3, 2>(S, st, lt, r64, acc);
+                    else lds_sweep_cg<double, double, RhoCoef<double>, 0, 2>(S, st, lt, r64, acc);
                 }
             } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
             else if (ph == K2_SUB_X) body_sub_x(S, st, lt, r64, acc);

@@ -49,6 +49,8 @@ enum Phase : int32_t {
     K2_IR_UPDATE = 14, // x += s d, d = 0
     K2_ZERO_X = 15,    // x = 0 (zero source with a warm start)
     K2_SUB_X = 16,     // singular problem: x -= its fluid mean
+    K2_CG_F = 17,      // one-sweep iteration: p = z + beta p, q = A p, x += alpha p
+                       // (three at a time), z' = z - alpha D^-1 q ; r.z, r.r, z'.A z'
     PH_DONE = 20
 };
 
@@ -86,7 +88,8 @@ struct alignas(128) SlotState {
     int32_t warm;     // warm start requested
     int32_t singular; // no Dirichlet face: solve for the mean-free source
     int32_t xpend;    // earlier iterations whose x (FP64) or d (IR) update is pending: 0..2
-    int32_t pad_[1];
+    int32_t fused;    // FP64 iterations run as one sweep (K2_CG_F)
+    int32_t zsel;     // one-sweep iterations: z is in Slot::z2 (1) or Slot::z (0)
 };
 
 // Read-only description of a slot (rewritten by the host between replays).
@@ -110,6 +113,10 @@ struct Slot {
     const double *rho64;   // density, +inf in solid cells
     const float *rho32;    // IR only
     void *z;               // D^-1 r   (double, or float for IR)
+    // second z buffer of the one-sweep iteration, or null: a sweep reads z
+    // in its neighbours' tiles while they write theirs, so it reads one
+    // buffer and writes the other
+    void *z2;
     // search directions, rotating: pass A reads buffer b and writes b + 1
     // (mod 3), so the two directions before the current one stay readable
     void *dir0, *dir1, *dir2;

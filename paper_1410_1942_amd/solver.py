@@ -168,10 +168,15 @@ class Solver:
     def tile_form(self):
         """(columns, rows) of the context's plane tiles, or (0, 0) for tiles
         of consecutive cells (pcg_tile_form)."""
-        tx, ty = ctypes.c_int32(), ctypes.c_int32()
-        L.check(self.lib.pcg_tile_form(self._ctx, ctypes.byref(tx), ctypes.byref(ty)),
-                "pcg_tile_form")
-        return tx.value, ty.value
+        return self.tile_form_ex()[:2]
+
+    def tile_form_ex(self):
+        """(columns, rows, sweeps per iteration) of the context's tiles
+        (pcg_tile_form)."""
+        tx, ty, sw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        L.check(self.lib.pcg_tile_form(self._ctx, ctypes.byref(tx), ctypes.byref(ty),
+                                       ctypes.byref(sw)), "pcg_tile_form")
+        return tx.value, ty.value, sw.value
 
     def set_fractions(self, ax=None, ay=None, az=None, vol=None):
         """Free-slip cut-cell fractions (pcg_set_fractions): MAC face area

@@ -223,25 +223,43 @@ def test_tile_rules_roundtrip(lib):
         zero = (ctypes.c_int32 * 2)(0, 8)
         ok_mc = (ctypes.c_int64 * 2)(5, 10)
         assert lib.pcg_set_tile_rules(0, 0, 2, ok_mc, zero, None) == L.EINVAL
-        assert lib.pcg_set_tile_rules(0, 2, 2, ok_mc, tz, None) == L.EINVAL
-        # the batch table is separate from the single-solve one
+        assert lib.pcg_set_tile_rules(0, 3, 2, ok_mc, tz, None) == L.EINVAL
+        assert lib.pcg_get_tile_rules(0, 3, 0, None, None, None, ctypes.byref(n)) == L.EINVAL
+        # the batch and plane-tile tables are separate from the single-solve one
         batch_saved = autotune.get_rules(0, for_batches=True)
         autotune.set_rules(0, [[10**9, 16, 0]], for_batches=True)
         assert autotune.get_rules(0, for_batches=True)[0][1] == 16
         assert [r[1:] for r in autotune.get_rules(0)] == [[4, 256], [8, 0], [64, 512]]
         autotune.set_rules(0, batch_saved, for_batches=True)
-        # workspace: partial sums scale with the number of tiles (tz = 64 -> fewer)
+        autotune.set_rules(0, [[10**9, 2, 0]], table=autotune.PLANE)
+        assert autotune.get_rules(0, table=autotune.PLANE) == [[2**63 - 1, 2, 0]]
+        assert [r[1:] for r in autotune.get_rules(0)] == [[4, 256], [8, 0], [64, 512]]
+        # workspace: partial sums scale with the number of tiles (tz = 64 -> fewer),
+        # on consecutive-cell tiles (rows of 96) from the single-solve table
         o = L.Opts()
         w64 = ctypes.c_size_t()
-        lib.pcg_workspace_bytes(ctypes.byref(_g(128, 128, 128)), ctypes.byref(o),
+        lib.pcg_workspace_bytes(ctypes.byref(_g(96, 128, 128)), ctypes.byref(o),
                                 ctypes.byref(w64))
+        # rows of 128 take plane tiles and the plane table (tz = 2 here)
+        wp2 = ctypes.c_size_t()
+        lib.pcg_workspace_bytes(ctypes.byref(_g(128, 128, 128)), ctypes.byref(o),
+                                ctypes.byref(wp2))
         autotune.set_rules(0, [[10**9, 1, 0]])
         w1 = ctypes.c_size_t()
-        lib.pcg_workspace_bytes(ctypes.byref(_g(128, 128, 128)), ctypes.byref(o),
+        lib.pcg_workspace_bytes(ctypes.byref(_g(96, 128, 128)), ctypes.byref(o),
                                 ctypes.byref(w1))
         assert w1.value > w64.value
+        wp = ctypes.c_size_t()
+        lib.pcg_workspace_bytes(ctypes.byref(_g(128, 128, 128)), ctypes.byref(o),
+                                ctypes.byref(wp))
+        assert wp.value == wp2.value
+        autotune.set_rules(0, [[10**9, 64, 0]], table=autotune.PLANE)
+        lib.pcg_workspace_bytes(ctypes.byref(_g(128, 128, 128)), ctypes.byref(o),
+                                ctypes.byref(wp))
+        assert wp.value < wp2.value
     finally:
         autotune.set_rules(0, saved)
+        autotune.install(arch="gfx950")
 
 
 def test_stage_entry_points_reject_null_context(lib):
@@ -299,9 +317,10 @@ def test_built_in_tile_rules_match_the_shipped_table():
     import subprocess
     import sys
     code = ("import json; from paper_1410_1942_amd import autotune, _lib as L; "
-            "print(json.dumps({k: [list(r) for r in autotune.get_rules(p, b)] "
-            "for k, p, b in (('fp64', L.PREC_FP64, False), ('fp32_ir', L.PREC_FP32_IR, False), "
-            "('fp64_batch', L.PREC_FP64, True), ('fp32_ir_batch', L.PREC_FP32_IR, True))}))")
+            "print(json.dumps({k: [list(r) for r in autotune.get_rules(p, table=b)] "
+            "for k, p, b in (('fp64', L.PREC_FP64, 0), ('fp32_ir', L.PREC_FP32_IR, 0), "
+            "('fp64_batch', L.PREC_FP64, 1), ('fp32_ir_batch', L.PREC_FP32_IR, 1), "
+            "('fp64_plane', L.PREC_FP64, 2), ('fp32_ir_plane', L.PREC_FP32_IR, 2))}))")
     env = dict(os.environ, PCGMI_TILE_TABLE="none")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, check=True,
                          capture_output=True, text=True).stdout
@@ -310,3 +329,38 @@ def test_built_in_tile_rules_match_the_shipped_table():
     unbounded = lambda rules: [[None if r[0] >= 2**62 else r[0], r[1], r[2]] for r in rules]
     for k, rules in built_in.items():
         assert unbounded(rules) == unbounded(table[k]), k
+
+
+def test_one_sweep_workspace(lib):
+    """The one-sweep iteration (the default of FP64 plane tiles) adds one FP64
+    vector, the second z, to the workspace; PCG_TWO_SWEEPS drops it, and
+    nothing changes where it does not apply (rows not a multiple of 128
+    cells, the FP32 refinement, consecutive-cell tiles)."""
+    def ws(g, flags, prec=0):
+        o = L.Opts()
+        o.flags = flags
+        o.precision = prec
+        out = ctypes.c_size_t()
+        assert lib.pcg_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ctypes.byref(out)) == L.OK
+        return out.value
+
+    g = _g(128, 16, 8)
+    n = 128 * 16 * 8
+    # (the partial sums of the two tile forms differ by a few aligned blocks)
+    assert 8 * n - 4 * 256 <= ws(g, L.PLANE_TILES) - ws(g, L.PLANE_TILES | L.TWO_SWEEPS) <= 8 * n
+    assert ws(g, 0) == ws(g, L.PLANE_TILES)           # FP64 takes plane tiles at any size
+    # with the walls unknown a periodic y axis may still send a grid to
+    # consecutive-cell tiles: the workspace covers both forms
+    for shape in [(128, 13, 6), (128, 1, 6), (256, 7, 5), (128, 16, 8), (384, 9, 3)]:
+        gs = _g(*shape)
+        for extra in (0, L.TWO_SWEEPS):
+            assert ws(gs, extra) >= ws(gs, L.FLAT_TILES), (shape, extra)
+            assert ws(gs, L.PLANE_TILES | extra) >= ws(gs, L.FLAT_TILES), (shape, extra)
+    g96 = _g(96, 16, 8)
+    assert ws(g96, L.PLANE_TILES) == ws(g96, L.PLANE_TILES | L.TWO_SWEEPS)
+    assert ws(g, L.PLANE_TILES | L.FLAT_TILES) == ws(g, L.PLANE_TILES | L.FLAT_TILES | L.TWO_SWEEPS)
+    g256 = _g(256, 16, 8)
+    assert ws(g256, L.PLANE_TILES, 1) == ws(g256, L.PLANE_TILES | L.TWO_SWEEPS, 1)
+    # a 512^3 FP64 grid takes plane tiles, hence the second z, by default
+    big = _g(512, 512, 512)
+    assert ws(big, 0) - ws(big, L.TWO_SWEEPS) == 8 * 512 ** 3

@@ -1,0 +1,208 @@
+"""The one-sweep FP64 iteration on plane tiles (the Chronopoulos-Gear
+recurrences, one pass over the grid per iteration; the default of FP64
+plane tiles, PCG_TWO_SWEEPS switches it off), through the C ABI, against
+the oracle.
+
+The recurrences give the iterates of the two-sweep iteration in exact
+arithmetic, so the bar is the oracle's: the converged answer against the
+oracle's 1e-12 solution, the iteration count against the oracle's, the k-th
+iterate of a capped solve against the oracle's k-th iterate, and the
+two-sweep plane-tile result.  The cases cover ragged tile rows, a single row,
+every wall kind on every side, periodic axes (and the fall-back to
+consecutive-cell tiles, where the flag is ignored), hulls, both coefficient
+sources, tile heights down to one plane (every tile then starts one plane
+below its first), launch-grid independence, a warm start, and a batch that
+mixes the one-sweep form with the others.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TANK = (0, 0, 0, 0, 0, 1)
+P = 2
+FLAT_TILES = 16
+PLANE = 32
+TWO = 64
+NO_CLASSES = 4
+WARM = 1
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+def _to(torch, dev, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _solve(torch_dev, case, tol=1e-8, flags=PLANE, maxit=1000000, p0=None, **kw):
+    torch, dev = torch_dev
+    from paper_1410_1942_amd.solver import Solver
+    s = Solver(_to(torch, dev, case.rho), _to(torch, dev, case.mask), case.bc, case.h,
+               flags=flags & ~WARM, **kw)
+    p = None if p0 is None else _to(torch, dev, p0)
+    p, st = s.solve(_to(torch, dev, case.rhs), p=p, tol=tol, maxit=maxit,
+                    raise_on_error=False, warm=bool(flags & WARM))
+    torch.cuda.synchronize()
+    s.close()
+    return p.cpu().numpy(), st
+
+
+def _case(F, shape, bc, wedge=True, s1=31, s2=32):
+    nx, ny, nz = shape
+    return F.make_two_phase(nx, ny, nz, surface_seed=s1, velocity_seed=s2,
+                            wedge=F.Wedge() if wedge else None, bc=bc)
+
+
+CASES = [
+    ((128, 20, 9), TANK, True),                 # one tile across, five tile rows
+    ((256, 7, 5), (1, 0, 0, 1, 0, 1), False),   # ragged last tile row (7 = 4 + 3)
+    ((128, 1, 6), TANK, False),                 # a single row: three of four tile rows empty
+    ((384, 9, 3), (1, 1, 1, 1, 1, 1), True),    # Dirichlet everywhere, three tiles across
+    ((128, 16, 12), (P, P, P, P, 0, 1), True),  # periodic x and y holding whole tiles
+    ((128, 12, 10), (P, P, 0, 0, 0, 0), True),  # periodic x, no-flux: singular
+    ((256, 8, 7), (0, 1, P, P, 1, 0), True),    # periodic y, Dirichlet x+ and z-
+    ((128, 13, 6), (0, 0, P, P, 0, 1), False),  # periodic y, 13 rows: consecutive-cell tiles
+]
+
+
+@pytest.mark.parametrize("shape,bc,wedge", CASES, ids=lambda v: str(v))
+@pytest.mark.parametrize("flags", [PLANE, PLANE | NO_CLASSES],
+                         ids=["classes", "density"])
+def test_one_sweep_parity(orc, F, torch_dev, shape, bc, wedge, flags):
+    case = _case(F, shape, bc, wedge)
+    _say(f"case one sweep {shape} bc={bc} wedge={wedge} flags={flags}")
+    p, st = _solve(torch_dev, case, flags=flags)
+    assert st["status"] == 0, st
+    rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p)
+    assert rr <= 1e-8, (rr, st)
+    assert abs(st["rel_res_true"] - rr) <= 1e-3 * rr + 1e-15
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-12)
+    assert ref.status == orc.OK
+    scale = np.abs(ref.p).max()
+    assert np.abs(p - ref.p).max() <= 1e-6 * scale
+    assert np.all(p[case.mask.astype(bool)] == 0.0)
+    o8 = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-8)
+    assert abs(st["iters"] - o8.iters) <= max(2, 0.02 * o8.iters), (st, o8.iters)
+    # the two-sweep iteration on the same tiles
+    p2, st2 = _solve(torch_dev, case, flags=flags | TWO)
+    assert abs(st2["iters"] - st["iters"]) <= max(1, 0.01 * st["iters"]), (st, st2)
+    assert np.abs(p2 - p).max() <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 13, 14, 15, 16, 17])
+def test_one_sweep_capped_iterate(orc, F, torch_dev, k):
+    """Capped at k iterations the solution is the oracle's k-th PCG iterate,
+    whatever k is modulo the interval of the deferred x update."""
+    case = _case(F, (128, 9, 14), TANK)
+    _say(f"case one sweep capped k={k}")
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=k)
+    prev = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=k - 1)
+    scale = np.abs(ref.p).max()
+    assert np.abs(ref.p - prev.p).max() > 1e-3 * scale
+    p, st = _solve(torch_dev, case, tol=1e-30, maxit=k)
+    assert st["status"] == 1 and st["iters"] == k, st
+    assert np.abs(p - ref.p).max() <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("tz", [1, 2, 3, 8])
+def test_one_sweep_tile_heights(orc, F, torch_dev, tz):
+    """Short tiles: every tile above the bottom starts one plane low."""
+    case = _case(F, (128, 10, 11), TANK)
+    _say(f"case one sweep tz={tz}")
+    p, st = _solve(torch_dev, case, tz=tz)
+    assert st["status"] == 0, st
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-12)
+    assert np.abs(p - ref.p).max() <= 1e-6 * np.abs(ref.p).max()
+
+
+def test_one_sweep_grid_independence(F, torch_dev):
+    """Per-tile partial sums: the result does not depend on the launch grid,
+    bit for bit, and repeats bit for bit."""
+    case = _case(F, (256, 18, 13), TANK)
+    _say("case one sweep grids")
+    p1, s1 = _solve(torch_dev, case, grid_blocks=8)
+    p2, s2 = _solve(torch_dev, case, grid_blocks=1024)
+    p3, s3 = _solve(torch_dev, case, grid_blocks=1024)
+    assert s1["iters"] == s2["iters"] == s3["iters"]
+    assert np.array_equal(p1, p2) and np.array_equal(p2, p3)
+
+
+def test_one_sweep_warm_start(orc, F, torch_dev):
+    """A warm start from a perturbed answer converges to the oracle's."""
+    case = _case(F, (128, 12, 9), (1, 0, 0, 0, 0, 1))
+    _say("case one sweep warm")
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-12)
+    rng = np.random.default_rng(5)
+    p0 = ref.p * (1.0 + 1e-3 * rng.standard_normal(ref.p.shape))
+    p0[case.mask.astype(bool)] = 0.0
+    p, st = _solve(torch_dev, case, flags=PLANE | WARM, p0=p0)
+    assert st["status"] == 0, st
+    assert np.abs(p - ref.p).max() <= 1e-6 * np.abs(ref.p).max()
+    pc, stc = _solve(torch_dev, case)
+    assert st["iters"] < stc["iters"]
+
+
+def test_one_sweep_in_a_batch(F, torch_dev):
+    """A batch mixing a one-sweep solve with two-sweep plane tiles and
+    consecutive-cell tiles gives each the result of its solo run, bit for
+    bit."""
+    import torch
+    from paper_1410_1942_amd import _lib as L
+    from paper_1410_1942_amd.solver import Batch
+    torch_, dev = torch_dev
+    members = [(_case(F, (128, 12, 10), TANK, s1=41, s2=42), PLANE),
+               (_case(F, (128, 8, 9), (1, 0, 0, 1, 0, 1), s1=47, s2=48), PLANE | TWO),
+               (_case(F, (37, 29, 23), TANK, s1=43, s2=44), 0)]
+
+    def run(ms):
+        b = Batch(1 << 28, len(ms), precision=L.PREC_FP64)
+        try:
+            outs = []
+            for c, fl in ms:
+                p = torch.empty(c.shape, dtype=torch.float64, device=dev)
+                code, slot = b.admit(_to(torch_, dev, c.rho), _to(torch_, dev, c.mask), c.bc,
+                                     c.h, _to(torch_, dev, c.rhs), p, tol=1e-8, flags=fl)
+                assert code == L.OK, code
+                outs.append((slot, p))
+            while b.step(1):
+                pass
+            res = [(b.poll(s)[1], p.cpu().numpy()) for s, p in outs]
+        finally:
+            b.close()
+        return res
+
+    _say("case one sweep in a batch")
+    mixed = run(members)
+    for i, m in enumerate(members):
+        (st1, p1), = run([m])
+        assert mixed[i][0]["status"] == 0 and st1["status"] == 0
+        assert mixed[i][0]["iters"] == st1["iters"], i
+        assert np.array_equal(mixed[i][1], p1), i
+
+
+def test_one_sweep_edge_cases(orc, F, torch_dev):
+    """Zero source, an iteration cap of zero, and a breakdown-free exact
+    start (the oracle's converged answer as a warm start)."""
+    case = _case(F, (128, 8, 6), TANK)
+    _say("case one sweep edges")
+    zc = dataclasses.replace(case, rhs=case.rhs * 0.0)
+    p, st = _solve(torch_dev, zc)
+    assert st["status"] == 0 and st["iters"] == 0 and np.all(p == 0.0)
+    p, st = _solve(torch_dev, case, maxit=0)
+    assert st["status"] == 1 and st["iters"] == 0
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-13)
+    p, st = _solve(torch_dev, case, flags=PLANE | WARM, p0=ref.p)
+    assert st["status"] == 0 and st["iters"] <= 2, st

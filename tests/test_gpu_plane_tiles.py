@@ -1,10 +1,13 @@
 """The 2-D plane-tile form (128 x 4 FP64 or 256 x 4 FP32 tiles, in-plane
 neighbours staged in LDS) of the two passes, through the C ABI, against the
-oracle.
+oracle.  FP64 solves on plane tiles run one sweep per iteration by default;
+the FP64 cases here ask for the two passes (PCG_TWO_SWEEPS), whose one-sweep
+counterpart has a test file of its own.
 
-Grids of at least 2^25 cells whose rows are a multiple of the tile width
-(128 cells for FP64, 256 for the FP32 inner solve) take this form by default; PCG_PLANE_TILES asks for it on smaller grids (as
-here) and PCG_FLAT_TILES keeps the consecutive-cell tiles.  The cases cover ragged
+FP64 grids whose rows are a multiple of 128 cells, and FP32 grids of at
+least 2^25 cells whose rows are a multiple of 256, take this form by
+default; PCG_PLANE_TILES asks for it on smaller FP32 grids (as here) and
+PCG_FLAT_TILES keeps the consecutive-cell tiles.  The cases cover ragged
 tile rows (ny not a multiple of 4), a single row, every wall kind on every
 side, periodic axes (and the fall-back to consecutive-cell tiles when a
 periodic y axis does not hold whole tiles), hulls, both coefficient sources,
@@ -23,6 +26,7 @@ TANK = (0, 0, 0, 0, 0, 1)
 P = 2
 FLAT_TILES = 16
 PLANE = 32
+TWO = 64
 NO_CLASSES = 4
 
 
@@ -42,7 +46,7 @@ def _to(torch, dev, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 
 
-def _solve(torch_dev, case, tol=1e-8, flags=PLANE, maxit=1000000, **kw):
+def _solve(torch_dev, case, tol=1e-8, flags=PLANE | TWO, maxit=1000000, **kw):
     torch, dev = torch_dev
     from paper_1410_1942_amd.solver import Solver
     s = Solver(_to(torch, dev, case.rho), _to(torch, dev, case.mask), case.bc, case.h,
@@ -71,7 +75,8 @@ CASES = [
 
 
 @pytest.mark.parametrize("shape,bc,wedge", CASES, ids=lambda v: str(v))
-@pytest.mark.parametrize("flags", [PLANE, PLANE | NO_CLASSES], ids=["classes", "density"])
+@pytest.mark.parametrize("flags", [PLANE | TWO, PLANE | TWO | NO_CLASSES],
+                         ids=["classes", "density"])
 def test_plane_tile_parity(orc, F, torch_dev, shape, bc, wedge, flags):
     case = _case(F, shape, bc, wedge)
     _say(f"case plane tiles {shape} bc={bc} wedge={wedge} flags={flags}")
@@ -188,7 +193,8 @@ def test_plane_tiles_in_a_batch(F, torch_dev):
             for c in members:
                 p = torch.empty(c.shape, dtype=torch.float64, device=dev)
                 code, slot = b.admit(_to(torch_, dev, c.rho), _to(torch_, dev, c.mask), c.bc,
-                                     c.h, _to(torch_, dev, c.rhs), p, tol=1e-8, flags=PLANE)
+                                     c.h, _to(torch_, dev, c.rhs), p, tol=1e-8,
+                                     flags=PLANE | TWO)
                 assert code == L.OK, code
                 outs.append((slot, p))
             while b.step(1):
@@ -208,20 +214,24 @@ def test_plane_tiles_in_a_batch(F, torch_dev):
 
 
 def test_tile_form_reported(F, torch_dev):
-    """pcg_tile_form names the tile form each context took."""
+    """pcg_tile_form names the tile form each context took and its sweeps
+    per iteration."""
     torch, dev = torch_dev
     from paper_1410_1942_amd.solver import Solver
     t = lambda a: _to(torch, dev, a)
     for shape, bc, flags, prec, want in [
-            ((128, 8, 6), TANK, PLANE, 0, (128, 4)),
-            ((256, 8, 6), TANK, PLANE, 1, (256, 4)),
-            ((128, 8, 6), TANK, PLANE | FLAT_TILES, 0, (0, 0)),
-            ((128, 8, 6), TANK, 0, 0, (0, 0)),              # below the size threshold
-            ((128, 13, 6), (0, 0, P, P, 0, 1), PLANE, 0, (0, 0)),   # ragged periodic y
-            ((96, 8, 6), TANK, PLANE, 0, (0, 0))]:          # rows not a multiple of 128
+            ((128, 8, 6), TANK, PLANE, 0, (128, 4, 1)),
+            ((128, 8, 6), TANK, PLANE | TWO, 0, (128, 4, 2)),
+            ((256, 8, 6), TANK, PLANE, 1, (256, 4, 2)),
+            ((128, 8, 6), TANK, PLANE | FLAT_TILES, 0, (0, 0, 2)),
+            ((128, 8, 6), TANK, 0, 0, (128, 4, 1)),            # FP64: plane tiles at any size
+            ((256, 8, 6), TANK, 0, 1, (0, 0, 2)),              # FP32: below the size threshold
+            ((128, 13, 6), (0, 0, P, P, 0, 1), PLANE, 0, (0, 0, 2)),   # ragged periodic y
+            ((96, 8, 6), TANK, PLANE, 0, (0, 0, 2))]:          # rows not a multiple of 128
         case = _case(F, shape, bc, wedge=False)
         s = Solver(t(case.rho), t(case.mask), case.bc, case.h, precision=prec, flags=flags)
         try:
-            assert s.tile_form() == want, (shape, bc, flags, prec)
+            assert s.tile_form_ex() == want, (shape, bc, flags, prec)
+            assert s.tile_form() == want[:2]
         finally:
             s.close()
