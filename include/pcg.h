@@ -117,27 +117,30 @@ enum {
                                         fractions (pcg_set_fractions; single
                                         contexts only)                       */
     PCG_FLAT_TILES = 16,             /* keep tiles of consecutive cells: by
-                                        default an FP64 grid of at least 2^25
-                                        cells whose rows are a multiple of
-                                        128 cells and whose periodic axes
-                                        hold whole tiles runs 128 x 4 plane
-                                        tiles with the operator's in-plane
-                                        neighbours staged in LDS; same
-                                        operator, another summation order   */
-    PCG_PLANE_TILES = 32,            /* use the plane tiles on any grid that
-                                        allows them, whatever its size, also
-                                        for FP32_IR (256 x 4 tiles, rows a
-                                        multiple of 256; PCG_FLAT_TILES wins
-                                        if both)                             */
-    PCG_TWO_SWEEPS = 64              /* FP64 on plane tiles: keep two sweeps
-                                        per iteration.  By default such a
-                                        solve runs one sweep per iteration
-                                        (the Chronopoulos-Gear recurrences:
-                                        the same iterates up to rounding, 33
+                                        default a grid whose rows are a
+                                        multiple of 128 cells (FP64) or 256
+                                        (FP32_IR) and whose periodic axes
+                                        hold whole tiles runs 128 x 4 (256 x
+                                        4) plane tiles with the operator's
+                                        in-plane neighbours staged in LDS;
+                                        same operator, another summation
+                                        order                               */
+    PCG_PLANE_TILES = 32,            /* plane tiles wherever they apply (the
+                                        default; kept for callers that name
+                                        the form); PCG_FLAT_TILES wins if
+                                        both                                 */
+    PCG_TWO_SWEEPS = 64              /* on plane tiles, keep two sweeps per
+                                        iteration.  By default a solve on
+                                        plane tiles (FP64, and the FP32
+                                        inner iterations of FP32_IR) runs
+                                        one sweep per iteration (the
+                                        Chronopoulos-Gear recurrences: the
+                                        same iterates up to rounding, 33
                                         instead of 50 bytes per cell and
-                                        iteration before the x updates) with
-                                        a second z vector in the workspace
-                                        (8 bytes per cell)                   */
+                                        FP64 iteration before the x
+                                        updates) with a second z vector in
+                                        the workspace (8 bytes per cell, 4
+                                        for FP32_IR)                         */
 };
 
 /*
@@ -257,7 +260,7 @@ int pcg_density_classes(const pcg_ctx_t *ctx, int32_t *nclasses);
  * Tile form of a context: *tx, *ty = columns and rows of its 2-D plane tiles
  * (128 x 4 FP64, 256 x 4 FP32), or 0, 0 when its tiles are runs of
  * consecutive cells; *sweeps = passes over the grid per iteration (1: the
- * one-sweep FP64 iteration on plane tiles, else 2).  PCG_EINVAL for null
+ * one-sweep iteration on plane tiles, else 2).  PCG_EINVAL for null
  * arguments.
  */
 int pcg_tile_form(const pcg_ctx_t *ctx, int32_t *tx, int32_t *ty, int32_t *sweeps);

@@ -126,8 +126,8 @@ std::vector<TileRule> g_rules_batch[2] = {
 // Single solves on 2-D plane tiles (their own optimum: a tile also runs the
 // plane below it in the one-sweep form, and its plane holds 512 cells).
 std::vector<TileRule> g_rules_plane[2] = {
-    { { 4194304, 16, 512 }, { 11863283, 32, 512 }, { 30821713, 64, 512 }, { 87176971, 32, 512 }, { INT64_MAX, 256, 512 } },
-    { { 10897121, 32, 768 }, { 30821713, 32, 768 }, { 87176971, 16, 512 }, { INT64_MAX, 256, 1024 } },
+    { { 4194304, 16, 768 }, { 11863283, 32, 1024 }, { 30821713, 64, 1024 }, { 87176971, 32, 512 }, { INT64_MAX, 256, 512 } },
+    { { 23726566, 32, 1024 }, { 67108864, 64, 768 }, { INT64_MAX, 256, 512 } },
 };
 
 // Table kinds: 0 single solves, 1 batches, 2 single solves on plane tiles.
@@ -207,27 +207,21 @@ struct Geometry {
     int64_t n, ntiles;
 };
 
-// Whether a grid runs 2-D plane tiles (the LDS-staged passes): rows a
+// Whether a grid runs 2-D plane tiles (the LDS-staged sweep): rows a
 // multiple of the tile width (128 cells for FP64, two per thread; 256 for
-// FP32, four), no cut-cell fractions, not switched off, a periodic y axis
-// holding whole tiles (periodic x always does), and FP64, or FP32 asked for
-// or large enough.
+// FP32, four), no cut-cell fractions, not switched off, and a periodic y
+// axis holding whole tiles (periodic x always does).
 // With the walls unknown (bc null: workspace sizing) the y condition is
 // assumed met, which sizes for the larger tile count.
-// FP64 takes them on every grid that allows them: with one sweep per
+// They are taken on every grid that allows them: with one sweep per
 // iteration they measured faster than the consecutive-cell tiles on every
-// grid tried (per iteration: 128^3 48 against 62 us, 256^3 187 against 239,
-// the 512 x 128 x 128 strut 113 against 137, 384^3 555 against 761, 512^3
-// 1167 against 1650).  The FP32 inner passes gain only on the largest
-// grids (512^3: 0.83 against 0.86 ms per inner iteration).
-constexpr int64_t kPlaneTileMinCells32 = int64_t(1) << 25;
-
+// grid tried (FP64 per iteration: 128^3 48 against 62 us, 256^3 187 against
+// 239, the 512 x 128 x 128 strut 113 against 137, 384^3 555 against 761,
+// 512^3 1167 against 1650; FP32 inner iterations: 256^3 117 against 159,
+// 512^3 643 against 864).
 bool plane_tiles_2d(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc)
 {
     if (flags & (PCG_FLAT_TILES | PCG_FRACTIONS)) return false;
-    if (!(flags & PCG_PLANE_TILES) && prec == PCG_PREC_FP32_IR &&
-        (int64_t)g.nx * g.ny * g.nz < kPlaneTileMinCells32)
-        return false;
     const int width = (prec == PCG_PREC_FP32_IR ? 4 : 2) * kBlock / kTileY;
     if (g.nx % width != 0) return false;
     if (bc && bc->kind[2] == PCG_BC_PERIODIC && g.ny > 1 && g.ny % kTileY != 0) return false;
@@ -272,12 +266,14 @@ size_t frac_bytes(const Geometry &G)
            align_up(8 * nx * ny * (nz + 1), kAlign) + align_up(8 * nx * ny * nz, kAlign);
 }
 
-// Whether the FP64 iterations of a grid run as one sweep each: on plane
-// tiles unless switched off.  Measured on the 512^3 wedge: 1.167 ms per
-// iteration against 1.559 for the two LDS-staged passes.
+// Whether the iterations of a grid (FP64, or the FP32 inner ones) run as
+// one sweep each: on plane tiles unless switched off.  Measured on the
+// 512^3 wedge against the two LDS-staged passes: FP64 1.167 against 1.559
+// ms per iteration, FP32 0.643 against 0.834.
 bool one_sweep(const Geometry &G, int prec, int flags)
 {
-    return !(flags & PCG_TWO_SWEEPS) && G.tx > 0 && prec == PCG_PREC_FP64;
+    (void)prec;
+    return !(flags & PCG_TWO_SWEEPS) && G.tx > 0;
 }
 
 size_t slot_bytes(const Geometry &G, int prec, bool frac = false, bool sweep = false)

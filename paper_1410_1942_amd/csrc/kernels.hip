@@ -1595,6 +1595,8 @@ __device__ void lds_sweep_cg(const Slot &S, const SlotState &st, int64_t lt, con
     using KP = KeyGroup<C, N>;
     using KR = typename KP::raw;
     using V = typename VecN<T, N>::type;
+    using XV = typename VecN<X, N>::type;
+    constexpr bool kXGroup = std::is_same<X, float>::value;   // d: ours, aligned
     LdsSweep<T, KE, N> &L = lds_sweep<T, KE, N>();
     const int l = (int)threadIdx.x;
     const TileCtx t = group_ctx(S, lt);
@@ -1789,8 +1791,14 @@ __device__ void lds_sweep_cg(const Slot &S, const SlotState &st, int64_t lt, con
             v0[n] = T(0);
         }
         if (XM == 3 && emit) {
+            if constexpr (kXGroup) {
+                const XV xv = __builtin_nontemporal_load(&((GLB XV *)x)[(c + qo) / N]);
 #pragma unroll
-            for (int n = 0; n < N; ++n) xo[n] = __builtin_nontemporal_load(&x[c + qo + n]);
+                for (int n = 0; n < N; ++n) xo[n] = xv[n];
+            } else {
+#pragma unroll
+                for (int n = 0; n < N; ++n) xo[n] = __builtin_nontemporal_load(&x[c + qo + n]);
+            }
             v0 = __builtin_nontemporal_load(&pv0[(c + qo) / N]);
         }
         __syncthreads();
@@ -1855,8 +1863,16 @@ __device__ void lds_sweep_cg(const Slot &S, const SlotState &st, int64_t lt, con
                 __builtin_nontemporal_store(pv_n, &pdv[(c + qo) / N]);
                 __builtin_nontemporal_store(zv_n, &zout[(c + qo) / N]);
                 if (XM == 3) {
+                    if constexpr (kXGroup) {
+                        XV xv;
 #pragma unroll
-                    for (int n = 0; n < N; ++n) __builtin_nontemporal_store(xn[n], &x[c + qo + n]);
+                        for (int n = 0; n < N; ++n) xv[n] = xn[n];
+                        __builtin_nontemporal_store(xv, &((GLB XV *)x)[(c + qo) / N]);
+                    } else {
+#pragma unroll
+                        for (int n = 0; n < N; ++n)
+                            __builtin_nontemporal_store(xn[n], &x[c + qo + n]);
+                    }
                 }
             }
         }
@@ -2367,6 +2383,7 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         const double rr = tot[0];
         st.rr_true = rr;
         st.outer += 1;
+        st.zsel = 0;   // the residual phase wrote z into its first buffer
         if (!isfinite(rr)) { finish(st, PCG_EBREAKDOWN); break; }
         st.phase = K2_IR_UPDATE;
         if (rr <= st.tol2) { st.final_upd = 1; st.status = PCG_OK; }
@@ -2404,7 +2421,37 @@ __device__ void advance(SlotState &st, int phase, const double (&tot)[3])
         st.alpha = st.rz / pap;
         st.pbuf = dir_next(st.pbuf);
         st.first = 0;
-        st.phase = K2_IR_B;
+        if (st.fused) { st.beta = 0.0; st.phase = K2_IR_F; }
+        else st.phase = K2_IR_B;
+        break;
+    }
+    case K2_IR_F: {
+        // tot = [r.z, r.r, z.A z] of the new inner residual
+        st.iter += 1;
+        st.inner_iter += 1;
+        st.rr = tot[1];
+        note_x_update(st);   // d, as x in FP64
+        st.pbuf = dir_next(st.pbuf);
+        st.zsel ^= 1;
+        if (!isfinite(tot[1])) { finish(st, PCG_EBREAKDOWN); break; }
+        const double beta = tot[0] / st.rz;
+        const double pap = tot[2] - beta * tot[0] / st.alpha;
+        st.beta = beta;
+        st.rz = tot[0];
+        st.pap = pap;
+        const bool ok = pap > 0.0 && isfinite(pap);
+        if (ok) st.alpha = tot[0] / pap;
+        const bool inner_done = st.rr <= st.inner_goal2 * st.rr0_inner ||
+                                st.inner_iter >= st.inner_maxit ||
+                                st.iter >= st.maxit;
+        if (inner_done || !ok) {
+            // refine (a vanished direction too, as after pass A); d complete first
+            st.scale = pow2_scale(sqrt(st.rr_true * st.inner_tol2));
+            st.phase = st.xpend ? K1_FLUSH_X : K1_IR_RESID;
+            st.after = K1_IR_RESID;
+        } else {
+            st.phase = K2_IR_F;
+        }
         break;
     }
     case K2_IR_B: {
@@ -2559,6 +2606,15 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
                 } else {
                     if (catch_up) lds_passB<float, float, RhoCoef<float>, 3, 4>(S, st, lt, r32, acc);
                     else lds_passB<float, float, RhoCoef<float>, 0, 4>(S, st, lt, r32, acc);
+                }
+            } else if (ph == K2_IR_F) {
+                const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
+                if (MODE == 3) {
+                    if (catch_up) lds_sweep_cg<float, float, ClsCoef<float>, 3, 4>(S, st, lt, c32, acc);
+                    else lds_sweep_cg<float, float, ClsCoef<float>, 0, 4>(S, st, lt, c32, acc);
+                } else {
+                    if (catch_up) lds_sweep_cg<float, float, RhoCoef<float>, 3, 4>(S, st, lt, r32, acc);
+                    else lds_sweep_cg<float, float, RhoCoef<float>, 0, 4>(S, st, lt, r32, acc);
                 }
             } else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);
             else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);

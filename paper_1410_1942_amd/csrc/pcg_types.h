@@ -51,6 +51,7 @@ enum Phase : int32_t {
     K2_SUB_X = 16,     // singular problem: x -= its fluid mean
     K2_CG_F = 17,      // one-sweep iteration: p = z + beta p, q = A p, x += alpha p
                        // (three at a time), z' = z - alpha D^-1 q ; r.z, r.r, z'.A z'
+    K2_IR_F = 18,      // the same for the FP32 inner solve (d in place of x; FP64 sums)
     PH_DONE = 20
 };
 
@@ -88,7 +89,7 @@ struct alignas(128) SlotState {
     int32_t warm;     // warm start requested
     int32_t singular; // no Dirichlet face: solve for the mean-free source
     int32_t xpend;    // earlier iterations whose x (FP64) or d (IR) update is pending: 0..2
-    int32_t fused;    // FP64 iterations run as one sweep (K2_CG_F)
+    int32_t fused;    // iterations run as one sweep (K2_CG_F, K2_IR_F)
     int32_t zsel;     // one-sweep iterations: z is in Slot::z2 (1) or Slot::z (0)
 };
 

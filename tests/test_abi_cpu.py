@@ -332,10 +332,10 @@ def test_built_in_tile_rules_match_the_shipped_table():
 
 
 def test_one_sweep_workspace(lib):
-    """The one-sweep iteration (the default of FP64 plane tiles) adds one FP64
-    vector, the second z, to the workspace; PCG_TWO_SWEEPS drops it, and
-    nothing changes where it does not apply (rows not a multiple of 128
-    cells, the FP32 refinement, consecutive-cell tiles)."""
+    """The one-sweep iteration (the default on plane tiles) adds one vector,
+    the second z (FP64, or FP32 for the refinement), to the workspace;
+    PCG_TWO_SWEEPS drops it, and nothing changes where it does not apply
+    (rows not a multiple of the tile width, consecutive-cell tiles)."""
     def ws(g, flags, prec=0):
         o = L.Opts()
         o.flags = flags
@@ -359,8 +359,11 @@ def test_one_sweep_workspace(lib):
     g96 = _g(96, 16, 8)
     assert ws(g96, L.PLANE_TILES) == ws(g96, L.PLANE_TILES | L.TWO_SWEEPS)
     assert ws(g, L.PLANE_TILES | L.FLAT_TILES) == ws(g, L.PLANE_TILES | L.FLAT_TILES | L.TWO_SWEEPS)
+    # the FP32 inner solve on plane tiles: a second FP32 z
     g256 = _g(256, 16, 8)
-    assert ws(g256, L.PLANE_TILES, 1) == ws(g256, L.PLANE_TILES | L.TWO_SWEEPS, 1)
+    d32 = ws(g256, L.PLANE_TILES, 1) - ws(g256, L.PLANE_TILES | L.TWO_SWEEPS, 1)
+    assert 4 * 256 * 16 * 8 - 4 * 256 <= d32 <= 4 * 256 * 16 * 8
+    assert ws(g256, 0, 1) == ws(g256, L.PLANE_TILES, 1)   # FP32: plane tiles at any size
     # a 512^3 FP64 grid takes plane tiles, hence the second z, by default
     big = _g(512, 512, 512)
     assert ws(big, 0) - ws(big, L.TWO_SWEEPS) == 8 * 512 ** 3

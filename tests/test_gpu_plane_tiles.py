@@ -1,13 +1,12 @@
 """The 2-D plane-tile form (128 x 4 FP64 or 256 x 4 FP32 tiles, in-plane
 neighbours staged in LDS) of the two passes, through the C ABI, against the
-oracle.  FP64 solves on plane tiles run one sweep per iteration by default;
-the FP64 cases here ask for the two passes (PCG_TWO_SWEEPS), whose one-sweep
+oracle.  Solves on plane tiles run one sweep per iteration by default; the
+cases here ask for the two passes (PCG_TWO_SWEEPS), whose one-sweep
 counterpart has a test file of its own.
 
-FP64 grids whose rows are a multiple of 128 cells, and FP32 grids of at
-least 2^25 cells whose rows are a multiple of 256, take this form by
-default; PCG_PLANE_TILES asks for it on smaller FP32 grids (as here) and
-PCG_FLAT_TILES keeps the consecutive-cell tiles.  The cases cover ragged
+Grids whose rows are a multiple of 128 cells (FP64) or 256 (the FP32 inner
+solve) take this form by default; PCG_FLAT_TILES keeps the consecutive-cell
+tiles.  The cases cover ragged
 tile rows (ny not a multiple of 4), a single row, every wall kind on every
 side, periodic axes (and the fall-back to consecutive-cell tiles when a
 periodic y axis does not hold whole tiles), hulls, both coefficient sources,
@@ -108,7 +107,8 @@ CASES_IR = [
 
 
 @pytest.mark.parametrize("shape,bc,wedge", CASES_IR, ids=lambda v: str(v))
-@pytest.mark.parametrize("flags", [PLANE, PLANE | NO_CLASSES], ids=["classes", "density"])
+@pytest.mark.parametrize("flags", [PLANE | TWO, PLANE | TWO | NO_CLASSES],
+                         ids=["classes", "density"])
 def test_plane_tile_parity_ir(orc, F, torch_dev, shape, bc, wedge, flags):
     """FP32 stencil with FP64 refinement on 256 x 4 plane tiles (four cells a
     thread): the oracle's bar, and the consecutive-cell tiles' answer."""
@@ -222,10 +222,11 @@ def test_tile_form_reported(F, torch_dev):
     for shape, bc, flags, prec, want in [
             ((128, 8, 6), TANK, PLANE, 0, (128, 4, 1)),
             ((128, 8, 6), TANK, PLANE | TWO, 0, (128, 4, 2)),
-            ((256, 8, 6), TANK, PLANE, 1, (256, 4, 2)),
+            ((256, 8, 6), TANK, PLANE, 1, (256, 4, 1)),
+            ((256, 8, 6), TANK, PLANE | TWO, 1, (256, 4, 2)),
             ((128, 8, 6), TANK, PLANE | FLAT_TILES, 0, (0, 0, 2)),
             ((128, 8, 6), TANK, 0, 0, (128, 4, 1)),            # FP64: plane tiles at any size
-            ((256, 8, 6), TANK, 0, 1, (0, 0, 2)),              # FP32: below the size threshold
+            ((256, 8, 6), TANK, 0, 1, (256, 4, 1)),            # FP32: plane tiles at any size
             ((128, 13, 6), (0, 0, P, P, 0, 1), PLANE, 0, (0, 0, 2)),   # ragged periodic y
             ((96, 8, 6), TANK, PLANE, 0, (0, 0, 2))]:          # rows not a multiple of 128
         case = _case(F, shape, bc, wedge=False)
