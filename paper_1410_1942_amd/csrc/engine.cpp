@@ -575,6 +575,8 @@ struct Engine {
     bool is_batch = false;  // created by pcg_batch_create (batch tile table)
     int modes = 0;          // bit m: a running slot uses coefficient mode m (slot_mode)
     int graph_modes = -1;   // modes the captured graph was built for
+    bool k2only = false;    // second-half launches only (every solve in one sweep)
+    int graph_k2only = -1;  // the same for the captured graph
     int fail_after = 0;     // test hook: the step call that reports a failure
     HostMirror *mirror = nullptr;  // caller-owned host mirrors: no pinned memory,
                                    // no capture stream, launches without graphs
@@ -977,6 +979,7 @@ struct Engine {
         int64_t tb = 0;
         int ns = 0;
         int m = 0;
+        bool all_fused = true;
         for (int id = 0; id < max_slots; ++id) {
             SlotHost &S = slots[id];
             if (!S.used || !S.running) continue;
@@ -1013,10 +1016,15 @@ struct Engine {
             d.tab32 = S.tab32;
             m |= 1 << slot_mode(S);
             tb += S.geo.ntiles;
+            all_fused = all_fused && S.z2 != nullptr;
         }
         h_hdr->total_tiles = tb;
         h_hdr->nslots = ns;
         h_hdr->chunked = ns > 1 ? 1 : 0;
+        // every solve in one sweep per iteration: second-half launches only
+        // (timed runs keep both positions, so each is timed on its own)
+        k2only = ns > 0 && all_fused && !timing;
+        h_hdr->k2only = k2only ? 1 : 0;
         total_tiles = tb;
         nrunning = ns;
         modes = m;
@@ -1052,7 +1060,8 @@ struct Engine {
     int capture()
     {
         const int g = choose_grid();
-        if (exec && g == grid && modes == graph_modes) return PCG_OK;
+        if (exec && g == grid && modes == graph_modes && (int)k2only == graph_k2only)
+            return PCG_OK;
         if (exec) { (void)hipGraphExecDestroy(exec); exec = nullptr; }
         if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
         grid = g;
@@ -1067,6 +1076,7 @@ struct Engine {
         graph = gph;
         HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         graph_modes = modes;
+        graph_k2only = k2only;
         return PCG_OK;
     }
 
@@ -1082,7 +1092,9 @@ struct Engine {
         bool first = true;
         for (int m = 0; m < kModes && e == hipSuccess; ++m) {
             if (!(modes & (1 << m))) continue;
-            e = launch_iter(prec, (w == 1 && first) ? 3 : w, m, grid, d_hdr, d_slots, s);
+            // second-half launches only: both positions launch kernel 2
+            const int which = k2only ? 2 : ((w == 1 && first) ? 3 : w);
+            e = launch_iter(prec, which, m, grid, d_hdr, d_slots, s);
             first = false;
         }
         return e;
@@ -1594,6 +1606,7 @@ int pcg_set_timing(pcg_ctx_t *c, int32_t on)
 {
     if (!c) return PCG_EINVAL;
     c->eng.timing = on != 0;
+    c->eng.table_dirty = true;   // the launch form depends on it
     return PCG_OK;
 }
 

@@ -2542,6 +2542,14 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
         else run_body<FAMILY, 1, MODE>(ph, S, st, lt, tab64, tab32, acc);
         return;
     }
+    if constexpr (WHICH == 2 && MODE >= 3) {
+        // second-half launches alone: the first-half actions too
+        if (k0_phase(ph)) { run_body<FAMILY, 0, 0>(ph, S, st, lt, tab64, tab32, acc); return; }
+        if (ph == K1_CG_A || ph == K1_IR_A) {
+            run_body<FAMILY, 1, MODE>(ph, S, st, lt, tab64, tab32, acc);
+            return;
+        }
+    }
     const RhoCoef<double> r64{ gp(S.rho64) };
     const ClsCoef<double> c64{ gp(S.cls), tab64 };
     if (WHICH == 0) {
@@ -2679,12 +2687,15 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
 }
 
 template <int WHICH, int MODE>
-__device__ __forceinline__ bool serves(const Slot &S, int ph)
+__device__ __forceinline__ bool serves(const Slot &S, int ph, bool k2only)
 {
     if (WHICH == 0) return k0_phase(ph);
     if (WHICH == 3 && k0_phase(ph)) return true;
     if (slot_mode(S) != MODE) return false;
     if (WHICH == 1 || WHICH == 3) return ph == K1_CG_A || ph == K1_IR_A;
+    // second-half launches alone (one-sweep solves on plane tiles): also
+    // the first-half actions of this mode's slots
+    if (MODE >= 3 && k2only && (k0_phase(ph) || ph == K1_CG_A || ph == K1_IR_A)) return true;
     return ph >= 11 && ph <= 19;
 }
 
@@ -2733,6 +2744,7 @@ k_iter(const BatchHeader *__restrict__ hdr, const Slot *__restrict__ slots)
     __shared__ int s_last;
     const int64_t T = hdr->total_tiles;
     const int ns = hdr->nslots;
+    const bool k2only = hdr->k2only != 0;
     const int G = (int)gridDim.x;
     const int g = xcd_major((int)blockIdx.x, G);
     // strided: tiles g, g + G, ...; chunked: tiles [g T / G, (g + 1) T / G)
@@ -2754,10 +2766,10 @@ k_iter(const BatchHeader *__restrict__ hdr, const Slot *__restrict__ slots)
             cur_end = S.tile_begin + S.ntiles;
             run = 0;
             cur_ph = S.st->phase;
-            cur_served = serves<WHICH, MODE>(S, cur_ph);
+            cur_served = serves<WHICH, MODE>(S, cur_ph, k2only);
             if (cur_served && S.cls) {   // class table of this slot into LDS
                 const bool need64 = FAMILY == PCG_PREC_FP64 || WHICH == 0 ||
-                                    (WHICH == 3 && k0_phase(cur_ph));
+                                    ((WHICH == 3 || WHICH == 2) && k0_phase(cur_ph));
                 const bool need32 = FAMILY == PCG_PREC_FP32_IR;
                 for (int i = threadIdx.x; i < kClasses * kClasses; i += kBlock) {
                     if (need64) s_tab64[i] = gp(S.tab64)[i];

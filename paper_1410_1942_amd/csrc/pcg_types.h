@@ -141,6 +141,11 @@ struct BatchHeader {
     // workgroup takes a contiguous range of tiles, so it meets few slots
     // per launch (several solves)
     int32_t chunked;
+    // 1: every resident solve runs one sweep per iteration and only
+    // second-half launches are issued; they also serve the rare first-half
+    // actions (set-up, the first pass A, residuals, flushes)
+    int32_t k2only;
+    int32_t pad_;
 };
 
 }  // namespace pcgmi
