@@ -1,9 +1,10 @@
 """The allocation-free entry point (pcg_solve_static) against the existing
-one (pcg_setup + pcg_solve on a caller workspace), through the C ABI: two
-calls in a row on the library's fixed device array, the second on a smaller
-grid, each equal to the workspace path's result (the same kernels in the
-same order, so bit for bit) and within tolerance by the oracle's residual;
-and a grid too large for the array is refused."""
+one (pcg_setup + pcg_solve on a caller workspace), through the C ABI: calls
+in a row on the library's fixed device array, each on a smaller grid than
+the one before (consecutive-cell tiles, then plane tiles with one sweep per
+iteration), each equal to the workspace path's result (the same kernels in
+the same order, so bit for bit) and within tolerance by the oracle's
+residual; and a grid too large for the array is refused."""
 import sys
 
 import numpy as np
@@ -27,9 +28,14 @@ def test_static_entry_point_matches_workspace_path(orc, F, precision):
     from paper_1410_1942_amd.solver import Solver, solve_static
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
-    # the second call is smaller; the first leaves its contents in the array
+    # each call smaller than the one before; each leaves its contents in the
+    # array; the last two take plane tiles (one sweep per iteration, the
+    # second z inside the array)
+    wide = 128 if precision == 0 else 256
     cases = [F.make_two_phase(96, 40, 33, surface_seed=51, velocity_seed=52, wedge=F.Wedge()),
-             F.make_two_phase(37, 29, 23, surface_seed=53, velocity_seed=54, wedge=F.Wedge())]
+             F.make_two_phase(37, 29, 23, surface_seed=53, velocity_seed=54, wedge=F.Wedge()),
+             F.make_two_phase(wide, 20, 17, surface_seed=55, velocity_seed=56, wedge=F.Wedge()),
+             F.make_two_phase(wide, 8, 9, surface_seed=57, velocity_seed=58, wedge=F.Wedge())]
     for case in cases:
         _say(f"case static {case.shape} prec={precision}")
         rho, mask, rhs = (_to(torch, dev, a) for a in (case.rho, case.mask, case.rhs))
