@@ -53,24 +53,42 @@ def kernel_stats(path: str) -> str:
 
 
 def _two_forms(values):
-    """Count and mean of the launches below and above the midpoint of the
-    range: the two forms of pass B (without and with the x update); a
-    kernel with one form splits into two near-equal halves."""
-    lo, hi = min(values), max(values)
-    mid = 0.5 * (lo + hi)
-    a = [v for v in values if v <= mid]
-    b = [v for v in values if v > mid] or a
+    """Count and mean of the two groups that a cut of the sorted values
+    leaves with the least summed squared deviation (two-means in one
+    dimension): the two forms of the iteration (without and with the x
+    update), which a handful of much longer set-up launches cannot pull
+    apart as they would a cut at the midpoint of the range."""
+    v = sorted(values)
+    n = len(v)
+    if n < 2:
+        return (n, statistics.mean(v)), (n, statistics.mean(v))
+    pre = [0.0]
+    pre2 = [0.0]
+    for x in v:
+        pre.append(pre[-1] + x)
+        pre2.append(pre2[-1] + x * x)
+
+    def sse(a, b):
+        m = b - a
+        s = pre[b] - pre[a]
+        return pre2[b] - pre2[a] - s * s / m
+
+    cut = min(range(1, n), key=lambda c: sse(0, c) + sse(c, n))
+    a, b = v[:cut], v[cut:]
     return (len(a), statistics.mean(a)), (len(b), statistics.mean(b))
 
 
 def _large(values, lo=0.5, hi=3.0):
-    """The values within [lo, hi] times the median: the launches of the
-    problem a run launches most (its median), every form of a kernel whose
-    launches alternate (pass B with and without the x update, within a
-    factor of about 2.3 of each other); not the empty launches at the end
-    of a captured chunk, those of much smaller problems, nor the rare
-    set-up and residual launches of the first-half kernel."""
-    med = statistics.median(values)
+    """The values within [lo, hi] times the median of the non-empty ones
+    (above a hundredth of the largest): the launches of the problem a run
+    launches most, every form of a kernel whose launches alternate (the
+    iteration with and without the x update, within a factor of about 2.3
+    of each other); not the empty launches at the end of a captured chunk,
+    however many, those of much smaller problems, nor the rare set-up and
+    residual launches."""
+    top = max(values)
+    busy = [v for v in values if v > 0.01 * top] or values
+    med = statistics.median(busy)
     return [v for v in values if lo * med <= v <= hi * med]
 
 
@@ -96,9 +114,9 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
     lines = [f"# FETCH_SIZE scale {sf:.4f}, WRITE_SIZE scale {sw:.4f} "
              f"(copy kernel: {copy_bytes} B read and written per launch)",
              f"# per launch, mean over the launches within half to three times the "
-             f"median (empty launches at the end of a captured chunk and the rare set-up "
-             f"launches excluded; both forms of pass B, with and without the x update, "
-             f"kept); cells = {cells}"]
+             f"median of the non-empty ones (empty launches at the end of a captured "
+             f"chunk, however many, and the rare set-up launches excluded; both forms of "
+             f"the iteration, with and without the x update, kept); cells = {cells}"]
     if sha:
         lines.append(f"kernel_source_sha = {sha}")
     lines.append(f"{'kernel':58s} {'n':>4s} {'fetch_B':>14s} {'write_B':>14s} "

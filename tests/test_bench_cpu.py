@@ -28,3 +28,19 @@ def test_committed_traffic_summary_parses():
     # the kernel-trace summary gives the command it came from
     stats = open(os.path.join(ROOT, "profiles", "kernel_stats_wedge512.txt")).read()
     assert "rocprofv3 --kernel-trace --stats" in stats and "k_iter<0, 2, 3>" in stats
+
+
+def test_launch_filters():
+    """The summaries' launch filters: the median is taken over the non-empty
+    launches even when empty ones (the end of a captured chunk) are the
+    majority, and the two forms of the iteration are told apart although a
+    few much longer set-up launches stretch the range."""
+    sys.path.insert(0, ROOT)
+    from paper_1410_1942_amd import profiling as pr
+    vals = [0.0] * 70 + [1.0, 1.0, 2.0] * 20
+    big = pr._large(vals)
+    assert len(big) == 60 and min(big) == 1.0
+    forms = [1.0] * 200 + [1.46] * 100 + [2.65] * 3
+    (na, ma), (nb, mb) = pr._two_forms(forms)
+    assert na == 200 and ma == 1.0
+    assert nb == 103 and 1.46 < mb < 1.5
