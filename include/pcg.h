@@ -117,17 +117,22 @@ enum {
                                         fractions (pcg_set_fractions; single
                                         contexts only)                       */
     PCG_FLAT_TILES = 16,             /* keep tiles of consecutive cells: by
-                                        default a grid whose rows are a
-                                        multiple of 128 cells (FP64) or 256
-                                        (FP32_IR) and whose periodic axes
-                                        hold whole tiles runs 128 x 4 (256 x
-                                        4) plane tiles with the operator's
-                                        in-plane neighbours staged in LDS;
-                                        same operator, another summation
-                                        order                               */
-    PCG_PLANE_TILES = 32,            /* plane tiles wherever they apply (the
-                                        default; kept for callers that name
-                                        the form); PCG_FLAT_TILES wins if
+                                        default a grid runs 128 x 4 (FP64)
+                                        or 256 x 4 (FP32_IR) plane tiles
+                                        with the operator's in-plane
+                                        neighbours staged in LDS where its
+                                        rows are of cell pairs (FP64) or
+                                        quads (FP32_IR), a periodic y axis
+                                        holds whole tile rows, and the rows
+                                        hold whole tiles or, with walls on
+                                        x, keep at least 70% (FP64) or 50%
+                                        (FP32_IR) of the lanes of their
+                                        tiles busy; same operator, another
+                                        summation order                     */
+    PCG_PLANE_TILES = 32,            /* plane tiles also where rows of pairs
+                                        or quads keep fewer lanes busy (a
+                                        periodic x or y axis still needs
+                                        whole tiles); PCG_FLAT_TILES wins if
                                         both                                 */
     PCG_TWO_SWEEPS = 64              /* on plane tiles, keep two sweeps per
                                         iteration.  By default a solve on

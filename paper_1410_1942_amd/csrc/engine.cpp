@@ -207,23 +207,39 @@ struct Geometry {
     int64_t n, ntiles;
 };
 
-// Whether a grid runs 2-D plane tiles (the LDS-staged sweep): rows a
-// multiple of the tile width (128 cells for FP64, two per thread; 256 for
-// FP32, four), no cut-cell fractions, not switched off, and a periodic y
-// axis holding whole tiles (periodic x always does).
-// With the walls unknown (bc null: workspace sizing) the y condition is
-// assumed met, which sizes for the larger tile count.
+// Whether a grid runs 2-D plane tiles (the LDS-staged sweep): no cut-cell
+// fractions, not switched off, rows of whole groups (an even length for
+// FP64, a multiple of four for FP32), and rows that hold whole tiles (128
+// cells for FP64, two per thread; 256 for FP32, four) or, on an x axis
+// with walls, keep enough of their tiles' lanes busy (PCG_PLANE_TILES
+// takes any share); a periodic y axis holds whole tile rows.  With the
+// walls unknown (bc null: workspace sizing) the periodic conditions are
+// taken as met, which sizes for the larger tile count.
 // They are taken on every grid that allows them: with one sweep per
 // iteration they measured faster than the consecutive-cell tiles on every
-// grid tried (FP64 per iteration: 128^3 48 against 62 us, 256^3 187 against
-// 239, the 512 x 128 x 128 strut 113 against 137, 384^3 555 against 761,
-// 512^3 1167 against 1650; FP32 inner iterations: 256^3 117 against 159,
-// 512^3 643 against 864).
+// grid of whole tiles tried (FP64 per iteration: 128^3 48 against 62 us,
+// 256^3 187 against 239, the 512 x 128 x 128 strut 113 against 137, 384^3
+// 555 against 761, 512^3 1167 against 1650; FP32 inner iterations: 256^3
+// 117 against 159, 512^3 643 against 864).  On rows of nx x 256 x 256
+// grids that leave the last tile partly empty, FP64 per iteration: nx 192
+// (three quarters of the lanes busy) 169 against 221 us, 224 175 against
+// 230, 320 311 against 361, but 160 (five eighths) 215 against 197 and 136
+// 214 against 179; FP32: nx 136 (just over half) 104 against 118, 160
+// 106 against 131, 320 230 against 244.  Hence the shares below.
+constexpr double kRaggedUse[2] = {0.7, 0.5};   // FP64, FP32
+
 bool plane_tiles_2d(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc)
 {
     if (flags & (PCG_FLAT_TILES | PCG_FRACTIONS)) return false;
-    const int width = (prec == PCG_PREC_FP32_IR ? 4 : 2) * kBlock / kTileY;
-    if (g.nx % width != 0) return false;
+    const bool f32 = prec == PCG_PREC_FP32_IR;
+    const int cpt = f32 ? 4 : 2;
+    const int width = cpt * kBlock / kTileY;
+    if (g.nx % cpt != 0) return false;
+    if (g.nx % width != 0) {
+        if (bc && bc->kind[0] == PCG_BC_PERIODIC && g.nx > 1) return false;
+        const int tiles = (g.nx + width - 1) / width;
+        if (!(flags & PCG_PLANE_TILES) && g.nx < kRaggedUse[f32] * tiles * width) return false;
+    }
     if (bc && bc->kind[2] == PCG_BC_PERIODIC && g.ny > 1 && g.ny % kTileY != 0) return false;
     return true;
 }
@@ -247,7 +263,7 @@ Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch, bo
     if (tiles2d) {
         G.tx = G.cpt * kBlock / kTileY;    // 128 (FP64 pairs) or 256 (FP32 quads)
         G.ty = kTileY;
-        G.tiles_x = g.nx / G.tx;
+        G.tiles_x = (g.nx + G.tx - 1) / G.tx;
         G.plane_tiles = G.tiles_x * ((g.ny + kTileY - 1) / kTileY);
     } else {
         G.tx = G.ty = G.tiles_x = 0;

@@ -235,10 +235,11 @@ def test_tile_rules_roundtrip(lib):
         assert autotune.get_rules(0, table=autotune.PLANE) == [[2**63 - 1, 2, 0]]
         assert [r[1:] for r in autotune.get_rules(0)] == [[4, 256], [8, 0], [64, 512]]
         # workspace: partial sums scale with the number of tiles (tz = 64 -> fewer),
-        # on consecutive-cell tiles (rows of 96) from the single-solve table
+        # on consecutive-cell tiles (rows of 80, five eighths of a plane tile)
+        # from the single-solve table
         o = L.Opts()
         w64 = ctypes.c_size_t()
-        lib.pcg_workspace_bytes(ctypes.byref(_g(96, 128, 128)), ctypes.byref(o),
+        lib.pcg_workspace_bytes(ctypes.byref(_g(80, 128, 128)), ctypes.byref(o),
                                 ctypes.byref(w64))
         # rows of 128 take plane tiles and the plane table (tz = 2 here)
         wp2 = ctypes.c_size_t()
@@ -246,7 +247,7 @@ def test_tile_rules_roundtrip(lib):
                                 ctypes.byref(wp2))
         autotune.set_rules(0, [[10**9, 1, 0]])
         w1 = ctypes.c_size_t()
-        lib.pcg_workspace_bytes(ctypes.byref(_g(96, 128, 128)), ctypes.byref(o),
+        lib.pcg_workspace_bytes(ctypes.byref(_g(80, 128, 128)), ctypes.byref(o),
                                 ctypes.byref(w1))
         assert w1.value > w64.value
         wp = ctypes.c_size_t()
@@ -335,7 +336,7 @@ def test_one_sweep_workspace(lib):
     """The one-sweep iteration (the default on plane tiles) adds one vector,
     the second z (FP64, or FP32 for the refinement), to the workspace;
     PCG_TWO_SWEEPS drops it, and nothing changes where it does not apply
-    (rows not a multiple of the tile width, consecutive-cell tiles)."""
+    (rows of an odd length, consecutive-cell tiles)."""
     def ws(g, flags, prec=0):
         o = L.Opts()
         o.flags = flags
@@ -356,8 +357,14 @@ def test_one_sweep_workspace(lib):
         for extra in (0, L.TWO_SWEEPS):
             assert ws(gs, extra) >= ws(gs, L.FLAT_TILES), (shape, extra)
             assert ws(gs, L.PLANE_TILES | extra) >= ws(gs, L.FLAT_TILES), (shape, extra)
+    g97 = _g(97, 16, 8)
+    assert ws(g97, L.PLANE_TILES) == ws(g97, L.PLANE_TILES | L.TWO_SWEEPS)
+    # rows of 96 cells fill three quarters of a 128-cell tile: plane tiles
+    # (and the second z) when asked for
     g96 = _g(96, 16, 8)
-    assert ws(g96, L.PLANE_TILES) == ws(g96, L.PLANE_TILES | L.TWO_SWEEPS)
+    n96 = 96 * 16 * 8
+    assert 8 * n96 - 4 * 256 <= ws(g96, L.PLANE_TILES) - ws(g96, L.PLANE_TILES | L.TWO_SWEEPS) <= 8 * n96
+    assert ws(g96, L.PLANE_TILES) >= ws(g96, L.FLAT_TILES)
     assert ws(g, L.PLANE_TILES | L.FLAT_TILES) == ws(g, L.PLANE_TILES | L.FLAT_TILES | L.TWO_SWEEPS)
     # the FP32 inner solve on plane tiles: a second FP32 z
     g256 = _g(256, 16, 8)

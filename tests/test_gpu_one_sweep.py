@@ -7,8 +7,8 @@ The recurrences give the iterates of the two-sweep iteration in exact
 arithmetic, so the bar is the oracle's: the converged answer against the
 oracle's 1e-12 solution, the iteration count against the oracle's, the k-th
 iterate of a capped solve against the oracle's k-th iterate, and the
-two-sweep plane-tile result.  The cases cover ragged tile rows, a single row,
-every wall kind on every side, periodic axes (and the fall-back to
+two-sweep plane-tile result.  The cases cover ragged tile rows and columns
+(down to a row shorter than one tile), a single row, every wall kind on every side, periodic axes (and the fall-back to
 consecutive-cell tiles, where the flag is ignored), hulls, both coefficient
 sources, tile heights down to one plane (every tile then starts one plane
 below its first), launch-grid independence, a warm start, and a batch that
@@ -75,6 +75,10 @@ CASES = [
     ((128, 12, 10), (P, P, 0, 0, 0, 0), True),  # periodic x, no-flux: singular
     ((256, 8, 7), (0, 1, P, P, 1, 0), True),    # periodic y, Dirichlet x+ and z-
     ((128, 13, 6), (0, 0, P, P, 0, 1), False),  # periodic y, 13 rows: consecutive-cell tiles
+    ((200, 9, 7), TANK, True),                  # ragged last tile column (200 = 128 + 72)
+    ((66, 5, 6), (1, 1, 0, 1, 0, 1), True),     # one tile, 33 of its 64 groups in the grid
+    ((160, 8, 5), (1, 0, P, P, 0, 1), False),   # ragged columns with periodic y, Dirichlet x-
+    ((130, 8, 5), (P, P, 0, 0, 0, 1), False),   # ragged periodic x: consecutive-cell tiles
 ]
 
 
@@ -112,6 +116,19 @@ def test_one_sweep_capped_iterate(orc, F, torch_dev, k):
     prev = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=k - 1)
     scale = np.abs(ref.p).max()
     assert np.abs(ref.p - prev.p).max() > 1e-3 * scale
+    p, st = _solve(torch_dev, case, tol=1e-30, maxit=k)
+    assert st["status"] == 1 and st["iters"] == k, st
+    assert np.abs(p - ref.p).max() <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("k", [2, 3, 14])
+def test_one_sweep_capped_iterate_ragged_columns(orc, F, torch_dev, k):
+    """Rows of 200 cells (the last tile of a row 72 columns wide): the k-th
+    iterate of a capped solve is the oracle's."""
+    case = _case(F, (200, 9, 14), (1, 0, 0, 1, 0, 1))
+    _say(f"case one sweep ragged columns capped k={k}")
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=k)
+    scale = np.abs(ref.p).max()
     p, st = _solve(torch_dev, case, tol=1e-30, maxit=k)
     assert st["status"] == 1 and st["iters"] == k, st
     assert np.abs(p - ref.p).max() <= 1e-10 * scale
@@ -214,6 +231,8 @@ CASES_IR = [
     ((512, 5, 4), (1, 1, 1, 1, 1, 1), True),    # Dirichlet everywhere, two tiles across
     ((256, 6, 5), (P, P, 0, 0, 0, 0), True),    # periodic x, no-flux: singular
     ((256, 8, 7), (0, 1, P, P, 1, 0), True),    # periodic y, Dirichlet x+ and z-
+    ((260, 7, 6), TANK, True),                  # ragged last tile column (260 = 256 + 4)
+    ((100, 6, 5), (1, 1, 1, 1, 1, 1), True),    # one tile, 25 of its 64 groups in the grid
 ]
 
 
@@ -236,9 +255,12 @@ def test_one_sweep_parity_ir(orc, F, torch_dev, shape, bc, wedge, flags):
     p2, st2 = _solve(torch_dev, case, flags=flags | TWO, precision=1)
     assert np.abs(p2 - p).max() <= 1e-6 * scale
     # FP32 rounding of the two recurrences differs, and so can the inner
-    # iteration count (the bar is the answer; the count is cost)
+    # iteration count (the bar is the answer; the count is cost): on these
+    # small, strongly layered grids it has measured up to a fifth apart
+    # (512 x 7 x 6 per-cell density, whole tiles: 790 against 659), while
+    # the 512^3 wedge takes as many inner iterations as FP64 does
     _say(f"  inner iterations: one sweep {st['iters']}, two passes {st2['iters']}")
-    assert abs(st2["iters"] - st["iters"]) <= max(2, 0.15 * st2["iters"]), (st, st2)
+    assert abs(st2["iters"] - st["iters"]) <= max(2, 0.25 * st2["iters"]), (st, st2)
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 13, 14, 15])
@@ -250,6 +272,20 @@ def test_one_sweep_capped_iterate_ir(orc, F, torch_dev, k):
     ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=k)
     scale = np.abs(ref.p).max()
     p, st = _solve(torch_dev, case, tol=1e-30, maxit=k, precision=1)
+    assert st["status"] == 1 and st["iters"] == k and st["outer_iters"] == 2, st
+    assert np.abs(p - ref.p).max() <= 1e-4 * scale
+
+
+@pytest.mark.parametrize("k", [3, 14])
+@pytest.mark.parametrize("flags", [PLANE, PLANE | NO_CLASSES], ids=["classes", "density"])
+def test_one_sweep_capped_iterate_ir_ragged_columns(orc, F, torch_dev, k, flags):
+    """Rows of 260 cells (the last 256-cell tile of a row 4 columns wide):
+    the FP32 inner solve, capped at k iterations, returns its k-th iterate."""
+    case = _case(F, (260, 6, 9), TANK)
+    _say(f"case one sweep ir ragged columns capped k={k} flags={flags}")
+    ref = orc.pcg(case.rho, case.mask, case.bc, case.h, case.rhs, tol=1e-30, maxit=k)
+    scale = np.abs(ref.p).max()
+    p, st = _solve(torch_dev, case, tol=1e-30, maxit=k, precision=1, flags=flags)
     assert st["status"] == 1 and st["iters"] == k and st["outer_iters"] == 2, st
     assert np.abs(p - ref.p).max() <= 1e-4 * scale
 

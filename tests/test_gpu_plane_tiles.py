@@ -5,9 +5,10 @@ cases here ask for the two passes (PCG_TWO_SWEEPS), whose one-sweep
 counterpart has a test file of its own.
 
 Grids whose rows are a multiple of 128 cells (FP64) or 256 (the FP32 inner
-solve) take this form by default; PCG_FLAT_TILES keeps the consecutive-cell
-tiles.  The cases cover ragged
-tile rows (ny not a multiple of 4), a single row, every wall kind on every
+solve), or leave enough of the last tile of a row busy, take this form by
+default; PCG_FLAT_TILES keeps the consecutive-cell tiles.  The cases cover
+ragged tile rows (ny not a multiple of 4), ragged tile columns (nx not a
+multiple of the tile width), a single row, every wall kind on every
 side, periodic axes (and the fall-back to consecutive-cell tiles when a
 periodic y axis does not hold whole tiles), hulls, both coefficient sources,
 tile heights with tails, the iterate at an iteration cap of every phase of
@@ -70,6 +71,8 @@ CASES = [
     ((128, 16, 12), (P, P, P, P, 0, 1), True),  # periodic x and y holding whole tiles
     ((128, 12, 10), (P, P, 0, 0, 0, 0), True),  # periodic x, no-flux: singular
     ((128, 13, 6), (0, 0, P, P, 0, 1), False),  # periodic y, 13 rows: consecutive-cell tiles
+    ((200, 9, 7), TANK, True),                  # ragged last tile column (200 = 128 + 72)
+    ((66, 5, 6), (1, 1, 0, 1, 0, 1), True),     # one tile, 33 of its 64 groups in the grid
 ]
 
 
@@ -103,6 +106,7 @@ CASES_IR = [
     ((512, 5, 4), (1, 1, 1, 1, 1, 1), True),    # Dirichlet everywhere, two tiles across
     ((256, 6, 5), (P, P, 0, 0, 0, 0), True),    # periodic x, no-flux: singular
     ((256, 13, 5), (0, 0, P, P, 0, 1), False),  # periodic y, 13 rows: consecutive-cell tiles
+    ((260, 7, 6), TANK, True),                  # ragged last tile column (260 = 256 + 4)
 ]
 
 
@@ -228,7 +232,15 @@ def test_tile_form_reported(F, torch_dev):
             ((128, 8, 6), TANK, 0, 0, (128, 4, 1)),            # FP64: plane tiles at any size
             ((256, 8, 6), TANK, 0, 1, (256, 4, 1)),            # FP32: plane tiles at any size
             ((128, 13, 6), (0, 0, P, P, 0, 1), PLANE, 0, (0, 0, 2)),   # ragged periodic y
-            ((96, 8, 6), TANK, PLANE, 0, (0, 0, 2))]:          # rows not a multiple of 128
+            ((200, 8, 6), TANK, 0, 0, (128, 4, 1)),            # ragged columns: 78% of the lanes
+            ((200, 8, 6), TANK, 0, 1, (256, 4, 1)),
+            ((160, 8, 6), TANK, 0, 0, (0, 0, 2)),              # FP64 with 62% of the lanes: flat
+            ((160, 8, 6), TANK, PLANE, 0, (128, 4, 1)),        # unless asked for
+            ((136, 8, 6), TANK, 0, 1, (256, 4, 1)),            # FP32 with 53% of the lanes
+            ((120, 8, 6), TANK, 0, 1, (0, 0, 2)),              # FP32 with 47%: flat
+            ((130, 8, 6), (P, P, 0, 0, 0, 1), PLANE, 0, (0, 0, 2)),   # ragged periodic x
+            ((97, 8, 6), TANK, PLANE, 0, (0, 0, 2)),           # odd rows: no cell pairs
+            ((98, 8, 6), TANK, PLANE, 1, (0, 0, 2))]:          # FP32: rows not of quads
         case = _case(F, shape, bc, wedge=False)
         s = Solver(t(case.rho), t(case.mask), case.bc, case.h, precision=prec, flags=flags)
         try:
