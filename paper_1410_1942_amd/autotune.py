@@ -13,7 +13,7 @@ fastest per iteration.  The result is a JSON table keyed by GPU architecture:
 
 Single-solve rules are tuned on one solve at a time, on tiles of consecutive
 cells ("fp64", "fp32_ir") and on 2-D plane tiles ("*_plane", grids whose
-rows hold whole tiles; FP64 plane tiles run one sweep per iteration); batch
+rows take them; plane tiles run one sweep per iteration); batch
 rules on a resident batch of several solves of the class size (their tiles
 share every launch, so longer tiles usually win).
 
@@ -43,12 +43,20 @@ PREC_KEYS = {L.PREC_FP64: "fp64", L.PREC_FP32_IR: "fp32_ir"}
 
 CLASSES = [16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512]
 BATCH_CLASSES = [16, 24, 32, 48, 64, 96, 128, 192]
-# plane-tile classes as grid shapes (nx, ny, nz): rows of whole tiles, and
-# for FP64 a 256 x 256 x 128 grid, whose tile count per plane and height
-# are those of the 512 x 128 x 128 strut tank
-PLANE_CLASSES = {L.PREC_FP64: [(128, 128, 128), (256, 256, 128), (256, 256, 256),
-                               (384, 384, 384), (512, 512, 512)],
-                 L.PREC_FP32_IR: [(256, 256, 256), (512, 256, 256), (512, 512, 512)]}
+# plane-tile classes as grid shapes (nx, ny, nz), sorted by cell count:
+# rows of whole tiles and of partly empty ones (96 and 192 cells: three
+# quarters of a tile's lanes busy; FP32 128 and 192: a half and three
+# quarters), small grids, where the chain of planes a tile walks sets the
+# time, and for FP64 a 256 x 256 x 128 grid, whose tile count per plane and
+# height are those of the 512 x 128 x 128 strut tank
+PLANE_CLASSES = {L.PREC_FP64: [(128, 64, 64), (96, 96, 96), (128, 128, 128), (192, 192, 192),
+                               (256, 256, 128), (256, 256, 256), (384, 384, 384),
+                               (512, 512, 512)],
+                 L.PREC_FP32_IR: [(128, 64, 64), (128, 128, 128), (192, 192, 192),
+                                  (256, 256, 256), (512, 256, 256), (512, 512, 512)]}
+# tile heights tried on plane tiles: a tile count just above the resident
+# workgroups costs a second round, so heights between the powers of two too
+PLANE_TZS = [2, 4, 8, 16, 24, 32, 48, 64, 96, 128, 256]
 # pcg_set_tile_rules table kinds
 SINGLE, BATCH, PLANE = 0, 1, 2
 TZS = [2, 4, 8, 16, 32, 64, 128, 256]
@@ -255,7 +263,7 @@ def tune(classes=CLASSES, precisions=(L.PREC_FP64, L.PREC_FP32_IR), tzs=TZS,
     return out
 
 
-def tune_plane(classes=PLANE_CLASSES, tzs=TZS, grids=(512, 768, 1024), log=print):
+def tune_plane(classes=PLANE_CLASSES, tzs=PLANE_TZS, grids=(512, 768, 1024), log=print):
     """Single solves on plane tiles, per grid shape; rules split at the
     geometric means of the shapes' cell counts."""
     import torch

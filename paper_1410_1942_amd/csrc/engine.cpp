@@ -126,8 +126,8 @@ std::vector<TileRule> g_rules_batch[2] = {
 // Single solves on 2-D plane tiles (their own optimum: a tile also runs the
 // plane below it in the one-sweep form, and its plane holds 512 cells).
 std::vector<TileRule> g_rules_plane[2] = {
-    { { 4194304, 16, 768 }, { 11863283, 32, 1024 }, { 30821713, 64, 1024 }, { 87176971, 32, 512 }, { INT64_MAX, 256, 512 } },
-    { { 23726566, 32, 1024 }, { 67108864, 64, 768 }, { INT64_MAX, 256, 512 } },
+    { { 681070, 4, 1024 }, { 1362140, 8, 768 }, { 3852714, 16, 1024 }, { 7705428, 48, 1024 }, { 11863283, 32, 1024 }, { 30821713, 64, 1024 }, { 87176971, 24, 512 }, { INT64_MAX, 256, 512 } },
+    { { 1048576, 4, 768 }, { 3852714, 8, 1024 }, { 10897121, 24, 1024 }, { 23726566, 32, 512 }, { 67108864, 64, 512 }, { INT64_MAX, 256, 768 } },
 };
 
 // Table kinds: 0 single solves, 1 batches, 2 single solves on plane tiles.
@@ -210,14 +210,15 @@ struct Geometry {
 // Whether a grid runs 2-D plane tiles (the LDS-staged sweep): no cut-cell
 // fractions, not switched off, rows of whole groups (an even length for
 // FP64, a multiple of four for FP32), and rows that hold whole tiles (128
-// cells for FP64, two per thread; 256 for FP32, four) or, on an x axis
-// with walls, keep enough of their tiles' lanes busy (PCG_PLANE_TILES
-// takes any share); a periodic y axis holds whole tile rows.  With the
-// walls unknown (bc null: workspace sizing) the periodic conditions are
-// taken as met, which sizes for the larger tile count.
+// cells for FP64, two per thread; 256 for FP32, four) or, in single-solve
+// contexts with walls on x, keep enough of their tiles' lanes busy
+// (PCG_PLANE_TILES takes any share, also in batches); a periodic y axis
+// holds whole tile rows.  With the walls unknown (bc null: workspace
+// sizing) the periodic conditions are taken as met, which sizes for the
+// larger tile count.
 // They are taken on every grid that allows them: with one sweep per
 // iteration they measured faster than the consecutive-cell tiles on every
-// grid of whole tiles tried (FP64 per iteration: 128^3 48 against 62 us,
+// grid of whole tiles tried (FP64 per iteration: 128^3 45 against 61 us,
 // 256^3 187 against 239, the 512 x 128 x 128 strut 113 against 137, 384^3
 // 555 against 761, 512^3 1167 against 1650; FP32 inner iterations: 256^3
 // 117 against 159, 512^3 643 against 864).  On rows of nx x 256 x 256
@@ -225,10 +226,15 @@ struct Geometry {
 // (three quarters of the lanes busy) 169 against 221 us, 224 175 against
 // 230, 320 311 against 361, but 160 (five eighths) 215 against 197 and 136
 // 214 against 179; FP32: nx 136 (just over half) 104 against 118, 160
-// 106 against 131, 320 230 against 244.  Hence the shares below.
+// 106 against 131, 320 230 against 244; on smaller grids at their tuned
+// tile heights, FP64 96^3 35 against 40, 192^3 127 against 131; FP32
+// 128 x 64 x 64 (half) 27 against 29, 128^3 49 against 47.  Hence the
+// shares below.  A batch of 64 small FP32 solves whose rows are multiples
+// of four ran 160 ms with its partly filled members on plane tiles against
+// 142 with none: batches keep such rows on consecutive tiles.
 constexpr double kRaggedUse[2] = {0.7, 0.5};   // FP64, FP32
 
-bool plane_tiles_2d(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc)
+bool plane_tiles_2d(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc, bool batch)
 {
     if (flags & (PCG_FLAT_TILES | PCG_FRACTIONS)) return false;
     const bool f32 = prec == PCG_PREC_FP32_IR;
@@ -238,7 +244,8 @@ bool plane_tiles_2d(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc
     if (g.nx % width != 0) {
         if (bc && bc->kind[0] == PCG_BC_PERIODIC && g.nx > 1) return false;
         const int tiles = (g.nx + width - 1) / width;
-        if (!(flags & PCG_PLANE_TILES) && g.nx < kRaggedUse[f32] * tiles * width) return false;
+        if (!(flags & PCG_PLANE_TILES) && (batch || g.nx < kRaggedUse[f32] * tiles * width))
+            return false;
     }
     if (bc && bc->kind[2] == PCG_BC_PERIODIC && g.ny > 1 && g.ny % kTileY != 0) return false;
     return true;
@@ -316,7 +323,7 @@ size_t grid_bytes(const pcg_grid_t &g, int prec, int tz_opt, bool batch, int fla
 {
     const Geometry flat = make_geometry(g, prec, tz_opt, batch, false);
     size_t b = slot_bytes(flat, prec, frac, false);
-    if (plane_tiles_2d(g, prec, flags, nullptr)) {
+    if (plane_tiles_2d(g, prec, flags, nullptr, batch)) {
         const Geometry G = make_geometry(g, prec, tz_opt, batch, true);
         b = std::max(b, slot_bytes(G, prec, frac, one_sweep(G, prec, flags)));
     }
@@ -776,7 +783,8 @@ struct Engine {
             if (!slots[i].used) { id = i; break; }
         if (id < 0) return PCG_EBUSY;
         const Geometry geo = make_geometry(*grid_, prec, tz_opt, batch_mode(),
-                                           plane_tiles_2d(*grid_, prec, flags | this->flags, bc));
+                                           plane_tiles_2d(*grid_, prec, flags | this->flags, bc,
+                                                          batch_mode()));
         const bool sweep = one_sweep(geo, prec, flags | this->flags);
         const size_t need = slot_bytes(geo, prec, frac_space, sweep);
         size_t off = 0;
