@@ -1,10 +1,12 @@
 """The allocation-free entry point (pcg_solve_static) against the existing
 one (pcg_setup + pcg_solve on a caller workspace), through the C ABI: calls
 in a row on the library's fixed device array, each on a smaller grid than
-the one before (consecutive-cell tiles, then plane tiles with one sweep per
-iteration), each equal to the workspace path's result (the same kernels in
-the same order, so bit for bit) and within tolerance by the oracle's
-residual; and a grid too large for the array is refused."""
+the one before (plane tiles with one sweep per iteration on rows that leave
+the last tile partly empty, on rows of whole tiles, consecutive-cell tiles
+on rows of an odd length, and plane tiles again), each equal to the
+workspace path's result (the same kernels in the same order, so bit for
+bit) and within tolerance by the oracle's residual; and a grid too large
+for the array is refused."""
 import sys
 
 import numpy as np
@@ -29,14 +31,18 @@ def test_static_entry_point_matches_workspace_path(orc, F, precision):
     assert torch.cuda.is_available()
     dev = torch.device("cuda:0")
     # each call smaller than the one before; each leaves its contents in the
-    # array; the last two take plane tiles (one sweep per iteration, the
-    # second z inside the array)
-    wide = 128 if precision == 0 else 256
-    cases = [F.make_two_phase(96, 40, 33, surface_seed=51, velocity_seed=52, wedge=F.Wedge()),
+    # array; plane tiles keep the second z of the one-sweep form in it too
+    wide = 128 if precision == 0 else 256     # one tile across
+    rows = 2560 // wide
+    cases = [F.make_two_phase(200, 24, 30, surface_seed=51, velocity_seed=52, wedge=F.Wedge()),
+             F.make_two_phase(wide, rows, 17, surface_seed=55, velocity_seed=56, wedge=F.Wedge()),
              F.make_two_phase(37, 29, 23, surface_seed=53, velocity_seed=54, wedge=F.Wedge()),
-             F.make_two_phase(wide, 20, 17, surface_seed=55, velocity_seed=56, wedge=F.Wedge()),
-             F.make_two_phase(wide, 8, 9, surface_seed=57, velocity_seed=58, wedge=F.Wedge())]
-    for case in cases:
+             F.make_two_phase(wide, 1024 // wide, 9, surface_seed=57, velocity_seed=58,
+                              wedge=F.Wedge())]
+    sizes = [c.rho.size for c in cases]
+    assert sizes == sorted(sizes, reverse=True) and len(set(sizes)) == len(sizes), sizes
+    forms = [(wide, 4, 1), (wide, 4, 1), (0, 0, 2), (wide, 4, 1)]
+    for case, form in zip(cases, forms):
         _say(f"case static {case.shape} prec={precision}")
         rho, mask, rhs = (_to(torch, dev, a) for a in (case.rho, case.mask, case.rhs))
         out = torch.full_like(rhs, np.nan)
@@ -44,6 +50,7 @@ def test_static_entry_point_matches_workspace_path(orc, F, precision):
                                  precision=precision)
         s = Solver(rho, mask, case.bc, case.h, precision=precision)
         try:
+            assert s.tile_form_ex() == form
             p_w, st_w = s.solve(rhs, tol=1e-8)
         finally:
             s.close()
