@@ -6,6 +6,7 @@ bytes from the FETCH_SIZE / WRITE_SIZE counters, calibrated against the plain
 copy kernel of known size that the same run launches.
 
     python -m paper_1410_1942_amd.profiling stats <kernel_stats.csv | kernel_trace.csv>
+        [--match S --gap-ms G --segment N]
     python -m paper_1410_1942_amd.profiling traffic <fetch counter_collection.csv>
         <write counter_collection.csv> --cells N --copy-bytes B [--sha S]
 """
@@ -22,9 +23,37 @@ def _short(name: str, width: int = 70) -> str:
     return name if len(name) <= width else name[: width - 3] + "..."
 
 
-def kernel_stats(path: str) -> str:
+def _segment(rows, match: str, gap_ms: float, segment: int):
+    """The launches whose kernel name contains `match`, in start order, cut
+    where the device ran none of them for more than gap_ms; the segment-th
+    run of launches (0 = the first)."""
+    rows = sorted((r for r in rows if match in r["Kernel_Name"]),
+                  key=lambda r: int(r["Start_Timestamp"]))
+    runs, cur, last_end = [], [], None
+    for r in rows:
+        s, e = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        if last_end is not None and s - last_end > gap_ms * 1e6:
+            runs.append(cur)
+            cur = []
+        cur.append(r)
+        last_end = e if last_end is None else max(last_end, e)
+    if cur:
+        runs.append(cur)
+    if not 0 <= segment < len(runs):
+        raise SystemExit(f"{len(runs)} runs of launches, no run {segment}")
+    return runs[segment]
+
+
+def kernel_stats(path: str, match: str = "", gap_ms: float = 0.0, segment: int = -1) -> str:
     rows = list(csv.DictReader(open(path)))
     out = []
+    if segment >= 0:
+        rows = _segment(rows, match, gap_ms, segment)
+        span = int(rows[-1]["End_Timestamp"]) - int(rows[0]["Start_Timestamp"])
+        busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows)
+        out.append(f"# run {segment} of the launches matching '{match}' (cut at idle gaps over "
+                   f"{gap_ms} ms): {len(rows)} launches over {span / 1e6:.2f} ms, "
+                   f"busy {busy / 1e6:.2f} ms ({busy / span:.0%})")
     if rows and "TotalDurationNs" in rows[0]:          # *_kernel_stats.csv
         out.append(f"{'kernel':70s} {'calls':>7s} {'avg_ms':>10s} {'min_ms':>10s} "
                    f"{'max_ms':>10s} {'total_s':>9s} {'pct':>6s}")
@@ -139,6 +168,11 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
     s.add_argument("csv")
+    s.add_argument("--match", default="", help="kernel name substring (with --segment)")
+    s.add_argument("--gap-ms", type=float, default=2.0,
+                   help="idle time that separates runs of launches (with --segment)")
+    s.add_argument("--segment", type=int, default=-1,
+                   help="summarize only this run of matching launches (trace CSV)")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -147,7 +181,7 @@ def main(argv=None):
     t.add_argument("--sha", default="")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
-        print(kernel_stats(a.csv))
+        print(kernel_stats(a.csv, a.match, a.gap_ms, a.segment))
     else:
         print(traffic(a.fetch_csv, a.write_csv, a.cells, a.copy_bytes, a.sha))
 

@@ -44,3 +44,25 @@ def test_launch_filters():
     (na, ma), (nb, mb) = pr._two_forms(forms)
     assert na == 200 and ma == 1.0
     assert nb == 103 and 1.46 < mb < 1.5
+
+
+def test_trace_segments(tmp_path):
+    """A trace cut at idle gaps: the runs of matching launches are told apart
+    and one of them is summarized alone."""
+    sys.path.insert(0, ROOT)
+    from paper_1410_1942_amd import profiling as pr
+    rows = ["Kernel_Name,Start_Timestamp,End_Timestamp"]
+    t = 0
+    for run, n in ((0, 3), (1, 5)):
+        for i in range(n):
+            rows.append(f'"k_iter<1, 2, 1>(run{run})",{t},{t + 1000 * (run + 1)}')
+            rows.append(f'"k_other",{t + 10},{t + 20}')
+            t += 100_000
+        t += 10_000_000                      # 10 ms without a matching launch
+    path = tmp_path / "trace.csv"
+    path.write_text("\n".join(rows) + "\n")
+    first = pr.kernel_stats(str(path), "k_iter<1,", 2.0, 0)
+    assert "3 launches" in first and "run1" not in first and "k_other" not in first
+    second = pr.kernel_stats(str(path), "k_iter<1,", 2.0, 1)
+    assert "5 launches" in second and "run0" not in second
+    assert "k_other" in pr.kernel_stats(str(path))
