@@ -134,7 +134,7 @@ enum {
                                         periodic x or y axis still needs
                                         whole tiles); PCG_FLAT_TILES wins if
                                         both                                 */
-    PCG_TWO_SWEEPS = 64              /* on plane tiles, keep two sweeps per
+    PCG_TWO_SWEEPS = 64,             /* on plane tiles, keep two sweeps per
                                         iteration.  By default a solve on
                                         plane tiles (FP64, and the FP32
                                         inner iterations of FP32_IR) runs
@@ -146,6 +146,19 @@ enum {
                                         updates) with a second z vector in
                                         the workspace (8 bytes per cell, 4
                                         for FP32_IR)                         */
+    PCG_NARROW_TILES = 128           /* where the wide plane tiles are not
+                                        taken (rows of an odd length, or
+                                        that fill too little of a wide
+                                        tile), run 64 x 4 plane tiles of one
+                                        cell a thread with one sweep per
+                                        iteration instead of consecutive-
+                                        cell tiles at any size: by default
+                                        they are taken in batches and for
+                                        single solves of at most 2^18 cells
+                                        (not with PCG_TWO_SWEEPS,
+                                        PCG_FLAT_TILES or fractions; a
+                                        periodic x axis needs rows of whole
+                                        64-cell tiles)                       */
 };
 
 /*
@@ -263,7 +276,7 @@ int pcg_density_classes(const pcg_ctx_t *ctx, int32_t *nclasses);
 
 /*
  * Tile form of a context: *tx, *ty = columns and rows of its 2-D plane tiles
- * (128 x 4 FP64, 256 x 4 FP32), or 0, 0 when its tiles are runs of
+ * (128 x 4 FP64, 256 x 4 FP32, 64 x 4 narrow tiles), or 0, 0 when its tiles are runs of
  * consecutive cells; *sweeps = passes over the grid per iteration (1: the
  * one-sweep iteration on plane tiles, else 2).  PCG_EINVAL for null
  * arguments.

@@ -18,7 +18,7 @@ EINVAL, EDOMAIN, ESINGULAR, EBREAKDOWN, ENOMEM, EBUSY, EHIP, EUNSUPPORTED = \
 BC_NEUMANN, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 PREC_FP64, PREC_FP32_IR = 0, 1
 WARM_START, SKIP_CONNECTIVITY_CHECK, NO_DENSITY_CLASSES, FRACTIONS = 1, 2, 4, 8
-FLAT_TILES, PLANE_TILES, TWO_SWEEPS = 16, 32, 64
+FLAT_TILES, PLANE_TILES, TWO_SWEEPS, NARROW_TILES = 16, 32, 64, 128
 
 EXPORTED = [
     "pcg_workspace_bytes", "pcg_setup", "pcg_solve", "pcg_destroy",

@@ -234,25 +234,49 @@ struct Geometry {
 // 142 with none: batches keep such rows on consecutive tiles.
 constexpr double kRaggedUse[2] = {0.7, 0.5};   // FP64, FP32
 
-bool plane_tiles_2d(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc, bool batch)
+// Narrow plane tiles (64 x 4, one cell a thread, one sweep per iteration)
+// where the wide ones are not taken: in batches, in single solves of at most
+// kNarrowCells cells, and wherever PCG_NARROW_TILES asks.  Measured against
+// consecutive-cell tiles: the 64-solve FP32+IR batch 159 against 175 ms (one
+// launch per iteration once every member sweeps), the served capacity 136
+// against 132 solves/s; single solves per iteration 33^3 17.0 against 20.8
+// us (FP64) and 17.0 against 21.7 (FP32), 37 x 29 x 23 15.5 against 19.3,
+// 64^3 22.5 against 25.8 and 23.4 against 25.0; but 99^3 FP32 69 against
+// 48, 127^3 FP32 72 against 63 (FP64 54 against 82).
+constexpr int64_t kNarrowCells = 1 << 18;
+
+bool narrow_allowed(const pcg_grid_t &g, int flags, bool batch)
 {
-    if (flags & (PCG_FLAT_TILES | PCG_FRACTIONS)) return false;
-    const bool f32 = prec == PCG_PREC_FP32_IR;
-    const int cpt = f32 ? 4 : 2;
-    const int width = cpt * kBlock / kTileY;
-    if (g.nx % cpt != 0) return false;
-    if (g.nx % width != 0) {
-        if (bc && bc->kind[0] == PCG_BC_PERIODIC && g.nx > 1) return false;
-        const int tiles = (g.nx + width - 1) / width;
-        if (!(flags & PCG_PLANE_TILES) && (batch || g.nx < kRaggedUse[f32] * tiles * width))
-            return false;
-    }
-    if (bc && bc->kind[2] == PCG_BC_PERIODIC && g.ny > 1 && g.ny % kTileY != 0) return false;
-    return true;
+    if (flags & (PCG_TWO_SWEEPS | PCG_FLAT_TILES | PCG_FRACTIONS)) return false;
+    return (flags & PCG_NARROW_TILES) || batch ||
+           (int64_t)g.nx * g.ny * g.nz <= kNarrowCells;
 }
 
-Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch, bool tiles2d)
+// The group width of a grid's plane tiles (cells a thread, of adjacent
+// columns): 0 for consecutive-cell tiles, 2 (FP64) or 4 (FP32) for the wide
+// tiles above, 1 for the narrow tiles.
+int plane_group(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc, bool batch)
 {
+    if (flags & (PCG_FLAT_TILES | PCG_FRACTIONS)) return 0;
+    if (bc && bc->kind[2] == PCG_BC_PERIODIC && g.ny > 1 && g.ny % kTileY != 0) return 0;
+    const bool f32 = prec == PCG_PREC_FP32_IR;
+    const bool px = bc && bc->kind[0] == PCG_BC_PERIODIC && g.nx > 1;
+    const int nw = f32 ? 4 : 2;
+    const int width = nw * kBlock / kTileY;
+    if (g.nx % nw == 0) {
+        if (g.nx % width == 0) return nw;
+        const int tiles = (g.nx + width - 1) / width;
+        if (!px && ((flags & PCG_PLANE_TILES) ||
+                    (!batch && g.nx >= kRaggedUse[f32] * tiles * width)))
+            return nw;
+    }
+    if (narrow_allowed(g, flags, batch) && (!px || g.nx % (kBlock / kTileY) == 0)) return 1;
+    return 0;
+}
+
+Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch, int group)
+{
+    const bool tiles2d = group > 0;
     Geometry G;
     G.nx = g.nx; G.ny = g.ny; G.nz = g.nz;
     G.n = (int64_t)g.nx * g.ny * g.nz;
@@ -265,10 +289,11 @@ Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch, bo
     if (G.tz > tz_cap) G.tz = (int)std::max<int64_t>(1, tz_cap);
     // adjacent columns per thread: two when rows have an even length, four
     // for FP32 passes when it is a multiple of four
-    G.cpt = (prec == PCG_PREC_FP32_IR && g.nx % 4 == 0) ? 4 : (g.nx % 2 == 0 ? 2 : 1);
+    G.cpt = tiles2d ? group
+                    : (prec == PCG_PREC_FP32_IR && g.nx % 4 == 0) ? 4 : (g.nx % 2 == 0 ? 2 : 1);
     const int64_t per_tile = (int64_t)G.cpt * kBlock;
     if (tiles2d) {
-        G.tx = G.cpt * kBlock / kTileY;    // 128 (FP64 pairs) or 256 (FP32 quads)
+        G.tx = G.cpt * kBlock / kTileY;    // 128 (FP64 pairs), 256 (FP32 quads) or 64
         G.ty = kTileY;
         G.tiles_x = (g.nx + G.tx - 1) / G.tx;
         G.plane_tiles = G.tiles_x * ((g.ny + kTileY - 1) / kTileY);
@@ -321,12 +346,16 @@ size_t slot_bytes(const Geometry &G, int prec, bool frac = false, bool sweep = f
 // so the larger of the two forms.
 size_t grid_bytes(const pcg_grid_t &g, int prec, int tz_opt, bool batch, int flags, bool frac)
 {
-    const Geometry flat = make_geometry(g, prec, tz_opt, batch, false);
+    const Geometry flat = make_geometry(g, prec, tz_opt, batch, 0);
     size_t b = slot_bytes(flat, prec, frac, false);
-    if (plane_tiles_2d(g, prec, flags, nullptr, batch)) {
-        const Geometry G = make_geometry(g, prec, tz_opt, batch, true);
+    auto cover = [&](int group) {
+        const Geometry G = make_geometry(g, prec, tz_opt, batch, group);
         b = std::max(b, slot_bytes(G, prec, frac, one_sweep(G, prec, flags)));
-    }
+    };
+    if (const int group = plane_group(g, prec, flags, nullptr, batch)) cover(group);
+    // walls that turn the wide tiles down leave the narrow ones, which have
+    // more tiles (and so partial sums)
+    if (narrow_allowed(g, flags, batch)) cover(1);
     return b;
 }
 
@@ -381,7 +410,8 @@ int check_opts(const pcg_opts_t *o)
     if (o->check_every < 0 || o->inner_maxit < 0 || o->tz < 0 || o->grid_blocks < 0) return PCG_EINVAL;
     if (o->inner_tol < 0.0 || o->inner_tol >= 1.0 || std::isnan(o->inner_tol)) return PCG_EINVAL;
     if (o->flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES |
-                     PCG_FRACTIONS | PCG_FLAT_TILES | PCG_PLANE_TILES | PCG_TWO_SWEEPS))
+                     PCG_FRACTIONS | PCG_FLAT_TILES | PCG_PLANE_TILES | PCG_TWO_SWEEPS |
+                     PCG_NARROW_TILES))
         return PCG_EINVAL;
     return PCG_OK;
 }
@@ -783,8 +813,8 @@ struct Engine {
             if (!slots[i].used) { id = i; break; }
         if (id < 0) return PCG_EBUSY;
         const Geometry geo = make_geometry(*grid_, prec, tz_opt, batch_mode(),
-                                           plane_tiles_2d(*grid_, prec, flags | this->flags, bc,
-                                                          batch_mode()));
+                                           plane_group(*grid_, prec, flags | this->flags, bc,
+                                                       batch_mode()));
         const bool sweep = one_sweep(geo, prec, flags | this->flags);
         const size_t need = slot_bytes(geo, prec, frac_space, sweep);
         size_t off = 0;
@@ -1677,7 +1707,7 @@ int pcg_batch_admit(pcg_batch_t *b, const pcg_grid_t *grid, const double *rho,
     if (!b || !slot || !rhs || !p) return PCG_EINVAL;
     if (!(tol > 0.0) || !std::isfinite(tol) || maxit < 0) return PCG_EINVAL;
     if (flags & ~(PCG_WARM_START | PCG_SKIP_CONNECTIVITY_CHECK | PCG_NO_DENSITY_CLASSES |
-                  PCG_FLAT_TILES | PCG_PLANE_TILES | PCG_TWO_SWEEPS))
+                  PCG_FLAT_TILES | PCG_PLANE_TILES | PCG_TWO_SWEEPS | PCG_NARROW_TILES))
         return PCG_EINVAL;
     int id = -1;
     int st = b->eng.prepare(grid, rho, mask, bc, flags, &id);

@@ -255,7 +255,8 @@ struct ClsCoef {
     __device__ __forceinline__ void loadN(int64_t c, Key (&k)[N]) const
     {
         static_assert(N == 2 || N == 4, "two or four cells");
-        using W = typename std::conditional<N == 2, uint16_t, uint32_t>::type;
+        using W = typename std::conditional<
+        N == 1, uint8_t, typename std::conditional<N == 2, uint16_t, uint32_t>::type>::type;
         const unsigned h = ((const GLB W *)cls)[c / N];
 #pragma unroll
         for (int n = 0; n < N; ++n) k[n] = (int)((h >> (8 * n)) & 0xffu);
@@ -1139,7 +1140,8 @@ __device__ __forceinline__ LdsPlanes<T, KE, N> &lds_planes()
 // after the load would make the wave wait for it before the plane's barrier.
 template <class C, int N> struct KeyGroup;
 template <typename T, int N> struct KeyGroup<ClsCoef<T>, N> {
-    using W = typename std::conditional<N == 2, uint16_t, uint32_t>::type;
+    using W = typename std::conditional<
+        N == 1, uint8_t, typename std::conditional<N == 2, uint16_t, uint32_t>::type>::type;
     using raw = unsigned;
     static __device__ __forceinline__ raw load(const ClsCoef<T> &cf, int64_t c)
     {
@@ -1569,27 +1571,49 @@ __device__ void lds_passA(const Slot &S, const SlotState &st, int64_t lt, const 
 // above the bottom of the grid starts one plane low: that plane's z' serves
 // the faces below the tile and nothing is stored or summed for it.
 constexpr int kLdsS = kTileY + 3;   // LDS rows: y0 - 2 .. y0 + kTileY
+// LDS row of the sweep: the left halo two cells deep (a group of N cells
+// ending at the tile, or for N = 1 two cells: the z' of the column left of
+// the tile needs p one cell further out), the TX cells, the right halo (a
+// group), so every group of N cells is aligned to its size
+template <int N> constexpr int sweep_left() { return N > 1 ? N : 2; }
+template <int N> constexpr int sweep_w() { return tile_x<N>() + sweep_left<N>() + N; }
 
 template <typename T, typename KE, int N>
 struct LdsSweep {
-    T p[2][kLdsS * lds_w<N>()];
-    T z[2][kLdsS * lds_w<N>()];
-    KE k[2][kLdsS * lds_w<N>()];
+    T p[2][kLdsS * sweep_w<N>()];
+    T z[2][kLdsS * sweep_w<N>()];
+    KE k[2][kLdsS * sweep_w<N>()];
 };
+
+// One LDS block per value and key type, sized for the widest groups of that
+// type (two FP64 or four FP32 cells a thread); one-cell-a-thread tiles use
+// a smaller view of the same block.  A workgroup's tiles are separated by
+// the barrier of their block sum, so the views never overlap in time.
+template <typename T, typename KE>
+__device__ __forceinline__ void *lds_sweep_block()
+{
+    constexpr int NW = sizeof(T) == 8 ? 2 : 4;
+    __shared__ __attribute__((aligned(16))) LdsSweep<T, KE, NW> s;
+    return &s;
+}
 
 template <typename T, typename KE, int N>
 __device__ __forceinline__ LdsSweep<T, KE, N> &lds_sweep()
 {
-    __shared__ __attribute__((aligned(16))) LdsSweep<T, KE, N> s;
-    return s;
+    static_assert(sizeof(LdsSweep<T, KE, N>) <= sizeof(LdsSweep<T, KE, sizeof(T) == 8 ? 2 : 4>),
+                  "the view fits the block");
+    return *static_cast<LdsSweep<T, KE, N> *>(lds_sweep_block<T, KE>());
 }
 
 template <typename T, typename X, class C, int XM, int N>
 __device__ void lds_sweep_cg(const Slot &S, const SlotState &st, int64_t lt, const C &cf,
                              double (&acc)[3])
 {
-    constexpr int TX = tile_x<N>(), W = lds_w<N>(), G = TX / N;
-    static_assert(3 * G + 2 * kTileY + 3 <= kBlock, "the halo roles fit the workgroup");
+    constexpr int TX = tile_x<N>(), W = sweep_w<N>(), G = TX / N, XL = sweep_left<N>();
+    // halo lanes: three rows of groups, the left column (z'), two corners,
+    // the right column, and for N = 1 the second left column (p only)
+    constexpr int kHalo = 3 * G + 2 * kTileY + 3 + (N == 1 ? kTileY : 0);
+    static_assert(kHalo <= kBlock, "the halo roles fit the workgroup");
     using K = typename C::Key;
     using KE = typename KeyElem<C>::type;
     using KP = KeyGroup<C, N>;
@@ -1616,12 +1640,13 @@ __device__ void lds_sweep_cg(const Slot &S, const SlotState &st, int64_t lt, con
     const T beta = (T)st.beta, alpha = (T)st.alpha;
     const T alpha_p0 = (T)st.alpha_p0, alpha_p1 = (T)st.alpha_p1;
     const int64_t qo = (int64_t)min(t.j, ny - 1) * nx + min(t.i, nx - N);
-    const int own = (jj + 2) * W + ii + N;
+    const int own = (jj + 2) * W + ii + XL;
     // halo role of this lane: a group of the rows below (two) or above the
-    // tile, of the two columns left of it (the right one of which also gets
-    // z'), or one cell (with its group) of the column right of it; wrapped
-    // on periodic axes, clamped at walls, where the cells that would use it
-    // substitute the wall.  role 2: p and z', role 1: p only.
+    // tile, of the column left of it (with z'; for N = 1 also the cell left
+    // of that, p only), of the corners left of the rows below and above, or
+    // of the column right of it; wrapped on periodic axes, clamped at walls,
+    // where the cells that would use it substitute the wall.  role 2: p and
+    // z', role 1: p only.
     int dx = 0, dy = 0, role = 0;
     if (l < G) { dx = N * l; dy = -1; role = 2; }
     else if (l < 2 * G) { dx = N * (l - G); dy = -2; role = 1; }
@@ -1631,6 +1656,7 @@ __device__ void lds_sweep_cg(const Slot &S, const SlotState &st, int64_t lt, con
         if (m < kTileY) { dx = -N; dy = m; role = 2; }
         else if (m < kTileY + 2) { dx = -N; dy = m == kTileY ? -1 : kTileY; role = 1; }
         else if (m < 2 * kTileY + 3) { dx = TX; dy = m - kTileY - 3; role = 1; }
+        else if (N == 1 && m < 3 * kTileY + 3) { dx = -2; dy = m - 2 * kTileY - 3; role = 1; }
     }
     int64_t qh = qo;
     int hslot = own, hi = t.i, hj = t.j;
@@ -1639,7 +1665,7 @@ __device__ void lds_sweep_cg(const Slot &S, const SlotState &st, int64_t lt, con
         ix = px ? (ix + nx) % nx : max(0, min(nx - N, ix));
         jy = py ? (jy + ny) % ny : max(0, min(ny - 1, jy));
         qh = (int64_t)jy * nx + ix;
-        hslot = (dy + 2) * W + dx + N;
+        hslot = (dy + 2) * W + dx + XL;
         hi = ix;
         hj = jy;
     }
@@ -1649,7 +1675,7 @@ __device__ void lds_sweep_cg(const Slot &S, const SlotState &st, int64_t lt, con
     const int lw = __builtin_amdgcn_readfirstlane(l);
     // the waves holding halo lanes load in every lane; those holding z'
     // halo lanes evaluate the halo groups in every lane
-    const bool hwave = lw < 3 * G + 2 * kTileY + 3;
+    const bool hwave = lw < kHalo;
     const bool swave = lw < G || (lw >= 3 * G && lw < 3 * G + kTileY);
     const int i0 = t.i, j = t.j;
     const bool hxm = i0 > 0 || px, hxp = i0 + N - 1 < nx - 1 || px;
@@ -2574,8 +2600,13 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
         // 2-D plane tiles: both passes LDS-staged (two FP64 or four FP32 cells a thread)
         if (FAMILY == PCG_PREC_FP64) {
             if (WHICH == 1) {
+                // one-cell-a-thread tiles run pass A once, for the first p.A p
+                // of their one-sweep iteration: cell by cell, unstaged
                 if (ph == K1_CG_A) {
-                    if (MODE == 3) lds_passA<double, ClsCoef<double>, 2>(S, st, lt, c64, acc);
+                    if (__builtin_amdgcn_readfirstlane(S.cpt) == 1) {
+                        if (MODE == 3) body_passA<double>(S, st, lt, c64, acc);
+                        else body_passA<double>(S, st, lt, r64, acc);
+                    } else if (MODE == 3) lds_passA<double, ClsCoef<double>, 2>(S, st, lt, c64, acc);
                     else lds_passA<double, RhoCoef<double>, 2>(S, st, lt, r64, acc);
                 }
             } else if (ph == K2_CG_B) {
@@ -2589,11 +2620,18 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
                 }
             } else if (ph == K2_CG_F) {
                 const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
+                const bool one = __builtin_amdgcn_readfirstlane(S.cpt) == 1;   // 64 x 4 tiles
                 if (MODE == 3) {
-                    if (catch_up) lds_sweep_cg<double, double, ClsCoef<double>, 3, 2>(S, st, lt, c64, acc);
+                    if (one) {
+                        if (catch_up) lds_sweep_cg<double, double, ClsCoef<double>, 3, 1>(S, st, lt, c64, acc);
+                        else lds_sweep_cg<double, double, ClsCoef<double>, 0, 1>(S, st, lt, c64, acc);
+                    } else if (catch_up) lds_sweep_cg<double, double, ClsCoef<double>, 3, 2>(S, st, lt, c64, acc);
                     else lds_sweep_cg<double, double, ClsCoef<double>, 0, 2>(S, st, lt, c64, acc);
                 } else {
-                    if (catch_up) lds_sweep_cg<double, double, RhoCoef<double>, 3, 2>(S, st, lt, r64, acc);
+                    if (one) {
+                        if (catch_up) lds_sweep_cg<double, double, RhoCoef<double>, 3, 1>(S, st, lt, r64, acc);
+                        else lds_sweep_cg<double, double, RhoCoef<double>, 0, 1>(S, st, lt, r64, acc);
+                    } else if (catch_up) lds_sweep_cg<double, double, RhoCoef<double>, 3, 2>(S, st, lt, r64, acc);
                     else lds_sweep_cg<double, double, RhoCoef<double>, 0, 2>(S, st, lt, r64, acc);
                 }
             } else if (ph == K2_ZERO_X) body_zero_x(S, st, lt, acc);
@@ -2603,7 +2641,10 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
             const ClsCoef<float> c32{ gp(S.cls), tab32 };
             if (WHICH == 1) {
                 if (ph == K1_IR_A) {
-                    if (MODE == 3) lds_passA<float, ClsCoef<float>, 4>(S, st, lt, c32, acc);
+                    if (__builtin_amdgcn_readfirstlane(S.cpt) == 1) {
+                        if (MODE == 3) body_passA<float>(S, st, lt, c32, acc);
+                        else body_passA<float>(S, st, lt, r32, acc);
+                    } else if (MODE == 3) lds_passA<float, ClsCoef<float>, 4>(S, st, lt, c32, acc);
                     else lds_passA<float, RhoCoef<float>, 4>(S, st, lt, r32, acc);
                 }
             } else if (ph == K2_IR_B) {
@@ -2617,11 +2658,18 @@ __device__ __forceinline__ void run_body(int ph, const Slot &S,
                 }
             } else if (ph == K2_IR_F) {
                 const bool catch_up = __builtin_amdgcn_readfirstlane(st.xpend) == 2;
+                const bool one = __builtin_amdgcn_readfirstlane(S.cpt) == 1;   // 64 x 4 tiles
                 if (MODE == 3) {
-                    if (catch_up) lds_sweep_cg<float, float, ClsCoef<float>, 3, 4>(S, st, lt, c32, acc);
+                    if (one) {
+                        if (catch_up) lds_sweep_cg<float, float, ClsCoef<float>, 3, 1>(S, st, lt, c32, acc);
+                        else lds_sweep_cg<float, float, ClsCoef<float>, 0, 1>(S, st, lt, c32, acc);
+                    } else if (catch_up) lds_sweep_cg<float, float, ClsCoef<float>, 3, 4>(S, st, lt, c32, acc);
                     else lds_sweep_cg<float, float, ClsCoef<float>, 0, 4>(S, st, lt, c32, acc);
                 } else {
-                    if (catch_up) lds_sweep_cg<float, float, RhoCoef<float>, 3, 4>(S, st, lt, r32, acc);
+                    if (one) {
+                        if (catch_up) lds_sweep_cg<float, float, RhoCoef<float>, 3, 1>(S, st, lt, r32, acc);
+                        else lds_sweep_cg<float, float, RhoCoef<float>, 0, 1>(S, st, lt, r32, acc);
+                    } else if (catch_up) lds_sweep_cg<float, float, RhoCoef<float>, 3, 4>(S, st, lt, r32, acc);
                     else lds_sweep_cg<float, float, RhoCoef<float>, 0, 4>(S, st, lt, r32, acc);
                 }
             } else if (ph == K2_IR_UPDATE) body_ir_update(S, st, lt, acc);

@@ -50,13 +50,22 @@ def test_workspace_bytes_validation(lib):
     assert lib.pcg_workspace_bytes(ctypes.byref(_g(32, 32, 32)), ctypes.byref(o),
                                    ctypes.byref(out)) == L.OK
     n = 32 ** 3
-    assert out.value >= 40 * n                 # rho, z and three directions in FP64
-    assert out.value < 48 * n
+    # rho, z, three directions and (narrow plane tiles, one sweep per
+    # iteration: the default at this size) the second z, in FP64
+    assert out.value >= 48 * n
+    assert out.value < 56 * n
     o.precision = L.PREC_FP32_IR
     out_ir = ctypes.c_size_t()
     assert lib.pcg_workspace_bytes(ctypes.byref(_g(32, 32, 32)), ctypes.byref(o),
                                    ctypes.byref(out_ir)) == L.OK
-    assert 32 * n <= out_ir.value < 40 * n
+    assert 36 * n <= out_ir.value < 44 * n
+    # consecutive-cell tiles drop the second z
+    o.precision = L.PREC_FP64
+    o.flags = L.FLAT_TILES
+    assert lib.pcg_workspace_bytes(ctypes.byref(_g(32, 32, 32)), ctypes.byref(o),
+                                   ctypes.byref(out)) == L.OK
+    assert 40 * n <= out.value < 48 * n
+    o.flags = 0
     for bad in (_g(0, 4, 4), _g(4, -1, 4), _g(4, 4, 4, 0.0), _g(4, 4, 4, float("nan"))):
         assert lib.pcg_workspace_bytes(ctypes.byref(bad), None, ctypes.byref(out)) == L.EINVAL
     big = _g(2048, 1024, 1024)
@@ -300,6 +309,8 @@ def test_fraction_flag_host_rules(lib):
     o = L.Opts()
     base, more = ctypes.c_size_t(), ctypes.c_size_t()
     g = _g(20, 16, 12)
+    # fractions run consecutive-cell tiles: compare with that form
+    o.flags = L.FLAT_TILES
     assert lib.pcg_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ctypes.byref(base)) == L.OK
     o.flags = L.FRACTIONS
     assert lib.pcg_workspace_bytes(ctypes.byref(g), ctypes.byref(o), ctypes.byref(more)) == L.OK
@@ -336,7 +347,7 @@ def test_one_sweep_workspace(lib):
     """The one-sweep iteration (the default on plane tiles) adds one vector,
     the second z (FP64, or FP32 for the refinement), to the workspace;
     PCG_TWO_SWEEPS drops it, and nothing changes where it does not apply
-    (rows of an odd length, consecutive-cell tiles)."""
+    (consecutive-cell tiles)."""
     def ws(g, flags, prec=0):
         o = L.Opts()
         o.flags = flags
@@ -357,8 +368,16 @@ def test_one_sweep_workspace(lib):
         for extra in (0, L.TWO_SWEEPS):
             assert ws(gs, extra) >= ws(gs, L.FLAT_TILES), (shape, extra)
             assert ws(gs, L.PLANE_TILES | extra) >= ws(gs, L.FLAT_TILES), (shape, extra)
-    g97 = _g(97, 16, 8)
+    # rows of an odd length: consecutive-cell tiles above 2^18 cells (no
+    # second z), narrow plane tiles (one cell a thread, one sweep) below it
+    # or when asked for
+    g97 = _g(97, 64, 64)
     assert ws(g97, L.PLANE_TILES) == ws(g97, L.PLANE_TILES | L.TWO_SWEEPS)
+    n97 = 97 * 64 * 64
+    # (narrow tiles are more, and so are their partial sums)
+    assert 8 * n97 <= ws(g97, L.NARROW_TILES) - ws(g97, L.TWO_SWEEPS) <= 8 * n97 + 65536
+    small = _g(97, 16, 8)
+    assert ws(small, 0) - ws(small, L.TWO_SWEEPS) >= 8 * 97 * 16 * 8 - 4 * 256
     # rows of 96 cells fill three quarters of a 128-cell tile: plane tiles
     # (and the second z) when asked for
     g96 = _g(96, 16, 8)
@@ -369,7 +388,9 @@ def test_one_sweep_workspace(lib):
     # the FP32 inner solve on plane tiles: a second FP32 z
     g256 = _g(256, 16, 8)
     d32 = ws(g256, L.PLANE_TILES, 1) - ws(g256, L.PLANE_TILES | L.TWO_SWEEPS, 1)
-    assert 4 * 256 * 16 * 8 - 4 * 256 <= d32 <= 4 * 256 * 16 * 8
+    # (at this size the sizing also covers narrow tiles, whose partial sums
+    # are more)
+    assert 4 * 256 * 16 * 8 - 4 * 256 <= d32 <= 4 * 256 * 16 * 8 + 65536
     assert ws(g256, 0, 1) == ws(g256, L.PLANE_TILES, 1)   # FP32: plane tiles at any size
     # a 512^3 FP64 grid takes plane tiles, hence the second z, by default
     big = _g(512, 512, 512)

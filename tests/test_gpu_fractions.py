@@ -129,7 +129,9 @@ def test_fraction_validation_and_clearing(F, torch_dev):
     # partial sets are refused; a context without reserved room refuses too
     fake = ctypes.c_void_p(t(ax).data_ptr())
     assert s.lib.pcg_set_fractions(s._ctx, fake, None, None, None) == L.EINVAL
-    plain = Solver(t(case.rho), t(case.mask), case.bc, case.h)
+    # (a context with room for fractions keeps consecutive-cell tiles: the
+    # plain context asks for the same form, so that the bits can match)
+    plain = Solver(t(case.rho), t(case.mask), case.bc, case.h, flags=L.FLAT_TILES)
     with pytest.raises(L.PCGError) as e:
         plain.set_fractions(t(ax), t(ay), t(az), t(vol))
     assert e.value.code == L.EINVAL

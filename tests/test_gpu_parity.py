@@ -191,11 +191,14 @@ def test_maxit_and_warm_resume(orc, F, torch_dev):
     assert rr <= 1e-8
 
 
-# k = 13..17 covers every residue modulo 3; a row length of 32 runs the
-# grouped passes, 33 the one-cell ones
+# k = 13..17 covers every residue modulo 3; at this size the default tiles
+# are narrow plane tiles (one sweep per iteration), and on consecutive-cell
+# tiles (flags 16) a row length of 32 runs the grouped passes, 33 the
+# one-cell ones
+@pytest.mark.parametrize("flags", [0, 16], ids=["default", "flat"])
 @pytest.mark.parametrize("k,nx", [(13, 32), (14, 32), (15, 32), (16, 32), (17, 32),
                                   (13, 33), (14, 33)])
-def test_capped_iterate_is_the_kth_iterate(orc, F, torch_dev, k, nx):
+def test_capped_iterate_is_the_kth_iterate(orc, F, torch_dev, k, nx, flags):
     """Stopped by the iteration cap, x is the reference's k-th PCG iterate,
     whatever k is modulo the interval at which pass B updates x: updates still
     pending at the cap are applied before the solve returns.  The FP32 inner
@@ -209,10 +212,10 @@ def test_capped_iterate_is_the_kth_iterate(orc, F, torch_dev, k, nx):
     scale = np.abs(ref.p).max()
     # one update more or less moves the iterate by about 1 %: far outside both bars
     assert np.abs(ref.p - prev.p).max() > 1e-3 * scale
-    p, st = gpu_solve(torch_dev, case, tol=1e-30, maxit=k)
+    p, st = gpu_solve(torch_dev, case, tol=1e-30, maxit=k, flags=flags)
     assert st["status"] == 1 and st["iters"] == k, st
     assert np.abs(p - ref.p).max() <= 1e-10 * scale
-    p32, st32 = gpu_solve(torch_dev, case, tol=1e-30, maxit=k, precision=1)
+    p32, st32 = gpu_solve(torch_dev, case, tol=1e-30, maxit=k, precision=1, flags=flags)
     # two FP64 residuals: the initial one and the one after the single inner solve
     assert st32["status"] == 1 and st32["iters"] == k and st32["outer_iters"] == 2, st32
     assert np.abs(p32 - ref.p).max() <= 1e-4 * scale

@@ -27,6 +27,7 @@ P = 2
 FLAT_TILES = 16
 PLANE = 32
 TWO = 64
+NARROW = 128
 NO_CLASSES = 4
 
 
@@ -234,13 +235,18 @@ def test_tile_form_reported(F, torch_dev):
             ((128, 13, 6), (0, 0, P, P, 0, 1), PLANE, 0, (0, 0, 2)),   # ragged periodic y
             ((200, 8, 6), TANK, 0, 0, (128, 4, 1)),            # ragged columns: 78% of the lanes
             ((200, 8, 6), TANK, 0, 1, (256, 4, 1)),
-            ((160, 8, 6), TANK, 0, 0, (0, 0, 2)),              # FP64 with 62% of the lanes: flat
-            ((160, 8, 6), TANK, PLANE, 0, (128, 4, 1)),        # unless asked for
+            ((160, 64, 32), TANK, 0, 0, (0, 0, 2)),            # FP64 with 62% of the lanes: flat
+            ((160, 8, 6), TANK, 0, 0, (64, 4, 1)),             # at most 2^18 cells: narrow
+            ((160, 8, 6), TANK, PLANE, 0, (128, 4, 1)),        # wide when asked for
             ((136, 8, 6), TANK, 0, 1, (256, 4, 1)),            # FP32 with 53% of the lanes
-            ((120, 8, 6), TANK, 0, 1, (0, 0, 2)),              # FP32 with 47%: flat
+            ((120, 64, 48), TANK, 0, 1, (0, 0, 2)),            # FP32 with 47%: flat
+            ((120, 8, 6), TANK, 0, 1, (64, 4, 1)),             # at most 2^18 cells: narrow
             ((130, 8, 6), (P, P, 0, 0, 0, 1), PLANE, 0, (0, 0, 2)),   # ragged periodic x
-            ((97, 8, 6), TANK, PLANE, 0, (0, 0, 2)),           # odd rows: no cell pairs
-            ((98, 8, 6), TANK, PLANE, 1, (0, 0, 2))]:          # FP32: rows not of quads
+            ((97, 64, 48), TANK, PLANE, 0, (0, 0, 2)),         # odd rows: no cell pairs
+            ((97, 8, 6), TANK, PLANE, 0, (64, 4, 1)),          # at most 2^18 cells: narrow
+            ((97, 64, 48), TANK, NARROW, 0, (64, 4, 1)),       # narrow when asked for
+            ((97, 8, 6), TANK, TWO, 0, (0, 0, 2)),             # two sweeps: no narrow tiles
+            ((98, 8, 6), TANK, PLANE, 1, (64, 4, 1))]:         # FP32: rows not of quads
         case = _case(F, shape, bc, wedge=False)
         s = Solver(t(case.rho), t(case.mask), case.bc, case.h, precision=prec, flags=flags)
         try:

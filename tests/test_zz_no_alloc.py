@@ -2,8 +2,9 @@
 one (pcg_setup + pcg_solve on a caller workspace), through the C ABI: calls
 in a row on the library's fixed device array, each on a smaller grid than
 the one before (plane tiles with one sweep per iteration on rows that leave
-the last tile partly empty, on rows of whole tiles, consecutive-cell tiles
-on rows of an odd length, and plane tiles again), each equal to the
+the last tile partly empty, on rows of whole tiles, narrow plane tiles of
+one cell a thread on rows of an odd length, and wide plane tiles again),
+each equal to the
 workspace path's result (the same kernels in the same order, so bit for
 bit) and within tolerance by the oracle's residual; and a grid too large
 for the array is refused."""
@@ -41,7 +42,7 @@ def test_static_entry_point_matches_workspace_path(orc, F, precision):
                               wedge=F.Wedge())]
     sizes = [c.rho.size for c in cases]
     assert sizes == sorted(sizes, reverse=True) and len(set(sizes)) == len(sizes), sizes
-    forms = [(wide, 4, 1), (wide, 4, 1), (0, 0, 2), (wide, 4, 1)]
+    forms = [(wide, 4, 1), (wide, 4, 1), (64, 4, 1), (wide, 4, 1)]
     for case, form in zip(cases, forms):
         _say(f"case static {case.shape} prec={precision}")
         rho, mask, rhs = (_to(torch, dev, a) for a in (case.rho, case.mask, case.rhs))
