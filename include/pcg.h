@@ -146,19 +146,16 @@ enum {
                                         updates) with a second z vector in
                                         the workspace (8 bytes per cell, 4
                                         for FP32_IR)                         */
-    PCG_NARROW_TILES = 128           /* where the wide plane tiles are not
-                                        taken (rows of an odd length, or
-                                        that fill too little of a wide
-                                        tile), run 64 x 4 plane tiles of one
-                                        cell a thread with one sweep per
-                                        iteration instead of consecutive-
-                                        cell tiles at any size: by default
-                                        they are taken in batches and for
-                                        single solves of at most 2^18 cells
-                                        (not with PCG_TWO_SWEEPS,
-                                        PCG_FLAT_TILES or fractions; a
-                                        periodic x axis needs rows of whole
-                                        64-cell tiles)                       */
+    PCG_NARROW_TILES = 128           /* 64 x 4 plane tiles of one cell a
+                                        thread with one sweep per iteration
+                                        wherever the wide plane tiles are
+                                        not taken.  By default they are
+                                        taken in batches, on rows of an odd
+                                        length, and for single solves of at
+                                        most 2^18 cells; not with
+                                        PCG_TWO_SWEEPS, PCG_FLAT_TILES or
+                                        fractions.  A periodic x axis needs
+                                        rows of whole 64-cell tiles         */
 };
 
 /*
@@ -470,11 +467,12 @@ int pcg_batch_destroy(pcg_batch_t *b);
  * cells uses the first rule with n <= max_cells[i]: tile height tz[i] and,
  * for single-solve contexts, grid[i] workgroups (0 = library default).
  * Rules must be ordered by increasing max_cells, 1 <= n <= 64, tz >= 1.
- * There are three tables per precision: table = 0 for single-solve
+ * There are four tables per precision: table = 0 for single-solve
  * contexts on tiles of consecutive cells, 1 for batches (any tile form),
  * where many resident solves already fill the device and longer tiles cost
- * less per-tile overhead, and 2 for single-solve contexts on 2-D plane
- * tiles.  Contexts and batches created afterwards use them.  A
+ * less per-tile overhead, 2 for single-solve contexts on wide 2-D plane
+ * tiles and 3 for single-solve contexts on narrow ones (64 x 4).  Contexts
+ * and batches created afterwards use them.  A
  * solve's tile height depends only on its own cell count, so its result
  * does not depend on the other solves of a batch.  Host-only; not
  * thread-safe against concurrent setup.  pcg_get_tile_rules copies at most

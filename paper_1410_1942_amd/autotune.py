@@ -9,11 +9,13 @@ fastest per iteration.  The result is a JSON table keyed by GPU architecture:
                 "fp32_ir": [[max_cells, tz, grid], ...],
                 "fp64_batch": [...], "fp32_ir_batch": [...],
                 "fp64_plane": [...], "fp32_ir_plane": [...],
+                "fp64_narrow": [...], "fp32_ir_narrow": [...],
                 "measured": {...}}}
 
 Single-solve rules are tuned on one solve at a time, on tiles of consecutive
-cells ("fp64", "fp32_ir") and on 2-D plane tiles ("*_plane", grids whose
-rows take them; plane tiles run one sweep per iteration); batch
+cells ("fp64", "fp32_ir"), on wide 2-D plane tiles ("*_plane", grids whose
+rows take them) and on narrow ones ("*_narrow", 64 x 4 tiles of one cell a
+thread, on rows of odd lengths); plane tiles run one sweep per iteration; batch
 rules on a resident batch of several solves of the class size (their tiles
 share every launch, so longer tiles usually win).
 
@@ -24,6 +26,7 @@ Tile height depends only on a solve's own cell count, so a tuned table never
 makes a solve's result depend on the other solves it is batched with.
 
     python -m paper_1410_1942_amd.autotune [--out FILE] [--quick] [--plane-only]
+        [--narrow-only]
 """
 from __future__ import annotations
 
@@ -57,8 +60,14 @@ PLANE_CLASSES = {L.PREC_FP64: [(128, 64, 64), (96, 96, 96), (128, 128, 128), (19
 # tile heights tried on plane tiles: a tile count just above the resident
 # workgroups costs a second round, so heights between the powers of two too
 PLANE_TZS = [2, 4, 8, 16, 24, 32, 48, 64, 96, 128, 256]
+# narrow-tile classes: rows of odd lengths (narrow tiles are what such rows
+# run), sorted by cell count
+NARROW_CLASSES = {p: [(33, 33, 33), (65, 65, 65), (99, 99, 99), (127, 127, 127),
+                      (161, 120, 100), (191, 191, 191), (255, 255, 255), (383, 383, 383)]
+                  for p in (L.PREC_FP64, L.PREC_FP32_IR)}
+NARROW_TZS = [4, 8, 16, 24, 32, 48, 64, 96, 128]
 # pcg_set_tile_rules table kinds
-SINGLE, BATCH, PLANE = 0, 1, 2
+SINGLE, BATCH, PLANE, NARROW = 0, 1, 2, 3
 TZS = [2, 4, 8, 16, 32, 64, 128, 256]
 GRIDS = [256, 512, 768, 1024, 2048]
 
@@ -70,8 +79,8 @@ def _kind(for_batches, table):
 
 
 def get_rules(precision: int, for_batches: bool = False, table=None):
-    """Rules of one table: single solves (default), batches, or (table =
-    PLANE) single solves on plane tiles."""
+    """Rules of one table: single solves (default), batches, or single
+    solves on wide (table = PLANE) or narrow (table = NARROW) plane tiles."""
     lib = L.load()
     cap = 64
     mc = (ctypes.c_int64 * cap)()
@@ -115,6 +124,8 @@ def install(path: str = None, arch: str = None) -> bool:
             set_rules(prec, table[arch][key + "_batch"], for_batches=True)
         if key + "_plane" in table[arch]:
             set_rules(prec, table[arch][key + "_plane"], table=PLANE)
+        if key + "_narrow" in table[arch]:
+            set_rules(prec, table[arch][key + "_narrow"], table=NARROW)
     return True
 
 
@@ -263,15 +274,18 @@ def tune(classes=CLASSES, precisions=(L.PREC_FP64, L.PREC_FP32_IR), tzs=TZS,
     return out
 
 
-def tune_plane(classes=PLANE_CLASSES, tzs=PLANE_TZS, grids=(512, 768, 1024), log=print):
-    """Single solves on plane tiles, per grid shape; rules split at the
-    geometric means of the shapes' cell counts."""
+def tune_plane(classes=PLANE_CLASSES, tzs=PLANE_TZS, grids=(512, 768, 1024), log=print,
+               form="plane"):
+    """Single solves on wide (form "plane") or narrow (form "narrow") plane
+    tiles, per grid shape; rules split at the geometric means of the shapes'
+    cell counts."""
+    flags = L.PLANE_TILES if form == "plane" else L.NARROW_TILES
     import torch
     from . import fields as F
     dev = torch.device("cuda:0")
     out, measured = {}, {}
     for prec, shapes in classes.items():
-        key = PREC_KEYS[prec] + "_plane"
+        key = PREC_KEYS[prec] + "_" + form
         best = []
         for nx, ny, nz in shapes:
             case = F.make_two_phase(nx, ny, nz, surface_seed=1, velocity_seed=2,
@@ -279,7 +293,7 @@ def tune_plane(classes=PLANE_CLASSES, tzs=PLANE_TZS, grids=(512, 768, 1024), log
             dev_case = (torch.from_numpy(case.rho).to(dev),
                         torch.from_numpy(case.mask).to(dev),
                         torch.from_numpy(case.rhs).to(dev), case.bc, case.h)
-            results = sorted((_time_per_iter(dev_case, prec, tz, g, flags=L.PLANE_TILES), tz, g)
+            results = sorted((_time_per_iter(dev_case, prec, tz, g, flags=flags), tz, g)
                              for tz in tzs if tz <= nz for g in grids)
             ms, tz, g = results[0]
             measured[f"{key}/{nx}x{ny}x{nz}"] = [[round(m, 5), t, gg] for m, t, gg in results[:5]]
@@ -291,7 +305,7 @@ def tune_plane(classes=PLANE_CLASSES, tzs=PLANE_TZS, grids=(512, 768, 1024), log
             torch.cuda.empty_cache()
         out[key] = [[int(math.sqrt(c * best[i + 1][0])) if i + 1 < len(best) else 2 ** 62, t, g]
                     for i, (c, t, g) in enumerate(best)]
-    out["measured_plane"] = measured
+    out["measured_" + form] = measured
     return out
 
 
@@ -303,19 +317,26 @@ def main(argv=None):
     ap.add_argument("--batches-only", action="store_true",
                     help="tune only the batch tables, keep the others")
     ap.add_argument("--plane-only", action="store_true",
-                    help="tune only the plane-tile tables, keep the others")
+                    help="tune only the wide plane-tile tables, keep the others")
+    ap.add_argument("--narrow-only", action="store_true",
+                    help="tune only the narrow plane-tile tables, keep the others")
     a = ap.parse_args(argv)
     os.environ["PCGMI_TILE_TABLE"] = "none"
     arch = device_arch()
     full = json.load(open(a.out)) if os.path.exists(a.out) else {}
     table = dict(full.get(arch, {}))
-    if not (a.batches_only or a.plane_only):
+    only = a.batches_only or a.plane_only or a.narrow_only
+    if not only:
         kw = dict(classes=[24, 64, 160], tzs=[4, 16, 32], grids=[512, 1024]) if a.quick else {}
         table.update(tune(**kw))
-    if not a.batches_only:
+    if not only or a.plane_only:
         kwp = dict(classes={L.PREC_FP64: [(128, 64, 64)]}, tzs=[8, 32]) if a.quick else {}
         table.update(tune_plane(**kwp))
-    if not a.plane_only:
+    if not only or a.narrow_only:
+        kwn = dict(classes={L.PREC_FP64: [(65, 64, 64)]}, tzs=[8, 32]) if a.quick else {}
+        table.update(tune_plane(**dict(dict(classes=NARROW_CLASSES, tzs=NARROW_TZS), **kwn),
+                                form="narrow"))
+    if not only or a.batches_only:
         kwb = dict(classes=[24, 64], tzs=[4, 16]) if a.quick else {}
         table.update(tune_batches(**kwb))
     full[arch] = table

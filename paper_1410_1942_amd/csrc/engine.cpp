@@ -130,20 +130,37 @@ std::vector<TileRule> g_rules_plane[2] = {
     { { 1048576, 4, 768 }, { 3852714, 8, 1024 }, { 10897121, 24, 1024 }, { 23726566, 32, 512 }, { 67108864, 64, 512 }, { INT64_MAX, 256, 768 } },
 };
 
-// Table kinds: 0 single solves, 1 batches, 2 single solves on plane tiles.
-enum { kTableSingle = 0, kTableBatch = 1, kTablePlane = 2 };
+// Single solves on narrow plane tiles (64 x 4, one cell a thread): the
+// autotuner's choice on odd-row grids, longer tiles than the wide ones at
+// the same size (a narrow plane holds half the cells of a wide FP64 one and
+// a quarter of a wide FP32 one).
+std::vector<TileRule> g_rules_narrow[2] = {
+    { { 99343, 4, 512 }, { 516205, 8, 512 }, { 1409802, 24, 1024 }, { 1989340, 16, 1024 }, { 3669049, 24, 1024 }, { 10748808, 64, 1024 }, { 30521679, 128, 512 }, { INT64_MAX, 64, 512 } },
+    { { 99343, 4, 1024 }, { 516205, 8, 768 }, { 1409802, 16, 1024 }, { 1989340, 16, 1024 }, { 3669049, 24, 1024 }, { 10748808, 64, 512 }, { 30521679, 128, 1024 }, { INT64_MAX, 48, 512 } },
+};
+
+// Table kinds: 0 single solves, 1 batches, 2 single solves on plane tiles,
+// 3 single solves on narrow plane tiles.
+enum { kTableSingle = 0, kTableBatch = 1, kTablePlane = 2, kTableNarrow = 3 };
 
 std::vector<TileRule> &rules_of(int prec, int table)
 {
-    std::vector<TileRule> *t = table == kTableBatch ? g_rules_batch
-                               : table == kTablePlane ? g_rules_plane : g_rules;
+    std::vector<TileRule> *t = table == kTableBatch    ? g_rules_batch
+                               : table == kTablePlane  ? g_rules_plane
+                               : table == kTableNarrow ? g_rules_narrow
+                                                       : g_rules;
     return t[prec == PCG_PREC_FP32_IR ? 1 : 0];
 }
 
-// Batches use the batch table whatever their tile form.
-const TileRule &rule_for(int64_t n, int prec, bool batch, bool plane)
+// Batches use the batch table whatever their tile form; single solves the
+// table of theirs (group: 0 consecutive cells, 1 narrow, else wide plane
+// tiles).
+const TileRule &rule_for(int64_t n, int prec, bool batch, int group)
 {
-    const auto &rules = rules_of(prec, batch ? kTableBatch : plane ? kTablePlane : kTableSingle);
+    const int table = batch ? kTableBatch
+                      : group == 1 ? kTableNarrow
+                      : group > 1 ? kTablePlane : kTableSingle;
+    const auto &rules = rules_of(prec, table);
     for (const auto &r : rules)
         if (n <= r.max_cells) return r;
     return rules.back();
@@ -235,21 +252,31 @@ struct Geometry {
 constexpr double kRaggedUse[2] = {0.7, 0.5};   // FP64, FP32
 
 // Narrow plane tiles (64 x 4, one cell a thread, one sweep per iteration)
-// where the wide ones are not taken: in batches, in single solves of at most
-// kNarrowCells cells, and wherever PCG_NARROW_TILES asks.  Measured against
-// consecutive-cell tiles: the 64-solve FP32+IR batch 159 against 175 ms (one
-// launch per iteration once every member sweeps), the served capacity 136
-// against 132 solves/s; single solves per iteration 33^3 17.0 against 20.8
-// us (FP64) and 17.0 against 21.7 (FP32), 37 x 29 x 23 15.5 against 19.3,
-// 64^3 22.5 against 25.8 and 23.4 against 25.0; but 99^3 FP32 69 against
-// 48, 127^3 FP32 72 against 63 (FP64 54 against 82).
+// where the wide ones are not taken: in batches, for single solves whose
+// consecutive-cell tiles would run one cell a thread (rows of an odd length)
+// or that have at most kNarrowCells cells, and wherever PCG_NARROW_TILES
+// asks; not with two sweeps, consecutive tiles asked for, or fractions.
+// Measured against consecutive-cell tiles, per iteration at the tuned tile
+// heights (FP64, FP32): 33^3 17.0 against 20.8 us and 17.0 against 21.7,
+// 64^3 22.5 against 25.8 and 23.4 against 25.0, odd rows 127^3 54 against
+// 83 and 46 against 64, 255^3 234 against 302 and 188 against 351, 383^3
+// 750 against 995 and 594 against 758, 447^3 1148 against 1583 and 982
+// against 1379; but against the grouped tiles of rows of pairs or quads
+// past 2^18 cells they lose (160 x 256 x 256 FP64 223 against 195,
+// 120 x 256 x 256 FP32 112 against 94, 100 x 300 x 300 FP32 176 against
+// 128).  The 64-solve FP32+IR batch 159 against 175 ms (one launch per
+// iteration once every member sweeps), the served capacity 136 against 132
+// solves/s.
 constexpr int64_t kNarrowCells = 1 << 18;
 
-bool narrow_allowed(const pcg_grid_t &g, int flags, bool batch)
+bool narrow_allowed(const pcg_grid_t &g, int prec, int flags, bool batch)
 {
     if (flags & (PCG_TWO_SWEEPS | PCG_FLAT_TILES | PCG_FRACTIONS)) return false;
-    return (flags & PCG_NARROW_TILES) || batch ||
-           (int64_t)g.nx * g.ny * g.nz <= kNarrowCells;
+    if ((flags & PCG_NARROW_TILES) || batch) return true;
+    (void)prec;
+    // consecutive-cell tiles group cells in pairs or quads on rows of even
+    // length, one cell a thread otherwise
+    return g.nx % 2 != 0 || (int64_t)g.nx * g.ny * g.nz <= kNarrowCells;
 }
 
 // The group width of a grid's plane tiles (cells a thread, of adjacent
@@ -270,7 +297,7 @@ int plane_group(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc, bo
                     (!batch && g.nx >= kRaggedUse[f32] * tiles * width)))
             return nw;
     }
-    if (narrow_allowed(g, flags, batch) && (!px || g.nx % (kBlock / kTileY) == 0)) return 1;
+    if (narrow_allowed(g, prec, flags, batch) && (!px || g.nx % (kBlock / kTileY) == 0)) return 1;
     return 0;
 }
 
@@ -280,7 +307,7 @@ Geometry make_geometry(const pcg_grid_t &g, int prec, int tz_opt, bool batch, in
     Geometry G;
     G.nx = g.nx; G.ny = g.ny; G.nz = g.nz;
     G.n = (int64_t)g.nx * g.ny * g.nz;
-    G.tz = tz_opt > 0 ? tz_opt : rule_for(G.n, prec, batch, tiles2d).tz;
+    G.tz = tz_opt > 0 ? tz_opt : rule_for(G.n, prec, batch, group).tz;
     if (G.tz > g.nz) G.tz = g.nz;
     const int64_t plane = (int64_t)g.nx * g.ny;
     // pass A addresses a tile's tz + 2 planes of 8-byte values with 32-bit
@@ -352,10 +379,12 @@ size_t grid_bytes(const pcg_grid_t &g, int prec, int tz_opt, bool batch, int fla
         const Geometry G = make_geometry(g, prec, tz_opt, batch, group);
         b = std::max(b, slot_bytes(G, prec, frac, one_sweep(G, prec, flags)));
     };
-    if (const int group = plane_group(g, prec, flags, nullptr, batch)) cover(group);
-    // walls that turn the wide tiles down leave the narrow ones, which have
-    // more tiles (and so partial sums)
-    if (narrow_allowed(g, flags, batch)) cover(1);
+    const int group = plane_group(g, prec, flags, nullptr, batch);
+    if (group) cover(group);
+    // a periodic x axis turns down wide tiles on rows of partial ones, which
+    // then take the narrow ones (more tiles, and so more partial sums)
+    const int width = (prec == PCG_PREC_FP32_IR ? 4 : 2) * kBlock / kTileY;
+    if (group > 1 && g.nx % width != 0 && narrow_allowed(g, prec, flags, batch)) cover(1);
     return b;
 }
 
@@ -1096,15 +1125,15 @@ struct Engine {
         int g = grid_opt > 0 ? grid_opt : (max_slots == 1 ? kDefaultGridMax : kBatchGrid);
         if (max_slots == 1) {
             int64_t t = 0, n = 0;
-            bool plane = false;
+            int group = 0;
             for (auto &S : slots)
                 if (S.used) {
                     t = std::max<int64_t>(t, S.geo.ntiles);
                     n = S.geo.n;
-                    plane = S.geo.tx > 0;
+                    group = S.geo.tx > 0 ? S.geo.cpt : 0;
                 }
-            if (grid_opt <= 0 && n > 0 && rule_for(n, prec, false, plane).grid > 0)
-                g = rule_for(n, prec, false, plane).grid;
+            if (grid_opt <= 0 && n > 0 && rule_for(n, prec, false, group).grid > 0)
+                g = rule_for(n, prec, false, group).grid;
             if (t > 0 && t < g) g = (int)t;
         }
         g = std::max(8, (g + 7) / 8 * 8);
@@ -1478,7 +1507,7 @@ int pcg_set_tile_rules(int32_t precision, int32_t table, int32_t n,
                        const int64_t *max_cells, const int32_t *tz, const int32_t *grid)
 {
     if (precision != PCG_PREC_FP64 && precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
-    if (table < kTableSingle || table > kTablePlane) return PCG_EINVAL;
+    if (table < kTableSingle || table > kTableNarrow) return PCG_EINVAL;
     if (n < 1 || n > 64 || !max_cells || !tz) return PCG_EINVAL;
     std::vector<TileRule> rules;
     for (int i = 0; i < n; ++i) {
@@ -1497,7 +1526,7 @@ int pcg_get_tile_rules(int32_t precision, int32_t table, int32_t cap,
                        int64_t *max_cells, int32_t *tz, int32_t *grid, int32_t *n_out)
 {
     if (precision != PCG_PREC_FP64 && precision != PCG_PREC_FP32_IR) return PCG_EINVAL;
-    if (table < kTableSingle || table > kTablePlane) return PCG_EINVAL;
+    if (table < kTableSingle || table > kTableNarrow) return PCG_EINVAL;
     if (!n_out || cap < 0) return PCG_EINVAL;
     const auto &rules = rules_of(precision, table);
     *n_out = (int32_t)rules.size();

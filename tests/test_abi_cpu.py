@@ -232,8 +232,8 @@ def test_tile_rules_roundtrip(lib):
         zero = (ctypes.c_int32 * 2)(0, 8)
         ok_mc = (ctypes.c_int64 * 2)(5, 10)
         assert lib.pcg_set_tile_rules(0, 0, 2, ok_mc, zero, None) == L.EINVAL
-        assert lib.pcg_set_tile_rules(0, 3, 2, ok_mc, tz, None) == L.EINVAL
-        assert lib.pcg_get_tile_rules(0, 3, 0, None, None, None, ctypes.byref(n)) == L.EINVAL
+        assert lib.pcg_set_tile_rules(0, 4, 2, ok_mc, tz, None) == L.EINVAL
+        assert lib.pcg_get_tile_rules(0, 4, 0, None, None, None, ctypes.byref(n)) == L.EINVAL
         # the batch and plane-tile tables are separate from the single-solve one
         batch_saved = autotune.get_rules(0, for_batches=True)
         autotune.set_rules(0, [[10**9, 16, 0]], for_batches=True)
@@ -243,12 +243,18 @@ def test_tile_rules_roundtrip(lib):
         autotune.set_rules(0, [[10**9, 2, 0]], table=autotune.PLANE)
         assert autotune.get_rules(0, table=autotune.PLANE) == [[2**63 - 1, 2, 0]]
         assert [r[1:] for r in autotune.get_rules(0)] == [[4, 256], [8, 0], [64, 512]]
+        narrow_saved = autotune.get_rules(0, table=autotune.NARROW)
+        autotune.set_rules(0, [[10**9, 3, 0]], table=autotune.NARROW)
+        assert autotune.get_rules(0, table=autotune.NARROW) == [[2**63 - 1, 3, 0]]
+        assert autotune.get_rules(0, table=autotune.PLANE) == [[2**63 - 1, 2, 0]]
+        autotune.set_rules(0, narrow_saved, table=autotune.NARROW)
         # workspace: partial sums scale with the number of tiles (tz = 64 -> fewer),
-        # on consecutive-cell tiles (rows of 80, five eighths of a plane tile)
-        # from the single-solve table
+        # on consecutive-cell tiles from the single-solve table
         o = L.Opts()
+        of = L.Opts()
+        of.flags = L.FLAT_TILES
         w64 = ctypes.c_size_t()
-        lib.pcg_workspace_bytes(ctypes.byref(_g(80, 128, 128)), ctypes.byref(o),
+        lib.pcg_workspace_bytes(ctypes.byref(_g(80, 128, 128)), ctypes.byref(of),
                                 ctypes.byref(w64))
         # rows of 128 take plane tiles and the plane table (tz = 2 here)
         wp2 = ctypes.c_size_t()
@@ -256,7 +262,7 @@ def test_tile_rules_roundtrip(lib):
                                 ctypes.byref(wp2))
         autotune.set_rules(0, [[10**9, 1, 0]])
         w1 = ctypes.c_size_t()
-        lib.pcg_workspace_bytes(ctypes.byref(_g(80, 128, 128)), ctypes.byref(o),
+        lib.pcg_workspace_bytes(ctypes.byref(_g(80, 128, 128)), ctypes.byref(of),
                                 ctypes.byref(w1))
         assert w1.value > w64.value
         wp = ctypes.c_size_t()
@@ -332,7 +338,8 @@ def test_built_in_tile_rules_match_the_shipped_table():
             "print(json.dumps({k: [list(r) for r in autotune.get_rules(p, table=b)] "
             "for k, p, b in (('fp64', L.PREC_FP64, 0), ('fp32_ir', L.PREC_FP32_IR, 0), "
             "('fp64_batch', L.PREC_FP64, 1), ('fp32_ir_batch', L.PREC_FP32_IR, 1), "
-            "('fp64_plane', L.PREC_FP64, 2), ('fp32_ir_plane', L.PREC_FP32_IR, 2))}))")
+            "('fp64_plane', L.PREC_FP64, 2), ('fp32_ir_plane', L.PREC_FP32_IR, 2), "
+            "('fp64_narrow', L.PREC_FP64, 3), ('fp32_ir_narrow', L.PREC_FP32_IR, 3))}))")
     env = dict(os.environ, PCGMI_TILE_TABLE="none")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, check=True,
                          capture_output=True, text=True).stdout
@@ -368,16 +375,15 @@ def test_one_sweep_workspace(lib):
         for extra in (0, L.TWO_SWEEPS):
             assert ws(gs, extra) >= ws(gs, L.FLAT_TILES), (shape, extra)
             assert ws(gs, L.PLANE_TILES | extra) >= ws(gs, L.FLAT_TILES), (shape, extra)
-    # rows of an odd length: consecutive-cell tiles above 2^18 cells (no
-    # second z), narrow plane tiles (one cell a thread, one sweep) below it
-    # or when asked for
+    # rows of an odd length: narrow plane tiles (one cell a thread, one
+    # sweep, so the second z) at any size; consecutive-cell tiles, without
+    # it, with two sweeps
     g97 = _g(97, 64, 64)
-    assert ws(g97, L.PLANE_TILES) == ws(g97, L.PLANE_TILES | L.TWO_SWEEPS)
     n97 = 97 * 64 * 64
-    # (narrow tiles are more, and so are their partial sums)
-    assert 8 * n97 <= ws(g97, L.NARROW_TILES) - ws(g97, L.TWO_SWEEPS) <= 8 * n97 + 65536
-    small = _g(97, 16, 8)
-    assert ws(small, 0) - ws(small, L.TWO_SWEEPS) >= 8 * 97 * 16 * 8 - 4 * 256
+    # (the two forms' tile counts, and so their partial sums, differ)
+    assert 8 * n97 - 65536 <= ws(g97, 0) - ws(g97, L.TWO_SWEEPS) <= 8 * n97 + 65536
+    assert ws(g97, L.NARROW_TILES) == ws(g97, 0)
+    assert ws(g97, L.TWO_SWEEPS) == ws(g97, L.FLAT_TILES)
     # rows of 96 cells fill three quarters of a 128-cell tile: plane tiles
     # (and the second z) when asked for
     g96 = _g(96, 16, 8)

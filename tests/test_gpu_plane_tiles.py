@@ -242,9 +242,10 @@ def test_tile_form_reported(F, torch_dev):
             ((120, 64, 48), TANK, 0, 1, (0, 0, 2)),            # FP32 with 47%: flat
             ((120, 8, 6), TANK, 0, 1, (64, 4, 1)),             # at most 2^18 cells: narrow
             ((130, 8, 6), (P, P, 0, 0, 0, 1), PLANE, 0, (0, 0, 2)),   # ragged periodic x
-            ((97, 64, 48), TANK, PLANE, 0, (0, 0, 2)),         # odd rows: no cell pairs
+            ((97, 64, 48), TANK, PLANE, 0, (64, 4, 1)),        # odd rows: narrow at any size
+            ((80, 64, 64), TANK, 0, 0, (0, 0, 2)),             # rows of pairs past 2^18: flat
             ((97, 8, 6), TANK, PLANE, 0, (64, 4, 1)),          # at most 2^18 cells: narrow
-            ((97, 64, 48), TANK, NARROW, 0, (64, 4, 1)),       # narrow when asked for
+            ((80, 64, 64), TANK, NARROW, 0, (64, 4, 1)),       # narrow when asked for
             ((97, 8, 6), TANK, TWO, 0, (0, 0, 2)),             # two sweeps: no narrow tiles
             ((98, 8, 6), TANK, PLANE, 1, (64, 4, 1))]:         # FP32: rows not of quads
         case = _case(F, shape, bc, wedge=False)
