@@ -107,7 +107,7 @@ struct TileCtx {
 // Column of this thread in tile lt.  A tile holds S.cpt kBlock cells of a
 // plane (S.cpt = 1, 2 or 4 cells per thread; 2 and 4 need a row length
 // divisible by them): consecutive cells, or with S.tx > 0 a 2-D block of
-// S.tx columns x S.ty rows numbered row by row.  Phases that treat cells
+// S.tx = S.cpt kBlock / S.ty columns x S.ty rows numbered row by row.  Phases that treat cells
 // one by one take them in S.cpt coalesced runs (r: cells r kBlock + l of
 // the tile); passes A and B give thread l the adjacent cells S.cpt l ..
 // S.cpt l + S.cpt - 1 of one row (group_ctx).  On a 2-D tile i and j are
@@ -1094,10 +1094,11 @@ __device__ void group_passB(const Slot &S, const SlotState &st, int64_t lt,
 }
 
 // ------------------------------------------------------------------------
-// LDS-staged passes on 2-D plane tiles (N = 2 FP64 or 4 FP32 cells per thread)
+// LDS-staged passes on 2-D plane tiles (N = 2 FP64 or 4 FP32 cells per
+// thread; the one-sweep iteration also N = 1, narrow tiles)
 // ------------------------------------------------------------------------
 // A tile is TX = N kBlock / kTileY columns x kTileY rows x tz planes (128 x 4
-// for FP64, 256 x 4 for FP32); thread l owns the group of N cells
+// for FP64, 256 x 4 for FP32, 64 x 4 narrow); thread l owns the group of N cells
 // (N l mod TX, N l / TX) of the tile.  Per plane the tile's
 // direction values and coefficient keys, with a one-cell x-y halo, are
 // written to LDS (two plane buffers, one barrier per plane) and every cell
