@@ -269,11 +269,10 @@ constexpr double kRaggedUse[2] = {0.7, 0.5};   // FP64, FP32
 // solves/s.
 constexpr int64_t kNarrowCells = 1 << 18;
 
-bool narrow_allowed(const pcg_grid_t &g, int prec, int flags, bool batch)
+bool narrow_allowed(const pcg_grid_t &g, int flags, bool batch)
 {
     if (flags & (PCG_TWO_SWEEPS | PCG_FLAT_TILES | PCG_FRACTIONS)) return false;
     if ((flags & PCG_NARROW_TILES) || batch) return true;
-    (void)prec;
     // consecutive-cell tiles group cells in pairs or quads on rows of even
     // length, one cell a thread otherwise
     return g.nx % 2 != 0 || (int64_t)g.nx * g.ny * g.nz <= kNarrowCells;
@@ -297,7 +296,7 @@ int plane_group(const pcg_grid_t &g, int prec, int flags, const pcg_bc_t *bc, bo
                     (!batch && g.nx >= kRaggedUse[f32] * tiles * width)))
             return nw;
     }
-    if (narrow_allowed(g, prec, flags, batch) && (!px || g.nx % (kBlock / kTileY) == 0)) return 1;
+    if (narrow_allowed(g, flags, batch) && (!px || g.nx % (kBlock / kTileY) == 0)) return 1;
     return 0;
 }
 
@@ -384,7 +383,7 @@ size_t grid_bytes(const pcg_grid_t &g, int prec, int tz_opt, bool batch, int fla
     // a periodic x axis turns down wide tiles on rows of partial ones, which
     // then take the narrow ones (more tiles, and so more partial sums)
     const int width = (prec == PCG_PREC_FP32_IR ? 4 : 2) * kBlock / kTileY;
-    if (group > 1 && g.nx % width != 0 && narrow_allowed(g, prec, flags, batch)) cover(1);
+    if (group > 1 && g.nx % width != 0 && narrow_allowed(g, flags, batch)) cover(1);
     return b;
 }
 
