@@ -221,3 +221,23 @@ def test_narrow_in_a_batch(F, torch_dev, precision):
     # all members on narrow tiles: one launch per iteration
     narrow_only = run([(c, NARROW) for c, _ in members[2:]] + [members[0]])
     assert all(st["status"] == 0 for st, _ in narrow_only)
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "ir"])
+def test_narrow_large_odd_rows(orc, F, torch_dev, precision):
+    """A 191^3 wedge tank (rows of an odd length take narrow tiles at any
+    size): the oracle's residual of the answer, and the consecutive-cell
+    tiles' answer to the error the tolerance allows."""
+    case = F.make_two_phase(191, 191, 191, surface_seed=81, velocity_seed=82,
+                            wedge=F.Wedge(), keep_velocity=False)
+    _say(f"case narrow 191^3 prec={precision}")
+    p, st = _solve(torch_dev, case, tol=1e-9, flags=0, precision=precision, form=NARROW_FORM)
+    assert st["status"] == 0, st
+    rr = orc.relres(case.rho, case.mask, case.bc, case.h, case.rhs, p)
+    assert rr <= 1e-9, (rr, st)
+    pf, stf = _solve(torch_dev, case, tol=1e-9, flags=FLAT_TILES, precision=precision,
+                     form=FLAT_FORM)
+    assert stf["status"] == 0, stf
+    assert np.abs(p - pf).max() <= 1e-5 * np.abs(pf).max()
+    if precision == 0:
+        assert abs(st["iters"] - stf["iters"]) <= max(2, 0.01 * stf["iters"]), (st, stf)
