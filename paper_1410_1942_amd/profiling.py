@@ -7,6 +7,7 @@ copy kernel of known size that the same run launches.
 
     python -m paper_1410_1942_amd.profiling stats <kernel_stats.csv | kernel_trace.csv>
         [--match S --gap-ms G --segment N]
+    python -m paper_1410_1942_amd.profiling counters <counter_collection.csv>... --match S
     python -m paper_1410_1942_amd.profiling traffic <fetch counter_collection.csv>
         <write counter_collection.csv> --cells N --copy-bytes B [--sha S]
 """
@@ -163,6 +164,23 @@ def traffic(fetch_csv: str, write_csv: str, cells: int, copy_bytes: int,
     return "\n".join(lines)
 
 
+def counters(paths, match: str) -> str:
+    """Per-counter means over the launches of the kernels whose name holds
+    `match`, from one or more PMC runs (counter_collection CSVs), each
+    counter over the launches within half to three times the median of its
+    non-empty values (see _large)."""
+    lines = [f"{'kernel':58s} {'counter':28s} {'n':>5s} {'mean':>14s}"]
+    for path in paths:
+        agg = collections.defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            if match in r["Kernel_Name"]:
+                agg[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+        for (k, c), v in sorted(agg.items()):
+            big = _large(v) if max(v) > 0 else v
+            lines.append(f"{_short(k, 58):58s} {c:28s} {len(big):5d} {statistics.mean(big):14.6e}")
+    return "\n".join(lines)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -173,6 +191,9 @@ def main(argv=None):
                    help="idle time that separates runs of launches (with --segment)")
     s.add_argument("--segment", type=int, default=-1,
                    help="summarize only this run of matching launches (trace CSV)")
+    c = sub.add_parser("counters")
+    c.add_argument("csv", nargs="+")
+    c.add_argument("--match", required=True, help="kernel name substring")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -182,6 +203,8 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(kernel_stats(a.csv, a.match, a.gap_ms, a.segment))
+    elif a.cmd == "counters":
+        print(counters(a.csv, a.match))
     else:
         print(traffic(a.fetch_csv, a.write_csv, a.cells, a.copy_bytes, a.sha))
 
